@@ -1,0 +1,264 @@
+"""ctypes binding of the plain FP64 CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path.  It shares no
+code with the GPU library; the only thing both sides take from one place is
+the seeded input generator module, which holds none of the method's
+arithmetic.
+
+Parameters arrive as a plain dict (see ``paper_1808_06381_amd.inputs``):
+    n, box, kT, gamma0, alpha, shear_rate, dt, rc, lam, u_amp,
+    weight_law ('gauss' | 'poly2'), potential ('gauss_core' | 'soft' | 'none'),
+    noise ('fdt' | 'paper' | 'off'), seed, stream
+Arrays are numpy, particles in original id order, n x 3 row-major.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+W_LAWS = {"gauss": 0, "poly2": 1}
+POTENTIALS = {"gauss_core": 0, "soft": 1, "none": 2}
+NOISE = {"fdt": 0, "paper": 1, "off": 2}
+PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "given": 3}
+STATUS = {0: "ok", -2: "no memory", -4: "no convergence", -5: "breakdown"}
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("box", C.c_double * 3),
+        ("kT", C.c_double),
+        ("gamma0", C.c_double),
+        ("alpha", C.c_double),
+        ("shear_rate", C.c_double),
+        ("dt", C.c_double),
+        ("rc", C.c_double),
+        ("lam", C.c_double),
+        ("u_amp", C.c_double),
+        ("weight_law", C.c_int32),
+        ("potential", C.c_int32),
+        ("noise_mode", C.c_int32),
+        ("pad0", C.c_int32),
+        ("seed", C.c_uint64),
+        ("stream", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b  # build on first use (CPU only, seconds)
+
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        d_p = P(C.c_double)
+        i64_p = P(C.c_int64)
+        u64_p = P(C.c_uint64)
+        pp = P(OrcParams)
+        L.orc_philox4x64_10.argtypes = [u64_p, u64_p, u64_p]
+        L.orc_gauss4.argtypes = [pp, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, d_p]
+        L.orc_le_offset.argtypes = [pp, C.c_int64]
+        L.orc_le_offset.restype = C.c_double
+        L.orc_separation.argtypes = [pp, C.c_double, d_p, d_p, d_p]
+        L.orc_separation.restype = C.c_int
+        for f in (L.orc_pairs_brute, L.orc_pairs_cells):
+            f.argtypes = [pp, C.c_double, d_p, C.c_int64, i64_p]
+            f.restype = C.c_int64
+        L.orc_count_pairs.argtypes = [pp, C.c_int64, d_p]
+        L.orc_count_pairs.restype = C.c_int64
+        L.orc_build_system.argtypes = [pp, C.c_int64, d_p, d_p, d_p, C.c_int64, i64_p, i64_p,
+                                       d_p, d_p, d_p, d_p]
+        L.orc_build_system.restype = C.c_int64
+        L.orc_spmv3.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, d_p]
+        L.orc_pcg.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, d_p, C.c_double, C.c_int,
+                              C.c_int, i64_p, i64_p, d_p, d_p, P(C.c_int), d_p]
+        L.orc_pcg.restype = C.c_int
+        L.orc_step.argtypes = [pp, C.c_int64, d_p, d_p, C.c_double, C.c_int, C.c_int, P(C.c_int)]
+        L.orc_step.restype = C.c_int
+        L.orc_wrap.argtypes = [pp, C.c_int64, d_p]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def make_params(cfg):
+    """dict -> OrcParams"""
+    p = OrcParams()
+    p.n = int(cfg["n"])
+    for k in range(3):
+        p.box[k] = float(cfg["box"][k])
+    p.kT = float(cfg["kT"])
+    p.gamma0 = float(cfg["gamma0"])
+    p.alpha = float(cfg["alpha"])
+    p.shear_rate = float(cfg["shear_rate"])
+    p.dt = float(cfg["dt"])
+    p.rc = float(cfg["rc"])
+    p.lam = float(cfg.get("lam", 1.0))
+    p.u_amp = float(cfg.get("u_amp", 0.0))
+    p.weight_law = W_LAWS[cfg.get("weight_law", "poly2")]
+    p.potential = POTENTIALS[cfg.get("potential", "soft")]
+    p.noise_mode = NOISE[cfg.get("noise", "fdt")]
+    p.seed = int(cfg.get("seed", 0)) & (2**64 - 1)
+    p.stream = int(cfg.get("stream", 0)) & (2**64 - 1)
+    return p
+
+
+def philox4x64_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    u64 = C.POINTER(C.c_uint64)
+    lib().orc_philox4x64_10(c.ctypes.data_as(u64), k.ctypes.data_as(u64), out.ctypes.data_as(u64))
+    return out
+
+
+def gauss4(cfg, step, tag, a, b):
+    p = make_params(cfg)
+    g = np.zeros(4)
+    lib().orc_gauss4(C.byref(p), step, tag, a, b, _dp(g))
+    return g
+
+
+def le_offset(cfg, step):
+    return lib().orc_le_offset(C.byref(make_params(cfg)), int(step))
+
+
+def separation(cfg, delta, ri, rj):
+    p = make_params(cfg)
+    ri = _f64(ri)
+    rj = _f64(rj)
+    d = np.zeros(3)
+    s = lib().orc_separation(C.byref(p), float(delta), _dp(ri), _dp(rj), _dp(d))
+    return d, s
+
+
+def pairs(cfg, pos, delta=0.0, method="brute"):
+    """Unordered pairs (i < j), sorted, as an int64 array of shape (m, 2)."""
+    p = make_params(cfg)
+    pos = _f64(pos, (-1, 3))
+    f = lib().orc_pairs_brute if method == "brute" else lib().orc_pairs_cells
+    m = f(C.byref(p), float(delta), _dp(pos), 0, None)
+    if m < 0:
+        raise MemoryError("oracle pair search failed")
+    out = np.zeros((max(m, 1), 2), dtype=np.int64)
+    f(C.byref(p), float(delta), _dp(pos), m, _ip(out))
+    return out[:m]
+
+
+def build_system(cfg, pos, step=0, xi=None, eta=None):
+    """Friction system at step `step`; returns dict(rowptr, col, val, diag, rhs, fcons)."""
+    p = make_params(cfg)
+    n = p.n
+    pos = _f64(pos, (n, 3))
+    m = lib().orc_count_pairs(C.byref(p), int(step), _dp(pos))
+    cap = 2 * m
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(cap, 1), dtype=np.int64)
+    val = np.zeros(max(cap, 1))
+    diag = np.zeros(n)
+    rhs = np.zeros((n, 3))
+    fcons = np.zeros((n, 3))
+    xi = None if xi is None else _f64(xi, (n, 3))
+    eta = None if eta is None else _f64(eta, (m, 3))
+    nnz = lib().orc_build_system(C.byref(p), int(step), _dp(pos), _dp(xi), _dp(eta), cap,
+                                 _ip(rowptr), _ip(col), _dp(val), _dp(diag), _dp(rhs),
+                                 _dp(fcons))
+    if nnz < 0:
+        raise MemoryError("oracle system build failed")
+    return dict(rowptr=rowptr, col=col[:nnz], val=val[:nnz], diag=diag, rhs=rhs, fcons=fcons,
+                npairs=m)
+
+
+def dense(sys_):
+    """Dense A (n x n) from a build_system result (test helper)."""
+    n = sys_["diag"].shape[0]
+    A = np.diag(sys_["diag"]).astype(np.float64)
+    rp = sys_["rowptr"]
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            A[i, sys_["col"][k]] += sys_["val"][k]
+    return A
+
+
+def spmv3(sys_, x):
+    n = sys_["diag"].shape[0]
+    x = _f64(x, (n, 3))
+    y = np.zeros((n, 3))
+    lib().orc_spmv3(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
+                    _dp(sys_["diag"]), _dp(x), _dp(y))
+    return y
+
+
+def pcg(sys_, rhs=None, tol=1e-10, maxit=10000, precond="jacobi", x0=None, m=None):
+    """Solve (A (x) I3) x = rhs; returns (x, iters[3], relres[3]).
+
+    precond 'given' applies z = M r with m = dict(rowptr, col, val, diag)."""
+    n = sys_["diag"].shape[0]
+    rhs = _f64(sys_["rhs"] if rhs is None else rhs, (n, 3))
+    x = np.zeros((n, 3)) if x0 is None else _f64(x0, (n, 3)).copy()
+    iters = (C.c_int * 3)()
+    rel = np.zeros(3)
+    mr = mc = mv = md = None
+    if precond == "given":
+        mr, mc = m["rowptr"].astype(np.int64), m["col"].astype(np.int64)
+        mv, md = _f64(m["val"]), _f64(m["diag"])
+    st = lib().orc_pcg(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
+                       _dp(sys_["diag"]), _dp(rhs), _dp(x), float(tol), int(maxit),
+                       PRECOND[precond], _ip(mr), _ip(mc), _dp(mv), _dp(md), iters, _dp(rel))
+    if st != 0:
+        raise RuntimeError("oracle pcg: " + STATUS.get(st, str(st)))
+    return x, list(iters), rel
+
+
+def step(cfg, pos, step_index, tol=1e-10, maxit=10000, precond="jacobi"):
+    """One step; returns (new_pos, vel, iters)."""
+    p = make_params(cfg)
+    pos = _f64(pos, (p.n, 3)).copy()
+    vel = np.zeros((p.n, 3))
+    iters = (C.c_int * 3)()
+    st = lib().orc_step(C.byref(p), int(step_index), _dp(pos), _dp(vel), float(tol), int(maxit),
+                        PRECOND[precond], iters)
+    if st != 0:
+        raise RuntimeError("oracle step: " + STATUS.get(st, str(st)))
+    return pos, vel, list(iters)
+
+
+def run(cfg, pos, nsteps, first_step=0, tol=1e-10, maxit=10000, precond="jacobi"):
+    """nsteps steps; returns (pos, last_vel, iteration counts per step)."""
+    pos = _f64(pos, (-1, 3)).copy()
+    vel = None
+    its = []
+    for k in range(nsteps):
+        pos, vel, it = step(cfg, pos, first_step + k, tol, maxit, precond)
+        its.append(it)
+    return pos, vel, its
+
+
+def wrap(cfg, pos, step_after):
+    p = make_params(cfg)
+    pos = _f64(pos, (p.n, 3)).copy()
+    lib().orc_wrap(C.byref(p), int(step_after), _dp(pos))
+    return pos
