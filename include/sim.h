@@ -1,0 +1,213 @@
+/*
+ * sim.h -- C ABI of libsim, the MI355X (gfx950) implementation of the time
+ * step of the sheared mesoscale blob simulation of Korolkovas,
+ * arXiv 1808.06381 (Method section).
+ *
+ * One step advances every particle c by R_c += v_c*dt, where the velocities
+ * solve the coupled overdamped equation of motion (Eq. 7), rewritten as the
+ * sparse linear system of Eq. 9:
+ *
+ *     (gamma0*I + alpha*L(w)) v = F + gamma0*kappa*(y - Ly/2) x
+ *                                   + alpha*sum_c' w_cc' V_cc' + f_thermal
+ *
+ * L(w) is the weighted graph Laplacian of the pairs closer than rc (weights
+ * below the threshold dropped, Method section), V_cc' the Lees-Edwards
+ * boundary velocity of Eq. 8, F the conservative pair force (Eq. 6b), and
+ * gamma0*kappa*(y - Ly/2) the Couette drive (Eq. 6c).  The friction acts on
+ * the full relative velocity vector, so the 3N x 3N system is A (x) I_3 and
+ * the library solves three right-hand sides against one scalar matrix A.
+ *
+ * Conventions of every entry point:
+ *  - Arrays are row-major n x 3 doubles (x, y, z per particle) in ORIGINAL
+ *    particle id order, for a batch the replicas one after another.
+ *  - Pointers are host pointers unless a flags argument carries
+ *    SIM_DEVICE_PTR; then they are device pointers on the library's device.
+ *  - The caller owns every buffer it passes; the library copies inputs and
+ *    writes outputs, and owns all device memory behind a handle.
+ *  - Every call returns SIM_OK (0) or a negative error code; sim_strerror
+ *    names it.  A failed sim_step leaves the state at the last committed step.
+ *  - Calls on one handle must not overlap; different handles are independent.
+ */
+#ifndef SIM_H
+#define SIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define SIM_OK 0
+#define SIM_EINVAL -1      /* invalid argument or parameter (see sim_create) */
+#define SIM_ENOMEM -2      /* host or device allocation failed */
+#define SIM_EDEVICE -3     /* a HIP runtime call failed */
+#define SIM_ENOCONV -4     /* CG hit cg_maxit: the step is not committed */
+#define SIM_EBREAKDOWN -5  /* CG breakdown (p.Ap <= 0) with a plain preconditioner */
+#define SIM_ECAPACITY -6   /* an output buffer given by the caller is too small */
+#define SIM_ENUMERIC -7    /* a position became non-finite: step not committed */
+#define SIM_ENOTSUP -8     /* option not available in this build */
+
+/* ---- flags --------------------------------------------------------------- */
+#define SIM_DEVICE_PTR 1u  /* array arguments are device pointers */
+
+/* ---- enumerations -------------------------------------------------------- */
+enum sim_weight_law { SIM_W_GAUSS = 0, SIM_W_POLY2 = 1 };
+enum sim_potential { SIM_U_GAUSS_CORE = 0, SIM_U_SOFT = 1, SIM_U_NONE = 2 };
+enum sim_noise { SIM_NOISE_FDT = 0, SIM_NOISE_PAPER = 1, SIM_NOISE_OFF = 2 };
+enum sim_precond { SIM_PC_JACOBI = 0, SIM_PC_NONE = 1, SIM_PC_IC0 = 2, SIM_PC_LEARNED = 3 };
+
+/* Physical and solver parameters of one box (one replica).
+ *  n           particles, >= 1
+ *  box         Lx, Ly, Lz > 0: flow along x, velocity gradient along y,
+ *              Lees-Edwards images along y, periodic in x and z
+ *  kT          temperature >= 0 (the thermal force of Eq. 6a scales with it)
+ *  gamma0      background friction > 0 (zeta of Eq. 6 and 7); it is the
+ *              smallest eigenvalue of A, so it must be positive
+ *  alpha       pair-friction strength >= 0 (alpha of Eq. 7)
+ *  shear_rate  kappa of Eq. 6c and Eq. 8 (any sign)
+ *  dt          time step > 0
+ *  rc          pair cut-off, 0 < rc < min(L)/2: a pair interacts iff r < rc
+ *  lambda      Gaussian width > 0 for SIM_W_GAUSS / SIM_U_GAUSS_CORE
+ *  u_amp       potential amplitude: v/lambda^3 of Eq. 6b (Gaussian core,
+ *              force (kT*u_amp/lambda^2) d exp(-r^2/2lambda^2)) or epsilon of
+ *              U = epsilon*(1 - r/rc)^2 (soft)
+ *  weight_law  pair friction envelope w(r): exp(-r^2/(2 lambda^2)) (paper)
+ *              or (1 - r/rc)^2
+ *  noise_mode  SIM_NOISE_FDT: f_i = sqrt(2kT/dt)*(sqrt(gamma0)*xi_i
+ *              + sum_j sigma_ij*sqrt(alpha*w_ij)*eta_ij), covariance
+ *              (2kT/dt)*A; SIM_NOISE_PAPER: sqrt(2*gamma0*kT/dt)*xi_i only
+ *              (Eq. 6a); SIM_NOISE_OFF.  Gaussians come from Philox4x64-10
+ *              keyed (seed, stream) with counter (step, 0, id, 0) for xi and
+ *              (step, 1, min id, max id) for eta, via Box-Muller.
+ *  precond     CG preconditioner (SIM_PC_*)
+ *  spmv_fp32   0: FP64 matrix values; 1: FP32 matrix values in the CG
+ *              matrix products with FP64 vectors, dots and true-residual
+ *              recompute (agreement with FP64 about 1e-5 relative)
+ *  warm_start  reserved, must be 0
+ *  cg_maxit    iteration limit per solve (> 0)
+ *  cg_tol      stop when ||b_k - A v_k||_2 <= cg_tol*||b_k||_2 for each
+ *              component k (true residual, checked at exit)
+ *  seed,stream Philox key */
+typedef struct sim_params {
+  int64_t n;
+  double box[3];
+  double kT;
+  double gamma0;
+  double alpha;
+  double shear_rate;
+  double dt;
+  double rc;
+  double lambda;
+  double u_amp;
+  int32_t weight_law;
+  int32_t potential;
+  int32_t noise_mode;
+  int32_t precond;
+  int32_t spmv_fp32;
+  int32_t warm_start;
+  int32_t cg_maxit;
+  int32_t reserved0;
+  double cg_tol;
+  uint64_t seed;
+  uint64_t stream;
+} sim_params;
+
+/* Statistics of the last sim_step / sim_solve call (max over replicas). */
+typedef struct sim_stats {
+  int32_t iters[3];      /* CG iterations per component of the last solve */
+  int32_t restarts;      /* true-residual restarts in the last solve */
+  double relres[3];      /* true relative residual per component at exit */
+  int64_t nnz;           /* off-diagonal entries of A (= 2 x pairs), all replicas */
+  int32_t max_row;       /* longest off-diagonal row */
+  int32_t fallback;      /* 1 if a learned solve fell back to Jacobi */
+  int64_t steps_done;    /* steps committed by the call */
+  int64_t cg_iters_total;/* sum over the call's solves of max-component iterations */
+} sim_stats;
+
+/* Metadata returned by sim_state. */
+typedef struct sim_meta {
+  int64_t step;          /* committed steps since creation */
+  double time;           /* step * dt of replica 0 */
+  double le_offset;      /* Lees-Edwards offset of replica 0 at `step` */
+  int32_t replicas;
+  int32_t reserved0;
+  int64_t n_total;       /* particles over all replicas */
+} sim_meta;
+
+typedef struct sim_t sim_t;
+
+/* Create a single-box simulation (Method section: particles R_c, parameters
+ * of Eq. 6-9).  pos0: n x 3 initial positions, each in [0, L] per axis.
+ * Validates: n >= 1, box > 0, gamma0 > 0 (A = gamma0*I + alpha*L is then
+ * SPD), alpha >= 0, kT >= 0, dt > 0, 0 < rc < min(box)/2, lambda > 0 where
+ * used, cg_tol > 0, cg_maxit > 0, enum ranges, finite positions inside the
+ * box; else SIM_EINVAL.  Copies pos0; *out receives the handle.           */
+int sim_create(const sim_params* params, const double* pos0, sim_t** out);
+
+/* Create R independent boxes advanced together (a block-diagonal system;
+ * each replica has its own n, box, shear rate and key).  pos0_concat holds
+ * the replicas' n_r x 3 blocks one after another.  Same validation.       */
+int sim_create_batch(const sim_params* params, int32_t replicas, const double* pos0_concat,
+                     sim_t** out);
+
+/* Advance every replica by nsteps steps (Eq. 7 integrated as R += v dt with
+ * Lees-Edwards re-entry).  Each step: cell binning, neighbour search under
+ * the Lees-Edwards minimum image, pair terms, assembly of A and b, PCG solve
+ * to cg_tol (x0 = 0), position update.  Stops at the first failing step
+ * (SIM_ENOCONV, SIM_EBREAKDOWN, SIM_ENUMERIC), which is not committed.
+ * st (nullable) receives the statistics.                                 */
+int sim_step(sim_t* sim, int32_t nsteps, sim_stats* st);
+
+/* Solve A v = b for the matrix of the current positions and step (Eq. 9,
+ * left-hand side), to tolerance tol (<= 0: the params' cg_tol) with the
+ * params' preconditioner.  b, v: n_total x 3.  flags: SIM_DEVICE_PTR.
+ * Does not change the state.                                              */
+int sim_solve(sim_t* sim, const double* b, double* v, double tol, uint32_t flags,
+              sim_stats* st);
+
+/* Copy out positions and the velocities of the last committed step (zeros
+ * before the first), n_total x 3 in original id order; any pointer may be
+ * NULL.  flags: SIM_DEVICE_PTR for pos/vel.                               */
+int sim_state(sim_t* sim, double* pos, double* vel, sim_meta* meta, uint32_t flags);
+
+/* Run the library's work on this HIP stream (hipStream_t as void*; NULL is
+ * the default stream).  The caller keeps the stream alive.                 */
+int sim_set_stream(sim_t* sim, void* hip_stream);
+
+/* Load learned-preconditioner weights (file written by the trainer).
+ * Returns SIM_ENOTSUP until the learned preconditioner is built in.       */
+int sim_load_precond(sim_t* sim, const char* path);
+
+/* Parity export: the unordered pairs {i < j} (original ids, per replica)
+ * of the current positions, as (replica, i, j) int64 triples in any order.
+ * cap is the triple capacity of ijr; *count receives the number of pairs.
+ * Returns SIM_ECAPACITY (with *count set) when cap is too small.          */
+int sim_debug_pairs(sim_t* sim, int64_t* ijr, int64_t cap, int64_t* count);
+
+/* Parity export of the system of the current positions and step, original
+ * ids: off-diagonal entries as triples (row, col, value) with global row and
+ * column numbers (replica offset + id), diag[n_total], rhs[n_total x 3]
+ * (including the thermal force of this step).  Same capacity rule.        */
+int sim_debug_system(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                     int64_t* count, double* diag, double* rhs);
+
+/* Replace the generated Gaussians of the thermal force (testing only,
+ * single-replica handles with n <= 1024): xi is n x 3 (particle i at row
+ * i), eta is n x n x 3 with the Gaussian vector of the unordered pair
+ * {a < b} at [(a*n + b)*3 + k].  Both NULL return to the generator.  The
+ * library copies the tables; they apply to subsequent builds.
+ * SIM_ENOTSUP for batches or larger n.                                    */
+int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
+
+/* Free the handle and all its device memory. NULL is a no-op.             */
+void sim_destroy(sim_t* sim);
+
+/* Static string for an error code.                                        */
+const char* sim_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIM_H */

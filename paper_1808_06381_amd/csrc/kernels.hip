@@ -1,0 +1,835 @@
+// kernels.hip -- gfx950 kernels of one time step of the sheared mesoscale
+// blob simulation (Korolkovas, arXiv 1808.06381, Method section):
+//   binning + stable cell sort -> Lees-Edwards neighbour search ->
+//   pair terms, assembly of A = gamma0 I + alpha L(w) and the rhs (Eq. 6-9)
+//   -> preconditioned CG on (A (x) I3) v = b -> R += v dt with LE re-entry.
+// Every kernel is row-parallel over the padded, cell-sorted row layout of
+// sim_dev.h; reductions are deterministic (fixed trees, per-replica "last
+// block finishes" with integer arrival counters, no float atomics).
+#include "sim_dev.h"
+#include "launch.h"
+
+// ===========================================================================
+// small utilities
+// ===========================================================================
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (3 passes: block sums, scan of block sums, down)
+// ---------------------------------------------------------------------------
+#define SCAN_ITEMS 8
+#define SCAN_TILE (BLOCK_THREADS * SCAN_ITEMS)
+
+__global__ __launch_bounds__(BLOCK_THREADS) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                               int64_t m,
+                                                               int32_t* __restrict__ bsum) {
+  __shared__ int32_t lds[BLOCK_THREADS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int32_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t i = base + (int64_t)k * BLOCK_THREADS + threadIdx.x;
+    if (i < m) s += in[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < BLOCK_THREADS / 64; ++w) t += lds[w];
+    bsum[blockIdx.x] = t;
+  }
+}
+
+// inclusive scan of one value per thread over the block (Hillis-Steele in LDS)
+__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const int32_t add = threadIdx.x >= (unsigned)o ? lds[threadIdx.x - o] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += add;
+    __syncthreads();
+  }
+  return lds[threadIdx.x];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int32_t lds[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = i < nb ? bsum[i] : 0;
+    const int32_t inc = block_incl_scan(v, lds);
+    const int32_t c = carry;
+    if (i < nb) bsum[i] = c + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = c + inc;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(BLOCK_THREADS) void k_scan_down(const int32_t* __restrict__ in,
+                                                             int64_t m,
+                                                             const int32_t* __restrict__ bsum,
+                                                             int32_t* __restrict__ out) {
+  __shared__ int32_t lds[BLOCK_THREADS];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int32_t tot = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < m ? in[base + k] : 0;
+    tot += v[k];
+  }
+  const int32_t inc = block_incl_scan(tot, lds);
+  int32_t run = bsum[blockIdx.x] + inc - tot;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < m) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ===========================================================================
+// a1: binning and the stable cell sort
+// ===========================================================================
+__device__ __forceinline__ int rep_of_entry(const RepDev* rep, int nrep, int e) {
+  int lo = 0, hi = nrep - 1;
+  while (lo < hi) {  // last replica with seg_off <= e
+    const int mid = (lo + hi + 1) >> 1;
+    if (rep[mid].seg_off <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// cell of every real particle; slot inside the cell by an integer atomic
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bin(DevPtrs d) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const double4 pp = d.pos[i];
+    const int cx = cell_axis(pp.x, R, 0), cy = cell_axis(pp.y, R, 1), cz = cell_axis(pp.z, R, 2);
+    const int c = R.seg_off + (cz * R.nc[1] + cy) * R.nc[0] + cx;
+    d.cellidx[i] = c;
+    d.slot[i] = atomicAdd(&d.cell_count[c], 1);
+  }
+}
+
+// scanned counts -> absolute first row of every cell entry of each segment
+__global__ void k_cell_rows(DevPtrs d, const int32_t* __restrict__ scan) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.ncell_entries) return;
+  const int r = rep_of_entry(d.rep, d.nrep, e);
+  const RepDev& R = d.rep[r];
+  d.cell_row[e] = (int32_t)(scan[e] - scan[R.seg_off] + R.row_off);
+}
+
+__global__ __launch_bounds__(BLOCK_THREADS) void k_scatter(DevPtrs d) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const int c = d.cellidx[i];
+    const int64_t dst = (int64_t)d.cell_row[c] + d.slot[i];
+    d.pos_alt[dst] = d.pos[i];
+    d.cellidx_alt[dst] = c;
+  }
+}
+
+// order each cell by original id (cells hold a handful of particles), so the
+// layout does not depend on the order the atomics were served in
+__global__ void k_cell_sort(DevPtrs d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.ncell_entries) return;
+  const int r = rep_of_entry(d.rep, d.nrep, e);
+  const RepDev& R = d.rep[r];
+  const int ncell = R.nc[0] * R.nc[1] * R.nc[2];
+  if (e - R.seg_off >= ncell) return;  // terminal entry of the segment
+  const int a = d.cell_row[e], b = d.cell_row[e + 1];
+  for (int i = a + 1; i < b; ++i) {
+    const double4 key = d.pos[i];
+    int j = i - 1;
+    while (j >= a && d.pos[j].w > key.w) {
+      d.pos[j + 1] = d.pos[j];
+      --j;
+    }
+    d.pos[j + 1] = key;
+  }
+}
+
+// ===========================================================================
+// a2-a5: neighbour search, pair terms, assembly of A and b
+// ===========================================================================
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d, int64_t step) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  const double delta = le_offset(R, step);
+  int mx = 0;
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    int cnt = 0;
+    if (i - R.row_off < R.n) {
+      const double4 pi = d.pos[i];
+      for_candidates(R, d.cell_row, delta, pi.x, pi.y, pi.z, i, [&](int j) {
+        const double4 pj = d.pos[j];
+        double dx, dy, dz;
+        le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+        if (dist2(dx, dy, dz) < R.rc2) ++cnt;
+      });
+    }
+    d.rowlen[i] = cnt;
+    mx = cnt > mx ? cnt : mx;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const int t = __shfl_xor(mx, o, 64);
+    mx = t > mx ? t : mx;
+  }
+  if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(&d.ctrl->max_row, mx);
+}
+
+__device__ __forceinline__ double pair_weight(const RepDev& R, double r2, double r) {
+  if (R.weight_law == 0) return exp(-0.5 * r2 * R.inv_lam2);
+  const double t = 1.0 - r / R.rc;
+  return t * t;
+}
+
+__device__ __forceinline__ double force_coef(const RepDev& R, double r2, double r) {
+  if (R.potential == 0) return R.force_gc * exp(-0.5 * r2 * R.inv_lam2);
+  if (R.potential == 1) return r > 0.0 ? R.force_soft * (1.0 - r / R.rc) / r : 0.0;
+  return 0.0;
+}
+
+// One row per thread: the same candidate order as k_nbr_count; writes the
+// row's CSR entries (-alpha*w), diag = gamma0 + alpha*sum w, 1/diag and the
+// three right-hand sides (Couette drive, conservative force, boundary
+// velocity term of Eq. 8, thermal force).
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_fill(DevPtrs d, int64_t step,
+                                                            double* __restrict__ dinv) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  const double delta = le_offset(R, step);
+  const double drag_unit = R.alpha * (R.shear * R.L[1]);
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) {
+      d.diag[i] = 1.0;
+      dinv[i] = 1.0;
+      d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
+      continue;
+    }
+    const int64_t e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    const bool fits = e1 <= d.nnz_cap;
+    if (!fits) atomicOr(&d.ctrl->overflow, 1);
+    const double4 pi = d.pos[i];
+    const int64_t idi = (int64_t)pi.w;
+    double wsum = 0.0, ws = 0.0;
+    double bx = 0.0, by = 0.0, bz = 0.0;
+    int64_t e = e0;
+    for_candidates(R, d.cell_row, delta, pi.x, pi.y, pi.z, i, [&](int j) {
+      const double4 pj = d.pos[j];
+      double dx, dy, dz;
+      const int s = le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+      const double r2 = dist2(dx, dy, dz);
+      if (!(r2 < R.rc2)) return;
+      const double r = sqrt(r2);
+      const double w = pair_weight(R, r2, r);
+      if (fits) {
+        d.col[e] = j;
+        d.val[e] = -R.alpha * w;
+        d.valf[e] = (float)(-R.alpha * w);
+      }
+      ++e;
+      wsum += w;
+      ws += w * (double)s;
+      const double fc = force_coef(R, r2, r);
+      bx += fc * dx;
+      by += fc * dy;
+      bz += fc * dz;
+      if (R.amp_pair != 0.0 && R.alpha != 0.0) {
+        const int64_t idj = (int64_t)pj.w;
+        const int64_t a = idi < idj ? idi : idj, bb = idi < idj ? idj : idi;
+        double g[3];
+        if (d.inj_eta) {
+          const double* src = d.inj_eta + 3 * (a * (int64_t)R.n + bb);
+          g[0] = src[0]; g[1] = src[1]; g[2] = src[2];
+        } else {
+          gauss3(R.seed, R.stream, (uint64_t)step, 1, (uint64_t)a, (uint64_t)bb, g);
+        }
+        const double amp = (idi < idj ? 1.0 : -1.0) * R.amp_pair * sqrt(R.alpha * w);
+        bx += amp * g[0];
+        by += amp * g[1];
+        bz += amp * g[2];
+      }
+    });
+    const double dg = R.gamma0 + R.alpha * wsum;
+    d.diag[i] = dg;
+    dinv[i] = 1.0 / dg;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (R.amp_node != 0.0) {
+      double g[3];
+      if (d.inj_xi) {
+        g[0] = d.inj_xi[3 * idi]; g[1] = d.inj_xi[3 * idi + 1]; g[2] = d.inj_xi[3 * idi + 2];
+      } else {
+        gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, g);
+      }
+      gx = R.amp_node * g[0];
+      gy = R.amp_node * g[1];
+      gz = R.amp_node * g[2];
+    }
+    d.b[3 * i + 0] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + gx + bx + drag_unit * ws;
+    d.b[3 * i + 1] = gy + by;
+    d.b[3 * i + 2] = gz + bz;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->nnz = d.rowptr[d.rows];
+}
+
+// ===========================================================================
+// a6: preconditioned conjugate gradients, three right-hand sides, one
+// recurrence per (replica, component).  Per iteration:
+//   k_cg_spmm   q = A p, p.q           -> last block: alpha = rz / pq
+//   k_cg_update x += alpha p, r -= alpha q, z = r/d, r.z, r.r
+//                                      -> last block: convergence, beta
+//   k_cg_pdir   p = z + beta p
+// Finished replicas skip their blocks; when nothing iterates the launches
+// return at once, so the host can queue iterations ahead of the readback.
+// ===========================================================================
+
+// Partial sums of one block -> per-replica totals, computed by the last
+// block of that replica to arrive (integer arrival counter, device-scope
+// fences).  Returns true in every thread of the finishing block; the totals
+// are then in tot[] of thread 0.
+template <int K>
+__device__ __forceinline__ bool reduce_to_replica(const DevPtrs& d, int rep_id, int blk,
+                                                  double (&v)[K], double (&tot)[K]) {
+  __shared__ double lds[BLOCK_THREADS / 64][NPART];
+  __shared__ int is_last;
+  const RepDev& R = d.rep[rep_id];
+  // block sum
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) lds[wave][k] = v[k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* dst = d.partial + (int64_t)blk * NPART;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][k];
+      __hip_atomic_store(dst + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    const int ticket = atomicAdd(&d.arrive[rep_id], 1);
+    is_last = (ticket == R.nblk - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  // deterministic: thread t sums blocks t, t+256, ... in order, then the tree
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < R.nblk; b += BLOCK_THREADS) {
+    const double* src = d.partial + (int64_t)(R.blk_off + b) * NPART;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      acc[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) lds[wave][k] = acc[k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][k];
+      tot[k] = s;
+    }
+    d.arrive[rep_id] = 0;
+  }
+  return true;
+}
+
+__global__ void k_ctrl_zero(Ctrl* c) {
+  if (threadIdx.x == 0) {
+    c->overflow = 0;
+    c->numeric = 0;
+    c->max_row = 0;
+    c->nnz = 0;
+  }
+}
+
+__global__ void k_cg_reset(DevPtrs d) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) {
+    d.ctrl->n_iterating = 0;
+    d.ctrl->n_pending = 0;
+  }
+  if (r < d.nrep) {
+    CgRep& c = d.cg[r];
+    for (int k = 0; k < 3; ++k) {
+      c.bb[k] = c.rz[k] = c.rr[k] = c.alpha[k] = c.beta[k] = 0.0;
+      c.state[k] = 2;
+      c.it[k] = 0;
+    }
+    c.active = 0;
+    c.restarts = 0;
+    c.breakdown = 0;
+    d.arrive[r] = 0;
+  }
+}
+
+// x = 0, r = b, z = r/d, p = z; totals b.b and r.z
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_init(DevPtrs d, const double* __restrict__ dinv) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  const int rid = d.blk_rep[blk];
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    const double di = dinv[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double bk = d.b[3 * i + k];
+      const double z = bk * di;
+      d.x[3 * i + k] = 0.0;
+      d.r[3 * i + k] = bk;
+      d.p[3 * i + k] = z;
+      v[k] += bk * bk;
+      v[3 + k] += bk * z;
+    }
+  }
+  double tot[6];
+  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
+  if (threadIdx.x == 0) {
+    CgRep& c = d.cg[rid];
+    int live = 0;
+    for (int k = 0; k < 3; ++k) {
+      c.bb[k] = tot[k];
+      c.rr[k] = tot[k];
+      c.rz[k] = tot[3 + k];
+      c.it[k] = 0;
+      c.state[k] = tot[k] > 0.0 ? 0 : 2;
+      live += c.state[k] == 0;
+    }
+    c.active = live > 0;
+    if (live) atomicAdd(&d.ctrl->n_iterating, live);
+  }
+}
+
+// q = A p (CSR, one row per thread), totals p.q; then alpha = rz / pq
+template <bool FP32>
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmm(DevPtrs d) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  const int rid = d.blk_rep[blk];
+  if (!d.cg[rid].active) return;
+  const double* __restrict__ p = d.p;
+  double v[3] = {0, 0, 0};
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    const double p0 = p[3 * i], p1 = p[3 * i + 1], p2 = p[3 * i + 2];
+    const double dg = d.diag[i];
+    double q0 = dg * p0, q1 = dg * p1, q2 = dg * p2;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int64_t j = d.col[e];
+      const double a = FP32 ? (double)d.valf[e] : d.val[e];
+      q0 += a * p[3 * j];
+      q1 += a * p[3 * j + 1];
+      q2 += a * p[3 * j + 2];
+    }
+    d.q[3 * i] = q0;
+    d.q[3 * i + 1] = q1;
+    d.q[3 * i + 2] = q2;
+    v[0] += p0 * q0;
+    v[1] += p1 * q1;
+    v[2] += p2 * q2;
+  }
+  double tot[3];
+  if (!reduce_to_replica<3>(d, rid, blk, v, tot)) return;
+  if (threadIdx.x == 0) {
+    CgRep& c = d.cg[rid];
+    for (int k = 0; k < 3; ++k) {
+      if (c.state[k] != 0) { c.alpha[k] = 0.0; continue; }
+      if (!(tot[k] > 0.0)) {  // breakdown: stop this component
+        c.alpha[k] = 0.0;
+        c.state[k] = 2;
+        c.breakdown = 1;
+        atomicSub(&d.ctrl->n_iterating, 1);
+        continue;
+      }
+      c.alpha[k] = c.rz[k] / tot[k];
+    }
+    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
+  }
+}
+
+// x += alpha p, r -= alpha q; totals r.z (z = r/d) and r.r; convergence, beta
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_update(DevPtrs d,
+                                                             const double* __restrict__ dinv) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  const int rid = d.blk_rep[blk];
+  const CgRep& cr = d.cg[rid];
+  if (!cr.active) return;
+  double al[3];
+  bool on[3];
+  for (int k = 0; k < 3; ++k) {
+    al[k] = cr.alpha[k];
+    on[k] = cr.state[k] == 0;
+  }
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    const double di = dinv[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!on[k]) continue;
+      const double xn = d.x[3 * i + k] + al[k] * d.p[3 * i + k];
+      const double rn = d.r[3 * i + k] - al[k] * d.q[3 * i + k];
+      d.x[3 * i + k] = xn;
+      d.r[3 * i + k] = rn;
+      v[k] += rn * (rn * di);
+      v[3 + k] += rn * rn;
+    }
+  }
+  double tot[6];
+  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
+  if (threadIdx.x == 0) {
+    CgRep& c = d.cg[rid];
+    const double tol2 = d.rep[rid].tol2;
+    for (int k = 0; k < 3; ++k) {
+      if (c.state[k] != 0) continue;
+      c.it[k] += 1;
+      c.rr[k] = tot[3 + k];
+      if (tot[3 + k] <= tol2 * c.bb[k]) {
+        c.state[k] = 1;
+        c.beta[k] = 0.0;
+        atomicSub(&d.ctrl->n_iterating, 1);
+        atomicAdd(&d.ctrl->n_pending, 1);
+      } else {
+        c.beta[k] = tot[k] / c.rz[k];
+        c.rz[k] = tot[k];
+      }
+    }
+    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
+  }
+}
+
+// p = r/d + beta p
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_pdir(DevPtrs d, const double* __restrict__ dinv) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  const int rid = d.blk_rep[blk];
+  const CgRep& cr = d.cg[rid];
+  if (!cr.active) return;
+  double be[3];
+  bool on[3];
+  for (int k = 0; k < 3; ++k) {
+    be[k] = cr.beta[k];
+    on[k] = cr.state[k] == 0;
+  }
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    const double di = dinv[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!on[k]) continue;
+      d.p[3 * i + k] = d.r[3 * i + k] * di + be[k] * d.p[3 * i + k];
+    }
+  }
+}
+
+// True-residual check of components whose recursive residual passed:
+// r = b - A x (FP64 matrix), z = r/d, p = z; a component whose true
+// residual fails the tolerance restarts from there.  A replica is checked
+// once none of its components iterates (a per-replica condition, so every
+// block of a replica takes the same branch).
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_check(DevPtrs d, const double* __restrict__ dinv) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  const int rid = d.blk_rep[blk];
+  const CgRep& cr = d.cg[rid];
+  if (cr.active) return;
+  bool on[3];
+  int any = 0;
+  for (int k = 0; k < 3; ++k) {
+    on[k] = cr.state[k] == 1;
+    any |= on[k];
+  }
+  if (!any) return;
+  const double* __restrict__ x = d.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    const double dg = d.diag[i], di = dinv[i];
+    double ax[3] = {dg * x[3 * i], dg * x[3 * i + 1], dg * x[3 * i + 2]};
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int64_t j = d.col[e];
+      const double a = d.val[e];
+      ax[0] += a * x[3 * j];
+      ax[1] += a * x[3 * j + 1];
+      ax[2] += a * x[3 * j + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!on[k]) continue;
+      const double rk = d.b[3 * i + k] - ax[k];
+      d.r[3 * i + k] = rk;
+      d.p[3 * i + k] = rk * di;
+      v[k] += rk * rk;
+      v[3 + k] += rk * (rk * di);
+    }
+  }
+  double tot[6];
+  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
+  if (threadIdx.x == 0) {
+    CgRep& c = d.cg[rid];
+    const double tol2 = d.rep[rid].tol2;
+    for (int k = 0; k < 3; ++k) {
+      if (c.state[k] != 1) continue;
+      c.rr[k] = tot[k];
+      atomicSub(&d.ctrl->n_pending, 1);
+      if (tot[k] <= tol2 * c.bb[k]) {
+        c.state[k] = 2;
+      } else {
+        c.state[k] = 0;
+        c.rz[k] = tot[3 + k];
+        c.restarts += 1;
+        atomicAdd(&d.ctrl->n_iterating, 1);
+      }
+    }
+    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
+  }
+}
+
+// ===========================================================================
+// a7: position update with Lees-Edwards re-entry
+// ===========================================================================
+__global__ __launch_bounds__(BLOCK_THREADS) void k_update(DevPtrs d, int64_t step_after) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  const double delta = le_offset(R, step_after);
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    double4 pp = d.pos[i];
+    const double vx = d.x[3 * i], vy = d.x[3 * i + 1], vz = d.x[3 * i + 2];
+    double x = pp.x + vx * R.dt, y = pp.y + vy * R.dt, z = pp.z + vz * R.dt;
+    if (y >= R.L[1]) { y = y - R.L[1]; x = x - delta; }
+    else if (y < 0.0) { y = y + R.L[1]; x = x + delta; }
+    for (int k = 0; k < 3; ++k)
+      if (x >= R.L[0]) x = x - R.L[0];
+    for (int k = 0; k < 3; ++k)
+      if (x < 0.0) x = x + R.L[0];
+    if (z >= R.L[2]) z = z - R.L[2];
+    else if (z < 0.0) z = z + R.L[2];
+    const bool ok = x >= 0.0 && x <= R.L[0] && y >= 0.0 && y <= R.L[1] && z >= 0.0 && z <= R.L[2];
+    if (!ok) atomicOr(&d.ctrl->numeric, 1);
+    pp.x = x; pp.y = y; pp.z = z;
+    d.pos_alt[i] = pp;
+  }
+}
+
+// velocities of the step in original order: vel_orig[3*(off + id) + k]
+__global__ __launch_bounds__(BLOCK_THREADS) void k_save_vel(DevPtrs d, const int64_t* __restrict__ id_off) {
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const int64_t g = id_off[rid] + (int64_t)d.pos[i].w;
+    for (int k = 0; k < 3; ++k) d.vel_orig[3 * g + k] = d.x[3 * i + k];
+  }
+}
+
+// ===========================================================================
+// boundary helpers: original-order <-> sorted-order gathers
+// ===========================================================================
+// mode 0: out[g] = pos.xyz; mode 1: b[i] = in[g]; mode 2: out[g] = x[i]
+__global__ __launch_bounds__(BLOCK_THREADS) void k_permute(DevPtrs d, const int64_t* __restrict__ id_off,
+                                                           int mode, const double* __restrict__ in,
+                                                           double* __restrict__ out) {
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const double4 pp = d.pos[i];
+    const int64_t g = id_off[rid] + (int64_t)pp.w;
+    if (mode == 0) {
+      out[3 * g] = pp.x; out[3 * g + 1] = pp.y; out[3 * g + 2] = pp.z;
+    } else if (mode == 1) {
+      for (int k = 0; k < 3; ++k) d.b[3 * i + k] = in[3 * g + k];
+    } else {
+      for (int k = 0; k < 3; ++k) out[3 * g + k] = d.x[3 * i + k];
+    }
+  }
+}
+
+// parity export of pairs (replica, i, j), i < j original ids; atomic slot
+__global__ __launch_bounds__(BLOCK_THREADS) void k_export_pairs(DevPtrs d, int64_t* __restrict__ out,
+                                                                int64_t cap,
+                                                                unsigned long long* __restrict__ cnt) {
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const int64_t idi = (int64_t)d.pos[i].w;
+    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+      const int64_t idj = (int64_t)d.pos[d.col[e]].w;
+      if (idj <= idi) continue;
+      const unsigned long long k = atomicAdd(cnt, 1ULL);
+      if ((int64_t)k < cap) {
+        out[3 * k] = rid; out[3 * k + 1] = idi; out[3 * k + 2] = idj;
+      }
+    }
+  }
+}
+
+// parity export of A (row, col, val in global original numbering), diag, rhs
+__global__ __launch_bounds__(BLOCK_THREADS) void k_export_system(DevPtrs d, const int64_t* __restrict__ id_off,
+                                                                 int64_t* __restrict__ rows, int64_t* __restrict__ cols,
+                                                                 double* __restrict__ vals, int64_t cap,
+                                                                 double* __restrict__ diag_out,
+                                                                 double* __restrict__ rhs_out) {
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
+    if (i - R.row_off >= R.n) continue;
+    const int64_t gi = id_off[rid] + (int64_t)d.pos[i].w;
+    diag_out[gi] = d.diag[i];
+    for (int k = 0; k < 3; ++k) rhs_out[3 * gi + k] = d.b[3 * i + k];
+    // entries are packed by sorted row: offset = rowptr - rowptr of replica start
+    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+      if (e >= cap) break;
+      rows[e] = gi;
+      cols[e] = id_off[rid] + (int64_t)d.pos[d.col[e]].w;
+      vals[e] = d.val[e];
+    }
+  }
+}
+
+// ===========================================================================
+// host launchers (C++ linkage, used by sim_api.hip)
+// ===========================================================================
+static inline unsigned nb_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(nb_of(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s) {
+  const int64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(BLOCK_THREADS), 0, s, in, m, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(BLOCK_THREADS), 0, s, in, m, bsum, out);
+  return hipGetLastError();
+}
+
+int64_t scan_bsum_len(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE; }
+
+hipError_t launch_bin(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_cell_rows(const DevPtrs& d, const int32_t* scan, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_rows, dim3(nb_of(d.ncell_entries, 256)), dim3(256), 0, s, d, scan);
+  return hipGetLastError();
+}
+hipError_t launch_scatter(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_sort, dim3(nb_of(d.ncell_entries, 256)), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_count, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step);
+  return hipGetLastError();
+}
+hipError_t launch_nbr_fill(const DevPtrs& d, int64_t step, double* dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_fill, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step, dinv);
+  return hipGetLastError();
+}
+hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_zero, dim3(1), dim3(64), 0, s, d.ctrl);
+  return hipGetLastError();
+}
+hipError_t launch_cg_reset(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_reset, dim3(nb_of(d.nrep, 64)), dim3(64), 0, s, d);
+  return hipGetLastError();
+}
+hipError_t launch_cg_init(const DevPtrs& d, const double* dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
+  return hipGetLastError();
+}
+hipError_t launch_cg_iteration(const DevPtrs& d, const double* dinv, hipStream_t s) {
+  if (d.spmv_fp32)
+    hipLaunchKernelGGL(k_cg_spmm<true>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_cg_spmm<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
+  hipLaunchKernelGGL(k_cg_update, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
+  hipLaunchKernelGGL(k_cg_pdir, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
+  return hipGetLastError();
+}
+hipError_t launch_cg_check(const DevPtrs& d, const double* dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
+  return hipGetLastError();
+}
+hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step_after);
+  return hipGetLastError();
+}
+hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_save_vel, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, id_off);
+  return hipGetLastError();
+}
+hipError_t launch_permute(const DevPtrs& d, const int64_t* id_off, int mode, const double* in,
+                          double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, id_off, mode, in, out);
+  return hipGetLastError();
+}
+hipError_t launch_export_pairs(const DevPtrs& d, int64_t* out, int64_t cap,
+                               unsigned long long* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_pairs, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, out, cap, cnt);
+  return hipGetLastError();
+}
+hipError_t launch_export_system(const DevPtrs& d, const int64_t* id_off, int64_t* rows,
+                                int64_t* cols, double* vals, int64_t cap, double* diag,
+                                double* rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_system, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, id_off, rows,
+                     cols, vals, cap, diag, rhs);
+  return hipGetLastError();
+}

@@ -1,0 +1,28 @@
+// launch.h -- host launchers of the kernels in kernels.hip (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sim_dev.h"
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s);
+int64_t scan_bsum_len(int64_t m);
+hipError_t launch_bin(const DevPtrs& d, hipStream_t s);
+hipError_t launch_cell_rows(const DevPtrs& d, const int32_t* scan, hipStream_t s);
+hipError_t launch_scatter(const DevPtrs& d, hipStream_t s);
+hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s);
+hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s);
+hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s);
+hipError_t launch_nbr_fill(const DevPtrs& d, int64_t step, double* dinv, hipStream_t s);
+hipError_t launch_cg_reset(const DevPtrs& d, hipStream_t s);
+hipError_t launch_cg_init(const DevPtrs& d, const double* dinv, hipStream_t s);
+hipError_t launch_cg_iteration(const DevPtrs& d, const double* dinv, hipStream_t s);
+hipError_t launch_cg_check(const DevPtrs& d, const double* dinv, hipStream_t s);
+hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s);
+hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, hipStream_t s);
+hipError_t launch_permute(const DevPtrs& d, const int64_t* id_off, int mode, const double* in,
+                          double* out, hipStream_t s);
+hipError_t launch_export_pairs(const DevPtrs& d, int64_t* out, int64_t cap,
+                               unsigned long long* cnt, hipStream_t s);
+hipError_t launch_export_system(const DevPtrs& d, const int64_t* id_off, int64_t* rows,
+                                int64_t* cols, double* vals, int64_t cap, double* diag,
+                                double* rhs, hipStream_t s);

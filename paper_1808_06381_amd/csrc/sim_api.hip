@@ -1,0 +1,655 @@
+// sim_api.hip -- host implementation of the C ABI declared in include/sim.h.
+//
+// The handle owns every device buffer (hipMalloc at creation, grown only
+// when the neighbour list outgrows its capacity).  One step queues:
+//   ctrl reset, binning, cell scan, scatter, per-cell id sort,
+//   neighbour count, row scan, neighbour fill (pairs, A, b),
+//   CG init, chunks of CG iterations + true-residual check,
+// reads the small control block back once per chunk, then queues the
+// position update and reads the control block once more before it commits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "launch.h"
+#include "sim.h"
+#include "sim_dev.h"
+
+#define SIM_EOVERFLOW_INTERNAL 1  // capacity of the CSR arrays exceeded: grow and refill
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) {                            \
+      sim_note_error(e_, #expr, __LINE__);             \
+      return SIM_EDEVICE;                              \
+    }                                                  \
+  } while (0)
+
+static thread_local char g_last_error[512];
+
+static void sim_note_error(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s failed (%s) at sim_api.hip:%d", what,
+           hipGetErrorString(e), line);
+}
+
+struct sim_t {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t R = 0;
+  std::vector<sim_params> prm;
+  std::vector<RepDev> reph;
+  std::vector<int32_t> blk_rep_h;
+  std::vector<int64_t> id_off_h;
+  int64_t rows = 0, n_total = 0;
+  int64_t step = 0;
+  int32_t last_iters = 0;
+  DevPtrs d{};
+  RepDev* rep_d = nullptr;
+  double* dinv = nullptr;
+  int32_t* scan_tmp = nullptr;
+  int32_t* bsum = nullptr;
+  int64_t* id_off_d = nullptr;
+  double* io = nullptr;  // n_total x 3 staging for the boundary
+  unsigned long long* counter_d = nullptr;
+  Ctrl* ctrl_h = nullptr;
+  CgRep* cg_h = nullptr;
+  double* inj_xi = nullptr;
+  double* inj_eta = nullptr;
+  std::vector<void*> allocs;
+  int32_t restarts_last = 0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static int dalloc(sim_t* s, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return SIM_ENOMEM;
+  }
+  s->allocs.push_back(*p);
+  return SIM_OK;
+}
+
+static void dfree(sim_t* s, void* p) {
+  if (!p) return;
+  auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+  if (it != s->allocs.end()) s->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+static int validate(const sim_params& p) {
+  if (p.n < 1 || p.n > (int64_t)1 << 30) return SIM_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(p.box[k] > 0.0) || !std::isfinite(p.box[k])) return SIM_EINVAL;
+  if (!(p.gamma0 > 0.0) || !std::isfinite(p.gamma0)) return SIM_EINVAL;
+  if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return SIM_EINVAL;
+  if (!(p.kT >= 0.0) || !std::isfinite(p.kT)) return SIM_EINVAL;
+  if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return SIM_EINVAL;
+  if (!std::isfinite(p.shear_rate)) return SIM_EINVAL;
+  const double lmin = std::min(p.box[0], std::min(p.box[1], p.box[2]));
+  if (!(p.rc > 0.0) || !(p.rc < 0.5 * lmin)) return SIM_EINVAL;
+  if (p.weight_law != SIM_W_GAUSS && p.weight_law != SIM_W_POLY2) return SIM_EINVAL;
+  if (p.potential < SIM_U_GAUSS_CORE || p.potential > SIM_U_NONE) return SIM_EINVAL;
+  if (p.noise_mode < SIM_NOISE_FDT || p.noise_mode > SIM_NOISE_OFF) return SIM_EINVAL;
+  if (p.precond < SIM_PC_JACOBI || p.precond > SIM_PC_LEARNED) return SIM_EINVAL;
+  if ((p.weight_law == SIM_W_GAUSS || p.potential == SIM_U_GAUSS_CORE) && !(p.lambda > 0.0))
+    return SIM_EINVAL;
+  if (!std::isfinite(p.u_amp)) return SIM_EINVAL;
+  if (!(p.cg_tol > 0.0) || p.cg_maxit < 1) return SIM_EINVAL;
+  if (p.warm_start != 0) return SIM_EINVAL;
+  if (p.spmv_fp32 != 0 && p.spmv_fp32 != 1) return SIM_EINVAL;
+  if (p.precond == SIM_PC_IC0 || p.precond == SIM_PC_LEARNED) return SIM_ENOTSUP;
+  return SIM_OK;
+}
+
+static RepDev make_rep(const sim_params& p) {
+  RepDev R;
+  std::memset(&R, 0, sizeof(R));
+  for (int k = 0; k < 3; ++k) {
+    R.L[k] = p.box[k];
+    R.hL[k] = 0.5 * p.box[k];
+    int nc = (int)std::floor(p.box[k] / (p.rc * (1.0 + 1e-9)));
+    if (nc < 3) nc = 1;
+    R.nc[k] = nc;
+    R.cell_len[k] = p.box[k] / (double)nc;
+    R.inv_cell[k] = (double)nc / p.box[k];
+  }
+  R.n = (int32_t)p.n;
+  R.kT = p.kT;
+  R.gamma0 = p.gamma0;
+  R.alpha = p.alpha;
+  R.shear = p.shear_rate;
+  R.dt = p.dt;
+  R.rc = p.rc;
+  R.rc2 = p.rc * p.rc;
+  R.lam = p.lambda > 0.0 ? p.lambda : 1.0;
+  R.inv_lam2 = 1.0 / (R.lam * R.lam);
+  R.u_amp = p.u_amp;
+  if (p.noise_mode == SIM_NOISE_FDT) {
+    const double c = std::sqrt(2.0 * p.kT / p.dt);
+    R.amp_node = c * std::sqrt(p.gamma0);
+    R.amp_pair = c;
+  } else if (p.noise_mode == SIM_NOISE_PAPER) {
+    R.amp_node = std::sqrt(2.0 * p.gamma0 * p.kT / p.dt);
+    R.amp_pair = 0.0;
+  }
+  R.force_gc = (p.kT * p.u_amp) / (R.lam * R.lam);
+  R.force_soft = 2.0 * p.u_amp / p.rc;
+  R.tol2 = p.cg_tol * p.cg_tol;
+  R.weight_law = p.weight_law;
+  R.potential = p.potential;
+  R.noise_mode = p.noise_mode;
+  R.precond = p.precond;
+  R.seed = p.seed;
+  R.stream = p.stream;
+  return R;
+}
+
+static double host_le_offset(const sim_params& p, int64_t step) {
+  const double t = (double)step * p.dt;
+  return std::fmod((p.shear_rate * p.box[1]) * t, p.box[0]);
+}
+
+static int alloc_csr(sim_t* s, int64_t cap) {
+  dfree(s, s->d.col);
+  dfree(s, s->d.val);
+  dfree(s, s->d.valf);
+  s->d.col = nullptr;
+  s->d.val = nullptr;
+  s->d.valf = nullptr;
+  if (cap > (int64_t)INT32_MAX) cap = INT32_MAX;
+  int rc;
+  if ((rc = dalloc(s, (void**)&s->d.col, sizeof(int32_t) * (size_t)cap))) return rc;
+  if ((rc = dalloc(s, (void**)&s->d.val, sizeof(double) * (size_t)cap))) return rc;
+  if ((rc = dalloc(s, (void**)&s->d.valf, sizeof(float) * (size_t)cap))) return rc;
+  s->d.nnz_cap = cap;
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the step's phases
+// ---------------------------------------------------------------------------
+
+// a1-a5: sort, neighbour list, A and b at `step`.  The capacity check of the
+// fill is read back later (with the first CG chunk).
+static int build_system(sim_t* s, int64_t step) {
+  DevPtrs& d = s->d;
+  hipStream_t st = s->stream;
+  HIPCHK(launch_ctrl_zero(d, st));
+  HIPCHK(launch_fill_i32(d.cell_count, 0, d.ncell_entries, st));
+  HIPCHK(launch_bin(d, st));
+  HIPCHK(launch_scan(d.cell_count, s->scan_tmp, d.ncell_entries, s->bsum, st));
+  HIPCHK(launch_cell_rows(d, s->scan_tmp, st));
+  HIPCHK(launch_scatter(d, st));
+  std::swap(d.pos, d.pos_alt);
+  std::swap(d.cellidx, d.cellidx_alt);
+  HIPCHK(launch_cell_sort(d, st));
+  HIPCHK(launch_nbr_count(d, step, st));
+  HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
+  HIPCHK(launch_nbr_fill(d, step, s->dinv, st));
+  return SIM_OK;
+}
+
+static int read_ctrl(sim_t* s, bool with_cg) {
+  HIPCHK(hipMemcpyAsync(s->ctrl_h, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  if (with_cg)
+    HIPCHK(hipMemcpyAsync(s->cg_h, s->d.cg, sizeof(CgRep) * (size_t)s->R, hipMemcpyDeviceToHost,
+                          s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+static int grow_and_refill(sim_t* s, int64_t step) {
+  int64_t need = s->ctrl_h->nnz;
+  int rc = alloc_csr(s, need + need / 4 + 1024);
+  if (rc) return rc;
+  if (need > s->d.nnz_cap) return SIM_ENOMEM;
+  HIPCHK(launch_ctrl_zero(s->d, s->stream));
+  HIPCHK(launch_nbr_fill(s->d, step, s->dinv, s->stream));
+  return SIM_OK;
+}
+
+// a6: CG on the current system (b in d.b), x0 = 0.  tol > 0 overrides the
+// replicas' own tolerances.  Returns SIM_EOVERFLOW_INTERNAL if the fill
+// overflowed (nothing solved).
+static int cg_solve(sim_t* s, double tol, sim_stats* st) {
+  DevPtrs& d = s->d;
+  hipStream_t stream = s->stream;
+  int maxit = 1;
+  for (auto& p : s->prm) maxit = std::max(maxit, p.cg_maxit);
+  HIPCHK(launch_cg_reset(d, stream));
+  if (tol > 0.0) {
+    // per-call tolerance: written into the replica table copy used by the finishers
+    for (auto& R : s->reph) R.tol2 = tol * tol;
+    HIPCHK(hipMemcpyAsync(s->rep_d, s->reph.data(), sizeof(RepDev) * (size_t)s->R,
+                          hipMemcpyHostToDevice, stream));
+  }
+  HIPCHK(launch_cg_init(d, s->dinv, stream));
+  int launched = 0;
+  int chunk = s->last_iters > 2 ? s->last_iters - 1 : 4;
+  int status = SIM_OK;
+  for (;;) {
+    int n = std::min(chunk, maxit + 1 - launched);
+    if (n < 1) n = 1;
+    for (int k = 0; k < n; ++k) HIPCHK(launch_cg_iteration(d, s->dinv, stream));
+    launched += n;
+    HIPCHK(launch_cg_check(d, s->dinv, stream));
+    int rc = read_ctrl(s, true);
+    if (rc) return rc;
+    if (s->ctrl_h->overflow) { status = SIM_EOVERFLOW_INTERNAL; break; }
+    if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending == 0) break;
+    if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending > 0) {
+      // checks were pending at the end of the chunk: run them now
+      HIPCHK(launch_cg_check(d, s->dinv, stream));
+      rc = read_ctrl(s, true);
+      if (rc) return rc;
+      if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending == 0) break;
+    }
+    if (launched > maxit) { status = SIM_ENOCONV; break; }
+    chunk = 2;
+  }
+  if (tol > 0.0) {
+    for (int r = 0; r < s->R; ++r) s->reph[r].tol2 = s->prm[r].cg_tol * s->prm[r].cg_tol;
+    HIPCHK(hipMemcpyAsync(s->rep_d, s->reph.data(), sizeof(RepDev) * (size_t)s->R,
+                          hipMemcpyHostToDevice, stream));
+  }
+  if (status == SIM_EOVERFLOW_INTERNAL) return status;
+  int itmax = 0, restarts = 0, breakdown = 0;
+  int iters[3] = {0, 0, 0};
+  double relres[3] = {0, 0, 0};
+  for (int r = 0; r < s->R; ++r) {
+    const CgRep& c = s->cg_h[r];
+    for (int k = 0; k < 3; ++k) {
+      iters[k] = std::max(iters[k], c.it[k]);
+      itmax = std::max(itmax, c.it[k]);
+      const double rel = c.bb[k] > 0.0 ? std::sqrt(c.rr[k] / c.bb[k]) : 0.0;
+      relres[k] = std::max(relres[k], rel);
+    }
+    restarts = std::max(restarts, c.restarts);
+    breakdown |= c.breakdown;
+  }
+  s->last_iters = itmax;
+  if (st) {
+    for (int k = 0; k < 3; ++k) {
+      st->iters[k] = iters[k];
+      st->relres[k] = relres[k];
+    }
+    st->restarts = restarts;
+    st->nnz = s->ctrl_h->nnz;
+    st->max_row = s->ctrl_h->max_row;
+    st->cg_iters_total += itmax;
+  }
+  if (status) return status;
+  if (breakdown) return SIM_EBREAKDOWN;
+  return SIM_OK;
+}
+
+static int build_and_solve(sim_t* s, int64_t step, bool replace_rhs, double tol, sim_stats* st) {
+  int rc = build_system(s, step);
+  if (rc) return rc;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if (replace_rhs) HIPCHK(launch_permute(s->d, s->id_off_d, 1, s->io, nullptr, s->stream));
+    rc = cg_solve(s, tol, st);
+    if (rc != SIM_EOVERFLOW_INTERNAL) return rc;
+    rc = grow_and_refill(s, step);
+    if (rc) return rc;
+  }
+  return SIM_ENOMEM;
+}
+
+// build + capacity check without a solve (parity exports)
+static int build_checked(sim_t* s, int64_t step) {
+  int rc = build_system(s, step);
+  if (rc) return rc;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    rc = read_ctrl(s, false);
+    if (rc) return rc;
+    if (!s->ctrl_h->overflow) return SIM_OK;
+    rc = grow_and_refill(s, step);
+    if (rc) return rc;
+  }
+  return SIM_ENOMEM;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* sim_strerror(int code) {
+  switch (code) {
+    case SIM_OK: return "ok";
+    case SIM_EINVAL: return "invalid argument";
+    case SIM_ENOMEM: return "out of memory";
+    case SIM_EDEVICE: return g_last_error[0] ? g_last_error : "HIP runtime error";
+    case SIM_ENOCONV: return "conjugate gradients did not converge within cg_maxit";
+    case SIM_EBREAKDOWN: return "conjugate gradients broke down (p.Ap <= 0)";
+    case SIM_ECAPACITY: return "output buffer too small";
+    case SIM_ENUMERIC: return "non-finite or escaped position";
+    case SIM_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+void sim_destroy(sim_t* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->ctrl_h) (void)hipHostFree(s->ctrl_h);
+  if (s->cg_h) (void)hipHostFree(s->cg_h);
+  delete s;
+}
+
+int sim_create_batch(const sim_params* params, int32_t replicas, const double* pos0,
+                     sim_t** out) {
+  if (!params || !pos0 || !out || replicas < 1) return SIM_EINVAL;
+  *out = nullptr;
+  for (int r = 0; r < replicas; ++r) {
+    int rc = validate(params[r]);
+    if (rc) return rc;
+  }
+  sim_t* s = new (std::nothrow) sim_t();
+  if (!s) return SIM_ENOMEM;
+  if (hipGetDevice(&s->device) != hipSuccess) { delete s; return SIM_EDEVICE; }
+  s->R = replicas;
+  s->prm.assign(params, params + replicas);
+  // layout
+  int64_t row_off = 0, seg_off = 0, n_total = 0;
+  int32_t blk_off = 0;
+  for (int r = 0; r < replicas; ++r) {
+    RepDev R = make_rep(params[r]);
+    const int64_t npad = (params[r].n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK * ROWS_PER_BLOCK;
+    const int64_t ncell = (int64_t)R.nc[0] * R.nc[1] * R.nc[2];
+    R.row_off = row_off;
+    R.npad = (int32_t)npad;
+    R.blk_off = blk_off;
+    R.nblk = (int32_t)(npad / ROWS_PER_BLOCK);
+    R.seg_off = (int32_t)seg_off;
+    if (seg_off + ncell + 1 > INT32_MAX || row_off + npad > INT32_MAX / 2) {
+      delete s;
+      return SIM_EINVAL;
+    }
+    s->reph.push_back(R);
+    for (int b = 0; b < R.nblk; ++b) s->blk_rep_h.push_back(r);
+    s->id_off_h.push_back(n_total);
+    row_off += npad;
+    seg_off += ncell + 1;
+    blk_off += R.nblk;
+    n_total += params[r].n;
+  }
+  s->rows = row_off;
+  s->n_total = n_total;
+  // positions: validate and lay out
+  std::vector<double4> ph((size_t)s->rows);
+  for (int r = 0; r < replicas; ++r) {
+    const RepDev& R = s->reph[r];
+    const double* src = pos0 + 3 * s->id_off_h[r];
+    for (int64_t i = 0; i < R.npad; ++i) {
+      double4 v = make_double4(0.0, 0.0, 0.0, -1.0);
+      if (i < R.n) {
+        v = make_double4(src[3 * i], src[3 * i + 1], src[3 * i + 2], (double)i);
+        const double c[3] = {v.x, v.y, v.z};
+        for (int k = 0; k < 3; ++k)
+          if (!std::isfinite(c[k]) || c[k] < 0.0 || c[k] > R.L[k]) { delete s; return SIM_EINVAL; }
+      }
+      ph[(size_t)(R.row_off + i)] = v;
+    }
+  }
+  DevPtrs& d = s->d;
+  d.rows = s->rows;
+  d.nblk = blk_off;
+  d.nrep = replicas;
+  d.ncell_entries = (int32_t)seg_off;
+  d.spmv_fp32 = params[0].spmv_fp32;
+  const size_t rows = (size_t)s->rows;
+  int rc = SIM_OK;
+#define ALLOC(ptr, bytes)                                      \
+  if ((rc = dalloc(s, (void**)&(ptr), (bytes))) != SIM_OK) {   \
+    sim_destroy(s);                                            \
+    return rc;                                                 \
+  }
+  ALLOC(s->rep_d, sizeof(RepDev) * replicas);
+  d.rep = s->rep_d;
+  ALLOC(d.cg, sizeof(CgRep) * replicas);
+  ALLOC(d.ctrl, sizeof(Ctrl));
+  int32_t* blk_rep_d = nullptr;
+  ALLOC(blk_rep_d, sizeof(int32_t) * d.nblk);
+  d.blk_rep = blk_rep_d;
+  ALLOC(d.arrive, sizeof(int32_t) * replicas);
+  ALLOC(d.partial, sizeof(double) * NPART * d.nblk);
+  ALLOC(d.pos, sizeof(double4) * rows);
+  ALLOC(d.pos_alt, sizeof(double4) * rows);
+  ALLOC(d.cellidx, sizeof(int32_t) * rows);
+  ALLOC(d.cellidx_alt, sizeof(int32_t) * rows);
+  ALLOC(d.slot, sizeof(int32_t) * rows);
+  ALLOC(d.cell_count, sizeof(int32_t) * d.ncell_entries);
+  ALLOC(d.cell_row, sizeof(int32_t) * d.ncell_entries);
+  ALLOC(s->scan_tmp, sizeof(int32_t) * d.ncell_entries);
+  ALLOC(d.rowlen, sizeof(int32_t) * (rows + 1));
+  ALLOC(d.rowptr, sizeof(int32_t) * (rows + 1));
+  ALLOC(d.diag, sizeof(double) * rows);
+  ALLOC(s->dinv, sizeof(double) * rows);
+  ALLOC(d.b, sizeof(double) * 3 * rows);
+  ALLOC(d.x, sizeof(double) * 3 * rows);
+  ALLOC(d.r, sizeof(double) * 3 * rows);
+  ALLOC(d.p, sizeof(double) * 3 * rows);
+  ALLOC(d.q, sizeof(double) * 3 * rows);
+  ALLOC(d.vel_orig, sizeof(double) * 3 * (size_t)n_total);
+  ALLOC(s->io, sizeof(double) * 3 * (size_t)n_total);
+  ALLOC(s->id_off_d, sizeof(int64_t) * replicas);
+  ALLOC(s->counter_d, sizeof(unsigned long long));
+  {
+    const int64_t m = std::max<int64_t>(s->rows + 1, d.ncell_entries);
+    ALLOC(s->bsum, sizeof(int32_t) * (size_t)(scan_bsum_len(m) + 1));
+  }
+#undef ALLOC
+  // neighbour-list capacity: twice the mean row of a uniform box, + slack
+  int64_t cap = 0;
+  for (int r = 0; r < replicas; ++r) {
+    const sim_params& p = params[r];
+    const double vol = p.box[0] * p.box[1] * p.box[2];
+    const double kmean = 4.18879020478639 * p.rc * p.rc * p.rc * (double)p.n / vol;
+    cap += s->reph[r].npad * (int64_t)std::ceil(2.0 * kmean + 16.0);
+  }
+  if ((rc = alloc_csr(s, cap)) != SIM_OK) { sim_destroy(s); return rc; }
+  if (hipHostMalloc((void**)&s->ctrl_h, sizeof(Ctrl), 0) != hipSuccess ||
+      hipHostMalloc((void**)&s->cg_h, sizeof(CgRep) * replicas, 0) != hipSuccess) {
+    sim_destroy(s);
+    return SIM_ENOMEM;
+  }
+  // uploads (synchronous: creation is not on the hot path)
+  auto fail = [&](hipError_t e, const char* what) {
+    sim_note_error(e, what, __LINE__);
+    sim_destroy(s);
+    return SIM_EDEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMemcpy(s->rep_d, s->reph.data(), sizeof(RepDev) * replicas, hipMemcpyHostToDevice)))
+    return fail(e, "upload replicas");
+  if ((e = hipMemcpy(blk_rep_d, s->blk_rep_h.data(), sizeof(int32_t) * d.nblk, hipMemcpyHostToDevice)))
+    return fail(e, "upload block table");
+  if ((e = hipMemcpy(s->id_off_d, s->id_off_h.data(), sizeof(int64_t) * replicas, hipMemcpyHostToDevice)))
+    return fail(e, "upload id offsets");
+  if ((e = hipMemcpy(d.pos, ph.data(), sizeof(double4) * rows, hipMemcpyHostToDevice)))
+    return fail(e, "upload positions");
+  if ((e = hipMemset(d.rowlen, 0, sizeof(int32_t) * (rows + 1)))) return fail(e, "clear rowlen");
+  if ((e = hipMemset(d.rowptr, 0, sizeof(int32_t) * (rows + 1)))) return fail(e, "clear rowptr");
+  if ((e = hipMemset(d.x, 0, sizeof(double) * 3 * rows))) return fail(e, "clear x");
+  if ((e = hipMemset(d.vel_orig, 0, sizeof(double) * 3 * n_total))) return fail(e, "clear vel");
+  if ((e = hipMemset(d.arrive, 0, sizeof(int32_t) * replicas))) return fail(e, "clear arrive");
+  if ((e = hipMemset(d.ctrl, 0, sizeof(Ctrl)))) return fail(e, "clear ctrl");
+  if ((e = hipMemset(d.cg, 0, sizeof(CgRep) * replicas))) return fail(e, "clear cg");
+  // padding rows of the second position buffer stay inert too
+  if ((e = hipMemcpy(d.pos_alt, ph.data(), sizeof(double4) * rows, hipMemcpyHostToDevice)))
+    return fail(e, "upload positions");
+  if ((e = hipDeviceSynchronize())) return fail(e, "synchronize");
+  *out = s;
+  return SIM_OK;
+}
+
+int sim_create(const sim_params* params, const double* pos0, sim_t** out) {
+  return sim_create_batch(params, 1, pos0, out);
+}
+
+int sim_set_stream(sim_t* s, void* stream) {
+  if (!s) return SIM_EINVAL;
+  s->stream = (hipStream_t)stream;
+  return SIM_OK;
+}
+
+int sim_load_precond(sim_t* s, const char* path) {
+  if (!s || !path) return SIM_EINVAL;
+  return SIM_ENOTSUP;
+}
+
+int sim_step(sim_t* s, int32_t nsteps, sim_stats* st) {
+  if (!s || nsteps < 0) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (st) std::memset(st, 0, sizeof(*st));
+  for (int32_t k = 0; k < nsteps; ++k) {
+    int rc = build_and_solve(s, s->step, false, 0.0, st);
+    if (rc) return rc;
+    HIPCHK(launch_update(s->d, s->step + 1, s->stream));
+    rc = read_ctrl(s, false);
+    if (rc) return rc;
+    if (s->ctrl_h->numeric) return SIM_ENUMERIC;
+    HIPCHK(launch_save_vel(s->d, s->id_off_d, s->stream));
+    std::swap(s->d.pos, s->d.pos_alt);
+    s->step += 1;
+    if (st) st->steps_done += 1;
+  }
+  return SIM_OK;
+}
+
+int sim_solve(sim_t* s, const double* b, double* v, double tol, uint32_t flags, sim_stats* st) {
+  if (!s || !b || !v) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (st) std::memset(st, 0, sizeof(*st));
+  const size_t bytes = sizeof(double) * 3 * (size_t)s->n_total;
+  const bool dev = flags & SIM_DEVICE_PTR;
+  HIPCHK(hipMemcpyAsync(s->io, b, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        s->stream));
+  int rc = build_and_solve(s, s->step, true, tol, st);
+  if (rc) return rc;
+  HIPCHK(launch_permute(s->d, s->id_off_d, 2, nullptr, s->io, s->stream));
+  HIPCHK(hipMemcpyAsync(v, s->io, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return SIM_OK;
+}
+
+int sim_state(sim_t* s, double* pos, double* vel, sim_meta* meta, uint32_t flags) {
+  if (!s) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  const size_t bytes = sizeof(double) * 3 * (size_t)s->n_total;
+  const bool dev = flags & SIM_DEVICE_PTR;
+  if (pos) {
+    HIPCHK(launch_permute(s->d, s->id_off_d, 0, nullptr, s->io, s->stream));
+    HIPCHK(hipMemcpyAsync(pos, s->io, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          s->stream));
+  }
+  if (vel)
+    HIPCHK(hipMemcpyAsync(vel, s->d.vel_orig, bytes,
+                          dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (meta) {
+    meta->step = s->step;
+    meta->time = (double)s->step * s->prm[0].dt;
+    meta->le_offset = host_le_offset(s->prm[0], s->step);
+    meta->replicas = s->R;
+    meta->reserved0 = 0;
+    meta->n_total = s->n_total;
+  }
+  return SIM_OK;
+}
+
+int sim_debug_pairs(sim_t* s, int64_t* ijr, int64_t cap, int64_t* count) {
+  if (!s || !count || cap < 0 || (cap > 0 && !ijr)) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = build_checked(s, s->step);
+  if (rc) return rc;
+  const int64_t npairs = s->ctrl_h->nnz / 2;
+  *count = npairs;
+  if (npairs > cap) return SIM_ECAPACITY;
+  int64_t* buf = nullptr;
+  if ((rc = dalloc(s, (void**)&buf, sizeof(int64_t) * 3 * (size_t)std::max<int64_t>(npairs, 1))))
+    return rc;
+  HIPCHK(hipMemsetAsync(s->counter_d, 0, sizeof(unsigned long long), s->stream));
+  HIPCHK(launch_export_pairs(s->d, buf, npairs, s->counter_d, s->stream));
+  HIPCHK(hipMemcpyAsync(ijr, buf, sizeof(int64_t) * 3 * (size_t)npairs, hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  dfree(s, buf);
+  return SIM_OK;
+}
+
+int sim_debug_system(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                     int64_t* count, double* diag, double* rhs) {
+  if (!s || !count || cap < 0) return SIM_EINVAL;
+  if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = build_checked(s, s->step);
+  if (rc) return rc;
+  const int64_t nnz = s->ctrl_h->nnz;
+  *count = nnz;
+  if (nnz > cap) return SIM_ECAPACITY;
+  int64_t *r_d = nullptr, *c_d = nullptr;
+  double *v_d = nullptr, *dg_d = nullptr, *b_d = nullptr;
+  const size_t m = (size_t)std::max<int64_t>(nnz, 1);
+  if ((rc = dalloc(s, (void**)&r_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&c_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * (size_t)s->n_total))) return rc;
+  if ((rc = dalloc(s, (void**)&b_d, sizeof(double) * 3 * (size_t)s->n_total))) return rc;
+  HIPCHK(launch_export_system(s->d, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, b_d, s->stream));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpyAsync(rows, r_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(cols, c_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vals, v_d, sizeof(double) * nnz, hipMemcpyDeviceToHost, s->stream));
+  }
+  if (diag)
+    HIPCHK(hipMemcpyAsync(diag, dg_d, sizeof(double) * s->n_total, hipMemcpyDeviceToHost, s->stream));
+  if (rhs)
+    HIPCHK(hipMemcpyAsync(rhs, b_d, sizeof(double) * 3 * s->n_total, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  dfree(s, r_d);
+  dfree(s, c_d);
+  dfree(s, v_d);
+  dfree(s, dg_d);
+  dfree(s, b_d);
+  return SIM_OK;
+}
+
+int sim_debug_set_gaussians(sim_t* s, const double* xi, const double* eta) {
+  if (!s) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (!xi && !eta) {
+    dfree(s, s->inj_xi);
+    dfree(s, s->inj_eta);
+    s->inj_xi = s->inj_eta = nullptr;
+    s->d.inj_xi = s->d.inj_eta = nullptr;
+    return SIM_OK;
+  }
+  if (!xi || !eta) return SIM_EINVAL;
+  if (s->R != 1 || s->n_total > 1024) return SIM_ENOTSUP;
+  const int64_t n = s->n_total;
+  int rc;
+  if (!s->inj_xi && (rc = dalloc(s, (void**)&s->inj_xi, sizeof(double) * 3 * n))) return rc;
+  if (!s->inj_eta && (rc = dalloc(s, (void**)&s->inj_eta, sizeof(double) * 3 * n * n))) return rc;
+  HIPCHK(hipMemcpy(s->inj_xi, xi, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->inj_eta, eta, sizeof(double) * 3 * n * n, hipMemcpyHostToDevice));
+  s->d.inj_xi = s->inj_xi;
+  s->d.inj_eta = s->inj_eta;
+  return SIM_OK;
+}
+
+}  // extern "C"

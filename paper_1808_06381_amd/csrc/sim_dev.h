@@ -1,0 +1,286 @@
+// sim_dev.h -- device-side data layout and helpers of libsim (gfx950).
+//
+// Layout in HBM (all replicas concatenated, rows padded per replica to a
+// multiple of ROWS_PER_BLOCK so that every thread block belongs to exactly one
+// replica; padding rows are inert: diag 1, no neighbours, zero rhs):
+//   pos      double4[rows]   x, y, z, original id (as an exact double)
+//                            in cell-sorted order (re-sorted every step)
+//   cellidx  int32[rows]     global cell of each particle
+//   rowptr   int32[rows+1]   CSR of the off-diagonal part of A, full rows
+//   col/val  int32/double    -alpha*w_ij per directed pair (valf: FP32 copy)
+//   diag     double[rows]    gamma0 + alpha*sum_j w_ij
+//   b,x,r,p,q double[3*rows] the three right-hand sides / CG vectors, AoS
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ROWS_PER_BLOCK 1024
+#define BLOCK_THREADS 256
+#define NPART 8  // doubles per block partial slot
+
+// ---------------------------------------------------------------------------
+// Per-replica constants (device copy built at creation)
+// ---------------------------------------------------------------------------
+struct RepDev {
+  double L[3];        // box
+  double hL[3];       // L/2
+  double cell_len[3]; // cell edge >= rc*(1+1e-9)
+  double inv_cell[3];
+  int32_t nc[3];      // cells per axis: >= 3, or 1 (whole axis one cell)
+  int32_t seg_off;    // first entry of this replica's cell segment (ncell+1 entries)
+  int64_t row_off;    // first row
+  int32_t n;          // real particles
+  int32_t npad;       // rows incl. padding (multiple of ROWS_PER_BLOCK)
+  int32_t blk_off;    // first block
+  int32_t nblk;       // blocks
+  double kT, gamma0, alpha, shear, dt, rc, rc2, lam, inv_lam2, u_amp;
+  double amp_node, amp_pair;  // thermal-force amplitudes
+  double force_gc;            // kT*u_amp/lambda^2 (Gaussian core)
+  double force_soft;          // 2*u_amp/rc (soft)
+  double tol2;                // cg_tol^2
+  int32_t weight_law, potential, noise_mode, precond;
+  uint64_t seed, stream;
+};
+
+// Per-replica conjugate-gradient scalars (three components)
+struct CgRep {
+  double bb[3];     // ||b||^2
+  double rz[3];     // r.z of the current iterate
+  double rr[3];     // ||r||^2 (recursive, or true after a check)
+  double alpha[3];
+  double beta[3];
+  int32_t state[3]; // 0 iterating, 1 recursive residual below tol (check pending), 2 done
+  int32_t it[3];
+  int32_t active;   // any component iterating
+  int32_t restarts;
+  int32_t breakdown;
+  int32_t pad;
+};
+
+// Global control words (one per handle)
+struct Ctrl {
+  int32_t n_iterating;  // (replica, component) pairs iterating
+  int32_t n_pending;    // pairs waiting for the true-residual check
+  int32_t overflow;     // CSR capacity exceeded in the last fill
+  int32_t numeric;      // non-finite position after an update
+  int32_t max_row;      // longest off-diagonal row of the last build
+  int32_t pad0;
+  int64_t nnz;          // off-diagonal entries of the last build
+};
+
+struct DevPtrs {
+  const RepDev* rep;
+  CgRep* cg;
+  Ctrl* ctrl;
+  const int32_t* blk_rep;   // block -> replica
+  int32_t* arrive;          // per-replica arrival counters (last-block pattern)
+  double* partial;          // [blocks][NPART]
+  double4* pos;             // current positions (sorted order)
+  double4* pos_alt;         // scatter target
+  int32_t* cellidx;
+  int32_t* cellidx_alt;
+  int32_t* slot;
+  int32_t* cell_count;      // [cell entries]
+  int32_t* cell_row;        // first row of each cell (segmented, absolute)
+  int32_t* rowlen;          // [rows+1]
+  int32_t* rowptr;          // [rows+1]
+  int32_t* col;
+  double* val;
+  float* valf;
+  double* diag;
+  double* b;
+  double* x;
+  double* r;
+  double* p;
+  double* q;
+  double* vel_orig;         // velocities of the last step, original order
+  const double* inj_xi;     // injected Gaussians (testing), or null
+  const double* inj_eta;
+  int64_t nnz_cap;
+  int64_t rows;
+  int32_t nblk;             // blocks over all replicas
+  int32_t nrep;
+  int32_t ncell_entries;
+  int32_t spmv_fp32;
+};
+
+// ---------------------------------------------------------------------------
+// Block -> tile mapping: hardware dispatches workgroups round-robin over the
+// 8 XCDs; give each XCD a contiguous range of row blocks so that the CSR
+// gathers of neighbouring rows hit that XCD's own L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_block(int hw, int nblk) {
+  const int per = (nblk + 7) >> 3;
+  return (hw & 7) * per + (hw >> 3);
+}
+__host__ __forceinline__ int xcd_grid(int nblk) { return ((nblk + 7) >> 3) << 3; }
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller Gaussians
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+    uint64_t lo0 = m0 * c[0], hi0 = __umul64hi(m0, c[0]);
+    uint64_t lo1 = m1 * c[2], hi1 = __umul64hi(m1, c[2]);
+    uint64_t n0 = hi1 ^ c[1] ^ k0;
+    uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B97F4A7C15ULL;
+    k1 += 0xBB67AE8584CAA73BULL;
+  }
+}
+
+__device__ __forceinline__ double u01_open(uint64_t bits) {
+  return ((double)(bits >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// three standard normals from counter (step, tag, a, b), key (seed, stream)
+__device__ __forceinline__ void gauss3(uint64_t seed, uint64_t stream, uint64_t step,
+                                       uint64_t tag, uint64_t a, uint64_t b, double g[3]) {
+  uint64_t c[4] = {step, tag, a, b};
+  philox4x64(c, seed, stream);
+  const double two_pi = 6.283185307179586;
+  const double u0 = u01_open(c[0]), u1 = u01_open(c[1]);
+  const double u2 = u01_open(c[2]), u3 = u01_open(c[3]);
+  const double rad0 = sqrt(-2.0 * log(u0));
+  const double rad1 = sqrt(-2.0 * log(u2));
+  g[0] = rad0 * cos(two_pi * u1);
+  g[1] = rad0 * sin(two_pi * u1);
+  g[2] = rad1 * cos(two_pi * u3);
+}
+
+// ---------------------------------------------------------------------------
+// Lees-Edwards geometry.  Offset of the image above at step n:
+// fmod(kappa*Ly*(n*dt), Lx).  Separation d = R_i - R_j(nearest image) with
+// the image index s (Eq. 8: s = round(y_ij/Ly)); explicit round-to-nearest
+// operations (no contraction) so the pair decision is reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double le_offset(const RepDev& R, int64_t step) {
+  const double t = __dmul_rn((double)step, R.dt);
+  return fmod(__dmul_rn(__dmul_rn(R.shear, R.L[1]), t), R.L[0]);
+}
+
+__device__ __forceinline__ int le_sep(const RepDev& R, double delta, double xi, double yi, double zi,
+                                      double xj, double yj, double zj, double& dx, double& dy,
+                                      double& dz) {
+  double ty = __dsub_rn(yi, yj);
+  int s = 0;
+  if (ty > R.hL[1]) s = 1;
+  else if (ty < -R.hL[1]) s = -1;
+  dy = __dsub_rn(ty, __dmul_rn((double)s, R.L[1]));
+  double tx = __dsub_rn(__dsub_rn(xi, xj), __dmul_rn((double)s, delta));
+  if (tx > R.hL[0]) tx = __dsub_rn(tx, R.L[0]);
+  if (tx > R.hL[0]) tx = __dsub_rn(tx, R.L[0]);
+  if (tx < -R.hL[0]) tx = __dadd_rn(tx, R.L[0]);
+  if (tx < -R.hL[0]) tx = __dadd_rn(tx, R.L[0]);
+  dx = tx;
+  double tz = __dsub_rn(zi, zj);
+  if (tz > R.hL[2]) tz = __dsub_rn(tz, R.L[2]);
+  if (tz < -R.hL[2]) tz = __dadd_rn(tz, R.L[2]);
+  dz = tz;
+  return s;
+}
+
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ int cell_axis(double v, const RepDev& R, int k) {
+  int c = (int)floor(v * R.inv_cell[k]);
+  c = c < 0 ? 0 : c;
+  return c > R.nc[k] - 1 ? R.nc[k] - 1 : c;
+}
+
+__device__ __forceinline__ int imod(int a, int m) {
+  int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+// Enumerate every candidate row j of particle (xi, yi, zi) in replica R:
+// 3 x 3 rows of cells (z, y) and, per row, a run of x cells: the three
+// around cx for rows inside the box, or for a row across the y boundary
+// the cells covering x - s*delta +- rc (the Lees-Edwards-shifted images).
+// Runs of consecutive x cells are contiguous in the sorted order, so each
+// run is one or two row ranges.  f(j) is called for every candidate j != i
+// in a fixed order.
+template <typename F>
+__device__ __forceinline__ void for_candidates(const RepDev& R, const int32_t* cell_row,
+                                               double delta, double xi, double yi, double zi,
+                                               int64_t self, F&& f) {
+  const int cx = cell_axis(xi, R, 0), cy = cell_axis(yi, R, 1), cz = cell_axis(zi, R, 2);
+  const int ncx = R.nc[0], ncy = R.nc[1], ncz = R.nc[2];
+  const int zlo = ncz == 1 ? 0 : -1, zhi = ncz == 1 ? 0 : 1;
+  const int ylo = ncy == 1 ? 0 : -1, yhi = ncy == 1 ? 0 : 1;
+  const double eps = 1e-9 * R.cell_len[0];
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int cz2 = imod(cz + dz, ncz);
+    for (int dyc = ylo; dyc <= yhi; ++dyc) {
+      const int cyr = cy + dyc;
+      int cy2, lo, hi;
+      if (ncy == 1) {
+        cy2 = 0; lo = 0; hi = ncx - 1;
+      } else if (cyr >= 0 && cyr < ncy) {
+        cy2 = cyr;
+        if (ncx == 1) { lo = 0; hi = 0; }
+        else { lo = cx - 1; hi = cx + 1; }
+      } else {
+        // across the y boundary: j's image is shifted by s*delta in x, with
+        // s = +1 going up (j in row 0) and -1 going down (j in the top row)
+        const double sd = cyr >= ncy ? delta : -delta;
+        cy2 = cyr >= ncy ? 0 : ncy - 1;
+        const double c0 = xi - sd;
+        lo = (int)floor((c0 - R.rc - eps) * R.inv_cell[0]);
+        hi = (int)floor((c0 + R.rc + eps) * R.inv_cell[0]);
+        if (hi - lo + 1 >= ncx) { lo = 0; hi = ncx - 1; }
+      }
+      const int rowbase = R.seg_off + (cz2 * ncy + cy2) * ncx;
+      // split [lo, hi] at the periodic x edge into at most two runs
+      int a = imod(lo, ncx);
+      int len = hi - lo + 1;
+      while (len > 0) {
+        const int run = (a + len <= ncx) ? len : (ncx - a);
+        const int j0 = cell_row[rowbase + a], j1 = cell_row[rowbase + a + run];
+        for (int j = j0; j < j1; ++j)
+          if (j != self) f(j);
+        len -= run;
+        a = 0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions: wave (64 lanes, fixed xor tree, lane 0 result),
+// then block (waves in order) -- no floating-point atomics anywhere.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sums K values over the block; result valid in thread 0
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double (*lds)[K]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w][k];
+      v[k] = s;
+    }
+  }
+}

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libsim (include/sim.h).  Argument marshalling only:
+every step of the simulation runs in the library's HIP kernels.  PyTorch is
+used for streams and, optionally, device memory (SIM_DEVICE_PTR calls).
+
+The functions keep the C names (sim_create, sim_step, sim_solve, sim_state,
+...); ``Sim`` wraps a handle with numpy in / numpy out.  The library must be
+built (``paper_1808_06381_amd.build``); loading fails loudly otherwise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libsim.so")
+
+SIM_OK = 0
+SIM_DEVICE_PTR = 1
+ERRORS = {-1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVICE", -4: "SIM_ENOCONV",
+          -5: "SIM_EBREAKDOWN", -6: "SIM_ECAPACITY", -7: "SIM_ENUMERIC", -8: "SIM_ENOTSUP"}
+W_LAWS = {"gauss": 0, "poly2": 1}
+POTENTIALS = {"gauss_core": 0, "soft": 1, "none": 2}
+NOISE = {"fdt": 0, "paper": 1, "off": 2}
+PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
+
+EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
+            "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
+            "sim_debug_set_gaussians", "sim_destroy", "sim_strerror"]
+
+
+class SimParams(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("box", C.c_double * 3),
+        ("kT", C.c_double),
+        ("gamma0", C.c_double),
+        ("alpha", C.c_double),
+        ("shear_rate", C.c_double),
+        ("dt", C.c_double),
+        ("rc", C.c_double),
+        ("lambda_", C.c_double),
+        ("u_amp", C.c_double),
+        ("weight_law", C.c_int32),
+        ("potential", C.c_int32),
+        ("noise_mode", C.c_int32),
+        ("precond", C.c_int32),
+        ("spmv_fp32", C.c_int32),
+        ("warm_start", C.c_int32),
+        ("cg_maxit", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("cg_tol", C.c_double),
+        ("seed", C.c_uint64),
+        ("stream", C.c_uint64),
+    ]
+
+
+class SimStats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32 * 3),
+        ("restarts", C.c_int32),
+        ("relres", C.c_double * 3),
+        ("nnz", C.c_int64),
+        ("max_row", C.c_int32),
+        ("fallback", C.c_int32),
+        ("steps_done", C.c_int64),
+        ("cg_iters_total", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return dict(iters=list(self.iters), restarts=self.restarts, relres=list(self.relres),
+                    nnz=self.nnz, max_row=self.max_row, fallback=self.fallback,
+                    steps_done=self.steps_done, cg_iters_total=self.cg_iters_total)
+
+
+class SimMeta(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64),
+        ("time", C.c_double),
+        ("le_offset", C.c_double),
+        ("replicas", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("n_total", C.c_int64),
+    ]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().sim_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({msg})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libsim.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsim.so not built ({LIB_PATH}); run paper_1808_06381_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.sim_create.argtypes = [P(SimParams), vp, P(vp)]
+        L.sim_create_batch.argtypes = [P(SimParams), C.c_int32, vp, P(vp)]
+        L.sim_step.argtypes = [vp, C.c_int32, P(SimStats)]
+        L.sim_solve.argtypes = [vp, vp, vp, C.c_double, C.c_uint32, P(SimStats)]
+        L.sim_state.argtypes = [vp, vp, vp, P(SimMeta), C.c_uint32]
+        L.sim_set_stream.argtypes = [vp, vp]
+        L.sim_load_precond.argtypes = [vp, C.c_char_p]
+        L.sim_debug_pairs.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
+        L.sim_debug_system.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp, vp]
+        L.sim_debug_set_gaussians.argtypes = [vp, vp, vp]
+        L.sim_destroy.argtypes = [vp]
+        L.sim_destroy.restype = None
+        L.sim_strerror.argtypes = [C.c_int]
+        L.sim_strerror.restype = C.c_char_p
+        for f in EXPORTED:
+            if f not in ("sim_destroy", "sim_strerror"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_params(cfg, tol=None, maxit=None, precond=None, spmv_fp32=None):
+    """Parameter dict (paper_1808_06381_amd.inputs vocabulary) -> SimParams."""
+    p = SimParams()
+    p.n = int(cfg["n"])
+    for k in range(3):
+        p.box[k] = float(cfg["box"][k])
+    p.kT = float(cfg["kT"])
+    p.gamma0 = float(cfg["gamma0"])
+    p.alpha = float(cfg["alpha"])
+    p.shear_rate = float(cfg["shear_rate"])
+    p.dt = float(cfg["dt"])
+    p.rc = float(cfg["rc"])
+    p.lambda_ = float(cfg.get("lam", 1.0))
+    p.u_amp = float(cfg.get("u_amp", 0.0))
+    p.weight_law = W_LAWS[cfg.get("weight_law", "poly2")]
+    p.potential = POTENTIALS[cfg.get("potential", "soft")]
+    p.noise_mode = NOISE[cfg.get("noise", "fdt")]
+    p.precond = PRECOND[precond or cfg.get("precond", "jacobi")]
+    p.spmv_fp32 = int(cfg.get("spmv_fp32", 0) if spmv_fp32 is None else spmv_fp32)
+    p.warm_start = 0
+    p.cg_maxit = int(maxit or cfg.get("cg_maxit", 10000))
+    p.cg_tol = float(tol or cfg.get("cg_tol", 1e-10))
+    p.seed = int(cfg.get("seed", 0)) & (2**64 - 1)
+    p.stream = int(cfg.get("stream", 0)) & (2**64 - 1)
+    return p
+
+
+def _check(code, where):
+    if code != SIM_OK:
+        raise SimError(code, where)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Sim:
+    """One handle: a single box (cfg dict) or a batch (list of cfg dicts)."""
+
+    def __init__(self, cfg, pos0, tol=None, maxit=None, precond=None, spmv_fp32=None,
+                 stream=None):
+        L = lib()
+        cfgs = cfg if isinstance(cfg, (list, tuple)) else [cfg]
+        self.cfgs = list(cfgs)
+        arr = (SimParams * len(cfgs))(*[make_params(c, tol, maxit, precond, spmv_fp32)
+                                        for c in cfgs])
+        pos0 = np.ascontiguousarray(pos0, dtype=np.float64).reshape(-1, 3)
+        self.n_total = sum(int(c["n"]) for c in cfgs)
+        if pos0.shape[0] != self.n_total:
+            raise ValueError("pos0 rows != total particles")
+        h = C.c_void_p()
+        _check(L.sim_create_batch(arr, len(cfgs), _ptr(pos0), C.byref(h)), "sim_create_batch")
+        self.h = h
+        if stream is not None:
+            self.set_stream(stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, a raw hipStream_t int, or None."""
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(lib().sim_set_stream(self.h, C.c_void_p(raw or 0)), "sim_set_stream")
+
+    def step(self, nsteps=1):
+        st = SimStats()
+        _check(lib().sim_step(self.h, int(nsteps), C.byref(st)), "sim_step")
+        return st.as_dict()
+
+    def solve(self, b, tol=0.0):
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(self.n_total, 3)
+        v = np.zeros_like(b)
+        st = SimStats()
+        _check(lib().sim_solve(self.h, _ptr(b), _ptr(v), float(tol), 0, C.byref(st)), "sim_solve")
+        return v, st.as_dict()
+
+    def solve_device(self, b, v, tol=0.0):
+        """b, v: contiguous float64 torch tensors on the library's device."""
+        st = SimStats()
+        _check(lib().sim_solve(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(v.data_ptr()),
+                               float(tol), SIM_DEVICE_PTR, C.byref(st)), "sim_solve")
+        return st.as_dict()
+
+    def state(self):
+        pos = np.zeros((self.n_total, 3))
+        vel = np.zeros((self.n_total, 3))
+        meta = SimMeta()
+        _check(lib().sim_state(self.h, _ptr(pos), _ptr(vel), C.byref(meta), 0), "sim_state")
+        return pos, vel, dict(step=meta.step, time=meta.time, le_offset=meta.le_offset,
+                              replicas=meta.replicas, n_total=meta.n_total)
+
+    def pairs(self):
+        """Unordered pairs as an int64 (m, 3) array of (replica, i, j), sorted."""
+        cnt = C.c_int64()
+        rc = lib().sim_debug_pairs(self.h, None, 0, C.byref(cnt))
+        if rc not in (SIM_OK, -6):
+            _check(rc, "sim_debug_pairs")
+        out = np.zeros((max(cnt.value, 1), 3), dtype=np.int64)
+        _check(lib().sim_debug_pairs(self.h, _ptr(out), cnt.value, C.byref(cnt)), "sim_debug_pairs")
+        out = out[:cnt.value]
+        order = np.lexsort((out[:, 2], out[:, 1], out[:, 0]))
+        return out[order]
+
+    def system(self):
+        """(rows, cols, vals, diag, rhs) of the current system, global original ids."""
+        cnt = C.c_int64()
+        rc = lib().sim_debug_system(self.h, None, None, None, 0, C.byref(cnt), None, None)
+        if rc not in (SIM_OK, -6):
+            _check(rc, "sim_debug_system")
+        m = max(cnt.value, 1)
+        rows = np.zeros(m, dtype=np.int64)
+        cols = np.zeros(m, dtype=np.int64)
+        vals = np.zeros(m)
+        diag = np.zeros(self.n_total)
+        rhs = np.zeros((self.n_total, 3))
+        _check(lib().sim_debug_system(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
+                                      C.byref(cnt), _ptr(diag), _ptr(rhs)), "sim_debug_system")
+        k = cnt.value
+        return rows[:k], cols[:k], vals[:k], diag, rhs
+
+    def set_gaussians(self, xi=None, eta=None):
+        if xi is None and eta is None:
+            _check(lib().sim_debug_set_gaussians(self.h, None, None), "sim_debug_set_gaussians")
+            return
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        _check(lib().sim_debug_set_gaussians(self.h, _ptr(xi), _ptr(eta)),
+               "sim_debug_set_gaussians")
+
+    def load_precond(self, path):
+        _check(lib().sim_load_precond(self.h, path.encode()), "sim_load_precond")
