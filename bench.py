@@ -1,0 +1,210 @@
+"""Benchmark of the sheared mesoscale blob step on one MI355X.
+
+Workload (default): three single boxes of N = 10^6 particles, L = 100
+(density 1, r_c = 1, (1 - r/r_c)^2 friction weight, soft potential,
+background friction 0.1, kT = 1, dt = 0.01, fluctuation-dissipation noise),
+one per shear rate 0.01, 0.1 and 0.5, Jacobi-PCG to a true relative residual
+of 1e-8 per component, FP64.  One bench step advances each of the three
+boxes by one time step (3 x 10^6 particle-steps); inputs are resident in HBM.
+
+Prints one JSON line: particle-steps/s over the timed steps, the roofline of
+the dominant CG kernel (algorithmic bytes per launch over its event-timed
+mean duration, sampled inside the timed region), and the oracle's own
+throughput on the host cores for a bounded sample of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec at CG rel. residual 1e-8; learned-PCG vs plain-PCG, same GPU"
+PEAK_HBM_GBS = 8000.0
+SHEARS = (0.01, 0.1, 0.5)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--probe-every", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-spmv", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "cg.hip", "sim_dev.h"):
+        with open(os.path.join(ROOT, "paper_1808_06381_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload_key):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = line.split("=", 1)
+        rec[k.strip()] = v.strip()
+    if rec.get("kernel") != kernel or rec.get("workload") != workload_key:
+        return None
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, pos0, steps, tol):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.run(cfg, pos0, steps, tol=tol)
+    dt = time.perf_counter() - t0
+    return dict(value=cfg["n"] * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{steps} steps of the N={cfg['n']} box at shear {cfg['shear_rate']} "
+                       f"from the same initial positions, single-threaded FP64 oracle, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each GPU would own whole boxes; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1808_06381_amd import inputs
+    from paper_1808_06381_amd import sim as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    L = (args.n) ** (1.0 / 3.0) if args.n != 1_000_000 else 100.0
+    # achievable HBM bandwidth: a plain 1 GiB device copy (read + write)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    copy_ms = S.copy_probe(src, dst, reps=10, stream=stream)
+    copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    cfgs, sims, pos0s = [], [], []
+    for k, shear in enumerate(SHEARS):
+        cfg = inputs.single_box(shear_rate=shear, seed=1 + k, n=args.n, L=L)["params"]
+        pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+        sim = S.Sim(cfg, pos0, tol=args.tol, maxit=5000,
+                    spmv_fp32=1 if args.fp32_spmv else 0, stream=stream)
+        cfgs.append(cfg)
+        pos0s.append(pos0)
+        sims.append(sim)
+    print(f"# workload: {len(sims)} boxes N={args.n} L={L:.3g} shears={SHEARS} "
+          f"tol={args.tol} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        for sim in sims:
+            sim.step(1)
+    for sim in sims:
+        sim.profile_read(reset=True)
+        sim.profile_enable(args.probe_every)
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for sim in sims:
+            st = sim.step(1)
+            iters.append(max(st["iters"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    for sim in sims:
+        for name, rec in sim.profile_read(reset=True).items():
+            acc = prof.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
+            for f in ("launches", "ms", "bytes"):
+                acc[f] += rec[f]
+        sim.profile_enable(0)
+    print(f"# timed {args.steps} steps x {len(sims)} boxes in {elapsed:.3f} s; "
+          f"mean CG iterations {np.mean(iters):.1f}", file=sys.stderr, flush=True)
+
+    particle_steps = args.steps * sum(c["n"] for c in cfgs)
+    value = particle_steps / elapsed
+    kernels = {}
+    for name, rec in prof.items():
+        if rec["launches"] == 0:
+            continue
+        ms = rec["ms"] / rec["launches"]
+        bpl = rec["bytes"] / rec["launches"]
+        kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3, bytes_per_launch=bpl,
+                             gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        kr = kernels[dom]
+        wl_key = f"single_n{args.n}"
+        traffic = read_traffic(dom, wl_key)
+        roofline = dict(bound="hbm", achieved=round(kr["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                        frac=round(kr["gbs"] / PEAK_HBM_GBS, 4),
+                        copy_probe_gbs=round(copy_gbs, 1),
+                        traffic=traffic, kernel=dom,
+                        bytes_per_launch=kr["bytes_per_launch"], mean_us=round(kr["mean_us"], 2))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfgs[1], pos0s[1], args.cpu_steps, args.tol)
+
+    for sim in sims:
+        sim.close()
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-spmv/f64" if args.fp32_spmv else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"three single boxes N={args.n}, L={L:.4g}, density 1, shear rates "
+                        f"{list(SHEARS)}, r_c=1, (1-r/r_c)^2 weight, soft potential eps=1kT, "
+                        f"gamma0=0.1, kT=1, dt=0.01, FDT noise; one bench step = one time step "
+                        f"of each box",
+            "precond": "jacobi",
+            "cg_tol": args.tol,
+            "particles_per_step": sum(c["n"] for c in cfgs),
+            "mean_cg_iters": round(float(np.mean(iters)), 2),
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "kernels": {k: {f: (round(v, 3) if isinstance(v, float) else v) for f, v in r.items()}
+                    for k, r in kernels.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -201,6 +201,31 @@ int sim_debug_system(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int
  * SIM_ENOTSUP for batches or larger n.                                    */
 int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
 
+/* Kernel timing probe (measurement, not part of the method).  With
+ * sample_every > 0, every sample_every-th CG iteration of later solves has
+ * its three kernels bracketed by HIP events on the library's stream; only
+ * iterations in which every component of every replica was still iterating
+ * are kept, so each kept launch did the full work of one iteration.
+ * sample_every = 0 switches the probe off.                                */
+typedef struct sim_kernel_prof {
+  char name[32];         /* kernel name */
+  int64_t launches;      /* timed launches kept */
+  double ms;             /* summed event-measured duration of those launches */
+  double bytes;          /* summed algorithmic HBM bytes of those launches */
+} sim_kernel_prof;
+int sim_profile_enable(sim_t* sim, int32_t sample_every);
+/* Copy up to cap kernel records into out (*count receives the number of
+ * kernels); reset != 0 clears the accumulated records afterwards.         */
+int sim_profile_read(sim_t* sim, sim_kernel_prof* out, int32_t cap, int32_t* count,
+                     int32_t reset);
+
+/* Plain device copy of `bytes` (a multiple of 16) from src to dst, device
+ * pointers, repeated reps times on `hip_stream` between HIP events;
+ * *ms_avg receives the mean duration of one copy.  Measurement reference
+ * (achievable HBM bandwidth, counter calibration), not part of the method. */
+int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* hip_stream,
+                   double* ms_avg);
+
 /* Free the handle and all its device memory. NULL is a no-op.             */
 void sim_destroy(sim_t* sim);
 

@@ -1,0 +1,308 @@
+// cg.hip -- the sparse solve of Eq. 9 (Method section) on gfx950:
+// (A (x) I3) v = b, A = gamma0*I + alpha*L(w), three right-hand sides sharing
+// one scalar matrix, Jacobi-preconditioned conjugate gradients in the
+// single-reduction form of Chronopoulos & Gear (J. Comput. Appl. Math. 25,
+// 1989), which in exact arithmetic produces the iterates of standard PCG:
+//
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r
+//   w = A u;  gamma = (r, u), delta = (w, u)
+//   beta' = gamma' / gamma, alpha' = gamma' / (delta' - beta' gamma' / alpha)
+//
+// Per iteration three launches, none with a device-scope fence:
+//   k_cg_vec   every vector update, element-parallel (fully coalesced), and
+//              the partial sums of (r, u) and (r, r) per tile;
+//   k_cg_spmv  w = A u with four lanes per CSR row, so the neighbours of a
+//              row -- contiguous runs of the cell-sorted order -- are fetched
+//              by adjacent lanes; partial sums of (w, u);
+//   k_cg_finish one block per replica: the tile partials in a fixed order,
+//              then the scalar recurrences and the convergence state.
+// Sums are deterministic (fixed trees, no floating-point atomics).
+#include "sim_dev.h"
+#include "launch.h"
+
+#define SPMV_LANES 4
+#define VEC_ELEMS (3 * ROWS_PER_BLOCK)  // elements (row, component) per tile
+
+// tile partial sums: [gamma0..2, delta0..2, rr0..2]; `first`..`first+n` written
+template <int N>
+__device__ __forceinline__ void write_partials(const DevPtrs& d, int tile, int first,
+                                               double (&v)[N]) {
+  __shared__ double lds[BLOCK_THREADS / 64][9];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+    for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][threadIdx.x];
+    d.partial[(int64_t)tile * NPART + first + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_cg_reset(DevPtrs d, double tol_override) {
+  for (int r = threadIdx.x; r < d.nrep; r += blockDim.x) {
+    CgRep& c = d.cg[r];
+    for (int k = 0; k < 3; ++k) {
+      c.bb[k] = c.rr[k] = c.gamma[k] = c.alpha[k] = c.beta[k] = 0.0;
+      c.state[k] = 0;
+      c.it[k] = 0;
+    }
+    c.tol2 = tol_override > 0.0 ? tol_override * tol_override : d.rep[r].tol2;
+    c.run = 1;
+    c.check = 0;
+    c.restart = 0;
+    c.restarts = 0;
+    c.breakdown = 0;
+  }
+  if (threadIdx.x == 0) d.ctrl->n_notdone = 3 * d.nrep;
+}
+
+// Element-parallel vector work of one tile (3 * 1024 consecutive doubles of
+// the AoS arrays; element e is row e/3, component e%3).
+//   mode 0 (fresh start):   x = 0, r = b, p = s = 0, u = M^-1 r
+//   mode 1 (restart, r already = b - A x):   p = s = 0, u = M^-1 r
+//   mode 2 (iteration):     p = u + beta p, s = w + beta s, x += alpha p,
+//                           r -= alpha s, u = M^-1 r
+// Partials (r, u) and (r, r) of the components touched.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const int rid = d.blk_rep[tile];
+  const CgRep& cr = d.cg[rid];
+  if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
+  bool on[3];
+  double al[3], be[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
+    al[k] = cr.alpha[k];
+    be[k] = cr.beta[k];
+  }
+  double v[6] = {0, 0, 0, 0, 0, 0};  // (r,u)[3], (r,r)[3]
+  const int64_t base = (int64_t)tile * VEC_ELEMS;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int le = q * BLOCK_THREADS + threadIdx.x;
+    const int k = le % 3;
+    if (!on[k]) continue;
+    const int64_t e = base + le;
+    const double di = d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
+    double rk;
+    if (mode == 0) {
+      rk = d.b[e];
+      d.x[e] = 0.0;
+      d.r[e] = rk;
+      d.p[e] = 0.0;
+      d.s[e] = 0.0;
+    } else if (mode == 1) {
+      rk = d.r[e];
+      d.p[e] = 0.0;
+      d.s[e] = 0.0;
+    } else {
+      const double r0 = d.r[e];
+      const double pk = di * r0 + be[k] * d.p[e];
+      const double sk = d.w[e] + be[k] * d.s[e];
+      d.p[e] = pk;
+      d.s[e] = sk;
+      d.x[e] = d.x[e] + al[k] * pk;
+      rk = r0 - al[k] * sk;
+      d.r[e] = rk;
+    }
+    const double uk = di * rk;
+    d.u[e] = uk;
+    v[k] += rk * uk;
+    v[3 + k] += rk * rk;
+  }
+  double g[3] = {v[0], v[1], v[2]}, rr[3] = {v[3], v[4], v[5]};
+  write_partials<3>(d, tile, 0, g);
+  __syncthreads();
+  write_partials<3>(d, tile, 6, rr);
+}
+
+// CSR product with SPMV_LANES lanes per row over the tile's 1024 rows.
+//   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
+//   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
+// Lane k < 3 of a row's group finishes component k (coalesced stores).
+template <bool FP32>
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const int rid = d.blk_rep[tile];
+  const CgRep& cr = d.cg[rid];
+  bool on[3];
+  if (mode == 0) {
+    // start_mode: 0 fresh start, 1 restart, 2 iteration (as in k_cg_vec)
+    if ((start_mode == 1 && !cr.restart) || (start_mode == 2 && !cr.run)) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      on[k] = start_mode == 0 ? true : (start_mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
+  } else {
+    if (!cr.check) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
+  }
+  const double* __restrict__ src = mode == 0 ? d.u : d.x;
+  const int lane = threadIdx.x & (SPMV_LANES - 1);
+  const int grp = threadIdx.x / SPMV_LANES;
+  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
+  double v[3] = {0, 0, 0};
+  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
+    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
+      const int64_t j = d.col[e];
+      const double a = FP32 ? (double)d.valf[e] : d.val[e];
+      a0 += a * src[3 * j];
+      a1 += a * src[3 * j + 1];
+      a2 += a * src[3 * j + 2];
+    }
+#pragma unroll
+    for (int o = 1; o < SPMV_LANES; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+    }
+    if (lane < 3 && on[lane]) {
+      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      const int64_t e = 3 * i + lane;
+      const double own = d.diag[i] * src[e] + acc;
+      if (mode == 0) {
+        d.w[e] = own;
+        v[lane] += own * src[e];
+      } else {
+        const double rk = d.b[e] - own;
+        d.r[e] = rk;
+        v[lane] += rk * rk;
+      }
+    }
+  }
+  write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
+}
+
+// One block per replica: reduce the replica's tile partials in a fixed
+// order and advance its recurrences.  mode 0: after a fresh start, 1: after
+// a restart, 2: after an iteration, 3: after a true-residual check.
+__global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
+  const int rid = blockIdx.x;
+  const RepDev& R = d.rep[rid];
+  CgRep& c = d.cg[rid];
+  const bool work = (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
+                    (mode == 3 && c.check);
+  if (!work) return;
+  __shared__ double lds[16][9];
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int t = threadIdx.x; t < R.nblk; t += blockDim.x) {
+    const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += src[k];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) lds[wave][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[9];
+  for (int k = 0; k < 9; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w][k];
+    tot[k] = s;
+  }
+  int finished = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double gam = tot[k], del = tot[3 + k], rr = tot[6 + k];
+    if (mode == 0 || (mode == 1 && c.state[k] == 3)) {
+      if (mode == 0) c.bb[k] = rr;
+      c.rr[k] = rr;
+      if (c.bb[k] == 0.0) {  // b = 0: x = 0 is exact
+        c.state[k] = 2;
+        ++finished;
+      } else if (rr <= c.tol2 * c.bb[k]) {
+        c.state[k] = 1;
+      } else if (!(del > 0.0)) {
+        c.state[k] = 2;
+        c.breakdown = 1;
+        ++finished;
+      } else {
+        c.state[k] = 0;
+        c.gamma[k] = gam;
+        c.alpha[k] = gam / del;
+        c.beta[k] = 0.0;
+      }
+    } else if (mode == 2 && c.state[k] == 0) {
+      c.it[k] += 1;
+      c.rr[k] = rr;
+      if (rr <= c.tol2 * c.bb[k]) {
+        c.state[k] = 1;
+      } else {
+        const double beta = gam / c.gamma[k];
+        const double den = del - beta * gam / c.alpha[k];
+        if (!(den > 0.0)) {
+          c.state[k] = 2;
+          c.breakdown = 1;
+          ++finished;
+        } else {
+          c.beta[k] = beta;
+          c.alpha[k] = gam / den;
+          c.gamma[k] = gam;
+        }
+      }
+    } else if (mode == 3 && c.state[k] == 1) {
+      c.rr[k] = rr;
+      if (rr <= c.tol2 * c.bb[k]) {
+        c.state[k] = 2;
+        ++finished;
+      } else {
+        c.state[k] = 3;
+        c.restarts += 1;
+      }
+    }
+  }
+  int run = 0, pend = 0, rst = 0;
+  for (int k = 0; k < 3; ++k) {
+    run |= c.state[k] == 0;
+    pend |= c.state[k] == 1;
+    rst |= c.state[k] == 3;
+  }
+  c.run = run;
+  c.check = !run && pend;
+  c.restart = rst;
+  if (finished) atomicSub(&d.ctrl->n_notdone, finished);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(256), 0, s, d, tol_override);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s) {
+  const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
+  if (d.spmv_fp32 && mode == 0)
+    hipLaunchKernelGGL(k_cg_spmv<true>, g, b, 0, s, d, mode, start_mode);
+  else
+    hipLaunchKernelGGL(k_cg_spmv<false>, g, b, 0, s, d, mode, start_mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_finish, dim3(d.nrep), dim3(1024), 0, s, d, mode);
+  return hipGetLastError();
+}

@@ -9,6 +9,8 @@
 #include "sim_dev.h"
 #include "launch.h"
 
+#include <algorithm>
+
 // ===========================================================================
 // small utilities
 // ===========================================================================
@@ -206,46 +208,64 @@ __device__ __forceinline__ double force_coef(const RepDev& R, double r2, double 
   return 0.0;
 }
 
-// One row per thread: the same candidate order as k_nbr_count; writes the
-// row's CSR entries (-alpha*w), diag = gamma0 + alpha*sum w, 1/diag and the
-// three right-hand sides (Couette drive, conservative force, boundary
-// velocity term of Eq. 8, thermal force).
-__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_fill(DevPtrs d, int64_t step,
-                                                            double* __restrict__ dinv) {
+// Neighbour list: the same candidate order as k_nbr_count; each passing
+// candidate's sorted row index goes to col[rowptr[i] + slot].
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d, int64_t step) {
   const int blk = blockIdx.x;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   const double delta = le_offset(R, step);
-  const double drag_unit = R.alpha * (R.shear * R.L[1]);
   for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
     const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    if (i - R.row_off >= R.n) {
-      d.diag[i] = 1.0;
-      dinv[i] = 1.0;
-      d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
+    if (i - R.row_off >= R.n) continue;
+    const int64_t e1 = d.rowptr[i + 1];
+    if (e1 > d.nnz_cap) {
+      atomicOr(&d.ctrl->overflow, 1);
       continue;
     }
-    const int64_t e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    const bool fits = e1 <= d.nnz_cap;
-    if (!fits) atomicOr(&d.ctrl->overflow, 1);
+    int64_t e = d.rowptr[i];
+    const double4 pi = d.pos[i];
+    for_candidates(R, d.cell_row, delta, pi.x, pi.y, pi.z, i, [&](int j) {
+      const double4 pj = d.pos[j];
+      double dx, dy, dz;
+      le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+      if (dist2(dx, dy, dz) < R.rc2) d.col[e++] = j;
+    });
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->nnz = d.rowptr[d.rows];
+}
+
+// Pair terms and assembly, PAIR_LANES lanes per row over the row's CSR
+// entries: -alpha*w_ij into val, diag = gamma0 + alpha*sum w, 1/diag, and the
+// three right-hand sides: Couette drive (Eq. 6c), conservative force
+// (Eq. 6b), boundary velocity term of Eq. 8, thermal force.
+#define PAIR_LANES 4
+#define PAIR_THREADS 256  // fewer threads per block: the pair noise needs ~130 registers
+__global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d, int64_t step) {
+  const int blk = blockIdx.x;
+  const RepDev& R = d.rep[d.blk_rep[blk]];
+  if (d.ctrl->overflow) return;
+  const double delta = le_offset(R, step);
+  const double drag_unit = R.alpha * (R.shear * R.L[1]);
+  const int lane = threadIdx.x & (PAIR_LANES - 1);
+  const int grp = threadIdx.x / PAIR_LANES;
+  constexpr int GROUPS = PAIR_THREADS / PAIR_LANES;
+  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
+    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + pass * GROUPS + grp;
+    const bool real = i - R.row_off < R.n;
     const double4 pi = d.pos[i];
     const int64_t idi = (int64_t)pi.w;
-    double wsum = 0.0, ws = 0.0;
-    double bx = 0.0, by = 0.0, bz = 0.0;
-    int64_t e = e0;
-    for_candidates(R, d.cell_row, delta, pi.x, pi.y, pi.z, i, [&](int j) {
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double wsum = 0.0, ws = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+    for (int e = e0 + lane; e < e1; e += PAIR_LANES) {
+      const int j = d.col[e];
       const double4 pj = d.pos[j];
       double dx, dy, dz;
       const int s = le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
       const double r2 = dist2(dx, dy, dz);
-      if (!(r2 < R.rc2)) return;
       const double r = sqrt(r2);
       const double w = pair_weight(R, r2, r);
-      if (fits) {
-        d.col[e] = j;
-        d.val[e] = -R.alpha * w;
-        d.valf[e] = (float)(-R.alpha * w);
-      }
-      ++e;
+      d.val[e] = -R.alpha * w;
+      d.valf[e] = (float)(-R.alpha * w);
       wsum += w;
       ws += w * (double)s;
       const double fc = force_coef(R, r2, r);
@@ -267,107 +287,39 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_fill(DevPtrs d, int64_t s
         by += amp * g[1];
         bz += amp * g[2];
       }
-    });
-    const double dg = R.gamma0 + R.alpha * wsum;
-    d.diag[i] = dg;
-    dinv[i] = 1.0 / dg;
-    double gx = 0.0, gy = 0.0, gz = 0.0;
+    }
+#pragma unroll
+    for (int o = 1; o < PAIR_LANES; o <<= 1) {
+      wsum += __shfl_xor(wsum, o, 64);
+      ws += __shfl_xor(ws, o, 64);
+      bx += __shfl_xor(bx, o, 64);
+      by += __shfl_xor(by, o, 64);
+      bz += __shfl_xor(bz, o, 64);
+    }
+    if (!real) {
+      if (lane == 0) { d.diag[i] = 1.0; d.dinv[i] = 1.0; }
+      if (lane < 3) d.b[3 * i + lane] = 0.0;
+      continue;
+    }
+    double g[3] = {0.0, 0.0, 0.0};
     if (R.amp_node != 0.0) {
-      double g[3];
       if (d.inj_xi) {
         g[0] = d.inj_xi[3 * idi]; g[1] = d.inj_xi[3 * idi + 1]; g[2] = d.inj_xi[3 * idi + 2];
       } else {
         gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, g);
       }
-      gx = R.amp_node * g[0];
-      gy = R.amp_node * g[1];
-      gz = R.amp_node * g[2];
     }
-    d.b[3 * i + 0] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + gx + bx + drag_unit * ws;
-    d.b[3 * i + 1] = gy + by;
-    d.b[3 * i + 2] = gz + bz;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->nnz = d.rowptr[d.rows];
-}
-
-// ===========================================================================
-// a6: preconditioned conjugate gradients, three right-hand sides, one
-// recurrence per (replica, component).  Per iteration:
-//   k_cg_spmm   q = A p, p.q           -> last block: alpha = rz / pq
-//   k_cg_update x += alpha p, r -= alpha q, z = r/d, r.z, r.r
-//                                      -> last block: convergence, beta
-//   k_cg_pdir   p = z + beta p
-// Finished replicas skip their blocks; when nothing iterates the launches
-// return at once, so the host can queue iterations ahead of the readback.
-// ===========================================================================
-
-// Partial sums of one block -> per-replica totals, computed by the last
-// block of that replica to arrive (integer arrival counter, device-scope
-// fences).  Returns true in every thread of the finishing block; the totals
-// are then in tot[] of thread 0.
-template <int K>
-__device__ __forceinline__ bool reduce_to_replica(const DevPtrs& d, int rep_id, int blk,
-                                                  double (&v)[K], double (&tot)[K]) {
-  __shared__ double lds[BLOCK_THREADS / 64][NPART];
-  __shared__ int is_last;
-  const RepDev& R = d.rep[rep_id];
-  // block sum
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
     if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) lds[wave][k] = v[k];
+      const double dg = R.gamma0 + R.alpha * wsum;
+      d.diag[i] = dg;
+      d.dinv[i] = 1.0 / dg;
+      d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * g[0] + bx + drag_unit * ws;
+    } else if (lane == 1) {
+      d.b[3 * i + 1] = R.amp_node * g[1] + by;
+    } else if (lane == 2) {
+      d.b[3 * i + 2] = R.amp_node * g[2] + bz;
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double* dst = d.partial + (int64_t)blk * NPART;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][k];
-      __hip_atomic_store(dst + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    const int ticket = atomicAdd(&d.arrive[rep_id], 1);
-    is_last = (ticket == R.nblk - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  // deterministic: thread t sums blocks t, t+256, ... in order, then the tree
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < R.nblk; b += BLOCK_THREADS) {
-    const double* src = d.partial + (int64_t)(R.blk_off + b) * NPART;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      acc[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) lds[wave][k] = acc[k];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][k];
-      tot[k] = s;
-    }
-    d.arrive[rep_id] = 0;
-  }
-  return true;
 }
 
 __global__ void k_ctrl_zero(Ctrl* c) {
@@ -376,252 +328,6 @@ __global__ void k_ctrl_zero(Ctrl* c) {
     c->numeric = 0;
     c->max_row = 0;
     c->nnz = 0;
-  }
-}
-
-__global__ void k_cg_reset(DevPtrs d) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r == 0) {
-    d.ctrl->n_iterating = 0;
-    d.ctrl->n_pending = 0;
-  }
-  if (r < d.nrep) {
-    CgRep& c = d.cg[r];
-    for (int k = 0; k < 3; ++k) {
-      c.bb[k] = c.rz[k] = c.rr[k] = c.alpha[k] = c.beta[k] = 0.0;
-      c.state[k] = 2;
-      c.it[k] = 0;
-    }
-    c.active = 0;
-    c.restarts = 0;
-    c.breakdown = 0;
-    d.arrive[r] = 0;
-  }
-}
-
-// x = 0, r = b, z = r/d, p = z; totals b.b and r.z
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_init(DevPtrs d, const double* __restrict__ dinv) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
-  const int rid = d.blk_rep[blk];
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    const double di = dinv[i];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double bk = d.b[3 * i + k];
-      const double z = bk * di;
-      d.x[3 * i + k] = 0.0;
-      d.r[3 * i + k] = bk;
-      d.p[3 * i + k] = z;
-      v[k] += bk * bk;
-      v[3 + k] += bk * z;
-    }
-  }
-  double tot[6];
-  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
-  if (threadIdx.x == 0) {
-    CgRep& c = d.cg[rid];
-    int live = 0;
-    for (int k = 0; k < 3; ++k) {
-      c.bb[k] = tot[k];
-      c.rr[k] = tot[k];
-      c.rz[k] = tot[3 + k];
-      c.it[k] = 0;
-      c.state[k] = tot[k] > 0.0 ? 0 : 2;
-      live += c.state[k] == 0;
-    }
-    c.active = live > 0;
-    if (live) atomicAdd(&d.ctrl->n_iterating, live);
-  }
-}
-
-// q = A p (CSR, one row per thread), totals p.q; then alpha = rz / pq
-template <bool FP32>
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmm(DevPtrs d) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
-  const int rid = d.blk_rep[blk];
-  if (!d.cg[rid].active) return;
-  const double* __restrict__ p = d.p;
-  double v[3] = {0, 0, 0};
-  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    const double p0 = p[3 * i], p1 = p[3 * i + 1], p2 = p[3 * i + 2];
-    const double dg = d.diag[i];
-    double q0 = dg * p0, q1 = dg * p1, q2 = dg * p2;
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    for (int e = e0; e < e1; ++e) {
-      const int64_t j = d.col[e];
-      const double a = FP32 ? (double)d.valf[e] : d.val[e];
-      q0 += a * p[3 * j];
-      q1 += a * p[3 * j + 1];
-      q2 += a * p[3 * j + 2];
-    }
-    d.q[3 * i] = q0;
-    d.q[3 * i + 1] = q1;
-    d.q[3 * i + 2] = q2;
-    v[0] += p0 * q0;
-    v[1] += p1 * q1;
-    v[2] += p2 * q2;
-  }
-  double tot[3];
-  if (!reduce_to_replica<3>(d, rid, blk, v, tot)) return;
-  if (threadIdx.x == 0) {
-    CgRep& c = d.cg[rid];
-    for (int k = 0; k < 3; ++k) {
-      if (c.state[k] != 0) { c.alpha[k] = 0.0; continue; }
-      if (!(tot[k] > 0.0)) {  // breakdown: stop this component
-        c.alpha[k] = 0.0;
-        c.state[k] = 2;
-        c.breakdown = 1;
-        atomicSub(&d.ctrl->n_iterating, 1);
-        continue;
-      }
-      c.alpha[k] = c.rz[k] / tot[k];
-    }
-    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
-  }
-}
-
-// x += alpha p, r -= alpha q; totals r.z (z = r/d) and r.r; convergence, beta
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_update(DevPtrs d,
-                                                             const double* __restrict__ dinv) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
-  const int rid = d.blk_rep[blk];
-  const CgRep& cr = d.cg[rid];
-  if (!cr.active) return;
-  double al[3];
-  bool on[3];
-  for (int k = 0; k < 3; ++k) {
-    al[k] = cr.alpha[k];
-    on[k] = cr.state[k] == 0;
-  }
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    const double di = dinv[i];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (!on[k]) continue;
-      const double xn = d.x[3 * i + k] + al[k] * d.p[3 * i + k];
-      const double rn = d.r[3 * i + k] - al[k] * d.q[3 * i + k];
-      d.x[3 * i + k] = xn;
-      d.r[3 * i + k] = rn;
-      v[k] += rn * (rn * di);
-      v[3 + k] += rn * rn;
-    }
-  }
-  double tot[6];
-  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
-  if (threadIdx.x == 0) {
-    CgRep& c = d.cg[rid];
-    const double tol2 = d.rep[rid].tol2;
-    for (int k = 0; k < 3; ++k) {
-      if (c.state[k] != 0) continue;
-      c.it[k] += 1;
-      c.rr[k] = tot[3 + k];
-      if (tot[3 + k] <= tol2 * c.bb[k]) {
-        c.state[k] = 1;
-        c.beta[k] = 0.0;
-        atomicSub(&d.ctrl->n_iterating, 1);
-        atomicAdd(&d.ctrl->n_pending, 1);
-      } else {
-        c.beta[k] = tot[k] / c.rz[k];
-        c.rz[k] = tot[k];
-      }
-    }
-    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
-  }
-}
-
-// p = r/d + beta p
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_pdir(DevPtrs d, const double* __restrict__ dinv) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
-  const int rid = d.blk_rep[blk];
-  const CgRep& cr = d.cg[rid];
-  if (!cr.active) return;
-  double be[3];
-  bool on[3];
-  for (int k = 0; k < 3; ++k) {
-    be[k] = cr.beta[k];
-    on[k] = cr.state[k] == 0;
-  }
-  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    const double di = dinv[i];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (!on[k]) continue;
-      d.p[3 * i + k] = d.r[3 * i + k] * di + be[k] * d.p[3 * i + k];
-    }
-  }
-}
-
-// True-residual check of components whose recursive residual passed:
-// r = b - A x (FP64 matrix), z = r/d, p = z; a component whose true
-// residual fails the tolerance restarts from there.  A replica is checked
-// once none of its components iterates (a per-replica condition, so every
-// block of a replica takes the same branch).
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_check(DevPtrs d, const double* __restrict__ dinv) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
-  const int rid = d.blk_rep[blk];
-  const CgRep& cr = d.cg[rid];
-  if (cr.active) return;
-  bool on[3];
-  int any = 0;
-  for (int k = 0; k < 3; ++k) {
-    on[k] = cr.state[k] == 1;
-    any |= on[k];
-  }
-  if (!any) return;
-  const double* __restrict__ x = d.x;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
-    const double dg = d.diag[i], di = dinv[i];
-    double ax[3] = {dg * x[3 * i], dg * x[3 * i + 1], dg * x[3 * i + 2]};
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    for (int e = e0; e < e1; ++e) {
-      const int64_t j = d.col[e];
-      const double a = d.val[e];
-      ax[0] += a * x[3 * j];
-      ax[1] += a * x[3 * j + 1];
-      ax[2] += a * x[3 * j + 2];
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (!on[k]) continue;
-      const double rk = d.b[3 * i + k] - ax[k];
-      d.r[3 * i + k] = rk;
-      d.p[3 * i + k] = rk * di;
-      v[k] += rk * rk;
-      v[3 + k] += rk * (rk * di);
-    }
-  }
-  double tot[6];
-  if (!reduce_to_replica<6>(d, rid, blk, v, tot)) return;
-  if (threadIdx.x == 0) {
-    CgRep& c = d.cg[rid];
-    const double tol2 = d.rep[rid].tol2;
-    for (int k = 0; k < 3; ++k) {
-      if (c.state[k] != 1) continue;
-      c.rr[k] = tot[k];
-      atomicSub(&d.ctrl->n_pending, 1);
-      if (tot[k] <= tol2 * c.bb[k]) {
-        c.state[k] = 2;
-      } else {
-        c.state[k] = 0;
-        c.rz[k] = tot[3 + k];
-        c.restarts += 1;
-        atomicAdd(&d.ctrl->n_iterating, 1);
-      }
-    }
-    c.active = (c.state[0] == 0) | (c.state[1] == 0) | (c.state[2] == 0);
   }
 }
 
@@ -738,10 +444,27 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_export_system(DevPtrs d, cons
   }
 }
 
+// plain 16-byte-per-lane copy (bandwidth reference)
+__global__ __launch_bounds__(BLOCK_THREADS) void k_copy16(const uint4* __restrict__ src,
+                                                          uint4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
 // ===========================================================================
 // host launchers (C++ linkage, used by sim_api.hip)
 // ===========================================================================
 static inline unsigned nb_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n16 = bytes / 16;
+  const int64_t want = (n16 + BLOCK_THREADS * 4 - 1) / (BLOCK_THREADS * 4);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16));
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(BLOCK_THREADS), 0, s, (const uint4*)src,
+                     (uint4*)dst, n16);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -779,33 +502,16 @@ hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s) {
   hipLaunchKernelGGL(k_nbr_count, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step);
   return hipGetLastError();
 }
-hipError_t launch_nbr_fill(const DevPtrs& d, int64_t step, double* dinv, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_fill, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step, dinv);
+hipError_t launch_nbr_list(const DevPtrs& d, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_list, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step);
+  return hipGetLastError();
+}
+hipError_t launch_pair_terms(const DevPtrs& d, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_terms, dim3(d.nblk), dim3(PAIR_THREADS), 0, s, d, step);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_zero, dim3(1), dim3(64), 0, s, d.ctrl);
-  return hipGetLastError();
-}
-hipError_t launch_cg_reset(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_reset, dim3(nb_of(d.nrep, 64)), dim3(64), 0, s, d);
-  return hipGetLastError();
-}
-hipError_t launch_cg_init(const DevPtrs& d, const double* dinv, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
-  return hipGetLastError();
-}
-hipError_t launch_cg_iteration(const DevPtrs& d, const double* dinv, hipStream_t s) {
-  if (d.spmv_fp32)
-    hipLaunchKernelGGL(k_cg_spmm<true>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
-  else
-    hipLaunchKernelGGL(k_cg_spmm<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
-  hipLaunchKernelGGL(k_cg_update, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
-  hipLaunchKernelGGL(k_cg_pdir, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
-  return hipGetLastError();
-}
-hipError_t launch_cg_check(const DevPtrs& d, const double* dinv, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_check, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, dinv);
   return hipGetLastError();
 }
 hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s) {

@@ -12,11 +12,8 @@ hipError_t launch_scatter(const DevPtrs& d, hipStream_t s);
 hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s);
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s);
 hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s);
-hipError_t launch_nbr_fill(const DevPtrs& d, int64_t step, double* dinv, hipStream_t s);
-hipError_t launch_cg_reset(const DevPtrs& d, hipStream_t s);
-hipError_t launch_cg_init(const DevPtrs& d, const double* dinv, hipStream_t s);
-hipError_t launch_cg_iteration(const DevPtrs& d, const double* dinv, hipStream_t s);
-hipError_t launch_cg_check(const DevPtrs& d, const double* dinv, hipStream_t s);
+hipError_t launch_nbr_list(const DevPtrs& d, int64_t step, hipStream_t s);
+hipError_t launch_pair_terms(const DevPtrs& d, int64_t step, hipStream_t s);
 hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s);
 hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, hipStream_t s);
 hipError_t launch_permute(const DevPtrs& d, const int64_t* id_off, int mode, const double* in,
@@ -26,3 +23,8 @@ hipError_t launch_export_pairs(const DevPtrs& d, int64_t* out, int64_t cap,
 hipError_t launch_export_system(const DevPtrs& d, const int64_t* id_off, int64_t* rows,
                                 int64_t* cols, double* vals, int64_t cap, double* diag,
                                 double* rhs, hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
+hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s);
+hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s);
+hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s);
+hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s);

@@ -3,8 +3,8 @@
 // The handle owns every device buffer (hipMalloc at creation, grown only
 // when the neighbour list outgrows its capacity).  One step queues:
 //   ctrl reset, binning, cell scan, scatter, per-cell id sort,
-//   neighbour count, row scan, neighbour fill (pairs, A, b),
-//   CG init, chunks of CG iterations + true-residual check,
+//   neighbour count, row scan, neighbour list, pair terms (A and b),
+//   CG start, chunks of CG iterations + true-residual check,
 // reads the small control block back once per chunk, then queues the
 // position update and reads the control block once more before it commits.
 #include <hip/hip_runtime.h>
@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <climits>
 #include <new>
 #include <vector>
 
@@ -51,7 +52,6 @@ struct sim_t {
   int32_t last_iters = 0;
   DevPtrs d{};
   RepDev* rep_d = nullptr;
-  double* dinv = nullptr;
   int32_t* scan_tmp = nullptr;
   int32_t* bsum = nullptr;
   int64_t* id_off_d = nullptr;
@@ -63,7 +63,16 @@ struct sim_t {
   double* inj_eta = nullptr;
   std::vector<void*> allocs;
   int32_t restarts_last = 0;
+  // kernel timing probe
+  int32_t prof_every = 0;
+  std::vector<hipEvent_t> prof_ev;      // pool of event pairs
+  struct Sample { int kernel; int iter; int ev; float ms; };
+  std::vector<Sample> prof_pending;     // recorded in the current solve
+  sim_kernel_prof prof_acc[3] = {};
 };
+
+static const int kProfKernels = 3;
+static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_finish"};
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -195,7 +204,8 @@ static int build_system(sim_t* s, int64_t step) {
   HIPCHK(launch_cell_sort(d, st));
   HIPCHK(launch_nbr_count(d, step, st));
   HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
-  HIPCHK(launch_nbr_fill(d, step, s->dinv, st));
+  HIPCHK(launch_nbr_list(d, step, st));
+  HIPCHK(launch_pair_terms(d, step, st));
   return SIM_OK;
 }
 
@@ -214,55 +224,67 @@ static int grow_and_refill(sim_t* s, int64_t step) {
   if (rc) return rc;
   if (need > s->d.nnz_cap) return SIM_ENOMEM;
   HIPCHK(launch_ctrl_zero(s->d, s->stream));
-  HIPCHK(launch_nbr_fill(s->d, step, s->dinv, s->stream));
+  HIPCHK(launch_nbr_list(s->d, step, s->stream));
+  HIPCHK(launch_pair_terms(s->d, step, s->stream));
   return SIM_OK;
 }
 
 // a6: CG on the current system (b in d.b), x0 = 0.  tol > 0 overrides the
-// replicas' own tolerances.  Returns SIM_EOVERFLOW_INTERNAL if the fill
+// replicas' own tolerances.  Iterations are queued in chunks without host
+// synchronisation (finished replicas' blocks return at once); the control
+// block is read once per chunk.  Returns SIM_EOVERFLOW_INTERNAL if the fill
 // overflowed (nothing solved).
 static int cg_solve(sim_t* s, double tol, sim_stats* st) {
   DevPtrs& d = s->d;
   hipStream_t stream = s->stream;
   int maxit = 1;
   for (auto& p : s->prm) maxit = std::max(maxit, p.cg_maxit);
-  HIPCHK(launch_cg_reset(d, stream));
-  if (tol > 0.0) {
-    // per-call tolerance: written into the replica table copy used by the finishers
-    for (auto& R : s->reph) R.tol2 = tol * tol;
-    HIPCHK(hipMemcpyAsync(s->rep_d, s->reph.data(), sizeof(RepDev) * (size_t)s->R,
-                          hipMemcpyHostToDevice, stream));
-  }
-  HIPCHK(launch_cg_init(d, s->dinv, stream));
+  HIPCHK(launch_cg_reset(d, tol, stream));
+  HIPCHK(launch_cg_vec(d, 0, stream));
+  HIPCHK(launch_cg_spmv(d, 0, 0, stream));
+  HIPCHK(launch_cg_finish(d, 0, stream));
   int launched = 0;
-  int chunk = s->last_iters > 2 ? s->last_iters - 1 : 4;
+  int chunk = s->last_iters > 2 ? s->last_iters - 1 : 8;
   int status = SIM_OK;
   for (;;) {
     int n = std::min(chunk, maxit + 1 - launched);
     if (n < 1) n = 1;
-    for (int k = 0; k < n; ++k) HIPCHK(launch_cg_iteration(d, s->dinv, stream));
+    for (int k = 0; k < n; ++k) {
+      const int g = launched + k;
+      const bool probe = s->prof_every > 0 && g % s->prof_every == 0 &&
+                         (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
+      for (int kern = 0; kern < kProfKernels; ++kern) {
+        int ev = -1;
+        if (probe) {
+          ev = (int)s->prof_pending.size();
+          s->prof_pending.push_back({kern, g, ev, 0.0f});
+          HIPCHK(hipEventRecord(s->prof_ev[2 * ev], stream));
+        }
+        if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream));
+        else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream));
+        else HIPCHK(launch_cg_finish(d, 2, stream));
+        if (probe) HIPCHK(hipEventRecord(s->prof_ev[2 * ev + 1], stream));
+      }
+    }
     launched += n;
-    HIPCHK(launch_cg_check(d, s->dinv, stream));
+    // true-residual checks of replicas whose components all passed, and
+    // restarts of the components that failed them
+    HIPCHK(launch_cg_spmv(d, 1, 0, stream));
+    HIPCHK(launch_cg_finish(d, 3, stream));
+    HIPCHK(launch_cg_vec(d, 1, stream));
+    HIPCHK(launch_cg_spmv(d, 0, 1, stream));
+    HIPCHK(launch_cg_finish(d, 1, stream));
     int rc = read_ctrl(s, true);
     if (rc) return rc;
     if (s->ctrl_h->overflow) { status = SIM_EOVERFLOW_INTERNAL; break; }
-    if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending == 0) break;
-    if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending > 0) {
-      // checks were pending at the end of the chunk: run them now
-      HIPCHK(launch_cg_check(d, s->dinv, stream));
-      rc = read_ctrl(s, true);
-      if (rc) return rc;
-      if (s->ctrl_h->n_iterating == 0 && s->ctrl_h->n_pending == 0) break;
-    }
+    if (s->ctrl_h->n_notdone == 0) break;
     if (launched > maxit) { status = SIM_ENOCONV; break; }
     chunk = 2;
   }
-  if (tol > 0.0) {
-    for (int r = 0; r < s->R; ++r) s->reph[r].tol2 = s->prm[r].cg_tol * s->prm[r].cg_tol;
-    HIPCHK(hipMemcpyAsync(s->rep_d, s->reph.data(), sizeof(RepDev) * (size_t)s->R,
-                          hipMemcpyHostToDevice, stream));
+  if (status == SIM_EOVERFLOW_INTERNAL) {
+    s->prof_pending.clear();
+    return status;
   }
-  if (status == SIM_EOVERFLOW_INTERNAL) return status;
   int itmax = 0, restarts = 0, breakdown = 0;
   int iters[3] = {0, 0, 0};
   double relres[3] = {0, 0, 0};
@@ -278,12 +300,38 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
     breakdown |= c.breakdown;
   }
   s->last_iters = itmax;
+  if (!s->prof_pending.empty()) {
+    // keep launches in which every component of every replica iterated
+    int itmin = INT32_MAX;
+    for (int r = 0; r < s->R; ++r)
+      for (int k = 0; k < 3; ++k)
+        if (s->cg_h[r].bb[k] > 0.0) itmin = std::min(itmin, s->cg_h[r].it[k]);
+    const double rows = (double)s->rows, nnz = (double)s->ctrl_h->nnz;
+    const double ntile = (double)d.nblk;
+    const double per_launch[kProfKernels] = {
+        // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written (120)
+        rows * 248.0 + ntile * 6.0 * 8.0,
+        // product: row pointers (4), u (24), diag (8), w written (24), CSR col + value
+        rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0,
+        // finish: the tile partials
+        ntile * 9.0 * 8.0};
+    for (auto& smp : s->prof_pending) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[2 * smp.ev], s->prof_ev[2 * smp.ev + 1]));
+      if (smp.iter >= itmin - 1) continue;
+      sim_kernel_prof& acc = s->prof_acc[smp.kernel];
+      acc.launches += 1;
+      acc.ms += ms;
+      acc.bytes += per_launch[smp.kernel];
+    }
+    s->prof_pending.clear();
+  }
   if (st) {
     for (int k = 0; k < 3; ++k) {
-      st->iters[k] = iters[k];
-      st->relres[k] = relres[k];
+      st->iters[k] = std::max(st->iters[k], iters[k]);
+      st->relres[k] = std::max(st->relres[k], relres[k]);
     }
-    st->restarts = restarts;
+    st->restarts = std::max(st->restarts, restarts);
     st->nnz = s->ctrl_h->nnz;
     st->max_row = s->ctrl_h->max_row;
     st->cg_iters_total += itmax;
@@ -344,6 +392,7 @@ void sim_destroy(sim_t* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   for (void* p : s->allocs) (void)hipFree(p);
+  for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->ctrl_h) (void)hipHostFree(s->ctrl_h);
   if (s->cg_h) (void)hipHostFree(s->cg_h);
   delete s;
@@ -424,7 +473,6 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   int32_t* blk_rep_d = nullptr;
   ALLOC(blk_rep_d, sizeof(int32_t) * d.nblk);
   d.blk_rep = blk_rep_d;
-  ALLOC(d.arrive, sizeof(int32_t) * replicas);
   ALLOC(d.partial, sizeof(double) * NPART * d.nblk);
   ALLOC(d.pos, sizeof(double4) * rows);
   ALLOC(d.pos_alt, sizeof(double4) * rows);
@@ -437,12 +485,14 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   ALLOC(d.rowlen, sizeof(int32_t) * (rows + 1));
   ALLOC(d.rowptr, sizeof(int32_t) * (rows + 1));
   ALLOC(d.diag, sizeof(double) * rows);
-  ALLOC(s->dinv, sizeof(double) * rows);
+  ALLOC(d.dinv, sizeof(double) * rows);
   ALLOC(d.b, sizeof(double) * 3 * rows);
   ALLOC(d.x, sizeof(double) * 3 * rows);
-  ALLOC(d.r, sizeof(double) * 3 * rows);
   ALLOC(d.p, sizeof(double) * 3 * rows);
-  ALLOC(d.q, sizeof(double) * 3 * rows);
+  ALLOC(d.r, sizeof(double) * 3 * rows);
+  ALLOC(d.s, sizeof(double) * 3 * rows);
+  ALLOC(d.w, sizeof(double) * 3 * rows);
+  ALLOC(d.u, sizeof(double) * 3 * rows);
   ALLOC(d.vel_orig, sizeof(double) * 3 * (size_t)n_total);
   ALLOC(s->io, sizeof(double) * 3 * (size_t)n_total);
   ALLOC(s->id_off_d, sizeof(int64_t) * replicas);
@@ -485,7 +535,6 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   if ((e = hipMemset(d.rowptr, 0, sizeof(int32_t) * (rows + 1)))) return fail(e, "clear rowptr");
   if ((e = hipMemset(d.x, 0, sizeof(double) * 3 * rows))) return fail(e, "clear x");
   if ((e = hipMemset(d.vel_orig, 0, sizeof(double) * 3 * n_total))) return fail(e, "clear vel");
-  if ((e = hipMemset(d.arrive, 0, sizeof(int32_t) * replicas))) return fail(e, "clear arrive");
   if ((e = hipMemset(d.ctrl, 0, sizeof(Ctrl)))) return fail(e, "clear ctrl");
   if ((e = hipMemset(d.cg, 0, sizeof(CgRep) * replicas))) return fail(e, "clear cg");
   // padding rows of the second position buffer stay inert too
@@ -626,6 +675,48 @@ int sim_debug_system(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64
   dfree(s, v_d);
   dfree(s, dg_d);
   dfree(s, b_d);
+  return SIM_OK;
+}
+
+int sim_profile_enable(sim_t* s, int32_t sample_every) {
+  if (!s || sample_every < 0) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (sample_every > 0 && s->prof_ev.empty()) {
+    s->prof_ev.resize(2 * kProfKernels * 256);
+    for (auto& e : s->prof_ev) HIPCHK(hipEventCreate(&e));
+  }
+  s->prof_every = sample_every;
+  return SIM_OK;
+}
+
+int sim_profile_read(sim_t* s, sim_kernel_prof* out, int32_t cap, int32_t* count, int32_t reset) {
+  if (!s || !count || cap < 0 || (cap > 0 && !out)) return SIM_EINVAL;
+  *count = kProfKernels;
+  for (int k = 0; k < kProfKernels && k < cap; ++k) {
+    out[k] = s->prof_acc[k];
+    std::snprintf(out[k].name, sizeof(out[k].name), "%s", kProfNames[k]);
+  }
+  if (reset) std::memset(s->prof_acc, 0, sizeof(s->prof_acc));
+  return cap < kProfKernels ? SIM_ECAPACITY : SIM_OK;
+}
+
+int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* stream,
+                   double* ms_avg) {
+  if (!src || !dst || bytes <= 0 || bytes % 16 || reps < 1 || !ms_avg) return SIM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(launch_copy16(src, dst, bytes, st));  // untimed first touch
+  HIPCHK(hipEventRecord(e0, st));
+  for (int k = 0; k < reps; ++k) HIPCHK(launch_copy16(src, dst, bytes, st));
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_avg = (double)ms / reps;
   return SIM_OK;
 }
 

@@ -8,15 +8,15 @@
 //   cellidx  int32[rows]     global cell of each particle
 //   rowptr   int32[rows+1]   CSR of the off-diagonal part of A, full rows
 //   col/val  int32/double    -alpha*w_ij per directed pair (valf: FP32 copy)
-//   diag     double[rows]    gamma0 + alpha*sum_j w_ij
-//   b,x,r,p,q double[3*rows] the three right-hand sides / CG vectors, AoS
+//   diag     double[rows]    gamma0 + alpha*sum_j w_ij (dinv = 1/diag)
+//   b, x, p, r, s, w, u   double[3*rows]  right-hand sides and the CG vectors
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #define ROWS_PER_BLOCK 1024
-#define BLOCK_THREADS 256
-#define NPART 8  // doubles per block partial slot
+#define BLOCK_THREADS 1024
+#define NPART 16  // doubles per tile partial slot (9 used)
 
 // ---------------------------------------------------------------------------
 // Per-replica constants (device copy built at creation)
@@ -42,16 +42,20 @@ struct RepDev {
   uint64_t seed, stream;
 };
 
-// Per-replica conjugate-gradient scalars (three components)
+// Per-replica conjugate-gradient scalars (three components), written only by
+// the finishing kernel and read by the row kernels that follow it.
 struct CgRep {
   double bb[3];     // ||b||^2
-  double rz[3];     // r.z of the current iterate
-  double rr[3];     // ||r||^2 (recursive, or true after a check)
+  double rr[3];     // ||r||^2 (recursive while iterating, true after a check)
+  double gamma[3];  // (r, M^-1 r) of the current iterate
   double alpha[3];
   double beta[3];
-  int32_t state[3]; // 0 iterating, 1 recursive residual below tol (check pending), 2 done
+  double tol2;      // tolerance^2 of this solve
+  int32_t state[3]; // 0 iterating, 1 check pending, 2 done, 3 restart pending
   int32_t it[3];
-  int32_t active;   // any component iterating
+  int32_t run;      // some component iterating
+  int32_t check;    // none iterating and some check pending
+  int32_t restart;  // some restart pending
   int32_t restarts;
   int32_t breakdown;
   int32_t pad;
@@ -59,12 +63,10 @@ struct CgRep {
 
 // Global control words (one per handle)
 struct Ctrl {
-  int32_t n_iterating;  // (replica, component) pairs iterating
-  int32_t n_pending;    // pairs waiting for the true-residual check
+  int32_t n_notdone;    // (replica, component) pairs not finished
   int32_t overflow;     // CSR capacity exceeded in the last fill
-  int32_t numeric;      // non-finite position after an update
+  int32_t numeric;      // non-finite or escaped position after an update
   int32_t max_row;      // longest off-diagonal row of the last build
-  int32_t pad0;
   int64_t nnz;          // off-diagonal entries of the last build
 };
 
@@ -73,8 +75,7 @@ struct DevPtrs {
   CgRep* cg;
   Ctrl* ctrl;
   const int32_t* blk_rep;   // block -> replica
-  int32_t* arrive;          // per-replica arrival counters (last-block pattern)
-  double* partial;          // [blocks][NPART]
+  double* partial;          // [tiles][NPART]
   double4* pos;             // current positions (sorted order)
   double4* pos_alt;         // scatter target
   int32_t* cellidx;
@@ -88,11 +89,14 @@ struct DevPtrs {
   double* val;
   float* valf;
   double* diag;
+  double* dinv;
   double* b;
   double* x;
-  double* r;
   double* p;
-  double* q;
+  double* r;
+  double* s;
+  double* w;
+  double* u;
   double* vel_orig;         // velocities of the last step, original order
   const double* inj_xi;     // injected Gaussians (testing), or null
   const double* inj_eta;

@@ -25,7 +25,8 @@ PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
 
 EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
-            "sim_debug_set_gaussians", "sim_destroy", "sim_strerror"]
+            "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
+            "sim_copy_probe", "sim_destroy", "sim_strerror"]
 
 
 class SimParams(C.Structure):
@@ -83,6 +84,15 @@ class SimMeta(C.Structure):
     ]
 
 
+class SimKernelProf(C.Structure):
+    _fields_ = [
+        ("name", C.c_char * 32),
+        ("launches", C.c_int64),
+        ("ms", C.c_double),
+        ("bytes", C.c_double),
+    ]
+
+
 class SimError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
@@ -112,6 +122,9 @@ def lib():
         L.sim_debug_pairs.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
         L.sim_debug_system.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp, vp]
         L.sim_debug_set_gaussians.argtypes = [vp, vp, vp]
+        L.sim_profile_enable.argtypes = [vp, C.c_int32]
+        L.sim_profile_read.argtypes = [vp, P(SimKernelProf), C.c_int32, P(C.c_int32), C.c_int32]
+        L.sim_copy_probe.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_double)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -266,5 +279,26 @@ class Sim:
         _check(lib().sim_debug_set_gaussians(self.h, _ptr(xi), _ptr(eta)),
                "sim_debug_set_gaussians")
 
+    def profile_enable(self, sample_every):
+        _check(lib().sim_profile_enable(self.h, int(sample_every)), "sim_profile_enable")
+
+    def profile_read(self, reset=True):
+        """{kernel: dict(launches, ms, bytes)} of the timing probe."""
+        arr = (SimKernelProf * 8)()
+        cnt = C.c_int32()
+        _check(lib().sim_profile_read(self.h, arr, 8, C.byref(cnt), int(reset)), "sim_profile_read")
+        return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms,
+                                           bytes=arr[k].bytes) for k in range(cnt.value)}
+
     def load_precond(self, path):
         _check(lib().sim_load_precond(self.h, path.encode()), "sim_load_precond")
+
+
+def copy_probe(src, dst, reps=20, stream=None):
+    """Mean ms of one device copy src -> dst (torch tensors, same byte size)."""
+    ms = C.c_double()
+    raw = getattr(stream, "cuda_stream", stream) or 0
+    nbytes = src.numel() * src.element_size()
+    _check(lib().sim_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                int(reps), C.c_void_p(raw), C.byref(ms)), "sim_copy_probe")
+    return ms.value
