@@ -52,8 +52,8 @@ def kernel_source_sha():
 
 
 def read_traffic(kernel, workload_key):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    """HBM traffic per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -64,12 +64,10 @@ def read_traffic(kernel, workload_key):
             continue
         k, v = line.split("=", 1)
         rec[k.strip()] = v.strip()
-    if rec.get("kernel") != kernel or rec.get("workload") != workload_key:
-        return None
-    if rec.get("source_sha") != kernel_source_sha():
+    if rec.get("workload") != workload_key or rec.get("source_sha") != kernel_source_sha():
         return None
     try:
-        return float(rec["traffic_bytes_per_launch"])
+        return float(rec[f"{kernel}.traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 

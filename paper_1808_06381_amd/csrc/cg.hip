@@ -8,7 +8,7 @@
 //   w = A u;  gamma = (r, u), delta = (w, u)
 //   beta' = gamma' / gamma, alpha' = gamma' / (delta' - beta' gamma' / alpha)
 //
-// Per iteration three launches, none with a device-scope fence:
+// Per iteration three launches, none with a cache write-back fence:
 //   k_cg_vec   every vector update, element-parallel (fully coalesced), and
 //              the partial sums of (r, u) and (r, r) per tile;
 //   k_cg_spmv  w = A u with four lanes per CSR row, so the neighbours of a
@@ -19,6 +19,8 @@
 // Sums are deterministic (fixed trees, no floating-point atomics).
 #include "sim_dev.h"
 #include "launch.h"
+
+#include <hip/hip_ext.h>
 
 #define SPMV_LANES 4
 #define VEC_ELEMS (3 * ROWS_PER_BLOCK)  // elements (row, component) per tile
@@ -123,101 +125,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   write_partials<3>(d, tile, 6, rr);
 }
 
-// CSR product with SPMV_LANES lanes per row over the tile's 1024 rows.
-//   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
-//   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
-// Lane k < 3 of a row's group finishes component k (coalesced stores).
-template <bool FP32>
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const int rid = d.blk_rep[tile];
-  const CgRep& cr = d.cg[rid];
-  bool on[3];
-  if (mode == 0) {
-    // start_mode: 0 fresh start, 1 restart, 2 iteration (as in k_cg_vec)
-    if ((start_mode == 1 && !cr.restart) || (start_mode == 2 && !cr.run)) return;
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      on[k] = start_mode == 0 ? true : (start_mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
-  } else {
-    if (!cr.check) return;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
-  }
-  const double* __restrict__ src = mode == 0 ? d.u : d.x;
-  const int lane = threadIdx.x & (SPMV_LANES - 1);
-  const int grp = threadIdx.x / SPMV_LANES;
-  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
-  double v[3] = {0, 0, 0};
-  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
-    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
-      const int64_t j = d.col[e];
-      const double a = FP32 ? (double)d.valf[e] : d.val[e];
-      a0 += a * src[3 * j];
-      a1 += a * src[3 * j + 1];
-      a2 += a * src[3 * j + 2];
-    }
-#pragma unroll
-    for (int o = 1; o < SPMV_LANES; o <<= 1) {
-      a0 += __shfl_xor(a0, o, 64);
-      a1 += __shfl_xor(a1, o, 64);
-      a2 += __shfl_xor(a2, o, 64);
-    }
-    if (lane < 3 && on[lane]) {
-      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
-      const int64_t e = 3 * i + lane;
-      const double own = d.diag[i] * src[e] + acc;
-      if (mode == 0) {
-        d.w[e] = own;
-        v[lane] += own * src[e];
-      } else {
-        const double rk = d.b[e] - own;
-        d.r[e] = rk;
-        v[lane] += rk * rk;
-      }
-    }
-  }
-  write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
-}
-
-// One block per replica: reduce the replica's tile partials in a fixed
-// order and advance its recurrences.  mode 0: after a fresh start, 1: after
+// Advance the recurrences of one replica from its totals
+// tot = [gamma0..2, delta0..2, rr0..2].  mode 0: after a fresh start, 1: after
 // a restart, 2: after an iteration, 3: after a true-residual check.
-__global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
-  const int rid = blockIdx.x;
-  const RepDev& R = d.rep[rid];
-  CgRep& c = d.cg[rid];
-  const bool work = (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
-                    (mode == 3 && c.check);
-  if (!work) return;
-  __shared__ double lds[16][9];
-  double acc[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-  for (int t = threadIdx.x; t < R.nblk; t += blockDim.x) {
-    const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] += src[k];
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) lds[wave][k] = acc[k];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double tot[9];
-  for (int k = 0; k < 9; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w][k];
-    tot[k] = s;
-  }
+__device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&tot)[9]) {
   int finished = 0;
   for (int k = 0; k < 3; ++k) {
     const double gam = tot[k], del = tot[3 + k], rr = tot[6 + k];
@@ -280,6 +191,110 @@ __global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
   if (finished) atomicSub(&d.ctrl->n_notdone, finished);
 }
 
+// Sum the replica's tile partials in a fixed order (thread t takes tiles t,
+// t + blockDim, ...; then the wave and block trees).  Totals valid in thread 0.
+__device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, double (&tot)[9]) {
+  __shared__ double lds[16][9];
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int t = threadIdx.x; t < R.nblk; t += blockDim.x) {
+    const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      acc[k] += src[k];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) lds[wave][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 9; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w][k];
+      tot[k] = s;
+    }
+  }
+}
+
+// CSR product with SPMV_LANES lanes per row over the tile's 1024 rows.
+//   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
+//   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
+// Lane k < 3 of a row's group finishes component k (coalesced stores).
+template <bool FP32>
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const int rid = d.blk_rep[tile];
+  const CgRep& cr = d.cg[rid];
+  bool on[3];
+  if (mode == 0) {
+    // start_mode: 0 fresh start, 1 restart, 2 iteration (as in k_cg_vec)
+    if ((start_mode == 1 && !cr.restart) || (start_mode == 2 && !cr.run)) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      on[k] = start_mode == 0 ? true : (start_mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
+  } else {
+    if (!cr.check) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
+  }
+  const double* __restrict__ src = mode == 0 ? d.u : d.x;
+  const int lane = threadIdx.x & (SPMV_LANES - 1);
+  const int grp = threadIdx.x / SPMV_LANES;
+  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
+  double v[3] = {0, 0, 0};
+  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
+    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
+      const int64_t j = d.col[e];
+      const double a = FP32 ? (double)d.valf[e] : d.val[e];
+      a0 += a * src[3 * j];
+      a1 += a * src[3 * j + 1];
+      a2 += a * src[3 * j + 2];
+    }
+#pragma unroll
+    for (int o = 1; o < SPMV_LANES; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+    }
+    if (lane < 3 && on[lane]) {
+      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      const int64_t e = 3 * i + lane;
+      const double own = d.diag[i] * src[e] + acc;
+      if (mode == 0) {
+        d.w[e] = own;
+        v[lane] += own * src[e];
+      } else {
+        const double rk = d.b[e] - own;
+        d.r[e] = rk;
+        v[lane] += rk * rk;
+      }
+    }
+  }
+  write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
+}
+
+// One block per replica: reduce the replica's tile partials and advance.
+__global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
+  const int rid = blockIdx.x;
+  const RepDev& R = d.rep[rid];
+  CgRep& c = d.cg[rid];
+  const bool work = (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
+                    (mode == 3 && c.check);
+  if (!work) return;
+  double tot[9];
+  reduce_tiles(d, R, tot);
+  if (threadIdx.x == 0) cg_advance(d, c, mode, tot);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -288,17 +303,21 @@ hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, mode);
+// ev0/ev1 (optional) take the kernel's own start and end timestamps
+hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1) {
+  hipExtLaunchKernelGGL(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, ev0, ev1, 0,
+                        d, mode);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s) {
+hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
   if (d.spmv_fp32 && mode == 0)
-    hipLaunchKernelGGL(k_cg_spmv<true>, g, b, 0, s, d, mode, start_mode);
+    hipExtLaunchKernelGGL(k_cg_spmv<true>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
   else
-    hipLaunchKernelGGL(k_cg_spmv<false>, g, b, 0, s, d, mode, start_mode);
+    hipExtLaunchKernelGGL(k_cg_spmv<false>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
   return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ hipError_t launch_export_system(const DevPtrs& d, const int64_t* id_off, int64_t
                                 double* rhs, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s);
-hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s);
-hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s);
+hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
+hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s);

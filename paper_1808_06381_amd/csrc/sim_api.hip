@@ -68,11 +68,11 @@ struct sim_t {
   std::vector<hipEvent_t> prof_ev;      // pool of event pairs
   struct Sample { int kernel; int iter; int ev; float ms; };
   std::vector<Sample> prof_pending;     // recorded in the current solve
-  sim_kernel_prof prof_acc[3] = {};
+  sim_kernel_prof prof_acc[2] = {};
 };
 
-static const int kProfKernels = 3;
-static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_finish"};
+static const int kProfKernels = 2;
+static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv"};
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -254,17 +254,17 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
       const bool probe = s->prof_every > 0 && g % s->prof_every == 0 &&
                          (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
       for (int kern = 0; kern < kProfKernels; ++kern) {
-        int ev = -1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (probe) {
-          ev = (int)s->prof_pending.size();
+          const int ev = (int)s->prof_pending.size();
           s->prof_pending.push_back({kern, g, ev, 0.0f});
-          HIPCHK(hipEventRecord(s->prof_ev[2 * ev], stream));
+          e0 = s->prof_ev[2 * ev];
+          e1 = s->prof_ev[2 * ev + 1];
         }
-        if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream));
-        else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream));
-        else HIPCHK(launch_cg_finish(d, 2, stream));
-        if (probe) HIPCHK(hipEventRecord(s->prof_ev[2 * ev + 1], stream));
+        if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
+        else HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
       }
+      HIPCHK(launch_cg_finish(d, 2, stream));
     }
     launched += n;
     // true-residual checks of replicas whose components all passed, and
@@ -312,9 +312,7 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
         // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written (120)
         rows * 248.0 + ntile * 6.0 * 8.0,
         // product: row pointers (4), u (24), diag (8), w written (24), CSR col + value
-        rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0,
-        // finish: the tile partials
-        ntile * 9.0 * 8.0};
+        rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0};
     for (auto& smp : s->prof_pending) {
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[2 * smp.ev], s->prof_ev[2 * smp.ev + 1]));
