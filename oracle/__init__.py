@@ -85,6 +85,17 @@ def lib():
         L.orc_step.argtypes = [pp, C.c_int64, d_p, d_p, C.c_double, C.c_int, C.c_int, P(C.c_int)]
         L.orc_step.restype = C.c_int
         L.orc_wrap.argtypes = [pp, C.c_int64, d_p]
+        f_p = P(C.c_float)
+        L.orc_mpnn_nparams.restype = C.c_int64
+        L.orc_bf16.argtypes = [C.c_float]
+        L.orc_bf16.restype = C.c_double
+        L.orc_mpnn_set_bf16.argtypes = [C.c_int]
+        L.orc_mpnn_forward.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double, f_p,
+                                       d_p, d_p]
+        L.orc_mpnn_forward.restype = C.c_int
+        L.orc_mpnn_loss_grad.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double, f_p,
+                                         d_p, d_p, d_p]
+        L.orc_mpnn_loss_grad.restype = C.c_double
         _lib = L
     return _lib
 
@@ -262,3 +273,65 @@ def wrap(cfg, pos, step_after):
     pos = _f64(pos, (p.n, 3)).copy()
     lib().orc_wrap(C.byref(p), int(step_after), _dp(pos))
     return pos
+
+
+# ---- learned preconditioner ---------------------------------------------------
+
+def mpnn_nparams():
+    return int(lib().orc_mpnn_nparams())
+
+
+def bf16(x):
+    return lib().orc_bf16(float(x))
+
+
+def mpnn_set_bf16(on):
+    lib().orc_mpnn_set_bf16(1 if on else 0)
+
+
+def edge_r(cfg, pos, sys_, step=0):
+    """r_ij / rc per CSR entry of a build_system result (oracle geometry)."""
+    delta = le_offset(cfg, step)
+    n = sys_["diag"].shape[0]
+    out = np.zeros(len(sys_["col"]))
+    rp = sys_["rowptr"]
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            d, _ = separation(cfg, delta, pos[i], pos[sys_["col"][k]])
+            out[k] = np.sqrt(float(d @ d)) / cfg["rc"]
+    return out
+
+
+def _theta(theta):
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    assert t.shape == (mpnn_nparams(),)
+    return t, t.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mpnn_forward(sys_, er, alpha, theta):
+    """M^-1 of the learned preconditioner: (mdiag[n], moff[nnz]) in A's pattern."""
+    n = sys_["diag"].shape[0]
+    t, tp = _theta(theta)
+    mdiag = np.zeros(n)
+    moff = np.zeros(max(len(sys_["col"]), 1))
+    er = np.ascontiguousarray(er, dtype=np.float64)
+    rc = lib().orc_mpnn_forward(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
+                                _dp(sys_["diag"]), _dp(er), float(alpha), tp, _dp(mdiag),
+                                _dp(moff))
+    if rc != 0:
+        raise RuntimeError("oracle mpnn forward failed")
+    return mdiag, moff[:len(sys_["col"])]
+
+
+def mpnn_loss_grad(sys_, er, alpha, theta, b, xstar, grad=True):
+    """Loss ||M^-1 b - x*||_A^2 / ||x*||_A^2 and its gradient (float64 array)."""
+    n = sys_["diag"].shape[0]
+    t, tp = _theta(theta)
+    g = np.zeros(mpnn_nparams()) if grad else None
+    er = np.ascontiguousarray(er, dtype=np.float64)
+    b = _f64(b, (n, 3))
+    xstar = _f64(xstar, (n, 3))
+    loss = lib().orc_mpnn_loss_grad(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
+                                    _dp(sys_["diag"]), _dp(er), float(alpha), tp, _dp(b),
+                                    _dp(xstar), _dp(g))
+    return (loss, g) if grad else loss

@@ -1,0 +1,374 @@
+/*
+ * mpnn.c -- plain FP64 oracle of the learned preconditioner: a 3-layer
+ * message-passing network on the pair graph of the friction matrix A
+ * (Method section, Eq. 9) that outputs an SPD approximate inverse M^-1 with
+ * the sparsity of A, and the training loss with its gradient.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written from the network's
+ * definition below with straightforward loops; the gradient is analytic
+ * backpropagation (pinned by finite differences in the tests).
+ *
+ * Inputs (A in original order, CSR of the off-diagonal part, val = -alpha*w):
+ *   node features x_i = (t_i, a_i, deg_i / 8):
+ *       t_i = -sum_j val_ij / D_i      (the pair share of the diagonal)
+ *       a_i = sum_j What_ij, What_ij = -val_ij / sqrt(D_i D_j)
+ *   edge features e_ij = (r_ij / rc, w_ij, What_ij), w_ij = -val_ij / alpha
+ * Network (hidden H = 32, three layers):
+ *   h0_i = relu(W0 x_i + b0)
+ *   layer l:  y_j = P_l h_j;   m_i = (1/8) sum_j relu(y_j + Q_l e_ij + c_l)
+ *             h_i <- h_i + relu(U_l h_i + V_l m_i + d_l)
+ *   heads:    lam'_i = softplus(v . h_i + v0)
+ *             g_ij   = 2 sigmoid(z . (h_i * h_j) + ze . e_ij + z0)   (symmetric)
+ * Preconditioner:
+ *   S_ij = g_ij What_ij,  lam_i = sum_j S_ij + lam'_i + eps   (eps = 1e-3)
+ *   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2:  mdiag_i = lam_i / D_i,
+ *   moff_ij = S_ij / sqrt(D_i D_j).
+ *   diag(lam) + S is strictly diagonally dominant with a positive diagonal,
+ *   so M^-1 is symmetric positive definite for every parameter value.
+ * Loss on a system (A, b, x*): L = ||M^-1 b - x*||_A^2 / ||x*||_A^2, summed
+ * over the three components.
+ * Weights enter in bfloat16 (round to nearest even of the FP32 master
+ * values); everything else is FP64 here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define H 32
+#define FN 3
+#define FE 3
+#define NL 3
+#define EPS_LAM 1e-3
+#define MSG_SCALE 0.125
+
+/* parameter offsets (floats) */
+#define OFF_W0 0
+#define OFF_B0 (OFF_W0 + H * FN)
+#define OFF_L0 (OFF_B0 + H)
+#define L_P 0
+#define L_Q (L_P + H * H)
+#define L_C (L_Q + H * FE)
+#define L_U (L_C + H)
+#define L_V (L_U + H * H)
+#define L_D (L_V + H * H)
+#define L_SIZE (L_D + H)
+#define OFF_HEAD (OFF_L0 + NL * L_SIZE)
+#define H_V 0
+#define H_V0 (H_V + H)
+#define H_Z (H_V0 + 1)
+#define H_ZE (H_Z + H)
+#define H_Z0 (H_ZE + FE)
+#define NPARAMS (OFF_HEAD + H_Z0 + 1)
+
+int64_t orc_mpnn_nparams(void) { return NPARAMS; }
+
+/* weights enter rounded to bfloat16 unless switched off (finite-difference
+ * tests perturb FP32 weights by amounts below the bfloat16 spacing) */
+static int g_use_bf16 = 1;
+void orc_mpnn_set_bf16(int on) { g_use_bf16 = on; }
+
+/* bfloat16 value of an FP32 number: keep the top 16 bits after rounding the
+ * discarded 16 to nearest, ties to even (NaN kept as NaN) */
+double orc_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+    u |= 0x00400000u;
+  } else {
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+  }
+  u &= 0xffff0000u;
+  float r;
+  memcpy(&r, &u, 4);
+  return (double)r;
+}
+
+static double relu(double a) { return a > 0.0 ? a : 0.0; }
+static double sigm(double a) { return 1.0 / (1.0 + exp(-a)); }
+static double softplus(double a) { return a > 30.0 ? a : log1p(exp(a)); }
+
+typedef struct {
+  int64_t n, nnz;
+  const int64_t *rowptr, *col;
+  const double *val, *diag, *edge_r;
+  double alpha;
+  double th[NPARAMS];    /* bf16-valued weights */
+  double *x;             /* n x FN */
+  double *e;             /* nnz x FE */
+  double *hs;            /* (NL+1) x n x H : h^0..h^3 */
+  double *ys;            /* NL x n x H     : y^l = P_l h^{l-1} */
+  double *ms;            /* NL x n x H     : m^l */
+  double *as;            /* NL x n x H     : pre-activation of the update */
+  double *tau;           /* n   : node head pre-activation */
+  double *tg;            /* nnz : edge head pre-activation */
+  double *g;             /* nnz */
+  double *what;          /* nnz */
+} net_t;
+
+static void net_free(net_t* t) {
+  free(t->x); free(t->e); free(t->hs); free(t->ys); free(t->ms); free(t->as);
+  free(t->tau); free(t->tg); free(t->g); free(t->what);
+}
+
+static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff) {
+  const int64_t n = t->n, nnz = t->nnz;
+  for (int k = 0; k < NPARAMS; ++k) t->th[k] = g_use_bf16 ? orc_bf16(theta[k]) : (double)theta[k];
+  t->x = (double*)calloc((size_t)(n * FN + 1), sizeof(double));
+  t->e = (double*)calloc((size_t)(nnz * FE + 1), sizeof(double));
+  t->hs = (double*)calloc((size_t)((NL + 1) * n * H + 1), sizeof(double));
+  t->ys = (double*)calloc((size_t)(NL * n * H + 1), sizeof(double));
+  t->ms = (double*)calloc((size_t)(NL * n * H + 1), sizeof(double));
+  t->as = (double*)calloc((size_t)(NL * n * H + 1), sizeof(double));
+  t->tau = (double*)calloc((size_t)(n + 1), sizeof(double));
+  t->tg = (double*)calloc((size_t)(nnz + 1), sizeof(double));
+  t->g = (double*)calloc((size_t)(nnz + 1), sizeof(double));
+  t->what = (double*)calloc((size_t)(nnz + 1), sizeof(double));
+  if (!t->x || !t->e || !t->hs || !t->ys || !t->ms || !t->as || !t->tau || !t->tg || !t->g ||
+      !t->what)
+    return -2;
+  const double* th = t->th;
+  /* features */
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0, a = 0.0;
+    for (int64_t q = t->rowptr[i]; q < t->rowptr[i + 1]; ++q) {
+      const int64_t j = t->col[q];
+      t->what[q] = -t->val[q] / sqrt(t->diag[i] * t->diag[j]);
+      s += -t->val[q];
+      a += t->what[q];
+      t->e[FE * q + 0] = t->edge_r[q];
+      t->e[FE * q + 1] = -t->val[q] / t->alpha;
+      t->e[FE * q + 2] = t->what[q];
+    }
+    t->x[FN * i + 0] = s / t->diag[i];
+    t->x[FN * i + 1] = a;
+    t->x[FN * i + 2] = (double)(t->rowptr[i + 1] - t->rowptr[i]) / 8.0;
+  }
+  /* encoder */
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < H; ++k) {
+      double acc = th[OFF_B0 + k];
+      for (int f = 0; f < FN; ++f) acc += th[OFF_W0 + k * FN + f] * t->x[FN * i + f];
+      t->hs[i * H + k] = relu(acc);
+    }
+  /* layers */
+  for (int l = 0; l < NL; ++l) {
+    const double* L = th + OFF_L0 + l * L_SIZE;
+    const double* hin = t->hs + (int64_t)l * n * H;
+    double* hout = t->hs + (int64_t)(l + 1) * n * H;
+    double* y = t->ys + (int64_t)l * n * H;
+    double* m = t->ms + (int64_t)l * n * H;
+    double* a = t->as + (int64_t)l * n * H;
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < H; ++k) {
+        double acc = 0.0;
+        for (int q = 0; q < H; ++q) acc += L[L_P + k * H + q] * hin[i * H + q];
+        y[i * H + k] = acc;
+      }
+    for (int64_t i = 0; i < n; ++i) {
+      for (int k = 0; k < H; ++k) m[i * H + k] = 0.0;
+      for (int64_t q = t->rowptr[i]; q < t->rowptr[i + 1]; ++q) {
+        const int64_t j = t->col[q];
+        for (int k = 0; k < H; ++k) {
+          double s = y[j * H + k] + L[L_C + k];
+          for (int f = 0; f < FE; ++f) s += L[L_Q + k * FE + f] * t->e[FE * q + f];
+          m[i * H + k] += MSG_SCALE * relu(s);
+        }
+      }
+      for (int k = 0; k < H; ++k) {
+        double acc = L[L_D + k];
+        for (int q = 0; q < H; ++q)
+          acc += L[L_U + k * H + q] * hin[i * H + q] + L[L_V + k * H + q] * m[i * H + q];
+        a[i * H + k] = acc;
+        hout[i * H + k] = hin[i * H + k] + relu(acc);
+      }
+    }
+  }
+  /* heads and the preconditioner */
+  const double* hd = th + OFF_HEAD;
+  const double* hf = t->hs + (int64_t)NL * n * H;
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = hd[H_V0];
+    for (int k = 0; k < H; ++k) acc += hd[H_V + k] * hf[i * H + k];
+    t->tau[i] = acc;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double lam = softplus(t->tau[i]) + EPS_LAM;
+    for (int64_t q = t->rowptr[i]; q < t->rowptr[i + 1]; ++q) {
+      const int64_t j = t->col[q];
+      double acc = hd[H_Z0];
+      for (int k = 0; k < H; ++k) acc += hd[H_Z + k] * (hf[i * H + k] * hf[j * H + k]);
+      for (int f = 0; f < FE; ++f) acc += hd[H_ZE + f] * t->e[FE * q + f];
+      t->tg[q] = acc;
+      t->g[q] = 2.0 * sigm(acc);
+      const double s = t->g[q] * t->what[q];
+      lam += s;
+      if (moff) moff[q] = s / sqrt(t->diag[i] * t->diag[j]);
+    }
+    if (mdiag) mdiag[i] = lam / t->diag[i];
+  }
+  return 0;
+}
+
+/* M^-1 (mdiag, moff) for the system (rowptr, col, val, diag) */
+int orc_mpnn_forward(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                     const double* diag, const double* edge_r, double alpha, const float* theta,
+                     double* mdiag, double* moff) {
+  net_t t;
+  memset(&t, 0, sizeof(t));
+  t.n = n; t.nnz = rowptr[n]; t.rowptr = rowptr; t.col = col; t.val = val; t.diag = diag;
+  t.edge_r = edge_r; t.alpha = alpha;
+  int rc = net_forward(&t, theta, mdiag, moff);
+  net_free(&t);
+  return rc;
+}
+
+/* Loss L = ||M^-1 b - x*||_A^2 / ||x*||_A^2 (three components) and, if grad
+ * is given, dL/dtheta (with respect to the bf16-rounded weights).          */
+double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                          const double* diag, const double* edge_r, double alpha,
+                          const float* theta, const double* b, const double* xstar, double* grad) {
+  net_t t;
+  memset(&t, 0, sizeof(t));
+  t.n = n; t.nnz = rowptr[n]; t.rowptr = rowptr; t.col = col; t.val = val; t.diag = diag;
+  t.edge_r = edge_r; t.alpha = alpha;
+  const int64_t nnz = t.nnz;
+  double* mdiag = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+  double* moff = (double*)malloc(sizeof(double) * (size_t)(nnz + 1));
+  double* z = (double*)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+  double* ae = (double*)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+  double* ax = (double*)malloc(sizeof(double) * 3 * (size_t)(n + 1));
+  double loss = NAN;
+  if (!mdiag || !moff || !z || !ae || !ax || net_forward(&t, theta, mdiag, moff) != 0) goto out;
+  /* z = M^-1 b, e = z - x*, A e, A x* */
+  orc_spmv3(n, rowptr, col, moff, mdiag, b, z);
+  for (int64_t i = 0; i < 3 * n; ++i) z[i] -= xstar[i];
+  orc_spmv3(n, rowptr, col, val, diag, z, ae);
+  orc_spmv3(n, rowptr, col, val, diag, xstar, ax);
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < 3 * n; ++i) {
+    num += z[i] * ae[i];
+    den += xstar[i] * ax[i];
+  }
+  loss = num / den;
+  if (!grad) goto out;
+  {
+    for (int k = 0; k < NPARAMS; ++k) grad[k] = 0.0;
+    const double* th = t.th;
+    const double* hd = th + OFF_HEAD;
+    double* gh = grad + OFF_HEAD;
+    /* dL/dz = 2 A e / den; dL/dmdiag_i = sum_c G_ic b_ic; dL/dmoff_ij = sum_c G_ic b_jc */
+    double* gl = (double*)calloc((size_t)(n + 1), sizeof(double));     /* dL/dlam */
+    double* gt = (double*)calloc((size_t)(n + 1), sizeof(double));     /* dL/dtau */
+    double* dh = (double*)calloc((size_t)(n * H + 1), sizeof(double)); /* dL/dh */
+    double* dm = (double*)calloc((size_t)(n * H + 1), sizeof(double));
+    double* da = (double*)calloc((size_t)(n * H + 1), sizeof(double));
+    if (!gl || !gt || !dh || !dm || !da) { free(gl); free(gt); free(dh); free(dm); free(da); loss = NAN; goto out; }
+    for (int64_t i = 0; i < n; ++i) {
+      double gd = 0.0;
+      for (int c = 0; c < 3; ++c) gd += 2.0 * ae[3 * i + c] / den * b[3 * i + c];
+      gl[i] = gd / diag[i];                      /* mdiag = lam / D */
+      gt[i] = gl[i] * sigm(t.tau[i]);            /* lam' = softplus(tau) */
+    }
+    const double* hf = t.hs + (int64_t)NL * n * H;
+    for (int64_t i = 0; i < n; ++i) {
+      /* node head */
+      gh[H_V0] += gt[i];
+      for (int k = 0; k < H; ++k) {
+        gh[H_V + k] += gt[i] * hf[i * H + k];
+        dh[i * H + k] += gt[i] * hd[H_V + k];
+      }
+      /* edge head: S_ij enters moff_ij, moff_ji (same g) and lam_i, lam_j;
+       * each directed entry carries moff_ij and lam_i; its reverse carries the rest */
+      for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const int64_t j = col[q];
+        double gm = 0.0;
+        for (int c = 0; c < 3; ++c) gm += 2.0 * ae[3 * i + c] / den * b[3 * j + c];
+        const double dS = gm / sqrt(diag[i] * diag[j]) + gl[i];
+        const double dg = dS * t.what[q];
+        const double sg = sigm(t.tg[q]);
+        const double dtg = dg * 2.0 * sg * (1.0 - sg);
+        gh[H_Z0] += dtg;
+        for (int f = 0; f < FE; ++f) gh[H_ZE + f] += dtg * t.e[FE * q + f];
+        for (int k = 0; k < H; ++k) {
+          gh[H_Z + k] += dtg * (hf[i * H + k] * hf[j * H + k]);
+          dh[i * H + k] += dtg * hd[H_Z + k] * hf[j * H + k];
+          dh[j * H + k] += dtg * hd[H_Z + k] * hf[i * H + k];
+        }
+      }
+    }
+    /* layers, last to first; dh holds dL/dh^{l+1} on entry to layer l */
+    for (int l = NL - 1; l >= 0; --l) {
+      const double* L = th + OFF_L0 + l * L_SIZE;
+      double* G = grad + OFF_L0 + l * L_SIZE;
+      const double* hin = t.hs + (int64_t)l * n * H;
+      const double* y = t.ys + (int64_t)l * n * H;
+      const double* m = t.ms + (int64_t)l * n * H;
+      const double* a = t.as + (int64_t)l * n * H;
+      for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < H; ++k) da[i * H + k] = a[i * H + k] > 0.0 ? dh[i * H + k] : 0.0;
+      /* h_out = h_in + relu(U h_in + V m + d): dh_in = dh_out + U^T da, dm = V^T da */
+      for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < H; ++k) {
+          const double dak = da[i * H + k];
+          G[L_D + k] += dak;
+          for (int q = 0; q < H; ++q) {
+            G[L_U + k * H + q] += dak * hin[i * H + q];
+            G[L_V + k * H + q] += dak * m[i * H + q];
+          }
+        }
+      for (int64_t i = 0; i < n; ++i)
+        for (int q = 0; q < H; ++q) {
+          double su = 0.0, sv = 0.0;
+          for (int k = 0; k < H; ++k) {
+            su += L[L_U + k * H + q] * da[i * H + k];
+            sv += L[L_V + k * H + q] * da[i * H + k];
+          }
+          dh[i * H + q] += su;   /* dh_in = dh_out + U^T da (dh_out already in dh) */
+          dm[i * H + q] = sv;
+        }
+      /* m_i = (1/8) sum_j relu(y_j + Q e_ij + c): dy_j, dQ, dc; dh_in += P^T dy */
+      double* dy = da; /* reuse: da is no longer needed */
+      for (int64_t i = 0; i < n * H; ++i) dy[i] = 0.0;
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+          const int64_t j = col[q];
+          for (int k = 0; k < H; ++k) {
+            double s = y[j * H + k] + L[L_C + k];
+            for (int f = 0; f < FE; ++f) s += L[L_Q + k * FE + f] * t.e[FE * q + f];
+            if (!(s > 0.0)) continue;
+            const double dq = MSG_SCALE * dm[i * H + k];
+            G[L_C + k] += dq;
+            for (int f = 0; f < FE; ++f) G[L_Q + k * FE + f] += dq * t.e[FE * q + f];
+            dy[j * H + k] += dq;
+          }
+        }
+      for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < H; ++k)
+          for (int q = 0; q < H; ++q) G[L_P + k * H + q] += dy[i * H + k] * hin[i * H + q];
+      for (int64_t i = 0; i < n; ++i)
+        for (int q = 0; q < H; ++q) {
+          double s = 0.0;
+          for (int k = 0; k < H; ++k) s += L[L_P + k * H + q] * dy[i * H + k];
+          dh[i * H + q] += s;
+        }
+    }
+    /* encoder: h0 = relu(W0 x + b0) */
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < H; ++k) {
+        double acc = th[OFF_B0 + k];
+        for (int f = 0; f < FN; ++f) acc += th[OFF_W0 + k * FN + f] * t.x[FN * i + f];
+        if (!(acc > 0.0)) continue;
+        grad[OFF_B0 + k] += dh[i * H + k];
+        for (int f = 0; f < FN; ++f) grad[OFF_W0 + k * FN + f] += dh[i * H + k] * t.x[FN * i + f];
+      }
+    free(gl); free(gt); free(dh); free(dm); free(da);
+  }
+out:
+  free(mdiag); free(moff); free(z); free(ae); free(ax);
+  net_free(&t);
+  return loss;
+}

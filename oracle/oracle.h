@@ -87,6 +87,17 @@ int orc_step(const orc_params* p, int64_t step, double* pos, double* vel,
              double tol, int maxit, int precond, int iters[3]);
 void orc_wrap(const orc_params* p, int64_t step_after, double* pos);
 
+/* ---- learned preconditioner (mpnn.c) --------------------------------------- */
+int64_t orc_mpnn_nparams(void);
+double orc_bf16(float f);
+void orc_mpnn_set_bf16(int on);
+int orc_mpnn_forward(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                     const double* diag, const double* edge_r, double alpha, const float* theta,
+                     double* mdiag, double* moff);
+double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                          const double* diag, const double* edge_r, double alpha,
+                          const float* theta, const double* b, const double* xstar, double* grad);
+
 #ifdef __cplusplus
 }
 #endif
