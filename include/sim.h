@@ -81,7 +81,9 @@ enum sim_precond { SIM_PC_JACOBI = 0, SIM_PC_NONE = 1, SIM_PC_IC0 = 2, SIM_PC_LE
  *              (Eq. 6a); SIM_NOISE_OFF.  Gaussians come from Philox4x64-10
  *              keyed (seed, stream) with counter (step, 0, id, 0) for xi and
  *              (step, 1, min id, max id) for eta, via Box-Muller.
- *  precond     CG preconditioner (SIM_PC_*)
+ *  precond     CG preconditioner: SIM_PC_JACOBI (u = D^-1 r), SIM_PC_NONE,
+ *              SIM_PC_LEARNED (see below; needs alpha > 0 and the same
+ *              choice for every replica); SIM_PC_IC0 returns SIM_ENOTSUP
  *  spmv_fp32   0: FP64 matrix values; 1: FP32 matrix values in the CG
  *              matrix products with FP64 vectors, dots and true-residual
  *              recompute (agreement with FP64 about 1e-5 relative)
@@ -176,8 +178,9 @@ int sim_state(sim_t* sim, double* pos, double* vel, sim_meta* meta, uint32_t fla
  * the default stream).  The caller keeps the stream alive.                 */
 int sim_set_stream(sim_t* sim, void* hip_stream);
 
-/* Load learned-preconditioner weights (file written by the trainer).
- * Returns SIM_ENOTSUP until the learned preconditioner is built in.       */
+/* Load learned-preconditioner weights from a file: 8 bytes "SIMPC001", an
+ * int64 count (= SIM_MPNN_NPARAMS), then the FP32 weights, little-endian.
+ * SIM_EINVAL for a malformed file.                                        */
 int sim_load_precond(sim_t* sim, const char* path);
 
 /* Parity export: the unordered pairs {i < j} (original ids, per replica)
@@ -200,6 +203,45 @@ int sim_debug_system(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int
  * library copies the tables; they apply to subsequent builds.
  * SIM_ENOTSUP for batches or larger n.                                    */
 int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
+
+/* ---- learned preconditioner (precond = SIM_PC_LEARNED) --------------------
+ * A three-layer message-passing network on the pair graph of A (hidden 32)
+ * maps node features (t_i, a_i, deg_i/8) and edge features (r_ij/rc, w_ij,
+ * What_ij) to M^-1 = D^-1/2 (diag(lam) + S) D^-1/2 in A's sparsity, with
+ * S_ij = g_ij What_ij, g_ij = 2 sigmoid(.) symmetric and
+ * lam_i = sum_j S_ij + softplus(.) + 1e-3, so M^-1 is SPD for any weights
+ * (D = diag A, What_ij = alpha w_ij / sqrt(D_i D_j)).  It replaces the
+ * Jacobi step u = D^-1 r of the CG solve of Eq. 9; the stopping rule (true
+ * residual) is unchanged, so it changes iteration counts, not answers.  A
+ * solve that stalls (residual not 10 % lower over 10 iterations after 20)
+ * or breaks down is redone with Jacobi and flagged in sim_stats.fallback.
+ * The weights are SIM_MPNN_NPARAMS FP32 values (bfloat16 in the kernels),
+ * in this order: W0[32][3], b0[32], then per layer P[32][32], Q[32][3],
+ * c[32], U[32][32], V[32][32], d[32], then v[32], v0, z[32], ze[3], z0.
+ * A new handle starts with all weights zero (a valid SPD preconditioner). */
+#define SIM_MPNN_NPARAMS 9893
+/* Copy the FP32 master weights in (set = 1) or out (set = 0).            */
+int sim_precond_weights(sim_t* sim, float* theta, int64_t count, int32_t set);
+/* Activations entering the network's products are rounded to bfloat16
+ * (round_act = 1, default) or kept in FP32 (0, for parity tests).
+ * learned_maxit > 0 bounds the iterations of a learned-preconditioned
+ * solve before it falls back to Jacobi (0: the params' cg_maxit).         */
+int sim_precond_config(sim_t* sim, int32_t round_act, int32_t learned_maxit);
+/* One training step on the system of the last successful solve of this
+ * single-box handle (A, b and its solution x* from sim_step or sim_solve):
+ * network forward, loss L = ||M^-1 b - x*||_A^2 / ||x*||_A^2 (three
+ * components), backward and one Adam step (beta 0.9 / 0.999) with learning
+ * rate lr; lr = 0 evaluates the loss and gradient only.  *loss receives L
+ * at the weights before the update.  SIM_EINVAL without a solved system;
+ * SIM_ENOTSUP for batches.                                               */
+int sim_train_step(sim_t* sim, double lr, double* loss);
+/* The gradient dL/dtheta of the last sim_train_step (with respect to the
+ * bfloat16 weights), count = SIM_MPNN_NPARAMS.                           */
+int sim_precond_grad(sim_t* sim, float* grad, int64_t count);
+/* Parity export of the learned M^-1 of the current positions and step, in
+ * the form of sim_debug_system (off-diagonal triples, diagonal).          */
+int sim_debug_precond(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                      int64_t* count, double* mdiag);
 
 /* Kernel timing probe (measurement, not part of the method).  With
  * sample_every > 0, every sample_every-th CG iteration of later solves has

@@ -106,7 +106,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
       d.s[e] = 0.0;
     } else {
       const double r0 = d.r[e];
-      const double pk = di * r0 + be[k] * d.p[e];
+      const double uk0 = d.learned ? d.u[e] : di * r0;
+      const double pk = uk0 + be[k] * d.p[e];
       const double sk = d.w[e] + be[k] * d.s[e];
       d.p[e] = pk;
       d.s[e] = sk;
@@ -114,15 +115,65 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
       rk = r0 - al[k] * sk;
       d.r[e] = rk;
     }
-    const double uk = di * rk;
-    d.u[e] = uk;
-    v[k] += rk * uk;
+    if (!d.learned) {
+      const double uk = di * rk;
+      d.u[e] = uk;
+      v[k] += rk * uk;
+    }
     v[3 + k] += rk * rk;
   }
   double g[3] = {v[0], v[1], v[2]}, rr[3] = {v[3], v[4], v[5]};
-  write_partials<3>(d, tile, 0, g);
-  __syncthreads();
+  if (!d.learned) {
+    write_partials<3>(d, tile, 0, g);
+    __syncthreads();
+  }
   write_partials<3>(d, tile, 6, rr);
+}
+
+// Learned preconditioner: u = M^-1 r with M^-1 in A's pattern (four lanes
+// per row, as the CSR product), partial (r, u).  Same component selection
+// as k_cg_vec's mode.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const int rid = d.blk_rep[tile];
+  const CgRep& cr = d.cg[rid];
+  if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
+  bool on[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
+  const int lane = threadIdx.x & (SPMV_LANES - 1);
+  const int grp = threadIdx.x / SPMV_LANES;
+  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
+  const double* __restrict__ r = d.r;
+  double v[3] = {0, 0, 0};
+  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
+    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
+      const int64_t j = d.col[e];
+      const double a = (double)d.moff[e];
+      a0 += a * r[3 * j];
+      a1 += a * r[3 * j + 1];
+      a2 += a * r[3 * j + 2];
+    }
+#pragma unroll
+    for (int o = 1; o < SPMV_LANES; o <<= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+    }
+    if (lane < 3 && on[lane]) {
+      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
+      const int64_t e = 3 * i + lane;
+      const double uk = d.mdiag[i] * r[e] + acc;
+      d.u[e] = uk;
+      v[lane] += r[e] * uk;
+    }
+  }
+  write_partials<3>(d, tile, 0, v);
 }
 
 // Advance the recurrences of one replica from its totals
@@ -318,6 +369,13 @@ hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_
     hipExtLaunchKernelGGL(k_cg_spmv<true>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
   else
     hipExtLaunchKernelGGL(k_cg_spmv<false>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  hipExtLaunchKernelGGL(k_cg_apply, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, ev0, ev1,
+                        0, d, mode);
   return hipGetLastError();
 }
 

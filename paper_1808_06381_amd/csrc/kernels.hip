@@ -266,6 +266,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d, int64_t 
       const double w = pair_weight(R, r2, r);
       d.val[e] = -R.alpha * w;
       d.valf[e] = (float)(-R.alpha * w);
+      d.er[e] = (float)(r / R.rc);
       wsum += w;
       ws += w * (double)s;
       const double fc = force_coef(R, r2, r);

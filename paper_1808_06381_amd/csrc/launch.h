@@ -30,3 +30,13 @@ hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t e
 hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s);
+hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
+struct MpPtrs;
+hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
+hipError_t launch_mp_loss(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
+hipError_t launch_mp_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
+hipError_t launch_mp_adam(const MpPtrs& m, float lr, int t, hipStream_t s);
+hipError_t launch_mp_cast(const MpPtrs& m, hipStream_t s);
+hipError_t launch_mp_export(const DevPtrs& d, const MpPtrs& m, const int64_t* id_off, int64_t* rows,
+                            int64_t* cols, double* vals, int64_t cap, double* diag, hipStream_t s);

@@ -1,0 +1,62 @@
+// mpnn.h -- parameter layout and device pointers of the learned
+// preconditioner (internal; the layout is also stated in include/sim.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MP_H 32        // hidden features
+#define MP_FN 3        // node input features
+#define MP_FE 3        // edge input features
+#define MP_NL 3        // message-passing layers
+#define MP_THREADS 256 // threads per block (8 nodes x 32 features)
+#define MP_ROWS 64     // rows per block
+#define MP_MSG 0.125f  // message scale
+#define MP_EPS_LAM 1e-3
+
+#define MP_OFF_W0 0
+#define MP_OFF_B0 (MP_OFF_W0 + MP_H * MP_FN)
+#define MP_OFF_L0 (MP_OFF_B0 + MP_H)
+#define MP_L_P 0
+#define MP_L_Q (MP_L_P + MP_H * MP_H)
+#define MP_L_C (MP_L_Q + MP_H * MP_FE)
+#define MP_L_U (MP_L_C + MP_H)
+#define MP_L_V (MP_L_U + MP_H * MP_H)
+#define MP_L_D (MP_L_V + MP_H * MP_H)
+#define MP_L_SIZE (MP_L_D + MP_H)
+#define MP_OFF_HEAD (MP_OFF_L0 + MP_NL * MP_L_SIZE)
+#define MP_H_V 0
+#define MP_H_V0 (MP_H_V + MP_H)
+#define MP_H_Z (MP_H_V0 + 1)
+#define MP_H_ZE (MP_H_Z + MP_H)
+#define MP_H_Z0 (MP_H_ZE + MP_FE)
+#define MP_NPARAMS (MP_OFF_HEAD + MP_H_Z0 + 1)
+
+struct MpPtrs {
+  uint16_t* w16;   // bf16 weights used by the kernels
+  float* th32;     // FP32 master weights
+  float* am;       // Adam first moment
+  float* av;       // Adam second moment
+  float* grad;     // gradient of the last training step
+  float* gpart;    // [blocks][MP_NPARAMS] partial gradients
+  float* x;        // [rows][3] node features
+  float* ef;       // [nnz][3] edge features
+  float* er;       // [nnz] r_ij / rc (written by the pair-terms kernel)
+  float* h;        // [NL+1][rows][H]
+  float* y;        // [NL][rows][H]
+  float* m;        // [NL][rows][H] (training)
+  float* a;        // [NL][rows][H] (training)
+  float* tau;      // [rows] node-head pre-activation
+  float* tg;       // [nnz] edge-head pre-activation
+  float* moff;     // [nnz] M^-1 off-diagonal
+  double* mdiag;   // [rows] M^-1 diagonal
+  double* zb;      // [rows][3] M^-1 b - x*
+  double* G;       // [rows][3] 2 A zb
+  double* lpart;   // loss partials
+  double* loss;    // [2]: loss, 1 / ||x*||_A^2
+  float* dh;       // [rows][H]
+  float* dh2;      // [rows][H]
+  float* dm;       // [rows][H]
+  int64_t rows;
+  int round_act;   // 1: round activations entering products to bf16
+  int store_train; // 1: keep m and a for the backward pass
+};

@@ -1,0 +1,658 @@
+// mpnn.hip -- learned preconditioner on gfx950: a three-layer message-passing
+// network on the pair graph of the friction matrix A (Method section, Eq. 9)
+// that produces an SPD approximate inverse with the sparsity of A, its
+// training loss and gradient, and Adam.
+//
+// Network (hidden 32; weights enter as bfloat16, products accumulate in FP32):
+//   x_i = (t_i, a_i, deg_i/8), t_i = alpha sum_j w_ij / D_i, a_i = sum_j What_ij,
+//   What_ij = alpha w_ij / sqrt(D_i D_j); e_ij = (r_ij/rc, w_ij, What_ij)
+//   h0 = relu(W0 x + b0)
+//   layer: y_j = P h_j, m_i = 1/8 sum_j relu(y_j + Q e_ij + c),
+//          h_i <- h_i + relu(U h_i + V m_i + d)
+//   heads: lam'_i = softplus(v.h_i + v0), g_ij = 2 sigmoid(z.(h_i*h_j) + ze.e_ij + z0)
+//   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2, S_ij = g_ij What_ij,
+//   lam_i = sum_j S_ij + lam'_i + 1e-3: strictly diagonally dominant -> SPD.
+// Loss on the last solved system (A, b, x*): ||M^-1 b - x*||_A^2 / ||x*||_A^2.
+//
+// Layout: one half-wave (32 lanes) per node, lane k = hidden feature k, so a
+// neighbour's feature row (32 floats) is one coalesced 128-byte load.
+// Blocks of 256 threads own 64 consecutive rows; the parameter gradients are
+// per-block partial sums reduced in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "mpnn.h"
+#include "sim_dev.h"
+
+namespace {
+
+constexpr int NODES = MP_THREADS / MP_H;     // nodes per pass (8)
+constexpr int PASSES = MP_ROWS / NODES;      // passes per block (8)
+
+__device__ __forceinline__ float bf16_value(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// round an FP32 value to the nearest bfloat16 (ties to even), as FP32
+__device__ __forceinline__ float bf16_round(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return f;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float act_in(const MpPtrs& m, float v) {
+  return m.round_act ? bf16_round(v) : v;
+}
+
+// sum over the 32 lanes of a half-wave, the same tree in every lane
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float sigmoidf_(float t) { return 1.0f / (1.0f + expf(-t)); }
+__device__ __forceinline__ float softplusf_(float t) { return t > 20.0f ? t : log1pf(expf(t)); }
+
+// copy n bf16 weights starting at off into LDS as FP32
+__device__ __forceinline__ void load_w(const MpPtrs& m, float* dst, int off, int n) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = bf16_value(m.w16[off + k]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+
+// node and edge features (one thread per row)
+__global__ __launch_bounds__(256) void k_mp_features(DevPtrs d, MpPtrs m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const double di = d.diag[i];
+  const double alpha = d.rep[d.blk_rep[i / ROWS_PER_BLOCK]].alpha;
+  const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+  double s = 0.0, a = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int j = d.col[e];
+    const double v = -d.val[e];
+    const double what = v / sqrt(di * d.diag[j]);
+    s += v;
+    a += what;
+    m.ef[3 * (int64_t)e + 0] = m.er[e];
+    m.ef[3 * (int64_t)e + 1] = (float)(v / alpha);
+    m.ef[3 * (int64_t)e + 2] = (float)what;
+  }
+  m.x[3 * i + 0] = (float)(s / di);
+  m.x[3 * i + 1] = (float)a;
+  m.x[3 * i + 2] = (float)(e1 - e0) * 0.125f;
+}
+
+// h0 = relu(W0 x + b0) and y^0 = P_0 h0
+__global__ __launch_bounds__(MP_THREADS) void k_mp_encode(DevPtrs d, MpPtrs m) {
+  __shared__ float w0[MP_H * MP_FN], b0[MP_H], P[MP_H * MP_H];
+  __shared__ float sh[NODES][MP_H];
+  load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
+  load_w(m, b0, MP_OFF_B0, MP_H);
+  load_w(m, P, MP_OFF_L0 + MP_L_P, MP_H * MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    float acc = b0[k];
+#pragma unroll
+    for (int f = 0; f < MP_FN; ++f) acc += w0[k * MP_FN + f] * act_in(m, m.x[3 * i + f]);
+    const float h = acc > 0.0f ? acc : 0.0f;
+    m.h[i * MP_H + k] = h;
+    sh[slot][k] = act_in(m, h);
+    __syncthreads();
+    float y = 0.0f;
+#pragma unroll 8
+    for (int q = 0; q < MP_H; ++q) y += P[k * MP_H + q] * sh[slot][q];
+    m.y[i * MP_H + k] = y;
+    __syncthreads();
+  }
+}
+
+// one message-passing layer l: m, a (stored for training), h^{l+1}, y^{l+1}
+__global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, int l) {
+  __shared__ float Q[MP_H * MP_FE], c[MP_H], U[MP_H * MP_H], V[MP_H * MP_H], dd[MP_H],
+      Pn[MP_H * MP_H];
+  __shared__ float sh[NODES][MP_H], sm[NODES][MP_H];
+  const int base = MP_OFF_L0 + l * MP_L_SIZE;
+  load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
+  load_w(m, c, base + MP_L_C, MP_H);
+  load_w(m, U, base + MP_L_U, MP_H * MP_H);
+  load_w(m, V, base + MP_L_V, MP_H * MP_H);
+  load_w(m, dd, base + MP_L_D, MP_H);
+  const bool next = l + 1 < MP_NL;
+  if (next) load_w(m, Pn, base + MP_L_SIZE + MP_L_P, MP_H * MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hin = m.h + (int64_t)l * m.rows * MP_H;
+  float* __restrict__ hout = m.h + (int64_t)(l + 1) * m.rows * MP_H;
+  const float* __restrict__ y = m.y + (int64_t)l * m.rows * MP_H;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    float msg = 0.0f;
+    for (int e = e0; e < e1; ++e) {
+      const int64_t j = d.col[e];
+      float s = y[j * MP_H + k] + c[k];
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) s += Q[k * MP_FE + f] * act_in(m, m.ef[3 * (int64_t)e + f]);
+      msg += s > 0.0f ? s : 0.0f;
+    }
+    msg *= MP_MSG;
+    const float h = hin[i * MP_H + k];
+    sh[slot][k] = act_in(m, h);
+    sm[slot][k] = act_in(m, msg);
+    __syncthreads();
+    float a = dd[k];
+#pragma unroll 8
+    for (int q = 0; q < MP_H; ++q) a += U[k * MP_H + q] * sh[slot][q] + V[k * MP_H + q] * sm[slot][q];
+    const float hn = h + (a > 0.0f ? a : 0.0f);
+    hout[i * MP_H + k] = hn;
+    if (m.store_train) {
+      m.m[((int64_t)l * m.rows + i) * MP_H + k] = msg;
+      m.a[((int64_t)l * m.rows + i) * MP_H + k] = a;
+    }
+    __syncthreads();
+    if (next) {
+      sh[slot][k] = act_in(m, hn);
+      __syncthreads();
+      float yn = 0.0f;
+#pragma unroll 8
+      for (int q = 0; q < MP_H; ++q) yn += Pn[k * MP_H + q] * sh[slot][q];
+      m.y[((int64_t)(l + 1) * m.rows + i) * MP_H + k] = yn;
+      __syncthreads();
+    }
+  }
+}
+
+// heads: M^-1 diagonal and off-diagonal values, head pre-activations
+__global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
+  __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
+  load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
+  load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
+  load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hf = m.h + (int64_t)MP_NL * m.rows * MP_H;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const float hk = act_in(m, hf[i * MP_H + k]);
+    const float tau = half_sum(hv[k] * hk) + hv[MP_H];
+    const double di = d.diag[i];
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double sum_s = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int64_t j = d.col[e];
+      const float hj = act_in(m, hf[j * MP_H + k]);
+      float t = half_sum(hz[k] * (hk * hj));
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) t += hze[f] * act_in(m, m.ef[3 * (int64_t)e + f]);
+      t += hze[MP_FE];
+      const double g = 2.0 * (double)sigmoidf_(t);
+      const double dj = d.diag[j];
+      const double s = g * (-d.val[e] / sqrt(di * dj));
+      sum_s += s;
+      if (k == 0) {
+        m.tg[e] = t;
+        m.moff[e] = (float)(s / sqrt(di * dj));
+      }
+    }
+    if (k == 0) {
+      m.tau[i] = tau;
+      const double lam = sum_s + (double)softplusf_(tau) + MP_EPS_LAM;
+      m.mdiag[i] = lam / di;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// loss: zb = M^-1 b - x*, G = 2 A zb, partials (zb.A zb, x*.A x*)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mp_resid(DevPtrs d, MpPtrs m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const double md = m.mdiag[i];
+  double z[3] = {md * d.b[3 * i], md * d.b[3 * i + 1], md * d.b[3 * i + 2]};
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int64_t j = d.col[e];
+    const double mv = m.moff[e];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] += mv * d.b[3 * j + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m.zb[3 * i + c] = z[c] - d.x[3 * i + c];
+}
+
+__global__ __launch_bounds__(256) void k_mp_aprod(DevPtrs d, MpPtrs m) {
+  __shared__ double lds[4][2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double num = 0.0, den = 0.0;
+  if (i < d.rows) {
+    const double dg = d.diag[i];
+    double az[3], ax[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      az[c] = dg * m.zb[3 * i + c];
+      ax[c] = dg * d.x[3 * i + c];
+    }
+    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+      const int64_t j = d.col[e];
+      const double a = d.val[e];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        az[c] += a * m.zb[3 * j + c];
+        ax[c] += a * d.x[3 * j + c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m.G[3 * i + c] = 2.0 * az[c];
+      num += m.zb[3 * i + c] * az[c];
+      den += d.x[3 * i + c] * ax[c];
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6][0] = num;
+    lds[threadIdx.x >> 6][1] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += lds[w][threadIdx.x];
+    m.lpart[2 * (int64_t)blockIdx.x + threadIdx.x] = s;
+  }
+}
+
+// loss = num / den and the gradient scale 1/den (one block, fixed order)
+__global__ __launch_bounds__(1024) void k_mp_loss(MpPtrs m, int nblk) {
+  __shared__ double lds[16][2];
+  double a[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    a[0] += m.lpart[2 * (int64_t)b];
+    a[1] += m.lpart[2 * (int64_t)b + 1];
+  }
+  a[0] = wave_sum(a[0]);
+  a[1] = wave_sum(a[1]);
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6][0] = a[0];
+    lds[threadIdx.x >> 6][1] = a[1];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double num = 0.0, den = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      num += lds[w][0];
+      den += lds[w][1];
+    }
+    m.loss[0] = den > 0.0 ? num / den : 0.0;
+    m.loss[1] = den > 0.0 ? 1.0 / den : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward.  dL/dmdiag_i = sum_c G_ic b_ic, dL/dmoff_ij = sum_c G_ic b_jc
+// (unscaled by 1/den: the reduction applies it).  Per-block partial
+// gradients go to gpart[block][param] for the block's parameter ranges.
+// ---------------------------------------------------------------------------
+
+// reduce an accumulator held by lane k of every node slot into gpart (one
+// float per k), fixed order
+__device__ __forceinline__ void slot_reduce_store(float v, float* lds, float* dst) {
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  lds[slot * MP_H + k] = v;
+  __syncthreads();
+  if (threadIdx.x < MP_H) {
+    float s = 0.0f;
+    for (int q = 0; q < NODES; ++q) s += lds[q * MP_H + k];
+    dst[k] = s;
+  }
+  __syncthreads();
+}
+
+// row-k accumulators acc[0..31] of a 32 x 32 matrix, summed over node slots
+__device__ __forceinline__ void slot_reduce_matrix(const float (&acc)[MP_H], float* lds, float* dst) {
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  for (int q = 0; q < MP_H; ++q) lds[(slot * MP_H + k) * MP_H + q] = acc[q];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < MP_H * MP_H; idx += blockDim.x) {
+    float s = 0.0f;
+    for (int sl = 0; sl < NODES; ++sl) s += lds[sl * MP_H * MP_H + idx];
+    dst[idx] = s;
+  }
+  __syncthreads();
+}
+
+// heads: dL/dh^3 (into dh) and the head parameters v, v0, z, ze, z0
+__global__ __launch_bounds__(MP_THREADS) void k_mp_heads_bwd(DevPtrs d, MpPtrs m) {
+  __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
+  __shared__ float red[NODES * MP_H * MP_H];
+  load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
+  load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
+  load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hf = m.h + (int64_t)MP_NL * m.rows * MP_H;
+  float g_v = 0.0f, g_v0 = 0.0f, g_z = 0.0f, g_z0 = 0.0f, g_ze[MP_FE] = {0.0f, 0.0f, 0.0f};
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const double di = d.diag[i];
+    double gd = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gd += m.G[3 * i + c] * d.b[3 * i + c];
+    const double gl = gd / di;
+    const float tau = m.tau[i];
+    const float gt = (float)gl * sigmoidf_(tau);
+    const float hk = act_in(m, hf[i * MP_H + k]);
+    float dh = gt * hv[k];
+    g_v += gt * hk;
+    if (k == 0) g_v0 += gt;
+    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+      const int64_t j = d.col[e];
+      const double dj = d.diag[j];
+      const double sq = sqrt(di * dj);
+      const double what = -d.val[e] / sq;
+      double gm = 0.0, gdj = 0.0, gmr = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gm += m.G[3 * i + c] * d.b[3 * j + c];    // this entry (i -> j)
+        gdj += m.G[3 * j + c] * d.b[3 * j + c];   // node j's diagonal term
+        gmr += m.G[3 * j + c] * d.b[3 * i + c];   // the reverse entry (j -> i)
+      }
+      const float t = m.tg[e];
+      const float g = 2.0f * sigmoidf_(t);
+      const float dgdt = g * (1.0f - 0.5f * g);
+      const float dt_own = (float)((gm / sq + gl) * what) * dgdt;
+      const float dt_rev = (float)((gmr / sq + gdj / dj) * what) * dgdt;
+      const float hj = act_in(m, hf[j * MP_H + k]);
+      dh += (dt_own + dt_rev) * hz[k] * hj;
+      g_z += dt_own * (hk * hj);
+      if (k == 0) {
+        g_z0 += dt_own;
+#pragma unroll
+        for (int f = 0; f < MP_FE; ++f) g_ze[f] += dt_own * act_in(m, m.ef[3 * (int64_t)e + f]);
+      }
+    }
+    m.dh[i * MP_H + k] = dh;
+  }
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + MP_OFF_HEAD;
+  slot_reduce_store(g_v, red, dst + MP_H_V);
+  slot_reduce_store(g_z, red, dst + MP_H_Z);
+  // scalar terms live in lane 0 of each slot
+  float sc[2 + MP_FE] = {g_v0, g_z0, g_ze[0], g_ze[1], g_ze[2]};
+  for (int q = 0; q < 2 + MP_FE; ++q) {
+    red[threadIdx.x] = sc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.0f;
+      for (int sl = 0; sl < NODES; ++sl) s += red[sl * MP_H];
+      const int off = q == 0 ? MP_H_V0 : (q == 1 ? MP_H_Z0 : MP_H_ZE + (q - 2));
+      dst[off] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// layer l backward, part A (per node i): da = dh * [a > 0];
+// dU, dV, dd; dh_in = dh + U^T da; dm = V^T da
+__global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_a(DevPtrs d, MpPtrs m, int l) {
+  __shared__ float U[MP_H * MP_H], V[MP_H * MP_H];
+  __shared__ float sda[NODES][MP_H];
+  __shared__ float red[NODES * MP_H * MP_H];
+  const int base = MP_OFF_L0 + l * MP_L_SIZE;
+  load_w(m, U, base + MP_L_U, MP_H * MP_H);
+  load_w(m, V, base + MP_L_V, MP_H * MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hin = m.h + (int64_t)l * m.rows * MP_H;
+  const float* __restrict__ mm = m.m + (int64_t)l * m.rows * MP_H;
+  const float* __restrict__ aa = m.a + (int64_t)l * m.rows * MP_H;
+  float accU[MP_H], accV[MP_H], accd = 0.0f;
+#pragma unroll
+  for (int q = 0; q < MP_H; ++q) accU[q] = accV[q] = 0.0f;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const float dh = m.dh[i * MP_H + k];
+    const float da = aa[i * MP_H + k] > 0.0f ? dh : 0.0f;
+    accd += da;
+    for (int q = 0; q < MP_H; ++q) {
+      accU[q] += da * act_in(m, hin[i * MP_H + q]);
+      accV[q] += da * act_in(m, mm[i * MP_H + q]);
+    }
+    sda[slot][k] = da;
+    __syncthreads();
+    float su = 0.0f, sv = 0.0f;
+#pragma unroll 8
+    for (int q = 0; q < MP_H; ++q) {
+      su += U[q * MP_H + k] * sda[slot][q];
+      sv += V[q * MP_H + k] * sda[slot][q];
+    }
+    m.dh2[i * MP_H + k] = dh + su;
+    m.dm[i * MP_H + k] = sv;
+    __syncthreads();
+  }
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + base;
+  slot_reduce_matrix(accU, red, dst + MP_L_U);
+  slot_reduce_matrix(accV, red, dst + MP_L_V);
+  slot_reduce_store(accd, red, dst + MP_L_D);
+}
+
+// layer l backward, part B (per node j, pulling from its neighbours i):
+// dy_j = 1/8 sum_i dm_i [y_j + Q e_ij + c > 0]; dQ, dc, dP; dh_in_j += P^T dy_j
+__global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_b(DevPtrs d, MpPtrs m, int l) {
+  __shared__ float P[MP_H * MP_H], Q[MP_H * MP_FE], c[MP_H];
+  __shared__ float sdy[NODES][MP_H];
+  __shared__ float red[NODES * MP_H * MP_H];
+  const int base = MP_OFF_L0 + l * MP_L_SIZE;
+  load_w(m, P, base + MP_L_P, MP_H * MP_H);
+  load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
+  load_w(m, c, base + MP_L_C, MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hin = m.h + (int64_t)l * m.rows * MP_H;
+  const float* __restrict__ y = m.y + (int64_t)l * m.rows * MP_H;
+  float accP[MP_H], accQ[MP_FE] = {0.0f, 0.0f, 0.0f}, accc = 0.0f;
+#pragma unroll
+  for (int q = 0; q < MP_H; ++q) accP[q] = 0.0f;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t j = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const float yj = y[j * MP_H + k];
+    float dy = 0.0f;
+    for (int e = d.rowptr[j]; e < d.rowptr[j + 1]; ++e) {
+      const int64_t i = d.col[e];
+      float s = yj + c[k];
+      float ef[MP_FE];
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) {
+        ef[f] = act_in(m, m.ef[3 * (int64_t)e + f]);
+        s += Q[k * MP_FE + f] * ef[f];
+      }
+      if (s > 0.0f) {
+        const float ds = MP_MSG * m.dm[i * MP_H + k];
+        dy += ds;
+        accc += ds;
+#pragma unroll
+        for (int f = 0; f < MP_FE; ++f) accQ[f] += ds * ef[f];
+      }
+    }
+    for (int q = 0; q < MP_H; ++q) accP[q] += dy * act_in(m, hin[j * MP_H + q]);
+    sdy[slot][k] = dy;
+    __syncthreads();
+    float sp = 0.0f;
+#pragma unroll 8
+    for (int q = 0; q < MP_H; ++q) sp += P[q * MP_H + k] * sdy[slot][q];
+    m.dh[j * MP_H + k] = m.dh2[j * MP_H + k] + sp;  // dL/dh^l for the next part A
+    __syncthreads();
+  }
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + base;
+  slot_reduce_matrix(accP, red, dst + MP_L_P);
+  slot_reduce_store(accc, red, dst + MP_L_C);
+  for (int f = 0; f < MP_FE; ++f) {
+    red[threadIdx.x] = accQ[f];
+    __syncthreads();
+    if (threadIdx.x < MP_H) {
+      float s = 0.0f;
+      for (int sl = 0; sl < NODES; ++sl) s += red[sl * MP_H + threadIdx.x];
+      dst[MP_L_Q + threadIdx.x * MP_FE + f] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// encoder backward: h0 = relu(W0 x + b0)
+__global__ __launch_bounds__(MP_THREADS) void k_mp_encode_bwd(DevPtrs d, MpPtrs m) {
+  __shared__ float w0[MP_H * MP_FN], b0[MP_H];
+  __shared__ float red[NODES * MP_H];
+  load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
+  load_w(m, b0, MP_OFF_B0, MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  float gw[MP_FN] = {0.0f, 0.0f, 0.0f}, gb = 0.0f;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    float x[MP_FN];
+    float acc = b0[k];
+#pragma unroll
+    for (int f = 0; f < MP_FN; ++f) {
+      x[f] = act_in(m, m.x[3 * i + f]);
+      acc += w0[k * MP_FN + f] * x[f];
+    }
+    if (acc > 0.0f) {
+      const float dh = m.dh[i * MP_H + k];
+      gb += dh;
+#pragma unroll
+      for (int f = 0; f < MP_FN; ++f) gw[f] += dh * x[f];
+    }
+  }
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS;
+  slot_reduce_store(gb, red, dst + MP_OFF_B0);
+  for (int f = 0; f < MP_FN; ++f) {
+    red[threadIdx.x] = gw[f];
+    __syncthreads();
+    if (threadIdx.x < MP_H) {
+      float s = 0.0f;
+      for (int sl = 0; sl < NODES; ++sl) s += red[sl * MP_H + threadIdx.x];
+      dst[MP_OFF_W0 + threadIdx.x * MP_FN + f] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// grad[p] = (1/den) sum_b gpart[b][p], blocks in order
+__global__ __launch_bounds__(256) void k_mp_grad_reduce(MpPtrs m, int nblk) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= MP_NPARAMS) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += m.gpart[(int64_t)b * MP_NPARAMS + p];
+  m.grad[p] = (float)(s * m.loss[1]);
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights, then the bf16 copy
+__global__ __launch_bounds__(256) void k_mp_adam(MpPtrs m, float lr, int t) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= MP_NPARAMS) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = m.grad[p];
+  const float mo = b1 * m.am[p] + (1.0f - b1) * g;
+  const float vo = b2 * m.av[p] + (1.0f - b2) * g * g;
+  m.am[p] = mo;
+  m.av[p] = vo;
+  const float mh = mo / (1.0f - powf(b1, (float)t));
+  const float vh = vo / (1.0f - powf(b2, (float)t));
+  const float th = m.th32[p] - lr * mh / (sqrtf(vh) + eps);
+  m.th32[p] = th;
+  m.w16[p] = bf16_bits(th);
+}
+
+// bf16 copy of the master weights
+__global__ __launch_bounds__(256) void k_mp_cast(MpPtrs m) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < MP_NPARAMS) m.w16[p] = bf16_bits(m.th32[p]);
+}
+
+// parity export of M^-1 in global original numbering (as k_export_system)
+__global__ __launch_bounds__(256) void k_mp_export(DevPtrs d, MpPtrs m, const int64_t* __restrict__ id_off,
+                                                   int64_t* __restrict__ rows, int64_t* __restrict__ cols,
+                                                   double* __restrict__ vals, int64_t cap,
+                                                   double* __restrict__ diag_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const int rid = d.blk_rep[i / ROWS_PER_BLOCK];
+  const RepDev& R = d.rep[rid];
+  if (i - R.row_off >= R.n) return;
+  const int64_t gi = id_off[rid] + (int64_t)d.pos[i].w;
+  diag_out[gi] = m.mdiag[i];
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    if (e >= cap) break;
+    rows[e] = gi;
+    cols[e] = id_off[rid] + (int64_t)d.pos[d.col[e]].w;
+    vals[e] = (double)m.moff[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+  const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
+  hipLaunchKernelGGL(k_mp_features, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m);
+  hipLaunchKernelGGL(k_mp_encode, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  for (int l = 0; l < MP_NL; ++l)
+    hipLaunchKernelGGL(k_mp_layer, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
+  hipLaunchKernelGGL(k_mp_heads, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_loss(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+  const unsigned b = nb(d.rows, 256);
+  hipLaunchKernelGGL(k_mp_resid, dim3(b), dim3(256), 0, s, d, m);
+  hipLaunchKernelGGL(k_mp_aprod, dim3(b), dim3(256), 0, s, d, m);
+  hipLaunchKernelGGL(k_mp_loss, dim3(1), dim3(1024), 0, s, m, (int)b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+  const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
+  hipLaunchKernelGGL(k_mp_heads_bwd, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  for (int l = MP_NL - 1; l >= 0; --l) {
+    hipLaunchKernelGGL(k_mp_layer_bwd_a, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
+    hipLaunchKernelGGL(k_mp_layer_bwd_b, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
+  }
+  hipLaunchKernelGGL(k_mp_encode_bwd, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  hipLaunchKernelGGL(k_mp_grad_reduce, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m,
+                     (int)blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_adam(const MpPtrs& m, float lr, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_adam, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m, lr, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_export(const DevPtrs& d, const MpPtrs& m, const int64_t* id_off, int64_t* rows,
+                            int64_t* cols, double* vals, int64_t cap, double* diag, hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_export, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m, id_off, rows, cols,
+                     vals, cap, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_cast(const MpPtrs& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_cast, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m);
+  return hipGetLastError();
+}

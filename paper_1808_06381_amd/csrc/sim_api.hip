@@ -18,10 +18,12 @@
 #include <vector>
 
 #include "launch.h"
+#include "mpnn.h"
 #include "sim.h"
 #include "sim_dev.h"
 
 #define SIM_EOVERFLOW_INTERNAL 1  // capacity of the CSR arrays exceeded: grow and refill
+#define SIM_ESTALL_INTERNAL 2     // learned-preconditioned solve stalled: redo with Jacobi
 
 #define HIPCHK(expr)                                   \
   do {                                                 \
@@ -68,11 +70,20 @@ struct sim_t {
   std::vector<hipEvent_t> prof_ev;      // pool of event pairs
   struct Sample { int kernel; int iter; int ev; float ms; };
   std::vector<Sample> prof_pending;     // recorded in the current solve
-  sim_kernel_prof prof_acc[2] = {};
+  sim_kernel_prof prof_acc[3] = {};
+  // learned preconditioner
+  bool learned = false;      // precond == SIM_PC_LEARNED
+  MpPtrs mp{};
+  bool mp_ready = false;     // node buffers and weights allocated
+  bool mp_train = false;     // training buffers allocated
+  int64_t mp_nnz_cap = 0;    // capacity of the per-entry buffers
+  int32_t mp_adam_t = 0;
+  int32_t learned_maxit = 0;  // 0: cg_maxit
+  bool system_valid = false; // A, b, x of a successful solve are in place
 };
 
-static const int kProfKernels = 2;
-static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv"};
+static const int kProfKernels = 3;
+static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_apply"};
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -116,7 +127,8 @@ static int validate(const sim_params& p) {
   if (!(p.cg_tol > 0.0) || p.cg_maxit < 1) return SIM_EINVAL;
   if (p.warm_start != 0) return SIM_EINVAL;
   if (p.spmv_fp32 != 0 && p.spmv_fp32 != 1) return SIM_EINVAL;
-  if (p.precond == SIM_PC_IC0 || p.precond == SIM_PC_LEARNED) return SIM_ENOTSUP;
+  if (p.precond == SIM_PC_LEARNED && !(p.alpha > 0.0)) return SIM_EINVAL;
+  if (p.precond == SIM_PC_IC0) return SIM_ENOTSUP;
   return SIM_OK;
 }
 
@@ -172,15 +184,78 @@ static int alloc_csr(sim_t* s, int64_t cap) {
   dfree(s, s->d.col);
   dfree(s, s->d.val);
   dfree(s, s->d.valf);
+  dfree(s, s->d.er);
   s->d.col = nullptr;
   s->d.val = nullptr;
   s->d.valf = nullptr;
+  s->d.er = nullptr;
   if (cap > (int64_t)INT32_MAX) cap = INT32_MAX;
   int rc;
   if ((rc = dalloc(s, (void**)&s->d.col, sizeof(int32_t) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.val, sizeof(double) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.valf, sizeof(float) * (size_t)cap))) return rc;
+  if ((rc = dalloc(s, (void**)&s->d.er, sizeof(float) * (size_t)cap))) return rc;
   s->d.nnz_cap = cap;
+  return SIM_OK;
+}
+
+// Buffers of the learned preconditioner: node arrays and weights once,
+// per-entry arrays whenever the CSR capacity changed, training arrays on the
+// first training step.  Weights start at zero (a valid SPD preconditioner).
+static int ensure_mp(sim_t* s, bool training) {
+  MpPtrs& m = s->mp;
+  const size_t rows = (size_t)s->rows, H = MP_H;
+  int rc;
+#define MPALLOC(ptr, bytes) \
+  if ((rc = dalloc(s, (void**)&(ptr), (bytes))) != SIM_OK) return rc;
+  if (!s->mp_ready) {
+    MPALLOC(m.w16, sizeof(uint16_t) * MP_NPARAMS);
+    MPALLOC(m.th32, sizeof(float) * MP_NPARAMS);
+    MPALLOC(m.am, sizeof(float) * MP_NPARAMS);
+    MPALLOC(m.av, sizeof(float) * MP_NPARAMS);
+    MPALLOC(m.grad, sizeof(float) * MP_NPARAMS);
+    MPALLOC(m.x, sizeof(float) * 3 * rows);
+    MPALLOC(m.h, sizeof(float) * (MP_NL + 1) * rows * H);
+    MPALLOC(m.y, sizeof(float) * MP_NL * rows * H);
+    MPALLOC(m.tau, sizeof(float) * rows);
+    MPALLOC(m.mdiag, sizeof(double) * rows);
+    MPALLOC(m.lpart, sizeof(double) * 2 * (rows / 256 + 1));
+    MPALLOC(m.loss, sizeof(double) * 2);
+    HIPCHK(hipMemset(m.w16, 0, sizeof(uint16_t) * MP_NPARAMS));
+    HIPCHK(hipMemset(m.th32, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemset(m.am, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemset(m.av, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemset(m.grad, 0, sizeof(float) * MP_NPARAMS));
+    m.rows = s->rows;
+    m.round_act = 1;
+    s->mp_ready = true;
+  }
+  if (s->mp_nnz_cap != s->d.nnz_cap) {
+    dfree(s, m.ef);
+    dfree(s, m.tg);
+    dfree(s, m.moff);
+    m.ef = m.tg = m.moff = nullptr;
+    const size_t cap = (size_t)s->d.nnz_cap;
+    MPALLOC(m.ef, sizeof(float) * 3 * cap);
+    MPALLOC(m.tg, sizeof(float) * cap);
+    MPALLOC(m.moff, sizeof(float) * cap);
+    s->mp_nnz_cap = s->d.nnz_cap;
+  }
+  if (training && !s->mp_train) {
+    MPALLOC(m.m, sizeof(float) * MP_NL * rows * H);
+    MPALLOC(m.a, sizeof(float) * MP_NL * rows * H);
+    MPALLOC(m.zb, sizeof(double) * 3 * rows);
+    MPALLOC(m.G, sizeof(double) * 3 * rows);
+    MPALLOC(m.dh, sizeof(float) * rows * H);
+    MPALLOC(m.dh2, sizeof(float) * rows * H);
+    MPALLOC(m.dm, sizeof(float) * rows * H);
+    MPALLOC(m.gpart, sizeof(float) * (rows / MP_ROWS) * MP_NPARAMS);
+    s->mp_train = true;
+  }
+#undef MPALLOC
+  m.er = s->d.er;
+  s->d.mdiag = m.mdiag;
+  s->d.moff = m.moff;
   return SIM_OK;
 }
 
@@ -192,6 +267,7 @@ static int alloc_csr(sim_t* s, int64_t cap) {
 // fill is read back later (with the first CG chunk).
 static int build_system(sim_t* s, int64_t step) {
   DevPtrs& d = s->d;
+  s->system_valid = false;
   hipStream_t st = s->stream;
   HIPCHK(launch_ctrl_zero(d, st));
   HIPCHK(launch_fill_i32(d.cell_count, 0, d.ncell_entries, st));
@@ -239,11 +315,15 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
   hipStream_t stream = s->stream;
   int maxit = 1;
   for (auto& p : s->prm) maxit = std::max(maxit, p.cg_maxit);
+  if (d.learned && s->learned_maxit > 0) maxit = std::min(maxit, (int)s->learned_maxit);
+  const bool learned = d.learned != 0;
   HIPCHK(launch_cg_reset(d, tol, stream));
   HIPCHK(launch_cg_vec(d, 0, stream));
+  if (learned) HIPCHK(launch_cg_apply(d, 0, stream));
   HIPCHK(launch_cg_spmv(d, 0, 0, stream));
   HIPCHK(launch_cg_finish(d, 0, stream));
   int launched = 0;
+  std::vector<std::pair<int, double>> hist;  // (iterations, worst relative residual^2)
   int chunk = s->last_iters > 2 ? s->last_iters - 1 : 8;
   int status = SIM_OK;
   for (;;) {
@@ -253,7 +333,11 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
       const int g = launched + k;
       const bool probe = s->prof_every > 0 && g % s->prof_every == 0 &&
                          (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
-      for (int kern = 0; kern < kProfKernels; ++kern) {
+      // vector update, then (learned) u = M^-1 r, then w = A u
+      const int order[3] = {0, 2, 1};
+      for (int oi = 0; oi < 3; ++oi) {
+        const int kern = order[oi];
+        if (kern == 2 && !learned) continue;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (probe) {
           const int ev = (int)s->prof_pending.size();
@@ -262,7 +346,8 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
           e1 = s->prof_ev[2 * ev + 1];
         }
         if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
-        else HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
+        else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
+        else HIPCHK(launch_cg_apply(d, 2, stream, e0, e1));
       }
       HIPCHK(launch_cg_finish(d, 2, stream));
     }
@@ -272,6 +357,7 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
     HIPCHK(launch_cg_spmv(d, 1, 0, stream));
     HIPCHK(launch_cg_finish(d, 3, stream));
     HIPCHK(launch_cg_vec(d, 1, stream));
+    if (learned) HIPCHK(launch_cg_apply(d, 1, stream));
     HIPCHK(launch_cg_spmv(d, 0, 1, stream));
     HIPCHK(launch_cg_finish(d, 1, stream));
     int rc = read_ctrl(s, true);
@@ -279,9 +365,28 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
     if (s->ctrl_h->overflow) { status = SIM_EOVERFLOW_INTERNAL; break; }
     if (s->ctrl_h->n_notdone == 0) break;
     if (launched > maxit) { status = SIM_ENOCONV; break; }
+    if (learned) {
+      // stall: the worst relative residual of an unfinished component has
+      // not dropped by 10 % over the last 10 or more iterations (after 20)
+      double worst = 0.0;
+      for (int r = 0; r < s->R; ++r)
+        for (int k = 0; k < 3; ++k) {
+          const CgRep& c = s->cg_h[r];
+          if (c.state[k] != 2 && c.bb[k] > 0.0) worst = std::max(worst, c.rr[k] / c.bb[k]);
+        }
+      hist.push_back({launched, worst});
+      if (launched >= 20) {
+        for (auto it = hist.rbegin(); it != hist.rend(); ++it)
+          if (launched - it->first >= 10) {
+            if (!(worst < 0.81 * it->second)) status = SIM_ESTALL_INTERNAL;  // 0.9^2 on squares
+            break;
+          }
+        if (status) break;
+      }
+    }
     chunk = 2;
   }
-  if (status == SIM_EOVERFLOW_INTERNAL) {
+  if (status == SIM_EOVERFLOW_INTERNAL || status == SIM_ESTALL_INTERNAL) {
     s->prof_pending.clear();
     return status;
   }
@@ -309,10 +414,14 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
     const double rows = (double)s->rows, nnz = (double)s->ctrl_h->nnz;
     const double ntile = (double)d.nblk;
     const double per_launch[kProfKernels] = {
-        // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written (120)
-        rows * 248.0 + ntile * 6.0 * 8.0,
+        // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written
+        // (120); with the learned preconditioner u is read instead of 1/diag and not written
+        (learned ? rows * 240.0 : rows * 248.0) + ntile * 6.0 * 8.0,
         // product: row pointers (4), u (24), diag (8), w written (24), CSR col + value
-        rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0};
+        rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0,
+        // learned apply: row pointers (4), r (24), M^-1 diagonal (8), u written (24),
+        // column + FP32 value per entry
+        rows * 60.0 + 4.0 + nnz * 8.0 + ntile * 3.0 * 8.0};
     for (auto& smp : s->prof_pending) {
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[2 * smp.ev], s->prof_ev[2 * smp.ev + 1]));
@@ -343,9 +452,25 @@ static int build_and_solve(sim_t* s, int64_t step, bool replace_rhs, double tol,
   int rc = build_system(s, step);
   if (rc) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
+    if (s->learned) {
+      if ((rc = ensure_mp(s, false))) return rc;
+      s->mp.store_train = 0;
+      HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+      s->d.learned = 1;
+    }
     if (replace_rhs) HIPCHK(launch_permute(s->d, s->id_off_d, 1, s->io, nullptr, s->stream));
     rc = cg_solve(s, tol, st);
-    if (rc != SIM_EOVERFLOW_INTERNAL) return rc;
+    if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
+      // the learned solve did not make progress: redo it with Jacobi
+      s->d.learned = 0;
+      rc = cg_solve(s, tol, st);
+      s->d.learned = 1;
+      if (st) st->fallback = 1;
+    }
+    if (rc != SIM_EOVERFLOW_INTERNAL) {
+      if (rc == SIM_OK) s->system_valid = true;
+      return rc;
+    }
     rc = grow_and_refill(s, step);
     if (rc) return rc;
   }
@@ -409,6 +534,9 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   if (hipGetDevice(&s->device) != hipSuccess) { delete s; return SIM_EDEVICE; }
   s->R = replicas;
   s->prm.assign(params, params + replicas);
+  s->learned = params[0].precond == SIM_PC_LEARNED;
+  for (int r = 1; r < replicas; ++r)
+    if ((params[r].precond == SIM_PC_LEARNED) != s->learned) { delete s; return SIM_EINVAL; }
   // layout
   int64_t row_off = 0, seg_off = 0, n_total = 0;
   int32_t blk_off = 0;
@@ -553,9 +681,109 @@ int sim_set_stream(sim_t* s, void* stream) {
   return SIM_OK;
 }
 
+int sim_precond_weights(sim_t* s, float* theta, int64_t count, int32_t set) {
+  if (!s || !theta || count != MP_NPARAMS) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, false);
+  if (rc) return rc;
+  if (set) {
+    HIPCHK(hipMemcpy(s->mp.th32, theta, sizeof(float) * MP_NPARAMS, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(s->mp.am, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemset(s->mp.av, 0, sizeof(float) * MP_NPARAMS));
+    s->mp_adam_t = 0;
+    HIPCHK(launch_mp_cast(s->mp, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+  } else {
+    HIPCHK(hipMemcpy(theta, s->mp.th32, sizeof(float) * MP_NPARAMS, hipMemcpyDeviceToHost));
+  }
+  return SIM_OK;
+}
+
+int sim_precond_config(sim_t* s, int32_t round_act, int32_t learned_maxit) {
+  if (!s || (round_act != 0 && round_act != 1) || learned_maxit < 0) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, false);
+  if (rc) return rc;
+  s->mp.round_act = round_act;
+  s->learned_maxit = learned_maxit;
+  return SIM_OK;
+}
+
 int sim_load_precond(sim_t* s, const char* path) {
   if (!s || !path) return SIM_EINVAL;
-  return SIM_ENOTSUP;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return SIM_EINVAL;
+  char magic[8];
+  int64_t count = 0;
+  std::vector<float> th(MP_NPARAMS);
+  const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "SIMPC001", 8) == 0 &&
+                  std::fread(&count, sizeof(count), 1, f) == 1 && count == MP_NPARAMS &&
+                  std::fread(th.data(), sizeof(float), MP_NPARAMS, f) == (size_t)MP_NPARAMS;
+  std::fclose(f);
+  if (!ok) return SIM_EINVAL;
+  return sim_precond_weights(s, th.data(), MP_NPARAMS, 1);
+}
+
+int sim_train_step(sim_t* s, double lr, double* loss) {
+  if (!s || !(lr >= 0.0)) return SIM_EINVAL;
+  if (s->R != 1) return SIM_ENOTSUP;
+  if (!s->system_valid) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, true);
+  if (rc) return rc;
+  s->mp.store_train = 1;
+  HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  HIPCHK(launch_mp_loss(s->d, s->mp, s->stream));
+  HIPCHK(launch_mp_backward(s->d, s->mp, s->stream));
+  if (lr > 0.0) HIPCHK(launch_mp_adam(s->mp, (float)lr, ++s->mp_adam_t, s->stream));
+  double l[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(l, s->mp.loss, sizeof(l), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (loss) *loss = l[0];
+  return std::isfinite(l[0]) ? SIM_OK : SIM_ENUMERIC;
+}
+
+int sim_precond_grad(sim_t* s, float* grad, int64_t count) {
+  if (!s || !grad || count != MP_NPARAMS || !s->mp_ready) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  HIPCHK(hipMemcpy(grad, s->mp.grad, sizeof(float) * MP_NPARAMS, hipMemcpyDeviceToHost));
+  return SIM_OK;
+}
+
+int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                      int64_t* count, double* mdiag) {
+  if (!s || !count || cap < 0) return SIM_EINVAL;
+  if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = build_checked(s, s->step);
+  if (rc) return rc;
+  if ((rc = ensure_mp(s, false))) return rc;
+  s->mp.store_train = 0;
+  HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  const int64_t nnz = s->ctrl_h->nnz;
+  *count = nnz;
+  if (nnz > cap) return SIM_ECAPACITY;
+  int64_t *r_d = nullptr, *c_d = nullptr;
+  double *v_d = nullptr, *dg_d = nullptr;
+  const size_t m = (size_t)std::max<int64_t>(nnz, 1);
+  if ((rc = dalloc(s, (void**)&r_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&c_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * (size_t)s->n_total))) return rc;
+  HIPCHK(launch_mp_export(s->d, s->mp, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, s->stream));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpyAsync(rows, r_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(cols, c_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vals, v_d, sizeof(double) * nnz, hipMemcpyDeviceToHost, s->stream));
+  }
+  if (mdiag)
+    HIPCHK(hipMemcpyAsync(mdiag, dg_d, sizeof(double) * s->n_total, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  dfree(s, r_d);
+  dfree(s, c_d);
+  dfree(s, v_d);
+  dfree(s, dg_d);
+  return SIM_OK;
 }
 
 int sim_step(sim_t* s, int32_t nsteps, sim_stats* st) {

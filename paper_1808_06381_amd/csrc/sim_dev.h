@@ -98,6 +98,9 @@ struct DevPtrs {
   double* w;
   double* u;
   double* vel_orig;         // velocities of the last step, original order
+  float* er;                // r_ij / rc per CSR entry (learned preconditioner input)
+  const double* mdiag;      // learned M^-1 diagonal, or null (Jacobi)
+  const float* moff;        // learned M^-1 off-diagonal (A's pattern)
   const double* inj_xi;     // injected Gaussians (testing), or null
   const double* inj_eta;
   int64_t nnz_cap;
@@ -106,6 +109,7 @@ struct DevPtrs {
   int32_t nrep;
   int32_t ncell_entries;
   int32_t spmv_fp32;
+  int32_t learned;          // 1: u = M^-1 r by the learned preconditioner
 };
 
 // ---------------------------------------------------------------------------

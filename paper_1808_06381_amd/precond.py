@@ -90,3 +90,36 @@ def load(path):
     if theta.size != NPARAMS:
         raise ValueError("weight count mismatch")
     return theta
+
+
+def train(steps, n=100_000, lr=3e-3, seed=0, episode=100, shear_range=(0.01, 1.0),
+          theta=None, tol=1e-10, log_every=0):
+    """Train the network on (A, b, x*) triples that the simulation generates:
+    boxes of n particles (density 1, the friction-matrix workload physics), a
+    new box with a log-uniform shear rate every `episode` steps; each step's
+    Jacobi-PCG solve (tolerance `tol`) supplies one triple and one Adam step.
+    Returns (theta, losses)."""
+    from . import inputs
+    from . import sim as S
+
+    rng = np.random.default_rng(seed)
+    theta = init_params(seed) if theta is None else np.asarray(theta, dtype=np.float32)
+    lo, hi = math.log(shear_range[0]), math.log(shear_range[1])
+    losses = []
+    done = 0
+    while done < steps:
+        kappa = math.exp(rng.uniform(lo, hi))
+        box_seed = int(rng.integers(1, 2**31))
+        cfg = inputs.cube_params(n, kappa, seed=box_seed)
+        pos = inputs.uniform_positions(n, cfg["box"], box_seed)
+        with S.Sim(cfg, pos, tol=tol, precond="jacobi") as sm:
+            sm.set_weights(theta)
+            for _ in range(min(episode, steps - done)):
+                sm.step(1)
+                losses.append(sm.train_step(lr))
+                done += 1
+                if log_every and done % log_every == 0:
+                    print(f"train step {done}: loss {np.mean(losses[-log_every:]):.4f}",
+                          flush=True)
+            theta = sm.get_weights()
+    return theta, np.array(losses)

@@ -26,7 +26,9 @@ PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
 EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
             "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
-            "sim_copy_probe", "sim_destroy", "sim_strerror"]
+            "sim_copy_probe", "sim_precond_weights", "sim_precond_config", "sim_train_step",
+            "sim_precond_grad", "sim_debug_precond", "sim_destroy", "sim_strerror"]
+MPNN_NPARAMS = 9893
 
 
 class SimParams(C.Structure):
@@ -125,6 +127,11 @@ def lib():
         L.sim_profile_enable.argtypes = [vp, C.c_int32]
         L.sim_profile_read.argtypes = [vp, P(SimKernelProf), C.c_int32, P(C.c_int32), C.c_int32]
         L.sim_copy_probe.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_double)]
+        L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
+        L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sim_train_step.argtypes = [vp, C.c_double, P(C.c_double)]
+        L.sim_precond_grad.argtypes = [vp, vp, C.c_int64]
+        L.sim_debug_precond.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -289,6 +296,45 @@ class Sim:
         _check(lib().sim_profile_read(self.h, arr, 8, C.byref(cnt), int(reset)), "sim_profile_read")
         return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms,
                                            bytes=arr[k].bytes) for k in range(cnt.value)}
+
+    def set_weights(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(lib().sim_precond_weights(self.h, _ptr(theta), theta.size, 1), "sim_precond_weights")
+
+    def get_weights(self):
+        theta = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        _check(lib().sim_precond_weights(self.h, _ptr(theta), theta.size, 0), "sim_precond_weights")
+        return theta
+
+    def precond_config(self, round_act=True, learned_maxit=0):
+        _check(lib().sim_precond_config(self.h, int(bool(round_act)), int(learned_maxit)),
+               "sim_precond_config")
+
+    def train_step(self, lr):
+        loss = C.c_double()
+        _check(lib().sim_train_step(self.h, float(lr), C.byref(loss)), "sim_train_step")
+        return loss.value
+
+    def precond_grad(self):
+        g = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        _check(lib().sim_precond_grad(self.h, _ptr(g), g.size), "sim_precond_grad")
+        return g
+
+    def precond_matrix(self):
+        """(rows, cols, vals, mdiag) of the learned M^-1 at the current positions."""
+        cnt = C.c_int64()
+        rc = lib().sim_debug_precond(self.h, None, None, None, 0, C.byref(cnt), None)
+        if rc not in (SIM_OK, -6):
+            _check(rc, "sim_debug_precond")
+        m = max(cnt.value, 1)
+        rows = np.zeros(m, dtype=np.int64)
+        cols = np.zeros(m, dtype=np.int64)
+        vals = np.zeros(m)
+        mdiag = np.zeros(self.n_total)
+        _check(lib().sim_debug_precond(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
+                                       C.byref(cnt), _ptr(mdiag)), "sim_debug_precond")
+        k = cnt.value
+        return rows[:k], cols[:k], vals[:k], mdiag
 
     def load_precond(self, path):
         _check(lib().sim_load_precond(self.h, path.encode()), "sim_load_precond")

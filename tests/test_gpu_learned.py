@@ -1,0 +1,155 @@
+"""GPU parity of the learned preconditioner (through the C ABI) against the
+oracle's FP64 network: M^-1 entry by entry, the training loss and its
+gradient; solves with the learned preconditioner against dense LAPACK; the
+forced Jacobi fallback; and what training gains over Jacobi.
+
+Tolerances: with activations kept in FP32 (round_act off) the GPU network is
+an FP32 evaluation of the oracle's FP64 one on the same bfloat16 weights:
+1e-4 relative on M^-1 and the loss, 1e-3 on the gradient norm.  With the
+default bfloat16 activations the products see inputs rounded to 2^-9
+relative, fan-in <= 64: 3e-2 relative on M^-1."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_06381_amd import inputs, precond
+from paper_1808_06381_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+
+
+def case(n=2000, seed=3, alpha=1.0):
+    cfg = inputs.cube_params(n, 0.3, seed=seed, alpha=alpha)
+    pos = inputs.uniform_positions(n, cfg["box"], seed)
+    return cfg, pos
+
+
+def random_theta(seed, scale=0.3):
+    th = precond.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for name in ("v", "v0", "z", "ze", "z0"):
+        off, shape = precond.LAYOUT[name]
+        th[off:off + int(np.prod(shape))] = rng.normal(0, scale, int(np.prod(shape)))
+    return th
+
+
+def oracle_minv(cfg, pos, theta, step=0):
+    s = oracle.build_system(cfg, pos, step)
+    er = oracle.edge_r(cfg, pos, s, step)
+    mdiag, moff = oracle.mpnn_forward(s, er, cfg["alpha"], theta)
+    rows = np.repeat(np.arange(cfg["n"]), np.diff(s["rowptr"]))
+    return s, er, mdiag, rows, s["col"], moff
+
+
+def sorted_triples(rows, cols, vals):
+    o = np.lexsort((cols, rows))
+    return rows[o], cols[o], vals[o]
+
+
+@pytest.mark.parametrize("round_act,rtol", [(False, 1e-4), (True, 3e-2)])
+def test_minv_matches_oracle(round_act, rtol):
+    cfg, pos = case()
+    th = random_theta(1)
+    with S.Sim(cfg, pos, precond="learned") as sim:
+        sim.set_weights(th)
+        sim.precond_config(round_act=round_act)
+        gr, gc, gv, gd = sim.precond_matrix()
+    s, er, md, orow, ocol, ov = oracle_minv(cfg, pos, th)
+    gr, gc, gv = sorted_triples(gr, gc, gv)
+    orow, ocol, ov = sorted_triples(orow, ocol, ov)
+    assert np.array_equal(gr, orow) and np.array_equal(gc, ocol)
+    np.testing.assert_allclose(gd, md, rtol=rtol)
+    np.testing.assert_allclose(gv, ov, rtol=rtol, atol=rtol * np.abs(ov).max())
+
+
+def test_minv_symmetric_and_spd():
+    cfg, pos = case(n=600, seed=5)
+    with S.Sim(cfg, pos, precond="learned") as sim:
+        sim.set_weights(random_theta(2, scale=1.0))
+        r, c, v, d = sim.precond_matrix()
+    M = np.diag(d)
+    M[r, c] = v
+    assert np.array_equal(M, M.T)
+    assert np.linalg.eigvalsh(M)[0] > 0
+
+
+def test_loss_and_gradient_match_oracle():
+    cfg, pos = case(n=2000, seed=7)
+    th = random_theta(3)
+    b = np.random.default_rng(0).normal(size=(cfg["n"], 3))
+    with S.Sim(cfg, pos, tol=1e-12, precond="jacobi") as sim:
+        sim.set_weights(th)
+        sim.precond_config(round_act=False)
+        v, _ = sim.solve(b)
+        loss = sim.train_step(0.0)
+        g = sim.precond_grad().astype(np.float64)
+    s = oracle.build_system(cfg, pos, 0)
+    er = oracle.edge_r(cfg, pos, s, 0)
+    lo, go = oracle.mpnn_loss_grad(s, er, cfg["alpha"], th, b, v)
+    assert loss == pytest.approx(lo, rel=1e-4)
+    assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+
+
+def test_learned_solve_matches_dense_and_converges():
+    cfg, pos = case(n=3000, seed=9)
+    b = np.random.default_rng(2).normal(size=(cfg["n"], 3))
+    with S.Sim(cfg, pos, tol=1e-10, precond="learned") as sim:
+        sim.set_weights(random_theta(4))
+        v, st = sim.solve(b)
+    A = oracle.dense(oracle.build_system(cfg, pos, 0))
+    x = np.linalg.solve(A, b)
+    assert st["fallback"] == 0
+    assert np.all(np.linalg.norm(b - A @ v, axis=0) / np.linalg.norm(b, axis=0) <= 1e-10 * 1.001)
+    assert np.all(np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
+                  <= np.linalg.cond(A) * 1e-10)
+
+
+def test_forced_fallback_gives_the_same_answer():
+    cfg, pos = case(n=2000, seed=11)
+    b = np.random.default_rng(3).normal(size=(cfg["n"], 3))
+    with S.Sim(cfg, pos, tol=1e-10, precond="learned") as sim:
+        sim.precond_config(round_act=True, learned_maxit=1)
+        v, st = sim.solve(b)
+    with S.Sim(cfg, pos, tol=1e-10, precond="jacobi") as ref:
+        vj, _ = ref.solve(b)
+    assert st["fallback"] == 1
+    np.testing.assert_allclose(v, vj, rtol=0, atol=1e-8 * np.abs(vj).max())
+
+
+def test_learned_trajectory_matches_oracle():
+    """The preconditioner changes iteration counts, not the converged answer."""
+    cfg = inputs.small_case(seed=1)["params"]
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=1e-10, precond="learned") as sim:
+        sim.set_weights(precond.init_params(0))
+        sim.step(5)
+        pg, vg, _ = sim.state()
+    po, vo, _ = oracle.run(cfg, pos0, 5, tol=1e-10)
+    rel = np.linalg.norm(vg - vo, axis=0) / np.linalg.norm(vo, axis=0)
+    assert np.all(rel < 1e-8)
+
+
+def iterations(cfg, pos, precond_name, theta, steps=3):
+    its = []
+    with S.Sim(cfg, pos, tol=1e-8, precond=precond_name) as sim:
+        if theta is not None:
+            sim.set_weights(theta)
+        for _ in range(steps):
+            st = sim.step(1)
+            its.append(max(st["iters"]))
+            assert st["fallback"] == 0
+    return np.mean(its)
+
+
+def test_training_gain_over_jacobi():
+    """A short training run on the simulation's own systems lowers the loss,
+    and the trained preconditioner needs fewer CG iterations than Jacobi on
+    held-out boxes (other seeds and shear rates)."""
+    theta, losses = precond.train(160, n=8000, lr=3e-3, seed=0, episode=40)
+    assert np.mean(losses[-20:]) < 0.8 * np.mean(losses[:20])
+    for seed, kappa in ((9001, 0.02), (9002, 0.5)):
+        cfg = inputs.cube_params(8000, kappa, seed=seed)
+        pos = inputs.uniform_positions(8000, cfg["box"], seed)
+        jac = iterations(cfg, pos, "jacobi", None)
+        lrn = iterations(cfg, pos, "learned", theta)
+        assert lrn < 0.75 * jac, (seed, jac, lrn)
