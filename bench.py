@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-spmv", action="store_true")
+    ap.add_argument("--forms", default="plain,learned",
+                    help="comma list of CG forms to time: plain (Jacobi-PCG), learned")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1808_06381_amd", "weights",
+                                                      "precond_n1e5.bin"))
     return ap.parse_args()
 
 
@@ -84,6 +88,54 @@ def cpu_baseline(cfg, pos0, steps, tol):
                        f"{dt:.1f} s")
 
 
+def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
+    """Warm up, then time args.steps bench steps of the three boxes with one CG form."""
+    sims = []
+    for cfg, pos0 in zip(cfgs, pos0s):
+        sim = S.Sim(cfg, pos0, tol=args.tol, maxit=5000,
+                    spmv_fp32=1 if args.fp32_spmv else 0, stream=stream,
+                    precond="learned" if form == "learned" else "jacobi")
+        if form == "learned":
+            sim.set_weights(theta)
+        sims.append(sim)
+    print(f"# form {form}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+    for k in range(args.warmup):
+        for sim in sims:
+            sim.step(1)
+    for sim in sims:
+        sim.profile_read(reset=True)
+        sim.profile_enable(args.probe_every)
+    iters, fallbacks = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for sim in sims:
+            st = sim.step(1)
+            iters.append(max(st["iters"]))
+            fallbacks += st["fallback"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    for sim in sims:
+        for name, rec in sim.profile_read(reset=True).items():
+            acc = prof.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
+            for f in ("launches", "ms", "bytes"):
+                acc[f] += rec[f]
+        sim.close()
+    print(f"# form {form}: {args.steps} steps x {len(sims)} boxes in {elapsed:.3f} s; "
+          f"mean CG iterations {np.mean(iters):.1f}", file=sys.stderr, flush=True)
+    kernels = {}
+    for name, rec in prof.items():
+        if rec["launches"] == 0:
+            continue
+        ms = rec["ms"] / rec["launches"]
+        bpl = rec["bytes"] / rec["launches"]
+        kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3, bytes_per_launch=bpl,
+                             gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
+    value = args.steps * sum(c["n"] for c in cfgs) / elapsed
+    return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -107,58 +159,35 @@ def main():
     copy_ms = S.copy_probe(src, dst, reps=10, stream=stream)
     copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
     del src, dst
-    cfgs, sims, pos0s = [], [], []
+    cfgs, pos0s = [], []
     for k, shear in enumerate(SHEARS):
         cfg = inputs.single_box(shear_rate=shear, seed=1 + k, n=args.n, L=L)["params"]
-        pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
-        sim = S.Sim(cfg, pos0, tol=args.tol, maxit=5000,
-                    spmv_fp32=1 if args.fp32_spmv else 0, stream=stream)
         cfgs.append(cfg)
-        pos0s.append(pos0)
-        sims.append(sim)
-    print(f"# workload: {len(sims)} boxes N={args.n} L={L:.3g} shears={SHEARS} "
-          f"tol={args.tol} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    for k in range(args.warmup):
-        for sim in sims:
-            sim.step(1)
-    for sim in sims:
-        sim.profile_read(reset=True)
-        sim.profile_enable(args.probe_every)
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        for sim in sims:
-            st = sim.step(1)
-            iters.append(max(st["iters"]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = {}
-    for sim in sims:
-        for name, rec in sim.profile_read(reset=True).items():
-            acc = prof.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
-            for f in ("launches", "ms", "bytes"):
-                acc[f] += rec[f]
-        sim.profile_enable(0)
-    print(f"# timed {args.steps} steps x {len(sims)} boxes in {elapsed:.3f} s; "
-          f"mean CG iterations {np.mean(iters):.1f}", file=sys.stderr, flush=True)
-
-    particle_steps = args.steps * sum(c["n"] for c in cfgs)
-    value = particle_steps / elapsed
-    kernels = {}
-    for name, rec in prof.items():
-        if rec["launches"] == 0:
-            continue
-        ms = rec["ms"] / rec["launches"]
-        bpl = rec["bytes"] / rec["launches"]
-        kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3, bytes_per_launch=bpl,
-                             gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
+        pos0s.append(inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"]))
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    theta = None
+    if "learned" in forms:
+        if not os.path.exists(args.weights):
+            print(f"# no weights at {args.weights}: skipping the learned form", file=sys.stderr)
+            forms = [f for f in forms if f != "learned"]
+        else:
+            from paper_1808_06381_amd import precond
+            theta = precond.load(args.weights)
+    runs = {}
+    for form in forms:
+        runs[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np)
+    head = "learned" if "learned" in runs else forms[0]
+    hr = runs[head]
+    value = hr["value"]
+    elapsed = hr["elapsed"]
+    iters = hr["iters"]
+    kernels = hr["kernels"]
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
         kr = kernels[dom]
         wl_key = f"single_n{args.n}"
-        traffic = read_traffic(dom, wl_key)
+        traffic = read_traffic(dom, wl_key) if head == "plain" else None
         roofline = dict(bound="hbm", achieved=round(kr["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
                         frac=round(kr["gbs"] / PEAK_HBM_GBS, 4),
                         copy_probe_gbs=round(copy_gbs, 1),
@@ -170,8 +199,6 @@ def main():
         print("# timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfgs[1], pos0s[1], args.cpu_steps, args.tol)
 
-    for sim in sims:
-        sim.close()
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -190,7 +217,7 @@ def main():
                         f"{list(SHEARS)}, r_c=1, (1-r/r_c)^2 weight, soft potential eps=1kT, "
                         f"gamma0=0.1, kT=1, dt=0.01, FDT noise; one bench step = one time step "
                         f"of each box",
-            "precond": "jacobi",
+            "precond": head,
             "cg_tol": args.tol,
             "particles_per_step": sum(c["n"] for c in cfgs),
             "mean_cg_iters": round(float(np.mean(iters)), 2),
@@ -200,7 +227,12 @@ def main():
         "kernels": {k: {f: (round(v, 3) if isinstance(v, float) else v) for f, v in r.items()}
                     for k, r in kernels.items()},
         "cpu_baseline": cpu,
+        "forms": {f: dict(value=round(r["value"], 1), ms_per_step=round(r["elapsed"] / args.steps * 1e3, 4),
+                          mean_cg_iters=round(float(np.mean(r["iters"])), 2), fallbacks=r["fallbacks"])
+                  for f, r in runs.items()},
     }
+    if "learned" in runs and "plain" in runs:
+        out["learned_vs_plain"] = round(runs["learned"]["value"] / runs["plain"]["value"], 4)
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,15 @@ __device__ __forceinline__ void load_w(const MpPtrs& m, float* dst, int off, int
   for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = bf16_value(m.w16[off + k]);
 }
 
+// copy a 32 x 32 weight matrix W[k][q] into LDS transposed, dst[q][k]: lane k
+// then reads consecutive words for a fixed q (no bank conflicts)
+__device__ __forceinline__ void load_wt(const MpPtrs& m, float* dst, int off) {
+  for (int idx = threadIdx.x; idx < MP_H * MP_H; idx += blockDim.x) {
+    const int k = idx / MP_H, q = idx % MP_H;
+    dst[q * MP_H + k] = bf16_value(m.w16[off + idx]);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode(DevPtrs d, MpPtrs m) {
   __shared__ float sh[NODES][MP_H];
   load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
   load_w(m, b0, MP_OFF_B0, MP_H);
-  load_w(m, P, MP_OFF_L0 + MP_L_P, MP_H * MP_H);
+  load_wt(m, P, MP_OFF_L0 + MP_L_P);
   __syncthreads();
   const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
   for (int pass = 0; pass < PASSES; ++pass) {
@@ -116,7 +125,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode(DevPtrs d, MpPtrs m) {
     __syncthreads();
     float y = 0.0f;
 #pragma unroll 8
-    for (int q = 0; q < MP_H; ++q) y += P[k * MP_H + q] * sh[slot][q];
+    for (int q = 0; q < MP_H; ++q) y += P[q * MP_H + k] * sh[slot][q];
     m.y[i * MP_H + k] = y;
     __syncthreads();
   }
@@ -130,11 +139,11 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, in
   const int base = MP_OFF_L0 + l * MP_L_SIZE;
   load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
   load_w(m, c, base + MP_L_C, MP_H);
-  load_w(m, U, base + MP_L_U, MP_H * MP_H);
-  load_w(m, V, base + MP_L_V, MP_H * MP_H);
+  load_wt(m, U, base + MP_L_U);
+  load_wt(m, V, base + MP_L_V);
   load_w(m, dd, base + MP_L_D, MP_H);
   const bool next = l + 1 < MP_NL;
-  if (next) load_w(m, Pn, base + MP_L_SIZE + MP_L_P, MP_H * MP_H);
+  if (next) load_wt(m, Pn, base + MP_L_SIZE + MP_L_P);
   __syncthreads();
   const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
   const float* __restrict__ hin = m.h + (int64_t)l * m.rows * MP_H;
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, in
     __syncthreads();
     float a = dd[k];
 #pragma unroll 8
-    for (int q = 0; q < MP_H; ++q) a += U[k * MP_H + q] * sh[slot][q] + V[k * MP_H + q] * sm[slot][q];
+    for (int q = 0; q < MP_H; ++q) a += U[q * MP_H + k] * sh[slot][q] + V[q * MP_H + k] * sm[slot][q];
     const float hn = h + (a > 0.0f ? a : 0.0f);
     hout[i * MP_H + k] = hn;
     if (m.store_train) {
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, in
       __syncthreads();
       float yn = 0.0f;
 #pragma unroll 8
-      for (int q = 0; q < MP_H; ++q) yn += Pn[k * MP_H + q] * sh[slot][q];
+      for (int q = 0; q < MP_H; ++q) yn += Pn[q * MP_H + k] * sh[slot][q];
       m.y[((int64_t)(l + 1) * m.rows + i) * MP_H + k] = yn;
       __syncthreads();
     }
