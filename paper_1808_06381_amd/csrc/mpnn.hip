@@ -228,6 +228,322 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
 }
 
 // ---------------------------------------------------------------------------
+// forward with bf16 activations on the matrix cores.  A block owns MP_ROWS
+// consecutive rows; their CSR entries form one contiguous range that is
+// walked in chunks of MX_EC entries, four threads per entry (eight features
+// each), so every thread keeps one 32-byte gather in flight per chunk.  The
+// dense node products (32 x 64 and 32 x 32 per node) run as 16 x 16 x 16
+// bf16 MFMA tiles, FP32 accumulate: wave w owns rows 16w..16w+15.
+// Operand layout of v_mfma_f32_16x16x16_bf16: lane l supplies
+// A[l%16][4(l/16)+i] and B[4(l/16)+i][l%16], i < 4, and receives
+// D[4(l/16)+r][l%16] in accumulator register r.
+// ---------------------------------------------------------------------------
+namespace {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MX_EC = 64;                  // CSR entries per chunk
+constexpr int MX_AS = 2 * MP_H + 8;        // row stride (bf16) of the [h | m] tile
+constexpr int MX_HS = MP_H + 8;            // row stride (bf16) of an h tile
+constexpr int MX_FS = MP_H + 4;            // row stride (float) of message / h rows
+
+// B operand of a 32-output product whose weight W[n][q] (n output, q input,
+// row-major 32 x 32 bf16) starts at off: step s covers inputs 16s..16s+15,
+// tile nt covers outputs 16nt..16nt+15.
+__device__ __forceinline__ s16x4 mx_bw(const uint16_t* __restrict__ w16, int off, int s, int nt) {
+  const int lane = threadIdx.x & 63;
+  const int n = 16 * nt + (lane & 15), q = 16 * s + 4 * (lane >> 4);
+  s16x4 b;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b[i] = (short)w16[off + n * MP_H + q + i];
+  return b;
+}
+
+// A operand from an LDS bf16 tile (row stride `stride`), rows of wave w
+__device__ __forceinline__ s16x4 mx_a(const uint16_t* tile, int stride, int s) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = 16 * w + (lane & 15), q = 16 * s + 4 * (lane >> 4);
+  return *reinterpret_cast<const s16x4*>(tile + row * stride + q);
+}
+
+__device__ __forceinline__ f32x4 mx_mma(s16x4 a, s16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// y = P h for the 16 rows of wave w: P at w16[off], h the bf16 tile xh;
+// stored as FP32 rows of dst (tile origin i0)
+__device__ __forceinline__ void mx_store_py(const uint16_t* __restrict__ w16, int off,
+                                            const uint16_t* xh, float* __restrict__ dst,
+                                            int64_t i0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const s16x4 a = mx_a(xh, MX_HS, s);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[nt] = mx_mma(a, mx_bw(w16, off, s, nt), acc[nt]);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * (lane >> 4) + r;
+      dst[(i0 + row) * MP_H + 16 * nt + (lane & 15)] = acc[nt][r];
+    }
+}
+
+}  // namespace
+
+// features, h0 = relu(W0 x + b0) and y^0 = P_0 h0; four lanes per row
+__global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m) {
+  __shared__ float w0[MP_H * MP_FN], b0[MP_H];
+  __shared__ float xs[MP_ROWS][MP_FN];
+  __shared__ __align__(16) uint16_t xh[MP_ROWS * MX_HS];
+  const int t = threadIdx.x;
+  load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
+  load_w(m, b0, MP_OFF_B0, MP_H);
+  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  const int n = t >> 2, q = t & 3;
+  const int64_t i = i0 + n;
+  {
+    const double di = d.diag[i];
+    const double alpha = d.rep[d.blk_rep[i / ROWS_PER_BLOCK]].alpha;
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    double s = 0.0, a = 0.0;
+    for (int e = e0 + q; e < e1; e += 4) {
+      const int j = d.col[e];
+      const double v = -d.val[e];
+      const double what = v / sqrt(di * d.diag[j]);
+      s += v;
+      a += what;
+      m.ef[3 * (int64_t)e + 0] = m.er[e];
+      m.ef[3 * (int64_t)e + 1] = (float)(v / alpha);
+      m.ef[3 * (int64_t)e + 2] = (float)what;
+    }
+    s += __shfl_xor(s, 1, 64);
+    a += __shfl_xor(a, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    a += __shfl_xor(a, 2, 64);
+    if (q == 0) {
+      const float x0 = (float)(s / di), x1 = (float)a, x2 = (float)(e1 - e0) * 0.125f;
+      m.x[3 * i + 0] = x0;
+      m.x[3 * i + 1] = x1;
+      m.x[3 * i + 2] = x2;
+      xs[n][0] = bf16_round(x0);
+      xs[n][1] = bf16_round(x1);
+      xs[n][2] = bf16_round(x2);
+    }
+  }
+  __syncthreads();
+  float hv[8];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int k = 8 * q + kk;
+    float acc = b0[k];
+#pragma unroll
+    for (int f = 0; f < MP_FN; ++f) acc += w0[k * MP_FN + f] * xs[n][f];
+    hv[kk] = acc > 0.0f ? acc : 0.0f;
+    xh[n * MX_HS + k] = bf16_bits(hv[kk]);
+  }
+  float4* hp = reinterpret_cast<float4*>(m.h + i * MP_H + 8 * q);
+  hp[0] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+  hp[1] = make_float4(hv[4], hv[5], hv[6], hv[7]);
+  __syncthreads();
+  mx_store_py(m.w16, MP_OFF_L0 + MP_L_P, xh, m.y, i0);
+}
+
+// one message-passing layer l (bf16 activations): m, a (training), h^{l+1}, y^{l+1}
+__global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
+  __shared__ float Q[MP_H * MP_FE], c[MP_H], dd[MP_H];
+  __shared__ int rp[MP_ROWS + 1];
+  // msg holds one chunk's messages during the gather, then the tile's FP32 h
+  __shared__ __align__(16) float msg[MX_EC * MX_FS];
+  static_assert(MX_EC == MP_ROWS, "the h tile reuses the message buffer");
+  float* const hs = msg;
+  __shared__ __align__(16) uint16_t xa[MP_ROWS * MX_AS];
+  __shared__ __align__(16) uint16_t xh[MP_ROWS * MX_HS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int base = MP_OFF_L0 + l * MP_L_SIZE;
+  load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
+  load_w(m, c, base + MP_L_C, MP_H);
+  load_w(m, dd, base + MP_L_D, MP_H);
+  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
+  __syncthreads();
+  const int n = t >> 2, q = t & 3;
+  const int64_t rows = m.rows;
+  const float* __restrict__ y = m.y + (int64_t)l * rows * MP_H;
+  // messages: relu(y_j + Q e_ij + c) of every entry, summed per row in entry order
+  float acc[8];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0f;
+  const int E0 = rp[0], E1 = rp[MP_ROWS];
+  for (int cb = E0; cb < E1; cb += MX_EC) {
+    const int e = cb + n;
+    if (e < E1) {
+      const int64_t j = d.col[e];
+      const float4* yp = reinterpret_cast<const float4*>(y + j * MP_H + 8 * q);
+      const float4 y0 = yp[0], y1 = yp[1];
+      const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+      float ef[MP_FE];
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) ef[f] = bf16_round(m.ef[3 * (int64_t)e + f]);
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 8 * q + kk;
+        float s = yv[kk] + c[k];
+#pragma unroll
+        for (int f = 0; f < MP_FE; ++f) s += Q[k * MP_FE + f] * ef[f];
+        msg[n * MX_FS + k] = s > 0.0f ? s : 0.0f;
+      }
+    }
+    __syncthreads();
+    const int lo = max(rp[n], cb), hi = min(rp[n + 1], cb + MX_EC);
+    for (int e2 = lo; e2 < hi; ++e2) {
+      const float4* mp = reinterpret_cast<const float4*>(msg + (e2 - cb) * MX_FS + 8 * q);
+      const float4 m0 = mp[0], m1 = mp[1];
+      acc[0] += m0.x; acc[1] += m0.y; acc[2] += m0.z; acc[3] += m0.w;
+      acc[4] += m1.x; acc[5] += m1.y; acc[6] += m1.z; acc[7] += m1.w;
+    }
+    __syncthreads();
+  }
+  // stage [bf16(h) | bf16(m)] and the FP32 residual h of the tile
+  {
+    const int64_t i = i0 + n;
+    const float4* hp = reinterpret_cast<const float4*>(m.h + ((int64_t)l * rows + i) * MP_H + 8 * q);
+    const float4 h0 = hp[0], h1 = hp[1];
+    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 8 * q + kk;
+      acc[kk] *= MP_MSG;
+      hs[n * MX_FS + k] = hv[kk];
+      xa[n * MX_AS + k] = bf16_bits(hv[kk]);
+      xa[n * MX_AS + MP_H + k] = bf16_bits(acc[kk]);
+    }
+    if (m.store_train) {
+      float4* mo = reinterpret_cast<float4*>(m.m + ((int64_t)l * rows + i) * MP_H + 8 * q);
+      mo[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      mo[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    }
+  }
+  __syncthreads();
+  // a = d + U h + V m
+  f32x4 av[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const float bias = dd[16 * nt + (lane & 15)];
+    av[nt] = f32x4{bias, bias, bias, bias};
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const s16x4 a = mx_a(xa, MX_AS, s);
+    const int off = base + (s < 2 ? MP_L_U : MP_L_V - 2 * 16);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) av[nt] = mx_mma(a, mx_bw(m.w16, off, s, nt), av[nt]);
+  }
+  float* __restrict__ hout = m.h + (int64_t)(l + 1) * rows * MP_H;
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * (lane >> 4) + r, k = 16 * nt + (lane & 15);
+      const float a = av[nt][r];
+      const float hn = hs[row * MX_FS + k] + (a > 0.0f ? a : 0.0f);
+      hout[(i0 + row) * MP_H + k] = hn;
+      if (m.store_train) m.a[((int64_t)l * rows + i0 + row) * MP_H + k] = a;
+      xh[row * MX_HS + k] = bf16_bits(hn);
+    }
+  if (l + 1 < MP_NL) {
+    __syncthreads();
+    mx_store_py(m.w16, base + MP_L_SIZE + MP_L_P, xh, m.y + (int64_t)(l + 1) * rows * MP_H, i0);
+  }
+}
+
+// heads (bf16 activations): M^-1 values, four lanes per CSR entry
+__global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m) {
+  __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
+  __shared__ int rp[MP_ROWS + 1];
+  __shared__ int erow[MX_EC];
+  __shared__ double sbuf[MX_EC];
+  __shared__ double ssum[MP_ROWS];
+  __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
+  const int t = threadIdx.x;
+  load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
+  load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
+  load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
+  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
+  const int n = t >> 2, q = t & 3;
+  const float* __restrict__ hf = m.h + (int64_t)MP_NL * m.rows * MP_H;
+  {
+    const float4* hp = reinterpret_cast<const float4*>(hf + (i0 + n) * MP_H + 8 * q);
+    const float4 h0 = hp[0], h1 = hp[1];
+    const float v[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = bf16_round(v[kk]);
+  }
+  double sum_s = 0.0;  // row t's sum of S_ij (threads t < MP_ROWS)
+  __syncthreads();
+  const int E0 = rp[0], E1 = rp[MP_ROWS];
+  for (int cb = E0; cb < E1; cb += MX_EC) {
+    if (t < MP_ROWS) {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + MX_EC);
+      for (int e2 = lo; e2 < hi; ++e2) erow[e2 - cb] = t;
+    }
+    __syncthreads();
+    const int e = cb + n;
+    if (e < E1) {
+      const int r = erow[n];
+      const int64_t j = d.col[e];
+      const float4* hp = reinterpret_cast<const float4*>(hf + j * MP_H + 8 * q);
+      const float4 h0 = hp[0], h1 = hp[1];
+      const float hj[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+      float p = 0.0f;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 8 * q + kk;
+        p += hz[k] * (hi_s[r * MX_FS + k] * bf16_round(hj[kk]));
+      }
+      p += __shfl_xor(p, 1, 64);
+      p += __shfl_xor(p, 2, 64);
+      float tt = p;
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) tt += hze[f] * bf16_round(m.ef[3 * (int64_t)e + f]);
+      tt += hze[MP_FE];
+      if (q == 0) {
+        const double g = 2.0 * (double)sigmoidf_(tt);
+        const double sq = sqrt(d.diag[i0 + r] * d.diag[j]);
+        const double s = g * (-d.val[e] / sq);
+        sbuf[n] = s;
+        m.moff[e] = (float)(s / sq);
+        if (m.store_train) m.tg[e] = tt;
+      }
+    }
+    __syncthreads();
+    if (t < MP_ROWS) {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + MX_EC);
+      for (int e2 = lo; e2 < hi; ++e2) sum_s += sbuf[e2 - cb];
+    }
+  }
+  if (t < MP_ROWS) ssum[t] = sum_s;
+  __syncthreads();
+  float p = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) p += hv[8 * q + kk] * hi_s[n * MX_FS + 8 * q + kk];
+  p += __shfl_xor(p, 1, 64);
+  p += __shfl_xor(p, 2, 64);
+  if (q == 0) {
+    const int64_t i = i0 + n;
+    const float tau = p + hv[MP_H];
+    m.tau[i] = tau;
+    const double lam = ssum[n] + (double)softplusf_(tau) + MP_EPS_LAM;
+    m.mdiag[i] = lam / d.diag[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // loss: zb = M^-1 b - x*, G = 2 A zb, partials (zb.A zb, x*.A x*)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mp_resid(DevPtrs d, MpPtrs m) {
@@ -620,6 +936,13 @@ static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t)
 
 hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
   const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
+  if (m.round_act) {
+    hipLaunchKernelGGL(k_mp_encode_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+    for (int l = 0; l < MP_NL; ++l)
+      hipLaunchKernelGGL(k_mp_layer_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
+    hipLaunchKernelGGL(k_mp_heads_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_mp_features, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m);
   hipLaunchKernelGGL(k_mp_encode, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
   for (int l = 0; l < MP_NL; ++l)
