@@ -7,6 +7,13 @@ one per shear rate 0.01, 0.1 and 0.5, Jacobi-PCG to a true relative residual
 of 1e-8 per component, FP64.  One bench step advances each of the three
 boxes by one time step (3 x 10^6 particle-steps); inputs are resident in HBM.
 
+Each form (plain Jacobi-PCG, learned-PCG) is timed with whole steps
+replayed as HIP graphs; every --probe-every-th step runs eagerly with its CG
+kernels bracketed by HIP events, which gives the per-kernel durations.  A
+second workload, 64 replicas of uneven size in one handle (N log-uniform in
+[1e4, 2e5], shear log-uniform in [0.005, 1]), is timed the same way and
+reported under "batch".
+
 Prints one JSON line: particle-steps/s over the timed steps, the roofline of
 the dominant CG kernel (algorithmic bytes per launch over its event-timed
 mean duration, sampled inside the timed region), and the oracle's own
@@ -36,7 +43,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--probe-every", type=int, default=4)
+    ap.add_argument("--probe-every", type=int, default=8,
+                    help="every k-th step runs eagerly with every k-th CG iteration timed")
+    ap.add_argument("--no-graph", action="store_true", help="eager steps only")
+    ap.add_argument("--batch", type=int, default=64, help="replicas of the batch workload (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-spmv", action="store_true")
@@ -88,8 +99,10 @@ def cpu_baseline(cfg, pos0, steps, tol):
                        f"{dt:.1f} s")
 
 
-def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
-    """Warm up, then time args.steps bench steps of the three boxes with one CG form."""
+def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label=""):
+    """Warm up, then time `steps` bench steps of the systems (one handle per
+    entry of cfgs; an entry may be a list of replicas) with one CG form."""
+    steps = args.steps if steps is None else steps
     sims = []
     for cfg, pos0 in zip(cfgs, pos0s):
         sim = S.Sim(cfg, pos0, tol=args.tol, maxit=5000,
@@ -97,8 +110,10 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
                     precond="learned" if form == "learned" else "jacobi")
         if form == "learned":
             sim.set_weights(theta)
+        if not args.no_graph:
+            sim.graph_mode(True)
         sims.append(sim)
-    print(f"# form {form}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+    print(f"# {label}form {form}: warmup {args.warmup}, timed {steps}", file=sys.stderr, flush=True)
     for k in range(args.warmup):
         for sim in sims:
             sim.step(1)
@@ -108,7 +123,7 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
     iters, fallbacks = [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         for sim in sims:
             st = sim.step(1)
             iters.append(max(st["iters"]))
@@ -116,14 +131,17 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {}
+    graphs = dict(captures=0, replays=0)
     for sim in sims:
+        for k, v in sim.graph_info().items():
+            graphs[k] += v
         for name, rec in sim.profile_read(reset=True).items():
             acc = prof.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
             for f in ("launches", "ms", "bytes"):
                 acc[f] += rec[f]
         sim.close()
-    print(f"# form {form}: {args.steps} steps x {len(sims)} boxes in {elapsed:.3f} s; "
-          f"mean CG iterations {np.mean(iters):.1f}", file=sys.stderr, flush=True)
+    print(f"# {label}form {form}: {steps} steps x {len(sims)} handles in {elapsed:.3f} s; "
+          f"mean CG iterations {np.mean(iters):.1f}; graphs {graphs}", file=sys.stderr, flush=True)
     kernels = {}
     for name, rec in prof.items():
         if rec["launches"] == 0:
@@ -132,8 +150,10 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np):
         bpl = rec["bytes"] / rec["launches"]
         kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3, bytes_per_launch=bpl,
                              gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
-    value = args.steps * sum(c["n"] for c in cfgs) / elapsed
-    return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks)
+    particles = sum(sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs)
+    value = steps * particles / elapsed
+    return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks,
+                graphs=graphs, particles=particles, steps=steps)
 
 
 def main():
@@ -228,11 +248,34 @@ def main():
                     for k, r in kernels.items()},
         "cpu_baseline": cpu,
         "forms": {f: dict(value=round(r["value"], 1), ms_per_step=round(r["elapsed"] / args.steps * 1e3, 4),
-                          mean_cg_iters=round(float(np.mean(r["iters"])), 2), fallbacks=r["fallbacks"])
+                          mean_cg_iters=round(float(np.mean(r["iters"])), 2), fallbacks=r["fallbacks"],
+                          graphs=r["graphs"])
                   for f, r in runs.items()},
+        "graph_steps": not args.no_graph,
     }
     if "learned" in runs and "plain" in runs:
         out["learned_vs_plain"] = round(runs["learned"]["value"] / runs["plain"]["value"], 4)
+    if args.batch > 0:
+        bcfgs = inputs.batch_replicas(count=args.batch, seed=7)
+        bpos = np.concatenate([inputs.uniform_positions(c["n"], c["box"], c["seed"]) for c in bcfgs])
+        bruns = {form: time_form(args, S, [bcfgs], [bpos], form, theta, stream, torch, np,
+                                 steps=args.batch_steps, label="batch ")
+                 for form in forms}
+        out["batch"] = {
+            "workload": f"{args.batch} replicas in one handle, N log-uniform in [1e4, 2e5] "
+                        f"(sum {bruns[forms[0]]['particles']}), density 1, shear log-uniform in "
+                        f"[0.005, 1], same physics; one bench step = one time step of every "
+                        f"replica",
+            "steps": args.batch_steps,
+            "forms": {f: dict(value=round(r["value"], 1),
+                              ms_per_step=round(r["elapsed"] / r["steps"] * 1e3, 4),
+                              mean_cg_iters=round(float(np.mean(r["iters"])), 2),
+                              fallbacks=r["fallbacks"], graphs=r["graphs"])
+                      for f, r in bruns.items()},
+        }
+        if "learned" in bruns and "plain" in bruns:
+            out["batch"]["learned_vs_plain"] = round(bruns["learned"]["value"] /
+                                                     bruns["plain"]["value"], 4)
     print(json.dumps(out), flush=True)
 
 

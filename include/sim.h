@@ -268,6 +268,42 @@ int sim_profile_read(sim_t* sim, sim_kernel_prof* out, int32_t cap, int32_t* cou
 int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* hip_stream,
                    double* ms_avg);
 
+/* Whole steps as HIP graphs (batched replicas, many short launches).
+ * on != 0: from the second step on, sim_step records one graph per step
+ * configuration -- sort, neighbour list, pair terms, the learned forward
+ * pass, CG start, the first K CG iterations (K >= the previous solve's
+ * count + 1, kept while within 8 of it) and a true-residual check, then the
+ * position update and velocity export, which run on the device only if
+ * every component of every replica has converged -- and replays it with
+ * one host synchronisation per step.  Solves that need more iterations
+ * continue with host-queued chunks, so graph and eager steps give identical
+ * bits.  With no stream set (NULL), the handle creates a stream of its own
+ * that synchronises with the default stream.  With the timing probe on
+ * (sim_profile_enable), every sample_every-th step runs eagerly so that its
+ * kernels can be timed.  on = 0 releases the graphs.
+ * *captures / *replays (optional) receive the counts so far.              */
+int sim_graph_mode(sim_t* sim, int32_t on);
+int sim_graph_info(sim_t* sim, int64_t* captures, int64_t* replays);
+
+/* Tuning of the CSR products (rows of ~5 entries): lanes per row group for
+ * w = A u and for the learned u = M^-1 r.  Changes only the summation order
+ * of each row (results stay within rounding of each other; a fixed choice
+ * is bitwise reproducible).  Default 4 and 4.                             */
+typedef struct sim_tuning {
+  int32_t spmv_lanes;    /* 1, 2, 4 or 8 */
+  int32_t apply_lanes;   /* 1, 2, 4 or 8 */
+  float spmv_us[4];      /* sim_autotune: mean duration per variant 1, 2, 4, 8 */
+  float apply_us[4];     /* (0 where not measured) */
+} sim_tuning;
+/* Time every variant `reps` times on the system at the current positions
+ * (built for the purpose; the state is unchanged) and keep the fastest.
+ * The choice depends on timing, so runs that must be bitwise reproducible
+ * should fix it with sim_set_tuning.  out (optional) receives the choice
+ * and the timings.                                                        */
+int sim_autotune(sim_t* sim, int32_t reps, sim_tuning* out);
+/* Use the given lanes (timings ignored); SIM_EINVAL for other values.     */
+int sim_set_tuning(sim_t* sim, const sim_tuning* tuning);
+
 /* Free the handle and all its device memory. NULL is a no-op.             */
 void sim_destroy(sim_t* sim);
 

@@ -11,7 +11,8 @@
 // Per iteration three launches, none with a cache write-back fence:
 //   k_cg_vec   every vector update, element-parallel (fully coalesced), and
 //              the partial sums of (r, u) and (r, r) per tile;
-//   k_cg_spmv  w = A u with four lanes per CSR row, so the neighbours of a
+//   k_cg_spmv  w = A u with a group of 1, 2, 4 or 8 lanes per CSR row (4
+//              unless the autotuner picked another), so the neighbours of a
 //              row -- contiguous runs of the cell-sorted order -- are fetched
 //              by adjacent lanes; partial sums of (w, u);
 //   k_cg_finish one block per replica: the tile partials in a fixed order,
@@ -22,8 +23,42 @@
 
 #include <hip/hip_ext.h>
 
-#define SPMV_LANES 4
 #define VEC_ELEMS (3 * ROWS_PER_BLOCK)  // elements (row, component) per tile
+
+// sum over the LANES lanes of a row's group (butterfly: every lane ends with
+// the same bits, since each step adds the same two operands)
+template <int LANES>
+__device__ __forceinline__ void lane_group_sum(double (&a)[3]) {
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] += __shfl_xor(a[k], o, 64);
+}
+
+// Components per row are finished by lanes 0..2 of the row's group; with
+// LANES < 3 a lane takes TURNS turns (component t * LANES + lane in turn t).
+// Register arrays are only indexed with compile-time indices here.
+template <int LANES>
+constexpr int TURNS = LANES >= 3 ? 1 : (3 + LANES - 1) / LANES;
+
+__device__ __forceinline__ double pick3(const double (&a)[3], int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+__device__ __forceinline__ bool on_k(const bool (&on)[3], int k) {
+  return k == 0 ? on[0] : (k == 1 ? on[1] : on[2]);
+}
+// v[k] = the turn sum that belongs to component k (0 where this lane has none)
+template <int LANES>
+__device__ __forceinline__ void turns_to_components(const double (&vt)[TURNS<LANES>], int lane,
+                                                    double (&v)[3]) {
+#pragma unroll
+  for (int t = 0; t < TURNS<LANES>; ++t) {
+    const int k = t * LANES + lane;
+    v[0] = k == 0 ? vt[t] : v[0];
+    v[1] = k == 1 ? vt[t] : v[1];
+    v[2] = k == 2 ? vt[t] : v[2];
+  }
+}
 
 // tile partial sums: [gamma0..2, delta0..2, rr0..2]; `first`..`first+n` written
 template <int N>
@@ -60,7 +95,10 @@ __global__ void k_cg_reset(DevPtrs d, double tol_override) {
     c.restarts = 0;
     c.breakdown = 0;
   }
-  if (threadIdx.x == 0) d.ctrl->n_notdone = 3 * d.nrep;
+  if (threadIdx.x == 0) {
+    d.ctrl->n_notdone = 3 * d.nrep;
+    d.ctrl->breakdown = 0;
+  }
 }
 
 // Element-parallel vector work of one tile (3 * 1024 consecutive doubles of
@@ -130,9 +168,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   write_partials<3>(d, tile, 6, rr);
 }
 
-// Learned preconditioner: u = M^-1 r with M^-1 in A's pattern (four lanes
-// per row, as the CSR product), partial (r, u).  Same component selection
-// as k_cg_vec's mode.
+// Learned preconditioner: u = M^-1 r with M^-1 in A's pattern (a group of
+// LANES lanes per row, as the CSR product), partial (r, u).  Same component
+// selection as k_cg_vec's mode.
+template <int LANES>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -143,36 +182,39 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode)
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
-  const int lane = threadIdx.x & (SPMV_LANES - 1);
-  const int grp = threadIdx.x / SPMV_LANES;
-  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
+  const int lane = threadIdx.x & (LANES - 1);
+  const int cap = (int)d.nnz_cap;
+  const int grp = threadIdx.x / LANES;
+  constexpr int GROUPS = BLOCK_THREADS / LANES;
   const double* __restrict__ r = d.r;
   double v[3] = {0, 0, 0};
+  double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
     const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
+    // clamped: after an overflowing fill the row pointers may pass the
+    // capacity (the host discards that solve; the reads stay in bounds)
+    const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int e = e0 + lane; e < e1; e += LANES) {
       const int64_t j = d.col[e];
-      const double a = (double)d.moff[e];
-      a0 += a * r[3 * j];
-      a1 += a * r[3 * j + 1];
-      a2 += a * r[3 * j + 2];
+      const double m = (double)d.moff[e];
+      a[0] += m * r[3 * j];
+      a[1] += m * r[3 * j + 1];
+      a[2] += m * r[3 * j + 2];
     }
+    lane_group_sum<LANES>(a);
+    // lane k finishes component k (one turn); narrower groups take turns
 #pragma unroll
-    for (int o = 1; o < SPMV_LANES; o <<= 1) {
-      a0 += __shfl_xor(a0, o, 64);
-      a1 += __shfl_xor(a1, o, 64);
-      a2 += __shfl_xor(a2, o, 64);
-    }
-    if (lane < 3 && on[lane]) {
-      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
-      const int64_t e = 3 * i + lane;
-      const double uk = d.mdiag[i] * r[e] + acc;
+    for (int t = 0; t < TURNS<LANES>; ++t) {
+      const int k = t * LANES + lane;
+      if (k >= 3 || !on_k(on, k)) continue;
+      const int64_t e = 3 * i + k;
+      const double uk = d.mdiag[i] * r[e] + pick3(a, k);
       d.u[e] = uk;
-      v[lane] += r[e] * uk;
+      vt[t] += r[e] * uk;
     }
   }
+  turns_to_components<LANES>(vt, lane, v);
   write_partials<3>(d, tile, 0, v);
 }
 
@@ -194,6 +236,7 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
       } else if (!(del > 0.0)) {
         c.state[k] = 2;
         c.breakdown = 1;
+        atomicOr(&d.ctrl->breakdown, 1);
         ++finished;
       } else {
         c.state[k] = 0;
@@ -212,6 +255,7 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
         if (!(den > 0.0)) {
           c.state[k] = 2;
           c.breakdown = 1;
+        atomicOr(&d.ctrl->breakdown, 1);
           ++finished;
         } else {
           c.beta[k] = beta;
@@ -272,11 +316,12 @@ __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, 
   }
 }
 
-// CSR product with SPMV_LANES lanes per row over the tile's 1024 rows.
+// CSR product with LANES lanes per row over the tile's 1024 rows.
 //   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
 //   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
-// Lane k < 3 of a row's group finishes component k (coalesced stores).
-template <bool FP32>
+// Lane k of a row's group finishes component k (coalesced stores); with
+// fewer than three lanes, lane l takes components l, l + LANES, ...
+template <bool FP32, int LANES>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -295,41 +340,44 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
     for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
   }
   const double* __restrict__ src = mode == 0 ? d.u : d.x;
-  const int lane = threadIdx.x & (SPMV_LANES - 1);
-  const int grp = threadIdx.x / SPMV_LANES;
-  constexpr int GROUPS = BLOCK_THREADS / SPMV_LANES;
+  const int lane = threadIdx.x & (LANES - 1);
+  const int cap = (int)d.nnz_cap;
+  const int grp = threadIdx.x / LANES;
+  constexpr int GROUPS = BLOCK_THREADS / LANES;
   double v[3] = {0, 0, 0};
+  double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
     const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int e = e0 + lane; e < e1; e += SPMV_LANES) {
+    // clamped: after an overflowing fill the row pointers may pass the
+    // capacity (the host discards that solve; the reads stay in bounds)
+    const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int e = e0 + lane; e < e1; e += LANES) {
       const int64_t j = d.col[e];
-      const double a = FP32 ? (double)d.valf[e] : d.val[e];
-      a0 += a * src[3 * j];
-      a1 += a * src[3 * j + 1];
-      a2 += a * src[3 * j + 2];
+      const double m = FP32 ? (double)d.valf[e] : d.val[e];
+      a[0] += m * src[3 * j];
+      a[1] += m * src[3 * j + 1];
+      a[2] += m * src[3 * j + 2];
     }
+    lane_group_sum<LANES>(a);
+    // lane k finishes component k (one turn); narrower groups take turns
 #pragma unroll
-    for (int o = 1; o < SPMV_LANES; o <<= 1) {
-      a0 += __shfl_xor(a0, o, 64);
-      a1 += __shfl_xor(a1, o, 64);
-      a2 += __shfl_xor(a2, o, 64);
-    }
-    if (lane < 3 && on[lane]) {
-      const double acc = lane == 0 ? a0 : (lane == 1 ? a1 : a2);
-      const int64_t e = 3 * i + lane;
-      const double own = d.diag[i] * src[e] + acc;
+    for (int t = 0; t < TURNS<LANES>; ++t) {
+      const int k = t * LANES + lane;
+      if (k >= 3 || !on_k(on, k)) continue;
+      const int64_t e = 3 * i + k;
+      const double own = d.diag[i] * src[e] + pick3(a, k);
       if (mode == 0) {
         d.w[e] = own;
-        v[lane] += own * src[e];
+        vt[t] += own * src[e];
       } else {
         const double rk = d.b[e] - own;
         d.r[e] = rk;
-        v[lane] += rk * rk;
+        vt[t] += rk * rk;
       }
     }
   }
+  turns_to_components<LANES>(vt, lane, v);
   write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
 }
 
@@ -349,6 +397,16 @@ __global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// With events, the extended launch records the kernel's own start and end;
+// without, a plain launch (the form that stream capture records).
+#define LAUNCH_EV(K, G, B, S, E0, E1, ...)                              \
+  do {                                                                  \
+    if ((E0) || (E1))                                                   \
+      hipExtLaunchKernelGGL(K, G, B, 0, S, E0, E1, 0, __VA_ARGS__);     \
+    else                                                                \
+      hipLaunchKernelGGL(K, G, B, 0, S, __VA_ARGS__);                   \
+  } while (0)
+
 hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(256), 0, s, d, tol_override);
   return hipGetLastError();
@@ -357,7 +415,7 @@ hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s)
 // ev0/ev1 (optional) take the kernel's own start and end timestamps
 hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1) {
-  hipExtLaunchKernelGGL(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, ev0, ev1, 0,
+  LAUNCH_EV(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1,
                         d, mode);
   return hipGetLastError();
 }
@@ -365,17 +423,32 @@ hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t e
 hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
-  if (d.spmv_fp32 && mode == 0)
-    hipExtLaunchKernelGGL(k_cg_spmv<true>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
-  else
-    hipExtLaunchKernelGGL(k_cg_spmv<false>, g, b, 0, s, ev0, ev1, 0, d, mode, start_mode);
+  const bool f32 = d.spmv_fp32 && mode == 0;
+  switch (d.spmv_lanes * 2 + (f32 ? 1 : 0)) {
+#define SPMV_CASE(L)                                                                         \
+    case 2 * L:                                                                             \
+      LAUNCH_EV((k_cg_spmv<false, L>), g, b, s, ev0, ev1, d, mode, start_mode); \
+      break;                                                                                \
+    case 2 * L + 1:                                                                         \
+      LAUNCH_EV((k_cg_spmv<true, L>), g, b, s, ev0, ev1, d, mode, start_mode);  \
+      break;
+    SPMV_CASE(1) SPMV_CASE(2) SPMV_CASE(4) SPMV_CASE(8)
+#undef SPMV_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
-  hipExtLaunchKernelGGL(k_cg_apply, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, ev0, ev1,
-                        0, d, mode);
+  const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
+  switch (d.apply_lanes) {
+    case 1: LAUNCH_EV(k_cg_apply<1>, g, b, s, ev0, ev1, d, mode); break;
+    case 2: LAUNCH_EV(k_cg_apply<2>, g, b, s, ev0, ev1, d, mode); break;
+    case 4: LAUNCH_EV(k_cg_apply<4>, g, b, s, ev0, ev1, d, mode); break;
+    case 8: LAUNCH_EV(k_cg_apply<8>, g, b, s, ev0, ev1, d, mode); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

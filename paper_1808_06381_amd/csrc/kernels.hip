@@ -169,9 +169,10 @@ __global__ void k_cell_sort(DevPtrs d) {
 // ===========================================================================
 // a2-a5: neighbour search, pair terms, assembly of A and b
 // ===========================================================================
-__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d, int64_t step) {
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d) {
   const int blk = blockIdx.x;
   const RepDev& R = d.rep[d.blk_rep[blk]];
+  const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
   int mx = 0;
   for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
@@ -210,9 +211,10 @@ __device__ __forceinline__ double force_coef(const RepDev& R, double r2, double 
 
 // Neighbour list: the same candidate order as k_nbr_count; each passing
 // candidate's sorted row index goes to col[rowptr[i] + slot].
-__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d, int64_t step) {
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
   const int blk = blockIdx.x;
   const RepDev& R = d.rep[d.blk_rep[blk]];
+  const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
   for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
     const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
@@ -240,10 +242,11 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d, int64_t s
 // (Eq. 6b), boundary velocity term of Eq. 8, thermal force.
 #define PAIR_LANES 4
 #define PAIR_THREADS 256  // fewer threads per block: the pair noise needs ~130 registers
-__global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d, int64_t step) {
+__global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
   const int blk = blockIdx.x;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   if (d.ctrl->overflow) return;
+  const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
   const double drag_unit = R.alpha * (R.shear * R.L[1]);
   const int lane = threadIdx.x & (PAIR_LANES - 1);
@@ -329,16 +332,19 @@ __global__ void k_ctrl_zero(Ctrl* c) {
     c->numeric = 0;
     c->max_row = 0;
     c->nnz = 0;
+    c->breakdown = 0;
   }
 }
 
 // ===========================================================================
 // a7: position update with Lees-Edwards re-entry
 // ===========================================================================
-__global__ __launch_bounds__(BLOCK_THREADS) void k_update(DevPtrs d, int64_t step_after) {
+// cond = 1 (graph replay): only if the solve finished (ctrl_commit_ok)
+__global__ __launch_bounds__(BLOCK_THREADS) void k_update(DevPtrs d, int cond) {
+  if (cond && !ctrl_commit_ok(d.ctrl)) return;
   const int blk = blockIdx.x;
   const RepDev& R = d.rep[d.blk_rep[blk]];
-  const double delta = le_offset(R, step_after);
+  const double delta = le_offset(R, *d.step_d + 1);
   for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
     const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
     if (i - R.row_off >= R.n) continue;
@@ -361,7 +367,9 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_update(DevPtrs d, int64_t ste
 }
 
 // velocities of the step in original order: vel_orig[3*(off + id) + k]
-__global__ __launch_bounds__(BLOCK_THREADS) void k_save_vel(DevPtrs d, const int64_t* __restrict__ id_off) {
+__global__ __launch_bounds__(BLOCK_THREADS) void k_save_vel(DevPtrs d, const int64_t* __restrict__ id_off,
+                                                            int cond) {
+  if (cond && !(ctrl_commit_ok(d.ctrl) && d.ctrl->numeric == 0)) return;
   const int blk = blockIdx.x;
   const int rid = d.blk_rep[blk];
   const RepDev& R = d.rep[rid];
@@ -371,6 +379,13 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_save_vel(DevPtrs d, const int
     const int64_t g = id_off[rid] + (int64_t)d.pos[i].w;
     for (int k = 0; k < 3; ++k) d.vel_orig[3 * g + k] = d.x[3 * i + k];
   }
+}
+
+// n -> n + 1 on the device (cond = 1: only for a committed step)
+__global__ void k_step_commit(DevPtrs d, int cond) {
+  if (threadIdx.x != 0) return;
+  if (cond && !(ctrl_commit_ok(d.ctrl) && d.ctrl->numeric == 0)) return;
+  *d.step_d += 1;
 }
 
 // ===========================================================================
@@ -499,28 +514,32 @@ hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_sort, dim3(nb_of(d.ncell_entries, 256)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
-hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_count, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step);
+hipError_t launch_nbr_count(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_count, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
   return hipGetLastError();
 }
-hipError_t launch_nbr_list(const DevPtrs& d, int64_t step, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_list, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step);
+hipError_t launch_nbr_list(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_list, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
   return hipGetLastError();
 }
-hipError_t launch_pair_terms(const DevPtrs& d, int64_t step, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_terms, dim3(d.nblk), dim3(PAIR_THREADS), 0, s, d, step);
+hipError_t launch_pair_terms(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_terms, dim3(d.nblk), dim3(PAIR_THREADS), 0, s, d);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_zero, dim3(1), dim3(64), 0, s, d.ctrl);
   return hipGetLastError();
 }
-hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, step_after);
+hipError_t launch_update(const DevPtrs& d, int cond, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, cond);
   return hipGetLastError();
 }
-hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, hipStream_t s) {
-  hipLaunchKernelGGL(k_save_vel, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, id_off);
+hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, int cond, hipStream_t s) {
+  hipLaunchKernelGGL(k_save_vel, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, id_off, cond);
+  return hipGetLastError();
+}
+hipError_t launch_step_commit(const DevPtrs& d, int cond, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_commit, dim3(1), dim3(64), 0, s, d, cond);
   return hipGetLastError();
 }
 hipError_t launch_permute(const DevPtrs& d, const int64_t* id_off, int mode, const double* in,

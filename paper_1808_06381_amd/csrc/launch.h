@@ -11,11 +11,12 @@ hipError_t launch_cell_rows(const DevPtrs& d, const int32_t* scan, hipStream_t s
 hipError_t launch_scatter(const DevPtrs& d, hipStream_t s);
 hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s);
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s);
-hipError_t launch_nbr_count(const DevPtrs& d, int64_t step, hipStream_t s);
-hipError_t launch_nbr_list(const DevPtrs& d, int64_t step, hipStream_t s);
-hipError_t launch_pair_terms(const DevPtrs& d, int64_t step, hipStream_t s);
-hipError_t launch_update(const DevPtrs& d, int64_t step_after, hipStream_t s);
-hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, hipStream_t s);
+hipError_t launch_nbr_count(const DevPtrs& d, hipStream_t s);
+hipError_t launch_nbr_list(const DevPtrs& d, hipStream_t s);
+hipError_t launch_pair_terms(const DevPtrs& d, hipStream_t s);
+hipError_t launch_update(const DevPtrs& d, int cond, hipStream_t s);
+hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, int cond, hipStream_t s);
+hipError_t launch_step_commit(const DevPtrs& d, int cond, hipStream_t s);
 hipError_t launch_permute(const DevPtrs& d, const int64_t* id_off, int mode, const double* in,
                           double* out, hipStream_t s);
 hipError_t launch_export_pairs(const DevPtrs& d, int64_t* out, int64_t cap,

@@ -84,6 +84,7 @@ __device__ __forceinline__ void load_wt(const MpPtrs& m, float* dst, int off) {
 
 // node and edge features (one thread per row)
 __global__ __launch_bounds__(256) void k_mp_features(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.rows) return;
   const double di = d.diag[i];
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(256) void k_mp_features(DevPtrs d, MpPtrs m) {
 
 // h0 = relu(W0 x + b0) and y^0 = P_0 h0
 __global__ __launch_bounds__(MP_THREADS) void k_mp_encode(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float w0[MP_H * MP_FN], b0[MP_H], P[MP_H * MP_H];
   __shared__ float sh[NODES][MP_H];
   load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
@@ -133,6 +135,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode(DevPtrs d, MpPtrs m) {
 
 // one message-passing layer l: m, a (stored for training), h^{l+1}, y^{l+1}
 __global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, int l) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float Q[MP_H * MP_FE], c[MP_H], U[MP_H * MP_H], V[MP_H * MP_H], dd[MP_H],
       Pn[MP_H * MP_H];
   __shared__ float sh[NODES][MP_H], sm[NODES][MP_H];
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer(DevPtrs d, MpPtrs m, in
 
 // heads: M^-1 diagonal and off-diagonal values, head pre-activations
 __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
   load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
@@ -297,6 +301,7 @@ __device__ __forceinline__ void mx_store_py(const uint16_t* __restrict__ w16, in
 
 // features, h0 = relu(W0 x + b0) and y^0 = P_0 h0; four lanes per row
 __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float w0[MP_H * MP_FN], b0[MP_H];
   __shared__ float xs[MP_ROWS][MP_FN];
   __shared__ __align__(16) uint16_t xh[MP_ROWS * MX_HS];
@@ -355,6 +360,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
 
 // one message-passing layer l (bf16 activations): m, a (training), h^{l+1}, y^{l+1}
 __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float Q[MP_H * MP_FE], c[MP_H], dd[MP_H];
   __shared__ int rp[MP_ROWS + 1];
   // msg holds one chunk's messages during the gather, then the tile's FP32 h
@@ -463,6 +469,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
 
 // heads (bf16 activations): M^-1 values, four lanes per CSR entry
 __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
   __shared__ int erow[MX_EC];
@@ -547,6 +554,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
 // loss: zb = M^-1 b - x*, G = 2 A zb, partials (zb.A zb, x*.A x*)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mp_resid(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.rows) return;
   const double md = m.mdiag[i];
@@ -562,6 +570,7 @@ __global__ __launch_bounds__(256) void k_mp_resid(DevPtrs d, MpPtrs m) {
 }
 
 __global__ __launch_bounds__(256) void k_mp_aprod(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ double lds[4][2];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double num = 0.0, den = 0.0;
@@ -664,6 +673,7 @@ __device__ __forceinline__ void slot_reduce_matrix(const float (&acc)[MP_H], flo
 
 // heads: dL/dh^3 (into dh) and the head parameters v, v0, z, ze, z0
 __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_bwd(DevPtrs d, MpPtrs m) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ float red[NODES * MP_H * MP_H];
   load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
@@ -779,6 +789,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_a(DevPtrs d, MpPtrs
 // layer l backward, part B (per node j, pulling from its neighbours i):
 // dy_j = 1/8 sum_i dm_i [y_j + Q e_ij + c > 0]; dQ, dc, dP; dh_in_j += P^T dy_j
 __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_b(DevPtrs d, MpPtrs m, int l) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float P[MP_H * MP_H], Q[MP_H * MP_FE], c[MP_H];
   __shared__ float sdy[NODES][MP_H];
   __shared__ float red[NODES * MP_H * MP_H];

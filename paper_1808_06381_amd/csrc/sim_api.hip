@@ -80,6 +80,20 @@ struct sim_t {
   int32_t mp_adam_t = 0;
   int32_t learned_maxit = 0;  // 0: cg_maxit
   bool system_valid = false; // A, b, x of a successful solve are in place
+  // whole steps replayed as HIP graphs (sim_graph_mode)
+  struct StepGraph {
+    hipGraphExec_t exec;
+    DevPtrs d;   // device state the graph was captured from
+    MpPtrs m;
+    int K;       // CG iterations recorded before the check round
+    bool learned;
+  };
+  int32_t graph_mode = 0;
+  hipStream_t own_stream = nullptr;  // created when graphs need a capturable stream
+  std::vector<StepGraph> graphs;
+  int64_t graph_captures = 0, graph_replays = 0;
+  int32_t graph_K = 0;
+  sim_tuning tune{};
 };
 
 static const int kProfKernels = 3;
@@ -88,6 +102,11 @@ static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_ap
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+static void drop_graphs(sim_t* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+  s->graphs.clear();
+}
+
 static int dalloc(sim_t* s, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
@@ -181,6 +200,7 @@ static double host_le_offset(const sim_params& p, int64_t step) {
 }
 
 static int alloc_csr(sim_t* s, int64_t cap) {
+  drop_graphs(s);
   dfree(s, s->d.col);
   dfree(s, s->d.val);
   dfree(s, s->d.valf);
@@ -231,6 +251,7 @@ static int ensure_mp(sim_t* s, bool training) {
     s->mp_ready = true;
   }
   if (s->mp_nnz_cap != s->d.nnz_cap) {
+    drop_graphs(s);
     dfree(s, m.ef);
     dfree(s, m.tg);
     dfree(s, m.moff);
@@ -265,7 +286,7 @@ static int ensure_mp(sim_t* s, bool training) {
 
 // a1-a5: sort, neighbour list, A and b at `step`.  The capacity check of the
 // fill is read back later (with the first CG chunk).
-static int build_system(sim_t* s, int64_t step) {
+static int build_system(sim_t* s) {
   DevPtrs& d = s->d;
   s->system_valid = false;
   hipStream_t st = s->stream;
@@ -278,10 +299,10 @@ static int build_system(sim_t* s, int64_t step) {
   std::swap(d.pos, d.pos_alt);
   std::swap(d.cellidx, d.cellidx_alt);
   HIPCHK(launch_cell_sort(d, st));
-  HIPCHK(launch_nbr_count(d, step, st));
+  HIPCHK(launch_nbr_count(d, st));
   HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
-  HIPCHK(launch_nbr_list(d, step, st));
-  HIPCHK(launch_pair_terms(d, step, st));
+  HIPCHK(launch_nbr_list(d, st));
+  HIPCHK(launch_pair_terms(d, st));
   return SIM_OK;
 }
 
@@ -294,74 +315,94 @@ static int read_ctrl(sim_t* s, bool with_cg) {
   return SIM_OK;
 }
 
-static int grow_and_refill(sim_t* s, int64_t step) {
+static int grow_and_refill(sim_t* s) {
   int64_t need = s->ctrl_h->nnz;
   int rc = alloc_csr(s, need + need / 4 + 1024);
   if (rc) return rc;
   if (need > s->d.nnz_cap) return SIM_ENOMEM;
   HIPCHK(launch_ctrl_zero(s->d, s->stream));
-  HIPCHK(launch_nbr_list(s->d, step, s->stream));
-  HIPCHK(launch_pair_terms(s->d, step, s->stream));
+  HIPCHK(launch_nbr_list(s->d, s->stream));
+  HIPCHK(launch_pair_terms(s->d, s->stream));
   return SIM_OK;
 }
 
-// a6: CG on the current system (b in d.b), x0 = 0.  tol > 0 overrides the
-// replicas' own tolerances.  Iterations are queued in chunks without host
-// synchronisation (finished replicas' blocks return at once); the control
-// block is read once per chunk.  Returns SIM_EOVERFLOW_INTERNAL if the fill
-// overflowed (nothing solved).
-static int cg_solve(sim_t* s, double tol, sim_stats* st) {
-  DevPtrs& d = s->d;
-  hipStream_t stream = s->stream;
+// a6: CG on the current system (b in d.b), x0 = 0, in three host pieces:
+// cg_queue_start (reset, fresh start), cg_queue_chunk (n iterations and a
+// true-residual check round; finished replicas' blocks return at once) and
+// cg_poll_loop (reads the control block after each chunk and queues the
+// next one).  A step graph records the start and the first chunk; the host
+// loop then continues from the replayed state.
+static int cg_maxit(const sim_t* s) {
   int maxit = 1;
   for (auto& p : s->prm) maxit = std::max(maxit, p.cg_maxit);
-  if (d.learned && s->learned_maxit > 0) maxit = std::min(maxit, (int)s->learned_maxit);
+  if (s->d.learned && s->learned_maxit > 0) maxit = std::min(maxit, (int)s->learned_maxit);
+  return maxit;
+}
+
+// tol > 0 overrides the replicas' own tolerances
+static int cg_queue_start(sim_t* s, double tol) {
+  const DevPtrs& d = s->d;
+  HIPCHK(launch_cg_reset(d, tol, s->stream));
+  HIPCHK(launch_cg_vec(d, 0, s->stream));
+  if (d.learned) HIPCHK(launch_cg_apply(d, 0, s->stream));
+  HIPCHK(launch_cg_spmv(d, 0, 0, s->stream));
+  HIPCHK(launch_cg_finish(d, 0, s->stream));
+  return SIM_OK;
+}
+
+// n iterations (iteration numbers first..first+n-1 for the timing probe,
+// which is off when probes is false), then the check round: true residuals
+// of replicas whose components all passed, restarts of those that failed
+static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
+  const DevPtrs& d = s->d;
+  hipStream_t stream = s->stream;
   const bool learned = d.learned != 0;
-  HIPCHK(launch_cg_reset(d, tol, stream));
-  HIPCHK(launch_cg_vec(d, 0, stream));
-  if (learned) HIPCHK(launch_cg_apply(d, 0, stream));
-  HIPCHK(launch_cg_spmv(d, 0, 0, stream));
-  HIPCHK(launch_cg_finish(d, 0, stream));
-  int launched = 0;
-  std::vector<std::pair<int, double>> hist;  // (iterations, worst relative residual^2)
-  int chunk = s->last_iters > 2 ? s->last_iters - 1 : 8;
-  int status = SIM_OK;
-  for (;;) {
-    int n = std::min(chunk, maxit + 1 - launched);
-    if (n < 1) n = 1;
-    for (int k = 0; k < n; ++k) {
-      const int g = launched + k;
-      const bool probe = s->prof_every > 0 && g % s->prof_every == 0 &&
-                         (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
-      // vector update, then (learned) u = M^-1 r, then w = A u
-      const int order[3] = {0, 2, 1};
-      for (int oi = 0; oi < 3; ++oi) {
-        const int kern = order[oi];
-        if (kern == 2 && !learned) continue;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (probe) {
-          const int ev = (int)s->prof_pending.size();
-          s->prof_pending.push_back({kern, g, ev, 0.0f});
-          e0 = s->prof_ev[2 * ev];
-          e1 = s->prof_ev[2 * ev + 1];
-        }
-        if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
-        else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
-        else HIPCHK(launch_cg_apply(d, 2, stream, e0, e1));
+  for (int k = 0; k < n; ++k) {
+    const int g = first + k;
+    const bool probe = probes && s->prof_every > 0 && g % s->prof_every == 0 &&
+                       (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
+    // vector update, then (learned) u = M^-1 r, then w = A u
+    const int order[3] = {0, 2, 1};
+    for (int oi = 0; oi < 3; ++oi) {
+      const int kern = order[oi];
+      if (kern == 2 && !learned) continue;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (probe) {
+        const int ev = (int)s->prof_pending.size();
+        s->prof_pending.push_back({kern, g, ev, 0.0f});
+        e0 = s->prof_ev[2 * ev];
+        e1 = s->prof_ev[2 * ev + 1];
       }
-      HIPCHK(launch_cg_finish(d, 2, stream));
+      if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
+      else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
+      else HIPCHK(launch_cg_apply(d, 2, stream, e0, e1));
     }
-    launched += n;
-    // true-residual checks of replicas whose components all passed, and
-    // restarts of the components that failed them
-    HIPCHK(launch_cg_spmv(d, 1, 0, stream));
-    HIPCHK(launch_cg_finish(d, 3, stream));
-    HIPCHK(launch_cg_vec(d, 1, stream));
-    if (learned) HIPCHK(launch_cg_apply(d, 1, stream));
-    HIPCHK(launch_cg_spmv(d, 0, 1, stream));
-    HIPCHK(launch_cg_finish(d, 1, stream));
+    HIPCHK(launch_cg_finish(d, 2, stream));
+  }
+  HIPCHK(launch_cg_spmv(d, 1, 0, stream));
+  HIPCHK(launch_cg_finish(d, 3, stream));
+  HIPCHK(launch_cg_vec(d, 1, stream));
+  if (learned) HIPCHK(launch_cg_apply(d, 1, stream));
+  HIPCHK(launch_cg_spmv(d, 0, 1, stream));
+  HIPCHK(launch_cg_finish(d, 1, stream));
+  return SIM_OK;
+}
+
+// Host loop after `launched` iterations have been queued (the last chunk not
+// yet polled).  *first_final (optional) tells whether the first poll already
+// found the solve finished.  Returns SIM_EOVERFLOW_INTERNAL if the fill
+// overflowed (nothing solved), SIM_ESTALL_INTERNAL on a learned stall.
+static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final) {
+  DevPtrs& d = s->d;
+  const int maxit = cg_maxit(s);
+  const bool learned = d.learned != 0;
+  std::vector<std::pair<int, double>> hist;  // (iterations, worst relative residual^2)
+  int status = SIM_OK;
+  for (int poll = 0;; ++poll) {
     int rc = read_ctrl(s, true);
     if (rc) return rc;
+    if (first_final && poll == 0)
+      *first_final = s->ctrl_h->overflow == 0 && s->ctrl_h->n_notdone == 0;
     if (s->ctrl_h->overflow) { status = SIM_EOVERFLOW_INTERNAL; break; }
     if (s->ctrl_h->n_notdone == 0) break;
     if (launched > maxit) { status = SIM_ENOCONV; break; }
@@ -384,7 +425,9 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
         if (status) break;
       }
     }
-    chunk = 2;
+    const int n = std::max(1, std::min(2, maxit + 1 - launched));
+    if ((rc = cg_queue_chunk(s, n, launched, true))) return rc;
+    launched += n;
   }
   if (status == SIM_EOVERFLOW_INTERNAL || status == SIM_ESTALL_INTERNAL) {
     s->prof_pending.clear();
@@ -448,8 +491,16 @@ static int cg_solve(sim_t* s, double tol, sim_stats* st) {
   return SIM_OK;
 }
 
-static int build_and_solve(sim_t* s, int64_t step, bool replace_rhs, double tol, sim_stats* st) {
-  int rc = build_system(s, step);
+static int cg_solve(sim_t* s, double tol, sim_stats* st) {
+  int rc = cg_queue_start(s, tol);
+  if (rc) return rc;
+  const int n = std::max(1, std::min(s->last_iters > 2 ? s->last_iters - 1 : 8, cg_maxit(s) + 1));
+  if ((rc = cg_queue_chunk(s, n, 0, true))) return rc;
+  return cg_poll_loop(s, n, st, nullptr);
+}
+
+static int build_and_solve(sim_t* s, bool replace_rhs, double tol, sim_stats* st) {
+  int rc = build_system(s);
   if (rc) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (s->learned) {
@@ -471,21 +522,21 @@ static int build_and_solve(sim_t* s, int64_t step, bool replace_rhs, double tol,
       if (rc == SIM_OK) s->system_valid = true;
       return rc;
     }
-    rc = grow_and_refill(s, step);
+    rc = grow_and_refill(s);
     if (rc) return rc;
   }
   return SIM_ENOMEM;
 }
 
 // build + capacity check without a solve (parity exports)
-static int build_checked(sim_t* s, int64_t step) {
-  int rc = build_system(s, step);
+static int build_checked(sim_t* s) {
+  int rc = build_system(s);
   if (rc) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     rc = read_ctrl(s, false);
     if (rc) return rc;
     if (!s->ctrl_h->overflow) return SIM_OK;
-    rc = grow_and_refill(s, step);
+    rc = grow_and_refill(s);
     if (rc) return rc;
   }
   return SIM_ENOMEM;
@@ -514,6 +565,8 @@ const char* sim_strerror(int code) {
 void sim_destroy(sim_t* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
+  drop_graphs(s);
+  if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
   for (void* p : s->allocs) (void)hipFree(p);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->ctrl_h) (void)hipHostFree(s->ctrl_h);
@@ -585,6 +638,10 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.nrep = replicas;
   d.ncell_entries = (int32_t)seg_off;
   d.spmv_fp32 = params[0].spmv_fp32;
+  d.spmv_lanes = 4;
+  d.apply_lanes = 4;
+  s->tune.spmv_lanes = 4;
+  s->tune.apply_lanes = 4;
   const size_t rows = (size_t)s->rows;
   int rc = SIM_OK;
 #define ALLOC(ptr, bytes)                                      \
@@ -596,6 +653,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.rep = s->rep_d;
   ALLOC(d.cg, sizeof(CgRep) * replicas);
   ALLOC(d.ctrl, sizeof(Ctrl));
+  ALLOC(d.step_d, sizeof(int64_t));
   int32_t* blk_rep_d = nullptr;
   ALLOC(blk_rep_d, sizeof(int32_t) * d.nblk);
   d.blk_rep = blk_rep_d;
@@ -662,6 +720,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   if ((e = hipMemset(d.x, 0, sizeof(double) * 3 * rows))) return fail(e, "clear x");
   if ((e = hipMemset(d.vel_orig, 0, sizeof(double) * 3 * n_total))) return fail(e, "clear vel");
   if ((e = hipMemset(d.ctrl, 0, sizeof(Ctrl)))) return fail(e, "clear ctrl");
+  if ((e = hipMemset(d.step_d, 0, sizeof(int64_t)))) return fail(e, "clear step");
   if ((e = hipMemset(d.cg, 0, sizeof(CgRep) * replicas))) return fail(e, "clear cg");
   // padding rows of the second position buffer stay inert too
   if ((e = hipMemcpy(d.pos_alt, ph.data(), sizeof(double4) * rows, hipMemcpyHostToDevice)))
@@ -678,6 +737,105 @@ int sim_create(const sim_params* params, const double* pos0, sim_t** out) {
 int sim_set_stream(sim_t* s, void* stream) {
   if (!s) return SIM_EINVAL;
   s->stream = (hipStream_t)stream;
+  if (!s->stream && s->graph_mode) s->stream = s->own_stream;  // graphs need a capturable stream
+  return SIM_OK;
+}
+
+int sim_graph_mode(sim_t* s, int32_t on) {
+  if (!s || (on != 0 && on != 1)) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (on && !s->stream) {
+    if (!s->own_stream) HIPCHK(hipStreamCreateWithFlags(&s->own_stream, hipStreamDefault));
+    s->stream = s->own_stream;
+  }
+  if (!on) {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graphs(s);
+  }
+  s->graph_mode = on;
+  return SIM_OK;
+}
+
+int sim_graph_info(sim_t* s, int64_t* captures, int64_t* replays) {
+  if (!s) return SIM_EINVAL;
+  if (captures) *captures = s->graph_captures;
+  if (replays) *replays = s->graph_replays;
+  return SIM_OK;
+}
+
+static bool valid_lanes(int32_t l) { return l == 1 || l == 2 || l == 4 || l == 8; }
+
+int sim_set_tuning(sim_t* s, const sim_tuning* t) {
+  if (!s || !t || !valid_lanes(t->spmv_lanes) || !valid_lanes(t->apply_lanes)) return SIM_EINVAL;
+  s->tune.spmv_lanes = t->spmv_lanes;
+  s->tune.apply_lanes = t->apply_lanes;
+  s->d.spmv_lanes = t->spmv_lanes;
+  s->d.apply_lanes = t->apply_lanes;
+  drop_graphs(s);
+  return SIM_OK;
+}
+
+int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
+  if (!s || reps < 1) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = build_checked(s);
+  if (rc) return rc;
+  DevPtrs& d = s->d;
+  if (s->learned) {
+    if ((rc = ensure_mp(s, false))) return rc;
+    s->mp.store_train = 0;
+    HIPCHK(launch_mp_forward(d, s->mp, s->stream));
+  }
+  s->system_valid = false;
+  // u = M^-1 b for every component (a fresh CG start), then time the products
+  d.learned = s->learned ? 1 : 0;
+  HIPCHK(launch_cg_reset(d, 0.0, s->stream));
+  HIPCHK(launch_cg_vec(d, 0, s->stream));
+  if (d.learned) HIPCHK(launch_cg_apply(d, 0, s->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int lanes[4] = {1, 2, 4, 8};
+  sim_tuning t{};
+  int kinds = d.learned ? 2 : 1;
+  hipError_t err = hipSuccess;
+  for (int kind = 0; kind < kinds && err == hipSuccess; ++kind) {
+    float best = 0.0f;
+    int pick = 4;
+    for (int v = 0; v < 4 && err == hipSuccess; ++v) {
+      if (kind == 0) d.spmv_lanes = lanes[v];
+      else d.apply_lanes = lanes[v];
+      auto once = [&]() {
+        return kind == 0 ? launch_cg_spmv(d, 0, 0, s->stream) : launch_cg_apply(d, 0, s->stream);
+      };
+      if ((err = once())) break;  // untimed warm-up
+      if ((err = hipEventRecord(e0, s->stream))) break;
+      for (int k = 0; k < reps && err == hipSuccess; ++k) err = once();
+      if (err || (err = hipEventRecord(e1, s->stream)) || (err = hipEventSynchronize(e1))) break;
+      float ms = 0.0f;
+      if ((err = hipEventElapsedTime(&ms, e0, e1))) break;
+      const float us = 1000.0f * ms / (float)reps;
+      (kind == 0 ? t.spmv_us : t.apply_us)[v] = us;
+      if (v == 0 || us < best) { best = us; pick = lanes[v]; }
+    }
+    if (kind == 0) t.spmv_lanes = pick;
+    else t.apply_lanes = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  d.learned = 0;
+  if (err != hipSuccess) {
+    d.spmv_lanes = s->tune.spmv_lanes;
+    d.apply_lanes = s->tune.apply_lanes;
+    sim_note_error(err, "autotune", __LINE__);
+    return SIM_EDEVICE;
+  }
+  if (!s->learned) t.apply_lanes = s->tune.apply_lanes;
+  s->tune = t;
+  d.spmv_lanes = t.spmv_lanes;
+  d.apply_lanes = t.apply_lanes;
+  drop_graphs(s);
+  if (out) *out = t;
   return SIM_OK;
 }
 
@@ -755,7 +913,7 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   if (!s || !count || cap < 0) return SIM_EINVAL;
   if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
-  int rc = build_checked(s, s->step);
+  int rc = build_checked(s);
   if (rc) return rc;
   if ((rc = ensure_mp(s, false))) return rc;
   s->mp.store_train = 0;
@@ -786,21 +944,157 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   return SIM_OK;
 }
 
+// a7 on the host's word: update, numeric check, velocities, n -> n + 1
+static int commit_step(sim_t* s, sim_stats* st) {
+  HIPCHK(launch_update(s->d, 0, s->stream));
+  int rc = read_ctrl(s, false);
+  if (rc) return rc;
+  if (s->ctrl_h->numeric) return SIM_ENUMERIC;
+  HIPCHK(launch_save_vel(s->d, s->id_off_d, 0, s->stream));
+  HIPCHK(launch_step_commit(s->d, 0, s->stream));
+  std::swap(s->d.pos, s->d.pos_alt);
+  s->step += 1;
+  if (st) st->steps_done += 1;
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step graphs: one HIP graph holds a whole step -- build, learned forward,
+// CG start, the first K iterations and a check round, then the update, the
+// velocity export and n -> n + 1, the last three conditional on the device
+// (they do nothing unless every component converged).  The host then polls
+// once; a solve that needs more iterations continues with host-queued chunks
+// and an eager commit, exactly as without graphs, so both paths give the
+// same bits.  A graph is keyed by the device pointers and configuration it
+// was captured from; the two position/cell buffers alternate, so at most
+// two graphs are live per configuration.
+// ---------------------------------------------------------------------------
+// iterations recorded before the check: at least the last solve's count + 1;
+// kept while it stays within 8 of that (the excess iterations of converged
+// replicas return at once), else reset to the count + 3 rounded up to a
+// multiple of 4, so that small changes of the count need no new capture
+static int graph_iters(sim_t* s) {
+  const int need = s->last_iters + 1;
+  if (s->graph_K < need || s->graph_K > need + 8) s->graph_K = ((need + 2 + 3) / 4) * 4;
+  return s->graph_K;
+}
+
+static bool same_bytes(const void* a, const void* b, size_t n) { return std::memcmp(a, b, n) == 0; }
+
+static int queue_graph_step(sim_t* s, int K) {
+  int rc = build_system(s);
+  if (rc) return rc;
+  if (s->learned) HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  if ((rc = cg_queue_start(s, 0.0))) return rc;
+  if ((rc = cg_queue_chunk(s, K, 0, false))) return rc;
+  HIPCHK(launch_update(s->d, 1, s->stream));
+  HIPCHK(launch_save_vel(s->d, s->id_off_d, 1, s->stream));
+  HIPCHK(launch_step_commit(s->d, 1, s->stream));
+  return SIM_OK;
+}
+
+static int step_graph(sim_t* s, sim_stats* st) {
+  int rc;
+  if (s->learned) {
+    if ((rc = ensure_mp(s, false))) return rc;
+    s->mp.store_train = 0;
+    s->d.learned = 1;
+  }
+  const int K = graph_iters(s);
+  const DevPtrs key_d = s->d;
+  const MpPtrs key_m = s->mp;
+  sim_t::StepGraph* g = nullptr;
+  for (auto& c : s->graphs)
+    if (c.K == K && c.learned == s->learned && same_bytes(&c.d, &key_d, sizeof(DevPtrs)) &&
+        same_bytes(&c.m, &key_m, sizeof(MpPtrs)))
+      g = &c;
+  if (!g) {
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    rc = queue_graph_step(s, K);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->stream, &graph);
+    hipGraphExec_t exec = nullptr;
+    hipError_t ei = hipSuccess;
+    if (!rc && e == hipSuccess) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc || e != hipSuccess || ei != hipSuccess) {
+      s->d = key_d;  // nothing ran: undo the host-side buffer swaps of the capture
+      if (rc) return rc;
+      sim_note_error(e != hipSuccess ? e : ei, "step graph capture", __LINE__);
+      return SIM_EDEVICE;
+    }
+    if (s->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(s->graphs.front().exec);
+      s->graphs.erase(s->graphs.begin());
+    }
+    s->graphs.push_back({exec, key_d, key_m, K, s->learned});
+    g = &s->graphs.back();
+    s->graph_captures += 1;
+  } else {
+    // the host-side effects of build_system
+    std::swap(s->d.pos, s->d.pos_alt);
+    std::swap(s->d.cellidx, s->d.cellidx_alt);
+  }
+  s->system_valid = false;
+  HIPCHK(hipGraphLaunch(g->exec, s->stream));
+  s->graph_replays += 1;
+  bool committed = false;
+  rc = cg_poll_loop(s, K, st, &committed);
+  if (rc == SIM_OK && committed) {
+    // update, velocities and n -> n + 1 already ran inside the graph
+    if (s->ctrl_h->numeric) return SIM_ENUMERIC;
+    s->system_valid = true;
+    std::swap(s->d.pos, s->d.pos_alt);
+    s->step += 1;
+    if (st) st->steps_done += 1;
+    return SIM_OK;
+  }
+  if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
+    s->d.learned = 0;
+    rc = cg_solve(s, 0.0, st);
+    s->d.learned = 1;
+    if (st) st->fallback = 1;
+  }
+  if (rc == SIM_EOVERFLOW_INTERNAL) {
+    // grow the neighbour list and solve eagerly (the graphs are stale)
+    drop_graphs(s);
+    for (int attempt = 0; attempt < 4 && rc == SIM_EOVERFLOW_INTERNAL; ++attempt) {
+      if ((rc = grow_and_refill(s))) return rc;
+      if (s->learned) {
+        if ((rc = ensure_mp(s, false))) return rc;
+        HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+      }
+      rc = cg_solve(s, 0.0, st);
+      if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
+        s->d.learned = 0;
+        rc = cg_solve(s, 0.0, st);
+        s->d.learned = 1;
+        if (st) st->fallback = 1;
+      }
+    }
+    if (rc == SIM_EOVERFLOW_INTERNAL) return SIM_ENOMEM;
+  }
+  if (rc) return rc;
+  s->system_valid = true;
+  return commit_step(s, st);
+}
+
 int sim_step(sim_t* s, int32_t nsteps, sim_stats* st) {
   if (!s || nsteps < 0) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   if (st) std::memset(st, 0, sizeof(*st));
   for (int32_t k = 0; k < nsteps; ++k) {
-    int rc = build_and_solve(s, s->step, false, 0.0, st);
+    // graphs need a solve count to size the first chunk; with the timing
+    // probe on, every prof_every-th step runs eagerly so its kernels are timed
+    const bool probe_step = s->prof_every > 0 && s->step % s->prof_every == 0;
+    if (s->graph_mode && s->last_iters > 0 && !probe_step) {
+      int rc = step_graph(s, st);
+      if (rc) return rc;
+      continue;
+    }
+    int rc = build_and_solve(s, false, 0.0, st);
     if (rc) return rc;
-    HIPCHK(launch_update(s->d, s->step + 1, s->stream));
-    rc = read_ctrl(s, false);
-    if (rc) return rc;
-    if (s->ctrl_h->numeric) return SIM_ENUMERIC;
-    HIPCHK(launch_save_vel(s->d, s->id_off_d, s->stream));
-    std::swap(s->d.pos, s->d.pos_alt);
-    s->step += 1;
-    if (st) st->steps_done += 1;
+    if ((rc = commit_step(s, st))) return rc;
   }
   return SIM_OK;
 }
@@ -813,7 +1107,7 @@ int sim_solve(sim_t* s, const double* b, double* v, double tol, uint32_t flags, 
   const bool dev = flags & SIM_DEVICE_PTR;
   HIPCHK(hipMemcpyAsync(s->io, b, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         s->stream));
-  int rc = build_and_solve(s, s->step, true, tol, st);
+  int rc = build_and_solve(s, true, tol, st);
   if (rc) return rc;
   HIPCHK(launch_permute(s->d, s->id_off_d, 2, nullptr, s->io, s->stream));
   HIPCHK(hipMemcpyAsync(v, s->io, bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
@@ -850,7 +1144,7 @@ int sim_state(sim_t* s, double* pos, double* vel, sim_meta* meta, uint32_t flags
 int sim_debug_pairs(sim_t* s, int64_t* ijr, int64_t cap, int64_t* count) {
   if (!s || !count || cap < 0 || (cap > 0 && !ijr)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
-  int rc = build_checked(s, s->step);
+  int rc = build_checked(s);
   if (rc) return rc;
   const int64_t npairs = s->ctrl_h->nnz / 2;
   *count = npairs;
@@ -872,7 +1166,7 @@ int sim_debug_system(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64
   if (!s || !count || cap < 0) return SIM_EINVAL;
   if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
-  int rc = build_checked(s, s->step);
+  int rc = build_checked(s);
   if (rc) return rc;
   const int64_t nnz = s->ctrl_h->nnz;
   *count = nnz;

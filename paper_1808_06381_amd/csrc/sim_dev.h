@@ -68,7 +68,15 @@ struct Ctrl {
   int32_t numeric;      // non-finite or escaped position after an update
   int32_t max_row;      // longest off-diagonal row of the last build
   int64_t nnz;          // off-diagonal entries of the last build
+  int32_t breakdown;    // a component of the current solve broke down
+  int32_t pad;
 };
+
+// A step may be committed on the device (graph replay) only when every
+// component converged and nothing overflowed or broke down.
+__device__ __forceinline__ bool ctrl_commit_ok(const Ctrl* c) {
+  return c->n_notdone == 0 && c->overflow == 0 && c->breakdown == 0;
+}
 
 struct DevPtrs {
   const RepDev* rep;
@@ -103,6 +111,7 @@ struct DevPtrs {
   const float* moff;        // learned M^-1 off-diagonal (A's pattern)
   const double* inj_xi;     // injected Gaussians (testing), or null
   const double* inj_eta;
+  int64_t* step_d;          // current step index n (device copy of the host's counter)
   int64_t nnz_cap;
   int64_t rows;
   int32_t nblk;             // blocks over all replicas
@@ -110,7 +119,11 @@ struct DevPtrs {
   int32_t ncell_entries;
   int32_t spmv_fp32;
   int32_t learned;          // 1: u = M^-1 r by the learned preconditioner
+  int32_t spmv_lanes;       // lanes per CSR row of the products (1, 2, 4 or 8)
+  int32_t apply_lanes;
+  int32_t pad0;             // explicit: the host compares whole structs bytewise
 };
+static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
 
 // ---------------------------------------------------------------------------
 // Block -> tile mapping: hardware dispatches workgroups round-robin over the

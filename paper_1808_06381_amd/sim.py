@@ -27,8 +27,18 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
             "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
             "sim_copy_probe", "sim_precond_weights", "sim_precond_config", "sim_train_step",
-            "sim_precond_grad", "sim_debug_precond", "sim_destroy", "sim_strerror"]
+            "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
+            "sim_autotune", "sim_set_tuning", "sim_destroy", "sim_strerror"]
 MPNN_NPARAMS = 9893
+
+
+class SimTuning(C.Structure):
+    _fields_ = [("spmv_lanes", C.c_int32), ("apply_lanes", C.c_int32),
+                ("spmv_us", C.c_float * 4), ("apply_us", C.c_float * 4)]
+
+    def as_dict(self):
+        return dict(spmv_lanes=self.spmv_lanes, apply_lanes=self.apply_lanes,
+                    spmv_us=list(self.spmv_us), apply_us=list(self.apply_us))
 
 
 class SimParams(C.Structure):
@@ -129,6 +139,10 @@ def lib():
         L.sim_copy_probe.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_double)]
         L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
         L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sim_graph_mode.argtypes = [vp, C.c_int32]
+        L.sim_graph_info.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
+        L.sim_autotune.argtypes = [vp, C.c_int32, P(SimTuning)]
+        L.sim_set_tuning.argtypes = [vp, P(SimTuning)]
         L.sim_train_step.argtypes = [vp, C.c_double, P(C.c_double)]
         L.sim_precond_grad.argtypes = [vp, vp, C.c_int64]
         L.sim_debug_precond.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp]
@@ -296,6 +310,24 @@ class Sim:
         _check(lib().sim_profile_read(self.h, arr, 8, C.byref(cnt), int(reset)), "sim_profile_read")
         return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms,
                                            bytes=arr[k].bytes) for k in range(cnt.value)}
+
+    def graph_mode(self, on=True):
+        _check(lib().sim_graph_mode(self.h, int(bool(on))), "sim_graph_mode")
+
+    def graph_info(self):
+        c, r = C.c_int64(), C.c_int64()
+        _check(lib().sim_graph_info(self.h, C.byref(c), C.byref(r)), "sim_graph_info")
+        return dict(captures=c.value, replays=r.value)
+
+    def autotune(self, reps=20):
+        t = SimTuning()
+        _check(lib().sim_autotune(self.h, int(reps), C.byref(t)), "sim_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, spmv_lanes=4, apply_lanes=4):
+        t = SimTuning()
+        t.spmv_lanes, t.apply_lanes = int(spmv_lanes), int(apply_lanes)
+        _check(lib().sim_set_tuning(self.h, C.byref(t)), "sim_set_tuning")
 
     def set_weights(self, theta):
         theta = np.ascontiguousarray(theta, dtype=np.float32)

@@ -1,0 +1,118 @@
+"""Whole steps replayed as HIP graphs, and the lane-width tuning of the CSR
+products.
+
+* Graph steps against eager steps: positions and velocities bitwise equal
+  (the graph records the same kernels in the same order; a solve that needs
+  more iterations than the graph holds continues eagerly), for one box, a
+  batch of uneven replicas and the learned preconditioner.
+* Every lane width of the products (1, 2, 4, 8) gives velocities within the
+  CG tolerance bound of the oracle; the autotuner returns one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_06381_amd import inputs, precond
+from paper_1808_06381_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+
+
+def run(cfg, pos0, steps, graph, precond_name=None, theta=None, tol=1e-10):
+    with S.Sim(cfg, pos0, tol=tol, precond=precond_name) as sim:
+        if theta is not None:
+            sim.set_weights(theta)
+        if graph:
+            sim.graph_mode(True)
+        its = []
+        for _ in range(steps):
+            st = sim.step(1)
+            its.append(max(st["iters"]))
+        pos, vel, meta = sim.state()
+        info = sim.graph_info()
+    return pos, vel, meta, its, info
+
+
+def test_graph_steps_bitwise_equal_eager():
+    cfg = inputs.small_case(seed=7)["params"]
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    pe, ve, me, ite, _ = run(cfg, pos0, 12, graph=False)
+    pg, vg, mg, itg, info = run(cfg, pos0, 12, graph=True)
+    assert np.array_equal(pe, pg) and np.array_equal(ve, vg)
+    assert ite == itg and me["step"] == mg["step"] == 12
+    # two graphs per configuration (the position and cell buffers alternate);
+    # a new one each time the iteration count outgrows the recorded chunk
+    assert info["replays"] == 11 and 2 <= info["captures"] <= 2 + info["replays"] // 2, (info, ite)
+
+
+def test_graph_batch_of_uneven_replicas_bitwise():
+    cfgs, pos = [], []
+    for r, (n, shear) in enumerate([(700, 0.01), (2500, 0.3), (1300, 1.0)]):
+        c = inputs.cube_params(n, shear, seed=100 + r)
+        c["stream"] = r
+        cfgs.append(c)
+        pos.append(inputs.uniform_positions(n, c["box"], 100 + r))
+    pos0 = np.concatenate(pos)
+    pe, ve, _, ite, _ = run(cfgs, pos0, 8, graph=False)
+    pg, vg, _, itg, info = run(cfgs, pos0, 8, graph=True)
+    assert np.array_equal(pe, pg) and np.array_equal(ve, vg)
+    assert ite == itg and info["replays"] == 7
+
+
+def test_graph_learned_bitwise_and_matches_oracle():
+    cfg = inputs.cube_params(2000, 0.2, seed=21)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], 21)
+    theta = precond.init_params(seed=3)
+    pe, ve, _, ite, _ = run(cfg, pos0, 6, graph=False, precond_name="learned", theta=theta)
+    pg, vg, _, itg, info = run(cfg, pos0, 6, graph=True, precond_name="learned", theta=theta)
+    assert np.array_equal(pe, pg) and np.array_equal(ve, vg)
+    assert info["replays"] == 5
+    # the learned preconditioner changes iterations, not the answer
+    po = pos0.copy()
+    for k in range(6):
+        po, vo, _ = oracle.step(cfg, po, k, tol=1e-10)
+    rel = np.linalg.norm(vg - vo, axis=0) / np.linalg.norm(vo, axis=0)
+    assert np.all(rel < 1e-7), rel
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_every_lane_width_solves_to_tolerance(lanes):
+    cfg = inputs.base_params(n=3000, box=(14.4, 14.4, 14.4), shear_rate=0.3, seed=11)
+    pos = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    b = np.random.default_rng(5).normal(size=(cfg["n"], 3))
+    ref = oracle.build_system(cfg, pos, 0)
+    A = oracle.dense(ref)
+    x = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A)
+    for name, extra in [("jacobi", {}), ("fp32", {"spmv_fp32": 1})]:
+        with S.Sim(dict(cfg, **extra), pos, tol=1e-10) as sim:
+            sim.set_tuning(spmv_lanes=lanes, apply_lanes=lanes)
+            v, st = sim.solve(b)
+        err = np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
+        assert np.all(err <= kappa * 1e-10), (name, err)
+    theta = precond.init_params(seed=1)
+    with S.Sim(cfg, pos, tol=1e-10, precond="learned") as sim:
+        sim.set_weights(theta)
+        sim.set_tuning(spmv_lanes=lanes, apply_lanes=lanes)
+        v, st = sim.solve(b)
+    err = np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
+    assert np.all(err <= kappa * 1e-10) and st["fallback"] == 0
+
+
+def test_autotune_picks_a_valid_width_and_keeps_state():
+    cfg = inputs.cube_params(20000, 0.1, seed=9)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], 9)
+    with S.Sim(cfg, pos0, tol=1e-8, precond="learned") as sim:
+        sim.set_weights(precond.init_params(seed=2))
+        sim.step(2)
+        before = sim.state()
+        t = sim.autotune(reps=5)
+        after = sim.state()
+        assert t["spmv_lanes"] in (1, 2, 4, 8) and t["apply_lanes"] in (1, 2, 4, 8)
+        assert all(u > 0 for u in t["spmv_us"]) and all(u > 0 for u in t["apply_us"])
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        st = sim.step(2)
+        assert max(st["relres"]) <= 1e-8 and st["steps_done"] == 2
+    with pytest.raises(S.SimError):
+        with S.Sim(cfg, pos0) as sim:
+            sim.set_tuning(spmv_lanes=3)

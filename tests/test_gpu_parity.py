@@ -148,6 +148,51 @@ def test_solve_matches_dense(name):
     assert max(abs(i - j) for i, j in zip(its, st["iters"])) <= 2
 
 
+@pytest.mark.parametrize("name", ["cube3000", "gauss_paperlike"])
+def test_fp32_spmv_solve_matches_dense(name):
+    """FP32 matrix values in the iteration product, FP64 dots and an FP64
+    true-residual recompute at every convergence check: the stopping test is
+    the same FP64 residual as the FP64 path, so the answer meets the same
+    forward-error bound; the 1e-5 relative bar is the stated floor."""
+    cfg = CASES[name]
+    n = cfg["n"]
+    pos = inputs.uniform_positions(n, cfg["box"], cfg["seed"])
+    b = np.random.default_rng(2).normal(size=(n, 3))
+    with S.Sim(cfg, pos, tol=1e-10, spmv_fp32=1) as sim:
+        v, st = sim.solve(b)
+    with S.Sim(cfg, pos, tol=1e-10) as sim:
+        v64, st64 = sim.solve(b)
+    ref = oracle.build_system(cfg, pos, 0)
+    A = oracle.dense(ref)
+    x = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
+    assert np.all(err <= 1e-5) and np.all(err <= kappa * 1e-10), err
+    res = np.linalg.norm(b - A @ v, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(res <= 1e-10 * (1 + 1e-6)), res
+    assert max(st["relres"]) <= 1e-10
+    # the FP32 product perturbs the recurrences by about 1e-7 relative, so
+    # reaching 1e-10 may take restarts but not many more iterations
+    assert max(st["iters"]) <= max(st64["iters"]) + 40
+    assert not np.array_equal(v, v64)
+
+
+def test_fp32_spmv_trajectory_small_workload():
+    case = inputs.small_case(seed=4)
+    cfg = dict(case["params"], spmv_fp32=1)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    pos_o = pos0.copy()
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        for k in range(10):
+            st = sim.step(1)
+            pos_g, vel_g, _ = sim.state()
+            pos_o, vel_o, _ = oracle.step(cfg, pos_o, k, tol=1e-10)
+            rel = np.linalg.norm(vel_g - vel_o, axis=0) / np.linalg.norm(vel_o, axis=0)
+            assert np.all(rel < 1e-5), (k, rel)
+            assert max(st["relres"]) <= 1e-10
+            assert np.max(np.abs(le_diff(cfg, k + 1, pos_g, pos_o))) < 1e-6, k
+
+
 def test_solve_edge_cases():
     cfg = inputs.base_params(n=1, box=(5.0, 5.0, 5.0), gamma0=0.25)
     with S.Sim(cfg, np.array([[1.0, 2.0, 3.0]])) as sim:
