@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--probe-every", type=int, default=8,
                     help="every k-th step runs eagerly with every k-th CG iteration timed")
     ap.add_argument("--no-graph", action="store_true", help="eager steps only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default lane widths of the CSR products")
     ap.add_argument("--batch", type=int, default=64, help="replicas of the batch workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=1)
@@ -117,6 +119,11 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     for k in range(args.warmup):
         for sim in sims:
             sim.step(1)
+    tuning = []
+    if not args.no_autotune:
+        for sim in sims:
+            tuning.append(sim.autotune(reps=10))
+            sim.step(1)  # re-records the step graph with the chosen widths
     for sim in sims:
         sim.profile_read(reset=True)
         sim.profile_enable(args.probe_every)
@@ -152,8 +159,11 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
                              gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
     particles = sum(sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs)
     value = steps * particles / elapsed
+    tuned = [dict(spmv_lanes=t["spmv_lanes"], apply_lanes=t["apply_lanes"],
+                  spmv_us=[round(u, 1) for u in t["spmv_us"]],
+                  apply_us=[round(u, 1) for u in t["apply_us"]]) for t in tuning]
     return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks,
-                graphs=graphs, particles=particles, steps=steps)
+                graphs=graphs, particles=particles, steps=steps, tuning=tuned)
 
 
 def main():
@@ -249,7 +259,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": {f: dict(value=round(r["value"], 1), ms_per_step=round(r["elapsed"] / args.steps * 1e3, 4),
                           mean_cg_iters=round(float(np.mean(r["iters"])), 2), fallbacks=r["fallbacks"],
-                          graphs=r["graphs"])
+                          graphs=r["graphs"], tuning=r["tuning"])
                   for f, r in runs.items()},
         "graph_steps": not args.no_graph,
     }
@@ -270,7 +280,7 @@ def main():
             "forms": {f: dict(value=round(r["value"], 1),
                               ms_per_step=round(r["elapsed"] / r["steps"] * 1e3, 4),
                               mean_cg_iters=round(float(np.mean(r["iters"])), 2),
-                              fallbacks=r["fallbacks"], graphs=r["graphs"])
+                              fallbacks=r["fallbacks"], graphs=r["graphs"], tuning=r["tuning"])
                       for f, r in bruns.items()},
         }
         if "learned" in bruns and "plain" in bruns:

@@ -170,7 +170,8 @@ __global__ void k_cell_sort(DevPtrs d) {
 // a2-a5: neighbour search, pair terms, assembly of A and b
 // ===========================================================================
 __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
+  if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
@@ -212,7 +213,8 @@ __device__ __forceinline__ double force_coef(const RepDev& R, double r2, double 
 // Neighbour list: the same candidate order as k_nbr_count; each passing
 // candidate's sorted row index goes to col[rowptr[i] + slot].
 __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
+  if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
@@ -243,7 +245,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
 #define PAIR_LANES 4
 #define PAIR_THREADS 256  // fewer threads per block: the pair noise needs ~130 registers
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
+  if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   if (d.ctrl->overflow) return;
   const int64_t step = *d.step_d;
@@ -515,15 +518,15 @@ hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_nbr_count(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_count, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
+  hipLaunchKernelGGL(k_nbr_count, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
   return hipGetLastError();
 }
 hipError_t launch_nbr_list(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_list, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
+  hipLaunchKernelGGL(k_nbr_list, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
   return hipGetLastError();
 }
 hipError_t launch_pair_terms(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_terms, dim3(d.nblk), dim3(PAIR_THREADS), 0, s, d);
+  hipLaunchKernelGGL(k_pair_terms, dim3(xcd_grid(d.nblk)), dim3(PAIR_THREADS), 0, s, d);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s) {
