@@ -208,17 +208,21 @@ int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
  * A three-layer message-passing network on the pair graph of A (hidden 32)
  * maps node features (t_i, a_i, deg_i/8) and edge features (r_ij/rc, w_ij,
  * What_ij) to M^-1 = D^-1/2 (diag(lam) + S) D^-1/2 in A's sparsity, with
- * S_ij = g_ij What_ij, g_ij = 2 sigmoid(.) symmetric and
- * lam_i = sum_j S_ij + softplus(.) + 1e-3, so M^-1 is SPD for any weights
- * (D = diag A, What_ij = alpha w_ij / sqrt(D_i D_j)).  It replaces the
- * Jacobi step u = D^-1 r of the CG solve of Eq. 9; the stopping rule (true
- * residual) is unchanged, so it changes iteration counts, not answers.  A
- * solve that stalls (residual not 10 % lower over 10 iterations after 20)
- * or breaks down is redone with Jacobi and flagged in sim_stats.fallback.
+ * S_ij = z.(h_i*h_j) + ze.e_ij + z0 symmetric and lam_i = softplus(.) + 1e-3
+ * (D = diag A, What_ij = alpha w_ij / sqrt(D_i D_j)).  M^-1 is symmetric
+ * with a positive diagonal but positive definite only for suitable weights
+ * (the best sparse approximate inverses of A are not diagonally dominant);
+ * lam = 1, S = What is the two-term Neumann series of A^-1, which is.  It
+ * replaces the Jacobi step u = D^-1 r of the CG solve of Eq. 9; the stopping
+ * rule (true residual) is unchanged, so it changes iteration counts, not
+ * answers.  A solve that stalls (residual not 10 % lower over 10 iterations
+ * after 20) or breaks down -- what an indefinite M^-1 leads to -- is redone
+ * with Jacobi and flagged in sim_stats.fallback.
  * The weights are SIM_MPNN_NPARAMS FP32 values (bfloat16 in the kernels),
  * in this order: W0[32][3], b0[32], then per layer P[32][32], Q[32][3],
  * c[32], U[32][32], V[32][32], d[32], then v[32], v0, z[32], ze[3], z0.
- * A new handle starts with all weights zero (a valid SPD preconditioner). */
+ * A new handle starts with all weights zero: S = 0, lam = ln 2 + 1e-3, a
+ * scaled Jacobi preconditioner.                                           */
 #define SIM_MPNN_NPARAMS 9893
 /* Copy the FP32 master weights in (set = 1) or out (set = 0).            */
 int sim_precond_weights(sim_t* sim, float* theta, int64_t count, int32_t set);
@@ -235,6 +239,24 @@ int sim_precond_config(sim_t* sim, int32_t round_act, int32_t learned_maxit);
  * at the weights before the update.  SIM_EINVAL without a solved system;
  * SIM_ENOTSUP for batches.                                               */
 int sim_train_step(sim_t* sim, double lr, double* loss);
+/* One training step on a white-noise probe of the current system (any
+ * number of replicas; needs a successful solve): x* = z with z_ik ~ N(0, 1)
+ * (Philox4x64-10, key (seed, replica stream), counter (index, 3, particle
+ * id, 0), Box-Muller as for the thermal force) and b = A z, so that
+ * L = ||(M^-1 A - I) z||^2 / ||z||^2 (summed over components and replicas)
+ * samples the Frobenius distance of M^-1 A from the identity, weighted by A
+ * (euclid = 0) or unweighted (euclid = 1, which gives the smooth modes that
+ * bound the CG convergence rate their full weight) -- every mode counts,
+ * where the solution of Eq. 9 is dominated by smooth ones.  Otherwise as
+ * sim_train_step; the solve's b and x are left as they were.              */
+int sim_train_probe(sim_t* sim, double lr, uint64_t seed, uint64_t index, int32_t euclid,
+                    double* loss);
+/* Adam state of the training steps: first and second moments (count =
+ * SIM_MPNN_NPARAMS each) and the step count t, copied out (set = 0) or in
+ * (set = 1), so that training can move between handles.  Setting weights
+ * with sim_precond_weights clears it.                                     */
+int sim_precond_optimizer(sim_t* sim, float* m1, float* m2, int64_t count, int32_t* t,
+                          int32_t set);
 /* The gradient dL/dtheta of the last sim_train_step (with respect to the
  * bfloat16 weights), count = SIM_MPNN_NPARAMS.                           */
 int sim_precond_grad(sim_t* sim, float* grad, int64_t count);
@@ -272,7 +294,7 @@ int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void
  * on != 0: from the second step on, sim_step records one graph per step
  * configuration -- sort, neighbour list, pair terms, the learned forward
  * pass, CG start, the first K CG iterations (K >= the previous solve's
- * count + 1, kept while within 8 of it) and a true-residual check, then the
+ * count + 1, kept while within 12 of it) and a true-residual check, then the
  * position update and velocity export, which run on the device only if
  * every component of every replica has converged -- and replays it with
  * one host synchronisation per step.  Solves that need more iterations

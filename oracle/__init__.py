@@ -96,6 +96,9 @@ def lib():
         L.orc_mpnn_loss_grad.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double, f_p,
                                          d_p, d_p, d_p]
         L.orc_mpnn_loss_grad.restype = C.c_double
+        L.orc_mpnn_loss_grad_norm.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double,
+                                              f_p, d_p, d_p, C.c_int, d_p]
+        L.orc_mpnn_loss_grad_norm.restype = C.c_double
         _lib = L
     return _lib
 
@@ -323,15 +326,19 @@ def mpnn_forward(sys_, er, alpha, theta):
     return mdiag, moff[:len(sys_["col"])]
 
 
-def mpnn_loss_grad(sys_, er, alpha, theta, b, xstar, grad=True):
-    """Loss ||M^-1 b - x*||_A^2 / ||x*||_A^2 and its gradient (float64 array)."""
+def mpnn_loss_grad(sys_, er, alpha, theta, b, xstar, grad=True, norm="A"):
+    """Loss ||M^-1 b - x*||^2 / ||x*||^2 in the A-norm (norm="A") or the
+    Euclidean norm (norm="2") and its gradient (float64 array)."""
     n = sys_["diag"].shape[0]
     t, tp = _theta(theta)
     g = np.zeros(mpnn_nparams()) if grad else None
     er = np.ascontiguousarray(er, dtype=np.float64)
     b = _f64(b, (n, 3))
     xstar = _f64(xstar, (n, 3))
-    loss = lib().orc_mpnn_loss_grad(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
-                                    _dp(sys_["diag"]), _dp(er), float(alpha), tp, _dp(b),
-                                    _dp(xstar), _dp(g))
+    if norm not in ("A", "2"):
+        raise ValueError("norm must be 'A' or '2'")
+    loss = lib().orc_mpnn_loss_grad_norm(n, _ip(sys_["rowptr"]), _ip(sys_["col"]),
+                                         _dp(sys_["val"]), _dp(sys_["diag"]), _dp(er),
+                                         float(alpha), tp, _dp(b), _dp(xstar),
+                                         1 if norm == "2" else 0, _dp(g))
     return (loss, g) if grad else loss

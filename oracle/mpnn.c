@@ -1,8 +1,8 @@
 /*
  * mpnn.c -- plain FP64 oracle of the learned preconditioner: a 3-layer
  * message-passing network on the pair graph of the friction matrix A
- * (Method section, Eq. 9) that outputs an SPD approximate inverse M^-1 with
- * the sparsity of A, and the training loss with its gradient.
+ * (Method section, Eq. 9) that outputs a symmetric approximate inverse M^-1
+ * with the sparsity of A, and the training loss with its gradient.
  *
  * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written from the network's
  * definition below with straightforward loops; the gradient is analytic
@@ -17,14 +17,17 @@
  *   h0_i = relu(W0 x_i + b0)
  *   layer l:  y_j = P_l h_j;   m_i = (1/8) sum_j relu(y_j + Q_l e_ij + c_l)
  *             h_i <- h_i + relu(U_l h_i + V_l m_i + d_l)
- *   heads:    lam'_i = softplus(v . h_i + v0)
- *             g_ij   = 2 sigmoid(z . (h_i * h_j) + ze . e_ij + z0)   (symmetric)
+ *   heads:    lam_i = softplus(v . h_i + v0) + eps              (eps = 1e-3)
+ *             S_ij  = z . (h_i * h_j) + ze . e_ij + z0          (symmetric)
  * Preconditioner:
- *   S_ij = g_ij What_ij,  lam_i = sum_j S_ij + lam'_i + eps   (eps = 1e-3)
  *   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2:  mdiag_i = lam_i / D_i,
  *   moff_ij = S_ij / sqrt(D_i D_j).
- *   diag(lam) + S is strictly diagonally dominant with a positive diagonal,
- *   so M^-1 is symmetric positive definite for every parameter value.
+ *   Symmetric with a positive diagonal; not positive definite for every
+ *   parameter value (the best sparse approximate inverses of A are not
+ *   diagonally dominant).  lam = 1, S = What is the two-term Neumann series
+ *   D^-1 + D^-1 (D - A) D^-1, which is positive definite because
+ *   D^-1/2 (D - A) D^-1/2 has spectral radius below 1 (A strictly
+ *   diagonally dominant).
  * Loss on a system (A, b, x*): L = ||M^-1 b - x*||_A^2 / ||x*||_A^2, summed
  * over the three components.
  * Weights enter in bfloat16 (round to nearest even of the FP32 master
@@ -105,13 +108,12 @@ typedef struct {
   double *as;            /* NL x n x H     : pre-activation of the update */
   double *tau;           /* n   : node head pre-activation */
   double *tg;            /* nnz : edge head pre-activation */
-  double *g;             /* nnz */
   double *what;          /* nnz */
 } net_t;
 
 static void net_free(net_t* t) {
   free(t->x); free(t->e); free(t->hs); free(t->ys); free(t->ms); free(t->as);
-  free(t->tau); free(t->tg); free(t->g); free(t->what);
+  free(t->tau); free(t->tg); free(t->what);
 }
 
 static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff) {
@@ -125,9 +127,8 @@ static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff
   t->as = (double*)calloc((size_t)(NL * n * H + 1), sizeof(double));
   t->tau = (double*)calloc((size_t)(n + 1), sizeof(double));
   t->tg = (double*)calloc((size_t)(nnz + 1), sizeof(double));
-  t->g = (double*)calloc((size_t)(nnz + 1), sizeof(double));
   t->what = (double*)calloc((size_t)(nnz + 1), sizeof(double));
-  if (!t->x || !t->e || !t->hs || !t->ys || !t->ms || !t->as || !t->tau || !t->tg || !t->g ||
+  if (!t->x || !t->e || !t->hs || !t->ys || !t->ms || !t->as || !t->tau || !t->tg ||
       !t->what)
     return -2;
   const double* th = t->th;
@@ -196,19 +197,15 @@ static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff
     t->tau[i] = acc;
   }
   for (int64_t i = 0; i < n; ++i) {
-    double lam = softplus(t->tau[i]) + EPS_LAM;
     for (int64_t q = t->rowptr[i]; q < t->rowptr[i + 1]; ++q) {
       const int64_t j = t->col[q];
       double acc = hd[H_Z0];
       for (int k = 0; k < H; ++k) acc += hd[H_Z + k] * (hf[i * H + k] * hf[j * H + k]);
       for (int f = 0; f < FE; ++f) acc += hd[H_ZE + f] * t->e[FE * q + f];
-      t->tg[q] = acc;
-      t->g[q] = 2.0 * sigm(acc);
-      const double s = t->g[q] * t->what[q];
-      lam += s;
-      if (moff) moff[q] = s / sqrt(t->diag[i] * t->diag[j]);
+      t->tg[q] = acc;  /* S_ij */
+      if (moff) moff[q] = acc / sqrt(t->diag[i] * t->diag[j]);
     }
-    if (mdiag) mdiag[i] = lam / t->diag[i];
+    if (mdiag) mdiag[i] = (softplus(t->tau[i]) + EPS_LAM) / t->diag[i];
   }
   return 0;
 }
@@ -226,11 +223,13 @@ int orc_mpnn_forward(int64_t n, const int64_t* rowptr, const int64_t* col, const
   return rc;
 }
 
-/* Loss L = ||M^-1 b - x*||_A^2 / ||x*||_A^2 (three components) and, if grad
- * is given, dL/dtheta (with respect to the bf16-rounded weights).          */
-double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
-                          const double* diag, const double* edge_r, double alpha,
-                          const float* theta, const double* b, const double* xstar, double* grad) {
+/* Loss L = ||M^-1 b - x*||^2 / ||x*||^2 (three components) in the A-norm
+ * (euclid = 0) or the Euclidean norm (euclid = 1) and, if grad is given,
+ * dL/dtheta (with respect to the bf16-rounded weights).                     */
+double orc_mpnn_loss_grad_norm(int64_t n, const int64_t* rowptr, const int64_t* col,
+                               const double* val, const double* diag, const double* edge_r,
+                               double alpha, const float* theta, const double* b,
+                               const double* xstar, int euclid, double* grad) {
   net_t t;
   memset(&t, 0, sizeof(t));
   t.n = n; t.nnz = rowptr[n]; t.rowptr = rowptr; t.col = col; t.val = val; t.diag = diag;
@@ -246,8 +245,14 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
   /* z = M^-1 b, e = z - x*, A e, A x* */
   orc_spmv3(n, rowptr, col, moff, mdiag, b, z);
   for (int64_t i = 0; i < 3 * n; ++i) z[i] -= xstar[i];
-  orc_spmv3(n, rowptr, col, val, diag, z, ae);
-  orc_spmv3(n, rowptr, col, val, diag, xstar, ax);
+  if (euclid) {
+    /* the identity in place of A */
+    memcpy(ae, z, sizeof(double) * 3 * (size_t)n);
+    memcpy(ax, xstar, sizeof(double) * 3 * (size_t)n);
+  } else {
+    orc_spmv3(n, rowptr, col, val, diag, z, ae);
+    orc_spmv3(n, rowptr, col, val, diag, xstar, ax);
+  }
   double num = 0.0, den = 0.0;
   for (int64_t i = 0; i < 3 * n; ++i) {
     num += z[i] * ae[i];
@@ -260,7 +265,8 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
     const double* th = t.th;
     const double* hd = th + OFF_HEAD;
     double* gh = grad + OFF_HEAD;
-    /* dL/dz = 2 A e / den; dL/dmdiag_i = sum_c G_ic b_ic; dL/dmoff_ij = sum_c G_ic b_jc */
+    /* dL/dz = 2 A e / den (2 e / den Euclidean); dL/dmdiag_i = sum_c G_ic b_ic;
+     * dL/dmoff_ij = sum_c G_ic b_jc */
     double* gl = (double*)calloc((size_t)(n + 1), sizeof(double));     /* dL/dlam */
     double* gt = (double*)calloc((size_t)(n + 1), sizeof(double));     /* dL/dtau */
     double* dh = (double*)calloc((size_t)(n * H + 1), sizeof(double)); /* dL/dh */
@@ -271,7 +277,7 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
       double gd = 0.0;
       for (int c = 0; c < 3; ++c) gd += 2.0 * ae[3 * i + c] / den * b[3 * i + c];
       gl[i] = gd / diag[i];                      /* mdiag = lam / D */
-      gt[i] = gl[i] * sigm(t.tau[i]);            /* lam' = softplus(tau) */
+      gt[i] = gl[i] * sigm(t.tau[i]);            /* lam = softplus(tau) + eps */
     }
     const double* hf = t.hs + (int64_t)NL * n * H;
     for (int64_t i = 0; i < n; ++i) {
@@ -281,16 +287,13 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
         gh[H_V + k] += gt[i] * hf[i * H + k];
         dh[i * H + k] += gt[i] * hd[H_V + k];
       }
-      /* edge head: S_ij enters moff_ij, moff_ji (same g) and lam_i, lam_j;
-       * each directed entry carries moff_ij and lam_i; its reverse carries the rest */
+      /* edge head: each directed entry evaluates S_ij for its own moff_ij
+       * (the reverse entry evaluates the same value for moff_ji) */
       for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
         const int64_t j = col[q];
         double gm = 0.0;
         for (int c = 0; c < 3; ++c) gm += 2.0 * ae[3 * i + c] / den * b[3 * j + c];
-        const double dS = gm / sqrt(diag[i] * diag[j]) + gl[i];
-        const double dg = dS * t.what[q];
-        const double sg = sigm(t.tg[q]);
-        const double dtg = dg * 2.0 * sg * (1.0 - sg);
+        const double dtg = gm / sqrt(diag[i] * diag[j]);
         gh[H_Z0] += dtg;
         for (int f = 0; f < FE; ++f) gh[H_ZE + f] += dtg * t.e[FE * q + f];
         for (int k = 0; k < H; ++k) {
@@ -371,4 +374,11 @@ out:
   free(mdiag); free(moff); free(z); free(ae); free(ax);
   net_free(&t);
   return loss;
+}
+
+double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                          const double* diag, const double* edge_r, double alpha,
+                          const float* theta, const double* b, const double* xstar, double* grad) {
+  return orc_mpnn_loss_grad_norm(n, rowptr, col, val, diag, edge_r, alpha, theta, b, xstar, 0,
+                                 grad);
 }

@@ -94,6 +94,10 @@ void orc_mpnn_set_bf16(int on);
 int orc_mpnn_forward(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
                      const double* diag, const double* edge_r, double alpha, const float* theta,
                      double* mdiag, double* moff);
+double orc_mpnn_loss_grad_norm(int64_t n, const int64_t* rowptr, const int64_t* col,
+                               const double* val, const double* diag, const double* edge_r,
+                               double alpha, const float* theta, const double* b,
+                               const double* xstar, int euclid, double* grad);
 double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
                           const double* diag, const double* edge_r, double alpha,
                           const float* theta, const double* b, const double* xstar, double* grad);

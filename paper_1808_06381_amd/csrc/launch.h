@@ -39,5 +39,7 @@ hipError_t launch_mp_loss(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
 hipError_t launch_mp_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
 hipError_t launch_mp_adam(const MpPtrs& m, float lr, int t, hipStream_t s);
 hipError_t launch_mp_cast(const MpPtrs& m, hipStream_t s);
+hipError_t launch_mp_probe(const DevPtrs& d, double* z, double* b, uint64_t seed, uint64_t index,
+                           hipStream_t s);
 hipError_t launch_mp_export(const DevPtrs& d, const MpPtrs& m, const int64_t* id_off, int64_t* rows,
                             int64_t* cols, double* vals, int64_t cap, double* diag, hipStream_t s);

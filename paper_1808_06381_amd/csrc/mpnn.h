@@ -53,10 +53,15 @@ struct MpPtrs {
   double* G;       // [rows][3] 2 A zb
   double* lpart;   // loss partials
   double* loss;    // [2]: loss, 1 / ||x*||_A^2
+  double* pz;      // [rows][3] probe vector z (training on probes)
+  double* pb;      // [rows][3] A z
   float* dh;       // [rows][H]
   float* dh2;      // [rows][H]
   float* dm;       // [rows][H]
   int64_t rows;
   int round_act;   // 1: round activations entering products to bf16
   int store_train; // 1: keep m and a for the backward pass
+  int loss_euclid; // loss norm: 0 the A-norm, 1 the Euclidean norm
+  int pad0;        // explicit: the host compares whole structs bytewise
 };
+static_assert(sizeof(MpPtrs) % 8 == 0, "MpPtrs must have no implicit tail padding");

@@ -9,9 +9,10 @@
 //   h0 = relu(W0 x + b0)
 //   layer: y_j = P h_j, m_i = 1/8 sum_j relu(y_j + Q e_ij + c),
 //          h_i <- h_i + relu(U h_i + V m_i + d)
-//   heads: lam'_i = softplus(v.h_i + v0), g_ij = 2 sigmoid(z.(h_i*h_j) + ze.e_ij + z0)
-//   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2, S_ij = g_ij What_ij,
-//   lam_i = sum_j S_ij + lam'_i + 1e-3: strictly diagonally dominant -> SPD.
+//   heads: lam_i = softplus(v.h_i + v0) + 1e-3, S_ij = z.(h_i*h_j) + ze.e_ij + z0
+//   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2: symmetric, positive diagonal (the
+//   solver's true-residual test and Jacobi fallback cover a non-definite M^-1;
+//   the initial heads give the positive definite two-term Neumann series).
 // Loss on the last solved system (A, b, x*): ||M^-1 b - x*||_A^2 / ||x*||_A^2.
 //
 // Layout: one half-wave (32 lanes) per node, lane k = hidden feature k, so a
@@ -206,7 +207,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
     const float tau = half_sum(hv[k] * hk) + hv[MP_H];
     const double di = d.diag[i];
     const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    double sum_s = 0.0;
     for (int e = e0; e < e1; ++e) {
       const int64_t j = d.col[e];
       const float hj = act_in(m, hf[j * MP_H + k]);
@@ -214,19 +214,14 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
 #pragma unroll
       for (int f = 0; f < MP_FE; ++f) t += hze[f] * act_in(m, m.ef[3 * (int64_t)e + f]);
       t += hze[MP_FE];
-      const double g = 2.0 * (double)sigmoidf_(t);
-      const double dj = d.diag[j];
-      const double s = g * (-d.val[e] / sqrt(di * dj));
-      sum_s += s;
       if (k == 0) {
         m.tg[e] = t;
-        m.moff[e] = (float)(s / sqrt(di * dj));
+        m.moff[e] = (float)((double)t / sqrt(di * d.diag[j]));
       }
     }
     if (k == 0) {
       m.tau[i] = tau;
-      const double lam = sum_s + (double)softplusf_(tau) + MP_EPS_LAM;
-      m.mdiag[i] = lam / di;
+      m.mdiag[i] = ((double)softplusf_(tau) + MP_EPS_LAM) / di;
     }
   }
 }
@@ -473,8 +468,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
   __shared__ int erow[MX_EC];
-  __shared__ double sbuf[MX_EC];
-  __shared__ double ssum[MP_ROWS];
   __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
   const int t = threadIdx.x;
   load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
@@ -491,7 +484,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = bf16_round(v[kk]);
   }
-  double sum_s = 0.0;  // row t's sum of S_ij (threads t < MP_ROWS)
   __syncthreads();
   const int E0 = rp[0], E1 = rp[MP_ROWS];
   for (int cb = E0; cb < E1; cb += MX_EC) {
@@ -520,22 +512,12 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
       for (int f = 0; f < MP_FE; ++f) tt += hze[f] * bf16_round(m.ef[3 * (int64_t)e + f]);
       tt += hze[MP_FE];
       if (q == 0) {
-        const double g = 2.0 * (double)sigmoidf_(tt);
-        const double sq = sqrt(d.diag[i0 + r] * d.diag[j]);
-        const double s = g * (-d.val[e] / sq);
-        sbuf[n] = s;
-        m.moff[e] = (float)(s / sq);
+        m.moff[e] = (float)((double)tt / sqrt(d.diag[i0 + r] * d.diag[j]));
         if (m.store_train) m.tg[e] = tt;
       }
     }
-    __syncthreads();
-    if (t < MP_ROWS) {
-      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + MX_EC);
-      for (int e2 = lo; e2 < hi; ++e2) sum_s += sbuf[e2 - cb];
-    }
+    __syncthreads();  // erow is rewritten for the next chunk
   }
-  if (t < MP_ROWS) ssum[t] = sum_s;
-  __syncthreads();
   float p = 0.0f;
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) p += hv[8 * q + kk] * hi_s[n * MX_FS + 8 * q + kk];
@@ -545,13 +527,12 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     const int64_t i = i0 + n;
     const float tau = p + hv[MP_H];
     m.tau[i] = tau;
-    const double lam = ssum[n] + (double)softplusf_(tau) + MP_EPS_LAM;
-    m.mdiag[i] = lam / d.diag[i];
+    m.mdiag[i] = ((double)softplusf_(tau) + MP_EPS_LAM) / d.diag[i];
   }
 }
 
 // ---------------------------------------------------------------------------
-// loss: zb = M^-1 b - x*, G = 2 A zb, partials (zb.A zb, x*.A x*)
+// loss: zb = M^-1 b - x*, G = 2 W zb, partials (zb.W zb, x*.W x*), W = A or I
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mp_resid(DevPtrs d, MpPtrs m) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
@@ -577,18 +558,26 @@ __global__ __launch_bounds__(256) void k_mp_aprod(DevPtrs d, MpPtrs m) {
   if (i < d.rows) {
     const double dg = d.diag[i];
     double az[3], ax[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      az[c] = dg * m.zb[3 * i + c];
-      ax[c] = dg * d.x[3 * i + c];
-    }
-    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
-      const int64_t j = d.col[e];
-      const double a = d.val[e];
+    if (m.loss_euclid) {  // the identity in place of A
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        az[c] += a * m.zb[3 * j + c];
-        ax[c] += a * d.x[3 * j + c];
+        az[c] = m.zb[3 * i + c];
+        ax[c] = d.x[3 * i + c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        az[c] = dg * m.zb[3 * i + c];
+        ax[c] = dg * d.x[3 * i + c];
+      }
+      for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+        const int64_t j = d.col[e];
+        const double a = d.val[e];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          az[c] += a * m.zb[3 * j + c];
+          ax[c] += a * d.x[3 * j + c];
+        }
       }
     }
 #pragma unroll
@@ -689,7 +678,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_bwd(DevPtrs d, MpPtrs m
     double gd = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) gd += m.G[3 * i + c] * d.b[3 * i + c];
-    const double gl = gd / di;
+    const double gl = gd / di;  // dL/dlam_i (mdiag = lam / D)
     const float tau = m.tau[i];
     const float gt = (float)gl * sigmoidf_(tau);
     const float hk = act_in(m, hf[i * MP_H + k]);
@@ -698,21 +687,16 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_bwd(DevPtrs d, MpPtrs m
     if (k == 0) g_v0 += gt;
     for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
       const int64_t j = d.col[e];
-      const double dj = d.diag[j];
-      const double sq = sqrt(di * dj);
-      const double what = -d.val[e] / sq;
-      double gm = 0.0, gdj = 0.0, gmr = 0.0;
+      const double sq = sqrt(di * d.diag[j]);
+      double gm = 0.0, gmr = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         gm += m.G[3 * i + c] * d.b[3 * j + c];    // this entry (i -> j)
-        gdj += m.G[3 * j + c] * d.b[3 * j + c];   // node j's diagonal term
         gmr += m.G[3 * j + c] * d.b[3 * i + c];   // the reverse entry (j -> i)
       }
-      const float t = m.tg[e];
-      const float g = 2.0f * sigmoidf_(t);
-      const float dgdt = g * (1.0f - 0.5f * g);
-      const float dt_own = (float)((gm / sq + gl) * what) * dgdt;
-      const float dt_rev = (float)((gmr / sq + gdj / dj) * what) * dgdt;
+      // moff = S / sqrt(D_i D_j): dL/dS of this entry and of its reverse
+      const float dt_own = (float)(gm / sq);
+      const float dt_rev = (float)(gmr / sq);
       const float hj = act_in(m, hf[j * MP_H + k]);
       dh += (dt_own + dt_rev) * hz[k] * hj;
       g_z += dt_own * (hk * hj);
@@ -941,6 +925,38 @@ __global__ __launch_bounds__(256) void k_mp_export(DevPtrs d, MpPtrs m, const in
 }
 
 // ---------------------------------------------------------------------------
+// white-noise probe of the current system: z ~ N(0, 1) per (row, component)
+// from Philox4x64-10 (key (seed, replica stream), counter (index, 3,
+// particle id, 0)), then b = A z; the loss kernels see x* = z, b = A z
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mp_probe_z(DevPtrs d, double* __restrict__ z, uint64_t seed,
+                                                    uint64_t index) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const RepDev& R = d.rep[d.blk_rep[i / ROWS_PER_BLOCK]];
+  double g[3] = {0.0, 0.0, 0.0};
+  if (i - R.row_off < R.n) gauss3(seed, R.stream, index, 3, (uint64_t)d.pos[i].w, 0, g);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) z[3 * i + c] = g[c];
+}
+
+__global__ __launch_bounds__(256) void k_mp_probe_b(DevPtrs d, const double* __restrict__ z,
+                                                    double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows || d.ctrl->overflow) return;
+  const double dg = d.diag[i];
+  double acc[3] = {dg * z[3 * i], dg * z[3 * i + 1], dg * z[3 * i + 2]};
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int64_t j = d.col[e];
+    const double a = d.val[e];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += a * z[3 * j + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[3 * i + c] = acc[c];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -992,6 +1008,13 @@ hipError_t launch_mp_export(const DevPtrs& d, const MpPtrs& m, const int64_t* id
                             int64_t* cols, double* vals, int64_t cap, double* diag, hipStream_t s) {
   hipLaunchKernelGGL(k_mp_export, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m, id_off, rows, cols,
                      vals, cap, diag);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_probe(const DevPtrs& d, double* z, double* b, uint64_t seed, uint64_t index,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_probe_z, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, z, seed, index);
+  hipLaunchKernelGGL(k_mp_probe_b, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, z, b);
   return hipGetLastError();
 }
 

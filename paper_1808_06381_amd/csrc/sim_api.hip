@@ -271,6 +271,8 @@ static int ensure_mp(sim_t* s, bool training) {
     MPALLOC(m.dh2, sizeof(float) * rows * H);
     MPALLOC(m.dm, sizeof(float) * rows * H);
     MPALLOC(m.gpart, sizeof(float) * (rows / MP_ROWS) * MP_NPARAMS);
+    MPALLOC(m.pz, sizeof(double) * 3 * rows);
+    MPALLOC(m.pb, sizeof(double) * 3 * rows);
     s->mp_train = true;
   }
 #undef MPALLOC
@@ -901,6 +903,51 @@ int sim_train_step(sim_t* s, double lr, double* loss) {
   return std::isfinite(l[0]) ? SIM_OK : SIM_ENUMERIC;
 }
 
+int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t euclid,
+                    double* loss) {
+  if (!s || !(lr >= 0.0) || (euclid != 0 && euclid != 1)) return SIM_EINVAL;
+  if (!s->system_valid) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, true);
+  if (rc) return rc;
+  s->mp.store_train = 1;
+  // the loss kernels read b and x* through the device-pointer block: point
+  // them at the probe (the solve's b and x stay untouched)
+  DevPtrs dp = s->d;
+  dp.x = s->mp.pz;
+  dp.b = s->mp.pb;
+  MpPtrs mq = s->mp;
+  mq.loss_euclid = euclid;
+  HIPCHK(launch_mp_probe(dp, s->mp.pz, s->mp.pb, seed, index, s->stream));
+  HIPCHK(launch_mp_forward(dp, mq, s->stream));
+  HIPCHK(launch_mp_loss(dp, mq, s->stream));
+  HIPCHK(launch_mp_backward(dp, mq, s->stream));
+  if (lr > 0.0) HIPCHK(launch_mp_adam(s->mp, (float)lr, ++s->mp_adam_t, s->stream));
+  double l[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(l, s->mp.loss, sizeof(l), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (loss) *loss = l[0];
+  return std::isfinite(l[0]) ? SIM_OK : SIM_ENUMERIC;
+}
+
+int sim_precond_optimizer(sim_t* s, float* m1, float* m2, int64_t count, int32_t* t, int32_t set) {
+  if (!s || !m1 || !m2 || !t || count != MP_NPARAMS || (set && *t < 0)) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, false);
+  if (rc) return rc;
+  const size_t bytes = sizeof(float) * MP_NPARAMS;
+  if (set) {
+    HIPCHK(hipMemcpy(s->mp.am, m1, bytes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->mp.av, m2, bytes, hipMemcpyHostToDevice));
+    s->mp_adam_t = *t;
+  } else {
+    HIPCHK(hipMemcpy(m1, s->mp.am, bytes, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(m2, s->mp.av, bytes, hipMemcpyDeviceToHost));
+    *t = s->mp_adam_t;
+  }
+  return SIM_OK;
+}
+
 int sim_precond_grad(sim_t* s, float* grad, int64_t count) {
   if (!s || !grad || count != MP_NPARAMS || !s->mp_ready) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
@@ -970,12 +1017,12 @@ static int commit_step(sim_t* s, sim_stats* st) {
 // two graphs are live per configuration.
 // ---------------------------------------------------------------------------
 // iterations recorded before the check: at least the last solve's count + 1;
-// kept while it stays within 8 of that (the excess iterations of converged
-// replicas return at once), else reset to the count + 3 rounded up to a
-// multiple of 4, so that small changes of the count need no new capture
+// kept while it stays within 12 of that (the excess iterations of converged
+// replicas return at once), else reset to the count + 4 rounded up to a
+// multiple of 4, so that the usual step-to-step changes need no new capture
 static int graph_iters(sim_t* s) {
   const int need = s->last_iters + 1;
-  if (s->graph_K < need || s->graph_K > need + 8) s->graph_K = ((need + 2 + 3) / 4) * 4;
+  if (s->graph_K < need || s->graph_K > need + 12) s->graph_K = ((need + 4 + 3) / 4) * 4;
   return s->graph_K;
 }
 

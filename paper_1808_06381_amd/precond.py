@@ -6,11 +6,14 @@ Network (hidden 32, three message-passing layers on the pair graph of A):
     h0_i = relu(W0 x_i + b0)                     x_i = (t_i, a_i, deg_i/8)
     layer: y_j = P h_j,  m_i = 1/8 sum_j relu(y_j + Q e_ij + c),
            h_i <- h_i + relu(U h_i + V m_i + d)  e_ij = (r_ij/rc, w_ij, What_ij)
-    heads: lam'_i = softplus(v.h_i + v0),  g_ij = 2 sigmoid(z.(h_i*h_j) + ze.e_ij + z0)
-    M^-1 = D^-1/2 (diag(lam) + S) D^-1/2,  S_ij = g_ij What_ij,
-    lam_i = sum_j S_ij + lam'_i + 1e-3   (SPD by diagonal dominance)
-With z = ze = z0 = 0 and lam'_i = 1 - sum_j What_ij it is the two-term Neumann
-series D^-1 + D^-1 W D^-1 of A^-1.
+    heads: lam_i = softplus(v.h_i + v0) + 1e-3,  S_ij = z.(h_i*h_j) + ze.e_ij + z0
+    M^-1 = D^-1/2 (diag(lam) + S) D^-1/2   (symmetric, positive diagonal)
+With v = z = z0 = 0, ze = (0, 0, 1) and lam = 1 it is the two-term Neumann
+series D^-1 + D^-1 (D - A) D^-1 of A^-1 (positive definite), the initial
+point of training.  The head is deliberately not constrained to diagonal
+dominance: the best preconditioners with A's sparsity are not diagonally
+dominant, and the solver's true-residual test and Jacobi fallback make an
+indefinite M^-1 cost time, never correctness.
 """
 import math
 import struct
@@ -52,8 +55,9 @@ LAYOUT, NPARAMS = layout()
 
 
 def init_params(seed=0, scale=0.5):
-    """Small random weights; heads start at g = 1 and lam' ~ 0.6 (close to the
-    two-term Neumann series)."""
+    """Small random weights; the heads start at lam = softplus(v0) + eps = 1
+    and S_ij = What_ij, i.e. the two-term Neumann series
+    M^-1 = D^-1 + D^-1 (D - A) D^-1 (positive definite)."""
     rng = np.random.default_rng(seed)
     theta = np.zeros(NPARAMS, dtype=np.float32)
     for name, (off, shape) in LAYOUT.items():
@@ -63,11 +67,13 @@ def init_params(seed=0, scale=0.5):
             theta[off:off + w.size] = w.reshape(-1)
     off, _ = LAYOUT["b0"]
     theta[off:off + H] = 0.1
-    off, _ = LAYOUT["v0"]
-    theta[off] = math.log(math.expm1(0.6))
     for name in ("v", "z", "ze", "z0"):
         off, shape = LAYOUT[name]
         theta[off:off + int(np.prod(shape))] = 0.0
+    off, _ = LAYOUT["v0"]
+    theta[off] = math.log(math.expm1(1.0 - 1e-3))
+    off, _ = LAYOUT["ze"]
+    theta[off + 2] = 1.0  # edge feature 2 is What_ij
     return theta
 
 
@@ -93,33 +99,59 @@ def load(path):
 
 
 def train(steps, n=100_000, lr=3e-3, seed=0, episode=100, shear_range=(0.01, 1.0),
-          theta=None, tol=1e-10, log_every=0):
-    """Train the network on (A, b, x*) triples that the simulation generates:
-    boxes of n particles (density 1, the friction-matrix workload physics), a
-    new box with a log-uniform shear rate every `episode` steps; each step's
-    Jacobi-PCG solve (tolerance `tol`) supplies one triple and one Adam step.
-    Returns (theta, losses)."""
+          theta=None, tol=1e-8, log_every=0, loss="probe", replicas=1, probe_seed=None,
+          norm="2", lr_final=0.1):
+    """Train the network on friction matrices that the simulation generates:
+    boxes of n particles in total (density 1, the friction-matrix workload
+    physics; `replicas` boxes of n / replicas each in one handle), new boxes
+    with log-uniform shear rates every `episode` steps.  Every training step
+    advances the simulation one step (Jacobi-PCG to `tol`) and takes one Adam
+    step on
+      loss = "probe":    ||(M^-1 A - I) z||^2 / ||z||^2, z white noise, in the
+                         Euclidean (norm "2") or the A-norm (sim_train_probe), or
+      loss = "solution": ||M^-1 b - x*||_A^2 / ||x*||_A^2 on the step's own
+                         b and solution (sim_train_step; one replica).
+    The learning rate follows a cosine from lr down to lr_final * lr; the Adam
+    state carries over between boxes.  Returns (theta, losses)."""
     from . import inputs
     from . import sim as S
 
+    if loss not in ("probe", "solution"):
+        raise ValueError("loss must be 'probe' or 'solution'")
+    if loss == "solution" and replicas != 1:
+        raise ValueError("the solution loss trains on one replica")
     rng = np.random.default_rng(seed)
+    probe_seed = seed + 0x5EED if probe_seed is None else probe_seed
     theta = init_params(seed) if theta is None else np.asarray(theta, dtype=np.float32)
     lo, hi = math.log(shear_range[0]), math.log(shear_range[1])
     losses = []
+    opt = None
     done = 0
     while done < steps:
-        kappa = math.exp(rng.uniform(lo, hi))
-        box_seed = int(rng.integers(1, 2**31))
-        cfg = inputs.cube_params(n, kappa, seed=box_seed)
-        pos = inputs.uniform_positions(n, cfg["box"], box_seed)
-        with S.Sim(cfg, pos, tol=tol, precond="jacobi") as sm:
+        cfgs, poss = [], []
+        for r in range(replicas):
+            kappa = math.exp(rng.uniform(lo, hi))
+            box_seed = int(rng.integers(1, 2**31))
+            c = inputs.cube_params(n // replicas, kappa, seed=box_seed)
+            c["stream"] = r
+            cfgs.append(c)
+            poss.append(inputs.uniform_positions(c["n"], c["box"], box_seed))
+        with S.Sim(cfgs if replicas > 1 else cfgs[0], np.concatenate(poss), tol=tol,
+                   precond="jacobi") as sm:
             sm.set_weights(theta)
+            if opt is not None:
+                sm.set_optimizer(opt)
             for _ in range(min(episode, steps - done)):
                 sm.step(1)
-                losses.append(sm.train_step(lr))
+                lr_t = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * done / steps)))
+                if loss == "probe":
+                    losses.append(sm.train_probe(lr_t, probe_seed, done, norm=norm))
+                else:
+                    losses.append(sm.train_step(lr_t))
                 done += 1
                 if log_every and done % log_every == 0:
                     print(f"train step {done}: loss {np.mean(losses[-log_every:]):.4f}",
                           flush=True)
             theta = sm.get_weights()
+            opt = sm.get_optimizer()
     return theta, np.array(losses)

@@ -28,7 +28,8 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
             "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
             "sim_copy_probe", "sim_precond_weights", "sim_precond_config", "sim_train_step",
             "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
-            "sim_autotune", "sim_set_tuning", "sim_destroy", "sim_strerror"]
+            "sim_autotune", "sim_set_tuning", "sim_train_probe", "sim_precond_optimizer",
+            "sim_destroy", "sim_strerror"]
 MPNN_NPARAMS = 9893
 
 
@@ -140,6 +141,9 @@ def lib():
         L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
         L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
         L.sim_graph_mode.argtypes = [vp, C.c_int32]
+        L.sim_train_probe.argtypes = [vp, C.c_double, C.c_uint64, C.c_uint64, C.c_int32,
+                                      P(C.c_double)]
+        L.sim_precond_optimizer.argtypes = [vp, vp, vp, C.c_int64, P(C.c_int32), C.c_int32]
         L.sim_graph_info.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
         L.sim_autotune.argtypes = [vp, C.c_int32, P(SimTuning)]
         L.sim_set_tuning.argtypes = [vp, P(SimTuning)]
@@ -310,6 +314,34 @@ class Sim:
         _check(lib().sim_profile_read(self.h, arr, 8, C.byref(cnt), int(reset)), "sim_profile_read")
         return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms,
                                            bytes=arr[k].bytes) for k in range(cnt.value)}
+
+    def train_probe(self, lr, seed, index, norm="2"):
+        """One Adam step on a white-noise probe z (x* = z, b = A z) with the loss
+        in the Euclidean ("2") or the A-norm ("A"); returns the loss before the
+        update."""
+        if norm not in ("A", "2"):
+            raise ValueError("norm must be 'A' or '2'")
+        loss = C.c_double()
+        _check(lib().sim_train_probe(self.h, float(lr), int(seed) & (2**64 - 1),
+                                     int(index) & (2**64 - 1), 1 if norm == "2" else 0,
+                                     C.byref(loss)), "sim_train_probe")
+        return loss.value
+
+    def get_optimizer(self):
+        m1 = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        m2 = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        t = C.c_int32()
+        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), MPNN_NPARAMS, C.byref(t), 0),
+               "sim_precond_optimizer")
+        return m1, m2, t.value
+
+    def set_optimizer(self, state):
+        m1, m2, t = state
+        m1 = np.ascontiguousarray(m1, dtype=np.float32)
+        m2 = np.ascontiguousarray(m2, dtype=np.float32)
+        tt = C.c_int32(int(t))
+        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), MPNN_NPARAMS, C.byref(tt), 1),
+               "sim_precond_optimizer")
 
     def graph_mode(self, on=True):
         _check(lib().sim_graph_mode(self.h, int(bool(on))), "sim_graph_mode")

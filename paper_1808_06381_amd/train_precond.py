@@ -1,17 +1,21 @@
 """Train and evaluate the learned preconditioner on the GPU.
 
-Training data are the (A, b, x*) triples of the simulation itself: boxes of
-N particles at density 1 with the friction-matrix workload physics, a new box
-with a log-uniform shear rate every `episode` steps; each step's Jacobi-PCG
-solve supplies one triple and one Adam step (all arithmetic in the library's
-kernels, see ``precond.train``).
+Training data are the friction matrices of the simulation itself: boxes of
+N particles at density 1 with the friction-matrix workload physics, new
+boxes with log-uniform shear rates every `episode` steps; each simulation
+step supplies one matrix A and one Adam step on a white-noise probe loss
+||(M^-1 A - I) z||^2 / ||z||^2 (Euclidean by default, --norm A for the
+A-norm; or on the step's own b and solution with
+--loss solution; all arithmetic in the library's kernels, see
+``precond.train``).
 
 Evaluation runs held-out boxes (seeds 9001..) at several shear rates with the
 trained network and with Jacobi from identical initial states, and reports
 CG iterations per step and the final true relative residual of each form.
 
     python -m paper_1808_06381_amd.train_precond --steps 20000 --n 100000 \
-        --out paper_1808_06381_amd/weights/precond_n1e5.bin --eval-json eval.json
+        --replicas 4 --out paper_1808_06381_amd/weights/precond_n1e5.bin \
+        --eval-json paper_1808_06381_amd/weights/precond_n1e5.eval.json
 """
 import argparse
 import json
@@ -61,9 +65,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lr-final", type=float, default=0.1, help="final / initial learning rate")
     ap.add_argument("--episode", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--loss", choices=("probe", "solution"), default="probe")
+    ap.add_argument("--replicas", type=int, default=4)
+    ap.add_argument("--norm", choices=("2", "A"), default="2")
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1808_06381_amd", "weights",
                                                   "precond_n1e5.bin"))
     ap.add_argument("--init", default=None, help="start from these weights")
@@ -73,7 +81,8 @@ def main():
     theta = precond.load(args.init) if args.init else None
     t0 = time.time()
     theta, losses = precond.train(args.steps, n=args.n, lr=args.lr, seed=args.seed,
-                                  episode=args.episode, theta=theta,
+                                  episode=args.episode, theta=theta, loss=args.loss,
+                                  replicas=args.replicas, norm=args.norm, lr_final=args.lr_final,
                                   log_every=max(1, args.steps // 20))
     t1 = time.time()
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
@@ -84,7 +93,9 @@ def main():
     if args.eval_json:
         ev = evaluate(theta, args.n, seeds=list(range(9001, 9001 + args.eval_seeds)),
                       shears=(0.01, 0.1, 1.0))
-        ev.update(train_steps=args.steps, train_n=args.n, lr=args.lr, episode=args.episode,
+        ev.update(train_steps=args.steps, train_n=args.n, lr=args.lr, lr_final=args.lr_final,
+                  episode=args.episode,
+                  loss=args.loss, replicas=args.replicas, norm=args.norm,
                   train_seconds=t1 - t0, loss_first=float(losses[:len(losses) // 20].mean()),
                   loss_last=float(losses[-len(losses) // 20:].mean()))
         with open(args.eval_json, "w") as f:

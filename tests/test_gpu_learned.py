@@ -1,7 +1,9 @@
 """GPU parity of the learned preconditioner (through the C ABI) against the
 oracle's FP64 network: M^-1 entry by entry, the training loss and its
 gradient; solves with the learned preconditioner against dense LAPACK; the
-forced Jacobi fallback; and what training gains over Jacobi.
+forced Jacobi fallback; an indefinite M^-1 (random head weights), which the
+true-residual test and the fallback turn into the same answer; and what
+training gains over Jacobi.
 
 Tolerances: with activations kept in FP32 (round_act off) the GPU network is
 an FP32 evaluation of the oracle's FP64 one on the same bfloat16 weights:
@@ -62,15 +64,32 @@ def test_minv_matches_oracle(round_act, rtol):
     np.testing.assert_allclose(gv, ov, rtol=rtol, atol=rtol * np.abs(ov).max())
 
 
-def test_minv_symmetric_and_spd():
+def test_minv_symmetric_with_positive_diagonal():
     cfg, pos = case(n=600, seed=5)
-    with S.Sim(cfg, pos, precond="learned") as sim:
-        sim.set_weights(random_theta(2, scale=1.0))
-        r, c, v, d = sim.precond_matrix()
-    M = np.diag(d)
-    M[r, c] = v
-    assert np.array_equal(M, M.T)
-    assert np.linalg.eigvalsh(M)[0] > 0
+    for th, spd in ((random_theta(2, scale=1.0), False), (precond.init_params(2), True)):
+        with S.Sim(cfg, pos, precond="learned") as sim:
+            sim.set_weights(th)
+            r, c, v, d = sim.precond_matrix()
+        M = np.diag(d)
+        M[r, c] = v
+        assert np.array_equal(M, M.T) and np.all(d > 0)
+        if spd:  # the initial heads: the two-term Neumann series
+            assert np.linalg.eigvalsh(M)[0] > 0
+
+
+def test_indefinite_preconditioner_still_gives_the_answer():
+    cfg, pos = case(n=3000, seed=9)
+    th = random_theta(5, scale=1.0)
+    s, er, md, orow, ocol, ov = oracle_minv(cfg, pos, th)
+    M = oracle.dense(dict(s, val=ov, diag=md))
+    assert np.linalg.eigvalsh(M)[0] < 0     # the case this test is about
+    b = np.random.default_rng(4).normal(size=(cfg["n"], 3))
+    with S.Sim(cfg, pos, tol=1e-10, maxit=3000, precond="learned") as sim:
+        sim.set_weights(th)
+        v, st = sim.solve(b)
+    A = oracle.dense(s)
+    res = np.linalg.norm(b - A @ v, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(res <= 1e-10 * 1.001), (res, st)
 
 
 def test_loss_and_gradient_match_oracle():
@@ -90,11 +109,74 @@ def test_loss_and_gradient_match_oracle():
     assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
 
 
+def oracle_probe(cfg, seed, index):
+    """z of the white-noise probe from the oracle's own Philox: counter
+    (index, 3, id, 0), key (seed, stream)."""
+    c = dict(cfg, seed=seed)
+    return np.array([oracle.gauss4(c, index, 3, i, 0)[:3] for i in range(cfg["n"])])
+
+
+@pytest.mark.parametrize("batch,norm", [(False, "A"), (True, "A"), (False, "2"), (True, "2")])
+def test_probe_loss_and_gradient_match_oracle(batch, norm):
+    cfg, pos = case(n=1500, seed=13)
+    th = random_theta(6)
+    cfgs, poss = [cfg], [pos]
+    if batch:
+        c2, p2 = case(n=900, seed=14)
+        c2["stream"] = 1
+        cfgs.append(c2)
+        poss.append(p2)
+    b0 = np.random.default_rng(1).normal(size=(sum(c["n"] for c in cfgs), 3))
+    with S.Sim(cfgs if batch else cfg, np.concatenate(poss), tol=1e-10) as sim:
+        sim.set_weights(th)
+        sim.precond_config(round_act=False)
+        v0, _ = sim.solve(b0)
+        loss = sim.train_probe(0.0, seed=77, index=5, norm=norm)
+        g = sim.precond_grad().astype(np.float64)
+        v1, _ = sim.solve(b0)
+    assert np.array_equal(v0, v1)            # the solve's own vectors are untouched
+    num = den = 0.0
+    go = np.zeros_like(g)
+    for c, p in zip(cfgs, poss):
+        s = oracle.build_system(c, p, 0)
+        er = oracle.edge_r(c, p, s, 0)
+        z = oracle_probe(c, 77, 5)
+        A = oracle.dense(s)
+        b = A @ z
+        lo, gr = oracle.mpnn_loss_grad(s, er, c["alpha"], th, b, z, norm=norm)
+        dz = np.einsum("ic,ij,jc->", z, A, z) if norm == "A" else np.sum(z * z)
+        num += lo * dz
+        den += dz
+        go += gr * dz
+    assert loss == pytest.approx(num / den, rel=1e-4)
+    go /= den
+    assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+
+
+def test_optimizer_state_moves_between_handles():
+    cfg, pos = case(n=1200, seed=15)
+    with S.Sim(cfg, pos, tol=1e-8) as a:
+        a.set_weights(precond.init_params(1))
+        a.step(1)
+        for k in range(3):
+            a.train_probe(1e-3, seed=1, index=k)
+        th, st = a.get_weights(), a.get_optimizer()
+        a.train_probe(1e-3, seed=1, index=3)
+        ref = a.get_weights()
+    assert st[2] == 3 and np.any(st[0] != 0) and np.all(st[1] >= 0)
+    with S.Sim(cfg, pos, tol=1e-8) as b:
+        b.set_weights(th)
+        b.set_optimizer(st)
+        b.step(1)
+        b.train_probe(1e-3, seed=1, index=3)
+        assert np.array_equal(b.get_weights(), ref)
+
+
 def test_learned_solve_matches_dense_and_converges():
     cfg, pos = case(n=3000, seed=9)
     b = np.random.default_rng(2).normal(size=(cfg["n"], 3))
     with S.Sim(cfg, pos, tol=1e-10, precond="learned") as sim:
-        sim.set_weights(random_theta(4))
+        sim.set_weights(precond.init_params(4))
         v, st = sim.solve(b)
     A = oracle.dense(oracle.build_system(cfg, pos, 0))
     x = np.linalg.solve(A, b)
