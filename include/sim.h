@@ -81,9 +81,14 @@ enum sim_precond { SIM_PC_JACOBI = 0, SIM_PC_NONE = 1, SIM_PC_IC0 = 2, SIM_PC_LE
  *              (Eq. 6a); SIM_NOISE_OFF.  Gaussians come from Philox4x64-10
  *              keyed (seed, stream) with counter (step, 0, id, 0) for xi and
  *              (step, 1, min id, max id) for eta, via Box-Muller.
- *  precond     CG preconditioner: SIM_PC_JACOBI (u = D^-1 r), SIM_PC_NONE,
- *              SIM_PC_LEARNED (see below; needs alpha > 0 and the same
- *              choice for every replica); SIM_PC_IC0 returns SIM_ENOTSUP
+ *  precond     CG preconditioner, the same for every replica:
+ *              SIM_PC_JACOBI (u = D^-1 r), SIM_PC_NONE (u = r),
+ *              SIM_PC_IC0 (incomplete Cholesky with A's lower pattern in
+ *              multicolour order: cells coloured by the parity of their
+ *              coordinates -- a third colour for the last cell of an odd
+ *              axis -- rows ordered by (colour, cell, particle id); exact
+ *              IC(0) of that ordering, Meijerink & van der Vorst 1977),
+ *              SIM_PC_LEARNED (see below; needs alpha > 0)
  *  spmv_fp32   0: FP64 matrix values; 1: FP32 matrix values in the CG
  *              matrix products with FP64 vectors, dots and true-residual
  *              recompute (agreement with FP64 about 1e-5 relative)
@@ -260,8 +265,12 @@ int sim_precond_optimizer(sim_t* sim, float* m1, float* m2, int64_t count, int32
 /* The gradient dL/dtheta of the last sim_train_step (with respect to the
  * bfloat16 weights), count = SIM_MPNN_NPARAMS.                           */
 int sim_precond_grad(sim_t* sim, float* grad, int64_t count);
-/* Parity export of the learned M^-1 of the current positions and step, in
- * the form of sim_debug_system (off-diagonal triples, diagonal).          */
+/* Parity export of the preconditioner of the current positions and step.
+ * Learned: M^-1 in the form of sim_debug_system (off-diagonal triples,
+ * diagonal).  IC(0): the strictly lower triangle of L (in the IC order) as
+ * (row, col, L_row,col) triples at the positions of A's off-diagonal
+ * entries, row = col = -1 in the slots of upper entries, and L's diagonal.
+ * SIM_ENOTSUP for Jacobi and no preconditioner.                           */
 int sim_debug_precond(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
                       int64_t* count, double* mdiag);
 

@@ -82,6 +82,8 @@ def lib():
         L.orc_pcg.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, d_p, C.c_double, C.c_int,
                               C.c_int, i64_p, i64_p, d_p, d_p, P(C.c_int), d_p]
         L.orc_pcg.restype = C.c_int
+        L.orc_ic0.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, C.c_int64, i64_p, i64_p, d_p]
+        L.orc_ic0.restype = C.c_int64
         L.orc_step.argtypes = [pp, C.c_int64, d_p, d_p, C.c_double, C.c_int, C.c_int, P(C.c_int)]
         L.orc_step.restype = C.c_int
         L.orc_wrap.argtypes = [pp, C.c_int64, d_p]
@@ -245,6 +247,21 @@ def pcg(sys_, rhs=None, tol=1e-10, maxit=10000, precond="jacobi", x0=None, m=Non
     if st != 0:
         raise RuntimeError("oracle pcg: " + STATUS.get(st, str(st)))
     return x, list(iters), rel
+
+
+def ic0(sys_):
+    """IC(0) factor L of A in the system's row order: (lrow, lcol, lval) CSR,
+    per row the strictly lower entries (ascending column) then L_ii."""
+    n = sys_["diag"].shape[0]
+    cap = n + len(sys_["col"]) // 2 + 1
+    lrow = np.zeros(n + 1, dtype=np.int64)
+    lcol = np.zeros(cap, dtype=np.int64)
+    lval = np.zeros(cap)
+    cnt = lib().orc_ic0(n, _ip(sys_["rowptr"]), _ip(sys_["col"]), _dp(sys_["val"]),
+                        _dp(sys_["diag"]), cap, _ip(lrow), _ip(lcol), _dp(lval))
+    if cnt < 0 or cnt > cap:
+        raise RuntimeError("oracle ic0: " + STATUS.get(int(cnt), str(cnt)))
+    return lrow, lcol[:cnt], lval[:cnt]
 
 
 def step(cfg, pos, step_index, tol=1e-10, maxit=10000, precond="jacobi"):

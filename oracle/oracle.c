@@ -449,6 +449,28 @@ static int orc_ic0_factor(orc_precond* pc, int64_t n, const int64_t* rowptr,
   return ORC_OK;
 }
 
+/* The IC(0) factor of A in the given row order: lrow[n+1], per row the
+ * strictly lower entries in ascending column then the diagonal; lcol/lval
+ * hold at most nnz_lower + n entries (cap).  Returns the entry count, or a
+ * negative ORC_ status.                                                    */
+int64_t orc_ic0(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                const double* diag, int64_t cap, int64_t* lrow, int64_t* lcol, double* lval) {
+  orc_precond pc;
+  memset(&pc, 0, sizeof(pc));
+  pc.n = n;
+  const int st = orc_ic0_factor(&pc, n, rowptr, col, val, diag);
+  int64_t cnt = st == ORC_OK ? pc.lrow[n] : st;
+  if (st == ORC_OK && cnt <= cap) {
+    memcpy(lrow, pc.lrow, sizeof(int64_t) * (size_t)(n + 1));
+    memcpy(lcol, pc.lcol, sizeof(int64_t) * (size_t)cnt);
+    memcpy(lval, pc.lval, sizeof(double) * (size_t)cnt);
+  }
+  free(pc.lrow);
+  free(pc.lcol);
+  free(pc.lval);
+  return cnt;
+}
+
 /* z = M^{-1} r for one component c of n x 3 arrays */
 static void orc_apply_precond(const orc_precond* pc, const double* r, double* z, int c) {
   const int64_t n = pc->n;

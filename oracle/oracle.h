@@ -82,6 +82,9 @@ int orc_pcg(int64_t n, const int64_t* rowptr, const int64_t* col,
             const int64_t* mrowptr, const int64_t* mcol, const double* mval,
             const double* mdiag, int iters[3], double relres[3]);
 
+int64_t orc_ic0(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
+                const double* diag, int64_t cap, int64_t* lrow, int64_t* lcol, double* lval);
+
 /* ---- time step ------------------------------------------------------------- */
 int orc_step(const orc_params* p, int64_t step, double* pos, double* vel,
              double tol, int maxit, int precond, int iters[3]);

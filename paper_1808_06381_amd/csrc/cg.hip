@@ -124,13 +124,14 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   }
   double v[6] = {0, 0, 0, 0, 0, 0};  // (r,u)[3], (r,r)[3]
   const int64_t base = (int64_t)tile * VEC_ELEMS;
+  const bool ext = d.learned || d.ic0;  // u = M^-1 r comes from a separate pass
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int le = q * BLOCK_THREADS + threadIdx.x;
     const int k = le % 3;
     if (!on[k]) continue;
     const int64_t e = base + le;
-    const double di = d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
+    const double di = d.pc_none ? 1.0 : d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
     double rk;
     if (mode == 0) {
       rk = d.b[e];
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
       d.s[e] = 0.0;
     } else {
       const double r0 = d.r[e];
-      const double uk0 = d.learned ? d.u[e] : di * r0;
+      const double uk0 = ext ? d.u[e] : di * r0;
       const double pk = uk0 + be[k] * d.p[e];
       const double sk = d.w[e] + be[k] * d.s[e];
       d.p[e] = pk;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
       rk = r0 - al[k] * sk;
       d.r[e] = rk;
     }
-    if (!d.learned) {
+    if (!ext) {
       const double uk = di * rk;
       d.u[e] = uk;
       v[k] += rk * uk;
@@ -161,11 +162,37 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
     v[3 + k] += rk * rk;
   }
   double g[3] = {v[0], v[1], v[2]}, rr[3] = {v[3], v[4], v[5]};
-  if (!d.learned) {
+  if (!ext) {
     write_partials<3>(d, tile, 0, g);
     __syncthreads();
   }
   write_partials<3>(d, tile, 6, rr);
+}
+
+// Partials (r, u) per tile after an external preconditioner pass (IC(0)),
+// component selection as k_cg_vec's mode.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const CgRep& cr = d.cg[d.blk_rep[tile]];
+  if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
+  bool on[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
+  double v[3] = {0, 0, 0};
+  const int64_t base = (int64_t)tile * VEC_ELEMS;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int le = q * BLOCK_THREADS + threadIdx.x;
+    const int k = le % 3;
+    if (!on_k(on, k)) continue;
+    const double add = d.r[base + le] * d.u[base + le];
+    v[0] += k == 0 ? add : 0.0;
+    v[1] += k == 1 ? add : 0.0;
+    v[2] += k == 2 ? add : 0.0;
+  }
+  write_partials<3>(d, tile, 0, v);
 }
 
 // Learned preconditioner: u = M^-1 r with M^-1 in A's pattern (a group of
@@ -436,6 +463,11 @@ hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_
 #undef SPMV_CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dot_ru(const DevPtrs& d, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dot_ru, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, mode);
   return hipGetLastError();
 }
 

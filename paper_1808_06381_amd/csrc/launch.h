@@ -33,6 +33,11 @@ hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s);
 hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);
+hipError_t launch_cg_dot_ru(const DevPtrs& d, int mode, hipStream_t s);
+hipError_t launch_ic_factor(const DevPtrs& d, const int32_t* color_off, int ncolors, hipStream_t s);
+hipError_t launch_ic_apply(const DevPtrs& d, const int32_t* color_off, int ncolors, hipStream_t s);
+hipError_t launch_ic_export(const DevPtrs& d, const int64_t* id_off, int64_t* rows, int64_t* cols,
+                            double* vals, double* diag, hipStream_t s);
 struct MpPtrs;
 hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
 hipError_t launch_mp_loss(const DevPtrs& d, const MpPtrs& m, hipStream_t s);

@@ -93,6 +93,9 @@ struct sim_t {
   std::vector<StepGraph> graphs;
   int64_t graph_captures = 0, graph_replays = 0;
   int32_t graph_K = 0;
+  // IC(0) preconditioner
+  bool ic0 = false;
+  std::vector<int32_t> ic_color_off;  // offsets of the colours in d.ic_cells (host copy)
   sim_tuning tune{};
 };
 
@@ -147,7 +150,6 @@ static int validate(const sim_params& p) {
   if (p.warm_start != 0) return SIM_EINVAL;
   if (p.spmv_fp32 != 0 && p.spmv_fp32 != 1) return SIM_EINVAL;
   if (p.precond == SIM_PC_LEARNED && !(p.alpha > 0.0)) return SIM_EINVAL;
-  if (p.precond == SIM_PC_IC0) return SIM_ENOTSUP;
   return SIM_OK;
 }
 
@@ -205,6 +207,10 @@ static int alloc_csr(sim_t* s, int64_t cap) {
   dfree(s, s->d.val);
   dfree(s, s->d.valf);
   dfree(s, s->d.er);
+  dfree(s, s->d.lcol);
+  dfree(s, s->d.lval);
+  s->d.lcol = nullptr;
+  s->d.lval = nullptr;
   s->d.col = nullptr;
   s->d.val = nullptr;
   s->d.valf = nullptr;
@@ -215,6 +221,11 @@ static int alloc_csr(sim_t* s, int64_t cap) {
   if ((rc = dalloc(s, (void**)&s->d.val, sizeof(double) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.valf, sizeof(float) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.er, sizeof(float) * (size_t)cap))) return rc;
+  if (s->ic0) {
+    if ((rc = dalloc(s, (void**)&s->d.lcol, sizeof(int32_t) * (size_t)cap))) return rc;
+    if ((rc = dalloc(s, (void**)&s->d.lval, sizeof(double) * (size_t)cap))) return rc;
+    HIPCHK(hipMemset(s->d.lcol, 0, sizeof(int32_t) * (size_t)cap));
+  }
   s->d.nnz_cap = cap;
   return SIM_OK;
 }
@@ -341,12 +352,44 @@ static int cg_maxit(const sim_t* s) {
   return maxit;
 }
 
+// u = M^-1 r by the learned product or the IC(0) triangular solves (with
+// the (r, u) partials), for the components selected by mode
+static int queue_apply(sim_t* s, int mode, hipEvent_t e0, hipEvent_t e1) {
+  const DevPtrs& d = s->d;
+  if (d.ic0) {
+    HIPCHK(launch_ic_apply(d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1, s->stream));
+    HIPCHK(launch_cg_dot_ru(d, mode, s->stream));
+  } else {
+    HIPCHK(launch_cg_apply(d, mode, s->stream, e0, e1));
+  }
+  return SIM_OK;
+}
+
+// the preconditioner of the system just built: learned forward pass or
+// IC(0) factorisation
+static int prepare_precond(sim_t* s) {
+  if (s->learned) {
+    int rc = ensure_mp(s, false);
+    if (rc) return rc;
+    s->mp.store_train = 0;
+    HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+    s->d.learned = 1;
+  }
+  if (s->ic0)
+    HIPCHK(launch_ic_factor(s->d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1,
+                            s->stream));
+  return SIM_OK;
+}
+
 // tol > 0 overrides the replicas' own tolerances
 static int cg_queue_start(sim_t* s, double tol) {
   const DevPtrs& d = s->d;
   HIPCHK(launch_cg_reset(d, tol, s->stream));
   HIPCHK(launch_cg_vec(d, 0, s->stream));
-  if (d.learned) HIPCHK(launch_cg_apply(d, 0, s->stream));
+  if (d.learned || d.ic0) {
+    int rc = queue_apply(s, 0, nullptr, nullptr);
+    if (rc) return rc;
+  }
   HIPCHK(launch_cg_spmv(d, 0, 0, s->stream));
   HIPCHK(launch_cg_finish(d, 0, s->stream));
   return SIM_OK;
@@ -358,7 +401,7 @@ static int cg_queue_start(sim_t* s, double tol) {
 static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
   const DevPtrs& d = s->d;
   hipStream_t stream = s->stream;
-  const bool learned = d.learned != 0;
+  const bool ext = d.learned || d.ic0;  // a separate preconditioner pass
   for (int k = 0; k < n; ++k) {
     const int g = first + k;
     const bool probe = probes && s->prof_every > 0 && g % s->prof_every == 0 &&
@@ -367,9 +410,9 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
     const int order[3] = {0, 2, 1};
     for (int oi = 0; oi < 3; ++oi) {
       const int kern = order[oi];
-      if (kern == 2 && !learned) continue;
+      if (kern == 2 && !ext) continue;
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (probe) {
+      if (probe && !(kern == 2 && d.ic0)) {  // the IC(0) pass is many launches: not probed
         const int ev = (int)s->prof_pending.size();
         s->prof_pending.push_back({kern, g, ev, 0.0f});
         e0 = s->prof_ev[2 * ev];
@@ -377,14 +420,20 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
       }
       if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
       else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
-      else HIPCHK(launch_cg_apply(d, 2, stream, e0, e1));
+      else {
+        int rc = queue_apply(s, 2, e0, e1);
+        if (rc) return rc;
+      }
     }
     HIPCHK(launch_cg_finish(d, 2, stream));
   }
   HIPCHK(launch_cg_spmv(d, 1, 0, stream));
   HIPCHK(launch_cg_finish(d, 3, stream));
   HIPCHK(launch_cg_vec(d, 1, stream));
-  if (learned) HIPCHK(launch_cg_apply(d, 1, stream));
+  if (ext) {
+    int rc = queue_apply(s, 1, nullptr, nullptr);
+    if (rc) return rc;
+  }
   HIPCHK(launch_cg_spmv(d, 0, 1, stream));
   HIPCHK(launch_cg_finish(d, 1, stream));
   return SIM_OK;
@@ -505,12 +554,7 @@ static int build_and_solve(sim_t* s, bool replace_rhs, double tol, sim_stats* st
   int rc = build_system(s);
   if (rc) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    if (s->learned) {
-      if ((rc = ensure_mp(s, false))) return rc;
-      s->mp.store_train = 0;
-      HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
-      s->d.learned = 1;
-    }
+    if ((rc = prepare_precond(s))) return rc;
     if (replace_rhs) HIPCHK(launch_permute(s->d, s->id_off_d, 1, s->io, nullptr, s->stream));
     rc = cg_solve(s, tol, st);
     if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
@@ -590,8 +634,13 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   s->R = replicas;
   s->prm.assign(params, params + replicas);
   s->learned = params[0].precond == SIM_PC_LEARNED;
+  s->ic0 = params[0].precond == SIM_PC_IC0;
   for (int r = 1; r < replicas; ++r)
-    if ((params[r].precond == SIM_PC_LEARNED) != s->learned) { delete s; return SIM_EINVAL; }
+    if ((params[r].precond == SIM_PC_LEARNED) != s->learned ||
+        (params[r].precond == SIM_PC_IC0) != s->ic0) {
+      delete s;
+      return SIM_EINVAL;
+    }
   // layout
   int64_t row_off = 0, seg_off = 0, n_total = 0;
   int32_t blk_off = 0;
@@ -642,6 +691,10 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.spmv_fp32 = params[0].spmv_fp32;
   d.spmv_lanes = 4;
   d.apply_lanes = 4;
+  d.ic0 = s->ic0 ? 1 : 0;
+  d.pc_none = params[0].precond == SIM_PC_NONE ? 1 : 0;
+  for (int r = 1; r < replicas; ++r)
+    if ((params[r].precond == SIM_PC_NONE) != (d.pc_none != 0)) { sim_destroy(s); return SIM_EINVAL; }
   s->tune.spmv_lanes = 4;
   s->tune.apply_lanes = 4;
   const size_t rows = (size_t)s->rows;
@@ -682,6 +735,36 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   ALLOC(d.vel_orig, sizeof(double) * 3 * (size_t)n_total);
   ALLOC(s->io, sizeof(double) * 3 * (size_t)n_total);
   ALLOC(s->id_off_d, sizeof(int64_t) * replicas);
+  std::vector<int32_t> ccolor_h, iccells_h;
+  if (s->ic0) {
+    // IC(0) colours: per axis the parity of the cell coordinate, 2 for the
+    // last cell of an odd axis (its neighbours on both sides have 0 and 1)
+    auto axc = [](int c, int nc) { return (nc > 1 && (nc & 1) && c == nc - 1) ? 2 : (c & 1); };
+    ccolor_h.assign((size_t)d.ncell_entries, -1);
+    std::vector<std::vector<int32_t>> by_color(27);
+    for (int r = 0; r < replicas; ++r) {
+      const RepDev& R = s->reph[r];
+      const int nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+      for (int c = 0; c < nx * ny * nz; ++c) {
+        const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+        const int col = axc(cx, nx) + 3 * (axc(cy, ny) + 3 * axc(cz, nz));
+        ccolor_h[(size_t)(R.seg_off + c)] = col;
+        by_color[col].push_back(R.seg_off + c);
+      }
+    }
+    s->ic_color_off.assign(1, 0);
+    for (auto& v : by_color) {
+      iccells_h.insert(iccells_h.end(), v.begin(), v.end());
+      s->ic_color_off.push_back((int32_t)iccells_h.size());
+    }
+    int32_t *cc = nullptr, *ic = nullptr;
+    ALLOC(cc, sizeof(int32_t) * ccolor_h.size());
+    ALLOC(ic, sizeof(int32_t) * std::max<size_t>(iccells_h.size(), 1));
+    d.cell_color = cc;
+    d.ic_cells = ic;
+    ALLOC(d.ldiag, sizeof(double) * rows);
+    ALLOC(d.lnlow, sizeof(int32_t) * rows);
+  }
   ALLOC(s->counter_d, sizeof(unsigned long long));
   {
     const int64_t m = std::max<int64_t>(s->rows + 1, d.ncell_entries);
@@ -720,6 +803,22 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   if ((e = hipMemset(d.rowlen, 0, sizeof(int32_t) * (rows + 1)))) return fail(e, "clear rowlen");
   if ((e = hipMemset(d.rowptr, 0, sizeof(int32_t) * (rows + 1)))) return fail(e, "clear rowptr");
   if ((e = hipMemset(d.x, 0, sizeof(double) * 3 * rows))) return fail(e, "clear x");
+  // padding rows never receive a cell: keep their cell index a valid entry
+  if ((e = hipMemset(d.cellidx, 0, sizeof(int32_t) * rows))) return fail(e, "clear cells");
+  if ((e = hipMemset(d.cellidx_alt, 0, sizeof(int32_t) * rows))) return fail(e, "clear cells");
+  // padding rows keep u = 0 (the IC(0) and learned passes write real rows only)
+  if ((e = hipMemset(d.u, 0, sizeof(double) * 3 * rows))) return fail(e, "clear u");
+  if (s->ic0) {
+    if ((e = hipMemcpy((void*)d.cell_color, ccolor_h.data(), sizeof(int32_t) * ccolor_h.size(),
+                       hipMemcpyHostToDevice)))
+      return fail(e, "upload cell colours");
+    if (!iccells_h.empty() &&
+        (e = hipMemcpy((void*)d.ic_cells, iccells_h.data(), sizeof(int32_t) * iccells_h.size(),
+                       hipMemcpyHostToDevice)))
+      return fail(e, "upload colour lists");
+    if ((e = hipMemset(d.lnlow, 0, sizeof(int32_t) * rows))) return fail(e, "clear L");
+    if ((e = hipMemset(d.ldiag, 0, sizeof(double) * rows))) return fail(e, "clear L");
+  }
   if ((e = hipMemset(d.vel_orig, 0, sizeof(double) * 3 * n_total))) return fail(e, "clear vel");
   if ((e = hipMemset(d.ctrl, 0, sizeof(Ctrl)))) return fail(e, "clear ctrl");
   if ((e = hipMemset(d.step_d, 0, sizeof(int64_t)))) return fail(e, "clear step");
@@ -960,11 +1059,17 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   if (!s || !count || cap < 0) return SIM_EINVAL;
   if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  if (!s->learned && !s->ic0) return SIM_ENOTSUP;
   int rc = build_checked(s);
   if (rc) return rc;
-  if ((rc = ensure_mp(s, false))) return rc;
-  s->mp.store_train = 0;
-  HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  if (s->learned) {
+    if ((rc = ensure_mp(s, false))) return rc;
+    s->mp.store_train = 0;
+    HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  } else {
+    HIPCHK(launch_ic_factor(s->d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1,
+                            s->stream));
+  }
   const int64_t nnz = s->ctrl_h->nnz;
   *count = nnz;
   if (nnz > cap) return SIM_ECAPACITY;
@@ -975,7 +1080,10 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   if ((rc = dalloc(s, (void**)&c_d, sizeof(int64_t) * m))) return rc;
   if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * m))) return rc;
   if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * (size_t)s->n_total))) return rc;
-  HIPCHK(launch_mp_export(s->d, s->mp, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, s->stream));
+  if (s->learned)
+    HIPCHK(launch_mp_export(s->d, s->mp, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, s->stream));
+  else
+    HIPCHK(launch_ic_export(s->d, s->id_off_d, r_d, c_d, v_d, dg_d, s->stream));
   if (nnz > 0) {
     HIPCHK(hipMemcpyAsync(rows, r_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(cols, c_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
@@ -1032,6 +1140,9 @@ static int queue_graph_step(sim_t* s, int K) {
   int rc = build_system(s);
   if (rc) return rc;
   if (s->learned) HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+  if (s->ic0)
+    HIPCHK(launch_ic_factor(s->d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1,
+                            s->stream));
   if ((rc = cg_queue_start(s, 0.0))) return rc;
   if ((rc = cg_queue_chunk(s, K, 0, false))) return rc;
   HIPCHK(launch_update(s->d, 1, s->stream));
@@ -1107,10 +1218,7 @@ static int step_graph(sim_t* s, sim_stats* st) {
     drop_graphs(s);
     for (int attempt = 0; attempt < 4 && rc == SIM_EOVERFLOW_INTERNAL; ++attempt) {
       if ((rc = grow_and_refill(s))) return rc;
-      if (s->learned) {
-        if ((rc = ensure_mp(s, false))) return rc;
-        HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
-      }
+      if ((rc = prepare_precond(s))) return rc;
       rc = cg_solve(s, 0.0, st);
       if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
         s->d.learned = 0;

@@ -111,6 +111,15 @@ struct DevPtrs {
   const float* moff;        // learned M^-1 off-diagonal (A's pattern)
   const double* inj_xi;     // injected Gaussians (testing), or null
   const double* inj_eta;
+  // IC(0) in multicolour order (precond = IC0): L in A's row pointers, per
+  // row its lower entries (ascending IC order) then its upper entries
+  // (descending IC order, holding L_ji); diagonal of L; lower-entry count
+  int32_t* lcol;
+  double* lval;
+  double* ldiag;
+  int32_t* lnlow;
+  const int32_t* ic_cells;  // cell entries grouped by colour
+  const int32_t* cell_color;// colour of every cell entry (-1 for terminal entries)
   int64_t* step_d;          // current step index n (device copy of the host's counter)
   int64_t nnz_cap;
   int64_t rows;
@@ -121,6 +130,8 @@ struct DevPtrs {
   int32_t learned;          // 1: u = M^-1 r by the learned preconditioner
   int32_t spmv_lanes;       // lanes per CSR row of the products (1, 2, 4 or 8)
   int32_t apply_lanes;
+  int32_t ic0;              // 1: u = M^-1 r by the IC(0) triangular solves
+  int32_t pc_none;          // 1: no preconditioner, u = r
   int32_t pad0;             // explicit: the host compares whole structs bytewise
 };
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");

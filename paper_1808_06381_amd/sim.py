@@ -385,7 +385,9 @@ class Sim:
         return g
 
     def precond_matrix(self):
-        """(rows, cols, vals, mdiag) of the learned M^-1 at the current positions."""
+        """(rows, cols, vals, diag) of the preconditioner at the current
+        positions: the learned M^-1, or L's strictly lower triangle and diagonal
+        for IC(0) (unused slots dropped)."""
         cnt = C.c_int64()
         rc = lib().sim_debug_precond(self.h, None, None, None, 0, C.byref(cnt), None)
         if rc not in (SIM_OK, -6):
@@ -398,7 +400,8 @@ class Sim:
         _check(lib().sim_debug_precond(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
                                        C.byref(cnt), _ptr(mdiag)), "sim_debug_precond")
         k = cnt.value
-        return rows[:k], cols[:k], vals[:k], mdiag
+        keep = rows[:k] >= 0
+        return rows[:k][keep], cols[:k][keep], vals[:k][keep], mdiag
 
     def load_precond(self, path):
         _check(lib().sim_load_precond(self.h, path.encode()), "sim_load_precond")

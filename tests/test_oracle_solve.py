@@ -98,3 +98,21 @@ def test_solid_body_limit():
         devs.append(np.max(np.abs(x - mean)) / np.max(np.abs(mean)))
     assert devs[1] < 1e-2
     assert devs[1] == pytest.approx(devs[0] / 100, rel=0.05)
+
+
+def test_ic0_factor_reproduces_a_on_its_pattern():
+    """IC(0): (L L^T)_ij = A_ij wherever A_ij != 0 (the definition), L lower
+    triangular with a positive diagonal, and fill outside the pattern."""
+    cfg = inputs.base_params(n=300, box=(6.0, 6.0, 6.0), seed=2)
+    pos = inputs.uniform_positions(300, cfg["box"], 2)
+    s = oracle.build_system(cfg, pos, 0)
+    lrow, lcol, lval = oracle.ic0(s)
+    A = oracle.dense(s)
+    L = np.zeros_like(A)
+    for i in range(cfg["n"]):
+        for q in range(lrow[i], lrow[i + 1]):
+            L[i, lcol[q]] = lval[q]
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.diag(L) > 0)
+    E = L @ L.T - A
+    assert np.abs(E[A != 0]).max() <= 1e-14 * np.abs(A).max()
+    assert np.abs(E[A == 0]).max() > 1e-3      # IC(0) is incomplete here
