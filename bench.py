@@ -53,8 +53,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-spmv", action="store_true")
-    ap.add_argument("--forms", default="plain,learned",
-                    help="comma list of CG forms to time: plain (Jacobi-PCG), learned")
+    ap.add_argument("--forms", default="plain,learned,ic0",
+                    help="comma list of CG forms to time: plain (Jacobi-PCG), learned, ic0")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1808_06381_amd", "weights",
                                                       "precond_n1e5.bin"))
     return ap.parse_args()
@@ -109,7 +109,7 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     for cfg, pos0 in zip(cfgs, pos0s):
         sim = S.Sim(cfg, pos0, tol=args.tol, maxit=5000,
                     spmv_fp32=1 if args.fp32_spmv else 0, stream=stream,
-                    precond="learned" if form == "learned" else "jacobi")
+                    precond={"plain": "jacobi"}.get(form, form))
         if form == "learned":
             sim.set_weights(theta)
         if not args.no_graph:
