@@ -61,16 +61,18 @@ def parse():
 
 
 def kernel_source_sha():
+    """Hash of the sources of the CG kernels the traffic record covers."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "cg.hip", "sim_dev.h"):
+    for f in ("cg.hip", "sim_dev.h"):
         with open(os.path.join(ROOT, "paper_1808_06381_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel, workload_key):
+def read_traffic(kernel, workload_key, form):
     """HBM traffic per launch of `kernel` from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+    if it was taken on the current kernel sources, workload and CG form
+    (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -81,7 +83,8 @@ def read_traffic(kernel, workload_key):
             continue
         k, v = line.split("=", 1)
         rec[k.strip()] = v.strip()
-    if rec.get("workload") != workload_key or rec.get("source_sha") != kernel_source_sha():
+    if (rec.get("workload") != workload_key or rec.get("form") != form or
+            rec.get("source_sha") != kernel_source_sha()):
         return None
     try:
         return float(rec[f"{kernel}.traffic_bytes_per_launch"])
@@ -217,7 +220,7 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
         kr = kernels[dom]
         wl_key = f"single_n{args.n}"
-        traffic = read_traffic(dom, wl_key) if head == "plain" else None
+        traffic = read_traffic(dom, wl_key, head)
         roofline = dict(bound="hbm", achieved=round(kr["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
                         frac=round(kr["gbs"] / PEAK_HBM_GBS, 4),
                         copy_probe_gbs=round(copy_gbs, 1),

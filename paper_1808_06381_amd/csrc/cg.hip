@@ -131,7 +131,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
     const int k = le % 3;
     if (!on[k]) continue;
     const int64_t e = base + le;
-    const double di = d.pc_none ? 1.0 : d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
+    // 1/diag only where this kernel applies Jacobi itself
+    const double di = (ext || d.pc_none) ? 1.0 : d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
     double rk;
     if (mode == 0) {
       rk = d.b[e];
