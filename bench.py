@@ -50,6 +50,11 @@ def parse():
                     help="keep the default lane widths of the CSR products")
     ap.add_argument("--batch", type=int, default=64, help="replicas of the batch workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--c5", action="store_true",
+                    help="the scale workloads instead: one N = 8e6 box (L = 200) and 16 replicas "
+                         "of N = 5e5, shear 0.5, from a pre-sheared state")
+    ap.add_argument("--c5-preshear", type=int, default=200,
+                    help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-spmv", action="store_true")
@@ -131,13 +136,15 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
         sim.profile_read(reset=True)
         sim.profile_enable(args.probe_every)
     iters, fallbacks = [], 0
+    rowstat = [None] * len(sims)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        for sim in sims:
+        for q, sim in enumerate(sims):
             st = sim.step(1)
             iters.append(max(st["iters"]))
             fallbacks += st["fallback"]
+            rowstat[q] = (st["nnz"], st["max_row"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {}
@@ -165,8 +172,67 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     tuned = [dict(spmv_lanes=t["spmv_lanes"], apply_lanes=t["apply_lanes"],
                   spmv_us=[round(u, 1) for u in t["spmv_us"]],
                   apply_us=[round(u, 1) for u in t["apply_us"]]) for t in tuning]
+    ns = [sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs]
+    rows = dict(mean_offdiag_per_row=round(sum(r[0] for r in rowstat) / sum(ns), 3),
+                max_row=max(r[1] for r in rowstat))
     return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks,
-                graphs=graphs, particles=particles, steps=steps, tuning=tuned)
+                graphs=graphs, particles=particles, steps=steps, tuning=tuned, rows=rows)
+
+
+def run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs):
+    """Scale workloads: one N = 8e6 box (L = 200) and 16 replicas of N = 5e5
+    (L = 79.37), shear 0.5, each from a state pre-sheared with plain steps;
+    every form starts from the same pre-sheared positions."""
+    import math
+    out_w = {}
+    single = inputs.single_box(shear_rate=0.5, seed=51, n=8_000_000, L=200.0)["params"]
+    batch = [dict(inputs.cube_params(500_000, 0.5, seed=60 + r), stream=r) for r in range(16)]
+    for name, cfg in (("single_n8e6", single), ("batch_16x5e5", batch)):
+        cl = cfg if isinstance(cfg, list) else [cfg]
+        pos = np.concatenate([inputs.uniform_positions(c["n"], c["box"], c["seed"]) for c in cl])
+        print(f"# c5 {name}: pre-shearing {args.c5_preshear} steps", file=sys.stderr, flush=True)
+        with S.Sim(cfg, pos, tol=args.tol, maxit=5000, stream=stream) as sim:
+            sim.graph_mode(True)
+            for k in range(args.c5_preshear):
+                sim.step(1)
+                if (k + 1) % 50 == 0:
+                    print(f"# c5 {name}: pre-shear step {k + 1}", file=sys.stderr, flush=True)
+            pos = sim.state()[0]
+        runs = {f: time_form(args, S, [cfg], [pos], f, theta, stream, torch, np, label=f"c5 {name} ")
+                for f in forms}
+        out_w[name] = {f: dict(value=round(r["value"], 1),
+                               ms_per_step=round(r["elapsed"] / r["steps"] * 1e3, 3),
+                               mean_cg_iters=round(float(np.mean(r["iters"])), 2),
+                               fallbacks=r["fallbacks"], rows=r["rows"],
+                               kernels={k: dict(mean_us=round(v["mean_us"], 2),
+                                                gbs=round(v["gbs"], 1),
+                                                frac=round(v["gbs"] / PEAK_HBM_GBS, 4))
+                                        for k, v in r["kernels"].items()})
+                       for f, r in runs.items()}
+        if "learned" in runs and "plain" in runs:
+            out_w[name]["learned_vs_plain"] = round(runs["learned"]["value"] /
+                                                    runs["plain"]["value"], 4)
+    head = "learned" if "learned" in forms else forms[0]
+    v = out_w["single_n8e6"][head]
+    dom = max(v["kernels"], key=lambda k: v["kernels"][k]["mean_us"]) if v["kernels"] else None
+    out = {
+        "metric": METRIC, "value": v["value"], "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": v["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-spmv/f64" if args.fp32_spmv else "f64", "data": "synthetic",
+        "config": {"workload": f"scale workloads: one box N=8000000, L=200, and 16 replicas N=500000 "
+                               f"(L=79.37), shear 0.5, density 1, r_c 1, gamma0 0.1, alpha 1, kT 1, dt 0.01, each pre-sheared "
+                               f"{args.c5_preshear} plain steps from uniform positions; value = the "
+                               f"N=8e6 box, {head} form",
+                   "precond": head, "cg_tol": args.tol, "parallelism": "single GPU"},
+        "roofline": None if dom is None else {
+            "bound": "hbm", "achieved": v["kernels"][dom]["gbs"], "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": v["kernels"][dom]["frac"], "traffic": None, "kernel": dom,
+            "copy_probe_gbs": round(copy_gbs, 1)},
+        "cpu_baseline": None,
+        "c5": out_w,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -206,6 +272,10 @@ def main():
         else:
             from paper_1808_06381_amd import precond
             theta = precond.load(args.weights)
+    if args.c5:
+        run_c5(args, S, inputs, theta, [f for f in forms if f != "ic0"], stream, torch, np,
+               copy_gbs)
+        return
     runs = {}
     for form in forms:
         runs[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np)

@@ -213,7 +213,7 @@ int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
  * A three-layer message-passing network on the pair graph of A (hidden 32)
  * maps node features (t_i, a_i, deg_i/8) and edge features (r_ij/rc, w_ij,
  * What_ij) to M^-1 = D^-1/2 (diag(lam) + S) D^-1/2 in A's sparsity, with
- * S_ij = z.(h_i*h_j) + ze.e_ij + z0 symmetric and lam_i = softplus(.) + 1e-3
+ * S_ij = z.(h_i*h_j) + ze.e_ij + z0 symmetric and lam_i = softplus(.) + 0.1
  * (D = diag A, What_ij = alpha w_ij / sqrt(D_i D_j)).  M^-1 is symmetric
  * with a positive diagonal but positive definite only for suitable weights
  * (the best sparse approximate inverses of A are not diagonally dominant);
@@ -226,7 +226,7 @@ int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
  * The weights are SIM_MPNN_NPARAMS FP32 values (bfloat16 in the kernels),
  * in this order: W0[32][3], b0[32], then per layer P[32][32], Q[32][3],
  * c[32], U[32][32], V[32][32], d[32], then v[32], v0, z[32], ze[3], z0.
- * A new handle starts with all weights zero: S = 0, lam = ln 2 + 1e-3, a
+ * A new handle starts with all weights zero: S = 0, lam = ln 2 + 0.1, a
  * scaled Jacobi preconditioner.                                           */
 #define SIM_MPNN_NPARAMS 9893
 /* Copy the FP32 master weights in (set = 1) or out (set = 0).            */

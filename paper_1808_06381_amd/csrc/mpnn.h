@@ -11,7 +11,7 @@
 #define MP_THREADS 256 // threads per block (8 nodes x 32 features)
 #define MP_ROWS 64     // rows per block
 #define MP_MSG 0.125f  // message scale
-#define MP_EPS_LAM 1e-3
+#define MP_EPS_LAM 0.1 // floor of the diagonal head lam
 
 #define MP_OFF_W0 0
 #define MP_OFF_B0 (MP_OFF_W0 + MP_H * MP_FN)

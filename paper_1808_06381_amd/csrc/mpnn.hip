@@ -9,7 +9,7 @@
 //   h0 = relu(W0 x + b0)
 //   layer: y_j = P h_j, m_i = 1/8 sum_j relu(y_j + Q e_ij + c),
 //          h_i <- h_i + relu(U h_i + V m_i + d)
-//   heads: lam_i = softplus(v.h_i + v0) + 1e-3, S_ij = z.(h_i*h_j) + ze.e_ij + z0
+//   heads: lam_i = softplus(v.h_i + v0) + 0.1, S_ij = z.(h_i*h_j) + ze.e_ij + z0
 //   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2: symmetric, positive diagonal (the
 //   solver's true-residual test and Jacobi fallback cover a non-definite M^-1;
 //   the initial heads give the positive definite two-term Neumann series).
