@@ -131,7 +131,7 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     if not args.no_autotune:
         for sim in sims:
             tuning.append(sim.autotune(reps=10))
-            sim.step(1)  # re-records the step graph with the chosen widths
+            sim.step(1)  # re-records the step graph with the chosen variants
     for sim in sims:
         sim.profile_read(reset=True)
         sim.profile_enable(args.probe_every)
@@ -169,7 +169,7 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
                              gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
     particles = sum(sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs)
     value = steps * particles / elapsed
-    tuned = [dict(spmv_lanes=t["spmv_lanes"], apply_lanes=t["apply_lanes"],
+    tuned = [dict(spmv=S.CSR_VARIANTS[t["spmv_variant"]], apply=S.CSR_VARIANTS[t["apply_variant"]],
                   spmv_us=[round(u, 1) for u in t["spmv_us"]],
                   apply_us=[round(u, 1) for u in t["apply_us"]]) for t in tuning]
     ns = [sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs]

@@ -316,15 +316,22 @@ int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void
 int sim_graph_mode(sim_t* sim, int32_t on);
 int sim_graph_info(sim_t* sim, int64_t* captures, int64_t* replays);
 
-/* Tuning of the CSR products (rows of ~5 entries): lanes per row group for
- * w = A u and for the learned u = M^-1 r.  Changes only the summation order
- * of each row (results stay within rounding of each other; a fixed choice
- * is bitwise reproducible).  Default 4 and 4.                             */
+/* Tuning of the CSR products (rows of ~5 entries) w = A u and the learned
+ * u = M^-1 r.  A variant is a group of `lanes` lanes per row and a number
+ * of entries per lane whose columns and values are loaded one pass of rows
+ * ahead of the gathers (0: one entry at a time, no look-ahead); index:
+ * (lanes, entries)
+ *   0: (1, 0)  1: (2, 0)  2: (4, 0)  3: (8, 0)
+ *   4: (2, 2)  5: (4, 1)  6: (4, 2)  7: (4, 3)
+ * The lane count fixes the summation order of a row; variants with the same
+ * lanes give the same bits, others agree to rounding.  A fixed choice is
+ * bitwise reproducible.  Default 6 and 6.                                */
+#define SIM_CSR_VARIANTS 8
 typedef struct sim_tuning {
-  int32_t spmv_lanes;    /* 1, 2, 4 or 8 */
-  int32_t apply_lanes;   /* 1, 2, 4 or 8 */
-  float spmv_us[4];      /* sim_autotune: mean duration per variant 1, 2, 4, 8 */
-  float apply_us[4];     /* (0 where not measured) */
+  int32_t spmv_variant;  /* 0 .. SIM_CSR_VARIANTS - 1 */
+  int32_t apply_variant;
+  float spmv_us[SIM_CSR_VARIANTS];  /* sim_autotune: mean duration per variant */
+  float apply_us[SIM_CSR_VARIANTS]; /* (0 where not measured) */
 } sim_tuning;
 /* Time every variant `reps` times on the system at the current positions
  * (built for the purpose; the state is unchanged) and keep the fastest.
@@ -332,7 +339,7 @@ typedef struct sim_tuning {
  * should fix it with sim_set_tuning.  out (optional) receives the choice
  * and the timings.                                                        */
 int sim_autotune(sim_t* sim, int32_t reps, sim_tuning* out);
-/* Use the given lanes (timings ignored); SIM_EINVAL for other values.     */
+/* Use the given variants (timings ignored); SIM_EINVAL for other values. */
 int sim_set_tuning(sim_t* sim, const sim_tuning* tuning);
 
 /* Free the handle and all its device memory. NULL is a no-op.             */

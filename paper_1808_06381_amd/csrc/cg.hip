@@ -25,14 +25,36 @@
 
 #define VEC_ELEMS (3 * ROWS_PER_BLOCK)  // elements (row, component) per tile
 
-// sum over the LANES lanes of a row's group (butterfly: every lane ends with
-// the same bits, since each step adds the same two operands)
+// sum over the LANES lanes of a row's group, on registers (DPP): lanes
+// exchange with lane ^ 1, then lane ^ 2 (quad permutes), then, for 8 lanes,
+// with the mirrored lane of the other quad, which after the quad steps holds
+// that quad's sum.  Every lane ends with the same bits, since each step adds
+// the same two operands.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- lane 7 - i within 8
+
 template <int LANES>
 __device__ __forceinline__ void lane_group_sum(double (&a)[3]) {
+  static_assert(LANES == 1 || LANES == 2 || LANES == 4 || LANES == 8, "lanes per row");
+  if constexpr (LANES >= 2) {
 #pragma unroll
-  for (int o = 1; o < LANES; o <<= 1)
+    for (int k = 0; k < 3; ++k) a[k] += dpp_move<DPP_XOR1>(a[k]);
+  }
+  if constexpr (LANES >= 4) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a[k] += __shfl_xor(a[k], o, 64);
+    for (int k = 0; k < 3; ++k) a[k] += dpp_move<DPP_XOR2>(a[k]);
+  }
+  if constexpr (LANES >= 8) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] += dpp_move<DPP_HALF_MIRROR>(a[k]);
+  }
 }
 
 // Components per row are finished by lanes 0..2 of the row's group; with
@@ -196,10 +218,133 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_dot_ru(DevPtrs d, int mode
   write_partials<3>(d, tile, 0, v);
 }
 
-// Learned preconditioner: u = M^-1 r with M^-1 in A's pattern (a group of
-// LANES lanes per row, as the CSR product), partial (r, u).  Same component
-// selection as k_cg_vec's mode.
-template <int LANES>
+// Products sum_j M_ij src_j (three components) of the tile's 1024 rows with
+// a group of LANES lanes per row, LANES passes over 1024 / LANES rows each.
+// Lane l of a group takes the row's entries l, l + LANES, l + 2 LANES, ...,
+// adds them in that order, then the group adds its lanes; both forms below
+// therefore give the same bits.
+//   ENT = 0: each lane walks its entries, loading column, value and the
+//            gathered row in turn.
+//   ENT > 0: software-pipelined over the passes.  The row pointers and the
+//            diagonal terms of every pass load first; then the columns and
+//            values of the first ENT entries per lane of pass p + 1 load
+//            while pass p gathers, so each pass waits for one gather instead
+//            of a column load followed by a gather.  Entries past LANES * ENT
+//            in a row follow in the loop form.  Loads of missing entries are
+//            masked, not issued.  (Loading further ahead was measured slower:
+//            the extra data in flight no longer fits the L1 cache.)
+// val(e) is the off-diagonal value of CSR entry e, dg the diagonal; epi(i, k,
+// t, src_ik, own) receives own = dg_i src_ik + sum_j M_ij src_jk for the
+// components finished by this lane (component k = t * LANES + lane, turn t).
+template <int LANES, int ENT, class Val, class Epi>
+__device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const double* __restrict__ src,
+                                         const double* __restrict__ dg, Val val, Epi epi) {
+  constexpr int GROUPS = BLOCK_THREADS / LANES;
+  constexpr int PASSES = ROWS_PER_BLOCK / GROUPS;
+  constexpr int T = TURNS<LANES>;
+  const int lane = threadIdx.x & (LANES - 1);
+  const int grp = threadIdx.x / LANES;
+  // clamped: after an overflowing fill the row pointers may pass the
+  // capacity (the host discards that solve; the reads stay in bounds)
+  const int cap = (int)d.nnz_cap;
+  if constexpr (ENT == 0) {
+    for (int pass = 0; pass < PASSES; ++pass) {
+      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
+      const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
+      double a[3] = {0.0, 0.0, 0.0};
+      for (int e = e0 + lane; e < e1; e += LANES) {
+        const int64_t j = d.col[e];
+        const double m = val(e);
+        a[0] += m * src[3 * j];
+        a[1] += m * src[3 * j + 1];
+        a[2] += m * src[3 * j + 2];
+      }
+      lane_group_sum<LANES>(a);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int k = t * LANES + lane;
+        if (k >= 3) continue;
+        const double sk = src[3 * i + k];
+        epi(i, k, t, sk, dg[i] * sk + pick3(a, k));
+      }
+    }
+  } else {
+    int e0[PASSES], e1[PASSES];
+    double dv[PASSES], sv[PASSES][T];
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + p * GROUPS + grp;
+      e0[p] = min(d.rowptr[i], cap);
+      e1[p] = min(d.rowptr[i + 1], cap);
+      dv[p] = lane < 3 ? dg[i] : 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int k = t * LANES + lane;
+        sv[p][t] = k < 3 ? src[3 * i + k] : 0.0;
+      }
+    }
+    int c[2][ENT];      // columns of the current / next pass (-1: no entry)
+    double m[2][ENT];
+    auto load_entries = [&](int p, int buf) {
+#pragma unroll
+      for (int q = 0; q < ENT; ++q) {
+        const int e = e0[p] + lane + q * LANES;
+        c[buf][q] = -1;
+        m[buf][q] = 0.0;
+        if (e < e1[p]) {
+          c[buf][q] = d.col[e];
+          m[buf][q] = val(e);
+        }
+      }
+    };
+    load_entries(0, 0);
+#pragma unroll
+    for (int p = 0; p < PASSES; ++p) {
+      const int cur = p & 1;
+      if (p + 1 < PASSES) load_entries(p + 1, cur ^ 1);
+      double g[ENT][3];
+#pragma unroll
+      for (int q = 0; q < ENT; ++q) {
+        g[q][0] = g[q][1] = g[q][2] = 0.0;
+        const int64_t j = c[cur][q];
+        if (j >= 0) {
+          g[q][0] = src[3 * j];
+          g[q][1] = src[3 * j + 1];
+          g[q][2] = src[3 * j + 2];
+        }
+      }
+      double a[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < ENT; ++q) {
+          const double prod = m[cur][q] * g[q][k];
+          a[k] += c[cur][q] >= 0 ? prod : 0.0;  // adding +0 leaves the bits
+        }
+      }
+      for (int e = e0[p] + lane + ENT * LANES; e < e1[p]; e += LANES) {
+        const int64_t j = d.col[e];
+        const double mv = val(e);
+        a[0] += mv * src[3 * j];
+        a[1] += mv * src[3 * j + 1];
+        a[2] += mv * src[3 * j + 2];
+      }
+      lane_group_sum<LANES>(a);
+      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + p * GROUPS + grp;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int k = t * LANES + lane;
+        if (k >= 3) continue;
+        epi(i, k, t, sv[p][t], dv[p] * sv[p][t] + pick3(a, k));
+      }
+    }
+  }
+}
+
+// Learned preconditioner: u = M^-1 r with M^-1 in A's pattern, partial
+// (r, u).  Same component selection as k_cg_vec's mode.
+template <int LANES, int ENT>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -210,39 +355,17 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode)
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
-  const int lane = threadIdx.x & (LANES - 1);
-  const int cap = (int)d.nnz_cap;
-  const int grp = threadIdx.x / LANES;
-  constexpr int GROUPS = BLOCK_THREADS / LANES;
-  const double* __restrict__ r = d.r;
-  double v[3] = {0, 0, 0};
+  const float* __restrict__ moff = d.moff;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
-  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
-    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    // clamped: after an overflowing fill the row pointers may pass the
-    // capacity (the host discards that solve; the reads stay in bounds)
-    const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
-    double a[3] = {0.0, 0.0, 0.0};
-    for (int e = e0 + lane; e < e1; e += LANES) {
-      const int64_t j = d.col[e];
-      const double m = (double)d.moff[e];
-      a[0] += m * r[3 * j];
-      a[1] += m * r[3 * j + 1];
-      a[2] += m * r[3 * j + 2];
-    }
-    lane_group_sum<LANES>(a);
-    // lane k finishes component k (one turn); narrower groups take turns
-#pragma unroll
-    for (int t = 0; t < TURNS<LANES>; ++t) {
-      const int k = t * LANES + lane;
-      if (k >= 3 || !on_k(on, k)) continue;
-      const int64_t e = 3 * i + k;
-      const double uk = d.mdiag[i] * r[e] + pick3(a, k);
-      d.u[e] = uk;
-      vt[t] += r[e] * uk;
-    }
-  }
-  turns_to_components<LANES>(vt, lane, v);
+  csr_tile<LANES, ENT>(
+      d, tile, d.r, d.mdiag, [&](int e) { return (double)moff[e]; },
+      [&](int64_t i, int k, int t, double rk, double uk) {
+        if (!on_k(on, k)) return;
+        d.u[3 * i + k] = uk;
+        vt[t] += rk * uk;
+      });
+  double v[3] = {0, 0, 0};
+  turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);
   write_partials<3>(d, tile, 0, v);
 }
 
@@ -344,12 +467,12 @@ __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, 
   }
 }
 
-// CSR product with LANES lanes per row over the tile's 1024 rows.
+// CSR product over the tile's 1024 rows.
 //   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
 //   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
 // Lane k of a row's group finishes component k (coalesced stores); with
 // fewer than three lanes, lane l takes components l, l + LANES, ...
-template <bool FP32, int LANES>
+template <bool FP32, int LANES, int ENT>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -368,44 +491,25 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
     for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
   }
   const double* __restrict__ src = mode == 0 ? d.u : d.x;
-  const int lane = threadIdx.x & (LANES - 1);
-  const int cap = (int)d.nnz_cap;
-  const int grp = threadIdx.x / LANES;
-  constexpr int GROUPS = BLOCK_THREADS / LANES;
-  double v[3] = {0, 0, 0};
+  const double* __restrict__ val = d.val;
+  const float* __restrict__ valf = d.valf;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
-  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
-    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    // clamped: after an overflowing fill the row pointers may pass the
-    // capacity (the host discards that solve; the reads stay in bounds)
-    const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
-    double a[3] = {0.0, 0.0, 0.0};
-    for (int e = e0 + lane; e < e1; e += LANES) {
-      const int64_t j = d.col[e];
-      const double m = FP32 ? (double)d.valf[e] : d.val[e];
-      a[0] += m * src[3 * j];
-      a[1] += m * src[3 * j + 1];
-      a[2] += m * src[3 * j + 2];
-    }
-    lane_group_sum<LANES>(a);
-    // lane k finishes component k (one turn); narrower groups take turns
-#pragma unroll
-    for (int t = 0; t < TURNS<LANES>; ++t) {
-      const int k = t * LANES + lane;
-      if (k >= 3 || !on_k(on, k)) continue;
-      const int64_t e = 3 * i + k;
-      const double own = d.diag[i] * src[e] + pick3(a, k);
-      if (mode == 0) {
-        d.w[e] = own;
-        vt[t] += own * src[e];
-      } else {
-        const double rk = d.b[e] - own;
-        d.r[e] = rk;
-        vt[t] += rk * rk;
-      }
-    }
-  }
-  turns_to_components<LANES>(vt, lane, v);
+  csr_tile<LANES, ENT>(
+      d, tile, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; },
+      [&](int64_t i, int k, int t, double sk, double own) {
+        if (!on_k(on, k)) return;
+        const int64_t e = 3 * i + k;
+        if (mode == 0) {
+          d.w[e] = own;
+          vt[t] += own * sk;
+        } else {
+          const double rk = d.b[e] - own;
+          d.r[e] = rk;
+          vt[t] += rk * rk;
+        }
+      });
+  double v[3] = {0, 0, 0};
+  turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);
   write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
 }
 
@@ -452,15 +556,15 @@ hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_
                           hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
   const bool f32 = d.spmv_fp32 && mode == 0;
-  switch (d.spmv_lanes * 2 + (f32 ? 1 : 0)) {
-#define SPMV_CASE(L)                                                                         \
-    case 2 * L:                                                                             \
-      LAUNCH_EV((k_cg_spmv<false, L>), g, b, s, ev0, ev1, d, mode, start_mode); \
-      break;                                                                                \
-    case 2 * L + 1:                                                                         \
-      LAUNCH_EV((k_cg_spmv<true, L>), g, b, s, ev0, ev1, d, mode, start_mode);  \
+  switch (d.spmv_var * 2 + (f32 ? 1 : 0)) {
+#define SPMV_CASE(V, L, E)                                                                  \
+    case 2 * V:                                                                            \
+      LAUNCH_EV((k_cg_spmv<false, L, E>), g, b, s, ev0, ev1, d, mode, start_mode);          \
+      break;                                                                               \
+    case 2 * V + 1:                                                                        \
+      LAUNCH_EV((k_cg_spmv<true, L, E>), g, b, s, ev0, ev1, d, mode, start_mode);           \
       break;
-    SPMV_CASE(1) SPMV_CASE(2) SPMV_CASE(4) SPMV_CASE(8)
+    CSR_VARIANT_LIST(SPMV_CASE)
 #undef SPMV_CASE
     default: return hipErrorInvalidValue;
   }
@@ -475,11 +579,11 @@ hipError_t launch_cg_dot_ru(const DevPtrs& d, int mode, hipStream_t s) {
 hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
   const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
-  switch (d.apply_lanes) {
-    case 1: LAUNCH_EV(k_cg_apply<1>, g, b, s, ev0, ev1, d, mode); break;
-    case 2: LAUNCH_EV(k_cg_apply<2>, g, b, s, ev0, ev1, d, mode); break;
-    case 4: LAUNCH_EV(k_cg_apply<4>, g, b, s, ev0, ev1, d, mode); break;
-    case 8: LAUNCH_EV(k_cg_apply<8>, g, b, s, ev0, ev1, d, mode); break;
+  switch (d.apply_var) {
+#define APPLY_CASE(V, L, E) \
+    case V: LAUNCH_EV((k_cg_apply<L, E>), g, b, s, ev0, ev1, d, mode); break;
+    CSR_VARIANT_LIST(APPLY_CASE)
+#undef APPLY_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -689,14 +689,14 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.nrep = replicas;
   d.ncell_entries = (int32_t)seg_off;
   d.spmv_fp32 = params[0].spmv_fp32;
-  d.spmv_lanes = 4;
-  d.apply_lanes = 4;
+  d.spmv_var = CSR_VARIANT_DEFAULT;
+  d.apply_var = CSR_VARIANT_DEFAULT;
   d.ic0 = s->ic0 ? 1 : 0;
   d.pc_none = params[0].precond == SIM_PC_NONE ? 1 : 0;
   for (int r = 1; r < replicas; ++r)
     if ((params[r].precond == SIM_PC_NONE) != (d.pc_none != 0)) { sim_destroy(s); return SIM_EINVAL; }
-  s->tune.spmv_lanes = 4;
-  s->tune.apply_lanes = 4;
+  s->tune.spmv_variant = CSR_VARIANT_DEFAULT;
+  s->tune.apply_variant = CSR_VARIANT_DEFAULT;
   const size_t rows = (size_t)s->rows;
   int rc = SIM_OK;
 #define ALLOC(ptr, bytes)                                      \
@@ -864,14 +864,15 @@ int sim_graph_info(sim_t* s, int64_t* captures, int64_t* replays) {
   return SIM_OK;
 }
 
-static bool valid_lanes(int32_t l) { return l == 1 || l == 2 || l == 4 || l == 8; }
+static bool valid_variant(int32_t v) { return v >= 0 && v < CSR_VARIANTS; }
 
 int sim_set_tuning(sim_t* s, const sim_tuning* t) {
-  if (!s || !t || !valid_lanes(t->spmv_lanes) || !valid_lanes(t->apply_lanes)) return SIM_EINVAL;
-  s->tune.spmv_lanes = t->spmv_lanes;
-  s->tune.apply_lanes = t->apply_lanes;
-  s->d.spmv_lanes = t->spmv_lanes;
-  s->d.apply_lanes = t->apply_lanes;
+  if (!s || !t || !valid_variant(t->spmv_variant) || !valid_variant(t->apply_variant))
+    return SIM_EINVAL;
+  s->tune.spmv_variant = t->spmv_variant;
+  s->tune.apply_variant = t->apply_variant;
+  s->d.spmv_var = t->spmv_variant;
+  s->d.apply_var = t->apply_variant;
   drop_graphs(s);
   return SIM_OK;
 }
@@ -896,16 +897,15 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  const int lanes[4] = {1, 2, 4, 8};
   sim_tuning t{};
   int kinds = d.learned ? 2 : 1;
   hipError_t err = hipSuccess;
   for (int kind = 0; kind < kinds && err == hipSuccess; ++kind) {
     float best = 0.0f;
-    int pick = 4;
-    for (int v = 0; v < 4 && err == hipSuccess; ++v) {
-      if (kind == 0) d.spmv_lanes = lanes[v];
-      else d.apply_lanes = lanes[v];
+    int pick = CSR_VARIANT_DEFAULT;
+    for (int v = 0; v < CSR_VARIANTS && err == hipSuccess; ++v) {
+      if (kind == 0) d.spmv_var = v;
+      else d.apply_var = v;
       auto once = [&]() {
         return kind == 0 ? launch_cg_spmv(d, 0, 0, s->stream) : launch_cg_apply(d, 0, s->stream);
       };
@@ -917,24 +917,24 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
       if ((err = hipEventElapsedTime(&ms, e0, e1))) break;
       const float us = 1000.0f * ms / (float)reps;
       (kind == 0 ? t.spmv_us : t.apply_us)[v] = us;
-      if (v == 0 || us < best) { best = us; pick = lanes[v]; }
+      if (v == 0 || us < best) { best = us; pick = v; }
     }
-    if (kind == 0) t.spmv_lanes = pick;
-    else t.apply_lanes = pick;
+    if (kind == 0) t.spmv_variant = pick;
+    else t.apply_variant = pick;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   d.learned = 0;
   if (err != hipSuccess) {
-    d.spmv_lanes = s->tune.spmv_lanes;
-    d.apply_lanes = s->tune.apply_lanes;
+    d.spmv_var = s->tune.spmv_variant;
+    d.apply_var = s->tune.apply_variant;
     sim_note_error(err, "autotune", __LINE__);
     return SIM_EDEVICE;
   }
-  if (!s->learned) t.apply_lanes = s->tune.apply_lanes;
+  if (!s->learned) t.apply_variant = s->tune.apply_variant;
   s->tune = t;
-  d.spmv_lanes = t.spmv_lanes;
-  d.apply_lanes = t.apply_lanes;
+  d.spmv_var = t.spmv_variant;
+  d.apply_var = t.apply_variant;
   drop_graphs(s);
   if (out) *out = t;
   return SIM_OK;

@@ -128,13 +128,21 @@ struct DevPtrs {
   int32_t ncell_entries;
   int32_t spmv_fp32;
   int32_t learned;          // 1: u = M^-1 r by the learned preconditioner
-  int32_t spmv_lanes;       // lanes per CSR row of the products (1, 2, 4 or 8)
-  int32_t apply_lanes;
+  int32_t spmv_var;         // CSR product variants (CSR_VARIANT_LIST index)
+  int32_t apply_var;
   int32_t ic0;              // 1: u = M^-1 r by the IC(0) triangular solves
   int32_t pc_none;          // 1: no preconditioner, u = r
   int32_t pad0;             // explicit: the host compares whole structs bytewise
 };
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
+
+// CSR product variants: X(index, lanes per row, entries per lane loaded
+// one pass ahead of the gathers; 0 = one entry at a time).  The order is the public
+// one of sim_tuning.
+#define CSR_VARIANTS 8
+#define CSR_VARIANT_DEFAULT 6
+#define CSR_VARIANT_LIST(X) \
+  X(0, 1, 0) X(1, 2, 0) X(2, 4, 0) X(3, 8, 0) X(4, 2, 2) X(5, 4, 1) X(6, 4, 2) X(7, 4, 3)
 
 // ---------------------------------------------------------------------------
 // Block -> tile mapping: hardware dispatches workgroups round-robin over the

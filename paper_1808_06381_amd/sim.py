@@ -33,12 +33,18 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
 MPNN_NPARAMS = 9893
 
 
+# CSR product variants of sim_tuning: (lanes per row, entries per lane loaded one
+# pass ahead of the gathers; 0 = one at a time), in the library's index order
+CSR_VARIANTS = [(1, 0), (2, 0), (4, 0), (8, 0), (2, 2), (4, 1), (4, 2), (4, 3)]
+
+
 class SimTuning(C.Structure):
-    _fields_ = [("spmv_lanes", C.c_int32), ("apply_lanes", C.c_int32),
-                ("spmv_us", C.c_float * 4), ("apply_us", C.c_float * 4)]
+    _fields_ = [("spmv_variant", C.c_int32), ("apply_variant", C.c_int32),
+                ("spmv_us", C.c_float * len(CSR_VARIANTS)),
+                ("apply_us", C.c_float * len(CSR_VARIANTS))]
 
     def as_dict(self):
-        return dict(spmv_lanes=self.spmv_lanes, apply_lanes=self.apply_lanes,
+        return dict(spmv_variant=self.spmv_variant, apply_variant=self.apply_variant,
                     spmv_us=list(self.spmv_us), apply_us=list(self.apply_us))
 
 
@@ -356,9 +362,10 @@ class Sim:
         _check(lib().sim_autotune(self.h, int(reps), C.byref(t)), "sim_autotune")
         return t.as_dict()
 
-    def set_tuning(self, spmv_lanes=4, apply_lanes=4):
+    def set_tuning(self, spmv_variant=6, apply_variant=6):
+        """Fix the CSR product variants (indices into CSR_VARIANTS)."""
         t = SimTuning()
-        t.spmv_lanes, t.apply_lanes = int(spmv_lanes), int(apply_lanes)
+        t.spmv_variant, t.apply_variant = int(spmv_variant), int(apply_variant)
         _check(lib().sim_set_tuning(self.h, C.byref(t)), "sim_set_tuning")
 
     def set_weights(self, theta):

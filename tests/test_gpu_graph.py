@@ -5,9 +5,13 @@ products.
   (the graph records the same kernels in the same order; a solve that needs
   more iterations than the graph holds continues eagerly), for one box, a
   batch of uneven replicas and the learned preconditioner.
-* Every lane width of the products (1, 2, 4, 8) gives velocities within the
-  CG tolerance bound of the oracle; the autotuner returns one of them.
+* Every CSR product variant (lanes per row 1, 2, 4, 8; entries loaded ahead
+  of the gathers) solves to the CG tolerance bound of a dense solve; the
+  variants that load ahead give the bits of the loop form with the same
+  lanes; the autotuner returns one of them.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -16,6 +20,7 @@ from paper_1808_06381_amd import inputs, precond
 from paper_1808_06381_amd import sim as S
 
 pytestmark = pytest.mark.gpu
+WEIGHTS = os.path.join(os.path.dirname(precond.__file__), "weights", "precond_n1e5.bin")
 
 
 def run(cfg, pos0, steps, graph, precond_name=None, theta=None, tol=1e-10):
@@ -75,8 +80,8 @@ def test_graph_learned_bitwise_and_matches_oracle():
     assert np.all(rel < 1e-7), rel
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
-def test_every_lane_width_solves_to_tolerance(lanes):
+@pytest.mark.parametrize("variant", range(len(S.CSR_VARIANTS)))
+def test_every_csr_variant_solves_to_tolerance(variant):
     cfg = inputs.base_params(n=3000, box=(14.4, 14.4, 14.4), shear_rate=0.3, seed=11)
     pos = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
     b = np.random.default_rng(5).normal(size=(cfg["n"], 3))
@@ -86,17 +91,40 @@ def test_every_lane_width_solves_to_tolerance(lanes):
     kappa = np.linalg.cond(A)
     for name, extra in [("jacobi", {}), ("fp32", {"spmv_fp32": 1})]:
         with S.Sim(dict(cfg, **extra), pos, tol=1e-10) as sim:
-            sim.set_tuning(spmv_lanes=lanes, apply_lanes=lanes)
+            sim.set_tuning(spmv_variant=variant, apply_variant=variant)
             v, st = sim.solve(b)
         err = np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
         assert np.all(err <= kappa * 1e-10), (name, err)
     theta = precond.init_params(seed=1)
     with S.Sim(cfg, pos, tol=1e-10, precond="learned") as sim:
         sim.set_weights(theta)
-        sim.set_tuning(spmv_lanes=lanes, apply_lanes=lanes)
+        sim.set_tuning(spmv_variant=variant, apply_variant=variant)
         v, st = sim.solve(b)
     err = np.linalg.norm(v - x, axis=0) / np.linalg.norm(x, axis=0)
     assert np.all(err <= kappa * 1e-10) and st["fallback"] == 0
+
+
+def test_prefetching_variants_give_the_loop_forms_bits():
+    """Variants that load entries ahead of the gathers sum each row in the
+    order of the loop form with the same lanes per row, so whole solves agree
+    bit for bit -- including rows longer than lanes x entries (the tail)."""
+    cfg = inputs.cube_params(20000, 0.5, seed=21)
+    pos = inputs.uniform_positions(cfg["n"], cfg["box"], 21)
+    theta = precond.load(WEIGHTS)
+    pairs = [(1, 4), (2, 5), (2, 6), (2, 7)]   # (loop form, pipelined form)
+    for fp32 in (0, 1):
+        out = {}
+        for v in sorted({v for p in pairs for v in p}):
+            with S.Sim(dict(cfg, spmv_fp32=fp32), pos, tol=1e-8, precond="learned") as sim:
+                sim.set_weights(theta)
+                sim.set_tuning(spmv_variant=v, apply_variant=v)
+                st = sim.step(3)
+                out[v] = sim.state()[:2] + (st["iters"],)
+                assert st["max_row"] > 8   # some rows use the tail loop
+        for a, b in pairs:
+            assert np.array_equal(out[a][0], out[b][0]), (fp32, a, b)
+            assert np.array_equal(out[a][1], out[b][1]), (fp32, a, b)
+            assert out[a][2] == out[b][2]
 
 
 def test_autotune_picks_a_valid_width_and_keeps_state():
@@ -108,11 +136,12 @@ def test_autotune_picks_a_valid_width_and_keeps_state():
         before = sim.state()
         t = sim.autotune(reps=5)
         after = sim.state()
-        assert t["spmv_lanes"] in (1, 2, 4, 8) and t["apply_lanes"] in (1, 2, 4, 8)
+        nv = len(S.CSR_VARIANTS)
+        assert t["spmv_variant"] in range(nv) and t["apply_variant"] in range(nv)
         assert all(u > 0 for u in t["spmv_us"]) and all(u > 0 for u in t["apply_us"])
         assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
         st = sim.step(2)
         assert max(st["relres"]) <= 1e-8 and st["steps_done"] == 2
     with pytest.raises(S.SimError):
         with S.Sim(cfg, pos0) as sim:
-            sim.set_tuning(spmv_lanes=3)
+            sim.set_tuning(spmv_variant=len(S.CSR_VARIANTS))
