@@ -30,16 +30,6 @@
 // with the mirrored lane of the other quad, which after the quad steps holds
 // that quad's sum.  Every lane ends with the same bits, since each step adds
 // the same two operands.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
-constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
-constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- lane 7 - i within 8
-
 template <int LANES>
 __device__ __forceinline__ void lane_group_sum(double (&a)[3]) {
   static_assert(LANES == 1 || LANES == 2 || LANES == 4 || LANES == 8, "lanes per row");
@@ -438,13 +428,14 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
 }
 
 // Sum the replica's tile partials in a fixed order (thread t takes tiles t,
-// t + blockDim, ...; then the wave and block trees).  Totals valid in thread 0.
+// t + nthr, ...; then the wave and block trees).  Totals valid in thread 0.
 __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, double (&tot)[9]) {
   __shared__ double lds[16][9];
   double acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-  for (int t = threadIdx.x; t < R.nblk; t += blockDim.x) {
+  const int nthr = finish_threads_for(R.nblk);
+  for (int t = threadIdx.x; threadIdx.x < nthr && t < R.nblk; t += nthr) {
     const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
@@ -590,6 +581,6 @@ hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t
 }
 
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_finish, dim3(d.nrep), dim3(1024), 0, s, d, mode);
+  hipLaunchKernelGGL(k_cg_finish, dim3(d.nrep), dim3(d.finish_threads), 0, s, d, mode);
   return hipGetLastError();
 }

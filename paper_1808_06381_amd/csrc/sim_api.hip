@@ -686,6 +686,9 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   DevPtrs& d = s->d;
   d.rows = s->rows;
   d.nblk = blk_off;
+  d.finish_threads = 64;
+  for (int r = 0; r < replicas; ++r)
+    d.finish_threads = std::max(d.finish_threads, finish_threads_for(s->reph[r].nblk));
   d.nrep = replicas;
   d.ncell_entries = (int32_t)seg_off;
   d.spmv_fp32 = params[0].spmv_fp32;
