@@ -92,7 +92,11 @@ enum sim_precond { SIM_PC_JACOBI = 0, SIM_PC_NONE = 1, SIM_PC_IC0 = 2, SIM_PC_LE
  *  spmv_fp32   0: FP64 matrix values; 1: FP32 matrix values in the CG
  *              matrix products with FP64 vectors, dots and true-residual
  *              recompute (agreement with FP64 about 1e-5 relative)
- *  warm_start  reserved, must be 0
+ *  warm_start  0: every solve of sim_step starts from v = 0; 1: from the
+ *              previous step's velocities (zero before the first step), a
+ *              restart whose answer differs from the cold start's only
+ *              within cg_tol; sim_solve always starts from 0.  The same
+ *              value for every replica of a batch.
  *  cg_maxit    iteration limit per solve (> 0)
  *  cg_tol      stop when ||b_k - A v_k||_2 <= cg_tol*||b_k||_2 for each
  *              component k (true residual, checked at exit)

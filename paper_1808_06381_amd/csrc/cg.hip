@@ -361,7 +361,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode)
 
 // Advance the recurrences of one replica from its totals
 // tot = [gamma0..2, delta0..2, rr0..2].  mode 0: after a fresh start, 1: after
-// a restart, 2: after an iteration, 3: after a true-residual check.
+// a restart, 2: after an iteration, 3: after a true-residual check, 4: after
+// the residual of a warm-start guess.
 __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&tot)[9]) {
   int finished = 0;
   for (int k = 0; k < 3; ++k) {
@@ -404,6 +405,11 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
           c.gamma[k] = gam;
         }
       }
+    } else if (mode == 4 && c.state[k] == 0) {
+      // residual of the warm-start guess: done if it passes, else restart
+      // from it (no restart is counted)
+      c.rr[k] = rr;
+      c.state[k] = rr <= c.tol2 * c.bb[k] ? 1 : 3;
     } else if (mode == 3 && c.state[k] == 1) {
       c.rr[k] = rr;
       if (rr <= c.tol2 * c.bb[k]) {
@@ -461,6 +467,8 @@ __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, 
 // CSR product over the tile's 1024 rows.
 //   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
 //   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
+//   mode 2: r = b - A x, partial (r, r)  (iterating components: the residual
+//           of a warm-start guess)
 // Lane k of a row's group finishes component k (coalesced stores); with
 // fewer than three lanes, lane l takes components l, l + LANES, ...
 template <bool FP32, int LANES, int ENT>
@@ -476,10 +484,14 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       on[k] = start_mode == 0 ? true : (start_mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
-  } else {
+  } else if (mode == 1) {
     if (!cr.check) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 1;
+  } else {
+    if (!cr.run) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) on[k] = cr.state[k] == 0;
   }
   const double* __restrict__ src = mode == 0 ? d.u : d.x;
   const double* __restrict__ val = d.val;
@@ -504,13 +516,31 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
   write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
 }
 
+// Warm start: x = the previous step's velocity of each row's particle (kept
+// in original order) for the components still iterating after the fresh
+// start, which has set ||b||^2 and finished the components with b = 0.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_warm(DevPtrs d, const int64_t* __restrict__ id_off) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const int rid = d.blk_rep[tile];
+  const CgRep& cr = d.cg[rid];
+  if (!cr.run) return;
+  const RepDev& R = d.rep[rid];
+  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
+  if (i - R.row_off >= R.n) return;  // padding rows keep x = 0
+  const int64_t g = id_off[rid] + (int64_t)d.pos[i].w;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (cr.state[k] == 0) d.x[3 * i + k] = d.vel_orig[3 * g + k];
+}
+
 // One block per replica: reduce the replica's tile partials and advance.
 __global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
   const int rid = blockIdx.x;
   const RepDev& R = d.rep[rid];
   CgRep& c = d.cg[rid];
   const bool work = (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
-                    (mode == 3 && c.check);
+                    (mode == 3 && c.check) || (mode == 4 && c.run);
   if (!work) return;
   double tot[9];
   reduce_tiles(d, R, tot);
@@ -577,6 +607,11 @@ hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t
 #undef APPLY_CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_warm(const DevPtrs& d, const int64_t* id_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_warm, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, id_off);
   return hipGetLastError();
 }
 

@@ -95,6 +95,7 @@ struct sim_t {
   int32_t graph_K = 0;
   // IC(0) preconditioner
   bool ic0 = false;
+  bool warm = false;         // step solves start from the previous velocities
   std::vector<int32_t> ic_color_off;  // offsets of the colours in d.ic_cells (host copy)
   sim_tuning tune{};
 };
@@ -147,7 +148,7 @@ static int validate(const sim_params& p) {
     return SIM_EINVAL;
   if (!std::isfinite(p.u_amp)) return SIM_EINVAL;
   if (!(p.cg_tol > 0.0) || p.cg_maxit < 1) return SIM_EINVAL;
-  if (p.warm_start != 0) return SIM_EINVAL;
+  if (p.warm_start != 0 && p.warm_start != 1) return SIM_EINVAL;
   if (p.spmv_fp32 != 0 && p.spmv_fp32 != 1) return SIM_EINVAL;
   if (p.precond == SIM_PC_LEARNED && !(p.alpha > 0.0)) return SIM_EINVAL;
   return SIM_OK;
@@ -382,16 +383,32 @@ static int prepare_precond(sim_t* s) {
 }
 
 // tol > 0 overrides the replicas' own tolerances
-static int cg_queue_start(sim_t* s, double tol) {
+// Fresh start from x = 0 (which also takes ||b||^2); with `warm`, the
+// iterating components then restart from the previous step's velocities:
+// x = v_prev, r = b - A x, done if r passes, else the restart path.
+static int cg_queue_start(sim_t* s, double tol, bool warm) {
   const DevPtrs& d = s->d;
+  const bool ext = d.learned || d.ic0;
   HIPCHK(launch_cg_reset(d, tol, s->stream));
   HIPCHK(launch_cg_vec(d, 0, s->stream));
-  if (d.learned || d.ic0) {
+  if (ext) {
     int rc = queue_apply(s, 0, nullptr, nullptr);
     if (rc) return rc;
   }
   HIPCHK(launch_cg_spmv(d, 0, 0, s->stream));
   HIPCHK(launch_cg_finish(d, 0, s->stream));
+  if (warm) {
+    HIPCHK(launch_cg_warm(d, s->id_off_d, s->stream));
+    HIPCHK(launch_cg_spmv(d, 2, 0, s->stream));
+    HIPCHK(launch_cg_finish(d, 4, s->stream));
+    HIPCHK(launch_cg_vec(d, 1, s->stream));
+    if (ext) {
+      int rc = queue_apply(s, 1, nullptr, nullptr);
+      if (rc) return rc;
+    }
+    HIPCHK(launch_cg_spmv(d, 0, 1, s->stream));
+    HIPCHK(launch_cg_finish(d, 1, s->stream));
+  }
   return SIM_OK;
 }
 
@@ -542,8 +559,8 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
   return SIM_OK;
 }
 
-static int cg_solve(sim_t* s, double tol, sim_stats* st) {
-  int rc = cg_queue_start(s, tol);
+static int cg_solve(sim_t* s, double tol, bool warm, sim_stats* st) {
+  int rc = cg_queue_start(s, tol, warm);
   if (rc) return rc;
   const int n = std::max(1, std::min(s->last_iters > 2 ? s->last_iters - 1 : 8, cg_maxit(s) + 1));
   if ((rc = cg_queue_chunk(s, n, 0, true))) return rc;
@@ -556,11 +573,11 @@ static int build_and_solve(sim_t* s, bool replace_rhs, double tol, sim_stats* st
   for (int attempt = 0; attempt < 4; ++attempt) {
     if ((rc = prepare_precond(s))) return rc;
     if (replace_rhs) HIPCHK(launch_permute(s->d, s->id_off_d, 1, s->io, nullptr, s->stream));
-    rc = cg_solve(s, tol, st);
+    rc = cg_solve(s, tol, s->warm && !replace_rhs, st);
     if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
       // the learned solve did not make progress: redo it with Jacobi
       s->d.learned = 0;
-      rc = cg_solve(s, tol, st);
+      rc = cg_solve(s, tol, s->warm && !replace_rhs, st);
       s->d.learned = 1;
       if (st) st->fallback = 1;
     }
@@ -698,6 +715,9 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.pc_none = params[0].precond == SIM_PC_NONE ? 1 : 0;
   for (int r = 1; r < replicas; ++r)
     if ((params[r].precond == SIM_PC_NONE) != (d.pc_none != 0)) { sim_destroy(s); return SIM_EINVAL; }
+  s->warm = params[0].warm_start != 0;
+  for (int r = 1; r < replicas; ++r)
+    if ((params[r].warm_start != 0) != s->warm) { sim_destroy(s); return SIM_EINVAL; }
   s->tune.spmv_variant = CSR_VARIANT_DEFAULT;
   s->tune.apply_variant = CSR_VARIANT_DEFAULT;
   const size_t rows = (size_t)s->rows;
@@ -1146,7 +1166,7 @@ static int queue_graph_step(sim_t* s, int K) {
   if (s->ic0)
     HIPCHK(launch_ic_factor(s->d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1,
                             s->stream));
-  if ((rc = cg_queue_start(s, 0.0))) return rc;
+  if ((rc = cg_queue_start(s, 0.0, s->warm))) return rc;
   if ((rc = cg_queue_chunk(s, K, 0, false))) return rc;
   HIPCHK(launch_update(s->d, 1, s->stream));
   HIPCHK(launch_save_vel(s->d, s->id_off_d, 1, s->stream));
@@ -1212,7 +1232,7 @@ static int step_graph(sim_t* s, sim_stats* st) {
   }
   if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
     s->d.learned = 0;
-    rc = cg_solve(s, 0.0, st);
+    rc = cg_solve(s, 0.0, s->warm, st);
     s->d.learned = 1;
     if (st) st->fallback = 1;
   }
@@ -1222,10 +1242,10 @@ static int step_graph(sim_t* s, sim_stats* st) {
     for (int attempt = 0; attempt < 4 && rc == SIM_EOVERFLOW_INTERNAL; ++attempt) {
       if ((rc = grow_and_refill(s))) return rc;
       if ((rc = prepare_precond(s))) return rc;
-      rc = cg_solve(s, 0.0, st);
+      rc = cg_solve(s, 0.0, s->warm, st);
       if (s->learned && (rc == SIM_ESTALL_INTERNAL || rc == SIM_EBREAKDOWN || rc == SIM_ENOCONV)) {
         s->d.learned = 0;
-        rc = cg_solve(s, 0.0, st);
+        rc = cg_solve(s, 0.0, s->warm, st);
         s->d.learned = 1;
         if (st) st->fallback = 1;
       }

@@ -186,7 +186,7 @@ def make_params(cfg, tol=None, maxit=None, precond=None, spmv_fp32=None):
     p.noise_mode = NOISE[cfg.get("noise", "fdt")]
     p.precond = PRECOND[precond or cfg.get("precond", "jacobi")]
     p.spmv_fp32 = int(cfg.get("spmv_fp32", 0) if spmv_fp32 is None else spmv_fp32)
-    p.warm_start = 0
+    p.warm_start = int(cfg.get("warm_start", 0))
     p.cg_maxit = int(maxit or cfg.get("cg_maxit", 10000))
     p.cg_tol = float(tol or cfg.get("cg_tol", 1e-10))
     p.seed = int(cfg.get("seed", 0)) & (2**64 - 1)
