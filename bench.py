@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--c5", action="store_true",
                     help="the scale workloads instead: one N = 8e6 box (L = 200) and 16 replicas "
                          "of N = 5e5, shear 0.5, from a pre-sheared state")
-    ap.add_argument("--c5-preshear", type=int, default=200,
+    ap.add_argument("--c5-preshear", type=int, default=2000,
                     help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -62,6 +62,7 @@ def parse():
                     help="comma list of CG forms to time: plain (Jacobi-PCG), learned, ic0")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1808_06381_amd", "weights",
                                                       "precond_n1e5.bin"))
+    ap.set_defaults(event_over_us=0.0)  # set from the event probe before any timing
     return ap.parse_args()
 
 
@@ -163,9 +164,13 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     for name, rec in prof.items():
         if rec["launches"] == 0:
             continue
-        ms = rec["ms"] / rec["launches"]
+        ms_ev = rec["ms"] / rec["launches"]
+        # the launch-bound event pair adds args.event_over_us to each timed
+        # launch (measured live by the event probe): the kernel's own time
+        ms = ms_ev - args.event_over_us * 1e-3
         bpl = rec["bytes"] / rec["launches"]
-        kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3, bytes_per_launch=bpl,
+        kernels[name] = dict(launches=rec["launches"], mean_us=ms * 1e3,
+                             mean_us_events=ms_ev * 1e3, bytes_per_launch=bpl,
                              gbs=bpl / (ms * 1e-3) / 1e9, total_ms=rec["ms"])
     particles = sum(sum(r["n"] for r in (c if isinstance(c, list) else [c])) for c in cfgs)
     value = steps * particles / elapsed
@@ -228,6 +233,7 @@ def run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs):
         "roofline": None if dom is None else {
             "bound": "hbm", "achieved": v["kernels"][dom]["gbs"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": v["kernels"][dom]["frac"], "traffic": None, "kernel": dom,
+            "mean_us": v["kernels"][dom]["mean_us"], "event_overhead_us": round(args.event_over_us, 2),
             "copy_probe_gbs": round(copy_gbs, 1)},
         "cpu_baseline": None,
         "c5": out_w,
@@ -257,6 +263,12 @@ def main():
     dst = torch.empty_like(src)
     copy_ms = S.copy_probe(src, dst, reps=10, stream=stream)
     copy_gbs = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+    # what the probe's launch-bound events add per timed launch: the same
+    # copy (64 MB, a CG kernel's duration) timed in a chain and one by one
+    ev_chain, ev_each = S.event_probe(src[:8 << 20], dst[:8 << 20], reps=64, stream=stream)
+    args.event_over_us = max(0.0, (ev_each - ev_chain) * 1e3)
+    print(f"# event probe: copy {ev_chain * 1e3:.2f} us in a chain, {ev_each * 1e3:.2f} us timed "
+          f"one by one: {args.event_over_us:.2f} us per timed launch", file=sys.stderr, flush=True)
     del src, dst
     cfgs, pos0s = [], []
     for k, shear in enumerate(SHEARS):
@@ -295,7 +307,9 @@ def main():
                         frac=round(kr["gbs"] / PEAK_HBM_GBS, 4),
                         copy_probe_gbs=round(copy_gbs, 1),
                         traffic=traffic, kernel=dom,
-                        bytes_per_launch=kr["bytes_per_launch"], mean_us=round(kr["mean_us"], 2))
+                        bytes_per_launch=kr["bytes_per_launch"], mean_us=round(kr["mean_us"], 2),
+                        mean_us_events=round(kr["mean_us_events"], 2),
+                        event_overhead_us=round(args.event_over_us, 2))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -183,6 +183,22 @@ int sim_solve(sim_t* sim, const double* b, double* v, double tol, uint32_t flags
  * NULL.  flags: SIM_DEVICE_PTR for pos/vel.                               */
 int sim_state(sim_t* sim, double* pos, double* vel, sim_meta* meta, uint32_t flags);
 
+/* Structure factor of the blob centres (Results section, Eq. Sfactor) of
+ * every replica at the current positions: S(q) = |sum_c exp(-i q.R_c)|^2 / C
+ * for one configuration (averaging over configurations is the caller's),
+ * on the wavevectors that the Lees-Edwards images of the box leave
+ * invariant,
+ *   q = (2 pi mx / Lx, 2 pi my / Ly - 2 pi mx delta / (Lx Ly), 2 pi mz / Lz)
+ * with delta the current offset, for mx = 0 .. nx-1, my = -my_max ..
+ * my_max and the given mz (S(-q) = S(q): mx >= 0 covers the plane).
+ * out (host): replicas x nx x (2 my_max + 1) doubles, row-major.  FP64
+ * throughout, deterministic.  kernel_ms (optional) receives the duration
+ * of the contraction kernel, measured with HIP events bracketing its
+ * launch.  1 <= nx <= 256, 0 <= my_max <= 128, |mz| <= 256, else
+ * SIM_EINVAL.  Device scratch of the handle grows on demand.              */
+int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, double* out,
+                         double* kernel_ms);
+
 /* Run the library's work on this HIP stream (hipStream_t as void*; NULL is
  * the default stream).  The caller keeps the stream alive.                 */
 int sim_set_stream(sim_t* sim, void* hip_stream);
@@ -280,9 +296,11 @@ int sim_debug_precond(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, in
 
 /* Kernel timing probe (measurement, not part of the method).  With
  * sample_every > 0, every sample_every-th CG iteration of later solves has
- * its three kernels bracketed by HIP events on the library's stream; only
- * iterations in which every component of every replica was still iterating
- * are kept, so each kept launch did the full work of one iteration.
+ * its three kernels bracketed by HIP events on the library's stream (the
+ * sampled residue of the iteration index advances by one per solve, so
+ * every position in a solve is sampled alike); only iterations in which
+ * every component of every replica was still iterating are kept, so each
+ * kept launch did the full work of one iteration.
  * sample_every = 0 switches the probe off.                                */
 typedef struct sim_kernel_prof {
   char name[32];         /* kernel name */
@@ -302,6 +320,16 @@ int sim_profile_read(sim_t* sim, sim_kernel_prof* out, int32_t cap, int32_t* cou
  * (achievable HBM bandwidth, counter calibration), not part of the method. */
 int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* hip_stream,
                    double* ms_avg);
+
+/* What timing one launch with events adds (measurement reference).  The
+ * copy of sim_copy_probe runs reps times back to back between one event
+ * pair (*ms_chain: mean per copy, the pair's own cost spread over reps) and
+ * reps times more, each after an untimed copy and between the launch-bound
+ * event pair the kernel timing probe uses (*ms_each: mean per copy).
+ * *ms_each - *ms_chain is the time the probe's events add to each timed
+ * launch.  1 <= reps <= 256; device pointers as sim_copy_probe.           */
+int sim_event_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* hip_stream,
+                    double* ms_chain, double* ms_each);
 
 /* Whole steps as HIP graphs (batched replicas, many short launches).
  * on != 0: from the second step on, sim_step records one graph per step

@@ -7,6 +7,8 @@
 // sim_dev.h; reductions are deterministic (fixed trees, per-replica "last
 // block finishes" with integer arrival counters, no float atomics).
 #include "sim_dev.h"
+
+#include <hip/hip_ext.h>
 #include "launch.h"
 
 #include <algorithm>
@@ -476,12 +478,18 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_copy16(const uint4* __restric
 // ===========================================================================
 static inline unsigned nb_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+// ev0/ev1 (optional): the launch-bound event pair of the kernel timing probe
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t n16 = bytes / 16;
   const int64_t want = (n16 + BLOCK_THREADS * 4 - 1) / (BLOCK_THREADS * 4);
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16));
-  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(BLOCK_THREADS), 0, s, (const uint4*)src,
-                     (uint4*)dst, n16);
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(k_copy16, dim3(grid), dim3(BLOCK_THREADS), 0, s, ev0, ev1, 0,
+                          (const uint4*)src, (uint4*)dst, n16);
+  else
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(BLOCK_THREADS), 0, s, (const uint4*)src,
+                       (uint4*)dst, n16);
   return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ hipError_t launch_export_pairs(const DevPtrs& d, int64_t* out, int64_t cap,
 hipError_t launch_export_system(const DevPtrs& d, const int64_t* id_off, int64_t* rows,
                                 int64_t* cols, double* vals, int64_t cap, double* diag,
                                 double* rhs, hipStream_t s);
-hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s);
 hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
@@ -49,3 +50,14 @@ hipError_t launch_mp_probe(const DevPtrs& d, double* z, double* b, uint64_t seed
                            hipStream_t s);
 hipError_t launch_mp_export(const DevPtrs& d, const MpPtrs& m, const int64_t* id_off, int64_t* rows,
                             int64_t* cols, double* vals, int64_t cap, double* diag, hipStream_t s);
+
+// structure factor (sq.hip)
+#include <vector>
+int64_t sq_chunk_count(const std::vector<int64_t>& rep_rows);
+int64_t sq_tile_count(int nx, int my_max);
+size_t sq_chunk_bytes();
+size_t sq_partial_bytes(int64_t nchunk, int nx, int my_max);
+hipError_t launch_sq(const DevPtrs& d, const std::vector<int64_t>& rep_row0,
+                     const std::vector<int64_t>& rep_rows, int nx, int my_max, int mz,
+                     void* chunks_d, int32_t* rep_chunk0_d, double2* partial_d, double* out_d,
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

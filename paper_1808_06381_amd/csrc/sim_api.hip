@@ -67,6 +67,7 @@ struct sim_t {
   int32_t restarts_last = 0;
   // kernel timing probe
   int32_t prof_every = 0;
+  int32_t prof_phase = 0;               // sampled residue of the iteration index
   std::vector<hipEvent_t> prof_ev;      // pool of event pairs
   struct Sample { int kernel; int iter; int ev; float ms; };
   std::vector<Sample> prof_pending;     // recorded in the current solve
@@ -96,6 +97,8 @@ struct sim_t {
   // IC(0) preconditioner
   bool ic0 = false;
   bool warm = false;         // step solves start from the previous velocities
+  void* sq_scratch = nullptr;  // structure-factor scratch (grown on demand)
+  size_t sq_bytes = 0;
   std::vector<int32_t> ic_color_off;  // offsets of the colours in d.ic_cells (host copy)
   sim_tuning tune{};
 };
@@ -421,7 +424,7 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
   const bool ext = d.learned || d.ic0;  // a separate preconditioner pass
   for (int k = 0; k < n; ++k) {
     const int g = first + k;
-    const bool probe = probes && s->prof_every > 0 && g % s->prof_every == 0 &&
+    const bool probe = probes && s->prof_every > 0 && g % s->prof_every == s->prof_phase &&
                        (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
     // vector update, then (learned) u = M^-1 r, then w = A u
     const int order[3] = {0, 2, 1};
@@ -543,6 +546,9 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
       acc.bytes += per_launch[smp.kernel];
     }
     s->prof_pending.clear();
+    // the next solve samples the next residue, so that every position in a
+    // solve is sampled alike (its first iterations run with colder caches)
+    s->prof_phase = (s->prof_phase + 1) % s->prof_every;
   }
   if (st) {
     for (int k = 0; k < 3; ++k) {
@@ -918,8 +924,8 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
   HIPCHK(launch_cg_vec(d, 0, s->stream));
   if (d.learned) HIPCHK(launch_cg_apply(d, 0, s->stream));
   hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   sim_tuning t{};
   int kinds = d.learned ? 2 : 1;
   hipError_t err = hipSuccess;
@@ -1381,9 +1387,13 @@ int sim_profile_enable(sim_t* s, int32_t sample_every) {
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   if (sample_every > 0 && s->prof_ev.empty()) {
     s->prof_ev.resize(2 * kProfKernels * 256);
-    for (auto& e : s->prof_ev) HIPCHK(hipEventCreate(&e));
+    // timing-only events: no system-scope fence (cache write-back and
+    // invalidation) when they complete, which would lengthen and perturb
+    // the bracketed kernel; they are read after the solve's own sync
+    for (auto& e : s->prof_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   s->prof_every = sample_every;
+  s->prof_phase = 0;
   return SIM_OK;
 }
 
@@ -1403,8 +1413,8 @@ int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void
   if (!src || !dst || bytes <= 0 || bytes % 16 || reps < 1 || !ms_avg) return SIM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   HIPCHK(launch_copy16(src, dst, bytes, st));  // untimed first touch
   HIPCHK(hipEventRecord(e0, st));
   for (int k = 0; k < reps; ++k) HIPCHK(launch_copy16(src, dst, bytes, st));
@@ -1415,6 +1425,99 @@ int sim_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms_avg = (double)ms / reps;
+  return SIM_OK;
+}
+
+int sim_event_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* stream,
+                    double* ms_chain, double* ms_each) {
+  if (!src || !dst || bytes <= 0 || bytes % 16 || reps < 1 || reps > 256 || !ms_chain || !ms_each)
+    return SIM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<hipEvent_t> ev(2 * (size_t)reps + 2, nullptr);
+  hipError_t err = hipSuccess;
+  for (auto& e : ev)
+    if ((err = hipEventCreateWithFlags(&e, hipEventDisableSystemFence))) break;
+  float chain = 0.0f, each = 0.0f;
+  if (!err) err = launch_copy16(src, dst, bytes, st);  // untimed first touch
+  // a chain of reps copies between one event pair
+  if (!err) err = hipEventRecord(ev[0], st);
+  for (int k = 0; k < reps && !err; ++k) err = launch_copy16(src, dst, bytes, st);
+  if (!err) err = hipEventRecord(ev[1], st);
+  // reps copies, each after an untimed one and between its own launch-bound
+  // pair, as the kernel timing probe times the CG kernels
+  for (int k = 0; k < reps && !err; ++k) {
+    err = launch_copy16(src, dst, bytes, st);
+    if (!err) err = launch_copy16(src, dst, bytes, st, ev[2 + 2 * k], ev[3 + 2 * k]);
+  }
+  if (!err) err = hipStreamSynchronize(st);
+  if (!err) err = hipEventElapsedTime(&chain, ev[0], ev[1]);
+  for (int k = 0; k < reps && !err; ++k) {
+    float ms = 0.0f;
+    err = hipEventElapsedTime(&ms, ev[2 + 2 * k], ev[3 + 2 * k]);
+    each += ms;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (err) {
+    sim_note_error(err, "event probe", __LINE__);
+    return SIM_EDEVICE;
+  }
+  *ms_chain = (double)chain / reps;
+  *ms_each = (double)each / reps;
+  return SIM_OK;
+}
+
+int sim_structure_factor(sim_t* s, int32_t nx, int32_t my_max, int32_t mz, double* out,
+                         double* kernel_ms) {
+  if (!s || !out || nx < 1 || nx > 256 || my_max < 0 || my_max > 128 || mz < -256 || mz > 256)
+    return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  std::vector<int64_t> row0, rows;
+  for (const RepDev& R : s->reph) {
+    row0.push_back(R.row_off);
+    rows.push_back(R.n);
+  }
+  const int64_t nchunk = sq_chunk_count(rows);
+  const int ny = 2 * my_max + 1;
+  // scratch: chunk table | chunk offsets | partial sums | output
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_ch = up(sq_chunk_bytes() * (size_t)std::max<int64_t>(nchunk, 1));
+  const size_t b_c0 = up(sizeof(int32_t) * (s->reph.size() + 1));
+  const size_t b_pa = up(sq_partial_bytes(std::max<int64_t>(nchunk, 1), nx, my_max));
+  const size_t b_out = up(sizeof(double) * s->reph.size() * (size_t)nx * ny);
+  const size_t need = b_ch + b_c0 + b_pa + b_out;
+  if (need > s->sq_bytes) {
+    dfree(s, s->sq_scratch);
+    s->sq_scratch = nullptr;
+    s->sq_bytes = 0;
+    int rc = dalloc(s, &s->sq_scratch, need);
+    if (rc) return rc;
+    s->sq_bytes = need;
+  }
+  char* base = (char*)s->sq_scratch;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+  }
+  hipError_t err = launch_sq(s->d, row0, rows, nx, my_max, mz, base, (int32_t*)(base + b_ch),
+                             (double2*)(base + b_ch + b_c0), (double*)(base + b_ch + b_c0 + b_pa),
+                             s->stream, e0, e1);
+  if (!err)
+    err = hipMemcpyAsync(out, base + b_ch + b_c0 + b_pa, sizeof(double) * s->reph.size() * nx * ny,
+                         hipMemcpyDeviceToHost, s->stream);
+  if (!err) err = hipStreamSynchronize(s->stream);
+  if (!err && kernel_ms) {
+    float ms = 0.0f;
+    err = hipEventElapsedTime(&ms, e0, e1);
+    *kernel_ms = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err) {
+    sim_note_error(err, "structure factor", __LINE__);
+    return SIM_EDEVICE;
+  }
   return SIM_OK;
 }
 

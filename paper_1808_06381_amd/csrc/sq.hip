@@ -1,0 +1,215 @@
+// sq.hip -- structure factor of the blob centres (Results section, Eq.
+// Sfactor) on gfx950: S(q) = |rho(q)|^2 / C, rho(q) = sum_c exp(-i q . R_c),
+// for one configuration of each replica.
+//
+// Wavevectors.  A Lees-Edwards box with offset delta has its images at
+// R + a Lx x + b (Ly y + delta x) + c Lz z; the wavevectors that give every
+// image the same phase are
+//   q = (2 pi mx / Lx, 2 pi my / Ly - 2 pi mx delta / (Lx Ly), 2 pi mz / Lz)
+// for integer (mx, my, mz), so that q . R = 2 pi (mx sx + my sy + mz sz) in
+// the sheared fractional coordinates sx = x / Lx - delta y / (Lx Ly),
+// sy = y / Ly, sz = z / Lz.  The phase factorises,
+//   exp(-i q . R_c) = A_c(mx) B_c(my),  A_c(mx) = exp(-2 pi i mx sx),
+//   B_c(my) = exp(-2 pi i (my sy + mz sz)),
+// so on an (mx, my) grid rho = sum_c A_c(mx) B_c(my) is a complex dense
+// contraction over particles whose operands are generated on the fly: the
+// work is FP64 arithmetic, not memory traffic (a particle's 24 bytes feed
+// nx * ny complex products).
+//
+// Layout.  k_sq_partial: a block takes one tile of 64 mx x 32 my values and
+// one chunk of one replica's rows; per group of 32 particles it writes the
+// A and B tables to LDS (sincospi, exact argument scaling), then each thread
+// adds the products of its 4 x 2 outputs in registers, particles in row
+// order.  k_sq_reduce: per replica and q, the chunks' partial sums in chunk
+// order, then |rho|^2 / C.  No floating-point atomics: the result is
+// deterministic.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "launch.h"
+#include "sim_dev.h"
+
+namespace {
+
+constexpr int SQ_THREADS = 256;
+constexpr int SQ_TX = 64;        // mx per tile
+constexpr int SQ_TY = 32;        // my per tile
+constexpr int SQ_PX = 4;         // mx per thread
+constexpr int SQ_PY = 2;         // my per thread
+constexpr int SQ_P = 32;         // particles per LDS group
+static_assert((SQ_TX / SQ_PX) * (SQ_TY / SQ_PY) == SQ_THREADS, "one 4 x 2 block per thread");
+
+struct SqChunk {
+  int32_t rep;     // replica
+  int32_t pad;
+  int64_t row0;    // first row
+  int64_t rows;    // rows of the chunk (all real particles)
+};
+
+}  // namespace
+
+// partial[(chunk * ntile + tile) * SQ_TX * SQ_TY + o] = sum over the chunk's
+// particles of A(mx) B(my), o = (mx - mx0) * SQ_TY + (my - my0); complex as
+// double2 (re, im)
+__global__ __launch_bounds__(SQ_THREADS) void k_sq_partial(DevPtrs d, const SqChunk* __restrict__ chunks,
+                                                           int nx, int my_max, int mz, int tiles_y,
+                                                           double2* __restrict__ partial) {
+  __shared__ double2 A[SQ_P][SQ_TX];
+  __shared__ double2 B[SQ_P][SQ_TY];
+  const int tile = blockIdx.x, ci = blockIdx.y;
+  const SqChunk ch = chunks[ci];
+  const RepDev& R = d.rep[ch.rep];
+  const int mx0 = (tile / tiles_y) * SQ_TX;
+  const int my0 = -my_max + (tile % tiles_y) * SQ_TY;
+  const double delta = le_offset(R, *d.step_d);
+  const double ilx = 1.0 / R.L[0], ily = 1.0 / R.L[1], ilz = 1.0 / R.L[2];
+  const int t = threadIdx.x;
+  const int tx = (t / (SQ_TY / SQ_PY)) * SQ_PX, ty = (t % (SQ_TY / SQ_PY)) * SQ_PY;
+  double acc[SQ_PX][SQ_PY][2];
+#pragma unroll
+  for (int a = 0; a < SQ_PX; ++a)
+#pragma unroll
+    for (int b = 0; b < SQ_PY; ++b) acc[a][b][0] = acc[a][b][1] = 0.0;
+  for (int64_t g = 0; g < ch.rows; g += SQ_P) {
+    const int np = (int)min<int64_t>(SQ_P, ch.rows - g);
+    // phase tables of this group: A[p][mx - mx0], B[p][my - my0]
+    for (int w = t; w < SQ_P * (SQ_TX + SQ_TY); w += SQ_THREADS) {
+      const int p = w / (SQ_TX + SQ_TY), k = w % (SQ_TX + SQ_TY);
+      double s = 0.0, c = 1.0;  // missing particles contribute 0 (A = 0 below)
+      bool ok = p < np;
+      if (ok) {
+        const double4 r = d.pos[ch.row0 + g + p];
+        if (k < SQ_TX) {
+          const double sx = r.x * ilx - delta * r.y * (ilx * ily);
+          // exp(-2 pi i m sx) = cos(2 pi m sx) - i sin(2 pi m sx)
+          sincospi(2.0 * (double)(mx0 + k) * sx, &s, &c);
+        } else {
+          const double sy = r.y * ily, sz = r.z * ilz;
+          sincospi(2.0 * ((double)(my0 + k - SQ_TX) * sy + (double)mz * sz), &s, &c);
+        }
+      }
+      if (k < SQ_TX) A[p][k] = ok ? make_double2(c, -s) : make_double2(0.0, 0.0);
+      else B[p][k - SQ_TX] = make_double2(c, -s);
+    }
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+      double2 av[SQ_PX], bv[SQ_PY];
+#pragma unroll
+      for (int a = 0; a < SQ_PX; ++a) av[a] = A[p][tx + a];
+#pragma unroll
+      for (int b = 0; b < SQ_PY; ++b) bv[b] = B[p][ty + b];
+#pragma unroll
+      for (int a = 0; a < SQ_PX; ++a)
+#pragma unroll
+        for (int b = 0; b < SQ_PY; ++b) {
+          // complex multiply-add as four FP64 fused multiply-adds
+          acc[a][b][0] = fma(av[a].x, bv[b].x, acc[a][b][0]);
+          acc[a][b][0] = fma(-av[a].y, bv[b].y, acc[a][b][0]);
+          acc[a][b][1] = fma(av[a].x, bv[b].y, acc[a][b][1]);
+          acc[a][b][1] = fma(av[a].y, bv[b].x, acc[a][b][1]);
+        }
+    }
+    __syncthreads();  // the tables are rewritten for the next group
+  }
+  const int64_t base = ((int64_t)ci * gridDim.x + tile) * (SQ_TX * SQ_TY);
+#pragma unroll
+  for (int a = 0; a < SQ_PX; ++a)
+#pragma unroll
+    for (int b = 0; b < SQ_PY; ++b)
+      partial[base + (tx + a) * SQ_TY + ty + b] = make_double2(acc[a][b][0], acc[a][b][1]);
+  (void)nx;
+}
+
+// out[(rep * nx + mx) * ny + (my + my_max)] = |sum of the replica's chunk
+// partials in chunk order|^2 / C
+__global__ __launch_bounds__(256) void k_sq_reduce(DevPtrs d, const int32_t* __restrict__ rep_chunk0,
+                                                   int nrep, int nx, int my_max, int tiles_y,
+                                                   int ntile, const double2* __restrict__ partial,
+                                                   double* __restrict__ out) {
+  const int ny = 2 * my_max + 1;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= (int64_t)nrep * nx * ny) return;
+  const int rep = (int)(o / ((int64_t)nx * ny));
+  const int q = (int)(o % ((int64_t)nx * ny));
+  const int mx = q / ny, myi = q % ny;
+  const int tile = (mx / SQ_TX) * tiles_y + myi / SQ_TY;
+  const int off = (mx % SQ_TX) * SQ_TY + myi % SQ_TY;
+  double re = 0.0, im = 0.0;
+  for (int c = rep_chunk0[rep]; c < rep_chunk0[rep + 1]; ++c) {
+    const double2 v = partial[((int64_t)c * ntile + tile) * (SQ_TX * SQ_TY) + off];
+    re += v.x;
+    im += v.y;
+  }
+  const int n = d.rep[rep].n;
+  out[o] = n > 0 ? (re * re + im * im) / (double)n : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host side: chunking and launches (device scratch from the caller)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t SQ_CHUNK = 4096;  // rows per block
+}
+
+int64_t sq_chunk_count(const std::vector<int64_t>& rep_rows) {
+  int64_t c = 0;
+  for (int64_t n : rep_rows) c += (n + SQ_CHUNK - 1) / SQ_CHUNK;
+  return c;
+}
+
+int64_t sq_tile_count(int nx, int my_max) {
+  const int ny = 2 * my_max + 1;
+  return (int64_t)((nx + SQ_TX - 1) / SQ_TX) * ((ny + SQ_TY - 1) / SQ_TY);
+}
+
+size_t sq_chunk_bytes() { return sizeof(SqChunk); }
+size_t sq_partial_bytes(int64_t nchunk, int nx, int my_max) {
+  return (size_t)nchunk * (size_t)sq_tile_count(nx, my_max) * SQ_TX * SQ_TY * sizeof(double2);
+}
+
+// rep_row0 / rep_rows: first row and real particles of each replica;
+// chunks_d (sq_chunk_bytes() x count) and rep_chunk0_d (nrep + 1 int32)
+// are device scratch, filled here from the host tables; ev0/ev1 (optional)
+// bracket the contraction kernel's launch
+hipError_t launch_sq(const DevPtrs& d, const std::vector<int64_t>& rep_row0,
+                     const std::vector<int64_t>& rep_rows, int nx, int my_max, int mz,
+                     void* chunks_d, int32_t* rep_chunk0_d, double2* partial_d, double* out_d,
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  std::vector<SqChunk> ch;
+  std::vector<int32_t> c0;
+  for (size_t r = 0; r < rep_rows.size(); ++r) {
+    c0.push_back((int32_t)ch.size());
+    for (int64_t a = 0; a < rep_rows[r]; a += SQ_CHUNK)
+      ch.push_back({(int32_t)r, 0, rep_row0[r] + a, std::min<int64_t>(SQ_CHUNK, rep_rows[r] - a)});
+  }
+  c0.push_back((int32_t)ch.size());
+  hipError_t e;
+  if (!ch.empty() &&
+      (e = hipMemcpyAsync(chunks_d, ch.data(), ch.size() * sizeof(SqChunk), hipMemcpyHostToDevice, s)))
+    return e;
+  if ((e = hipMemcpyAsync(rep_chunk0_d, c0.data(), c0.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s)))
+    return e;
+  const int ny = 2 * my_max + 1;
+  const int tiles_y = (ny + SQ_TY - 1) / SQ_TY;
+  const int ntile = (int)sq_tile_count(nx, my_max);
+  if (!ch.empty()) {
+    const dim3 g(ntile, (unsigned)ch.size()), b(SQ_THREADS);
+    if (ev0 || ev1)
+      hipExtLaunchKernelGGL(k_sq_partial, g, b, 0, s, ev0, ev1, 0, d, (const SqChunk*)chunks_d,
+                            nx, my_max, mz, tiles_y, partial_d);
+    else
+      hipLaunchKernelGGL(k_sq_partial, g, b, 0, s, d, (const SqChunk*)chunks_d, nx, my_max, mz,
+                         tiles_y, partial_d);
+  }
+  const int64_t nout = (int64_t)rep_rows.size() * nx * ny;
+  hipLaunchKernelGGL(k_sq_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, d,
+                     rep_chunk0_d, (int)rep_rows.size(), nx, my_max, tiles_y, ntile, partial_d,
+                     out_d);
+  // host tables must outlive the asynchronous copies
+  if ((e = hipStreamSynchronize(s))) return e;
+  return hipGetLastError();
+}

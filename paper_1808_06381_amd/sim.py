@@ -26,7 +26,8 @@ PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
 EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
             "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
-            "sim_copy_probe", "sim_precond_weights", "sim_precond_config", "sim_train_step",
+            "sim_copy_probe", "sim_event_probe", "sim_structure_factor", "sim_precond_weights",
+            "sim_precond_config", "sim_train_step",
             "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
             "sim_autotune", "sim_set_tuning", "sim_train_probe", "sim_precond_optimizer",
             "sim_destroy", "sim_strerror"]
@@ -136,6 +137,8 @@ def lib():
         L.sim_step.argtypes = [vp, C.c_int32, P(SimStats)]
         L.sim_solve.argtypes = [vp, vp, vp, C.c_double, C.c_uint32, P(SimStats)]
         L.sim_state.argtypes = [vp, vp, vp, P(SimMeta), C.c_uint32]
+        L.sim_structure_factor.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp,
+                                           P(C.c_double)]
         L.sim_set_stream.argtypes = [vp, vp]
         L.sim_load_precond.argtypes = [vp, C.c_char_p]
         L.sim_debug_pairs.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
@@ -144,6 +147,8 @@ def lib():
         L.sim_profile_enable.argtypes = [vp, C.c_int32]
         L.sim_profile_read.argtypes = [vp, P(SimKernelProf), C.c_int32, P(C.c_int32), C.c_int32]
         L.sim_copy_probe.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_double)]
+        L.sim_event_probe.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_double),
+                                      P(C.c_double)]
         L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
         L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
         L.sim_graph_mode.argtypes = [vp, C.c_int32]
@@ -215,6 +220,7 @@ class Sim:
                                         for c in cfgs])
         pos0 = np.ascontiguousarray(pos0, dtype=np.float64).reshape(-1, 3)
         self.n_total = sum(int(c["n"]) for c in cfgs)
+        self.replicas = len(cfgs)
         if pos0.shape[0] != self.n_total:
             raise ValueError("pos0 rows != total particles")
         h = C.c_void_p()
@@ -271,6 +277,19 @@ class Sim:
         _check(lib().sim_state(self.h, _ptr(pos), _ptr(vel), C.byref(meta), 0), "sim_state")
         return pos, vel, dict(step=meta.step, time=meta.time, le_offset=meta.le_offset,
                               replicas=meta.replicas, n_total=meta.n_total)
+
+    def structure_factor(self, nx, my_max, mz=0, timed=False):
+        """S(q) of every replica on the Lees-Edwards grid: array (replicas,
+        nx, 2 my_max + 1), [r, mx, my + my_max]; with timed=True also the
+        contraction kernel's duration in ms."""
+        ny = 2 * int(my_max) + 1
+        # sized for valid arguments; the library rejects the others
+        out = np.zeros((self.replicas, max(int(nx), 0), max(ny, 0)))
+        ms = C.c_double()
+        _check(lib().sim_structure_factor(self.h, int(nx), int(my_max), int(mz), _ptr(out),
+                                          C.byref(ms) if timed else None),
+               "sim_structure_factor")
+        return (out, ms.value) if timed else out
 
     def pairs(self):
         """Unordered pairs as an int64 (m, 3) array of (replica, i, j), sorted."""
@@ -412,6 +431,19 @@ class Sim:
 
     def load_precond(self, path):
         _check(lib().sim_load_precond(self.h, path.encode()), "sim_load_precond")
+
+
+def event_probe(src, dst, reps=64, stream=None):
+    """(ms per copy in a chain between one event pair, ms per copy each
+    between its own launch-bound event pair): the difference is what the
+    kernel timing probe's events add to a timed launch."""
+    chain, each = C.c_double(), C.c_double()
+    raw = getattr(stream, "cuda_stream", stream) or 0
+    nbytes = src.numel() * src.element_size()
+    _check(lib().sim_event_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                 int(reps), C.c_void_p(raw), C.byref(chain), C.byref(each)),
+           "sim_event_probe")
+    return chain.value, each.value
 
 
 def copy_probe(src, dst, reps=20, stream=None):
