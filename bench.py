@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec at CG rel. residual 1e-8; learned-PCG vs plain-PCG, same GPU"
 PEAK_HBM_GBS = 8000.0
+# FP64 vector FMA peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
 SHEARS = (0.01, 0.1, 0.5)
 
 
@@ -110,7 +112,26 @@ def cpu_baseline(cfg, pos0, steps, tol):
                        f"{dt:.1f} s")
 
 
-def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label=""):
+def measure_sq(sim, n, np, nx=64, my_max=64, reps=3):
+    """Structure factor of the final state (Eq. Sfactor, 64 x 129 wavevectors,
+    mz = 0): the contraction kernel's event-timed duration less the event
+    overhead, and its FP64 rate at 8 flops (one complex multiply-add) per
+    particle and wavevector."""
+    sim.structure_factor(nx, my_max)  # untimed first call (scratch, code load)
+    ms = []
+    for _ in range(reps):
+        s, t = sim.structure_factor(nx, my_max, timed=True)
+        ms.append(t)
+    ny = 2 * my_max + 1
+    kernel_ms = float(np.mean(ms))
+    flops = 8.0 * n * nx * ny
+    return dict(grid=f"mx 0..{nx - 1} x my -{my_max}..{my_max}, mz 0", particles=n,
+                kernel_ms_events=round(kernel_ms, 4), flops_per_call=flops,
+                s_q0=float(s[0, 0, my_max]))
+
+
+def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label="",
+              after=None):
     """Warm up, then time `steps` bench steps of the systems (one handle per
     entry of cfgs; an entry may be a list of replicas) with one CG form."""
     steps = args.steps if steps is None else steps
@@ -148,6 +169,7 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
             rowstat[q] = (st["nnz"], st["max_row"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    extra = after(sims) if after else None
     prof = {}
     graphs = dict(captures=0, replays=0)
     for sim in sims:
@@ -181,7 +203,8 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
     rows = dict(mean_offdiag_per_row=round(sum(r[0] for r in rowstat) / sum(ns), 3),
                 max_row=max(r[1] for r in rowstat))
     return dict(value=value, elapsed=elapsed, iters=iters, kernels=kernels, fallbacks=fallbacks,
-                graphs=graphs, particles=particles, steps=steps, tuning=tuned, rows=rows)
+                graphs=graphs, particles=particles, steps=steps, tuning=tuned, rows=rows,
+                extra=extra)
 
 
 def run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs):
@@ -289,9 +312,10 @@ def main():
                copy_gbs)
         return
     runs = {}
+    head = "learned" if "learned" in forms else forms[0]
     for form in forms:
-        runs[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np)
-    head = "learned" if "learned" in runs else forms[0]
+        after = (lambda sims: measure_sq(sims[0], cfgs[0]["n"], np)) if form == head else None
+        runs[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, after=after)
     hr = runs[head]
     value = hr["value"]
     elapsed = hr["elapsed"]
@@ -350,6 +374,17 @@ def main():
                   for f, r in runs.items()},
         "graph_steps": not args.no_graph,
     }
+    sqm = hr.get("extra")
+    if sqm:
+        # structure factor of the first box's final state: the contraction
+        # kernel is bound by FP64 FMA throughput (the 24 bytes of a particle
+        # feed nx * ny complex multiply-adds)
+        ms = sqm["kernel_ms_events"] - args.event_over_us * 1e-3
+        tf = sqm["flops_per_call"] / (ms * 1e-3) / 1e12
+        out["structure_factor"] = dict(
+            sqm, kernel="k_sq_partial", kernel_ms=round(ms, 4),
+            roofline=dict(bound="alu", achieved=round(tf, 2), peak=PEAK_FP64_TFLOPS,
+                          unit="TFLOP/s", frac=round(tf / PEAK_FP64_TFLOPS, 4)))
     if "learned" in runs and "plain" in runs:
         out["learned_vs_plain"] = round(runs["learned"]["value"] / runs["plain"]["value"], 4)
     if args.batch > 0:
