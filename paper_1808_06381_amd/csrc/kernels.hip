@@ -240,31 +240,52 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->nnz = d.rowptr[d.rows];
 }
 
-// Pair terms and assembly, PAIR_LANES lanes per row over the row's CSR
-// entries: -alpha*w_ij into val, diag = gamma0 + alpha*sum w, 1/diag, and the
-// three right-hand sides: Couette drive (Eq. 6c), conservative force
-// (Eq. 6b), boundary velocity term of Eq. 8, thermal force.
-#define PAIR_LANES 4
-#define PAIR_THREADS 256  // fewer threads per block: the pair noise needs ~130 registers
+// Pair terms and assembly: -alpha*w_ij into val, diag = gamma0 + alpha*sum w,
+// 1/diag, and the three right-hand sides: Couette drive (Eq. 6c),
+// conservative force (Eq. 6b), boundary velocity term of Eq. 8, thermal
+// force.  A block owns a tile of 1024 rows and walks the tile's CSR entries
+// (contiguous) in chunks of PAIR_THREADS, one entry per lane, so every lane
+// has an entry to work on whatever the row lengths; each entry leaves its
+// five row contributions (w, w s, and the three force components with the
+// pair noise) in LDS, and each thread then adds those of its four rows in
+// entry order.  The node noise and the assembly run once per row.
+#define PAIR_THREADS 256
+#define PAIR_ROWS_PER_THREAD (ROWS_PER_BLOCK / PAIR_THREADS)
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
   const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
   if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   if (d.ctrl->overflow) return;
+  __shared__ int rp[ROWS_PER_BLOCK + 1];      // row pointers of the tile
+  __shared__ int16_t erow[PAIR_THREADS];      // tile row of each entry of the chunk
+  __shared__ double contrib[5][PAIR_THREADS]; // w, w s, fx, fy, fz of each entry
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blk * ROWS_PER_BLOCK;
+  for (int r = t; r <= ROWS_PER_BLOCK; r += PAIR_THREADS) rp[r] = d.rowptr[row0 + r];
+  __syncthreads();
   const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
-  const double drag_unit = R.alpha * (R.shear * R.L[1]);
-  const int lane = threadIdx.x & (PAIR_LANES - 1);
-  const int grp = threadIdx.x / PAIR_LANES;
-  constexpr int GROUPS = PAIR_THREADS / PAIR_LANES;
-  for (int pass = 0; pass < ROWS_PER_BLOCK / GROUPS; ++pass) {
-    const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + pass * GROUPS + grp;
-    const bool real = i - R.row_off < R.n;
-    const double4 pi = d.pos[i];
-    const int64_t idi = (int64_t)pi.w;
-    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
-    double wsum = 0.0, ws = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
-    for (int e = e0 + lane; e < e1; e += PAIR_LANES) {
+  const bool noise = R.amp_pair != 0.0 && R.alpha != 0.0;
+  // this thread's rows: t, t + 256, t + 512, t + 768 (tile-local)
+  double acc[PAIR_ROWS_PER_THREAD][5];
+#pragma unroll
+  for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[q][k] = 0.0;
+  const int E0 = rp[0], E1 = rp[ROWS_PER_BLOCK];
+  for (int cb = E0; cb < E1; cb += PAIR_THREADS) {
+    // the tile row of each entry of this chunk
+#pragma unroll
+    for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
+      const int r = t + q * PAIR_THREADS;
+      const int lo = max(rp[r], cb), hi = min(rp[r + 1], cb + PAIR_THREADS);
+      for (int e = lo; e < hi; ++e) erow[e - cb] = (int16_t)r;
+    }
+    __syncthreads();
+    const int e = cb + t;
+    if (e < E1) {
+      const int64_t i = row0 + erow[t];
+      const double4 pi = d.pos[i];
       const int j = d.col[e];
       const double4 pj = d.pos[j];
       double dx, dy, dz;
@@ -275,14 +296,10 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
       d.val[e] = -R.alpha * w;
       d.valf[e] = (float)(-R.alpha * w);
       d.er[e] = (float)(r / R.rc);
-      wsum += w;
-      ws += w * (double)s;
       const double fc = force_coef(R, r2, r);
-      bx += fc * dx;
-      by += fc * dy;
-      bz += fc * dz;
-      if (R.amp_pair != 0.0 && R.alpha != 0.0) {
-        const int64_t idj = (int64_t)pj.w;
+      double fx = fc * dx, fy = fc * dy, fz = fc * dz;
+      if (noise) {
+        const int64_t idi = (int64_t)pi.w, idj = (int64_t)pj.w;
         const int64_t a = idi < idj ? idi : idj, bb = idi < idj ? idj : idi;
         double g[3];
         if (d.inj_eta) {
@@ -292,24 +309,39 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
           gauss3(R.seed, R.stream, (uint64_t)step, 1, (uint64_t)a, (uint64_t)bb, g);
         }
         const double amp = (idi < idj ? 1.0 : -1.0) * R.amp_pair * sqrt(R.alpha * w);
-        bx += amp * g[0];
-        by += amp * g[1];
-        bz += amp * g[2];
+        fx += amp * g[0];
+        fy += amp * g[1];
+        fz += amp * g[2];
       }
+      contrib[0][t] = w;
+      contrib[1][t] = w * (double)s;
+      contrib[2][t] = fx;
+      contrib[3][t] = fy;
+      contrib[4][t] = fz;
     }
+    __syncthreads();
 #pragma unroll
-    for (int o = 1; o < PAIR_LANES; o <<= 1) {
-      wsum += __shfl_xor(wsum, o, 64);
-      ws += __shfl_xor(ws, o, 64);
-      bx += __shfl_xor(bx, o, 64);
-      by += __shfl_xor(by, o, 64);
-      bz += __shfl_xor(bz, o, 64);
+    for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
+      const int r = t + q * PAIR_THREADS;
+      const int lo = max(rp[r], cb), hi = min(rp[r + 1], cb + PAIR_THREADS);
+      for (int e2 = lo; e2 < hi; ++e2)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[q][k] += contrib[k][e2 - cb];
     }
-    if (!real) {
-      if (lane == 0) { d.diag[i] = 1.0; d.dinv[i] = 1.0; }
-      if (lane < 3) d.b[3 * i + lane] = 0.0;
+    __syncthreads();  // erow and contrib are rewritten for the next chunk
+  }
+  const double drag_unit = R.alpha * (R.shear * R.L[1]);
+#pragma unroll
+  for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
+    const int64_t i = row0 + t + q * PAIR_THREADS;
+    if (i - R.row_off >= R.n) {  // padding row: identity, no right-hand side
+      d.diag[i] = 1.0;
+      d.dinv[i] = 1.0;
+      d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
       continue;
     }
+    const double4 pi = d.pos[i];
+    const int64_t idi = (int64_t)pi.w;
     double g[3] = {0.0, 0.0, 0.0};
     if (R.amp_node != 0.0) {
       if (d.inj_xi) {
@@ -318,16 +350,13 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
         gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, g);
       }
     }
-    if (lane == 0) {
-      const double dg = R.gamma0 + R.alpha * wsum;
-      d.diag[i] = dg;
-      d.dinv[i] = 1.0 / dg;
-      d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * g[0] + bx + drag_unit * ws;
-    } else if (lane == 1) {
-      d.b[3 * i + 1] = R.amp_node * g[1] + by;
-    } else if (lane == 2) {
-      d.b[3 * i + 2] = R.amp_node * g[2] + bz;
-    }
+    const double dg = R.gamma0 + R.alpha * acc[q][0];
+    d.diag[i] = dg;
+    d.dinv[i] = 1.0 / dg;
+    d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * g[0] + acc[q][2] +
+                 drag_unit * acc[q][1];
+    d.b[3 * i + 1] = R.amp_node * g[1] + acc[q][3];
+    d.b[3 * i + 2] = R.amp_node * g[2] + acc[q][4];
   }
 }
 

@@ -18,7 +18,8 @@
 //
 // Layout.  k_sq_partial: a block takes one tile of 64 mx x 32 my values and
 // one chunk of one replica's rows; per group of 32 particles it writes the
-// A and B tables to LDS (sincospi, exact argument scaling), then each thread
+// A and B tables to LDS (runs of 8 entries: sincospi with exact argument
+// scaling, then complex multiplication by the unit step), then each thread
 // adds the products of its 4 x 2 outputs in registers, particles in row
 // order.  k_sq_reduce: per replica and q, the chunks' partial sums in chunk
 // order, then |rho|^2 / C.  No floating-point atomics: the result is
@@ -40,6 +41,7 @@ constexpr int SQ_TY = 32;        // my per tile
 constexpr int SQ_PX = 4;         // mx per thread
 constexpr int SQ_PY = 2;         // my per thread
 constexpr int SQ_P = 32;         // particles per LDS group
+constexpr int SQ_RUN = 8;        // table entries per sincospi (complex recurrence)
 static_assert((SQ_TX / SQ_PX) * (SQ_TY / SQ_PY) == SQ_THREADS, "one 4 x 2 block per thread");
 
 struct SqChunk {
@@ -75,24 +77,40 @@ __global__ __launch_bounds__(SQ_THREADS) void k_sq_partial(DevPtrs d, const SqCh
     for (int b = 0; b < SQ_PY; ++b) acc[a][b][0] = acc[a][b][1] = 0.0;
   for (int64_t g = 0; g < ch.rows; g += SQ_P) {
     const int np = (int)min<int64_t>(SQ_P, ch.rows - g);
-    // phase tables of this group: A[p][mx - mx0], B[p][my - my0]
-    for (int w = t; w < SQ_P * (SQ_TX + SQ_TY); w += SQ_THREADS) {
-      const int p = w / (SQ_TX + SQ_TY), k = w % (SQ_TX + SQ_TY);
-      double s = 0.0, c = 1.0;  // missing particles contribute 0 (A = 0 below)
-      bool ok = p < np;
-      if (ok) {
-        const double4 r = d.pos[ch.row0 + g + p];
-        if (k < SQ_TX) {
-          const double sx = r.x * ilx - delta * r.y * (ilx * ily);
-          // exp(-2 pi i m sx) = cos(2 pi m sx) - i sin(2 pi m sx)
-          sincospi(2.0 * (double)(mx0 + k) * sx, &s, &c);
-        } else {
-          const double sy = r.y * ily, sz = r.z * ilz;
-          sincospi(2.0 * ((double)(my0 + k - SQ_TX) * sy + (double)mz * sz), &s, &c);
-        }
+    // phase tables of this group: A[p][mx - mx0], B[p][my - my0], in runs
+    // of SQ_RUN consecutive entries: the first by sincospi, the others by
+    // complex multiplication with the unit step exp(-2 pi i s) (error
+    // <= 2 (SQ_RUN - 1) ulp, against one sincospi per entry)
+    constexpr int RUNS_A = SQ_TX / SQ_RUN, RUNS = RUNS_A + SQ_TY / SQ_RUN;
+    for (int w = t; w < SQ_P * RUNS; w += SQ_THREADS) {
+      const int p = w / RUNS, run = w % RUNS;
+      if (p >= np) continue;  // the loop below reads only p < np
+      const double4 r = d.pos[ch.row0 + g + p];
+      const bool isA = run < RUNS_A;
+      const int k0 = (isA ? run : run - RUNS_A) * SQ_RUN;
+      double s0, c0, ss, cs;
+      if (isA) {
+        const double sx = r.x * ilx - delta * r.y * (ilx * ily);
+        sincospi(2.0 * (double)(mx0 + k0) * sx, &s0, &c0);
+        sincospi(2.0 * sx, &ss, &cs);
+      } else {
+        const double sy = r.y * ily, sz = r.z * ilz;
+        sincospi(2.0 * ((double)(my0 + k0) * sy + (double)mz * sz), &s0, &c0);
+        sincospi(2.0 * sy, &ss, &cs);
       }
-      if (k < SQ_TX) A[p][k] = ok ? make_double2(c, -s) : make_double2(0.0, 0.0);
-      else B[p][k - SQ_TX] = make_double2(c, -s);
+      // z = exp(-i phase) = (c, -s); step u = (cs, -ss)
+      double zr = c0, zi = -s0;
+      const double ur = cs, ui = -ss;
+      double2* dst = isA ? &A[p][k0] : &B[p][k0];
+      dst[0] = make_double2(zr, zi);
+#pragma unroll
+      for (int j = 1; j < SQ_RUN; ++j) {
+        const double nr = fma(zr, ur, -zi * ui);
+        const double ni = fma(zr, ui, zi * ur);
+        zr = nr;
+        zi = ni;
+        dst[j] = make_double2(zr, zi);
+      }
     }
     __syncthreads();
     for (int p = 0; p < np; ++p) {

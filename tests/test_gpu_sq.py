@@ -3,7 +3,9 @@ against the oracle, on the Lees-Edwards-compatible grid.
 
 Tolerance from the arithmetic: each side forms the phase 2 pi (mx sx + my sy
 + mz sz) (library) or q . R (oracle) in FP64, an error of at most about
-dtheta = 2 pi |m| * 4 eps per term (|m| = |mx| + |my| + |mz|, eps = 2^-53),
+2 pi |m| * 4 eps per term (|m| = |mx| + |my| + |mz|, eps = 2^-53), and the
+library's tables take up to 7 complex multiplications by a unit step after
+each sincospi (<= 16 eps more): dtheta = 2 pi |m| 4 eps + 16 eps per term,
 so rho = sum_c exp(-i q.R_c) may differ by N dtheta at most and
 S = |rho|^2 / N by 2 dtheta sqrt(N S) (+ dtheta^2 N); the sum order adds
 N eps per term at most, far less.  The tests allow twice that bound.
@@ -31,7 +33,7 @@ EPS = 2.0 ** -53
 
 def bound(m, n, s_ref):
     mag = np.abs(m).sum(axis=1)
-    dth = 2 * math.pi * np.maximum(mag, 1) * 4 * EPS
+    dth = 2 * math.pi * np.maximum(mag, 1) * 4 * EPS + 16 * EPS
     return 2 * (2 * dth * np.sqrt(n * np.maximum(s_ref, 0)) + dth * dth * n) + 1e-14
 
 
