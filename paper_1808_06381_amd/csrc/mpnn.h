@@ -58,6 +58,8 @@ struct MpPtrs {
   float* dh;       // [rows][H]
   float* dh2;      // [rows][H]
   float* dm;       // [rows][H]
+  uint16_t* hb;    // [rows][H] bfloat16 of the final h (the heads round it anyway)
+  uint16_t* efh;   // [nnz][4] bfloat16 edge features and a zero (likewise)
   int64_t rows;
   int round_act;   // 1: round activations entering products to bf16
   int store_train; // 1: keep m and a for the backward pass

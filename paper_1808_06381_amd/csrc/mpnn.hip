@@ -317,9 +317,15 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
       const double what = v / sqrt(di * d.diag[j]);
       s += v;
       a += what;
-      m.ef[3 * (int64_t)e + 0] = m.er[e];
-      m.ef[3 * (int64_t)e + 1] = (float)(v / alpha);
-      m.ef[3 * (int64_t)e + 2] = (float)what;
+      const float f0 = m.er[e], f1 = (float)(v / alpha), f2 = (float)what;
+      if (m.store_train) {  // the backward pass reads the FP32 features
+        m.ef[3 * (int64_t)e + 0] = f0;
+        m.ef[3 * (int64_t)e + 1] = f1;
+        m.ef[3 * (int64_t)e + 2] = f2;
+      }
+      // the forward kernels round the features to bf16 before every use
+      *reinterpret_cast<ushort4*>(m.efh + 4 * (int64_t)e) =
+          make_ushort4(bf16_bits(f0), bf16_bits(f1), bf16_bits(f2), 0);
     }
     s += __shfl_xor(s, 1, 64);
     a += __shfl_xor(a, 1, 64);
@@ -387,9 +393,8 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
       const float4* yp = reinterpret_cast<const float4*>(y + j * MP_H + 8 * q);
       const float4 y0 = yp[0], y1 = yp[1];
       const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-      float ef[MP_FE];
-#pragma unroll
-      for (int f = 0; f < MP_FE; ++f) ef[f] = bf16_round(m.ef[3 * (int64_t)e + f]);
+      const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
+      const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const int k = 8 * q + kk;
@@ -452,9 +457,13 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
       const int row = 16 * w + 4 * (lane >> 4) + r, k = 16 * nt + (lane & 15);
       const float a = av[nt][r];
       const float hn = hs[row * MX_FS + k] + (a > 0.0f ? a : 0.0f);
-      hout[(i0 + row) * MP_H + k] = hn;
+      const uint16_t hnb = bf16_bits(hn);
+      // the final h feeds the heads, which round it to bf16; its FP32 copy
+      // is for the backward pass only
+      if (l + 1 < MP_NL || m.store_train) hout[(i0 + row) * MP_H + k] = hn;
+      if (l + 1 == MP_NL) m.hb[(i0 + row) * MP_H + k] = hnb;
       if (m.store_train) m.a[((int64_t)l * rows + i0 + row) * MP_H + k] = a;
-      xh[row * MX_HS + k] = bf16_bits(hn);
+      xh[row * MX_HS + k] = hnb;
     }
   if (l + 1 < MP_NL) {
     __syncthreads();
@@ -476,13 +485,21 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
   const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
   if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
   const int n = t >> 2, q = t & 3;
-  const float* __restrict__ hf = m.h + (int64_t)MP_NL * m.rows * MP_H;
-  {
-    const float4* hp = reinterpret_cast<const float4*>(hf + (i0 + n) * MP_H + 8 * q);
-    const float4 h0 = hp[0], h1 = hp[1];
-    const float v[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+  // the final h in bf16 (the heads use it rounded): 8 features per thread
+  auto hb8 = [&](int64_t row, float (&v)[8]) {
+    const uint4 hq = *reinterpret_cast<const uint4*>(m.hb + row * MP_H + 8 * q);
+    const uint32_t wv[4] = {hq.x, hq.y, hq.z, hq.w};
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = bf16_round(v[kk]);
+    for (int h2 = 0; h2 < 4; ++h2) {
+      v[2 * h2] = bf16_value((uint16_t)(wv[h2] & 0xffffu));
+      v[2 * h2 + 1] = bf16_value((uint16_t)(wv[h2] >> 16));
+    }
+  };
+  {
+    float v[8];
+    hb8(i0 + n, v);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = v[kk];
   }
   __syncthreads();
   const int E0 = rp[0], E1 = rp[MP_ROWS];
@@ -496,20 +513,21 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     if (e < E1) {
       const int r = erow[n];
       const int64_t j = d.col[e];
-      const float4* hp = reinterpret_cast<const float4*>(hf + j * MP_H + 8 * q);
-      const float4 h0 = hp[0], h1 = hp[1];
-      const float hj[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+      float hj[8];
+      hb8(j, hj);
       float p = 0.0f;
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const int k = 8 * q + kk;
-        p += hz[k] * (hi_s[r * MX_FS + k] * bf16_round(hj[kk]));
+        p += hz[k] * (hi_s[r * MX_FS + k] * hj[kk]);
       }
       p += __shfl_xor(p, 1, 64);
       p += __shfl_xor(p, 2, 64);
       float tt = p;
+      const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
+      const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
 #pragma unroll
-      for (int f = 0; f < MP_FE; ++f) tt += hze[f] * bf16_round(m.ef[3 * (int64_t)e + f]);
+      for (int f = 0; f < MP_FE; ++f) tt += hze[f] * ef[f];
       tt += hze[MP_FE];
       if (q == 0) {
         m.moff[e] = (float)((double)tt / sqrt(d.diag[i0 + r] * d.diag[j]));

@@ -252,6 +252,7 @@ static int ensure_mp(sim_t* s, bool training) {
     MPALLOC(m.x, sizeof(float) * 3 * rows);
     MPALLOC(m.h, sizeof(float) * (MP_NL + 1) * rows * H);
     MPALLOC(m.y, sizeof(float) * MP_NL * rows * H);
+    MPALLOC(m.hb, sizeof(uint16_t) * rows * H);
     MPALLOC(m.tau, sizeof(float) * rows);
     MPALLOC(m.mdiag, sizeof(double) * rows);
     MPALLOC(m.lpart, sizeof(double) * 2 * (rows / 256 + 1));
@@ -268,11 +269,14 @@ static int ensure_mp(sim_t* s, bool training) {
   if (s->mp_nnz_cap != s->d.nnz_cap) {
     drop_graphs(s);
     dfree(s, m.ef);
+    dfree(s, m.efh);
     dfree(s, m.tg);
     dfree(s, m.moff);
     m.ef = m.tg = m.moff = nullptr;
+    m.efh = nullptr;
     const size_t cap = (size_t)s->d.nnz_cap;
     MPALLOC(m.ef, sizeof(float) * 3 * cap);
+    MPALLOC(m.efh, sizeof(uint16_t) * 4 * cap);
     MPALLOC(m.tg, sizeof(float) * cap);
     MPALLOC(m.moff, sizeof(float) * cap);
     s->mp_nnz_cap = s->d.nnz_cap;
