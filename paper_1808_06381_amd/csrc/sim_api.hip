@@ -165,6 +165,10 @@ static RepDev make_rep(const sim_params& p) {
     R.hL[k] = 0.5 * p.box[k];
     int nc = (int)std::floor(p.box[k] / (p.rc * (1.0 + 1e-9)));
     if (nc < 3) nc = 1;
+    // IC(0) colours cells by coordinate parity, with a third colour for the
+    // last cell of an odd axis: an even count (one fewer, larger cells)
+    // keeps two colours per axis, 8 launches per triangular sweep, not 27
+    if (p.precond == SIM_PC_IC0 && nc >= 5 && nc % 2 == 1) nc -= 1;
     R.nc[k] = nc;
     R.cell_len[k] = p.box[k] / (double)nc;
     R.inv_cell[k] = (double)nc / p.box[k];

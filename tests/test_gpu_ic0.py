@@ -3,9 +3,11 @@ oracle's sequential IC(0) of the same ordering.
 
 The ordering is computed here from the positions alone: cell coordinates
 floor(x n_c / L) per axis (n_c = floor(L / r_c) cells, one cell where that
-is below three), colour per axis = coordinate parity, 2 for the last cell of
-an odd axis, rows sorted by (colour, linear cell index z-major x fastest,
-particle id).  The oracle factors and solves the permuted system.
+is below three, one fewer where it is odd and at least five, so that the
+axis keeps two colours), colour per axis = coordinate parity, 2 for the
+last cell of an odd axis (three cells), rows sorted by (colour, linear cell
+index z-major x fastest, particle id).  The oracle factors and solves the
+permuted system.
 
 Checks: the factor L entry by entry (same operations in the same order:
 1e-13 relative), iteration counts within 2 of the oracle's PCG, converged
@@ -30,6 +32,7 @@ def ic_order(cfg, pos):
     for k in range(3):
         m = int(np.floor(cfg["box"][k] / (cfg["rc"] * (1.0 + 1e-9))))
         m = 1 if m < 3 else m
+        m = m - 1 if (m >= 5 and m % 2 == 1) else m
         c = np.floor(pos[:, k] * (m / cfg["box"][k])).astype(np.int64)
         nc.append(m)
         cell.append(np.clip(c, 0, m - 1))
@@ -55,6 +58,7 @@ CASES = {
     "even_cells": inputs.base_params(n=3000, box=(14.4, 14.4, 14.4), shear_rate=0.3, seed=11),
     "odd_cells": inputs.base_params(n=2300, box=(13.5, 13.2, 12.9), shear_rate=0.7, seed=12),
     "thin_axes": inputs.base_params(n=200, box=(2.6, 9.0, 2.2), shear_rate=0.8, seed=5),
+    "three_cells": inputs.base_params(n=250, box=(3.4, 9.3, 7.6), shear_rate=0.5, seed=6),
 }
 
 
