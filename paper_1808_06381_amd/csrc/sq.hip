@@ -19,11 +19,16 @@
 // Layout.  k_sq_partial: a block takes one tile of 64 mx x 32 my values and
 // one chunk of one replica's rows; per group of 32 particles it writes the
 // A and B tables to LDS (runs of 8 entries: sincospi with exact argument
-// scaling, then complex multiplication by the unit step), then each thread
-// adds the products of its 4 x 2 outputs in registers, particles in row
-// order.  k_sq_reduce: per replica and q, the chunks' partial sums in chunk
-// order, then |rho|^2 / C.  No floating-point atomics: the result is
-// deterministic.
+// scaling, then complex multiplication by the unit step), then the
+// contraction runs on the matrix cores: FP64 16 x 16 x 4 MFMA, wave w owning
+// mx rows 16w..16w+15 and two 16-wide my tiles, four particles per step,
+// Re += Ar Br - Ai Bi and Im += Ar Bi + Ai Br as four real products.  The
+// vector units only generate the tables.  k_sq_reduce: per replica and q,
+// the chunks' partial sums in chunk order, then |rho|^2 / C.  No
+// floating-point atomics: the result is deterministic.
+// Operand layout of v_mfma_f64_16x16x4f64 (checked on the device): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives D[4r + l/16][l%16]
+// in accumulator register r.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -38,11 +43,11 @@ namespace {
 constexpr int SQ_THREADS = 256;
 constexpr int SQ_TX = 64;        // mx per tile
 constexpr int SQ_TY = 32;        // my per tile
-constexpr int SQ_PX = 4;         // mx per thread
-constexpr int SQ_PY = 2;         // my per thread
-constexpr int SQ_P = 32;         // particles per LDS group
+constexpr int SQ_P = 32;         // particles per LDS group (a multiple of 4)
 constexpr int SQ_RUN = 8;        // table entries per sincospi (complex recurrence)
-static_assert((SQ_TX / SQ_PX) * (SQ_TY / SQ_PY) == SQ_THREADS, "one 4 x 2 block per thread");
+static_assert(SQ_TX == 16 * (SQ_THREADS / 64) && SQ_TY == 32, "16 mx rows and two my tiles per wave");
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct SqChunk {
   int32_t rep;     // replica
@@ -68,13 +73,10 @@ __global__ __launch_bounds__(SQ_THREADS) void k_sq_partial(DevPtrs d, const SqCh
   const int my0 = -my_max + (tile % tiles_y) * SQ_TY;
   const double delta = le_offset(R, *d.step_d);
   const double ilx = 1.0 / R.L[0], ily = 1.0 / R.L[1], ilz = 1.0 / R.L[2];
-  const int t = threadIdx.x;
-  const int tx = (t / (SQ_TY / SQ_PY)) * SQ_PX, ty = (t % (SQ_TY / SQ_PY)) * SQ_PY;
-  double acc[SQ_PX][SQ_PY][2];
-#pragma unroll
-  for (int a = 0; a < SQ_PX; ++a)
-#pragma unroll
-    for (int b = 0; b < SQ_PY; ++b) acc[a][b][0] = acc[a][b][1] = 0.0;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;  // operand row / column, particle of the step
+  f64x4 re[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  f64x4 im[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
   for (int64_t g = 0; g < ch.rows; g += SQ_P) {
     const int np = (int)min<int64_t>(SQ_P, ch.rows - g);
     // phase tables of this group: A[p][mx - mx0], B[p][my - my0], in runs
@@ -84,10 +86,15 @@ __global__ __launch_bounds__(SQ_THREADS) void k_sq_partial(DevPtrs d, const SqCh
     constexpr int RUNS_A = SQ_TX / SQ_RUN, RUNS = RUNS_A + SQ_TY / SQ_RUN;
     for (int w = t; w < SQ_P * RUNS; w += SQ_THREADS) {
       const int p = w / RUNS, run = w % RUNS;
-      if (p >= np) continue;  // the loop below reads only p < np
-      const double4 r = d.pos[ch.row0 + g + p];
       const bool isA = run < RUNS_A;
       const int k0 = (isA ? run : run - RUNS_A) * SQ_RUN;
+      if (p >= np) {  // rows past the group's particles: exact zeros
+        double2* dst = isA ? &A[p][k0] : &B[p][k0];
+#pragma unroll
+        for (int j = 0; j < SQ_RUN; ++j) dst[j] = make_double2(0.0, 0.0);
+        continue;
+      }
+      const double4 r = d.pos[ch.row0 + g + p];
       double s0, c0, ss, cs;
       if (isA) {
         const double sx = r.x * ilx - delta * r.y * (ilx * ily);
@@ -113,31 +120,27 @@ __global__ __launch_bounds__(SQ_THREADS) void k_sq_partial(DevPtrs d, const SqCh
       }
     }
     __syncthreads();
-    for (int p = 0; p < np; ++p) {
-      double2 av[SQ_PX], bv[SQ_PY];
+    // the contraction over this group's particles, four per MFMA step
+    for (int p0 = 0; p0 < np; p0 += 4) {
+      const double2 a = A[p0 + lk][16 * wave + li];
 #pragma unroll
-      for (int a = 0; a < SQ_PX; ++a) av[a] = A[p][tx + a];
-#pragma unroll
-      for (int b = 0; b < SQ_PY; ++b) bv[b] = B[p][ty + b];
-#pragma unroll
-      for (int a = 0; a < SQ_PX; ++a)
-#pragma unroll
-        for (int b = 0; b < SQ_PY; ++b) {
-          // complex multiply-add as four FP64 fused multiply-adds
-          acc[a][b][0] = fma(av[a].x, bv[b].x, acc[a][b][0]);
-          acc[a][b][0] = fma(-av[a].y, bv[b].y, acc[a][b][0]);
-          acc[a][b][1] = fma(av[a].x, bv[b].y, acc[a][b][1]);
-          acc[a][b][1] = fma(av[a].y, bv[b].x, acc[a][b][1]);
-        }
+      for (int tt = 0; tt < 2; ++tt) {
+        const double2 b = B[p0 + lk][16 * tt + li];
+        re[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re[tt], 0, 0, 0);
+        re[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[tt], 0, 0, 0);
+        im[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[tt], 0, 0, 0);
+        im[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[tt], 0, 0, 0);
+      }
     }
     __syncthreads();  // the tables are rewritten for the next group
   }
   const int64_t base = ((int64_t)ci * gridDim.x + tile) * (SQ_TX * SQ_TY);
 #pragma unroll
-  for (int a = 0; a < SQ_PX; ++a)
+  for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-    for (int b = 0; b < SQ_PY; ++b)
-      partial[base + (tx + a) * SQ_TY + ty + b] = make_double2(acc[a][b][0], acc[a][b][1]);
+    for (int r = 0; r < 4; ++r)
+      partial[base + (16 * wave + 4 * r + lk) * SQ_TY + 16 * tt + li] =
+          make_double2(re[tt][r], im[tt][r]);
   (void)nx;
 }
 
