@@ -87,6 +87,9 @@ def lib():
         L.orc_step.argtypes = [pp, C.c_int64, d_p, d_p, C.c_double, C.c_int, C.c_int, P(C.c_int)]
         L.orc_step.restype = C.c_int
         L.orc_wrap.argtypes = [pp, C.c_int64, d_p]
+        L.orc_velocity_correlation.argtypes = [pp, C.c_double, d_p, d_p, C.c_double, C.c_int32,
+                                               C.c_int32, C.c_int32, d_p, i64_p, d_p]
+        L.orc_velocity_correlation.restype = C.c_int
         f_p = P(C.c_float)
         L.orc_mpnn_nparams.restype = C.c_int64
         L.orc_bf16.argtypes = [C.c_float]
@@ -296,6 +299,28 @@ def wrap(cfg, pos, step_after):
 
 
 # ---- learned preconditioner ---------------------------------------------------
+
+def velocity_correlation(cfg, delta, pos, vel, r_max, nbins, flow=True, cells=None):
+    """Pair sums of u_i . u_j, pair counts (unordered pairs) per distance bin
+    and sum_c |u_c|^2 (vv.c).  cells: cell-list pair search (default for
+    n > 2048), else brute force."""
+    p = make_params(cfg)
+    pos = _f64(pos, (-1, 3))
+    vel = _f64(vel, (-1, 3))
+    if cells is None:
+        cells = p.n > 2048
+    s = np.zeros(nbins)
+    c = np.zeros(nbins, dtype=np.int64)
+    u2 = np.zeros(1)
+    rc = lib().orc_velocity_correlation(C.byref(p), float(delta), _dp(pos), _dp(vel),
+                                        float(r_max), int(nbins), int(bool(flow)), int(bool(cells)),
+                                        _dp(s), _ip(c), _dp(u2))
+    if rc == -1:
+        raise ValueError("bad velocity-correlation arguments")
+    if rc:
+        raise MemoryError("oracle velocity correlation failed")
+    return s, c, float(u2[0])
+
 
 def mpnn_nparams():
     return int(lib().orc_mpnn_nparams())

@@ -66,6 +66,16 @@ int64_t orc_pairs_brute(const orc_params* p, double delta, const double* pos,
 int64_t orc_pairs_cells(const orc_params* p, double delta, const double* pos,
                         int64_t cap, int64_t* pairs);
 
+/* ---- velocity cross-correlation (vv.c) ------------------------------------- */
+/* Pairs with r < r_max binned by r into nbins equal bins; per bin the sum of
+ * u_i . u_j and the pair count over unordered pairs, and u2 = sum |u|^2;
+ * u = v, or v minus the Couette flow when `flow` is set.  use_cells picks
+ * the cell-list pair search (same set as brute force).  Returns 0, -1 for
+ * bad arguments, -2 when out of memory.                                     */
+int orc_velocity_correlation(const orc_params* p, double delta, const double* pos,
+                             const double* vel, double r_max, int32_t nbins, int32_t flow,
+                             int32_t use_cells, double* sum, int64_t* count, double* u2);
+
 /* ---- friction system ------------------------------------------------------ */
 int64_t orc_count_pairs(const orc_params* p, int64_t step, const double* pos);
 int64_t orc_build_system(const orc_params* p, int64_t step, const double* pos,
