@@ -19,6 +19,9 @@
  *   count[k] = number of pairs of bin k
  *   u2       = sum_c |u_c|^2
  * so the normalised correlation of bin k is (sum[k] / count[k]) / (u2 / n).
+ * The per-bin sums are the exact sums of the FP64 products, evaluated with
+ * compensated (Neumaier) summation: within about two units in the last place
+ * of the result, however many pairs a bin holds.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -51,8 +54,14 @@ int orc_velocity_correlation(const orc_params* p, double delta, const double* po
     s2 += (u[3 * c] * u[3 * c] + u[3 * c + 1] * u[3 * c + 1]) + u[3 * c + 2] * u[3 * c + 2];
   }
   *u2 = s2;
+  double* comp = (double*)malloc(sizeof(double) * (size_t)nbins);
+  if (!comp) {
+    free(u);
+    return -2;
+  }
   for (int32_t k = 0; k < nbins; ++k) {
     sum[k] = 0.0;
+    comp[k] = 0.0;
     count[k] = 0;
   }
   /* the pair set at cut-off r_max, by the oracle's own search */
@@ -60,12 +69,9 @@ int orc_velocity_correlation(const orc_params* p, double delta, const double* po
   q.rc = r_max;
   int64_t np = use_cells ? orc_pairs_cells(&q, delta, pos, 0, NULL)
                          : orc_pairs_brute(&q, delta, pos, 0, NULL);
-  if (np < 0) {
-    free(u);
-    return -2;
-  }
-  int64_t* pr = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(np > 0 ? np : 1));
+  int64_t* pr = np < 0 ? NULL : (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(np > 0 ? np : 1));
   if (!pr) {
+    free(comp);
     free(u);
     return -2;
   }
@@ -79,10 +85,16 @@ int orc_velocity_correlation(const orc_params* p, double delta, const double* po
     const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
     int64_t k = orc_floor_sqrt(r2 * cscale);
     if (k > nbins - 1) k = nbins - 1;
-    sum[k] += (u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1]) + u[3 * i + 2] * u[3 * j + 2];
+    const double x = (u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1]) + u[3 * i + 2] * u[3 * j + 2];
+    const double t = sum[k] + x;
+    if (fabs(sum[k]) >= fabs(x)) comp[k] += (sum[k] - t) + x;
+    else comp[k] += (x - t) + sum[k];
+    sum[k] = t;
     count[k] += 1;
   }
+  for (int32_t k = 0; k < nbins; ++k) sum[k] += comp[k];
   free(pr);
+  free(comp);
   free(u);
   return 0;
 }
