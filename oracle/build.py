@@ -1,7 +1,9 @@
 """Build the CPU oracle shared library (oracle/liboracle.so) with gcc.
 
 Plain FP64 C, no FMA contraction and no fast-math, so the pair decision
-r^2 < rc^2 is the IEEE result of the operations as written.
+r^2 < rc^2 is the IEEE result of the operations as written.  OpenMP only
+spreads the brute-force pair loop of the velocity correlation over threads
+(fixed chunks, per-thread compensated sums added in thread order).
 """
 import os
 import subprocess
@@ -15,7 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose=False):
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp"] + srcs + ["-lm"]
+           "-fopenmp", "-Wall", "-Wextra", "-o", LIB + ".tmp"] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

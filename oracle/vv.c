@@ -24,6 +24,7 @@
  * of the result, however many pairs a bin holds.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 
 #include "oracle.h"
@@ -35,6 +36,14 @@ static int64_t orc_floor_sqrt(double t) {
   while ((double)(k + 1) * (double)(k + 1) <= t) ++k;
   while (k > 0 && (double)k * (double)k > t) --k;
   return k;
+}
+
+/* s + x with the rounding error kept in *c (Neumaier's compensated sum) */
+static void neumaier_add(double* s, double* c, double x) {
+  const double t = *s + x;
+  if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+  else *c += (x - t) + *s;
+  *s = t;
 }
 
 int orc_velocity_correlation(const orc_params* p, double delta, const double* pos,
@@ -64,33 +73,82 @@ int orc_velocity_correlation(const orc_params* p, double delta, const double* po
     comp[k] = 0.0;
     count[k] = 0;
   }
-  /* the pair set at cut-off r_max, by the oracle's own search */
-  orc_params q = *p;
-  q.rc = r_max;
-  int64_t np = use_cells ? orc_pairs_cells(&q, delta, pos, 0, NULL)
-                         : orc_pairs_brute(&q, delta, pos, 0, NULL);
-  int64_t* pr = np < 0 ? NULL : (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(np > 0 ? np : 1));
-  if (!pr) {
-    free(comp);
-    free(u);
-    return -2;
-  }
-  if (use_cells) orc_pairs_cells(&q, delta, pos, np, pr);
-  else orc_pairs_brute(&q, delta, pos, np, pr);
+  const double rmax2 = r_max * r_max;
   const double cscale = ((double)nbins * (double)nbins) / (r_max * r_max);
   double d[3];
-  for (int64_t m = 0; m < np; ++m) {
-    const int64_t i = pr[2 * m], j = pr[2 * m + 1];
-    orc_separation(p, delta, pos + 3 * i, pos + 3 * j, d);
-    const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    int64_t k = orc_floor_sqrt(r2 * cscale);
-    if (k > nbins - 1) k = nbins - 1;
-    const double x = (u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1]) + u[3 * i + 2] * u[3 * j + 2];
-    const double t = sum[k] + x;
-    if (fabs(sum[k]) >= fabs(x)) comp[k] += (sum[k] - t) + x;
-    else comp[k] += (x - t) + sum[k];
-    sum[k] = t;
-    count[k] += 1;
+  /* pairs in (i, j) order: every pair tested (brute force, no storage), or
+   * the cell-list pair set at cut-off r_max (same set, same order)        */
+  int64_t* pr = NULL;
+  int64_t np = 0;
+  if (use_cells) {
+    orc_params q = *p;
+    q.rc = r_max;
+    np = orc_pairs_cells(&q, delta, pos, 0, NULL);
+    pr = np < 0 ? NULL : (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(np > 0 ? np : 1));
+    if (!pr) {
+      free(comp);
+      free(u);
+      return -2;
+    }
+    orc_pairs_cells(&q, delta, pos, np, pr);
+  }
+  if (use_cells) {
+    for (int64_t m = 0; m < np; ++m) {
+      const int64_t i = pr[2 * m], j = pr[2 * m + 1];
+      orc_separation(p, delta, pos + 3 * i, pos + 3 * j, d);
+      const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+      int64_t k = orc_floor_sqrt(r2 * cscale);
+      if (k > nbins - 1) k = nbins - 1;
+      neumaier_add(&sum[k], &comp[k],
+                   (u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1]) + u[3 * i + 2] * u[3 * j + 2]);
+      count[k] += 1;
+    }
+  } else {
+    /* every pair tested; rows i are dealt to the threads in fixed chunks,
+     * each thread keeps its own compensated sums, added in thread order   */
+    int nt = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+      nt = omp_get_num_threads();
+    }
+    double* ts = (double*)calloc((size_t)nt * 2 * nbins, sizeof(double));
+    int64_t* tc = (int64_t*)calloc((size_t)nt * nbins, sizeof(int64_t));
+    if (!ts || !tc) {
+      free(ts);
+      free(tc);
+      free(comp);
+      free(u);
+      return -2;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+      const int th = omp_get_thread_num();
+      double* s_t = ts + (size_t)th * 2 * nbins;
+      double* c_t = s_t + nbins;
+      int64_t* n_t = tc + (size_t)th * nbins;
+      double dd[3];
+#pragma omp for schedule(static, 16)
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+          orc_separation(p, delta, pos + 3 * i, pos + 3 * j, dd);
+          const double r2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+          if (!(r2 < rmax2)) continue;
+          int64_t k = orc_floor_sqrt(r2 * cscale);
+          if (k > nbins - 1) k = nbins - 1;
+          neumaier_add(&s_t[k], &c_t[k],
+                       (u[3 * i] * u[3 * j] + u[3 * i + 1] * u[3 * j + 1]) + u[3 * i + 2] * u[3 * j + 2]);
+          n_t[k] += 1;
+        }
+    }
+    for (int t = 0; t < nt; ++t)
+      for (int32_t k = 0; k < nbins; ++k) {
+        neumaier_add(&sum[k], &comp[k], ts[(size_t)t * 2 * nbins + k]);
+        neumaier_add(&sum[k], &comp[k], ts[(size_t)t * 2 * nbins + nbins + k]);
+        count[k] += tc[(size_t)t * nbins + k];
+      }
+    free(ts);
+    free(tc);
   }
   for (int32_t k = 0; k < nbins; ++k) sum[k] += comp[k];
   free(pr);
