@@ -199,6 +199,36 @@ int sim_state(sim_t* sim, double* pos, double* vel, sim_meta* meta, uint32_t fla
 int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, double* out,
                          double* kernel_ms);
 
+/* Velocity cross-correlation against separation (Results section: the
+ * velocity correlation of two chains, normalised by the mean square
+ * velocity, against |R_cc'|, longer-ranged as alpha grows), of every
+ * replica's last committed step: the configuration R_n of that step and
+ * the velocities v_n solved at it (sim_state reports R_{n+1} = R_n + v_n dt
+ * and v_n).  With u = v_n, or with `flow` != 0 u = v_n - kappa (y - Ly/2) x
+ * (relative to the imposed Couette flow of Eq. 6c, the same for every
+ * Lees-Edwards image):
+ *   sum[r][k]   = sum of u_i . u_j over unordered pairs of replica r in bin k
+ *   count[r][k] = number of those pairs
+ *   u2[r]       = sum_c |u_c|^2
+ * Pairs: r^2 < r_max^2 under the Lees-Edwards minimum image of step n (the
+ * neighbour search's separation, rounding included); bin k = the largest
+ * integer with k^2 <= r^2 * (nbins^2 / r_max^2), capped at nbins - 1.  The
+ * normalised correlation is (sum / count) / (u2 / n); sums and counts of
+ * several calls add up for averages over configurations.
+ * sum and u2 are FP64; each pair product is rounded to a fixed-point
+ * integer of step 2^-S with S = 61 - ceil(log2(128 n_r)) - e_r, where
+ * max_c |u_c|^2 < 2^e_r, and the integers are added exactly, so sum[r][k]
+ * is within count * 2^-(S+1) (plus one rounding) of the exact pair sum and
+ * is bitwise reproducible.  sum, count: replicas x nbins (host); u2:
+ * replicas (host).  kernel_ms (optional) receives the duration of the pair
+ * kernel.  SIM_EINVAL when no step has been committed since the handle was
+ * created or since the last sim_solve / debug export (they overwrite the
+ * step's buffers), for nbins outside 1..1024, r_max <= 0 or r_max larger
+ * than half the smallest box side of any replica.  Device scratch of the
+ * handle grows on demand.                                                 */
+int sim_velocity_correlation(sim_t* sim, double r_max, int32_t nbins, int32_t flow, double* sum,
+                             int64_t* count, double* u2, double* kernel_ms);
+
 /* Run the library's work on this HIP stream (hipStream_t as void*; NULL is
  * the default stream).  The caller keeps the stream alive.                 */
 int sim_set_stream(sim_t* sim, void* hip_stream);

@@ -61,3 +61,35 @@ hipError_t launch_sq(const DevPtrs& d, const std::vector<int64_t>& rep_row0,
                      const std::vector<int64_t>& rep_rows, int nx, int my_max, int mz,
                      void* chunks_d, int32_t* rep_chunk0_d, double2* partial_d, double* out_d,
                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// velocity cross-correlation (vv.hip)
+struct VvRep {          // coarse cell grid of one replica
+  double len[3];        // cell edge per axis (>= r_max / M, or the whole axis)
+  double inv_len[3];
+  double margin;        // slack of the distance culling (rounding of cell indices)
+  double rmax2;         // r_max^2: pair iff r^2 < rmax2
+  double cscale;        // nbins^2 / r_max^2: bin = floor(sqrt(r^2 cscale))
+  int32_t nc[3];        // cells per axis (1: the whole axis is one cell)
+  int32_t M;            // stencil reach in cells
+  int32_t cell0;        // first global cell of this replica
+  int32_t log2p;        // ceil(log2(home particles per block x n)): pair bound of a block
+};
+struct VvBlock {        // one chunk of home particles of one coarse cell
+  int32_t rep, cell, start, count;
+};
+int vv_home();
+hipError_t launch_vv_bin(const DevPtrs& d, const VvRep* vr, int flow, int32_t* cnt,
+                         int32_t* vcell, int32_t* slot, unsigned long long* umax, double* u2_part,
+                         hipStream_t s);
+hipError_t launch_vv_scatter(const DevPtrs& d, int flow, const int32_t* cstart,
+                             const int32_t* vcell, const int32_t* slot, double4* spos,
+                             double4* su, hipStream_t s);
+hipError_t launch_vv_pairs(const DevPtrs& d, const VvRep* vr, const VvBlock* blocks, int nblk,
+                           const int32_t* cstart, const double4* spos, const double4* su,
+                           const unsigned long long* umax, int nb, long long* psum,
+                           unsigned long long* pcnt, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
+hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int32_t* rep_blk0, int nrep,
+                            int nb, const long long* psum, const unsigned long long* pcnt,
+                            const unsigned long long* umax, const double* u2_part,
+                            double* out_sum, long long* out_cnt, double* out_u2, hipStream_t s);

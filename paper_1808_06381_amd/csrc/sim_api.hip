@@ -99,6 +99,14 @@ struct sim_t {
   bool warm = false;         // step solves start from the previous velocities
   void* sq_scratch = nullptr;  // structure-factor scratch (grown on demand)
   size_t sq_bytes = 0;
+  void* vv_scratch = nullptr;  // velocity-correlation scratch (grown on demand)
+  size_t vv_bytes = 0;
+  void* vv_scratch2 = nullptr;
+  size_t vv_bytes2 = 0;
+  // pos_alt and x hold the last committed step's configuration R_n (cell
+  // order) and the velocities solved at it; cleared by anything that
+  // rebuilds the system or starts a solve
+  bool vv_valid = false;
   std::vector<int32_t> ic_color_off;  // offsets of the colours in d.ic_cells (host copy)
   sim_tuning tune{};
 };
@@ -130,6 +138,18 @@ static void dfree(sim_t* s, void* p) {
   auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
   if (it != s->allocs.end()) s->allocs.erase(it);
   (void)hipFree(p);
+}
+
+// device scratch *p of at least `need` bytes (kept between calls)
+static int grow_scratch(sim_t* s, void** p, size_t* have, size_t need) {
+  if (need <= *have) return SIM_OK;
+  dfree(s, *p);
+  *p = nullptr;
+  *have = 0;
+  int rc = dalloc(s, p, need);
+  if (rc) return rc;
+  *have = need;
+  return SIM_OK;
 }
 
 static int validate(const sim_params& p) {
@@ -314,6 +334,7 @@ static int ensure_mp(sim_t* s, bool training) {
 static int build_system(sim_t* s) {
   DevPtrs& d = s->d;
   s->system_valid = false;
+  s->vv_valid = false;
   hipStream_t st = s->stream;
   HIPCHK(launch_ctrl_zero(d, st));
   HIPCHK(launch_fill_i32(d.cell_count, 0, d.ncell_entries, st));
@@ -398,6 +419,7 @@ static int prepare_precond(sim_t* s) {
 // iterating components then restart from the previous step's velocities:
 // x = v_prev, r = b - A x, done if r passes, else the restart path.
 static int cg_queue_start(sim_t* s, double tol, bool warm) {
+  s->vv_valid = false;
   const DevPtrs& d = s->d;
   const bool ext = d.learned || d.ic0;
   HIPCHK(launch_cg_reset(d, tol, s->stream));
@@ -1146,6 +1168,7 @@ static int commit_step(sim_t* s, sim_stats* st) {
   HIPCHK(launch_step_commit(s->d, 0, s->stream));
   std::swap(s->d.pos, s->d.pos_alt);
   s->step += 1;
+  s->vv_valid = true;
   if (st) st->steps_done += 1;
   return SIM_OK;
 }
@@ -1241,6 +1264,7 @@ static int step_graph(sim_t* s, sim_stats* st) {
     s->system_valid = true;
     std::swap(s->d.pos, s->d.pos_alt);
     s->step += 1;
+    s->vv_valid = true;
     if (st) st->steps_done += 1;
     return SIM_OK;
   }
@@ -1524,6 +1548,162 @@ int sim_structure_factor(sim_t* s, int32_t nx, int32_t my_max, int32_t mz, doubl
   if (e1) (void)hipEventDestroy(e1);
   if (err) {
     sim_note_error(err, "structure factor", __LINE__);
+    return SIM_EDEVICE;
+  }
+  return SIM_OK;
+}
+
+int sim_velocity_correlation(sim_t* s, double r_max, int32_t nbins, int32_t flow, double* sum,
+                             int64_t* count, double* u2, double* kernel_ms) {
+  if (!s || !sum || !count || !u2 || nbins < 1 || nbins > 1024 || !(r_max > 0.0) ||
+      !std::isfinite(r_max))
+    return SIM_EINVAL;
+  if (!s->vv_valid) return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  const int nrep = (int)s->reph.size();
+  const int home = vv_home();
+  // coarse grid per replica: cells of at least r_max / M, M such that a
+  // cell holds about one block of home particles, at most ~2 cells per
+  // particle; an axis too short for the 2M+1 stencil is one cell (and a
+  // one-cell y axis makes x one cell too: the image shift is then per pair)
+  std::vector<VvRep> vr(nrep);
+  int64_t ncell = 0;
+  for (int r = 0; r < nrep; ++r) {
+    const RepDev& R = s->reph[r];
+    if (r_max > 0.5 * std::min(R.L[0], std::min(R.L[1], R.L[2]))) return SIM_EINVAL;
+    const double vol = R.L[0] * R.L[1] * R.L[2];
+    const double rho = (double)std::max(R.n, 1) / vol;
+    const int M = std::max(1, std::min(8, (int)std::floor(r_max / std::cbrt((double)home / rho))));
+    const double ell = std::max(r_max / M * (1.0 + 1e-12), std::cbrt(vol / (2.0 * std::max(R.n, 1))));
+    VvRep& V = vr[r];
+    V.M = M;
+    for (int k = 0; k < 3; ++k)
+      V.nc[k] = (int32_t)std::max(1.0, std::min(std::floor(R.L[k] / ell), 4096.0));
+    if (V.nc[1] < 2 * M + 1) { V.nc[1] = 1; V.nc[0] = 1; }
+    if (V.nc[2] < 2 * M + 1) V.nc[2] = 1;
+    if (V.nc[0] < 2 * M + 2) V.nc[0] = 1;
+    double lmin = R.L[0];
+    for (int k = 0; k < 3; ++k) {
+      V.len[k] = R.L[k] / V.nc[k];
+      V.inv_len[k] = 1.0 / V.len[k];
+      lmin = std::min(lmin, V.len[k]);
+    }
+    V.margin = 1e-9 * lmin;
+    V.rmax2 = r_max * r_max;
+    V.cscale = ((double)nbins * (double)nbins) / (r_max * r_max);
+    V.cell0 = (int32_t)ncell;
+    const uint64_t pb = (uint64_t)home * (uint64_t)std::max(R.n, 1);
+    int lg = 0;
+    while ((1ull << lg) < pb) ++lg;
+    V.log2p = lg;
+    ncell += (int64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    if (ncell > (int64_t)1 << 30) return SIM_EINVAL;
+  }
+  const int64_t rows = s->rows;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  // scratch: the grid, binning and sorted copies first; the block table and
+  // the blocks' partial sums once the cell populations are known
+  size_t off = 0;
+  auto take = [&](size_t b) { const size_t o = off; off += up(std::max<size_t>(b, 8)); return o; };
+  const size_t o_vr = take(sizeof(VvRep) * nrep);
+  const size_t o_cnt = take(sizeof(int32_t) * (ncell + 1));
+  const size_t o_cstart = take(sizeof(int32_t) * (ncell + 1));
+  const size_t o_vcell = take(sizeof(int32_t) * rows);
+  const size_t o_slot = take(sizeof(int32_t) * rows);
+  const size_t o_spos = take(sizeof(double4) * s->n_total);
+  const size_t o_su = take(sizeof(double4) * s->n_total);
+  const size_t o_umax = take(sizeof(unsigned long long) * nrep);
+  const size_t o_u2p = take(sizeof(double) * s->d.nblk);
+  const size_t o_rb = take(sizeof(int32_t) * (nrep + 1));
+  const size_t o_osum = take(sizeof(double) * nrep * nbins);
+  const size_t o_ocnt = take(sizeof(long long) * nrep * nbins);
+  const size_t o_ou2 = take(sizeof(double) * nrep);
+  int rc;
+  if ((rc = grow_scratch(s, &s->vv_scratch, &s->vv_bytes, off))) return rc;
+  char* base = (char*)s->vv_scratch;
+  VvRep* vr_d = (VvRep*)(base + o_vr);
+  int32_t* cnt_d = (int32_t*)(base + o_cnt);
+  int32_t* cstart_d = (int32_t*)(base + o_cstart);
+  unsigned long long* umax_d = (unsigned long long*)(base + o_umax);
+  hipStream_t st = s->stream;
+  HIPCHK(hipMemcpyAsync(vr_d, vr.data(), sizeof(VvRep) * nrep, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(cnt_d, 0, sizeof(int32_t) * (ncell + 1), st));
+  HIPCHK(hipMemsetAsync(umax_d, 0, sizeof(unsigned long long) * nrep, st));
+  HIPCHK(launch_vv_bin(s->d, vr_d, flow ? 1 : 0, cnt_d, (int32_t*)(base + o_vcell),
+                       (int32_t*)(base + o_slot), umax_d, (double*)(base + o_u2p), st));
+  std::vector<int32_t> cnt_h(ncell + 1);
+  HIPCHK(hipMemcpyAsync(cnt_h.data(), cnt_d, sizeof(int32_t) * (ncell + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // cell starts and the block table (chunks of home particles per cell)
+  std::vector<int32_t> cstart_h(ncell + 1);
+  std::vector<VvBlock> blk;
+  std::vector<int32_t> rb(nrep + 1);
+  int64_t acc = 0;
+  for (int r = 0; r < nrep; ++r) {
+    rb[r] = (int32_t)blk.size();
+    const VvRep& V = vr[r];
+    const int64_t nc = (int64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    for (int64_t c = V.cell0; c < V.cell0 + nc; ++c) {
+      cstart_h[c] = (int32_t)acc;
+      for (int32_t a = 0; a < cnt_h[c]; a += home)
+        blk.push_back({r, (int32_t)c, (int32_t)(acc + a), std::min(home, cnt_h[c] - a)});
+      acc += cnt_h[c];
+    }
+  }
+  rb[nrep] = (int32_t)blk.size();
+  cstart_h[ncell] = (int32_t)acc;
+  if (acc != s->n_total) {
+    snprintf(g_last_error, sizeof(g_last_error), "velocity correlation: binned %lld of %lld rows",
+             (long long)acc, (long long)s->n_total);
+    return SIM_EDEVICE;
+  }
+  HIPCHK(hipMemcpyAsync(cstart_d, cstart_h.data(), sizeof(int32_t) * (ncell + 1),
+                        hipMemcpyHostToDevice, st));
+  size_t off2 = 0;
+  auto take2 = [&](size_t b) { const size_t o = off2; off2 += up(std::max<size_t>(b, 8)); return o; };
+  const size_t o_blk = take2(sizeof(VvBlock) * blk.size());
+  const size_t o_psum = take2(sizeof(long long) * blk.size() * nbins);
+  const size_t o_pcnt = take2(sizeof(unsigned long long) * blk.size() * nbins);
+  if ((rc = grow_scratch(s, &s->vv_scratch2, &s->vv_bytes2, off2))) return rc;
+  char* base2 = (char*)s->vv_scratch2;
+  VvBlock* blk_d = (VvBlock*)(base2 + o_blk);
+  int32_t* rb_d = (int32_t*)(base + o_rb);
+  if (!blk.empty())
+    HIPCHK(hipMemcpyAsync(blk_d, blk.data(), sizeof(VvBlock) * blk.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(rb_d, rb.data(), sizeof(int32_t) * (nrep + 1), hipMemcpyHostToDevice, st));
+  double4* spos_d = (double4*)(base + o_spos);
+  double4* su_d = (double4*)(base + o_su);
+  HIPCHK(launch_vv_scatter(s->d, flow ? 1 : 0, cstart_d, (int32_t*)(base + o_vcell),
+                           (int32_t*)(base + o_slot), spos_d, su_d, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+  }
+  long long* psum_d = (long long*)(base2 + o_psum);
+  unsigned long long* pcnt_d = (unsigned long long*)(base2 + o_pcnt);
+  hipError_t err = launch_vv_pairs(s->d, vr_d, blk_d, (int)blk.size(), cstart_d, spos_d, su_d,
+                                   umax_d, nbins, psum_d, pcnt_d, st, e0, e1);
+  if (!err)
+    err = launch_vv_reduce(s->d, vr_d, rb_d, nrep, nbins, psum_d, pcnt_d, umax_d,
+                           (double*)(base + o_u2p), (double*)(base + o_osum),
+                           (long long*)(base + o_ocnt), (double*)(base + o_ou2), st);
+  if (!err)
+    err = hipMemcpyAsync(sum, base + o_osum, sizeof(double) * nrep * nbins, hipMemcpyDeviceToHost, st);
+  if (!err)
+    err = hipMemcpyAsync(count, base + o_ocnt, sizeof(int64_t) * nrep * nbins,
+                         hipMemcpyDeviceToHost, st);
+  if (!err) err = hipMemcpyAsync(u2, base + o_ou2, sizeof(double) * nrep, hipMemcpyDeviceToHost, st);
+  if (!err) err = hipStreamSynchronize(st);
+  if (!err && kernel_ms) {
+    float ms = 0.0f;
+    err = blk.empty() ? hipSuccess : hipEventElapsedTime(&ms, e0, e1);
+    *kernel_ms = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err) {
+    sim_note_error(err, "velocity correlation", __LINE__);
     return SIM_EDEVICE;
   }
   return SIM_OK;

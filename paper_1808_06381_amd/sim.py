@@ -26,7 +26,8 @@ PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
 EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
             "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
-            "sim_copy_probe", "sim_event_probe", "sim_structure_factor", "sim_precond_weights",
+            "sim_copy_probe", "sim_event_probe", "sim_structure_factor",
+            "sim_velocity_correlation", "sim_precond_weights",
             "sim_precond_config", "sim_train_step",
             "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
             "sim_autotune", "sim_set_tuning", "sim_train_probe", "sim_precond_optimizer",
@@ -139,6 +140,8 @@ def lib():
         L.sim_state.argtypes = [vp, vp, vp, P(SimMeta), C.c_uint32]
         L.sim_structure_factor.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp,
                                            P(C.c_double)]
+        L.sim_velocity_correlation.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp, vp, vp,
+                                               P(C.c_double)]
         L.sim_set_stream.argtypes = [vp, vp]
         L.sim_load_precond.argtypes = [vp, C.c_char_p]
         L.sim_debug_pairs.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
@@ -290,6 +293,25 @@ class Sim:
                                           C.byref(ms) if timed else None),
                "sim_structure_factor")
         return (out, ms.value) if timed else out
+
+    def velocity_correlation(self, r_max, nbins, flow=True, timed=False):
+        """Velocity cross-correlation of the last committed step (the
+        configuration the velocities were solved at): per replica and
+        distance bin the sum of u_i . u_j and the count over unordered pairs
+        with r < r_max, and sum |u|^2; u relative to the Couette flow when
+        flow is set.  Returns (sum (replicas, nbins), count (replicas,
+        nbins), u2 (replicas,)), with timed=True also the pair kernel's
+        duration in ms."""
+        nb = max(int(nbins), 0)
+        s = np.zeros((self.replicas, nb))
+        c = np.zeros((self.replicas, nb), dtype=np.int64)
+        u2 = np.zeros(self.replicas)
+        ms = C.c_double()
+        _check(lib().sim_velocity_correlation(self.h, float(r_max), int(nbins), int(bool(flow)),
+                                              _ptr(s), _ptr(c), _ptr(u2),
+                                              C.byref(ms) if timed else None),
+               "sim_velocity_correlation")
+        return (s, c, u2, ms.value) if timed else (s, c, u2)
 
     def pairs(self):
         """Unordered pairs as an int64 (m, 3) array of (replica, i, j), sorted."""

@@ -1,0 +1,159 @@
+"""Velocity cross-correlation (Results section: velocity correlation of two
+chains against their separation) of the library against the oracle.
+
+The library correlates the configuration R_n of the last committed step with
+the velocities v_n solved at it; the tests take R_n from the state before
+that step and v_n from the state after it, and the offset of step n.
+
+Tolerance from the arithmetic: both sides form r^2, the bin and every product
+u_i . u_j with the same FP64 operations (no contraction), so pair counts are
+compared exactly.  The library rounds each product to a multiple of 2^-S
+(S = 61 - ceil(log2(128 n)) - e, max |u|^2 < 2^e) and adds integers exactly,
+then converts once to FP64; the oracle's compensated sum is within ~2 ulp of
+the exact sum.  So |sum - sum_ref| <= count 2^-(S+1) + 4 eps |sum_ref|; the
+tests allow 2^-S per pair (S one lower, for a maximum that rounds across a
+power of two) plus 4 eps umax^2 per pair and 8 eps |sum|.
+
+Cases:
+* small cubes, sheared and not, flow removed and not, one with r_max close
+  to L/2 (every axis one coarse cell: all pairs tested);
+* a stencil reach of two cells with x one cell (N = 20000, r_max = 10.5);
+* a reach of three cells on every axis with distance culling of cells
+  (N = 66000, r_max = 15.15), through step graphs;
+* a batch of uneven replicas;
+* N = 10^6 (L = 100): r_max = 2 against the oracle, and r_max = 16 (reach
+  three) giving the same bits in the bins both cover;
+* determinism, validity after sim_solve, argument checks.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_06381_amd import inputs
+from paper_1808_06381_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
+
+
+def rel_u(cfg, pos, vel, flow):
+    u = np.array(vel, dtype=np.float64)
+    if flow:
+        u[:, 0] = u[:, 0] - cfg["shear_rate"] * (pos[:, 1] - 0.5 * cfg["box"][1])
+    return u
+
+
+def check(cfg, pos_n, vel_n, step_n, got, r_max, nb, flow):
+    s, c, u2 = (np.asarray(a).reshape(-1) for a in got[:3])
+    u2 = float(u2[0])
+    delta = oracle.le_offset(cfg, step_n)
+    s_ref, c_ref, u2_ref = oracle.velocity_correlation(cfg, delta, pos_n, vel_n, r_max, nb,
+                                                       flow=flow)
+    np.testing.assert_array_equal(c, c_ref)
+    u = rel_u(cfg, pos_n, vel_n, flow)
+    umax2 = float((u * u).sum(1).max())
+    e = math.frexp(umax2)[1]
+    lg = math.ceil(math.log2(128 * len(pos_n)))
+    S_lo = 61 - lg - e - 1
+    tol = c_ref * (2.0 ** -S_lo + 4 * EPS * umax2) + 8 * EPS * np.abs(s_ref) + 1e-300
+    err = np.abs(s - s_ref)
+    assert np.all(err <= tol), (np.max(err / tol), int(np.argmax(err / tol)))
+    assert abs(u2 - u2_ref) <= 4 * len(pos_n) * EPS * u2_ref
+    return s_ref, c_ref, u2_ref
+
+
+def run_and_correlate(sim, steps, r_max, nb, flow, timed=False):
+    """advance, keep R_n of the last step, return (R_n, v_n, n, result)"""
+    if steps > 1:
+        sim.step(steps - 1)
+    pos_n, _, meta0 = sim.state()
+    sim.step(1)
+    _, vel, meta = sim.state()
+    assert meta["step"] == meta0["step"] + 1
+    return pos_n, vel, meta0["step"], sim.velocity_correlation(r_max, nb, flow=flow, timed=timed)
+
+
+@pytest.mark.parametrize("shear,r_max,nb,flow", [(0.0, 2.5, 25, False), (0.5, 2.5, 25, True),
+                                                 (0.5, 7.0, 35, True), (0.2, 4.3, 17, False)])
+def test_small_cube_matches_oracle(shear, r_max, nb, flow):
+    cfg = inputs.cube_params(3000, shear, seed=21)
+    pos0 = inputs.uniform_positions(3000, cfg["box"], 21)
+    with S.Sim(cfg, pos0) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 3, r_max, nb, flow)
+    s_ref, c_ref, _ = check(cfg, pos_n, vel, n, got, r_max, nb, flow)
+    assert c_ref.sum() > 0
+
+
+def test_reach_two_with_one_cell_in_x():
+    cfg = inputs.cube_params(20000, 0.3, seed=22)
+    pos0 = inputs.uniform_positions(20000, cfg["box"], 22)
+    with S.Sim(cfg, pos0) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 2, 10.5, 42, True)
+    check(cfg, pos_n, vel, n, got, 10.5, 42, True)
+
+
+def test_reach_three_with_culling_through_graphs():
+    cfg = inputs.cube_params(66000, 0.5, seed=23)
+    pos0 = inputs.uniform_positions(66000, cfg["box"], 23)
+    with S.Sim(cfg, pos0) as sim:
+        sim.graph_mode(True)
+        pos_n, vel, n, got = run_and_correlate(sim, 4, 15.15, 30, True)
+        assert sim.graph_info()["replays"] > 0   # the last steps were graph replays
+    check(cfg, pos_n, vel, n, got, 15.15, 30, True)
+
+
+def test_batch_of_uneven_replicas():
+    cfgs, pos = [], []
+    for r, (n, shear) in enumerate([(5000, 0.3), (700, 1.0), (9000, 0.05)]):
+        c = inputs.cube_params(n, shear, seed=60 + r)
+        c["stream"] = r
+        cfgs.append(c)
+        pos.append(inputs.uniform_positions(n, c["box"], 60 + r))
+    with S.Sim(cfgs, np.concatenate(pos)) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 2, 3.0, 12, True)
+    off = np.cumsum([0] + [c["n"] for c in cfgs])
+    for r, c in enumerate(cfgs):
+        sl = slice(off[r], off[r + 1])
+        check(c, pos_n[sl], vel[sl], n, (got[0][r], got[1][r], got[2][r]), 3.0, 12, True)
+
+
+def test_full_size_against_oracle_and_across_reaches():
+    cfg = inputs.single_box(shear_rate=0.5, seed=24, n=1_000_000, L=100.0)["params"]
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], 24)
+    with S.Sim(cfg, pos0, tol=1e-8) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 2, 2.0, 4, True)
+        big = sim.velocity_correlation(16.0, 32, flow=True, timed=True)
+    check(cfg, pos_n, vel, n, got, 2.0, 4, True)
+    # bins of width 0.5 in both: the reach-three grid gives the same integers
+    np.testing.assert_array_equal(big[1][0, :4], got[1][0])
+    np.testing.assert_array_equal(big[0][0, :4], got[0][0])
+    assert big[3] > 0
+    # uniform random positions: pair counts near n/2 * shell volume
+    r = np.arange(33) * 0.5
+    shell = 0.5 * 1_000_000 * 4.0 / 3.0 * math.pi * (r[1:] ** 3 - r[:-1] ** 3)  # density 1
+    assert np.all(np.abs(big[1][0, 8:] / shell[8:] - 1.0) < 0.05)
+
+
+def test_determinism_validity_and_arguments():
+    cfg = inputs.cube_params(2000, 0.4, seed=25)
+    pos0 = inputs.uniform_positions(2000, cfg["box"], 25)
+    with S.Sim(cfg, pos0) as sim:
+        with pytest.raises(S.SimError):
+            sim.velocity_correlation(2.0, 8)     # no step yet
+        sim.step(2)
+        a = sim.velocity_correlation(3.0, 30)
+        b = sim.velocity_correlation(3.0, 30)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        L = cfg["box"][0]
+        for args in [(2.0, 0), (2.0, 1025), (0.0, 8), (-1.0, 8), (0.5 * L + 1e-9, 8)]:
+            with pytest.raises(S.SimError):
+                sim.velocity_correlation(*args)
+        sim.solve(np.ones((2000, 3)))
+        with pytest.raises(S.SimError):
+            sim.velocity_correlation(2.0, 8)     # the solve overwrote the step's buffers
+        sim.step(1)
+        c = sim.velocity_correlation(0.5 * L, 8)
+        assert c[1].sum() > 0
