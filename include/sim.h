@@ -216,7 +216,7 @@ int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, dou
  * normalised correlation is (sum / count) / (u2 / n); sums and counts of
  * several calls add up for averages over configurations.
  * sum and u2 are FP64; each pair product is rounded to a fixed-point
- * integer of step 2^-S with S = 61 - ceil(log2(128 n_r)) - e_r, where
+ * integer of step 2^-S with S = 61 - ceil(log2(64 n_r)) - e_r, where
  * max_c |u_c|^2 < 2^e_r, and the integers are added exactly, so sum[r][k]
  * is within count * 2^-(S+1) (plus one rounding) of the exact pair sum and
  * is bitwise reproducible.  sum, count: replicas x nbins (host); u2:
@@ -224,7 +224,8 @@ int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, dou
  * kernel.  SIM_EINVAL when no step has been committed since the handle was
  * created or since the last sim_solve / debug export (they overwrite the
  * step's buffers), for nbins outside 1..1024, r_max <= 0 or r_max larger
- * than half the smallest box side of any replica.  Device scratch of the
+ * than half the smallest box side of any replica, or a replica of 2^26
+ * particles or more.  Device scratch of the
  * handle grows on demand.                                                 */
 int sim_velocity_correlation(sim_t* sim, double r_max, int32_t nbins, int32_t flow, double* sum,
                              int64_t* count, double* u2, double* kernel_ms);

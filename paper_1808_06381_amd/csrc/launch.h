@@ -89,7 +89,10 @@ hipError_t launch_vv_pairs(const DevPtrs& d, const VvRep* vr, const VvBlock* blo
                            const unsigned long long* umax, int nb, long long* psum,
                            unsigned long long* pcnt, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);
-hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int32_t* rep_blk0, int nrep,
-                            int nb, const long long* psum, const unsigned long long* pcnt,
+int vv_fold();
+hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int2* chunks, int nchunk,
+                            const int32_t* rep_chunk0, int nrep, int nb, const long long* psum,
+                            const unsigned long long* pcnt, unsigned long long* f_lo,
+                            long long* f_hi, unsigned long long* f_cnt,
                             const unsigned long long* umax, const double* u2_part,
                             double* out_sum, long long* out_cnt, double* out_u2, hipStream_t s);

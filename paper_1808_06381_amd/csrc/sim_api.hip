@@ -1553,6 +1553,27 @@ int sim_structure_factor(sim_t* s, int32_t nx, int32_t my_max, int32_t mz, doubl
   return SIM_OK;
 }
 
+// coarse grid of reach M for one replica (cells, edges, culling margin)
+static VvRep vv_grid(const RepDev& R, double r_max, int M) {
+  const double vol = R.L[0] * R.L[1] * R.L[2];
+  const double ell = std::max(r_max / M * (1.0 + 1e-12), std::cbrt(vol / (2.0 * std::max(R.n, 1))));
+  VvRep V{};
+  V.M = M;
+  for (int k = 0; k < 3; ++k)
+    V.nc[k] = (int32_t)std::max(1.0, std::min(std::floor(R.L[k] / ell), 4096.0));
+  if (V.nc[1] < 2 * M + 1) { V.nc[1] = 1; V.nc[0] = 1; }
+  if (V.nc[2] < 2 * M + 1) V.nc[2] = 1;
+  if (V.nc[0] < 2 * M + 2) V.nc[0] = 1;
+  double lmin = R.L[0];
+  for (int k = 0; k < 3; ++k) {
+    V.len[k] = R.L[k] / V.nc[k];
+    V.inv_len[k] = 1.0 / V.len[k];
+    lmin = std::min(lmin, V.len[k]);
+  }
+  V.margin = 1e-9 * lmin;
+  return V;
+}
+
 int sim_velocity_correlation(sim_t* s, double r_max, int32_t nbins, int32_t flow, double* sum,
                              int64_t* count, double* u2, double* kernel_ms) {
   if (!s || !sum || !count || !u2 || nbins < 1 || nbins > 1024 || !(r_max > 0.0) ||
@@ -1562,33 +1583,31 @@ int sim_velocity_correlation(sim_t* s, double r_max, int32_t nbins, int32_t flow
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   const int nrep = (int)s->reph.size();
   const int home = vv_home();
-  // coarse grid per replica: cells of at least r_max / M, M such that a
-  // cell holds about one block of home particles, at most ~2 cells per
-  // particle; an axis too short for the 2M+1 stencil is one cell (and a
-  // one-cell y axis makes x one cell too: the image shift is then per pair)
+  // coarse grid per replica: cells of at least r_max / M per axis (at most
+  // ~2 cells per particle); an axis too short for the 2M+1 stencil is one
+  // cell (and a one-cell y axis makes x one cell too: the image shift is
+  // then per pair).  M is the largest reach (<= 8) whose cells hold at least
+  // 8 particles on average and that makes no axis one cell that reach 1
+  // splits: smaller cells cull more of the stencil, but
+  // below that the per-run overhead of the pair kernel dominates (measured
+  // at N = 1e6 and 6.6e4 over r_max = 5 .. 16).
   std::vector<VvRep> vr(nrep);
   int64_t ncell = 0;
   for (int r = 0; r < nrep; ++r) {
     const RepDev& R = s->reph[r];
     if (r_max > 0.5 * std::min(R.L[0], std::min(R.L[1], R.L[2]))) return SIM_EINVAL;
-    const double vol = R.L[0] * R.L[1] * R.L[2];
-    const double rho = (double)std::max(R.n, 1) / vol;
-    const int M = std::max(1, std::min(8, (int)std::floor(r_max / std::cbrt((double)home / rho))));
-    const double ell = std::max(r_max / M * (1.0 + 1e-12), std::cbrt(vol / (2.0 * std::max(R.n, 1))));
+    if (R.n >= (1 << 26)) return SIM_EINVAL;  // 32-bit pair counts of one block
     VvRep& V = vr[r];
-    V.M = M;
-    for (int k = 0; k < 3; ++k)
-      V.nc[k] = (int32_t)std::max(1.0, std::min(std::floor(R.L[k] / ell), 4096.0));
-    if (V.nc[1] < 2 * M + 1) { V.nc[1] = 1; V.nc[0] = 1; }
-    if (V.nc[2] < 2 * M + 1) V.nc[2] = 1;
-    if (V.nc[0] < 2 * M + 2) V.nc[0] = 1;
-    double lmin = R.L[0];
-    for (int k = 0; k < 3; ++k) {
-      V.len[k] = R.L[k] / V.nc[k];
-      V.inv_len[k] = 1.0 / V.len[k];
-      lmin = std::min(lmin, V.len[k]);
+    V = vv_grid(R, r_max, 1);
+    for (int M = 8; M > 1; --M) {
+      const VvRep c = vv_grid(R, r_max, M);
+      bool keeps = true;  // no axis made one cell that reach 1 splits
+      for (int k = 0; k < 3; ++k) keeps = keeps && !(V.nc[k] > 1 && c.nc[k] == 1);
+      if (keeps && (double)R.n >= 8.0 * ((double)c.nc[0] * c.nc[1] * c.nc[2])) {
+        V = c;
+        break;
+      }
     }
-    V.margin = 1e-9 * lmin;
     V.rmax2 = r_max * r_max;
     V.cscale = ((double)nbins * (double)nbins) / (r_max * r_max);
     V.cell0 = (int32_t)ncell;
@@ -1661,16 +1680,32 @@ int sim_velocity_correlation(sim_t* s, double r_max, int32_t nbins, int32_t flow
                         hipMemcpyHostToDevice, st));
   size_t off2 = 0;
   auto take2 = [&](size_t b) { const size_t o = off2; off2 += up(std::max<size_t>(b, 8)); return o; };
+  // chunks of table blocks for the first reduce stage (never across replicas)
+  std::vector<int2> chunks;
+  std::vector<int32_t> rc0(nrep + 1);
+  for (int r = 0; r < nrep; ++r) {
+    rc0[r] = (int32_t)chunks.size();
+    for (int32_t b0 = rb[r]; b0 < rb[r + 1]; b0 += vv_fold())
+      chunks.push_back(make_int2(b0, std::min(b0 + vv_fold(), rb[r + 1])));
+  }
+  rc0[nrep] = (int32_t)chunks.size();
+  const size_t nch = chunks.size();
   const size_t o_blk = take2(sizeof(VvBlock) * blk.size());
   const size_t o_psum = take2(sizeof(long long) * blk.size() * nbins);
   const size_t o_pcnt = take2(sizeof(unsigned long long) * blk.size() * nbins);
+  const size_t o_ch = take2(sizeof(int2) * nch);
+  const size_t o_flo = take2(sizeof(unsigned long long) * nch * nbins);
+  const size_t o_fhi = take2(sizeof(long long) * nch * nbins);
+  const size_t o_fcnt = take2(sizeof(unsigned long long) * nch * nbins);
   if ((rc = grow_scratch(s, &s->vv_scratch2, &s->vv_bytes2, off2))) return rc;
   char* base2 = (char*)s->vv_scratch2;
   VvBlock* blk_d = (VvBlock*)(base2 + o_blk);
   int32_t* rb_d = (int32_t*)(base + o_rb);
+  if (!chunks.empty())
+    HIPCHK(hipMemcpyAsync(base2 + o_ch, chunks.data(), sizeof(int2) * nch, hipMemcpyHostToDevice, st));
   if (!blk.empty())
     HIPCHK(hipMemcpyAsync(blk_d, blk.data(), sizeof(VvBlock) * blk.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(rb_d, rb.data(), sizeof(int32_t) * (nrep + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(rb_d, rc0.data(), sizeof(int32_t) * (nrep + 1), hipMemcpyHostToDevice, st));
   double4* spos_d = (double4*)(base + o_spos);
   double4* su_d = (double4*)(base + o_su);
   HIPCHK(launch_vv_scatter(s->d, flow ? 1 : 0, cstart_d, (int32_t*)(base + o_vcell),
@@ -1685,8 +1720,10 @@ int sim_velocity_correlation(sim_t* s, double r_max, int32_t nbins, int32_t flow
   hipError_t err = launch_vv_pairs(s->d, vr_d, blk_d, (int)blk.size(), cstart_d, spos_d, su_d,
                                    umax_d, nbins, psum_d, pcnt_d, st, e0, e1);
   if (!err)
-    err = launch_vv_reduce(s->d, vr_d, rb_d, nrep, nbins, psum_d, pcnt_d, umax_d,
-                           (double*)(base + o_u2p), (double*)(base + o_osum),
+    err = launch_vv_reduce(s->d, vr_d, (const int2*)(base2 + o_ch), (int)nch, rb_d, nrep, nbins,
+                           psum_d, pcnt_d, (unsigned long long*)(base2 + o_flo),
+                           (long long*)(base2 + o_fhi), (unsigned long long*)(base2 + o_fcnt),
+                           umax_d, (double*)(base + o_u2p), (double*)(base + o_osum),
                            (long long*)(base + o_ocnt), (double*)(base + o_ou2), st);
   if (!err)
     err = hipMemcpyAsync(sum, base + o_osum, sizeof(double) * nrep * nbins, hipMemcpyDeviceToHost, st);

@@ -15,14 +15,15 @@
 // k^2 <= r^2 c, c = nbins^2 / r_max^2, capped at nbins - 1.
 //
 // Layout.  A coarse Lees-Edwards cell grid with cells of at least r_max / M
-// per axis (M from the density, so that a cell holds about a block's worth
-// of particles); the particles are copied into coarse-cell order with their
-// relative velocities.  k_vv_pairs: one block per chunk of up to VV_HOME
+// per axis (the host picks the largest reach M <= 8 whose cells hold at
+// least 8 particles on average); the particles are copied into coarse-cell
+// order with their relative velocities.  k_vv_pairs: one block (one wave) per chunk of up to VV_HOME
 // particles of one cell; it walks the (2M+1)^2 rows of candidate cells
 // (rows across the y boundary cover the x range shifted by the offset;
 // cells farther than r_max from the home cell are skipped), stages each run
 // of cells through LDS and lets every home particle test every staged
-// candidate.  Ordered pairs are counted from both ends.
+// candidate (lanes of a small cell split into groups that take every G-th
+// candidate).  Ordered pairs are counted from both ends.
 //
 // Determinism.  Each product u_i . u_j is rounded to a fixed-point integer
 // with a per-replica power-of-two scale 2^S (S from the largest |u|^2 and a
@@ -46,16 +47,20 @@
 
 namespace {
 
-constexpr int VV_HOME = 128;      // home particles (threads) per block
+constexpr int VV_HOME = 64;       // home particles (threads, one wave) per block
+constexpr int VV_STAGE = 256;     // candidates staged in LDS at a time
 constexpr int VV_THREADS = 1024;  // threads of the binning kernels
+constexpr int VV_FOLD = 256;      // table blocks folded per first-stage reduce block
 
 }  // namespace
 
 // bin of t >= 0: the largest k with k^2 <= t, capped at nb - 1
+// (t < nb^2 (1 + eps) <= 2^20 (1 + eps) for an accepted pair, so the
+// single-precision root is within one of the answer: one correction each way)
 __device__ __forceinline__ int vv_bin(double t, int nb) {
   int k = (int)sqrtf((float)t);
-  while ((double)(k + 1) * (double)(k + 1) <= t) ++k;
-  while (k > 0 && (double)k * (double)k > t) --k;
+  k += ((double)(k + 1) * (double)(k + 1) <= t) ? 1 : 0;
+  k -= ((double)k * (double)k > t) ? 1 : 0;
   return k < nb - 1 ? k : nb - 1;
 }
 
@@ -140,7 +145,28 @@ __global__ __launch_bounds__(VV_THREADS) void k_vv_scatter(DevPtrs d, int flow,
   }
 }
 
-// pairs of one chunk of home particles with every candidate of its stencil
+// one accepted pair: its bin, and the fixed-point product added to the
+// block's histogram (integer LDS atomics: order-independent)
+__device__ __forceinline__ void vv_accept(double r2, const double4& hu, const double4& w,
+                                          double cscale, double scale, int nb,
+                                          unsigned long long* hs, unsigned int* hc) {
+  const int k = vv_bin(__dmul_rn(r2, cscale), nb);
+  const double p = __dadd_rn(__dadd_rn(__dmul_rn(hu.x, w.x), __dmul_rn(hu.y, w.y)),
+                             __dmul_rn(hu.z, w.z));
+  const long long qv = (long long)rint(p * scale);
+  atomicAdd(&hs[k], (unsigned long long)qv);
+  atomicAdd(&hc[k], 1u);
+}
+
+// pairs of one chunk of home particles with every candidate of its stencil.
+// Rows of cells inside the box (0 <= row < ncy, every axis split into cells)
+// take a fast path: the image of a whole run of cells is known (no y image,
+// x and z periodic shifts fixed per run), so d = R_i - R_j is formed with
+// the same rounded operations the neighbour search applies to every pair it
+// accepts (a shift of L in x or z only where the search would apply it, and
+// where the two disagree -- |d| exactly L/2 -- only the sign differs), and
+// r^2 is the same bits.  Rows across the y boundary and one-cell axes use
+// the full per-pair separation.
 __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __restrict__ vr,
                                                       const VvBlock* __restrict__ blocks, int nblk,
                                                       const int32_t* __restrict__ cstart,
@@ -149,21 +175,30 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
                                                       const unsigned long long* __restrict__ umax,
                                                       int nb, long long* __restrict__ psum,
                                                       unsigned long long* __restrict__ pcnt) {
-  extern __shared__ unsigned long long vv_hist[];  // [nb] sums, then [nb] counts
-  __shared__ double4 cp[VV_HOME], cu[VV_HOME];
+  extern __shared__ unsigned long long vv_hist[];  // [nb] sums, then [nb] 32-bit counts
+  __shared__ double4 cp[VV_STAGE], cu[VV_STAGE];
   const int b = xcd_block(blockIdx.x, nblk);
   if (b >= nblk) return;
   const VvBlock B = blocks[b];
   const RepDev& R = d.rep[B.rep];
   const VvRep& V = vr[B.rep];
   const int t = threadIdx.x;
-  for (int k = t; k < 2 * nb; k += VV_HOME) vv_hist[k] = 0ull;
   unsigned long long* hs = vv_hist;
-  unsigned long long* hc = vv_hist + nb;
+  unsigned int* hc = (unsigned int*)(vv_hist + nb);
+  for (int k = t; k < nb; k += VV_HOME) {
+    hs[k] = 0ull;
+    hc[k] = 0u;
+  }
   const double delta = le_offset(R, *d.step_d - 1);
   const double scale = ldexp(1.0, vv_scale_exp(umax[B.rep], V.log2p));
-  const bool home = t < B.count;
-  const int64_t self = (int64_t)B.start + t;
+  const double rmax2 = V.rmax2, cscale = V.cscale;
+  // lanes: P = next power of two >= the home count; G = 64 / P groups of P
+  // lanes share the wave, group g testing candidates g, g + G, g + 2G, ...
+  int P = 1;
+  while (P < B.count) P <<= 1;
+  const int G = VV_HOME / P, g = t / P, hl = t & (P - 1);
+  const bool home = hl < B.count;
+  const int64_t self = (int64_t)B.start + hl;
   double4 hp = make_double4(0.0, 0.0, 0.0, 0.0), hu = hp;
   if (home) {
     hp = spos[self];
@@ -174,21 +209,26 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
   const int cx = cl % ncx, cy = (cl / ncx) % ncy, cz = cl / (ncx * ncy);
   const int M = V.M;
   const int zr = ncz == 1 ? 0 : M, yr = ncy == 1 ? 0 : M;
+  const bool split = ncx > 1 && ncy > 1 && ncz > 1;
   __syncthreads();
   for (int dz = -zr; dz <= zr; ++dz) {
     const double gz = fmax((double)(abs(dz) - 1) * V.len[2] - V.margin, 0.0);
+    const int czu = cz + dz;
+    const int cz2 = imod(czu, ncz);
+    const int kz = czu < 0 ? -1 : (czu >= ncz ? 1 : 0);  // z image of the row
     for (int dy = -yr; dy <= yr; ++dy) {
       const double gy = fmax((double)(abs(dy) - 1) * V.len[1] - V.margin, 0.0);
-      const double rem = V.rmax2 - gy * gy - gz * gz;
+      const double rem = rmax2 - gy * gy - gz * gz;
       if (rem < 0.0) continue;  // the whole row of cells is beyond r_max
       const double reach = sqrt(rem) + V.margin;
-      const int cz2 = imod(cz + dz, ncz);
       const int cyr = cy + dy;
       int cy2, lo, hi;
+      bool fast = false;
       if (ncy == 1) {
         cy2 = 0; lo = 0; hi = ncx - 1;
       } else if (cyr >= 0 && cyr < ncy) {
         cy2 = cyr;
+        fast = split;
         if (ncx == 1) {
           lo = 0; hi = 0;
         } else {
@@ -205,38 +245,48 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
         if (hi - lo + 1 >= ncx) { lo = 0; hi = ncx - 1; }
       }
       const int rowbase = V.cell0 + (cz2 * ncy + cy2) * ncx;
-      int a = imod(lo, ncx);
+      int u0 = lo;            // unwrapped first cell of the next segment
       int len = hi - lo + 1;
       while (len > 0) {
+        const int a = imod(u0, ncx);
+        const int kx = u0 < 0 ? -1 : (u0 >= ncx ? 1 : 0);  // x image of the segment
         const int run = (a + len <= ncx) ? len : (ncx - a);
         const int j0 = cstart[rowbase + a], j1 = cstart[rowbase + a + run];
-        for (int c0 = j0; c0 < j1; c0 += VV_HOME) {
-          const int m = min(VV_HOME, j1 - c0);
-          if (t < m) {
-            cp[t] = spos[c0 + t];
-            cu[t] = su[c0 + t];
+        for (int c0 = j0; c0 < j1; c0 += VV_STAGE) {
+          const int m = min(VV_STAGE, j1 - c0);
+          for (int q = t; q < m; q += VV_HOME) {
+            cp[q] = spos[c0 + q];
+            cu[q] = su[c0 + q];
           }
           __syncthreads();
-          if (home) {
-            for (int jj = 0; jj < m; ++jj) {
+          if (home && fast) {
+            for (int jj = g; jj < m; jj += G) {
+              const double4 q = cp[jj];
+              double dx = __dsub_rn(hp.x, q.x);
+              if (kx < 0) dx = __dadd_rn(dx, R.L[0]);        // j's image one box below in x
+              else if (kx > 0) dx = __dsub_rn(dx, R.L[0]);   // one box above
+              const double dyy = __dsub_rn(hp.y, q.y);
+              double dzz = __dsub_rn(hp.z, q.z);
+              if (kz < 0) dzz = __dadd_rn(dzz, R.L[2]);
+              else if (kz > 0) dzz = __dsub_rn(dzz, R.L[2]);
+              const double r2 = dist2(dx, dyy, dzz);
+              if (r2 < rmax2 && (int64_t)(c0 + jj) != self)
+                vv_accept(r2, hu, cu[jj], cscale, scale, nb, hs, hc);
+            }
+          } else if (home) {
+            for (int jj = g; jj < m; jj += G) {
               const double4 q = cp[jj];
               double dx, dyy, dzz;
               le_sep(R, delta, hp.x, hp.y, hp.z, q.x, q.y, q.z, dx, dyy, dzz);
               const double r2 = dist2(dx, dyy, dzz);
-              if (r2 < V.rmax2 && (int64_t)(c0 + jj) != self) {
-                const int k = vv_bin(__dmul_rn(r2, V.cscale), nb);
-                const double4 w = cu[jj];
-                const double p = hu.x * w.x + hu.y * w.y + hu.z * w.z;
-                const long long qv = (long long)rint(p * scale);
-                atomicAdd(&hs[k], (unsigned long long)qv);
-                atomicAdd(&hc[k], 1ull);
-              }
+              if (r2 < rmax2 && (int64_t)(c0 + jj) != self)
+                vv_accept(r2, hu, cu[jj], cscale, scale, nb, hs, hc);
             }
           }
           __syncthreads();
         }
+        u0 += run;
         len -= run;
-        a = 0;
       }
     }
   }
@@ -247,13 +297,46 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
   }
 }
 
-// per replica and bin: the blocks' integers added exactly (128 bits, block
-// order), halved (each pair was counted from both ends) and scaled back;
-// per replica the blocks' |u|^2 sums in block order
+// first reduce stage: per chunk of up to VV_FOLD table blocks of one
+// replica and per bin, the blocks' integers added exactly in 128 bits
+__device__ __forceinline__ void add128(unsigned long long& lo, long long& hi,
+                                       unsigned long long vlo, long long vhi) {
+  const unsigned long long nlo = lo + vlo;
+  hi += vhi + (nlo < lo ? 1 : 0);
+  lo = nlo;
+}
+
+__global__ __launch_bounds__(256) void k_vv_fold(const int2* __restrict__ chunks, int nb,
+                                                 const long long* __restrict__ psum,
+                                                 const unsigned long long* __restrict__ pcnt,
+                                                 unsigned long long* __restrict__ f_lo,
+                                                 long long* __restrict__ f_hi,
+                                                 unsigned long long* __restrict__ f_cnt) {
+  const int2 c = chunks[blockIdx.x];
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    unsigned long long lo = 0ull, cnt = 0ull;
+    long long hi = 0;
+    for (int bb = c.x; bb < c.y; ++bb) {
+      const long long v = psum[(int64_t)bb * nb + k];
+      add128(lo, hi, (unsigned long long)v, v < 0 ? -1 : 0);
+      cnt += pcnt[(int64_t)bb * nb + k];
+    }
+    const int64_t o = (int64_t)blockIdx.x * nb + k;
+    f_lo[o] = lo;
+    f_hi[o] = hi;
+    f_cnt[o] = cnt;
+  }
+}
+
+// second stage, per replica and bin: the chunks' 128-bit integers added
+// exactly (chunk order), halved (each pair was counted from both ends) and
+// scaled back; per replica the blocks' |u|^2 sums in block order
 __global__ __launch_bounds__(256) void k_vv_reduce(DevPtrs d, const VvRep* __restrict__ vr,
-                                                   const int32_t* __restrict__ rep_blk0, int nrep,
-                                                   int nb, const long long* __restrict__ psum,
-                                                   const unsigned long long* __restrict__ pcnt,
+                                                   const int32_t* __restrict__ rep_chunk0,
+                                                   int nrep, int nb,
+                                                   const unsigned long long* __restrict__ f_lo,
+                                                   const long long* __restrict__ f_hi,
+                                                   const unsigned long long* __restrict__ f_cnt,
                                                    const unsigned long long* __restrict__ umax,
                                                    const double* __restrict__ u2_part,
                                                    double* __restrict__ out_sum,
@@ -262,15 +345,12 @@ __global__ __launch_bounds__(256) void k_vv_reduce(DevPtrs d, const VvRep* __res
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o < (int64_t)nrep * nb) {
     const int rep = (int)(o / nb), k = (int)(o % nb);
-    unsigned long long lo = 0ull;
+    unsigned long long lo = 0ull, c = 0ull;
     long long hi = 0;
-    unsigned long long c = 0ull;
-    for (int bb = rep_blk0[rep]; bb < rep_blk0[rep + 1]; ++bb) {
-      const long long v = psum[(int64_t)bb * nb + k];
-      const unsigned long long nlo = lo + (unsigned long long)v;
-      hi += (v < 0 ? -1 : 0) + (nlo < lo ? 1 : 0);
-      lo = nlo;
-      c += pcnt[(int64_t)bb * nb + k];
+    for (int ch = rep_chunk0[rep]; ch < rep_chunk0[rep + 1]; ++ch) {
+      const int64_t q = (int64_t)ch * nb + k;
+      add128(lo, hi, f_lo[q], f_hi[q]);
+      c += f_cnt[q];
     }
     // halve exactly: the total is even
     lo = (lo >> 1) | ((unsigned long long)hi << 63);
@@ -316,7 +396,7 @@ hipError_t launch_vv_pairs(const DevPtrs& d, const VvRep* vr, const VvBlock* blo
                            hipEvent_t ev1) {
   if (nblk <= 0) return hipSuccess;
   const dim3 g(xcd_grid(nblk)), bl(VV_HOME);
-  const size_t lds = sizeof(unsigned long long) * 2 * (size_t)nb;
+  const size_t lds = (sizeof(unsigned long long) + sizeof(unsigned int)) * (size_t)nb;
   if (ev0 || ev1)
     hipExtLaunchKernelGGL(k_vv_pairs, g, bl, lds, s, ev0, ev1, 0, d, vr, blocks, nblk, cstart,
                           spos, su, umax, nb, psum, pcnt);
@@ -326,12 +406,20 @@ hipError_t launch_vv_pairs(const DevPtrs& d, const VvRep* vr, const VvBlock* blo
   return hipGetLastError();
 }
 
-hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int32_t* rep_blk0, int nrep,
-                            int nb, const long long* psum, const unsigned long long* pcnt,
+int vv_fold() { return VV_FOLD; }
+
+hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int2* chunks, int nchunk,
+                            const int32_t* rep_chunk0, int nrep, int nb, const long long* psum,
+                            const unsigned long long* pcnt, unsigned long long* f_lo,
+                            long long* f_hi, unsigned long long* f_cnt,
                             const unsigned long long* umax, const double* u2_part,
                             double* out_sum, long long* out_cnt, double* out_u2, hipStream_t s) {
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_vv_fold, dim3((unsigned)nchunk), dim3(256), 0, s, chunks, nb, psum, pcnt,
+                       f_lo, f_hi, f_cnt);
   const int64_t n = std::max<int64_t>((int64_t)nrep * nb, nrep);
   hipLaunchKernelGGL(k_vv_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, vr,
-                     rep_blk0, nrep, nb, psum, pcnt, umax, u2_part, out_sum, out_cnt, out_u2);
+                     rep_chunk0, nrep, nb, f_lo, f_hi, f_cnt, umax, u2_part, out_sum, out_cnt,
+                     out_u2);
   return hipGetLastError();
 }

@@ -8,7 +8,7 @@ that step and v_n from the state after it, and the offset of step n.
 Tolerance from the arithmetic: both sides form r^2, the bin and every product
 u_i . u_j with the same FP64 operations (no contraction), so pair counts are
 compared exactly.  The library rounds each product to a multiple of 2^-S
-(S = 61 - ceil(log2(128 n)) - e, max |u|^2 < 2^e) and adds integers exactly,
+(S = 61 - ceil(log2(64 n)) - e, max |u|^2 < 2^e) and adds integers exactly,
 then converts once to FP64; the oracle's compensated sum is within ~2 ulp of
 the exact sum.  So |sum - sum_ref| <= count 2^-(S+1) + 4 eps |sum_ref|; the
 tests allow 2^-S per pair (S one lower, for a maximum that rounds across a
@@ -17,12 +17,13 @@ power of two) plus 4 eps umax^2 per pair and 8 eps |sum|.
 Cases:
 * small cubes, sheared and not, flow removed and not, one with r_max close
   to L/2 (every axis one coarse cell: all pairs tested);
-* a stencil reach of two cells with x one cell (N = 20000, r_max = 10.5);
-* a reach of three cells on every axis with distance culling of cells
+* N = 20000: stencil reaches of three and five cells on every axis;
+* a flat box whose x axis is one cell (reach five in y and z);
+* a reach of seven cells on every axis with distance culling of cells
   (N = 66000, r_max = 15.15), through step graphs;
 * a batch of uneven replicas;
 * N = 10^6 (L = 100): r_max = 2 against the oracle, and r_max = 16 (reach
-  three) giving the same bits in the bins both cover;
+  eight) giving the same bits in the bins both cover;
 * determinism, validity after sim_solve, argument checks.
 """
 import math
@@ -55,7 +56,7 @@ def check(cfg, pos_n, vel_n, step_n, got, r_max, nb, flow):
     u = rel_u(cfg, pos_n, vel_n, flow)
     umax2 = float((u * u).sum(1).max())
     e = math.frexp(umax2)[1]
-    lg = math.ceil(math.log2(128 * len(pos_n)))
+    lg = math.ceil(math.log2(64 * len(pos_n)))
     S_lo = 61 - lg - e - 1
     tol = c_ref * (2.0 ** -S_lo + 4 * EPS * umax2) + 8 * EPS * np.abs(s_ref) + 1e-300
     err = np.abs(s - s_ref)
@@ -86,15 +87,29 @@ def test_small_cube_matches_oracle(shear, r_max, nb, flow):
     assert c_ref.sum() > 0
 
 
-def test_reach_two_with_one_cell_in_x():
+@pytest.mark.parametrize("r_max,nb", [(7.0, 28), (10.5, 42)])
+def test_reach_three_and_five(r_max, nb):
+    # N = 20000 (L = 27.1): the library's grid for r_max = 7 has a reach of
+    # three cells on 11 x 11 x 11 cells, for r_max = 10.5 a reach of five on
+    # 12 x 12 x 12 (cells of the stencil's corners culled)
     cfg = inputs.cube_params(20000, 0.3, seed=22)
     pos0 = inputs.uniform_positions(20000, cfg["box"], 22)
     with S.Sim(cfg, pos0) as sim:
-        pos_n, vel, n, got = run_and_correlate(sim, 2, 10.5, 42, True)
-    check(cfg, pos_n, vel, n, got, 10.5, 42, True)
+        pos_n, vel, n, got = run_and_correlate(sim, 2, r_max, nb, True)
+    check(cfg, pos_n, vel, n, got, r_max, nb, True)
 
 
-def test_reach_three_with_culling_through_graphs():
+def test_flat_box_with_one_cell_in_x():
+    # box 10 x 26 x 26 (density 1): x is one cell, y and z have a reach of
+    # five cells, so rows across the y boundary and culled rows both occur
+    cfg = inputs.base_params(n=6760, box=(10.0, 26.0, 26.0), shear_rate=0.8, seed=26)
+    pos0 = inputs.uniform_positions(6760, cfg["box"], 26)
+    with S.Sim(cfg, pos0) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 3, 4.5, 45, True)
+    check(cfg, pos_n, vel, n, got, 4.5, 45, True)
+
+
+def test_reach_seven_with_culling_through_graphs():
     cfg = inputs.cube_params(66000, 0.5, seed=23)
     pos0 = inputs.uniform_positions(66000, cfg["box"], 23)
     with S.Sim(cfg, pos0) as sim:
@@ -126,7 +141,7 @@ def test_full_size_against_oracle_and_across_reaches():
         pos_n, vel, n, got = run_and_correlate(sim, 2, 2.0, 4, True)
         big = sim.velocity_correlation(16.0, 32, flow=True, timed=True)
     check(cfg, pos_n, vel, n, got, 2.0, 4, True)
-    # bins of width 0.5 in both: the reach-three grid gives the same integers
+    # bins of width 0.5 in both: the reach-eight grid gives the same integers
     np.testing.assert_array_equal(big[1][0, :4], got[1][0])
     np.testing.assert_array_equal(big[0][0, :4], got[0][0])
     assert big[3] > 0
