@@ -35,6 +35,9 @@ METRIC = "particle-steps/sec at CG rel. residual 1e-8; learned-PCG vs plain-PCG,
 PEAK_HBM_GBS = 8000.0
 # FP64 vector FMA peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
+# FP64 vector instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (an add or
+# multiply is one op; the 78.6 TFLOP/s figure counts a fused multiply-add as two)
+PEAK_FP64_TOPS = 39.3
 SHEARS = (0.01, 0.1, 0.5)
 
 
@@ -128,6 +131,29 @@ def measure_sq(sim, n, np, nx=64, my_max=64, reps=3):
     return dict(grid=f"mx 0..{nx - 1} x my -{my_max}..{my_max}, mz 0", particles=n,
                 kernel_ms_events=round(kernel_ms, 4), flops_per_call=flops,
                 s_q0=float(s[0, 0, my_max]))
+
+
+# FP64 operations of one accepted ordered pair in the velocity correlation:
+# separation 3, r^2 5, cut-off compare 1, bin scale 1, u_i . u_j 5,
+# fixed-point scale and rounding 2
+VV_OPS_PER_PAIR = 17
+
+
+def measure_vv(sim, n, np, r_max=10.0, nbins=100, reps=3):
+    """Velocity cross-correlation of the last step (Results section), pairs
+    with r < r_max = 10 in bins of 0.1: the pair kernel's event-timed
+    duration and its rate in accepted ordered pairs (each unordered pair is
+    tested from both ends)."""
+    sim.velocity_correlation(r_max, nbins)  # untimed first call (scratch)
+    ms = []
+    for _ in range(reps):
+        s, c, u2, t = sim.velocity_correlation(r_max, nbins, timed=True)
+        ms.append(t)
+    pairs = int(c.sum())
+    norm = (s[0] / np.maximum(c[0], 1)) / (u2[0] / n)
+    return dict(r_max=r_max, nbins=nbins, particles=n, pairs=pairs,
+                kernel_ms_events=round(float(np.mean(ms)), 4),
+                corr_bins_0_to_2=[round(float(x), 5) for x in norm[:20]])
 
 
 def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label="",
@@ -314,7 +340,8 @@ def main():
     runs = {}
     head = "learned" if "learned" in forms else forms[0]
     for form in forms:
-        after = (lambda sims: measure_sq(sims[0], cfgs[0]["n"], np)) if form == head else None
+        after = (lambda sims: dict(sq=measure_sq(sims[0], cfgs[0]["n"], np),
+                                   vv=measure_vv(sims[0], cfgs[0]["n"], np))) if form == head else None
         runs[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, after=after)
     hr = runs[head]
     value = hr["value"]
@@ -374,17 +401,31 @@ def main():
                   for f, r in runs.items()},
         "graph_steps": not args.no_graph,
     }
-    sqm = hr.get("extra")
+    extra = hr.get("extra") or {}
+    sqm = extra.get("sq")
     if sqm:
         # structure factor of the first box's final state: the contraction
-        # kernel is bound by FP64 FMA throughput (the 24 bytes of a particle
-        # feed nx * ny complex multiply-adds)
+        # runs on the FP64 matrix cores (the 24 bytes of a particle feed
+        # nx * ny complex multiply-adds)
         ms = sqm["kernel_ms_events"] - args.event_over_us * 1e-3
         tf = sqm["flops_per_call"] / (ms * 1e-3) / 1e12
         out["structure_factor"] = dict(
             sqm, kernel="k_sq_partial", kernel_ms=round(ms, 4),
-            roofline=dict(bound="alu", achieved=round(tf, 2), peak=PEAK_FP64_TFLOPS,
+            roofline=dict(bound="mfma", achieved=round(tf, 2), peak=PEAK_FP64_TFLOPS,
                           unit="TFLOP/s", frac=round(tf / PEAK_FP64_TFLOPS, 4)))
+    vvm = extra.get("vv")
+    if vvm:
+        # velocity correlation of the first box's last step: pair tests and
+        # accepted-pair arithmetic on the FP64 vector units
+        ms = vvm["kernel_ms_events"] - args.event_over_us * 1e-3
+        ordered = 2 * vvm["pairs"]
+        tops = VV_OPS_PER_PAIR * ordered / (ms * 1e-3) / 1e12
+        out["velocity_correlation"] = dict(
+            vvm, kernel="k_vv_pairs", kernel_ms=round(ms, 4),
+            ordered_pairs_per_s=round(ordered / (ms * 1e-3), 1),
+            roofline=dict(bound="alu", achieved=round(tops, 3), peak=PEAK_FP64_TOPS,
+                          unit="Top/s", frac=round(tops / PEAK_FP64_TOPS, 4),
+                          ops_per_pair=VV_OPS_PER_PAIR))
     if "learned" in runs and "plain" in runs:
         out["learned_vs_plain"] = round(runs["learned"]["value"] / runs["plain"]["value"], 4)
     if args.batch > 0:
