@@ -87,6 +87,15 @@ def lib():
         L.orc_step.argtypes = [pp, C.c_int64, d_p, d_p, C.c_double, C.c_int, C.c_int, P(C.c_int)]
         L.orc_step.restype = C.c_int
         L.orc_wrap.argtypes = [pp, C.c_int64, d_p]
+        L.orc_build_block_system.argtypes = [pp, C.c_double, C.c_double, C.c_int64, d_p,
+                                             C.c_int64, i64_p, i64_p, d_p, d_p, d_p]
+        L.orc_build_block_system.restype = C.c_int64
+        L.orc_block_pcg.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, d_p, C.c_double,
+                                    C.c_int, P(C.c_int)]
+        L.orc_block_pcg.restype = C.c_int
+        L.orc_step_block.argtypes = [pp, C.c_double, C.c_double, C.c_int64, d_p, d_p,
+                                     C.c_double, C.c_int, P(C.c_int)]
+        L.orc_step_block.restype = C.c_int
         L.orc_velocity_correlation.argtypes = [pp, C.c_double, d_p, d_p, C.c_double, C.c_int32,
                                                C.c_int32, C.c_int32, d_p, i64_p, d_p]
         L.orc_velocity_correlation.restype = C.c_int
@@ -299,6 +308,64 @@ def wrap(cfg, pos, step_after):
 
 
 # ---- learned preconditioner ---------------------------------------------------
+
+def build_block_system(cfg, pos, a_par, a_perp, step=0):
+    """Anisotropic friction system (block.c): dict(rowptr, col, bval (m, 3, 3),
+    bdiag (n, 3, 3), rhs (n, 3)), original ids, rows' entries in pair order."""
+    p = make_params(cfg)
+    n = p.n
+    pos = _f64(pos, (-1, 3))
+    np_ = lib().orc_count_pairs(C.byref(p), int(step), _dp(pos))
+    cap = max(2 * np_, 1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(cap, dtype=np.int64)
+    bval = np.zeros((cap, 3, 3))
+    bdiag = np.zeros((n, 3, 3))
+    rhs = np.zeros((n, 3))
+    m = lib().orc_build_block_system(C.byref(p), float(a_par), float(a_perp), int(step), _dp(pos),
+                                     cap, _ip(rowptr), _ip(col), _dp(bval), _dp(bdiag), _dp(rhs))
+    if m < 0:
+        raise MemoryError("oracle block system failed")
+    return dict(rowptr=rowptr, col=col[:m], bval=bval[:m], bdiag=bdiag, rhs=rhs)
+
+
+def block_dense(sys_):
+    """the 3n x 3n matrix of a block system"""
+    n = len(sys_["bdiag"])
+    A = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        A[3 * i:3 * i + 3, 3 * i:3 * i + 3] = sys_["bdiag"][i]
+        for e in range(sys_["rowptr"][i], sys_["rowptr"][i + 1]):
+            j = sys_["col"][e]
+            A[3 * i:3 * i + 3, 3 * j:3 * j + 3] = sys_["bval"][e]
+    return A
+
+
+def block_pcg(sys_, rhs=None, tol=1e-12, maxit=20000):
+    n = len(sys_["bdiag"])
+    b = _f64(sys_["rhs"] if rhs is None else rhs, (n, 3))
+    x = np.zeros((n, 3))
+    it = C.c_int(0)
+    rc = lib().orc_block_pcg(n, _ip(sys_["rowptr"]), _ip(np.ascontiguousarray(sys_["col"])),
+                             _dp(np.ascontiguousarray(sys_["bval"])), _dp(sys_["bdiag"]), _dp(b),
+                             _dp(x), float(tol), int(maxit), C.byref(it))
+    if rc:
+        raise RuntimeError(f"oracle block PCG status {rc}")
+    return x, it.value
+
+
+def step_block(cfg, pos, step_index, a_par, a_perp, tol=1e-10, maxit=20000):
+    """one step with anisotropic friction; returns (new positions, velocities, iterations)"""
+    p = make_params(cfg)
+    pos = _f64(pos, (-1, 3)).copy()
+    vel = np.zeros_like(pos)
+    it = C.c_int(0)
+    rc = lib().orc_step_block(C.byref(p), float(a_par), float(a_perp), int(step_index), _dp(pos),
+                              _dp(vel), float(tol), int(maxit), C.byref(it))
+    if rc:
+        raise RuntimeError(f"oracle block step status {rc}")
+    return pos, vel, it.value
+
 
 def velocity_correlation(cfg, delta, pos, vel, r_max, nbins, flow=True, cells=None):
     """Pair sums of u_i . u_j, pair counts (unordered pairs) per distance bin

@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle.c", "mpnn.c", "vv.c"]
+SOURCES = ["oracle.c", "mpnn.c", "vv.c", "block.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -255,7 +255,7 @@ int64_t orc_count_pairs(const orc_params* p, int64_t step, const double* pos) {
 
 /* entanglement weight w(r): Gaussian of width lambda (Method, after Eq. 7)
  * or the polynomial envelope (1 - r/rc)^2 (another "reasonable shape")   */
-static double orc_weight(const orc_params* p, double r2) {
+double orc_weight(const orc_params* p, double r2) {
   if (p->weight_law == ORC_W_GAUSS) return exp(-0.5 * r2 / (p->lambda * p->lambda));
   double t = 1.0 - sqrt(r2) / p->rc;
   return t * t;
@@ -265,7 +265,7 @@ static double orc_weight(const orc_params* p, double r2) {
  * Gaussian core, Eq. 6b: U = kT*u_amp*exp(-r^2/(2 lambda^2)), u_amp = v/lambda^3,
  *   so F = (kT*u_amp/lambda^2) * exp(-r^2/(2 lambda^2)) * d.
  * Soft: U = u_amp*(1 - r/rc)^2, so F = (2*u_amp/rc)*(1 - r/rc) * d/r (0 at r = 0). */
-static void orc_pair_force(const orc_params* p, const double d[3], double r2, double f[3]) {
+void orc_pair_force(const orc_params* p, const double d[3], double r2, double f[3]) {
   double coef = 0.0;
   if (p->potential == ORC_U_GAUSS_CORE) {
     double l2 = p->lambda * p->lambda;

@@ -76,6 +76,32 @@ int orc_velocity_correlation(const orc_params* p, double delta, const double* po
                              const double* vel, double r_max, int32_t nbins, int32_t flow,
                              int32_t use_cells, double* sum, int64_t* count, double* u2);
 
+/* pair weight w(r^2) and conservative force F_ij on i (used by block.c) */
+double orc_weight(const orc_params* p, double r2);
+void orc_pair_force(const orc_params* p, const double d[3], double r2, double f[3]);
+
+/* ---- anisotropic pair friction (block.c) ----------------------------------- */
+/* Pair friction tensor W_ij = alpha w_ij (a_perp I + (a_par - a_perp) P_ij),
+ * P_ij = d d^T / r^2 (0 at r = 0): friction a_par along the line of centres,
+ * a_perp across it; a_par = a_perp = 1 is the isotropic system A (x) I_3.
+ * The 3n x 3n system: A_ii = gamma0 I + sum_j W_ij, A_ij = -W_ij (3 x 3
+ * blocks, 9 doubles row-major per entry / per row), rhs as orc_build_system
+ * with the boundary drag W_ij V_ij and, in FDT mode, the pair noise
+ * sqrt(2kT/dt) sigma_ij W_ij^(1/2) eta_ij, W^(1/2) = sqrt(alpha w)
+ * (sqrt(a_perp) I + (sqrt(a_par) - sqrt(a_perp)) P).  Returns the entries
+ * (2 x pairs) or -1.                                                       */
+int64_t orc_build_block_system(const orc_params* p, double a_par, double a_perp, int64_t step,
+                               const double* pos, int64_t cap, int64_t* rowptr, int64_t* col,
+                               double* bval, double* bdiag, double* rhs);
+/* plain CG (Jacobi on the scalar diagonal) on the 3n stacked unknowns;
+ * stops when ||b - A x|| <= tol ||b|| (true residual).  0, -4 no convergence. */
+int orc_block_pcg(int64_t n, const int64_t* rowptr, const int64_t* col, const double* bval,
+                  const double* bdiag, const double* rhs, double* x, double tol, int maxit,
+                  int* iters);
+/* one step with the block system: build, solve to tol, R += v dt, wrap */
+int orc_step_block(const orc_params* p, double a_par, double a_perp, int64_t step, double* pos,
+                   double* vel, double tol, int maxit, int* iters);
+
 /* ---- friction system ------------------------------------------------------ */
 int64_t orc_count_pairs(const orc_params* p, int64_t step, const double* pos);
 int64_t orc_build_system(const orc_params* p, int64_t step, const double* pos,
