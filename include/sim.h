@@ -123,6 +123,19 @@ typedef struct sim_params {
   double cg_tol;
   uint64_t seed;
   uint64_t stream;
+  /* Anisotropic pair friction (the paper's elongated-particle remedy,
+   * Discussion): the pair coefficient of Eq. 7 becomes the tensor
+   * W_ij = alpha w_ij (friction_perp I + (friction_par - friction_perp)
+   * d d^T / r^2), friction_par along the line of centres and friction_perp
+   * across it, so A has 3 x 3 blocks and the pair noise is
+   * sqrt(2kT/dt) W^(1/2) eta.  0 stands for 1; both 1 (or 0) is the
+   * isotropic method.  When any replica has a value other than 1 the handle
+   * solves the block system: block-Jacobi CG over the 3n coupled unknowns,
+   * one true-residual tolerance per replica on the stacked vector; steps run
+   * eagerly (no step graphs); precond must be Jacobi or none and spmv_fp32,
+   * warm_start 0, else SIM_ENOTSUP.                                          */
+  double friction_par;
+  double friction_perp;
 } sim_params;
 
 /* Statistics of the last sim_step / sim_solve call (max over replicas). */
@@ -251,6 +264,15 @@ int sim_debug_pairs(sim_t* sim, int64_t* ijr, int64_t cap, int64_t* count);
  * (including the thermal force of this step).  Same capacity rule.        */
 int sim_debug_system(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
                      int64_t* count, double* diag, double* rhs);
+
+/* The block system (handles with anisotropic friction) of the current
+ * positions and step, in original ids: rows/cols (cap entries, *count set
+ * to the number of off-diagonal blocks), vals (9 doubles per entry,
+ * row-major -W_ij), diag (9 per particle, nullable), rhs (n_total x 3,
+ * nullable); host pointers.  SIM_ENOTSUP on an isotropic handle,
+ * SIM_ECAPACITY when cap is too small.  For parity tests.                  */
+int sim_debug_block_system(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                           int64_t* count, double* diag, double* rhs);
 
 /* Replace the generated Gaussians of the thermal force (testing only,
  * single-replica handles with n <= 1024): xi is n x 3 (particle i at row

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libsim.so")
-SOURCES = ["kernels.hip", "cg.hip", "ic0.hip", "mpnn.hip", "sq.hip", "vv.hip", "sim_api.hip"]
+SOURCES = ["kernels.hip", "cg.hip", "ic0.hip", "mpnn.hip", "sq.hip", "vv.hip", "block.hip", "sim_api.hip"]
 ARCH = os.environ.get("SIM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,384 @@
+// block.hip -- the friction system with anisotropic pair friction on gfx950:
+// the pair coefficient of Eq. 7 becomes a tensor
+//   W_ij = alpha w_ij (a_perp I + (a_par - a_perp) P_ij),  P_ij = d d^T / r^2
+// (friction a_par along the line of centres, a_perp across it; P = 0 at
+// r = 0), so A of Eq. 9 has genuine 3 x 3 blocks:
+//   A_ii = gamma0 I + sum_j W_ij,  A_ij = -W_ij,
+//   b_i  = sum_j F_ij + gamma0 kappa (y_i - Ly/2) x + sum_j W_ij V_ij + f_i,
+// with the fluctuation-dissipation pair noise
+//   sqrt(2kT/dt) sigma_ij W_ij^(1/2) eta_ij,
+//   W^(1/2) = sqrt(alpha w) (sqrt(a_perp) I + (sqrt(a_par) - sqrt(a_perp)) P),
+// eta_ij the same Philox pair Gaussians as the isotropic system.
+//
+// Layout: the neighbour list (CSR, cell order) of the isotropic path; per
+// entry the six values of -W_ij (xx, xy, xz, yy, yz, zz), per row the six
+// values of the diagonal block and of its inverse (block-Jacobi).
+//
+// Solve: preconditioned CG with one recurrence over the 3n stacked
+// unknowns of each replica (the three components are coupled), stopping on
+// the true residual ||b - A x|| <= tol ||b||.  Per iteration: q = A p with
+// tile partials of (p, q); a per-replica finisher (alpha); x, r, z = M^-1 r
+// with partials of (r, z), (r, r); the finisher (convergence, beta);
+// p = z + beta p.  Residual rounds (start, and after the recursive residual
+// meets the tolerance): r = b - A x, z = M^-1 r, p = z.  All reductions in a
+// fixed order: deterministic.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "sim_dev.h"
+
+namespace {
+
+// 3 x 3 symmetric, stored xx, xy, xz, yy, yz, zz
+__device__ __forceinline__ void sym_mul(const double* m, const double v[3], double out[3]) {
+  out[0] = (m[0] * v[0] + m[1] * v[1]) + m[2] * v[2];
+  out[1] = (m[1] * v[0] + m[3] * v[1]) + m[4] * v[2];
+  out[2] = (m[2] * v[0] + m[4] * v[1]) + m[5] * v[2];
+}
+
+__device__ __forceinline__ void sym_inverse(const double* m, double* inv) {
+  const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+  const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+  const double c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+  const double det = (a * c00 + b * c01) + c * c02;
+  const double id = 1.0 / det;
+  inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
+  inv[3] = c11 * id; inv[4] = c12 * id; inv[5] = c22 * id;
+}
+
+__device__ __forceinline__ double pweight(const RepDev& R, double r2, double r) {
+  if (R.weight_law == 0) return exp(-0.5 * r2 * R.inv_lam2);
+  const double t = 1.0 - r / R.rc;
+  return t * t;
+}
+
+__device__ __forceinline__ double pforce(const RepDev& R, double r2, double r) {
+  if (R.potential == 0) return R.force_gc * exp(-0.5 * r2 * R.inv_lam2);
+  if (R.potential == 1) return r > 0.0 ? R.force_soft * (1.0 - r / R.rc) / r : 0.0;
+  return 0.0;
+}
+
+// the tile's partial slots 0..2 from every thread's values (fixed order)
+__device__ __forceinline__ void tile_partials(const DevPtrs& d, int tile, double v0, double v1,
+                                              double v2) {
+  __shared__ double lds[BLOCK_THREADS / 64][3];
+  double v[3] = {v0, v1, v2};
+  block_sum<3>(v, lds);
+  if (threadIdx.x == 0) {
+    double* dst = d.partial + (int64_t)tile * NPART;
+    dst[0] = v[0];
+    dst[1] = v[1];
+    dst[2] = v[2];
+  }
+}
+
+}  // namespace
+
+// Pair terms and assembly of the block system, one thread per row (its CSR
+// entries in order).  Every entry's block and right-hand-side contribution
+// is formed from the separation d_ij of the row's particle; the mirror
+// entry gets the same block and the negated contribution, bit for bit.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_pair_block(DevPtrs d, BlockPtrs bp) {
+  const int blk = xcd_block(blockIdx.x, d.nblk);
+  if (blk >= d.nblk) return;
+  if (d.ctrl->overflow) return;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  const BlockRep& Q = bp.brep[rid];
+  const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + threadIdx.x;
+  if (i - R.row_off >= R.n) {  // padding row: identity, no right-hand side
+    double* D = bp.bdiag + 6 * i;
+    double* I = bp.binv + 6 * i;
+    D[0] = D[3] = D[5] = I[0] = I[3] = I[5] = 1.0;
+    D[1] = D[2] = D[4] = I[1] = I[2] = I[4] = 0.0;
+    d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
+    return;
+  }
+  const int64_t step = *d.step_d;
+  const double delta = le_offset(R, step);
+  const bool noise = R.amp_pair != 0.0 && R.alpha != 0.0;
+  const double c = Q.a_par - Q.a_perp, cs = Q.sq_par - Q.sq_perp;
+  const double vunit = R.shear * R.L[1];
+  const double4 pi = d.pos[i];
+  const int64_t idi = (int64_t)pi.w;
+  double D[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int j = d.col[e];
+    const double4 pj = d.pos[j];
+    double dv[3];
+    const int s = le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dv[0], dv[1], dv[2]);
+    const double r2 = dist2(dv[0], dv[1], dv[2]);
+    const double r = sqrt(r2);
+    const double g = R.alpha * pweight(R, r2, r);
+    double P[6];
+    P[0] = r2 > 0.0 ? (dv[0] * dv[0]) / r2 : 0.0;
+    P[1] = r2 > 0.0 ? (dv[0] * dv[1]) / r2 : 0.0;
+    P[2] = r2 > 0.0 ? (dv[0] * dv[2]) / r2 : 0.0;
+    P[3] = r2 > 0.0 ? (dv[1] * dv[1]) / r2 : 0.0;
+    P[4] = r2 > 0.0 ? (dv[1] * dv[2]) / r2 : 0.0;
+    P[5] = r2 > 0.0 ? (dv[2] * dv[2]) / r2 : 0.0;
+    double W[6];
+    W[0] = g * (Q.a_perp + c * P[0]);
+    W[1] = g * (c * P[1]);
+    W[2] = g * (c * P[2]);
+    W[3] = g * (Q.a_perp + c * P[3]);
+    W[4] = g * (c * P[4]);
+    W[5] = g * (Q.a_perp + c * P[5]);
+    double* out = bp.bval + 6 * e;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      out[m] = -W[m];
+      D[m] += W[m];
+    }
+    // conservative force and boundary drag W V, V = kappa Ly s x (column 0)
+    const double fc = pforce(R, r2, r);
+    const double v = vunit * (double)s;
+    acc[0] += fc * dv[0] + W[0] * v;
+    acc[1] += fc * dv[1] + W[1] * v;
+    acc[2] += fc * dv[2] + W[2] * v;
+    if (noise) {
+      const int64_t idj = (int64_t)pj.w;
+      const int64_t a = idi < idj ? idi : idj, bb = idi < idj ? idj : idi;
+      double gz[3];
+      gauss3(R.seed, R.stream, (uint64_t)step, 1, (uint64_t)a, (uint64_t)bb, gz);
+      const double amp = (idi < idj ? 1.0 : -1.0) * (R.amp_pair * sqrt(g));
+      const double t = (dv[0] * gz[0] + dv[1] * gz[1]) + dv[2] * gz[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double q = r2 > 0.0 ? (dv[k] * t) / r2 : 0.0;
+        acc[k] += amp * (Q.sq_perp * gz[k] + cs * q);
+      }
+    }
+  }
+  double gn[3] = {0.0, 0.0, 0.0};
+  if (R.amp_node != 0.0) gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, gn);
+  D[0] += R.gamma0;
+  D[3] += R.gamma0;
+  D[5] += R.gamma0;
+  double* Dout = bp.bdiag + 6 * i;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) Dout[m] = D[m];
+  sym_inverse(D, bp.binv + 6 * i);
+  d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * gn[0] + acc[0];
+  d.b[3 * i + 1] = R.amp_node * gn[1] + acc[1];
+  d.b[3 * i + 2] = R.amp_node * gn[2] + acc[2];
+}
+
+// per replica: fresh solve state (x = 0 is written by k_bcg_zero)
+__global__ void k_bcg_reset(DevPtrs d, BlockPtrs bp, double tol) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.nrep) return;
+  BcgRep& B = bp.bcg[r];
+  B.bb = -1.0;
+  B.rz = B.alpha = B.beta = B.rr = 0.0;
+  B.tol2 = tol > 0.0 ? tol * tol : d.rep[r].tol2;
+  B.state = 1;
+  B.it = B.restarts = B.breakdown = 0;
+}
+
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK_THREADS + threadIdx.x;
+  if (i >= d.rows) return;
+  d.x[3 * i] = d.x[3 * i + 1] = d.x[3 * i + 2] = 0.0;
+}
+
+// mode 0: q = A p (into w), partial (p, q)             [iterating replicas]
+// mode 1: r = b - A x, z = M^-1 r, p = z, partials (r, z), (r, r)
+//                                                       [residual round]
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs bp, int mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const BcgRep& B = bp.bcg[d.blk_rep[tile]];
+  if (B.state != (mode == 0 ? 0 : 1)) return;
+  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
+  const double* src = mode == 0 ? d.p : d.x;
+  double si[3] = {src[3 * i], src[3 * i + 1], src[3 * i + 2]};
+  double acc[3];
+  sym_mul(bp.bdiag + 6 * i, si, acc);
+  for (int64_t e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int64_t j = d.col[e];
+    const double sj[3] = {src[3 * j], src[3 * j + 1], src[3 * j + 2]};
+    double t[3];
+    sym_mul(bp.bval + 6 * e, sj, t);
+    acc[0] += t[0];
+    acc[1] += t[1];
+    acc[2] += t[2];
+  }
+  if (mode == 0) {
+    d.w[3 * i] = acc[0];
+    d.w[3 * i + 1] = acc[1];
+    d.w[3 * i + 2] = acc[2];
+    const double pq = (si[0] * acc[0] + si[1] * acc[1]) + si[2] * acc[2];
+    tile_partials(d, tile, pq, 0.0, 0.0);
+  } else {
+    double r[3] = {d.b[3 * i] - acc[0], d.b[3 * i + 1] - acc[1], d.b[3 * i + 2] - acc[2]};
+    double z[3];
+    sym_mul(bp.binv + 6 * i, r, z);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d.r[3 * i + k] = r[k];
+      d.u[3 * i + k] = z[k];
+      d.p[3 * i + k] = z[k];
+    }
+    tile_partials(d, tile, 0.0, (r[0] * z[0] + r[1] * z[1]) + r[2] * z[2],
+                  (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+  }
+}
+
+// x += alpha p, r -= alpha q, z = M^-1 r, partials (r, z), (r, r)
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_update(DevPtrs d, BlockPtrs bp) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const BcgRep& B = bp.bcg[d.blk_rep[tile]];
+  if (B.state != 0) return;
+  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
+  const double a = B.alpha;
+  double r[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t e = 3 * i + k;
+    d.x[e] += a * d.p[e];
+    r[k] = d.r[e] - a * d.w[e];
+    d.r[e] = r[k];
+  }
+  double z[3];
+  sym_mul(bp.binv + 6 * i, r, z);
+  d.u[3 * i] = z[0];
+  d.u[3 * i + 1] = z[1];
+  d.u[3 * i + 2] = z[2];
+  tile_partials(d, tile, 0.0, (r[0] * z[0] + r[1] * z[1]) + r[2] * z[2],
+                (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_dir(DevPtrs d, BlockPtrs bp) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const BcgRep& B = bp.bcg[d.blk_rep[tile]];
+  if (B.state != 0) return;
+  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
+  const double be = B.beta;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.p[3 * i + k] = d.u[3 * i + k] + be * d.p[3 * i + k];
+}
+
+// one block per replica: the tile partials in tile order, then
+//   mode 0 (after q = A p):   alpha = (r, z) / (p, q)
+//   mode 1 (after update):    iteration count, convergence of the recursive
+//                             residual (-> residual round), beta
+//   mode 2 (residual round):  ||b||^2 on the first round; done if the true
+//                             residual meets the tolerance, else (re)start
+__global__ __launch_bounds__(256) void k_bcg_finish(DevPtrs d, BlockPtrs bp, int mode) {
+  const int rid = blockIdx.x;
+  BcgRep& B = bp.bcg[rid];
+  if (B.state != (mode == 2 ? 1 : 0)) return;
+  const RepDev& R = d.rep[rid];
+  __shared__ double lds[4][3];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < R.nblk; t += blockDim.x) {
+    const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
+    acc[0] += src[0];
+    acc[1] += src[1];
+    acc[2] += src[2];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lds[wave][k] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tot[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+  if (mode == 0) {
+    if (!(tot[0] > 0.0)) {
+      B.breakdown = 1;
+      B.state = 2;
+    } else {
+      B.alpha = B.rz / tot[0];
+    }
+  } else if (mode == 1) {
+    B.it += 1;
+    B.rr = tot[2];
+    if (tot[2] <= B.tol2 * B.bb) {
+      B.state = 1;
+    } else {
+      B.beta = tot[1] / B.rz;
+      B.rz = tot[1];
+    }
+  } else {
+    if (B.bb < 0.0) B.bb = tot[2];
+    B.rr = tot[2];
+    if (tot[2] <= B.tol2 * B.bb) {
+      B.state = 2;
+    } else {
+      if (B.it > 0) B.restarts += 1;
+      B.rz = tot[1];
+      B.state = 0;
+    }
+  }
+}
+
+// the block system in original ids: entries (row, col, 9 values row-major),
+// diagonal blocks (9 values per particle) and right-hand sides
+__global__ __launch_bounds__(BLOCK_THREADS) void k_block_export(DevPtrs d, BlockPtrs bp,
+                                                                const int64_t* __restrict__ id_off,
+                                                                int64_t* rows, int64_t* cols,
+                                                                double* vals, double* diag,
+                                                                double* rhs) {
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  const RepDev& R = d.rep[rid];
+  const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + threadIdx.x;
+  if (i - R.row_off >= R.n) return;
+  const int64_t g = id_off[rid] + (int64_t)d.pos[i].w;
+  const int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+  for (int64_t e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    rows[e] = g;
+    cols[e] = id_off[rid] + (int64_t)d.pos[d.col[e]].w;
+    for (int m = 0; m < 9; ++m) vals[9 * e + m] = bp.bval[6 * e + map[m]];
+  }
+  for (int m = 0; m < 9; ++m) diag[9 * g + m] = bp.bdiag[6 * i + map[m]];
+  for (int k = 0; k < 3; ++k) rhs[3 * g + k] = d.b[3 * i + k];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_block, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_reset, dim3((d.nrep + 63) / 64), dim3(64), 0, s, d, bp, tol);
+  hipLaunchKernelGGL(k_bcg_zero, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
+  hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 2);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
+  hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 0);
+  hipLaunchKernelGGL(k_bcg_update, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 1);
+  hipLaunchKernelGGL(k_bcg_dir, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                               int64_t* rows, int64_t* cols, double* vals, double* diag,
+                               double* rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_export, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, bp, id_off, rows,
+                     cols, vals, diag, rhs);
+  return hipGetLastError();
+}

@@ -96,3 +96,34 @@ hipError_t launch_vv_reduce(const DevPtrs& d, const VvRep* vr, const int2* chunk
                             long long* f_hi, unsigned long long* f_cnt,
                             const unsigned long long* umax, const double* u2_part,
                             double* out_sum, long long* out_cnt, double* out_u2, hipStream_t s);
+
+// anisotropic pair friction, block system (block.hip)
+struct BlockRep {       // per replica: W = alpha w (a_perp I + (a_par - a_perp) d d^T / r^2)
+  double a_par, a_perp;
+  double sq_par, sq_perp;  // square roots (the noise amplitude W^(1/2))
+};
+struct BcgRep {         // per-replica scalars of the block CG (3n stacked unknowns)
+  double bb;            // ||b||^2 (negative until the first residual round)
+  double rz;            // (r, z) of the current iterate
+  double alpha, beta;
+  double rr;            // ||r||^2 (recursive while iterating, true after a residual round)
+  double tol2;          // tolerance^2 of this solve
+  int32_t state;        // 0 iterating, 1 residual round pending, 2 done
+  int32_t it;
+  int32_t restarts;
+  int32_t breakdown;
+};
+struct BlockPtrs {
+  double* bval;         // -W_ij per CSR entry: xx, xy, xz, yy, yz, zz
+  double* bdiag;        // gamma0 I + sum_j W_ij per row (6 values)
+  double* binv;         // its inverse (6 values): the block-Jacobi preconditioner
+  BcgRep* bcg;          // [replicas]
+  const BlockRep* brep; // [replicas]
+};
+hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, hipStream_t s);
+hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_block_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                               int64_t* rows, int64_t* cols, double* vals, double* diag,
+                               double* rhs, hipStream_t s);

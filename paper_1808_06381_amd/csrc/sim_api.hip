@@ -107,6 +107,11 @@ struct sim_t {
   // order) and the velocities solved at it; cleared by anything that
   // rebuilds the system or starts a solve
   bool vv_valid = false;
+  // anisotropic friction: the block system and its CG
+  bool block = false;
+  BlockPtrs bp{};
+  BlockRep* brep_d = nullptr;
+  BcgRep* bcg_h = nullptr;   // pinned host copy of the per-replica solve state
   std::vector<int32_t> ic_color_off;  // offsets of the colours in d.ic_cells (host copy)
   sim_tuning tune{};
 };
@@ -174,7 +179,16 @@ static int validate(const sim_params& p) {
   if (p.warm_start != 0 && p.warm_start != 1) return SIM_EINVAL;
   if (p.spmv_fp32 != 0 && p.spmv_fp32 != 1) return SIM_EINVAL;
   if (p.precond == SIM_PC_LEARNED && !(p.alpha > 0.0)) return SIM_EINVAL;
+  if (!(p.friction_par >= 0.0) || !std::isfinite(p.friction_par) || !(p.friction_perp >= 0.0) ||
+      !std::isfinite(p.friction_perp))
+    return SIM_EINVAL;
   return SIM_OK;
+}
+
+// friction along / across the line of centres (0 stands for 1)
+static double fric(double v) { return v == 0.0 ? 1.0 : v; }
+static bool anisotropic(const sim_params& p) {
+  return fric(p.friction_par) != 1.0 || fric(p.friction_perp) != 1.0;
 }
 
 static RepDev make_rep(const sim_params& p) {
@@ -249,6 +263,11 @@ static int alloc_csr(sim_t* s, int64_t cap) {
   if ((rc = dalloc(s, (void**)&s->d.val, sizeof(double) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.valf, sizeof(float) * (size_t)cap))) return rc;
   if ((rc = dalloc(s, (void**)&s->d.er, sizeof(float) * (size_t)cap))) return rc;
+  if (s->block) {
+    dfree(s, s->bp.bval);
+    s->bp.bval = nullptr;
+    if ((rc = dalloc(s, (void**)&s->bp.bval, sizeof(double) * 6 * (size_t)cap))) return rc;
+  }
   if (s->ic0) {
     if ((rc = dalloc(s, (void**)&s->d.lcol, sizeof(int32_t) * (size_t)cap))) return rc;
     if ((rc = dalloc(s, (void**)&s->d.lval, sizeof(double) * (size_t)cap))) return rc;
@@ -348,7 +367,8 @@ static int build_system(sim_t* s) {
   HIPCHK(launch_nbr_count(d, st));
   HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
   HIPCHK(launch_nbr_list(d, st));
-  HIPCHK(launch_pair_terms(d, st));
+  if (s->block) HIPCHK(launch_pair_block(d, s->bp, st));
+  else HIPCHK(launch_pair_terms(d, st));
   return SIM_OK;
 }
 
@@ -368,7 +388,8 @@ static int grow_and_refill(sim_t* s) {
   if (need > s->d.nnz_cap) return SIM_ENOMEM;
   HIPCHK(launch_ctrl_zero(s->d, s->stream));
   HIPCHK(launch_nbr_list(s->d, s->stream));
-  HIPCHK(launch_pair_terms(s->d, s->stream));
+  if (s->block) HIPCHK(launch_pair_block(s->d, s->bp, s->stream));
+  else HIPCHK(launch_pair_terms(s->d, s->stream));
   return SIM_OK;
 }
 
@@ -595,7 +616,62 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
   return SIM_OK;
 }
 
+// the block system's CG (anisotropic friction): residual round, then chunks
+// of iterations each closed by a residual round, the host reading the
+// per-replica states after each chunk
+static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
+  s->vv_valid = false;
+  HIPCHK(hipMemcpyAsync(s->ctrl_h, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (s->ctrl_h->overflow) return SIM_EOVERFLOW_INTERNAL;
+  HIPCHK(launch_bcg_reset(s->d, s->bp, tol, s->stream));
+  HIPCHK(launch_bcg_residual(s->d, s->bp, s->stream));
+  const int maxit = cg_maxit(s);
+  int chunk = std::max(4, std::min(32, s->last_iters > 0 ? s->last_iters : 8));
+  int status = SIM_OK;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(s->bcg_h, s->bp.bcg, sizeof(BcgRep) * (size_t)s->R,
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    bool all_done = true, broke = false;
+    int itmax = 0;
+    for (int r = 0; r < s->R; ++r) {
+      all_done = all_done && s->bcg_h[r].state == 2;
+      broke = broke || s->bcg_h[r].breakdown;
+      itmax = std::max(itmax, (int)s->bcg_h[r].it);
+    }
+    if (broke) { status = SIM_EBREAKDOWN; break; }
+    if (all_done) break;
+    if (itmax >= maxit) { status = SIM_ENOCONV; break; }
+    const int k = std::min(chunk, maxit - itmax);
+    for (int q = 0; q < k; ++q) HIPCHK(launch_bcg_iteration(s->d, s->bp, s->stream));
+    HIPCHK(launch_bcg_residual(s->d, s->bp, s->stream));
+    chunk = 8;
+  }
+  int itmax = 0, restarts = 0;
+  double rel = 0.0;
+  for (int r = 0; r < s->R; ++r) {
+    const BcgRep& B = s->bcg_h[r];
+    itmax = std::max(itmax, (int)B.it);
+    restarts = std::max(restarts, (int)B.restarts);
+    if (B.bb > 0.0) rel = std::max(rel, std::sqrt(B.rr / B.bb));
+  }
+  s->last_iters = itmax;
+  if (st) {
+    for (int k = 0; k < 3; ++k) {
+      st->iters[k] = itmax;
+      st->relres[k] = rel;
+    }
+    st->restarts = restarts;
+    st->nnz = s->ctrl_h->nnz;
+    st->max_row = s->ctrl_h->max_row;
+    st->cg_iters_total += itmax;
+  }
+  return status;
+}
+
 static int cg_solve(sim_t* s, double tol, bool warm, sim_stats* st) {
+  if (s->block) return bcg_solve(s, tol, st);
   int rc = cg_queue_start(s, tol, warm);
   if (rc) return rc;
   const int n = std::max(1, std::min(s->last_iters > 2 ? s->last_iters - 1 : 8, cg_maxit(s) + 1));
@@ -670,6 +746,7 @@ void sim_destroy(sim_t* s) {
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->ctrl_h) (void)hipHostFree(s->ctrl_h);
   if (s->cg_h) (void)hipHostFree(s->cg_h);
+  if (s->bcg_h) (void)hipHostFree(s->bcg_h);
   delete s;
 }
 
@@ -688,6 +765,14 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   s->prm.assign(params, params + replicas);
   s->learned = params[0].precond == SIM_PC_LEARNED;
   s->ic0 = params[0].precond == SIM_PC_IC0;
+  for (int r = 0; r < replicas; ++r) s->block = s->block || anisotropic(params[r]);
+  if (s->block)
+    for (int r = 0; r < replicas; ++r)
+      if (params[r].precond == SIM_PC_LEARNED || params[r].precond == SIM_PC_IC0 ||
+          params[r].spmv_fp32 || params[r].warm_start) {
+        delete s;
+        return SIM_ENOTSUP;
+      }
   for (int r = 1; r < replicas; ++r)
     if ((params[r].precond == SIM_PC_LEARNED) != s->learned ||
         (params[r].precond == SIM_PC_IC0) != s->ic0) {
@@ -825,6 +910,13 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
     ALLOC(d.lnlow, sizeof(int32_t) * rows);
   }
   ALLOC(s->counter_d, sizeof(unsigned long long));
+  if (s->block) {
+    ALLOC(s->brep_d, sizeof(BlockRep) * replicas);
+    ALLOC(s->bp.bcg, sizeof(BcgRep) * replicas);
+    ALLOC(s->bp.bdiag, sizeof(double) * 6 * rows);
+    ALLOC(s->bp.binv, sizeof(double) * 6 * rows);
+    s->bp.brep = s->brep_d;
+  }
   {
     const int64_t m = std::max<int64_t>(s->rows + 1, d.ncell_entries);
     ALLOC(s->bsum, sizeof(int32_t) * (size_t)(scan_bsum_len(m) + 1));
@@ -840,7 +932,8 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   }
   if ((rc = alloc_csr(s, cap)) != SIM_OK) { sim_destroy(s); return rc; }
   if (hipHostMalloc((void**)&s->ctrl_h, sizeof(Ctrl), 0) != hipSuccess ||
-      hipHostMalloc((void**)&s->cg_h, sizeof(CgRep) * replicas, 0) != hipSuccess) {
+      hipHostMalloc((void**)&s->cg_h, sizeof(CgRep) * replicas, 0) != hipSuccess ||
+      (s->block && hipHostMalloc((void**)&s->bcg_h, sizeof(BcgRep) * replicas, 0) != hipSuccess)) {
     sim_destroy(s);
     return SIM_ENOMEM;
   }
@@ -855,6 +948,17 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
     return fail(e, "upload replicas");
   if ((e = hipMemcpy(blk_rep_d, s->blk_rep_h.data(), sizeof(int32_t) * d.nblk, hipMemcpyHostToDevice)))
     return fail(e, "upload block table");
+  if (s->block) {
+    std::vector<BlockRep> br((size_t)replicas);
+    for (int r = 0; r < replicas; ++r) {
+      br[r].a_par = fric(params[r].friction_par);
+      br[r].a_perp = fric(params[r].friction_perp);
+      br[r].sq_par = std::sqrt(br[r].a_par);
+      br[r].sq_perp = std::sqrt(br[r].a_perp);
+    }
+    if ((e = hipMemcpy(s->brep_d, br.data(), sizeof(BlockRep) * replicas, hipMemcpyHostToDevice)))
+      return fail(e, "upload friction tensors");
+  }
   if ((e = hipMemcpy(s->id_off_d, s->id_off_h.data(), sizeof(int64_t) * replicas, hipMemcpyHostToDevice)))
     return fail(e, "upload id offsets");
   if ((e = hipMemcpy(d.pos, ph.data(), sizeof(double4) * rows, hipMemcpyHostToDevice)))
@@ -938,6 +1042,7 @@ int sim_set_tuning(sim_t* s, const sim_tuning* t) {
 
 int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
   if (!s || reps < 1) return SIM_EINVAL;
+  if (s->block) return SIM_ENOTSUP;  // the variants tune the scalar CSR products
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = build_checked(s);
   if (rc) return rc;
@@ -1303,7 +1408,7 @@ int sim_step(sim_t* s, int32_t nsteps, sim_stats* st) {
     // graphs need a solve count to size the first chunk; with the timing
     // probe on, every prof_every-th step runs eagerly so its kernels are timed
     const bool probe_step = s->prof_every > 0 && s->step % s->prof_every == 0;
-    if (s->graph_mode && s->last_iters > 0 && !probe_step) {
+    if (s->graph_mode && s->last_iters > 0 && !probe_step && !s->block) {
       int rc = step_graph(s, st);
       if (rc) return rc;
       continue;
@@ -1377,9 +1482,49 @@ int sim_debug_pairs(sim_t* s, int64_t* ijr, int64_t cap, int64_t* count) {
   return SIM_OK;
 }
 
+int sim_debug_block_system(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
+                           int64_t* count, double* diag, double* rhs) {
+  if (!s || !count || cap < 0) return SIM_EINVAL;
+  if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
+  if (!s->block) return SIM_ENOTSUP;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = build_checked(s);
+  if (rc) return rc;
+  const int64_t nnz = s->ctrl_h->nnz;
+  *count = nnz;
+  if (nnz > cap) return SIM_ECAPACITY;
+  int64_t *r_d = nullptr, *c_d = nullptr;
+  double *v_d = nullptr, *dg_d = nullptr, *b_d = nullptr;
+  const size_t m = (size_t)std::max<int64_t>(nnz, 1);
+  if ((rc = dalloc(s, (void**)&r_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&c_d, sizeof(int64_t) * m))) return rc;
+  if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * 9 * m))) return rc;
+  if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * 9 * (size_t)s->n_total))) return rc;
+  if ((rc = dalloc(s, (void**)&b_d, sizeof(double) * 3 * (size_t)s->n_total))) return rc;
+  HIPCHK(launch_block_export(s->d, s->bp, s->id_off_d, r_d, c_d, v_d, dg_d, b_d, s->stream));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpyAsync(rows, r_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(cols, c_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vals, v_d, sizeof(double) * 9 * nnz, hipMemcpyDeviceToHost, s->stream));
+  }
+  if (diag)
+    HIPCHK(hipMemcpyAsync(diag, dg_d, sizeof(double) * 9 * s->n_total, hipMemcpyDeviceToHost,
+                          s->stream));
+  if (rhs)
+    HIPCHK(hipMemcpyAsync(rhs, b_d, sizeof(double) * 3 * s->n_total, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  dfree(s, r_d);
+  dfree(s, c_d);
+  dfree(s, v_d);
+  dfree(s, dg_d);
+  dfree(s, b_d);
+  return SIM_OK;
+}
+
 int sim_debug_system(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int64_t cap,
                      int64_t* count, double* diag, double* rhs) {
   if (!s || !count || cap < 0) return SIM_EINVAL;
+  if (s->block) return SIM_ENOTSUP;
   if (cap > 0 && (!rows || !cols || !vals)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = build_checked(s);

@@ -25,7 +25,7 @@ PRECOND = {"jacobi": 0, "none": 1, "ic0": 2, "learned": 3}
 
 EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_state",
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
-            "sim_debug_set_gaussians", "sim_profile_enable", "sim_profile_read",
+            "sim_debug_set_gaussians", "sim_debug_block_system", "sim_profile_enable", "sim_profile_read",
             "sim_copy_probe", "sim_event_probe", "sim_structure_factor",
             "sim_velocity_correlation", "sim_precond_weights",
             "sim_precond_config", "sim_train_step",
@@ -73,6 +73,8 @@ class SimParams(C.Structure):
         ("cg_tol", C.c_double),
         ("seed", C.c_uint64),
         ("stream", C.c_uint64),
+        ("friction_par", C.c_double),
+        ("friction_perp", C.c_double),
     ]
 
 
@@ -146,6 +148,7 @@ def lib():
         L.sim_load_precond.argtypes = [vp, C.c_char_p]
         L.sim_debug_pairs.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
         L.sim_debug_system.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp, vp]
+        L.sim_debug_block_system.argtypes = [vp, vp, vp, vp, C.c_int64, P(C.c_int64), vp, vp]
         L.sim_debug_set_gaussians.argtypes = [vp, vp, vp]
         L.sim_profile_enable.argtypes = [vp, C.c_int32]
         L.sim_profile_read.argtypes = [vp, P(SimKernelProf), C.c_int32, P(C.c_int32), C.c_int32]
@@ -195,6 +198,8 @@ def make_params(cfg, tol=None, maxit=None, precond=None, spmv_fp32=None):
     p.precond = PRECOND[precond or cfg.get("precond", "jacobi")]
     p.spmv_fp32 = int(cfg.get("spmv_fp32", 0) if spmv_fp32 is None else spmv_fp32)
     p.warm_start = int(cfg.get("warm_start", 0))
+    p.friction_par = float(cfg.get("friction_par", 1.0))
+    p.friction_perp = float(cfg.get("friction_perp", 1.0))
     p.cg_maxit = int(maxit or cfg.get("cg_maxit", 10000))
     p.cg_tol = float(tol or cfg.get("cg_tol", 1e-10))
     p.seed = int(cfg.get("seed", 0)) & (2**64 - 1)
@@ -339,6 +344,25 @@ class Sim:
         rhs = np.zeros((self.n_total, 3))
         _check(lib().sim_debug_system(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
                                       C.byref(cnt), _ptr(diag), _ptr(rhs)), "sim_debug_system")
+        k = cnt.value
+        return rows[:k], cols[:k], vals[:k], diag, rhs
+
+    def block_system(self):
+        """(rows, cols, vals (m, 3, 3), diag (n, 3, 3), rhs) of the current
+        block system (anisotropic friction), global original ids."""
+        cnt = C.c_int64()
+        rc = lib().sim_debug_block_system(self.h, None, None, None, 0, C.byref(cnt), None, None)
+        if rc not in (SIM_OK, -6):
+            _check(rc, "sim_debug_block_system")
+        m = max(cnt.value, 1)
+        rows = np.zeros(m, dtype=np.int64)
+        cols = np.zeros(m, dtype=np.int64)
+        vals = np.zeros((m, 3, 3))
+        diag = np.zeros((self.n_total, 3, 3))
+        rhs = np.zeros((self.n_total, 3))
+        _check(lib().sim_debug_block_system(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
+                                            C.byref(cnt), _ptr(diag), _ptr(rhs)),
+               "sim_debug_block_system")
         k = cnt.value
         return rows[:k], cols[:k], vals[:k], diag, rhs
 

@@ -31,8 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # sim_params: 1 int64 + 11 doubles + 8 int32 + 1 double + 2 uint64
-    assert C.sizeof(S.SimParams) == 8 + 11 * 8 + 8 * 4 + 8 + 16
+    # sim_params: 1 int64 + 11 doubles + 8 int32 + 1 double + 2 uint64 + 2 doubles
+    assert C.sizeof(S.SimParams) == 8 + 11 * 8 + 8 * 4 + 8 + 16 + 16
     assert C.sizeof(S.SimStats) == 3 * 4 + 4 + 3 * 8 + 8 + 4 + 4 + 8 + 8
     assert C.sizeof(S.SimMeta) == 8 + 8 + 8 + 4 + 4 + 8
     assert C.sizeof(S.SimTuning) == 2 * 4 + 2 * len(S.CSR_VARIANTS) * 4

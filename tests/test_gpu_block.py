@@ -1,0 +1,159 @@
+"""Anisotropic pair friction (3 x 3 blocks) of the library against the oracle.
+
+Tolerances: the block of every pair is formed with the same rounded FP64
+operations on both sides (polynomial weight), so the off-diagonal blocks are
+compared bit for bit; the diagonal blocks and right-hand sides are sums in
+another order (row entries in cell order against pair order), compared at
+1e-13 of the largest entry; velocities of a solve to tolerance tau agree with
+the oracle's (also to tau) within 2 kappa(A) tau, kappa(A) from Gershgorin on
+the oracle's matrix (each step compared from the same positions), and the
+new positions within dt times that velocity error.
+
+Cases: the system at creation and after steps with a large Lees-Edwards
+offset; ten steps, each from the GPU's positions; a scaled isotropic tensor (a_par = a_perp = 2)
+against the scalar path with alpha doubled; a batch with an isotropic and
+two anisotropic replicas; sim_solve against a dense solve; refused options.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_06381_amd import inputs
+from paper_1808_06381_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+
+
+def aniso(cfg, a_par, a_perp):
+    return dict(cfg, friction_par=a_par, friction_perp=a_perp)
+
+
+def le_diff(cfg, step, a, b):
+    delta = oracle.le_offset(cfg, step)
+    return np.array([oracle.separation(cfg, delta, x, y)[0] for x, y in zip(a, b)])
+
+
+def check_system(sim, cfg, a_par, a_perp, off=0, n=None):
+    rows, cols, vals, diag, rhs = sim.block_system()
+    pos, _, meta = sim.state()
+    n = n or cfg["n"]
+    pos = pos[off:off + n]
+    ref = oracle.build_block_system(cfg, pos, a_par, a_perp, step=meta["step"])
+    sel = (rows >= off) & (rows < off + n)
+    rows, cols, vals = rows[sel] - off, cols[sel] - off, vals[sel]
+    o = np.lexsort((cols, rows))
+    rr = np.repeat(np.arange(n), np.diff(ref["rowptr"]))
+    oref = np.lexsort((ref["col"], rr))
+    np.testing.assert_array_equal(rows[o], rr[oref])
+    np.testing.assert_array_equal(cols[o], ref["col"][oref])
+    np.testing.assert_array_equal(vals[o], ref["bval"][oref])
+    scale = np.abs(ref["bdiag"]).max()
+    np.testing.assert_allclose(diag[off:off + n], ref["bdiag"], rtol=0, atol=1e-13 * scale)
+    bs = np.abs(ref["rhs"]).max()
+    np.testing.assert_allclose(rhs[off:off + n], ref["rhs"], rtol=0, atol=1e-11 * bs)
+    return ref
+
+
+@pytest.mark.parametrize("a_par,a_perp", [(3.0, 0.5), (0.25, 2.0)])
+def test_system_matches_oracle(a_par, a_perp):
+    cfg = aniso(inputs.cube_params(1500, 0.4, seed=31), a_par, a_perp)
+    pos0 = inputs.uniform_positions(1500, cfg["box"], 31)
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        check_system(sim, cfg, a_par, a_perp)
+        sim.step(3)
+        check_system(sim, cfg, a_par, a_perp)
+
+
+def kappa_bound(cfg, pos, a_par, a_perp, step):
+    """Gershgorin bound of the condition number of the block system"""
+    sys_ = oracle.build_block_system(cfg, pos, a_par, a_perp, step=step)
+    n = len(sys_["bdiag"])
+    row = np.abs(sys_["bdiag"]).sum(axis=2)
+    owner = np.repeat(np.arange(n), np.diff(sys_["rowptr"]))
+    np.add.at(row, owner, np.abs(sys_["bval"]).sum(axis=2))
+    return row.max() / cfg["gamma0"]
+
+
+def test_steps_match_oracle():
+    """Ten steps; each compared with the oracle's step from the GPU's own
+    positions (both solves to tau = 1e-10: velocities within 2 kappa tau,
+    positions within dt times that)."""
+    case = inputs.small_case(seed=6)
+    cfg = aniso(dict(case["params"], shear_rate=0.5), 2.5, 0.4)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        sim.graph_mode(True)   # block handles step eagerly regardless
+        for k in range(10):
+            pos_k, _, meta = sim.state()
+            assert meta["step"] == k
+            st = sim.step(1)
+            pos_g, vel_g, _ = sim.state()
+            pos_o, vel_o, _ = oracle.step_block(cfg, pos_k, k, 2.5, 0.4, tol=1e-10)
+            kap = kappa_bound(cfg, pos_k, 2.5, 0.4, k)
+            rel = np.linalg.norm(vel_g - vel_o) / np.linalg.norm(vel_o)
+            assert rel < 2 * kap * 1e-10, (k, rel, kap)
+            assert max(st["relres"]) <= 1e-10
+            dx = np.abs(le_diff(cfg, k + 1, pos_g, pos_o)).max()
+            assert dx <= cfg["dt"] * 2 * kap * 1e-10 * np.linalg.norm(vel_o) + 1e-13, k
+
+
+def test_scaled_isotropic_tensor_equals_scalar_path():
+    base = inputs.cube_params(4000, 0.2, seed=33)
+    pos0 = inputs.uniform_positions(4000, base["box"], 33)
+    with S.Sim(aniso(base, 2.0, 2.0), pos0, tol=1e-11) as blk, \
+            S.Sim(dict(base, alpha=2.0 * base["alpha"]), pos0, tol=1e-11) as iso:
+        for _ in range(3):
+            blk.step(1)
+            iso.step(1)
+            _, vb, _ = blk.state()
+            _, vi, _ = iso.state()
+            assert np.linalg.norm(vb - vi) / np.linalg.norm(vi) < 1e-8
+
+
+def test_batch_with_isotropic_replica():
+    cfgs, pos = [], []
+    for r, (n, shear, ap, aq) in enumerate([(2000, 0.3, 1.0, 1.0), (900, 0.8, 4.0, 0.7),
+                                            (2500, 0.05, 0.5, 1.5)]):
+        c = aniso(inputs.cube_params(n, shear, seed=40 + r), ap, aq)
+        c["stream"] = r
+        cfgs.append(c)
+        pos.append(inputs.uniform_positions(n, c["box"], 40 + r))
+    with S.Sim(cfgs, np.concatenate(pos), tol=1e-10) as sim:
+        off = np.cumsum([0] + [c["n"] for c in cfgs])
+        for r, c in enumerate(cfgs):
+            check_system(sim, c, c["friction_par"], c["friction_perp"], off=off[r], n=c["n"])
+        p_before, _, _ = sim.state()
+        sim.step(1)
+        _, vel, _ = sim.state()
+        for r, c in enumerate(cfgs):
+            _, vo, _ = oracle.step_block(c, p_before[off[r]:off[r + 1]], 0, c["friction_par"],
+                                         c["friction_perp"], tol=1e-10)
+            v = vel[off[r]:off[r + 1]]
+            assert np.linalg.norm(v - vo) / np.linalg.norm(vo) < 1e-8, r
+
+
+def test_solve_against_dense():
+    cfg = aniso(inputs.cube_params(300, 0.6, seed=35), 5.0, 0.3)
+    pos0 = inputs.uniform_positions(300, cfg["box"], 35)
+    b = np.random.default_rng(1).normal(size=(300, 3))
+    with S.Sim(cfg, pos0) as sim:
+        v, st = sim.solve(b, tol=1e-12)
+    ref = oracle.build_block_system(cfg, pos0, 5.0, 0.3)
+    A = oracle.block_dense(ref)
+    want = np.linalg.solve(A, b.ravel()).reshape(-1, 3)
+    assert np.linalg.norm(v - want) / np.linalg.norm(want) < 1e-10
+    assert st["iters"][0] > 0
+
+
+def test_refused_options():
+    base = inputs.cube_params(500, 0.1, seed=36)
+    pos0 = inputs.uniform_positions(500, base["box"], 36)
+    for extra in (dict(precond="ic0"), dict(warm_start=1), dict(spmv_fp32=1)):
+        with pytest.raises(S.SimError):
+            S.Sim(aniso(dict(base, **extra), 2.0, 1.0), pos0)
+    with S.Sim(aniso(base, 2.0, 1.0), pos0) as sim:
+        with pytest.raises(S.SimError):
+            sim.system()
+    with S.Sim(base, pos0) as sim:
+        with pytest.raises(S.SimError):
+            sim.block_system()
