@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-spmv", action="store_true")
+    ap.add_argument("--no-aniso", action="store_true",
+                    help="skip the anisotropic-friction (3x3 block) measurement")
     ap.add_argument("--forms", default="plain,learned,ic0",
                     help="comma list of CG forms to time: plain (Jacobi-PCG), learned, ic0")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1808_06381_amd", "weights",
@@ -154,6 +156,33 @@ def measure_vv(sim, n, np, r_max=10.0, nbins=100, reps=3):
     return dict(r_max=r_max, nbins=nbins, particles=n, pairs=pairs,
                 kernel_ms_events=round(float(np.mean(ms)), 4),
                 corr_bins_0_to_2=[round(float(x), 5) for x in norm[:20]])
+
+
+def measure_aniso(args, S, inputs, np, a_par=2.0, a_perp=0.5, warm=3, steps=10):
+    """Anisotropic pair friction (3 x 3 blocks, block-Jacobi CG over the 3n
+    coupled unknowns) on the shear-0.1 box: eager steps, whole-step rate."""
+    cfg = inputs.single_box(shear_rate=0.1, seed=1, n=args.n, L=round(args.n ** (1 / 3), 6))["params"]
+    cfg = dict(cfg, friction_par=a_par, friction_perp=a_perp)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=args.tol) as sim:
+        sim.step(warm)
+        its = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = sim.step(1)
+            its.append(st["iters"][0])
+        dt = time.perf_counter() - t0
+        nnz = st["nnz"]
+        rows = (cfg["n"] + 1023) // 1024 * 1024   # rows padded to whole 1024-row tiles
+    return dict(workload=f"the N={cfg['n']} box at shear 0.1 with pair friction a_par={a_par} "
+                         f"along and a_perp={a_perp} across the line of centres",
+                value=round(cfg["n"] * steps / dt, 1), unit="particle-steps/s",
+                ms_per_step=round(dt / steps * 1e3, 3), steps=steps,
+                mean_cg_iters=round(float(np.mean(its)), 2),
+                # block product per launch: row pointers 8, own vector 24,
+                # diagonal block 48, result 24 B per row; block 48 + column 4 B
+                # per entry (each gathered vector counted once)
+                k_bcg_spmv_bytes_per_launch=104 * rows + 52 * nnz)
 
 
 def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label="",
@@ -428,6 +457,8 @@ def main():
                           ops_per_pair=VV_OPS_PER_PAIR))
     if "learned" in runs and "plain" in runs:
         out["learned_vs_plain"] = round(runs["learned"]["value"] / runs["plain"]["value"], 4)
+    if not args.no_aniso:
+        out["anisotropic"] = measure_aniso(args, S, inputs, np)
     if args.batch > 0:
         bcfgs = inputs.batch_replicas(count=args.batch, seed=7)
         bpos = np.concatenate([inputs.uniform_positions(c["n"], c["box"], c["seed"]) for c in bcfgs])

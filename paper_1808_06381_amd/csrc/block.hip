@@ -186,44 +186,63 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
 // mode 0: q = A p (into w), partial (p, q)             [iterating replicas]
 // mode 1: r = b - A x, z = M^-1 r, p = z, partials (r, z), (r, r)
 //                                                       [residual round]
+// Four lanes per row (a row's entries are contiguous and interleaved over
+// its lanes, so neighbouring lanes read neighbouring blocks); the lanes'
+// sums meet by shuffles within the group, lane k < 3 finishes component k.
+// A 1024-row tile takes four turns of 256 rows.
+constexpr int BLANES = 4;
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs bp, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
   const BcgRep& B = bp.bcg[d.blk_rep[tile]];
   if (B.state != (mode == 0 ? 0 : 1)) return;
-  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
+  const int lane = threadIdx.x & (BLANES - 1);
   const double* src = mode == 0 ? d.p : d.x;
-  double si[3] = {src[3 * i], src[3 * i + 1], src[3 * i + 2]};
-  double acc[3];
-  sym_mul(bp.bdiag + 6 * i, si, acc);
-  for (int64_t e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
-    const int64_t j = d.col[e];
-    const double sj[3] = {src[3 * j], src[3 * j + 1], src[3 * j + 2]};
-    double t[3];
-    sym_mul(bp.bval + 6 * e, sj, t);
-    acc[0] += t[0];
-    acc[1] += t[1];
-    acc[2] += t[2];
-  }
-  if (mode == 0) {
-    d.w[3 * i] = acc[0];
-    d.w[3 * i + 1] = acc[1];
-    d.w[3 * i + 2] = acc[2];
-    const double pq = (si[0] * acc[0] + si[1] * acc[1]) + si[2] * acc[2];
-    tile_partials(d, tile, pq, 0.0, 0.0);
-  } else {
-    double r[3] = {d.b[3 * i] - acc[0], d.b[3 * i + 1] - acc[1], d.b[3 * i + 2] - acc[2]};
-    double z[3];
-    sym_mul(bp.binv + 6 * i, r, z);
+  double v1 = 0.0, v2 = 0.0;  // this lane's dot-product terms
+  for (int turn = 0; turn < BLANES; ++turn) {
+    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + turn * (BLOCK_THREADS / BLANES) +
+                      (threadIdx.x / BLANES);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t e1 = d.rowptr[i + 1];
+    for (int64_t e = d.rowptr[i] + lane; e < e1; e += BLANES) {
+      const int64_t j = d.col[e];
+      const double sj[3] = {src[3 * j], src[3 * j + 1], src[3 * j + 2]};
+      double t[3];
+      sym_mul(bp.bval + 6 * e, sj, t);
+      acc[0] += t[0];
+      acc[1] += t[1];
+      acc[2] += t[2];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      d.r[3 * i + k] = r[k];
-      d.u[3 * i + k] = z[k];
-      d.p[3 * i + k] = z[k];
+      acc[k] += __shfl_xor(acc[k], 1, 64);
+      acc[k] += __shfl_xor(acc[k], 2, 64);
     }
-    tile_partials(d, tile, 0.0, (r[0] * z[0] + r[1] * z[1]) + r[2] * z[2],
-                  (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    const double si[3] = {src[3 * i], src[3 * i + 1], src[3 * i + 2]};
+    double dg[3];
+    sym_mul(bp.bdiag + 6 * i, si, dg);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = dg[k] + acc[k];
+    if (mode == 0) {
+      if (lane < 3) {
+        d.w[3 * i + lane] = acc[lane];
+        v1 += si[lane] * acc[lane];
+      }
+    } else {
+      const double r[3] = {d.b[3 * i] - acc[0], d.b[3 * i + 1] - acc[1], d.b[3 * i + 2] - acc[2]};
+      double z[3];
+      sym_mul(bp.binv + 6 * i, r, z);
+      if (lane < 3) {
+        d.r[3 * i + lane] = r[lane];
+        d.u[3 * i + lane] = z[lane];
+        d.p[3 * i + lane] = z[lane];
+        v1 += r[lane] * z[lane];
+        v2 += r[lane] * r[lane];
+      }
+    }
   }
+  if (mode == 0) tile_partials(d, tile, v1, 0.0, 0.0);
+  else tile_partials(d, tile, 0.0, v1, v2);
 }
 
 // x += alpha p, r -= alpha q, z = M^-1 r, partials (r, z), (r, r)
