@@ -355,7 +355,16 @@ __global__ __launch_bounds__(256) void k_vv_reduce(DevPtrs d, const VvRep* __res
     // halve exactly: the total is even
     lo = (lo >> 1) | ((unsigned long long)hi << 63);
     hi >>= 1;
-    const double val = (double)hi * 18446744073709551616.0 + (double)lo;
+    // to FP64 through the magnitude (a small negative total has hi = -1 and
+    // lo near 2^64: converting those parts separately would cancel)
+    const bool neg = hi < 0;
+    unsigned long long mlo = lo, mhi = (unsigned long long)hi;
+    if (neg) {
+      mlo = ~lo + 1ull;
+      mhi = ~mhi + (mlo == 0ull ? 1ull : 0ull);
+    }
+    const double mag = (double)mhi * 18446744073709551616.0 + (double)mlo;
+    const double val = neg ? -mag : mag;
     const int S = vv_scale_exp(umax[rep], vr[rep].log2p);
     out_sum[o] = ldexp(val, -S);
     out_cnt[o] = (long long)(c >> 1);

@@ -74,6 +74,41 @@ def kappa_bound(cfg, pos, a_par, a_perp, step):
     return row.max() / cfg["gamma0"]
 
 
+def test_gaussian_weight_and_core():
+    """the paper's weight and potential (transcendental ulps differ between
+    the GPU and the CPU, so blocks are compared at 1e-14 relative)"""
+    cfg = inputs.base_params(n=1200, box=(24.5, 17.1, 12.3), shear_rate=0.5, gamma0=1.0,
+                             alpha=4.0, rc=inputs.gauss_cutoff(1.0, 0.05), lam=1.0, u_amp=0.1,
+                             weight_law="gauss", potential="gauss_core", seed=37)
+    cfg = aniso(cfg, 3.0, 0.6)
+    pos0 = inputs.uniform_positions(1200, cfg["box"], 37)
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        sim.step(2)
+        rows, cols, vals, diag, rhs = sim.block_system()
+        pos, _, meta = sim.state()
+        p_k = pos
+        sim.step(1)
+        _, vel, _ = sim.state()
+    ref = oracle.build_block_system(cfg, p_k, 3.0, 0.6, step=meta["step"])
+    o = np.lexsort((cols, rows))
+    rr = np.repeat(np.arange(1200), np.diff(ref["rowptr"]))
+    oref = np.lexsort((ref["col"], rr))
+    np.testing.assert_array_equal(cols[o], ref["col"][oref])
+    np.testing.assert_allclose(vals[o], ref["bval"][oref], rtol=1e-14, atol=1e-300)
+    np.testing.assert_allclose(diag, ref["bdiag"], rtol=0, atol=1e-13 * np.abs(ref["bdiag"]).max())
+    np.testing.assert_allclose(rhs, ref["rhs"], rtol=0, atol=1e-11 * np.abs(ref["rhs"]).max())
+    _, vo, _ = oracle.step_block(cfg, p_k, meta["step"], 3.0, 0.6, tol=1e-10)
+    kap = kappa_bound(cfg, p_k, 3.0, 0.6, meta["step"])
+    assert np.linalg.norm(vel - vo) / np.linalg.norm(vo) < 2 * kap * 1e-10
+
+
+def test_one_particle():
+    cfg = aniso(inputs.base_params(n=1, box=(5.0, 5.0, 5.0), gamma0=0.25), 3.0, 0.5)
+    with S.Sim(cfg, np.array([[1.0, 2.0, 3.0]])) as sim:
+        v, st = sim.solve(np.array([[1.0, -2.0, 0.5]]))
+    np.testing.assert_allclose(v, [[4.0, -8.0, 2.0]], rtol=1e-15)
+
+
 def test_steps_match_oracle():
     """Ten steps; each compared with the oracle's step from the GPU's own
     positions (both solves to tau = 1e-10: velocities within 2 kappa tau,

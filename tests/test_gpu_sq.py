@@ -119,3 +119,18 @@ def test_invalid_arguments():
         for args in [(0, 4, 0), (257, 4, 0), (8, -1, 0), (8, 129, 0), (8, 4, 300)]:
             with pytest.raises(S.SimError):
                 sim.structure_factor(*args)
+
+
+def test_largest_grid():
+    # nx = 256, my_max = 128, |mz| = 256: the limits of the call, sampled outputs
+    cfg = inputs.cube_params(1500, 0.7, seed=9)
+    pos0 = inputs.uniform_positions(1500, cfg["box"], 9)
+    with S.Sim(cfg, pos0) as sim:
+        sim.step(2)
+        pos, _, _ = sim.state()
+        got = sim.structure_factor(256, 128, mz=-256)
+    assert got.shape == (1, 256, 257)
+    rng = np.random.default_rng(3)
+    sample = np.unique(np.concatenate([[0, 256 * 257 - 1, 128, 255 * 257 + 128],
+                                       rng.integers(0, 256 * 257, 200)]))
+    check(cfg, pos, 2, got[0], 256, 128, -256, sample=sample)

@@ -172,3 +172,23 @@ def test_determinism_validity_and_arguments():
         sim.step(1)
         c = sim.velocity_correlation(0.5 * L, 8)
         assert c[1].sum() > 0
+
+
+def test_edge_cases_one_particle_no_pairs_max_bins():
+    # one particle: no pairs, u2 = |u|^2
+    cfg1 = inputs.base_params(n=1, box=(5.0, 5.0, 5.0), shear_rate=0.3, seed=27)
+    with S.Sim(cfg1, np.array([[1.0, 2.0, 3.0]])) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 1, 2.5, 7, True)
+        s, c, u2 = got
+        assert not c.any() and not s.any()
+        u = rel_u(cfg1, pos_n, vel, True)
+        assert u2[0] == pytest.approx(float((u * u).sum()), rel=1e-15)
+    # a cut-off below every separation, and the largest bin count
+    cfg = inputs.cube_params(2500, 0.6, seed=28)
+    pos0 = inputs.uniform_positions(2500, cfg["box"], 28)
+    with S.Sim(cfg, pos0) as sim:
+        pos_n, vel, n, got = run_and_correlate(sim, 2, 1e-6, 3, True)
+        assert not got[1].any()
+        got2 = sim.velocity_correlation(6.0, 1024, flow=True)
+    check(cfg, pos_n, vel, n, got2, 6.0, 1024, True)
+    assert (got2[1][0] == 0).any()   # empty bins near r = 0
