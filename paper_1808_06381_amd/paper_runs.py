@@ -15,6 +15,8 @@ samples, every `every` steps, per replica:
 The summary checks what the paper reports qualitatively:
 * zero shear: the radially averaged S(q) has a minimum near q lambda = 2.3
   (the first shell of neighbours);
+* shear: more neighbours in quadrants 2 and 4 of the flow-gradient plane
+  than in 1 and 3 (the pair correlation skewed backwards);
 * shear: the intensity at small q along the flow (q_x lambda of about 0.1;
   the box allows 0.072 and 0.143) grows with the shear rate, by about 20x
   between zero and the highest shear in the paper;
@@ -67,6 +69,30 @@ def radial(box, s_plane, my_max, dq=0.1, qmax=4.0):
     return mid[good], tot[good] / cnt[good]
 
 
+def quadrant_counts(sim, cfgs):
+    """per replica, the interacting pairs whose separation lies in quadrants
+    2 and 4 of the flow-gradient plane (d_x d_y < 0) and in 1 and 3 (> 0),
+    from the library's pair list and positions (Lees-Edwards nearest image;
+    the pair export rebuilds the system, so it runs after the other samples)"""
+    pos, _, meta = sim.state()
+    pr = sim.pairs()
+    off = np.cumsum([0] + [c["n"] for c in cfgs])
+    out = np.zeros((len(cfgs), 2))
+    for r, c in enumerate(cfgs):
+        sel = pr[pr[:, 0] == r]
+        a = pos[off[r] + sel[:, 1]]
+        b = pos[off[r] + sel[:, 2]]
+        Lx, Ly, Lz = c["box"]
+        delta = math.fmod(c["shear_rate"] * Ly * (meta["step"] * c["dt"]), Lx)
+        dy = a[:, 1] - b[:, 1]
+        sy = (dy > 0.5 * Ly).astype(float) - (dy < -0.5 * Ly).astype(float)
+        dy = dy - sy * Ly
+        dx = a[:, 0] - b[:, 0] - sy * delta
+        dx = dx - Lx * np.round(dx / Lx)
+        out[r] = [(dx * dy < 0).sum(), (dx * dy > 0).sum()]
+    return out
+
+
 def run(steps=20000, discard=10000, every=100, noise="paper", nx=48, my_max=24, r_max=10.9,
         nbins=109, tol=1e-8, seed=11, shears=SHEARS, log=sys.stderr):
     cfgs, pos0 = make_batch(noise, seed, shears)
@@ -76,6 +102,7 @@ def run(steps=20000, discard=10000, every=100, noise="paper", nx=48, my_max=24, 
     vv_s = np.zeros((R, nbins))
     vv_c = np.zeros((R, nbins), dtype=np.int64)
     vv_u2 = np.zeros(R)
+    quad = np.zeros((R, 2))   # neighbour pairs with d_x d_y < 0 (quadrants 2, 4) and > 0
     samples = 0
     t0 = time.perf_counter()
     with S.Sim(cfgs, pos0, tol=tol) as sim:
@@ -91,6 +118,7 @@ def run(steps=20000, discard=10000, every=100, noise="paper", nx=48, my_max=24, 
                 vv_s += s
                 vv_c += c
                 vv_u2 += u2
+                quad += quadrant_counts(sim, cfgs)
                 samples += 1
             if done % (10 * every) == 0 or done == steps:
                 print(f"# {done} steps, {time.perf_counter() - t0:.1f} s", file=log, flush=True)
@@ -131,6 +159,8 @@ def run(steps=20000, discard=10000, every=100, noise="paper", nx=48, my_max=24, 
     wmean = [float(s_mean[r][win3].mean()) for r in range(R)]
     out["small_q_window_mean"] = [round(x, 4) for x in wmean]
     out["small_q_window_growth"] = [round(x / wmean[0], 3) for x in wmean]
+    # neighbours skewed backwards under shear: (N_24 - N_13) / (N_24 + N_13)
+    out["quadrant_asymmetry"] = [round(float((q[0] - q[1]) / max(q.sum(), 1)), 5) for q in quad]
     # velocity correlation, normalised by the mean square relative velocity
     n = cfgs[0]["n"]
     corr = (vv_s / np.maximum(vv_c, 1)) / (vv_u2[:, None] / (n * max(samples, 1)))
