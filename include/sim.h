@@ -315,7 +315,7 @@ int sim_precond_config(sim_t* sim, int32_t round_act, int32_t learned_maxit);
  * components), backward and one Adam step (beta 0.9 / 0.999) with learning
  * rate lr; lr = 0 evaluates the loss and gradient only.  *loss receives L
  * at the weights before the update.  SIM_EINVAL without a solved system;
- * SIM_ENOTSUP for batches.                                               */
+ * SIM_ENOTSUP for batches and for handles with anisotropic friction.      */
 int sim_train_step(sim_t* sim, double lr, double* loss);
 /* One training step on a white-noise probe of the current system (any
  * number of replicas; needs a successful solve): x* = z with z_ik ~ N(0, 1)

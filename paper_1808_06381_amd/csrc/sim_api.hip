@@ -1149,7 +1149,7 @@ int sim_load_precond(sim_t* s, const char* path) {
 
 int sim_train_step(sim_t* s, double lr, double* loss) {
   if (!s || !(lr >= 0.0)) return SIM_EINVAL;
-  if (s->R != 1) return SIM_ENOTSUP;
+  if (s->R != 1 || s->block) return SIM_ENOTSUP;  // the network reads the scalar system
   if (!s->system_valid) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, true);
@@ -1169,6 +1169,7 @@ int sim_train_step(sim_t* s, double lr, double* loss) {
 int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t euclid,
                     double* loss) {
   if (!s || !(lr >= 0.0) || (euclid != 0 && euclid != 1)) return SIM_EINVAL;
+  if (s->block) return SIM_ENOTSUP;  // the network reads the scalar system
   if (!s->system_valid) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, true);

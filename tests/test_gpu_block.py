@@ -189,6 +189,9 @@ def test_refused_options():
     with S.Sim(aniso(base, 2.0, 1.0), pos0) as sim:
         with pytest.raises(S.SimError):
             sim.system()
+        sim.step(1)
+        with pytest.raises(S.SimError):
+            sim.train_step(1e-3)   # the network reads the scalar system
     with S.Sim(base, pos0) as sim:
         with pytest.raises(S.SimError):
             sim.block_system()
