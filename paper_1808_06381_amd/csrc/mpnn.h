@@ -58,7 +58,9 @@ struct MpPtrs {
   float* dh;       // [rows][H]
   float* dh2;      // [rows][H]
   float* dm;       // [rows][H]
-  uint16_t* hb;    // [rows][H] bfloat16 of the final h (the heads round it anyway)
+  uint16_t* hb;    // [rows][H] bfloat16 of h^l for l = NL, NL-2, ... (the heads and
+                   // the layers round h to bf16 before every product anyway)
+  uint16_t* hb2;   // [rows][H] bfloat16 of h^l for l = NL-1, NL-3, ...
   uint16_t* efh;   // [nnz][4] bfloat16 edge features and a zero (likewise)
   int64_t rows;
   int round_act;   // 1: round activations entering products to bf16

@@ -230,9 +230,13 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
 // forward with bf16 activations on the matrix cores.  A block owns MP_ROWS
 // consecutive rows; their CSR entries form one contiguous range that is
 // walked in chunks of MX_EC entries, four threads per entry (eight features
-// each), so every thread keeps one 32-byte gather in flight per chunk.  The
-// dense node products (32 x 64 and 32 x 32 per node) run as 16 x 16 x 16
-// bf16 MFMA tiles, FP32 accumulate: wave w owns rows 16w..16w+15.
+// each).  Every product consumes h rounded to bf16, so each layer gathers the
+// 64-byte bf16 row of h_j per entry (one 16-byte load per thread) and forms
+// y_j = P h_j of the chunk on the matrix cores, rather than gathering a stored
+// FP32 y_j (twice the bytes); the product is the one that writes y for the
+// backward pass, operand for operand, so both give the same bits.  The dense
+// node products (32 x 64 and 32 x 32 per node) run as 16 x 16 x 16 bf16 MFMA
+// tiles, FP32 accumulate: wave w owns rows 16w..16w+15 of a tile.
 // Operand layout of v_mfma_f32_16x16x16_bf16: lane l supplies
 // A[l%16][4(l/16)+i] and B[4(l/16)+i][l%16], i < 4, and receives
 // D[4(l/16)+r][l%16] in accumulator register r.
@@ -270,19 +274,44 @@ __device__ __forceinline__ f32x4 mx_mma(s16x4 a, s16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// y = P h for the 16 rows of wave w: P at w16[off], h the bf16 tile xh;
-// stored as FP32 rows of dst (tile origin i0)
-__device__ __forceinline__ void mx_store_py(const uint16_t* __restrict__ w16, int off,
-                                            const uint16_t* xh, float* __restrict__ dst,
-                                            int64_t i0) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+// B operands of P (at w16[off]) for mx_py
+__device__ __forceinline__ void mx_load_p(const uint16_t* __restrict__ w16, int off,
+                                          s16x4 (&pw)[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) pw[s][nt] = mx_bw(w16, off, s, nt);
+}
+
+// y = P h for the 16 rows of wave w: P as loaded by mx_load_p, h the bf16
+// tile xh (row stride `stride`).  Lane l holds y[16w + 4(l/16) + r][16nt + l%16]
+// in acc[nt][r].
+__device__ __forceinline__ void mx_py(const s16x4 (&pw)[2][2], const uint16_t* xh, int stride,
+                                      f32x4 (&acc)[2]) {
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const s16x4 a = mx_a(xh, MX_HS, s);
+    const s16x4 a = mx_a(xh, stride, s);
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) acc[nt] = mx_mma(a, mx_bw(w16, off, s, nt), acc[nt]);
+    for (int nt = 0; nt < 2; ++nt) acc[nt] = mx_mma(a, pw[s][nt], acc[nt]);
   }
+}
+
+// bf16 copy of h^l: layer l gathers it, layer l - 1 (or the encoder) writes it
+__device__ __forceinline__ uint16_t* mx_hb(const MpPtrs& m, int l) {
+  return ((l ^ MP_NL) & 1) ? m.hb2 : m.hb;
+}
+
+// y = P h as FP32 rows of dst (tile origin i0), kept for the backward pass
+__device__ __forceinline__ void mx_store_py(const uint16_t* __restrict__ w16, int off,
+                                            const uint16_t* xh, int stride,
+                                            float* __restrict__ dst, int64_t i0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  s16x4 pw[2][2];
+  mx_load_p(w16, off, pw);
+  f32x4 acc[2];
+  mx_py(pw, xh, stride, acc);
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
@@ -294,7 +323,8 @@ __device__ __forceinline__ void mx_store_py(const uint16_t* __restrict__ w16, in
 
 }  // namespace
 
-// features, h0 = relu(W0 x + b0) and y^0 = P_0 h0; four lanes per row
+// features and h0 = relu(W0 x + b0) (FP32 and bf16; y^0 = P_0 h0 when
+// training); four lanes per row
 __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float w0[MP_H * MP_FN], b0[MP_H];
@@ -356,11 +386,17 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
   hp[0] = make_float4(hv[0], hv[1], hv[2], hv[3]);
   hp[1] = make_float4(hv[4], hv[5], hv[6], hv[7]);
   __syncthreads();
-  mx_store_py(m.w16, MP_OFF_L0 + MP_L_P, xh, m.y, i0);
+  *reinterpret_cast<uint4*>(mx_hb(m, 0) + i * MP_H + 8 * q) =
+      *reinterpret_cast<const uint4*>(xh + n * MX_HS + 8 * q);
+  if (m.store_train) mx_store_py(m.w16, MP_OFF_L0 + MP_L_P, xh, MX_HS, m.y, i0);
 }
 
-// one message-passing layer l (bf16 activations): m, a (training), h^{l+1}, y^{l+1}
-__global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
+// one message-passing layer l (bf16 activations): m, a and y^{l+1} (training),
+// h^{l+1} in FP32 and bf16
+// (six waves per SIMD: the gather is latency-bound; the register budget of
+// six still holds the kernel without spills)
+__global__ __launch_bounds__(MP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float Q[MP_H * MP_FE], c[MP_H], dd[MP_H];
   __shared__ int rp[MP_ROWS + 1];
@@ -368,8 +404,14 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
   __shared__ __align__(16) float msg[MX_EC * MX_FS];
   static_assert(MX_EC == MP_ROWS, "the h tile reuses the message buffer");
   float* const hs = msg;
+  // xa holds, in turn: one chunk's bf16 h_j (stride MX_HS) and bf16 edge
+  // features during the gather; the tile's [bf16 h | bf16 m] (stride MX_AS);
+  // bf16 h^{l+1} in the h half, each wave overwriting only its own 16 rows
+  // once its products have read them
   __shared__ __align__(16) uint16_t xa[MP_ROWS * MX_AS];
-  __shared__ __align__(16) uint16_t xh[MP_ROWS * MX_HS];
+  static_assert(MX_EC * (MX_HS + 4) <= MP_ROWS * MX_AS, "gather tile exceeds xa");
+  uint16_t* const xg = xa;
+  uint16_t* const es = xa + MX_EC * MX_HS;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int base = MP_OFF_L0 + l * MP_L_SIZE;
   load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
@@ -380,28 +422,55 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
   __syncthreads();
   const int n = t >> 2, q = t & 3;
   const int64_t rows = m.rows;
-  const float* __restrict__ y = m.y + (int64_t)l * rows * MP_H;
+  const uint16_t* __restrict__ hbl = mx_hb(m, l);
   // messages: relu(y_j + Q e_ij + c) of every entry, summed per row in entry order
   float acc[8];
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0f;
+  s16x4 pw[2][2];
+  mx_load_p(m.w16, base + MP_L_P, pw);
   const int E0 = rp[0], E1 = rp[MP_ROWS];
+  // software pipeline: while a chunk is processed, the gather of the next one
+  // is in flight and the column indices of the one after are being read
+  // (bf16 h_j and edge features are zero past the range)
+  uint4 hq = make_uint4(0u, 0u, 0u, 0u);
+  ushort4 eq = make_ushort4(0, 0, 0, 0);
+  if (E0 + n < E1) {
+    hq = *reinterpret_cast<const uint4*>(hbl + (int64_t)d.col[E0 + n] * MP_H + 8 * q);
+    if (q == 0) eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)(E0 + n));
+  }
+  int jn = E0 + MX_EC + n < E1 ? d.col[E0 + MX_EC + n] : 0;
   for (int cb = E0; cb < E1; cb += MX_EC) {
-    const int e = cb + n;
-    if (e < E1) {
-      const int64_t j = d.col[e];
-      const float4* yp = reinterpret_cast<const float4*>(y + j * MP_H + 8 * q);
-      const float4 y0 = yp[0], y1 = yp[1];
-      const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-      const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
-      const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
+    *reinterpret_cast<uint4*>(xg + n * MX_HS + 8 * q) = hq;
+    if (q == 0) *reinterpret_cast<ushort4*>(es + 4 * n) = eq;
+    __syncthreads();
+    {
+      const int e = cb + MX_EC + n;   // entry n of the next chunk (column jn)
+      hq = make_uint4(0u, 0u, 0u, 0u);
+      eq = make_ushort4(0, 0, 0, 0);
+      if (e < E1) {
+        hq = *reinterpret_cast<const uint4*>(hbl + (int64_t)jn * MP_H + 8 * q);
+        if (q == 0) eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
+      }
+      jn = e + MX_EC < E1 ? d.col[e + MX_EC] : 0;
+    }
+    // y_j = P h_j on the matrix cores, then the message of each entry
+    {
+      f32x4 yv[2];
+      mx_py(pw, xg, MX_HS, yv);
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = 8 * q + kk;
-        float s = yv[kk] + c[k];
+      for (int r = 0; r < 4; ++r) {
+        const int en = 16 * w + 4 * (lane >> 4) + r;
+        const ushort4 eq = *reinterpret_cast<const ushort4*>(es + 4 * en);
+        const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
 #pragma unroll
-        for (int f = 0; f < MP_FE; ++f) s += Q[k * MP_FE + f] * ef[f];
-        msg[n * MX_FS + k] = s > 0.0f ? s : 0.0f;
+        for (int nt = 0; nt < 2; ++nt) {
+          const int k = 16 * nt + (lane & 15);
+          float s = yv[nt][r] + c[k];
+#pragma unroll
+          for (int f = 0; f < MP_FE; ++f) s += Q[k * MP_FE + f] * ef[f];
+          msg[en * MX_FS + k] = s > 0.0f ? s : 0.0f;
+        }
       }
     }
     __syncthreads();
@@ -412,8 +481,10 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
       acc[0] += m0.x; acc[1] += m0.y; acc[2] += m0.z; acc[3] += m0.w;
       acc[4] += m1.x; acc[5] += m1.y; acc[6] += m1.z; acc[7] += m1.w;
     }
-    __syncthreads();
+    // no barrier here: xg and es were last read before the one above, and
+    // msg is next written after the next chunk's first barrier
   }
+  __syncthreads();   // every row has summed its messages: msg and xa are restaged
   // stage [bf16(h) | bf16(m)] and the FP32 residual h of the tile
   {
     const int64_t i = i0 + n;
@@ -461,22 +532,28 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_mx(DevPtrs d, MpPtrs m,
       // the final h feeds the heads, which round it to bf16; its FP32 copy
       // is for the backward pass only
       if (l + 1 < MP_NL || m.store_train) hout[(i0 + row) * MP_H + k] = hn;
-      if (l + 1 == MP_NL) m.hb[(i0 + row) * MP_H + k] = hnb;
       if (m.store_train) m.a[((int64_t)l * rows + i0 + row) * MP_H + k] = a;
-      xh[row * MX_HS + k] = hnb;
+      xa[row * MX_AS + k] = hnb;
     }
-  if (l + 1 < MP_NL) {
-    __syncthreads();
-    mx_store_py(m.w16, base + MP_L_SIZE + MP_L_P, xh, m.y + (int64_t)(l + 1) * rows * MP_H, i0);
-  }
+  __syncthreads();
+  // bf16 h^{l+1}: gathered by the next layer, read by the heads after the last
+  *reinterpret_cast<uint4*>(mx_hb(m, l + 1) + (i0 + n) * MP_H + 8 * q) =
+      *reinterpret_cast<const uint4*>(xa + n * MX_AS + 8 * q);
+  if (l + 1 < MP_NL && m.store_train)
+    mx_store_py(m.w16, base + MP_L_SIZE + MP_L_P, xa, MX_AS,
+                m.y + (int64_t)(l + 1) * rows * MP_H, i0);
 }
 
-// heads (bf16 activations): M^-1 values, four lanes per CSR entry
+// heads (bf16 activations): M^-1 values, four lanes per CSR entry.  After
+// one barrier (weights, row pointers, the tile's h) every quad walks its
+// entries on its own: the owning row comes from a binary search of the
+// tile's row pointers, and the next entry's column index is read one entry
+// ahead.
 __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
-  __shared__ int erow[MX_EC];
+  __shared__ double dg[MP_ROWS];
   __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
   const int t = threadIdx.x;
   load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
@@ -484,6 +561,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
   load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
   const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
   if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
+  if (t < MP_ROWS) dg[t] = d.diag[i0 + t];
   const int n = t >> 2, q = t & 3;
   // the final h in bf16 (the heads use it rounded): 8 features per thread
   auto hb8 = [&](int64_t row, float (&v)[8]) {
@@ -502,39 +580,40 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = v[kk];
   }
   __syncthreads();
-  const int E0 = rp[0], E1 = rp[MP_ROWS];
-  for (int cb = E0; cb < E1; cb += MX_EC) {
-    if (t < MP_ROWS) {
-      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + MX_EC);
-      for (int e2 = lo; e2 < hi; ++e2) erow[e2 - cb] = t;
-    }
-    __syncthreads();
-    const int e = cb + n;
-    if (e < E1) {
-      const int r = erow[n];
-      const int64_t j = d.col[e];
-      float hj[8];
-      hb8(j, hj);
-      float p = 0.0f;
+  // no barrier below: the four lanes of a quad share every entry, so the
+  // quad's shuffles see only active lanes
+  const int E1 = rp[MP_ROWS];
+  int e = rp[0] + n;
+  int jn = e < E1 ? d.col[e] : 0;
+  for (; e < E1; e += MX_EC) {
+    const int64_t j = jn;
+    jn = e + MX_EC < E1 ? d.col[e + MX_EC] : 0;
+    float hj[8];
+    hb8(j, hj);
+    const double dj = d.diag[j];
+    const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
+    static_assert((MP_ROWS & (MP_ROWS - 1)) == 0, "the row search halves a power of two");
+    int r = 0;   // the last row whose range starts at or before e
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = 8 * q + kk;
-        p += hz[k] * (hi_s[r * MX_FS + k] * hj[kk]);
-      }
-      p += __shfl_xor(p, 1, 64);
-      p += __shfl_xor(p, 2, 64);
-      float tt = p;
-      const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
-      const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
+    for (int half = MP_ROWS / 2; half > 0; half >>= 1)
+      if (rp[r + half] <= e) r += half;
+    float p = 0.0f;
 #pragma unroll
-      for (int f = 0; f < MP_FE; ++f) tt += hze[f] * ef[f];
-      tt += hze[MP_FE];
-      if (q == 0) {
-        m.moff[e] = (float)((double)tt / sqrt(d.diag[i0 + r] * d.diag[j]));
-        if (m.store_train) m.tg[e] = tt;
-      }
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 8 * q + kk;
+      p += hz[k] * (hi_s[r * MX_FS + k] * hj[kk]);
     }
-    __syncthreads();  // erow is rewritten for the next chunk
+    p += __shfl_xor(p, 1, 64);
+    p += __shfl_xor(p, 2, 64);
+    float tt = p;
+    const float ef[MP_FE] = {bf16_value(eq.x), bf16_value(eq.y), bf16_value(eq.z)};
+#pragma unroll
+    for (int f = 0; f < MP_FE; ++f) tt += hze[f] * ef[f];
+    tt += hze[MP_FE];
+    if (q == 0) {
+      m.moff[e] = (float)((double)tt / sqrt(dg[r] * dj));
+      if (m.store_train) m.tg[e] = tt;
+    }
   }
   float p = 0.0f;
 #pragma unroll

@@ -296,6 +296,7 @@ static int ensure_mp(sim_t* s, bool training) {
     MPALLOC(m.h, sizeof(float) * (MP_NL + 1) * rows * H);
     MPALLOC(m.y, sizeof(float) * MP_NL * rows * H);
     MPALLOC(m.hb, sizeof(uint16_t) * rows * H);
+    MPALLOC(m.hb2, sizeof(uint16_t) * rows * H);
     MPALLOC(m.tau, sizeof(float) * rows);
     MPALLOC(m.mdiag, sizeof(double) * rows);
     MPALLOC(m.lpart, sizeof(double) * 2 * (rows / 256 + 1));
