@@ -171,7 +171,10 @@ __global__ void k_cell_sort(DevPtrs d) {
 // ===========================================================================
 // a2-a5: neighbour search, pair terms, assembly of A and b
 // ===========================================================================
-__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d) {
+// Neighbour count.  The first NBR_SLOTS accepted candidates of each row are
+// also kept, slot-major (slots[k * rows + i]), so that the list pass copies
+// them instead of searching the stencil again.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d, int32_t* __restrict__ slots) {
   const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
   if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
@@ -187,7 +190,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d) {
         const double4 pj = d.pos[j];
         double dx, dy, dz;
         le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
-        if (dist2(dx, dy, dz) < R.rc2) ++cnt;
+        if (dist2(dx, dy, dz) < R.rc2) {
+          if (cnt < NBR_SLOTS) slots[(int64_t)cnt * d.rows + i] = j;
+          ++cnt;
+        }
       });
     }
     d.rowlen[i] = cnt;
@@ -212,9 +218,11 @@ __device__ __forceinline__ double force_coef(const RepDev& R, double r2, double 
   return 0.0;
 }
 
-// Neighbour list: the same candidate order as k_nbr_count; each passing
-// candidate's sorted row index goes to col[rowptr[i] + slot].
-__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
+// Neighbour list: each passing candidate's sorted row index goes to
+// col[rowptr[i] + k], in k_nbr_count's candidate order: copied from the
+// count pass's slots, or searched again for a row longer than NBR_SLOTS.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d,
+                                                            const int32_t* __restrict__ slots) {
   const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
   if (blk >= d.nblk) return;
   const RepDev& R = d.rep[d.blk_rep[blk]];
@@ -229,6 +237,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
       continue;
     }
     int64_t e = d.rowptr[i];
+    if (e1 - e <= NBR_SLOTS) {
+      for (int k = 0; e < e1; ++k, ++e) d.col[e] = slots[(int64_t)k * d.rows + i];
+      continue;
+    }
     const double4 pi = d.pos[i];
     for_candidates(R, d.cell_row, delta, pi.x, pi.y, pi.z, i, [&](int j) {
       const double4 pj = d.pos[j];
@@ -243,43 +255,41 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d) {
 // Pair terms and assembly: -alpha*w_ij into val, diag = gamma0 + alpha*sum w,
 // 1/diag, and the three right-hand sides: Couette drive (Eq. 6c),
 // conservative force (Eq. 6b), boundary velocity term of Eq. 8, thermal
-// force.  A block owns a tile of 1024 rows and walks the tile's CSR entries
-// (contiguous) in chunks of PAIR_THREADS, one entry per lane, so every lane
-// has an entry to work on whatever the row lengths; each entry leaves its
-// five row contributions (w, w s, and the three force components with the
-// pair noise) in LDS, and each thread then adds those of its four rows in
-// entry order.  The node noise and the assembly run once per row.
+// force.  A block owns a tile of PAIR_THREADS rows (a quarter of a row
+// block, so that the grid holds enough waves to hide the gathers) and walks
+// the tile's CSR entries (contiguous) in chunks of PAIR_THREADS, one entry
+// per lane, so every lane has an entry to work on whatever the row lengths;
+// each entry leaves its five row contributions (w, w s, and the three force
+// components with the pair noise) in LDS, and each thread then adds those of
+// its row in entry order.  The node noise and the assembly run once per row.
 #define PAIR_THREADS 256
-#define PAIR_ROWS_PER_THREAD (ROWS_PER_BLOCK / PAIR_THREADS)
+#define PAIR_TILES (ROWS_PER_BLOCK / PAIR_THREADS)   // tiles per row block
 __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);  // neighbour rows in this XCD's L2
-  if (blk >= d.nblk) return;
+  const int tile = xcd_block(blockIdx.x, PAIR_TILES * d.nblk);  // rows in this XCD's L2
+  if (tile >= PAIR_TILES * d.nblk) return;
+  const int blk = tile / PAIR_TILES;
   const RepDev& R = d.rep[d.blk_rep[blk]];
   if (d.ctrl->overflow) return;
-  __shared__ int rp[ROWS_PER_BLOCK + 1];      // row pointers of the tile
+  __shared__ int rp[PAIR_THREADS + 1];        // row pointers of the tile
   __shared__ int16_t erow[PAIR_THREADS];      // tile row of each entry of the chunk
   __shared__ double contrib[5][PAIR_THREADS]; // w, w s, fx, fy, fz of each entry
   const int t = threadIdx.x;
-  const int64_t row0 = (int64_t)blk * ROWS_PER_BLOCK;
-  for (int r = t; r <= ROWS_PER_BLOCK; r += PAIR_THREADS) rp[r] = d.rowptr[row0 + r];
+  const int64_t row0 = (int64_t)blk * ROWS_PER_BLOCK + (tile % PAIR_TILES) * PAIR_THREADS;
+  for (int r = t; r <= PAIR_THREADS; r += PAIR_THREADS) rp[r] = d.rowptr[row0 + r];
   __syncthreads();
   const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
   const bool noise = R.amp_pair != 0.0 && R.alpha != 0.0;
-  // this thread's rows: t, t + 256, t + 512, t + 768 (tile-local)
-  double acc[PAIR_ROWS_PER_THREAD][5];
+  // this thread's row: t (tile-local)
+  double acc[5];
 #pragma unroll
-  for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) acc[q][k] = 0.0;
-  const int E0 = rp[0], E1 = rp[ROWS_PER_BLOCK];
+  for (int k = 0; k < 5; ++k) acc[k] = 0.0;
+  const int E0 = rp[0], E1 = rp[PAIR_THREADS];
   for (int cb = E0; cb < E1; cb += PAIR_THREADS) {
     // the tile row of each entry of this chunk
-#pragma unroll
-    for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
-      const int r = t + q * PAIR_THREADS;
-      const int lo = max(rp[r], cb), hi = min(rp[r + 1], cb + PAIR_THREADS);
-      for (int e = lo; e < hi; ++e) erow[e - cb] = (int16_t)r;
+    {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + PAIR_THREADS);
+      for (int e = lo; e < hi; ++e) erow[e - cb] = (int16_t)t;
     }
     __syncthreads();
     const int e = cb + t;
@@ -320,25 +330,22 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
       contrib[4][t] = fz;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
-      const int r = t + q * PAIR_THREADS;
-      const int lo = max(rp[r], cb), hi = min(rp[r + 1], cb + PAIR_THREADS);
+    {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + PAIR_THREADS);
       for (int e2 = lo; e2 < hi; ++e2)
 #pragma unroll
-        for (int k = 0; k < 5; ++k) acc[q][k] += contrib[k][e2 - cb];
+        for (int k = 0; k < 5; ++k) acc[k] += contrib[k][e2 - cb];
     }
     __syncthreads();  // erow and contrib are rewritten for the next chunk
   }
   const double drag_unit = R.alpha * (R.shear * R.L[1]);
-#pragma unroll
-  for (int q = 0; q < PAIR_ROWS_PER_THREAD; ++q) {
-    const int64_t i = row0 + t + q * PAIR_THREADS;
+  {
+    const int64_t i = row0 + t;
     if (i - R.row_off >= R.n) {  // padding row: identity, no right-hand side
       d.diag[i] = 1.0;
       d.dinv[i] = 1.0;
       d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
-      continue;
+      return;
     }
     const double4 pi = d.pos[i];
     const int64_t idi = (int64_t)pi.w;
@@ -350,13 +357,13 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
         gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, g);
       }
     }
-    const double dg = R.gamma0 + R.alpha * acc[q][0];
+    const double dg = R.gamma0 + R.alpha * acc[0];
     d.diag[i] = dg;
     d.dinv[i] = 1.0 / dg;
-    d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * g[0] + acc[q][2] +
-                 drag_unit * acc[q][1];
-    d.b[3 * i + 1] = R.amp_node * g[1] + acc[q][3];
-    d.b[3 * i + 2] = R.amp_node * g[2] + acc[q][4];
+    d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * g[0] + acc[2] +
+                 drag_unit * acc[1];
+    d.b[3 * i + 1] = R.amp_node * g[1] + acc[3];
+    d.b[3 * i + 2] = R.amp_node * g[2] + acc[4];
   }
 }
 
@@ -554,16 +561,17 @@ hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_sort, dim3(nb_of(d.ncell_entries, 256)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
-hipError_t launch_nbr_count(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_count, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
+hipError_t launch_nbr_count(const DevPtrs& d, int32_t* slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_count, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, slots);
   return hipGetLastError();
 }
-hipError_t launch_nbr_list(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_nbr_list, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d);
+hipError_t launch_nbr_list(const DevPtrs& d, const int32_t* slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_nbr_list, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, slots);
   return hipGetLastError();
 }
 hipError_t launch_pair_terms(const DevPtrs& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_terms, dim3(xcd_grid(d.nblk)), dim3(PAIR_THREADS), 0, s, d);
+  hipLaunchKernelGGL(k_pair_terms, dim3(xcd_grid(PAIR_TILES * d.nblk)), dim3(PAIR_THREADS), 0, s,
+                     d);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s) {

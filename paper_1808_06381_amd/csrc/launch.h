@@ -11,8 +11,11 @@ hipError_t launch_cell_rows(const DevPtrs& d, const int32_t* scan, hipStream_t s
 hipError_t launch_scatter(const DevPtrs& d, hipStream_t s);
 hipError_t launch_cell_sort(const DevPtrs& d, hipStream_t s);
 hipError_t launch_ctrl_zero(const DevPtrs& d, hipStream_t s);
-hipError_t launch_nbr_count(const DevPtrs& d, hipStream_t s);
-hipError_t launch_nbr_list(const DevPtrs& d, hipStream_t s);
+// the count pass keeps the first NBR_SLOTS neighbours of every row in
+// slots[NBR_SLOTS][rows] (slot-major) for the list pass
+#define NBR_SLOTS 16
+hipError_t launch_nbr_count(const DevPtrs& d, int32_t* slots, hipStream_t s);
+hipError_t launch_nbr_list(const DevPtrs& d, const int32_t* slots, hipStream_t s);
 hipError_t launch_pair_terms(const DevPtrs& d, hipStream_t s);
 hipError_t launch_update(const DevPtrs& d, int cond, hipStream_t s);
 hipError_t launch_save_vel(const DevPtrs& d, const int64_t* id_off, int cond, hipStream_t s);

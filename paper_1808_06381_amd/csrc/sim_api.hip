@@ -55,6 +55,7 @@ struct sim_t {
   DevPtrs d{};
   RepDev* rep_d = nullptr;
   int32_t* scan_tmp = nullptr;
+  int32_t* nbr_slots = nullptr;  // [NBR_SLOTS][rows] neighbours kept by the count pass
   int32_t* bsum = nullptr;
   int64_t* id_off_d = nullptr;
   double* io = nullptr;  // n_total x 3 staging for the boundary
@@ -365,9 +366,9 @@ static int build_system(sim_t* s) {
   std::swap(d.pos, d.pos_alt);
   std::swap(d.cellidx, d.cellidx_alt);
   HIPCHK(launch_cell_sort(d, st));
-  HIPCHK(launch_nbr_count(d, st));
+  HIPCHK(launch_nbr_count(d, s->nbr_slots, st));
   HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
-  HIPCHK(launch_nbr_list(d, st));
+  HIPCHK(launch_nbr_list(d, s->nbr_slots, st));
   if (s->block) HIPCHK(launch_pair_block(d, s->bp, st));
   else HIPCHK(launch_pair_terms(d, st));
   return SIM_OK;
@@ -388,7 +389,7 @@ static int grow_and_refill(sim_t* s) {
   if (rc) return rc;
   if (need > s->d.nnz_cap) return SIM_ENOMEM;
   HIPCHK(launch_ctrl_zero(s->d, s->stream));
-  HIPCHK(launch_nbr_list(s->d, s->stream));
+  HIPCHK(launch_nbr_list(s->d, s->nbr_slots, s->stream));
   if (s->block) HIPCHK(launch_pair_block(s->d, s->bp, s->stream));
   else HIPCHK(launch_pair_terms(s->d, s->stream));
   return SIM_OK;
@@ -866,6 +867,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   ALLOC(d.cell_count, sizeof(int32_t) * d.ncell_entries);
   ALLOC(d.cell_row, sizeof(int32_t) * d.ncell_entries);
   ALLOC(s->scan_tmp, sizeof(int32_t) * d.ncell_entries);
+  ALLOC(s->nbr_slots, sizeof(int32_t) * NBR_SLOTS * rows);
   ALLOC(d.rowlen, sizeof(int32_t) * (rows + 1));
   ALLOC(d.rowptr, sizeof(int32_t) * (rows + 1));
   ALLOC(d.diag, sizeof(double) * rows);
