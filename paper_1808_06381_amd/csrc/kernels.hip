@@ -199,11 +199,19 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_count(DevPtrs d, int32_t*
     d.rowlen[i] = cnt;
     mx = cnt > mx ? cnt : mx;
   }
+  // longest row: one atomic per block (atomics on one address serialise
+  // across the chip)
+  __shared__ int wmax[BLOCK_THREADS / 64];
   for (int o = 32; o > 0; o >>= 1) {
     const int t = __shfl_xor(mx, o, 64);
     mx = t > mx ? t : mx;
   }
-  if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(&d.ctrl->max_row, mx);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BLOCK_THREADS / 64; ++w) mx = wmax[w] > mx ? wmax[w] : mx;
+    if (mx > 0) atomicMax(&d.ctrl->max_row, mx);
+  }
 }
 
 __device__ __forceinline__ double pair_weight(const RepDev& R, double r2, double r) {

@@ -122,8 +122,16 @@ __global__ __launch_bounds__(VV_THREADS) void k_vv_bin(DevPtrs d, const VvRep* _
   }
   block_sum(acc, lds);
   if (threadIdx.x == 0) u2_part[blk] = acc[0];
+  // largest |u|^2: one atomic per block (atomics on one address serialise
+  // across the chip)
+  __shared__ double wmax[VV_THREADS / 64];
   for (int o = 32; o > 0; o >>= 1) um = fmax(um, __shfl_xor(um, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(&umax[rid], (unsigned long long)__double_as_longlong(um));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = um;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < VV_THREADS / 64; ++w) um = fmax(um, wmax[w]);
+    atomicMax(&umax[rid], (unsigned long long)__double_as_longlong(um));
+  }
 }
 
 // copy of every real row into coarse-cell order: position and velocity
