@@ -48,6 +48,10 @@ CASES = {
                                           potential="gauss_core", seed=3),
     "thin_axes": inputs.base_params(n=200, box=(2.6, 9.0, 2.2), shear_rate=0.8, seed=5),
     "thin_y": inputs.base_params(n=300, box=(9.0, 2.1, 9.0), shear_rate=0.4, seed=6),
+    # density 5: about 21 neighbours per row, so most rows are longer than
+    # the 16 columns the count pass keeps and are searched again by the list
+    # pass, and the rest are copied
+    "dense_rows": inputs.base_params(n=2000, box=(7.4, 7.4, 7.3), shear_rate=0.6, seed=12),
 }
 
 
@@ -61,7 +65,7 @@ def test_pairs_bit_exact_at_creation(name):
     assert got.shape == ref.shape and np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("name", ["cube3000", "gauss_paperlike", "thin_y"])
+@pytest.mark.parametrize("name", ["cube3000", "gauss_paperlike", "thin_y", "dense_rows"])
 def test_pairs_bit_exact_with_le_offset(name):
     """Advect with a large dt (no friction, no noise) so the offset is large."""
     cfg = dict(CASES[name], noise="off", alpha=0.0, potential="none", dt=0.2)
@@ -88,7 +92,21 @@ def test_pairs_on_cell_and_box_boundaries():
     assert np.array_equal(got, oracle_pairs(cfg, pos, 0))
 
 
-@pytest.mark.parametrize("name", ["cube3000", "gauss_paperlike", "thin_axes"])
+def test_dense_rows_longest_row():
+    """Rows above and below the 16 columns the count pass keeps: the longest
+    row reported by the step matches the oracle's degree count (the entries
+    themselves are compared by the pair and system tests of this case)."""
+    cfg = CASES["dense_rows"]
+    pos = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    ref = oracle_pairs(cfg, pos, 0)
+    deg = np.bincount(ref.ravel(), minlength=cfg["n"])
+    assert (deg > 16).mean() > 0.5 and (deg <= 16).sum() > 20   # both paths in use
+    with S.Sim(cfg, pos, tol=1e-10) as sim:
+        st = sim.step(1)
+    assert st["max_row"] == deg.max()
+
+
+@pytest.mark.parametrize("name", ["cube3000", "gauss_paperlike", "thin_axes", "dense_rows"])
 def test_system_matches_oracle(name):
     cfg = CASES[name]
     n = cfg["n"]
