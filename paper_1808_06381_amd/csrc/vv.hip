@@ -23,7 +23,11 @@
 // cells farther than r_max from the home cell are skipped), stages each run
 // of cells through LDS and lets every home particle test every staged
 // candidate (lanes of a small cell split into groups that take every G-th
-// candidate).  Ordered pairs are counted from both ends.
+// candidate).  Each unordered pair is counted once, by the home particle
+// with the lower coarse-order index: the separation, r^2 and u_i . u_j come
+// out with the same bits from either end, so the other end would add the
+// same integer; staged runs that lie wholly before the home chunk are
+// skipped.
 //
 // Determinism.  Each product u_i . u_j is rounded to a fixed-point integer
 // with a per-replica power-of-two scale 2^S (S from the largest |u|^2 and a
@@ -32,9 +36,8 @@
 // reduce kernel adds the blocks' integers exactly in 128 bits.  Integer
 // sums do not depend on the order of the additions, so neither the cell
 // order inside a coarse cell nor the scheduling changes a bit of the
-// result.  Each unordered pair is counted twice with the same integer, so
-// halving is exact; the error against the exact pair sum is at most
-// 2^-(S+1) per pair plus the final conversion to FP64.
+// result.  The error against the exact pair sum is at most 2^-(S+1) per
+// pair plus the final conversion to FP64.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -260,7 +263,9 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
         const int kx = u0 < 0 ? -1 : (u0 >= ncx ? 1 : 0);  // x image of the segment
         const int run = (a + len <= ncx) ? len : (ncx - a);
         const int j0 = cstart[rowbase + a], j1 = cstart[rowbase + a + run];
-        for (int c0 = j0; c0 < j1; c0 += VV_STAGE) {
+        // candidates before the home chunk are skipped: their pairs are
+        // counted from the other end
+        for (int c0 = max(j0, B.start); c0 < j1; c0 += VV_STAGE) {
           const int m = min(VV_STAGE, j1 - c0);
           for (int q = t; q < m; q += VV_HOME) {
             cp[q] = spos[c0 + q];
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
               if (kz < 0) dzz = __dadd_rn(dzz, R.L[2]);
               else if (kz > 0) dzz = __dsub_rn(dzz, R.L[2]);
               const double r2 = dist2(dx, dyy, dzz);
-              if (r2 < rmax2 && (int64_t)(c0 + jj) != self)
+              if (r2 < rmax2 && (int64_t)(c0 + jj) > self)
                 vv_accept(r2, hu, cu[jj], cscale, scale, nb, hs, hc);
             }
           } else if (home) {
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
               double dx, dyy, dzz;
               le_sep(R, delta, hp.x, hp.y, hp.z, q.x, q.y, q.z, dx, dyy, dzz);
               const double r2 = dist2(dx, dyy, dzz);
-              if (r2 < rmax2 && (int64_t)(c0 + jj) != self)
+              if (r2 < rmax2 && (int64_t)(c0 + jj) > self)
                 vv_accept(r2, hu, cu[jj], cscale, scale, nb, hs, hc);
             }
           }
@@ -360,9 +365,6 @@ __global__ __launch_bounds__(256) void k_vv_reduce(DevPtrs d, const VvRep* __res
       add128(lo, hi, f_lo[q], f_hi[q]);
       c += f_cnt[q];
     }
-    // halve exactly: the total is even
-    lo = (lo >> 1) | ((unsigned long long)hi << 63);
-    hi >>= 1;
     // to FP64 through the magnitude (a small negative total has hi = -1 and
     // lo near 2^64: converting those parts separately would cancel)
     const bool neg = hi < 0;
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void k_vv_reduce(DevPtrs d, const VvRep* __res
     const double val = neg ? -mag : mag;
     const int S = vv_scale_exp(umax[rep], vr[rep].log2p);
     out_sum[o] = ldexp(val, -S);
-    out_cnt[o] = (long long)(c >> 1);
+    out_cnt[o] = (long long)c;
   }
   if (o < nrep) {
     const RepDev& R = d.rep[o];
