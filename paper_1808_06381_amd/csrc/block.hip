@@ -14,14 +14,19 @@
 // entry the six values of -W_ij (xx, xy, xz, yy, yz, zz), per row the six
 // values of the diagonal block and of its inverse (block-Jacobi).
 //
-// Solve: preconditioned CG with one recurrence over the 3n stacked
-// unknowns of each replica (the three components are coupled), stopping on
-// the true residual ||b - A x|| <= tol ||b||.  Per iteration: q = A p with
-// tile partials of (p, q); a per-replica finisher (alpha); x, r, z = M^-1 r
-// with partials of (r, z), (r, r); the finisher (convergence, beta);
-// p = z + beta p.  Residual rounds (start, and after the recursive residual
-// meets the tolerance): r = b - A x, z = M^-1 r, p = z.  All reductions in a
-// fixed order: deterministic.
+// Solve: block-Jacobi preconditioned CG with one recurrence over the 3n
+// stacked unknowns of each replica (the three components are coupled), in
+// the single-reduction form of Chronopoulos & Gear (as the scalar solve),
+// stopping on the true residual ||b - A x|| <= tol ||b||.  Per iteration
+// three launches: w = A u with tile partials of (w, u); a per-replica
+// finisher that reduces (w, u), (r, u) and (r, r) together (convergence of
+// the recursive residual, then beta = gamma / gamma_old and
+// alpha = gamma / (delta - beta gamma / alpha_old)); and the vector pass
+// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r with
+// partials of (r, u), (r, r).  Residual rounds (start, and after the
+// recursive residual meets the tolerance): r = b - A x, u = M^-1 r,
+// p = s = 0 (so the next pass starts with p = u, s = w).  All reductions in
+// a fixed order: deterministic.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -59,16 +64,16 @@ __device__ __forceinline__ double pforce(const RepDev& R, double r2, double r) {
 }
 
 // the tile's partial slots 0..2 from every thread's values (fixed order)
-__device__ __forceinline__ void tile_partials(const DevPtrs& d, int tile, double v0, double v1,
-                                              double v2) {
-  __shared__ double lds[BLOCK_THREADS / 64][3];
-  double v[3] = {v0, v1, v2};
-  block_sum<3>(v, lds);
+// tile partial sums [(w, u), (r, u), (r, r)]: slots first .. first + N - 1
+template <int N>
+__device__ __forceinline__ void tile_partials(const DevPtrs& d, int tile, int first,
+                                              double (&v)[N]) {
+  __shared__ double lds[BLOCK_THREADS / 64][N];
+  block_sum<N>(v, lds);
   if (threadIdx.x == 0) {
-    double* dst = d.partial + (int64_t)tile * NPART;
-    dst[0] = v[0];
-    dst[1] = v[1];
-    dst[2] = v[2];
+    double* dst = d.partial + (int64_t)tile * NPART + first;
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[k] = v[k];
   }
 }
 
@@ -175,6 +180,7 @@ __global__ void k_bcg_reset(DevPtrs d, BlockPtrs bp, double tol) {
   B.tol2 = tol > 0.0 ? tol * tol : d.rep[r].tol2;
   B.state = 1;
   B.it = B.restarts = B.breakdown = 0;
+  B.first = 1;
 }
 
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
@@ -183,9 +189,9 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
   d.x[3 * i] = d.x[3 * i + 1] = d.x[3 * i + 2] = 0.0;
 }
 
-// mode 0: q = A p (into w), partial (p, q)             [iterating replicas]
-// mode 1: r = b - A x, z = M^-1 r, p = z, partials (r, z), (r, r)
-//                                                       [residual round]
+// mode 0: w = A u, partial (w, u)                        [iterating replicas]
+// mode 1: r = b - A x, u = M^-1 r, p = s = 0, partials (r, u), (r, r)
+//                                                          [residual round]
 // Four lanes per row (a row's entries are contiguous and interleaved over
 // its lanes, so neighbouring lanes read neighbouring blocks); the lanes'
 // sums meet by shuffles within the group, lane k < 3 finishes component k.
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs
   const BcgRep& B = bp.bcg[d.blk_rep[tile]];
   if (B.state != (mode == 0 ? 0 : 1)) return;
   const int lane = threadIdx.x & (BLANES - 1);
-  const double* src = mode == 0 ? d.p : d.x;
+  const double* src = mode == 0 ? d.u : d.x;
   double v1 = 0.0, v2 = 0.0;  // this lane's dot-product terms
   for (int turn = 0; turn < BLANES; ++turn) {
     const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + turn * (BLOCK_THREADS / BLANES) +
@@ -235,57 +241,71 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs
       if (lane < 3) {
         d.r[3 * i + lane] = r[lane];
         d.u[3 * i + lane] = z[lane];
-        d.p[3 * i + lane] = z[lane];
+        d.p[3 * i + lane] = 0.0;
+        d.s[3 * i + lane] = 0.0;
         v1 += r[lane] * z[lane];
         v2 += r[lane] * r[lane];
       }
     }
   }
-  if (mode == 0) tile_partials(d, tile, v1, 0.0, 0.0);
-  else tile_partials(d, tile, 0.0, v1, v2);
+  if (mode == 0) {
+    double v[1] = {v1};
+    tile_partials<1>(d, tile, 0, v);
+  } else {
+    double v[2] = {v1, v2};
+    tile_partials<2>(d, tile, 1, v);
+  }
 }
 
-// x += alpha p, r -= alpha q, z = M^-1 r, partials (r, z), (r, r)
-__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_update(DevPtrs d, BlockPtrs bp) {
+// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r,
+// partials (r, u), (r, r).  The vector updates run element-parallel over
+// the tile's 3 * 1024 consecutive doubles (coalesced); the new r goes
+// through LDS to one thread per row for the 3 x 3 block product, and u
+// back through LDS to coalesced stores.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_vec(DevPtrs d, BlockPtrs bp) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
   const BcgRep& B = bp.bcg[d.blk_rep[tile]];
   if (B.state != 0) return;
-  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
-  const double a = B.alpha;
-  double r[3];
+  __shared__ double rs[3 * ROWS_PER_BLOCK];
+  static_assert(ROWS_PER_BLOCK == BLOCK_THREADS, "one row per thread in the block product");
+  const double a = B.alpha, be = B.beta;
+  const int64_t base = (int64_t)tile * 3 * ROWS_PER_BLOCK;
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int64_t e = 3 * i + k;
-    d.x[e] += a * d.p[e];
-    r[k] = d.r[e] - a * d.w[e];
-    d.r[e] = r[k];
+  for (int q = 0; q < 3; ++q) {
+    const int le = q * BLOCK_THREADS + t;
+    const int64_t e = base + le;
+    const double pk = d.u[e] + be * d.p[e];
+    const double sk = d.w[e] + be * d.s[e];
+    d.p[e] = pk;
+    d.s[e] = sk;
+    d.x[e] += a * pk;
+    const double rk = d.r[e] - a * sk;
+    d.r[e] = rk;
+    rs[le] = rk;
   }
+  __syncthreads();
+  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + t;
+  const double r[3] = {rs[3 * t], rs[3 * t + 1], rs[3 * t + 2]};
   double z[3];
   sym_mul(bp.binv + 6 * i, r, z);
-  d.u[3 * i] = z[0];
-  d.u[3 * i + 1] = z[1];
-  d.u[3 * i + 2] = z[2];
-  tile_partials(d, tile, 0.0, (r[0] * z[0] + r[1] * z[1]) + r[2] * z[2],
-                (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_dir(DevPtrs d, BlockPtrs bp) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const BcgRep& B = bp.bcg[d.blk_rep[tile]];
-  if (B.state != 0) return;
-  const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + threadIdx.x;
-  const double be = B.beta;
+  double v[2] = {(r[0] * z[0] + r[1] * z[1]) + r[2] * z[2], (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]};
+  __syncthreads();  // every row has read its r: rs now takes u
+  rs[3 * t] = z[0];
+  rs[3 * t + 1] = z[1];
+  rs[3 * t + 2] = z[2];
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 3; ++k) d.p[3 * i + k] = d.u[3 * i + k] + be * d.p[3 * i + k];
+  for (int q = 0; q < 3; ++q) d.u[base + q * BLOCK_THREADS + t] = rs[q * BLOCK_THREADS + t];
+  tile_partials<2>(d, tile, 1, v);
 }
 
-// one block per replica: the tile partials in tile order, then
-//   mode 0 (after q = A p):   alpha = (r, z) / (p, q)
-//   mode 1 (after update):    iteration count, convergence of the recursive
-//                             residual (-> residual round), beta
+// one block per replica: the tile partials [(w, u), (r, u), (r, r)] in tile
+// order, then
+//   mode 0 (after w = A u):   convergence of the recursive residual (-> a
+//                             residual round), else beta and alpha of the
+//                             next vector pass
 //   mode 2 (residual round):  ||b||^2 on the first round; done if the true
 //                             residual meets the tolerance, else (re)start
 __global__ __launch_bounds__(256) void k_bcg_finish(DevPtrs d, BlockPtrs bp, int mode) {
@@ -313,22 +333,28 @@ __global__ __launch_bounds__(256) void k_bcg_finish(DevPtrs d, BlockPtrs bp, int
   double tot[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) tot[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+  const double delta = tot[0], gamma = tot[1];
   if (mode == 0) {
-    if (!(tot[0] > 0.0)) {
-      B.breakdown = 1;
-      B.state = 2;
-    } else {
-      B.alpha = B.rz / tot[0];
-    }
-  } else if (mode == 1) {
-    B.it += 1;
     B.rr = tot[2];
     if (tot[2] <= B.tol2 * B.bb) {
       B.state = 1;
-    } else {
-      B.beta = tot[1] / B.rz;
-      B.rz = tot[1];
+      return;
     }
+    double beta = 0.0, den = delta;
+    if (!B.first) {
+      beta = gamma / B.rz;
+      den = delta - beta * gamma / B.alpha;
+    }
+    if (!(den > 0.0) || !(gamma > 0.0)) {
+      B.breakdown = 1;
+      B.state = 2;
+      return;
+    }
+    B.beta = beta;
+    B.alpha = gamma / den;
+    B.rz = gamma;
+    B.first = 0;
+    B.it += 1;
   } else {
     if (B.bb < 0.0) B.bb = tot[2];
     B.rr = tot[2];
@@ -336,7 +362,7 @@ __global__ __launch_bounds__(256) void k_bcg_finish(DevPtrs d, BlockPtrs bp, int
       B.state = 2;
     } else {
       if (B.it > 0) B.restarts += 1;
-      B.rz = tot[1];
+      B.first = 1;
       B.state = 0;
     }
   }
@@ -388,9 +414,7 @@ hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_
 hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
   hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
   hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 0);
-  hipLaunchKernelGGL(k_bcg_update, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
-  hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 1);
-  hipLaunchKernelGGL(k_bcg_dir, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  hipLaunchKernelGGL(k_bcg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
   return hipGetLastError();
 }
 

@@ -107,7 +107,7 @@ struct BlockRep {       // per replica: W = alpha w (a_perp I + (a_par - a_perp)
 };
 struct BcgRep {         // per-replica scalars of the block CG (3n stacked unknowns)
   double bb;            // ||b||^2 (negative until the first residual round)
-  double rz;            // (r, z) of the current iterate
+  double rz;            // gamma = (r, u) of the last vector pass (or residual round)
   double alpha, beta;
   double rr;            // ||r||^2 (recursive while iterating, true after a residual round)
   double tol2;          // tolerance^2 of this solve
@@ -115,6 +115,8 @@ struct BcgRep {         // per-replica scalars of the block CG (3n stacked unkno
   int32_t it;
   int32_t restarts;
   int32_t breakdown;
+  int32_t first;        // 1: the next vector pass starts the recurrences (beta = 0)
+  int32_t pad0;
 };
 struct BlockPtrs {
   double* bval;         // -W_ij per CSR entry: xx, xy, xz, yy, yz, zz
