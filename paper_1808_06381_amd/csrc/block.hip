@@ -79,83 +79,124 @@ __device__ __forceinline__ void tile_partials(const DevPtrs& d, int tile, int fi
 
 }  // namespace
 
-// Pair terms and assembly of the block system, one thread per row (its CSR
-// entries in order).  Every entry's block and right-hand-side contribution
-// is formed from the separation d_ij of the row's particle; the mirror
-// entry gets the same block and the negated contribution, bit for bit.
-__global__ __launch_bounds__(BLOCK_THREADS) void k_pair_block(DevPtrs d, BlockPtrs bp) {
-  const int blk = xcd_block(blockIdx.x, d.nblk);
-  if (blk >= d.nblk) return;
+// Pair terms and assembly of the block system.  A block owns a tile of
+// PB_THREADS rows and walks the tile's contiguous CSR entries in chunks of
+// PB_THREADS, one entry per lane: every entry's block is formed from the
+// separation d_ij of the row's particle (the mirror entry gets the same
+// block and the negated contribution, bit for bit) and written out, and its
+// twelve row contributions (the block, the force and drag term, the noise
+// term) go to LDS; each thread then adds its row's in entry order, with the
+// same operations a walk of the row would make, and assembles the row.
+constexpr int PB_THREADS = 256;
+constexpr int PB_TILES = ROWS_PER_BLOCK / PB_THREADS;  // tiles per row block
+__global__ __launch_bounds__(PB_THREADS) void k_pair_block(DevPtrs d, BlockPtrs bp) {
+  const int tile = xcd_block(blockIdx.x, PB_TILES * d.nblk);  // rows in this XCD's L2
+  if (tile >= PB_TILES * d.nblk) return;
   if (d.ctrl->overflow) return;
+  const int blk = tile / PB_TILES;
   const int rid = d.blk_rep[blk];
   const RepDev& R = d.rep[rid];
   const BlockRep& Q = bp.brep[rid];
-  const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + threadIdx.x;
-  if (i - R.row_off >= R.n) {  // padding row: identity, no right-hand side
-    double* D = bp.bdiag + 6 * i;
-    double* I = bp.binv + 6 * i;
-    D[0] = D[3] = D[5] = I[0] = I[3] = I[5] = 1.0;
-    D[1] = D[2] = D[4] = I[1] = I[2] = I[4] = 0.0;
-    d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
-    return;
-  }
+  __shared__ int rp[PB_THREADS + 1];
+  __shared__ int16_t erow[PB_THREADS];
+  __shared__ double contrib[12][PB_THREADS];  // W (6), force and drag (3), noise (3)
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blk * ROWS_PER_BLOCK + (tile % PB_TILES) * PB_THREADS;
+  for (int r = t; r <= PB_THREADS; r += PB_THREADS) rp[r] = d.rowptr[row0 + r];
+  __syncthreads();
   const int64_t step = *d.step_d;
   const double delta = le_offset(R, step);
   const bool noise = R.amp_pair != 0.0 && R.alpha != 0.0;
   const double c = Q.a_par - Q.a_perp, cs = Q.sq_par - Q.sq_perp;
   const double vunit = R.shear * R.L[1];
-  const double4 pi = d.pos[i];
-  const int64_t idi = (int64_t)pi.w;
   double D[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
-    const int j = d.col[e];
-    const double4 pj = d.pos[j];
-    double dv[3];
-    const int s = le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dv[0], dv[1], dv[2]);
-    const double r2 = dist2(dv[0], dv[1], dv[2]);
-    const double r = sqrt(r2);
-    const double g = R.alpha * pweight(R, r2, r);
-    double P[6];
-    P[0] = r2 > 0.0 ? (dv[0] * dv[0]) / r2 : 0.0;
-    P[1] = r2 > 0.0 ? (dv[0] * dv[1]) / r2 : 0.0;
-    P[2] = r2 > 0.0 ? (dv[0] * dv[2]) / r2 : 0.0;
-    P[3] = r2 > 0.0 ? (dv[1] * dv[1]) / r2 : 0.0;
-    P[4] = r2 > 0.0 ? (dv[1] * dv[2]) / r2 : 0.0;
-    P[5] = r2 > 0.0 ? (dv[2] * dv[2]) / r2 : 0.0;
-    double W[6];
-    W[0] = g * (Q.a_perp + c * P[0]);
-    W[1] = g * (c * P[1]);
-    W[2] = g * (c * P[2]);
-    W[3] = g * (Q.a_perp + c * P[3]);
-    W[4] = g * (c * P[4]);
-    W[5] = g * (Q.a_perp + c * P[5]);
-    double* out = bp.bval + 6 * e;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      out[m] = -W[m];
-      D[m] += W[m];
+  const int E0 = rp[0], E1 = rp[PB_THREADS];
+  for (int cb = E0; cb < E1; cb += PB_THREADS) {
+    {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + PB_THREADS);
+      for (int e = lo; e < hi; ++e) erow[e - cb] = (int16_t)t;
     }
-    // conservative force and boundary drag W V, V = kappa Ly s x (column 0)
-    const double fc = pforce(R, r2, r);
-    const double v = vunit * (double)s;
-    acc[0] += fc * dv[0] + W[0] * v;
-    acc[1] += fc * dv[1] + W[1] * v;
-    acc[2] += fc * dv[2] + W[2] * v;
-    if (noise) {
-      const int64_t idj = (int64_t)pj.w;
-      const int64_t a = idi < idj ? idi : idj, bb = idi < idj ? idj : idi;
-      double gz[3];
-      gauss3(R.seed, R.stream, (uint64_t)step, 1, (uint64_t)a, (uint64_t)bb, gz);
-      const double amp = (idi < idj ? 1.0 : -1.0) * (R.amp_pair * sqrt(g));
-      const double t = (dv[0] * gz[0] + dv[1] * gz[1]) + dv[2] * gz[2];
+    __syncthreads();
+    const int e = cb + t;
+    if (e < E1) {
+      const int64_t i = row0 + erow[t];
+      const double4 pi = d.pos[i];
+      const int j = d.col[e];
+      const double4 pj = d.pos[j];
+      double dv[3];
+      const int s = le_sep(R, delta, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dv[0], dv[1], dv[2]);
+      const double r2 = dist2(dv[0], dv[1], dv[2]);
+      const double r = sqrt(r2);
+      const double g = R.alpha * pweight(R, r2, r);
+      double P[6];
+      P[0] = r2 > 0.0 ? (dv[0] * dv[0]) / r2 : 0.0;
+      P[1] = r2 > 0.0 ? (dv[0] * dv[1]) / r2 : 0.0;
+      P[2] = r2 > 0.0 ? (dv[0] * dv[2]) / r2 : 0.0;
+      P[3] = r2 > 0.0 ? (dv[1] * dv[1]) / r2 : 0.0;
+      P[4] = r2 > 0.0 ? (dv[1] * dv[2]) / r2 : 0.0;
+      P[5] = r2 > 0.0 ? (dv[2] * dv[2]) / r2 : 0.0;
+      double W[6];
+      W[0] = g * (Q.a_perp + c * P[0]);
+      W[1] = g * (c * P[1]);
+      W[2] = g * (c * P[2]);
+      W[3] = g * (Q.a_perp + c * P[3]);
+      W[4] = g * (c * P[4]);
+      W[5] = g * (Q.a_perp + c * P[5]);
+      double* out = bp.bval + 6 * (int64_t)e;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double q = r2 > 0.0 ? (dv[k] * t) / r2 : 0.0;
-        acc[k] += amp * (Q.sq_perp * gz[k] + cs * q);
+      for (int m = 0; m < 6; ++m) {
+        out[m] = -W[m];
+        contrib[m][t] = W[m];
+      }
+      // conservative force and boundary drag W V, V = kappa Ly s x (column 0)
+      const double fc = pforce(R, r2, r);
+      const double v = vunit * (double)s;
+      contrib[6][t] = fc * dv[0] + W[0] * v;
+      contrib[7][t] = fc * dv[1] + W[1] * v;
+      contrib[8][t] = fc * dv[2] + W[2] * v;
+      if (noise) {
+        const int64_t idi = (int64_t)pi.w, idj = (int64_t)pj.w;
+        const int64_t a = idi < idj ? idi : idj, bb = idi < idj ? idj : idi;
+        double gz[3];
+        gauss3(R.seed, R.stream, (uint64_t)step, 1, (uint64_t)a, (uint64_t)bb, gz);
+        const double amp = (idi < idj ? 1.0 : -1.0) * (R.amp_pair * sqrt(g));
+        const double tt = (dv[0] * gz[0] + dv[1] * gz[1]) + dv[2] * gz[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double q = r2 > 0.0 ? (dv[k] * tt) / r2 : 0.0;
+          contrib[9 + k][t] = amp * (Q.sq_perp * gz[k] + cs * q);
+        }
       }
     }
+    __syncthreads();
+    {
+      const int lo = max(rp[t], cb), hi = min(rp[t + 1], cb + PB_THREADS);
+      for (int e2 = lo; e2 < hi; ++e2) {
+        const int q = e2 - cb;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) D[m] += contrib[m][q];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += contrib[6 + k][q];
+        if (noise) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc[k] += contrib[9 + k][q];
+        }
+      }
+    }
+    __syncthreads();  // erow and contrib are rewritten for the next chunk
   }
+  const int64_t i = row0 + t;
+  if (i - R.row_off >= R.n) {  // padding row: identity, no right-hand side
+    double* Dp = bp.bdiag + 6 * i;
+    double* Ip = bp.binv + 6 * i;
+    Dp[0] = Dp[3] = Dp[5] = Ip[0] = Ip[3] = Ip[5] = 1.0;
+    Dp[1] = Dp[2] = Dp[4] = Ip[1] = Ip[2] = Ip[4] = 0.0;
+    d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
+    return;
+  }
+  const double4 pi = d.pos[i];
+  const int64_t idi = (int64_t)pi.w;
   double gn[3] = {0.0, 0.0, 0.0};
   if (R.amp_node != 0.0) gauss3(R.seed, R.stream, (uint64_t)step, 0, (uint64_t)idi, 0, gn);
   D[0] += R.gamma0;
@@ -395,7 +436,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_block_export(DevPtrs d, Block
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_block, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  hipLaunchKernelGGL(k_pair_block, dim3(xcd_grid(PB_TILES * d.nblk)), dim3(PB_THREADS), 0, s, d,
+                     bp);
   return hipGetLastError();
 }
 
