@@ -157,6 +157,29 @@ __global__ void k_cell_sort(DevPtrs d) {
   const int ncell = R.nc[0] * R.nc[1] * R.nc[2];
   if (e - R.seg_off >= ncell) return;  // terminal entry of the segment
   const int a = d.cell_row[e], b = d.cell_row[e + 1];
+  const int n = b - a;
+  if (n <= 1) return;
+  if (n <= 8) {
+    // in registers: Batcher's odd-even merge network on 8 (19 compare-
+    // exchanges, checked against every permutation), absent slots keyed +inf
+    constexpr int NET[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                                {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                                {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+    double4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k < n ? d.pos[a + k] : make_double4(0.0, 0.0, 0.0, INFINITY);
+#pragma unroll
+    for (int c = 0; c < 19; ++c) {
+      const double4 lo = v[NET[c][0]], hi = v[NET[c][1]];
+      const bool sw = lo.w > hi.w;
+      v[NET[c][0]] = sw ? hi : lo;
+      v[NET[c][1]] = sw ? lo : hi;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < n) d.pos[a + k] = v[k];
+    return;
+  }
   for (int i = a + 1; i < b; ++i) {
     const double4 key = d.pos[i];
     int j = i - 1;
