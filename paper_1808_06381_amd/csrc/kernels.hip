@@ -60,21 +60,38 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t* lds) {
   return lds[threadIdx.x];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, int64_t nb) {
-  __shared__ int32_t lds[1024];
-  __shared__ int32_t carry;
+// The block sums are scanned in 64 bits: if the total passes INT32_MAX the
+// 32-bit offsets below would wrap, so *too_many (optional) is raised and the
+// consumers of the offsets (the neighbour list) write nothing.
+__device__ __forceinline__ int64_t block_incl_scan64(int64_t v, int64_t* lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    const int64_t add = threadIdx.x >= (unsigned)o ? lds[threadIdx.x - o] : 0;
+    __syncthreads();
+    lds[threadIdx.x] += add;
+    __syncthreads();
+  }
+  return lds[threadIdx.x];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, int64_t nb,
+                                                   int32_t* __restrict__ too_many) {
+  __shared__ int64_t lds[1024];
+  __shared__ int64_t carry;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int64_t base = 0; base < nb; base += 1024) {
     const int64_t i = base + threadIdx.x;
-    const int32_t v = i < nb ? bsum[i] : 0;
-    const int32_t inc = block_incl_scan(v, lds);
-    const int32_t c = carry;
-    if (i < nb) bsum[i] = c + inc - v;
+    const int64_t v = i < nb ? bsum[i] : 0;
+    const int64_t inc = block_incl_scan64(v, lds);
+    const int64_t c = carry;
+    if (i < nb) bsum[i] = (int32_t)(c + inc - v);
     __syncthreads();
     if (threadIdx.x == 1023) carry = c + inc;
     __syncthreads();
   }
+  if (threadIdx.x == 0 && too_many && carry > (int64_t)INT32_MAX) *too_many = 1;
 }
 
 __global__ __launch_bounds__(BLOCK_THREADS) void k_scan_down(const int32_t* __restrict__ in,
@@ -262,6 +279,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d,
   for (int u = 0; u < ROWS_PER_BLOCK / BLOCK_THREADS; ++u) {
     const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + u * BLOCK_THREADS + threadIdx.x;
     if (i - R.row_off >= R.n) continue;
+    if (d.ctrl->too_many) {  // offsets wrapped: nothing is written, the fill fails
+      atomicOr(&d.ctrl->overflow, 1);
+      continue;
+    }
     const int64_t e1 = d.rowptr[i + 1];
     if (e1 > d.nnz_cap) {
       atomicOr(&d.ctrl->overflow, 1);
@@ -280,7 +301,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_nbr_list(DevPtrs d,
       if (dist2(dx, dy, dz) < R.rc2) d.col[e++] = j;
     });
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.ctrl->nnz = d.rowptr[d.rows];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !d.ctrl->too_many) d.ctrl->nnz = d.rowptr[d.rows];
 }
 
 // Pair terms and assembly: -alpha*w_ij into val, diag = gamma0 + alpha*sum w,
@@ -405,6 +426,7 @@ __global__ void k_ctrl_zero(Ctrl* c) {
     c->max_row = 0;
     c->nnz = 0;
     c->breakdown = 0;
+    c->too_many = 0;
   }
 }
 
@@ -566,10 +588,11 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s) {
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s,
+                       int32_t* too_many) {
   const int64_t nb = (m + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(BLOCK_THREADS), 0, s, in, m, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, nb, too_many);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(BLOCK_THREADS), 0, s, in, m, bsum, out);
   return hipGetLastError();
 }

@@ -4,7 +4,10 @@
 #include "sim_dev.h"
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s);
+// exclusive scan of int32; too_many (optional, device) is set to 1 when the
+// total passes INT32_MAX (the int32 outputs are then not valid)
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* bsum, hipStream_t s,
+                       int32_t* too_many = nullptr);
 int64_t scan_bsum_len(int64_t m);
 hipError_t launch_bin(const DevPtrs& d, hipStream_t s);
 hipError_t launch_cell_rows(const DevPtrs& d, const int32_t* scan, hipStream_t s);

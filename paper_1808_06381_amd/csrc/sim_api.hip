@@ -186,6 +186,13 @@ static int validate(const sim_params& p) {
   return SIM_OK;
 }
 
+// off-diagonal entries of a box with uniform density: n times the mean
+// number of neighbours (4/3) pi rc^3 n / V
+static double expected_entries(const sim_params& p) {
+  const double vol = p.box[0] * p.box[1] * p.box[2];
+  return (double)p.n * (4.18879020478639 * p.rc * p.rc * p.rc * (double)p.n / vol);
+}
+
 // friction along / across the line of centres (0 stands for 1)
 static double fric(double v) { return v == 0.0 ? 1.0 : v; }
 static bool anisotropic(const sim_params& p) {
@@ -367,7 +374,7 @@ static int build_system(sim_t* s) {
   std::swap(d.cellidx, d.cellidx_alt);
   HIPCHK(launch_cell_sort(d, st));
   HIPCHK(launch_nbr_count(d, s->nbr_slots, st));
-  HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st));
+  HIPCHK(launch_scan(d.rowlen, d.rowptr, s->rows + 1, s->bsum, st, &d.ctrl->too_many));
   HIPCHK(launch_nbr_list(d, s->nbr_slots, st));
   if (s->block) HIPCHK(launch_pair_block(d, s->bp, st));
   else HIPCHK(launch_pair_terms(d, st));
@@ -384,6 +391,11 @@ static int read_ctrl(sim_t* s, bool with_cg) {
 }
 
 static int grow_and_refill(sim_t* s) {
+  if (s->ctrl_h->too_many) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "the neighbour list holds more than INT32_MAX entries (32-bit CSR offsets)");
+    return SIM_ENOMEM;
+  }
   int64_t need = s->ctrl_h->nnz;
   int rc = alloc_csr(s, need + need / 4 + 1024);
   if (rc) return rc;
@@ -760,6 +772,14 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
     int rc = validate(params[r]);
     if (rc) return rc;
   }
+  // The CSR offsets are 32-bit: refuse a handle whose uniform-density
+  // neighbour list alone would fill half that range (clustering adds about
+  // a third to it; the row scan still raises SIM_ENOMEM if a state passes it)
+  {
+    double expect = 0.0;
+    for (int r = 0; r < replicas; ++r) expect += expected_entries(params[r]);
+    if (expect > 0.5 * (double)INT32_MAX) return SIM_EINVAL;
+  }
   sim_t* s = new (std::nothrow) sim_t();
   if (!s) return SIM_ENOMEM;
   if (hipGetDevice(&s->device) != hipSuccess) { delete s; return SIM_EDEVICE; }
@@ -928,9 +948,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   // neighbour-list capacity: twice the mean row of a uniform box, + slack
   int64_t cap = 0;
   for (int r = 0; r < replicas; ++r) {
-    const sim_params& p = params[r];
-    const double vol = p.box[0] * p.box[1] * p.box[2];
-    const double kmean = 4.18879020478639 * p.rc * p.rc * p.rc * (double)p.n / vol;
+    const double kmean = expected_entries(params[r]) / (double)params[r].n;
     cap += s->reph[r].npad * (int64_t)std::ceil(2.0 * kmean + 16.0);
   }
   if ((rc = alloc_csr(s, cap)) != SIM_OK) { sim_destroy(s); return rc; }

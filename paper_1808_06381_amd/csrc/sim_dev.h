@@ -69,7 +69,7 @@ struct Ctrl {
   int32_t max_row;      // longest off-diagonal row of the last build
   int64_t nnz;          // off-diagonal entries of the last build
   int32_t breakdown;    // a component of the current solve broke down
-  int32_t pad;
+  int32_t too_many;     // the row scan passed INT32_MAX entries (32-bit CSR indices)
 };
 
 // A step may be committed on the device (graph replay) only when every

@@ -57,6 +57,9 @@ BAD = [
     dict(box=(10.0, 0.0, 10.0)),
     dict(weight_law="gauss", lam=0.0),
     dict(shear_rate=float("nan")),
+    # density 296 with rc = 1: about 1.24e9 expected neighbour entries, past
+    # half of the 32-bit CSR offset range
+    dict(n=1_000_000, box=(15.0, 15.0, 15.0)),
 ]
 
 

@@ -7,7 +7,8 @@ training gains over Jacobi.
 
 Tolerances: with activations kept in FP32 (round_act off) the GPU network is
 an FP32 evaluation of the oracle's FP64 one on the same bfloat16 weights:
-1e-4 relative on M^-1 and the loss, 1e-3 on the gradient norm.  With the
+1e-4 relative on M^-1 and the loss, 1e-3 on the gradient norm and on the
+gradient of every parameter tensor against that tensor's own norm.  With the
 default bfloat16 activations the products see inputs rounded to 2^-9
 relative, fan-in <= 64: 3e-2 relative on M^-1."""
 import numpy as np
@@ -107,6 +108,23 @@ def test_loss_and_gradient_match_oracle():
     lo, go = oracle.mpnn_loss_grad(s, er, cfg["alpha"], th, b, v)
     assert loss == pytest.approx(lo, rel=1e-4)
     assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+    assert_grad_per_tensor(g, go)
+
+
+def assert_grad_per_tensor(g, go):
+    """Every parameter tensor's gradient against its own norm, so that an
+    error in a small tensor (v0, z0, ze, a layer's Q or c) cannot hide under
+    the 32 x 32 matrices: 1e-3 relative (an FP32 evaluation of the FP64
+    oracle on the same weights), plus 1e-7 of the whole gradient's norm
+    (FP32 rounding of the sums that feed a tensor whose own gradient is
+    small)."""
+    floor = 1e-7 * np.linalg.norm(go)
+    for name, (off, shape) in precond.LAYOUT.items():
+        sl = slice(off, off + int(np.prod(shape)))
+        err = np.linalg.norm(g[sl] - go[sl])
+        ref = np.linalg.norm(go[sl])
+        assert ref > 0.0 or name in ("z0",), name
+        assert err <= 1e-3 * ref + floor, (name, err, ref)
 
 
 def oracle_probe(cfg, seed, index):
@@ -151,6 +169,7 @@ def test_probe_loss_and_gradient_match_oracle(batch, norm):
     assert loss == pytest.approx(num / den, rel=1e-4)
     go /= den
     assert np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+    assert_grad_per_tensor(g, go)
 
 
 def test_optimizer_state_moves_between_handles():

@@ -6,8 +6,12 @@
 * solves against dense LAPACK and the oracle's PCG;
 * trajectories of the small workload (N = 1000, L = 10) step by step;
 * a batch of replicas of uneven size against per-replica oracle runs;
-* determinism, error paths and the full-size workload (N = 10^6) checked on
-  sampled rows and by the oracle's residual of the GPU velocities.
+* the paper's own thermal force (Eq. 6a: node noise only) in the paper's
+  geometry, right-hand side and a 10-step trajectory;
+* determinism, error paths and the full-size workloads (N = 10^6, and
+  N = 2.2 * 10^6, whose 2149 tiles take the 1024-thread reduction of the CG
+  finisher) checked on the pair set, A's diagonal, b, and the oracle's
+  residual of the GPU velocities.
 
 Tolerances: pairs exact; matrix values within 1e-14 relative (the
 polynomial weight is the same IEEE sequence; the Gaussian differs by the
@@ -38,6 +42,20 @@ def le_diff(cfg, step, a, b):
     """Lees-Edwards-aware difference a - b per particle (oracle geometry)."""
     delta = oracle.le_offset(cfg, step)
     return np.array([oracle.separation(cfg, delta, x, y)[0] for x, y in zip(a, b)])
+
+
+def le_diff_np(cfg, step, a, b):
+    """The same difference for nearby positions, vectorised: the image index
+    from the y difference, the offset delta of that image, periodic x and z."""
+    L = np.asarray(cfg["box"], dtype=np.float64)
+    delta = oracle.le_offset(cfg, step)
+    d = a - b
+    s = np.rint(d[:, 1] / L[1])
+    d[:, 1] -= s * L[1]
+    d[:, 0] -= s * delta
+    for k in (0, 2):
+        d[:, k] -= np.rint(d[:, k] / L[k]) * L[k]
+    return d
 
 
 CASES = {
@@ -329,3 +347,87 @@ def test_full_size_single_box():
     res = np.linalg.norm(ref["rhs"] - Av, axis=0) / np.linalg.norm(ref["rhs"], axis=0)
     assert np.all(res <= tol * 1.01), res
     assert max(st["relres"]) <= tol
+
+
+def test_paper_noise_system_matches_oracle():
+    """The paper's own thermal force (Method, Eq. 6a: sqrt(2 gamma0 kT / dt)
+    xi on the background friction only, no pair noise) in the paper's
+    geometry (87.6 x 43.6 x 22 box, C = 20060, Gaussian weight cut at 5 %,
+    Gaussian core, gamma0 = 1, alpha = 4): b element by element against the
+    oracle, at creation and after sheared steps (same Philox streams; the
+    Gaussians differ by the log/cos ulps, hence 1e-11 of max|b|)."""
+    cfg = dict(inputs.paper_box(shear_rate=0.5, seed=5), noise="paper")
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        for k in (0, 3):
+            if k:
+                sim.step(k)
+            pos, _, meta = sim.state()
+            assert meta["step"] == k
+            rows, cols, vals, diag, rhs = sim.system()
+            ref = oracle.build_system(cfg, pos, k)
+            np.testing.assert_allclose(diag, ref["diag"], rtol=1e-14)
+            np.testing.assert_allclose(rhs, ref["rhs"], rtol=0,
+                                       atol=1e-11 * np.abs(ref["rhs"]).max())
+            # the pair noise is absent: the FDT form of the same state differs
+            fdt = oracle.build_system(dict(cfg, noise="fdt"), pos, k)["rhs"]
+            assert np.abs(fdt - ref["rhs"]).max() > 1e3 * 1e-11 * np.abs(ref["rhs"]).max()
+
+
+def test_paper_noise_trajectory_paper_geometry():
+    """10 steps of the paper's box with the paper's noise form, GPU and oracle
+    advancing independently from the same positions: velocities within 1e-8
+    relative per component and step (CG tolerance 1e-10, kappa(A) < 40 by
+    Gershgorin at alpha = 4, gamma0 = 1), positions within 1e-9."""
+    cfg = dict(inputs.paper_box(shear_rate=0.05, seed=8), noise="paper")
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    pos_o = pos0.copy()
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        for k in range(10):
+            st = sim.step(1)
+            pos_g, vel_g, _ = sim.state()
+            pos_o, vel_o, its = oracle.step(cfg, pos_o, k, tol=1e-10)
+            rel = np.linalg.norm(vel_g - vel_o, axis=0) / np.linalg.norm(vel_o, axis=0)
+            assert np.all(rel < 1e-8), (k, rel)
+            assert np.max(np.abs(le_diff_np(cfg, k + 1, pos_g, pos_o))) < 1e-9, k
+            assert max(abs(a - b) for a, b in zip(st["iters"], its)) <= 2
+            assert max(st["relres"]) <= 1e-10
+
+
+@pytest.mark.slow
+def test_full_size_above_2048_tiles():
+    """N = 2.2 * 10^6 in one box (2149 tiles of 1024 rows): the per-replica
+    reduction of the CG finisher runs with 1024 threads here (256 up to 2048
+    tiles), as on the N = 8 * 10^6 box.  The complete pair set equals the
+    oracle's cell list, A's diagonal and b match, and the oracle's own
+    residual of the GPU velocities -- computed without any GPU sum --
+    meets the tolerance, so a wrong reduction cannot pass unseen."""
+    n = 2_200_000
+    cfg = inputs.cube_params(n, 0.5, seed=17)
+    tol = 1e-8
+    assert (n + 1023) // 1024 > 2048
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=tol) as sim:
+        sim.step(2)
+        p2, _, meta = sim.state()
+        got = gpu_pairs_rep(sim)
+        rows, cols, vals, diag, rhs = sim.system()
+        st = sim.step(1)
+        _, v2, _ = sim.state()
+    ref = oracle.build_system(cfg, p2, 2)
+    assert got.shape[0] == ref["npairs"]
+    assert np.array_equal(got, oracle.pairs(cfg, p2, oracle.le_offset(cfg, 2), "cells"))
+    np.testing.assert_allclose(diag, ref["diag"], rtol=1e-14)
+    np.testing.assert_allclose(rhs, ref["rhs"], rtol=0, atol=1e-11 * np.abs(ref["rhs"]).max())
+    # sampled off-diagonal values of A (every 97th entry of the GPU export)
+    o_rows = np.repeat(np.arange(n), np.diff(ref["rowptr"]))
+    key_o = o_rows * n + ref["col"]
+    order = np.argsort(key_o)
+    pick = np.arange(0, len(rows), 97)
+    idx = order[np.searchsorted(key_o[order], rows[pick] * n + cols[pick])]
+    assert np.array_equal(key_o[idx], rows[pick] * n + cols[pick])
+    assert np.array_equal(vals[pick], ref["val"][idx])
+    Av = oracle.spmv3(ref, v2)
+    res = np.linalg.norm(ref["rhs"] - Av, axis=0) / np.linalg.norm(ref["rhs"], axis=0)
+    assert np.all(res <= tol * 1.01), res
+    assert max(st["relres"]) <= tol and st["iters"][0] > 10
