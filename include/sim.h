@@ -212,6 +212,26 @@ int sim_state(sim_t* sim, double* pos, double* vel, sim_meta* meta, uint32_t fla
 int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, double* out,
                          double* kernel_ms);
 
+/* sim_structure_factor for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result bits, with every
+ * intermediate (chunk table, chunk offsets, partial sums) in one static
+ * device array of SIM_NOALLOC_SCRATCH_MAX bytes that the library holds on
+ * each GPU it runs on until the process ends.  out is a DEVICE pointer on
+ * the handle's device: replicas x nx x (2 my_max + 1) doubles, row-major,
+ * written by the call (the caller owns it).  The call allocates nothing and
+ * copies nothing from the host; it returns after the result is written.
+ * Every call on one GPU shares the one array, so calls that overlap on a GPU
+ * (several host threads or streams) race and must be serialised by the
+ * caller.  Arguments as sim_structure_factor (SIM_EINVAL); SIM_ECAPACITY
+ * when the scratch would exceed SIM_NOALLOC_SCRATCH_MAX: it needs about
+ * 32 KiB x ceil(N_r / 4096) summed over replicas x ceil(nx / 64) x
+ * ceil((2 my_max + 1) / 32) (e.g. N = 10^6 with nx = 64, my_max = 64 uses
+ * 38 MiB).                                                                */
+#define SIM_NOALLOC_SCRATCH_MAX (48u << 20)
+int sim_structure_factor_noalloc(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz,
+                                 double* out);
+
 /* Velocity cross-correlation against separation (Results section: the
  * velocity correlation of two chains, normalised by the mean square
  * velocity, against |R_cc'|, longer-ranged as alpha grows), of every

@@ -63,6 +63,9 @@ int64_t sq_chunk_count(const std::vector<int64_t>& rep_rows);
 int64_t sq_tile_count(int nx, int my_max);
 size_t sq_chunk_bytes();
 size_t sq_partial_bytes(int64_t nchunk, int nx, int my_max);
+size_t sq_scratch_bytes(int64_t nchunk, int nrep, int nx, int my_max);
+hipError_t launch_sq_scratch(const DevPtrs& d, int64_t nchunk, int nx, int my_max, int mz,
+                             void* scratch, double* out_d, hipStream_t s);
 hipError_t launch_sq(const DevPtrs& d, const std::vector<int64_t>& rep_row0,
                      const std::vector<int64_t>& rep_rows, int nx, int my_max, int mz,
                      void* chunks_d, int32_t* rep_chunk0_d, double2* partial_d, double* out_d,

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <climits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -24,6 +25,7 @@
 
 #define SIM_EOVERFLOW_INTERNAL 1  // capacity of the CSR arrays exceeded: grow and refill
 #define SIM_ESTALL_INTERNAL 2     // learned-preconditioned solve stalled: redo with Jacobi
+#define SIM_MAX_DEVICES 64
 
 #define HIPCHK(expr)                                   \
   do {                                                 \
@@ -1663,6 +1665,61 @@ int sim_event_probe(const void* src, void* dst, int64_t bytes, int32_t reps, voi
   }
   *ms_chain = (double)chain / reps;
   *ms_each = (double)each / reps;
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free structure factor: the chunk table and partial sums live in
+// one file-scope device array, `scratch`, shared by every call on a GPU.  In
+// host code the array's name is not a device address: its address on each
+// device is taken once with hipGetSymbolAddress (with that device current)
+// and only that pointer is passed to kernels.
+// ---------------------------------------------------------------------------
+#define SIM_NOALLOC_SCRATCH_BYTES ((size_t)SIM_NOALLOC_SCRATCH_MAX)
+static __device__ __align__(256) unsigned char scratch[SIM_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SIM_MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (taken on first use)
+static int noalloc_scratch(int device, void** ptr) {
+  if (device < 0 || device >= SIM_MAX_DEVICES) return SIM_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      sim_note_error(e, "hipGetSymbolAddress(scratch)", __LINE__);
+      return SIM_EDEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return SIM_OK;
+}
+
+int sim_structure_factor_noalloc(sim_t* s, int32_t nx, int32_t my_max, int32_t mz, double* out) {
+  if (!s || !out || nx < 1 || nx > 256 || my_max < 0 || my_max > 128 || mz < -256 || mz > 256)
+    return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int64_t nchunk = 0;
+  for (const RepDev& R : s->reph) nchunk += ((int64_t)R.n + 4095) / 4096;
+  const size_t need = sq_scratch_bytes(nchunk, s->R, nx, my_max);
+  if (need > SIM_NOALLOC_SCRATCH_BYTES) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "structure factor needs %zu bytes of scratch, the allocation-free call has %zu",
+             need, SIM_NOALLOC_SCRATCH_BYTES);
+    return SIM_ECAPACITY;
+  }
+  void* base = nullptr;
+  int rc = noalloc_scratch(s->device, &base);
+  if (rc) return rc;
+  hipError_t err = launch_sq_scratch(s->d, nchunk, nx, my_max, mz, base, out, s->stream);
+  if (!err) err = hipStreamSynchronize(s->stream);
+  if (err) {
+    sim_note_error(err, "structure factor (scratch)", __LINE__);
+    return SIM_EDEVICE;
+  }
   return SIM_OK;
 }
 

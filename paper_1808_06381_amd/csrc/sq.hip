@@ -191,6 +191,59 @@ size_t sq_partial_bytes(int64_t nchunk, int nx, int my_max) {
   return (size_t)nchunk * (size_t)sq_tile_count(nx, my_max) * SQ_TX * SQ_TY * sizeof(double2);
 }
 
+// The chunk table of every replica built on the device (one thread walks the
+// replicas: a handful of stores per chunk), so that a caller's scratch can
+// be filled without a host table.
+__global__ void k_sq_chunks(DevPtrs d, SqChunk* __restrict__ chunks, int32_t* __restrict__ rep_chunk0) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int32_t c = 0;
+  for (int r = 0; r < d.nrep; ++r) {
+    rep_chunk0[r] = c;
+    const RepDev& R = d.rep[r];
+    for (int64_t a = 0; a < R.n; a += SQ_CHUNK)
+      chunks[c++] = SqChunk{r, 0, R.row_off + a, min<int64_t>(SQ_CHUNK, (int64_t)R.n - a)};
+  }
+  rep_chunk0[d.nrep] = c;
+}
+
+namespace {
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+}
+
+// Bytes of caller scratch that launch_sq_scratch needs: chunk table, chunk
+// offsets, partial sums (256-byte aligned pieces).
+size_t sq_scratch_bytes(int64_t nchunk, int nrep, int nx, int my_max) {
+  return up256(sizeof(SqChunk) * (size_t)std::max<int64_t>(nchunk, 1)) +
+         up256(sizeof(int32_t) * (size_t)(nrep + 1)) +
+         up256(sq_partial_bytes(std::max<int64_t>(nchunk, 1), nx, my_max));
+}
+
+// The same kernels as launch_sq with every table on the device: `scratch`
+// (sq_scratch_bytes() bytes, 256-byte aligned) holds the chunk table, the
+// chunk offsets and the partial sums, out_d receives replicas x nx x ny.
+// Nothing is allocated and nothing is copied from the host; the launches
+// are asynchronous on stream s.
+hipError_t launch_sq_scratch(const DevPtrs& d, int64_t nchunk, int nx, int my_max, int mz,
+                             void* scratch, double* out_d, hipStream_t s) {
+  char* base = (char*)scratch;
+  SqChunk* chunks = (SqChunk*)base;
+  const size_t b_ch = up256(sizeof(SqChunk) * (size_t)std::max<int64_t>(nchunk, 1));
+  int32_t* c0 = (int32_t*)(base + b_ch);
+  const size_t b_c0 = up256(sizeof(int32_t) * (size_t)(d.nrep + 1));
+  double2* partial = (double2*)(base + b_ch + b_c0);
+  hipLaunchKernelGGL(k_sq_chunks, dim3(1), dim3(64), 0, s, d, chunks, c0);
+  const int ny = 2 * my_max + 1;
+  const int tiles_y = (ny + SQ_TY - 1) / SQ_TY;
+  const int ntile = (int)sq_tile_count(nx, my_max);
+  if (nchunk > 0)
+    hipLaunchKernelGGL(k_sq_partial, dim3(ntile, (unsigned)nchunk), dim3(SQ_THREADS), 0, s, d,
+                       (const SqChunk*)chunks, nx, my_max, mz, tiles_y, partial);
+  const int64_t nout = (int64_t)d.nrep * nx * ny;
+  hipLaunchKernelGGL(k_sq_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, d, c0,
+                     d.nrep, nx, my_max, tiles_y, ntile, partial, out_d);
+  return hipGetLastError();
+}
+
 // rep_row0 / rep_rows: first row and real particles of each replica;
 // chunks_d (sq_chunk_bytes() x count) and rep_chunk0_d (nrep + 1 int32)
 // are device scratch, filled here from the host tables; ev0/ev1 (optional)

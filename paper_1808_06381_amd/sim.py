@@ -27,6 +27,7 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
             "sim_set_stream", "sim_load_precond", "sim_debug_pairs", "sim_debug_system",
             "sim_debug_set_gaussians", "sim_debug_block_system", "sim_profile_enable", "sim_profile_read",
             "sim_copy_probe", "sim_event_probe", "sim_structure_factor",
+            "sim_structure_factor_noalloc",
             "sim_velocity_correlation", "sim_precond_weights",
             "sim_precond_config", "sim_train_step",
             "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
@@ -142,6 +143,7 @@ def lib():
         L.sim_state.argtypes = [vp, vp, vp, P(SimMeta), C.c_uint32]
         L.sim_structure_factor.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp,
                                            P(C.c_double)]
+        L.sim_structure_factor_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
         L.sim_velocity_correlation.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp, vp, vp,
                                                P(C.c_double)]
         L.sim_set_stream.argtypes = [vp, vp]
@@ -298,6 +300,18 @@ class Sim:
                                           C.byref(ms) if timed else None),
                "sim_structure_factor")
         return (out, ms.value) if timed else out
+
+    def structure_factor_noalloc(self, nx, my_max, out, mz=0):
+        """S(q) as structure_factor, written into `out`, a contiguous float64
+        torch tensor on the library's device of shape (replicas, nx,
+        2 my_max + 1); the library allocates nothing for the call."""
+        ny = 2 * int(my_max) + 1
+        if tuple(out.shape) != (self.replicas, int(nx), ny) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (replicas, nx, 2 my_max + 1) tensor")
+        _check(lib().sim_structure_factor_noalloc(self.h, int(nx), int(my_max), int(mz),
+                                                  C.c_void_p(out.data_ptr())),
+               "sim_structure_factor_noalloc")
+        return out
 
     def velocity_correlation(self, r_max, nbins, flow=True, timed=False):
         """Velocity cross-correlation of the last committed step (the
