@@ -329,13 +329,27 @@ int sim_precond_weights(sim_t* sim, float* theta, int64_t count, int32_t set);
  * learned_maxit > 0 bounds the iterations of a learned-preconditioned
  * solve before it falls back to Jacobi (0: the params' cg_maxit).         */
 int sim_precond_config(sim_t* sim, int32_t round_act, int32_t learned_maxit);
+/* Safeguards of the learned M^-1 against rare strongly coupled low-degree
+ * clusters where it is not positive definite.  lam_floor is added to the
+ * diagonal head: lam_i = softplus(v.h_i + v0) + lam_floor (default 0.1,
+ * >= 0; it adds lam_floor D^-1 to M^-1, at the price of a slightly weaker
+ * preconditioner elsewhere).  s_clamp > 0 bounds each off-diagonal head
+ * value at inference, |S_ij| <= s_clamp sqrt(lam_i lam_j), so that no 2 x 2
+ * principal block of diag(lam) + S is indefinite for s_clamp < 1 (0, the
+ * default, leaves S as the network gives it; training always sees the
+ * unclamped S).                                                           */
+int sim_precond_floor(sim_t* sim, double lam_floor, double s_clamp);
 /* One training step on the system of the last successful solve of this
  * single-box handle (A, b and its solution x* from sim_step or sim_solve):
  * network forward, loss L = ||M^-1 b - x*||_A^2 / ||x*||_A^2 (three
  * components), backward and one Adam step (beta 0.9 / 0.999) with learning
  * rate lr; lr = 0 evaluates the loss and gradient only.  *loss receives L
- * at the weights before the update.  SIM_EINVAL without a solved system;
- * SIM_ENOTSUP for batches and for handles with anisotropic friction.      */
+ * at the weights before the update.  SIM_EINVAL without a solved system,
+ * or when that system was built before the first preconditioner call on
+ * the handle (sim_precond_weights, sim_precond_config, sim_load_precond,
+ * sim_precond_floor; a Jacobi handle writes the network's edge input only
+ * from then on); SIM_ENOTSUP for batches and for handles with anisotropic
+ * friction.                                                               */
 int sim_train_step(sim_t* sim, double lr, double* loss);
 /* One training step on a white-noise probe of the current system (any
  * number of replicas; needs a successful solve): x* = z with z_ik ~ N(0, 1)
@@ -368,13 +382,22 @@ int sim_debug_precond(sim_t* sim, int64_t* rows, int64_t* cols, double* vals, in
                       int64_t* count, double* mdiag);
 
 /* Kernel timing probe (measurement, not part of the method).  With
- * sample_every > 0, every sample_every-th CG iteration of later solves has
- * its three kernels bracketed by HIP events on the library's stream (the
- * sampled residue of the iteration index advances by one per solve, so
- * every position in a solve is sampled alike); only iterations in which
- * every component of every replica was still iterating are kept, so each
- * kept launch did the full work of one iteration.
- * sample_every = 0 switches the probe off.                                */
+ * sample_every > 0, later eager solves (with step graphs on, every
+ * sample_every-th step runs eagerly) alternate two forms.  Kernel form:
+ * every sample_every-th CG iteration has its three kernels (k_cg_vec,
+ * k_cg_spmv, k_cg_apply) bracketed by HIP events on the library's stream
+ * (the sampled residue of the iteration index advances by one per such
+ * solve, so every position in a solve is sampled alike).  Iteration form
+ * ("cg_iteration"): one event pair around the first chunk's iterations
+ * except its last two -- every kernel, the finisher and the gaps between
+ * launches -- counted as that many launches, each priced at the solve's
+ * algorithmic bytes per iteration: 12(nnz + N) + 4N (the matrix: value 8 +
+ * column 4 per entry, the diagonal as one more entry, a row pointer; 8
+ * instead of 12 with FP32 values) + 200N (the CG vectors) for N particles
+ * and nnz off-diagonal entries, plus 12(nnz + N) + 4N for the learned
+ * preconditioner's product.  Only iterations in which every component of
+ * every replica was still iterating are kept, so each kept record did the
+ * full work of its iterations.  sample_every = 0 switches the probe off.   */
 typedef struct sim_kernel_prof {
   char name[32];         /* kernel name */
   int64_t launches;      /* timed launches kept */
@@ -437,6 +460,11 @@ typedef struct sim_tuning {
   int32_t apply_variant;
   float spmv_us[SIM_CSR_VARIANTS];  /* sim_autotune: mean duration per variant */
   float apply_us[SIM_CSR_VARIANTS]; /* (0 where not measured) */
+  /* CG vector kernel: 0 ordinary loads and stores, 1 nontemporal (streaming)
+   * for the vectors not read again within the iteration (faster on a working
+   * set larger than the last-level cache); the same bits either way         */
+  int32_t vec_variant;
+  float vec_us[2];
 } sim_tuning;
 /* Time every variant `reps` times on the system at the current positions
  * (built for the purpose; the state is unchanged) and keep the fastest.

@@ -99,6 +99,8 @@ def lib():
         L.orc_velocity_correlation.argtypes = [pp, C.c_double, d_p, d_p, C.c_double, C.c_int32,
                                                C.c_int32, C.c_int32, d_p, i64_p, d_p]
         L.orc_velocity_correlation.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         f_p = P(C.c_float)
         L.orc_mpnn_nparams.restype = C.c_int64
         L.orc_bf16.argtypes = [C.c_float]
@@ -130,6 +132,13 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's row-parallel loops (1: sequential);
+    results are the same bits with any count.  Returns the count in force."""
+    lib().orc_set_threads(int(n))
+    return lib().orc_get_threads()
 
 
 def make_params(cfg):

@@ -1,9 +1,11 @@
 """Build the CPU oracle shared library (oracle/liboracle.so) with gcc.
 
 Plain FP64 C, no FMA contraction and no fast-math, so the pair decision
-r^2 < rc^2 is the IEEE result of the operations as written.  OpenMP only
-spreads the brute-force pair loop of the velocity correlation over threads
-(fixed chunks, per-thread compensated sums added in thread order).
+r^2 < rc^2 is the IEEE result of the operations as written.  OpenMP spreads
+the brute-force pair loop of the velocity correlation over threads (fixed
+chunks, per-thread compensated sums added in thread order) and the row loops
+of the solve's products and vector updates (one thread per output, sums
+sequential): results do not depend on the thread count.
 """
 import os
 import subprocess

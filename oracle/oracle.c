@@ -4,8 +4,13 @@
  *
  * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
  * CPU-baseline leg of the benchmark; never by the product path.  It shares no
- * code with the GPU library.  Single-threaded, slow on purpose, written so a
- * reader can check each function against the paper by eye:
+ * code with the GPU library.  Slow on purpose, written so a reader can check
+ * each function against the paper by eye.  The row loops of the products and
+ * the element-wise vector updates of the solve run on OpenMP threads (all
+ * cores unless orc_set_threads or OMP_NUM_THREADS say otherwise; the CPU
+ * timing baseline measures 1 and all): each output is written by one thread
+ * in the sequential order of operations and every sum stays sequential, so
+ * no result bit depends on the thread count:
  *
  *   orc_separation    Lees-Edwards minimum image (Method: "standard
  *                     Lees-Edwards boundary conditions"; image index of Eq. 8)
@@ -23,6 +28,9 @@
 #include "oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -383,6 +391,9 @@ int64_t orc_build_system(const orc_params* p, int64_t step, const double* pos,
 /* y = A x, x and y n x 3 */
 void orc_spmv3(int64_t n, const int64_t* rowptr, const int64_t* col,
                const double* val, const double* diag, const double* x, double* y) {
+  /* rows are independent and each is summed in entry order by one thread:
+     the same bits with any thread count */
+#pragma omp parallel for schedule(static) if (n > 20000)
   for (int64_t i = 0; i < n; ++i) {
     for (int c = 0; c < 3; ++c) {
       double acc = diag[i] * x[3 * i + c];
@@ -501,6 +512,26 @@ static void orc_apply_precond(const orc_precond* pc, const double* r, double* z,
   }
 }
 
+/* Threads of the element-wise loops and products (OpenMP; 1 = the plain
+   sequential oracle).  Every parallel loop writes disjoint outputs in the
+   sequential order of operations, and every sum stays sequential, so
+   results do not depend on the thread count. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 static double orc_dot(int64_t n, const double* a, const double* b, int c) {
   double s = 0.0;
   for (int64_t i = 0; i < n; ++i) s += a[3 * i + c] * b[3 * i + c];
@@ -563,6 +594,7 @@ int orc_pcg(int64_t n, const int64_t* rowptr, const int64_t* col,
       const double pq = orc_dot(n, pv, q, c);
       if (!(pq > 0.0)) { status = ORC_EBREAKDOWN; break; }
       const double a = rz / pq;
+#pragma omp parallel for schedule(static) if (n > 20000)
       for (int64_t i = 0; i < n; ++i) {
         x[3 * i + c] += a * pv[3 * i + c];
         r[3 * i + c] -= a * q[3 * i + c];
@@ -575,6 +607,7 @@ int orc_pcg(int64_t n, const int64_t* rowptr, const int64_t* col,
       const double rz_new = orc_dot(n, r, z, c);
       const double beta = rz_new / rz;
       rz = rz_new;
+#pragma omp parallel for schedule(static) if (n > 20000)
       for (int64_t i = 0; i < n; ++i) pv[3 * i + c] = z[3 * i + c] + beta * pv[3 * i + c];
     }
     if (status != ORC_OK) break;

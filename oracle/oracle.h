@@ -109,6 +109,12 @@ int64_t orc_build_system(const orc_params* p, int64_t step, const double* pos,
                          int64_t* rowptr, int64_t* col, double* val,
                          double* diag, double* rhs, double* fcons);
 
+/* ---- threads --------------------------------------------------------------- */
+/* OpenMP threads of the row-parallel loops (CPU timing only; results do not
+   depend on it); orc_get_threads reports the count in force */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
 /* ---- linear solve ---------------------------------------------------------- */
 void orc_spmv3(int64_t n, const int64_t* rowptr, const int64_t* col,
                const double* val, const double* diag, const double* x, double* y);

@@ -113,13 +113,31 @@ __global__ void k_cg_reset(DevPtrs d, double tol_override) {
   }
 }
 
+// nontemporal (streaming) loads and stores, or ordinary ones
+template <bool NT, class T>
+__device__ __forceinline__ T ldv(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void stv(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Element-parallel vector work of one tile (3 * 1024 consecutive doubles of
-// the AoS arrays; element e is row e/3, component e%3).
+// the AoS arrays; element e is row e/3, component e%3).  NT: the streams
+// that are not read again within the iteration (r, p, w, s, x, 1/diag) are
+// loaded and stored as nontemporal, u (gathered by the product next) as
+// usual: on a working set larger than the last-level cache this streams
+// faster (measured at N = 8e6), below it the ordinary form keeps the
+// vectors cached; the autotuner picks.  Same bits either way.
 //   mode 0 (fresh start):   x = 0, r = b, p = s = 0, u = M^-1 r
 //   mode 1 (restart, r already = b - A x):   p = s = 0, u = M^-1 r
 //   mode 2 (iteration):     p = u + beta p, s = w + beta s, x += alpha p,
 //                           r -= alpha s, u = M^-1 r
 // Partials (r, u) and (r, r) of the components touched.
+template <bool NT>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -144,7 +162,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
     if (!on[k]) continue;
     const int64_t e = base + le;
     // 1/diag only where this kernel applies Jacobi itself
-    const double di = (ext || d.pc_none) ? 1.0 : d.dinv[(int64_t)tile * ROWS_PER_BLOCK + le / 3];
+    const double di =
+        (ext || d.pc_none) ? 1.0 : ldv<NT>(d.dinv + (int64_t)tile * ROWS_PER_BLOCK + le / 3);
     double rk;
     if (mode == 0) {
       rk = d.b[e];
@@ -157,15 +176,15 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
       d.p[e] = 0.0;
       d.s[e] = 0.0;
     } else {
-      const double r0 = d.r[e];
-      const double uk0 = ext ? d.u[e] : di * r0;
-      const double pk = uk0 + be[k] * d.p[e];
-      const double sk = d.w[e] + be[k] * d.s[e];
-      d.p[e] = pk;
-      d.s[e] = sk;
-      d.x[e] = d.x[e] + al[k] * pk;
+      const double r0 = ldv<NT>(d.r + e);
+      const double uk0 = ext ? ldv<NT>(d.u + e) : di * r0;
+      const double pk = uk0 + be[k] * ldv<NT>(d.p + e);
+      const double sk = ldv<NT>(d.w + e) + be[k] * ldv<NT>(d.s + e);
+      stv<NT>(d.p + e, pk);
+      stv<NT>(d.s + e, sk);
+      stv<NT>(d.x + e, ldv<NT>(d.x + e) + al[k] * pk);
       rk = r0 - al[k] * sk;
-      d.r[e] = rk;
+      stv<NT>(d.r + e, rk);
     }
     if (!ext) {
       const double uk = di * rk;
@@ -568,8 +587,10 @@ hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s)
 // ev0/ev1 (optional) take the kernel's own start and end timestamps
 hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1) {
-  LAUNCH_EV(k_cg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1,
-                        d, mode);
+  if (d.vec_nt && mode == 2)
+    LAUNCH_EV(k_cg_vec<true>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1, d, mode);
+  else
+    LAUNCH_EV(k_cg_vec<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1, d, mode);
   return hipGetLastError();
 }
 

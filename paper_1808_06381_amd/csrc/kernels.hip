@@ -356,8 +356,9 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
       const double r = sqrt(r2);
       const double w = pair_weight(R, r2, r);
       d.val[e] = -R.alpha * w;
-      d.valf[e] = (float)(-R.alpha * w);
-      d.er[e] = (float)(r / R.rc);
+      // the FP32 copy and the network's edge input only where they are read
+      if (d.spmv_fp32) d.valf[e] = (float)(-R.alpha * w);
+      if (d.want_er) d.er[e] = (float)(r / R.rc);
       const double fc = force_coef(R, r2, r);
       double fx = fc * dx, fy = fc * dy, fz = fc * dz;
       if (noise) {

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads(DevPtrs d, MpPtrs m) {
     }
     if (k == 0) {
       m.tau[i] = tau;
-      m.mdiag[i] = ((double)softplusf_(tau) + MP_EPS_LAM) / di;
+      m.mdiag[i] = ((double)softplusf_(tau) + m.lam_floor) / di;
     }
   }
 }
@@ -331,9 +331,14 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
   __shared__ float xs[MP_ROWS][MP_FN];
   __shared__ __align__(16) uint16_t xh[MP_ROWS * MX_HS];
   const int t = threadIdx.x;
+  // tiles of MP_ROWS rows in XCD-contiguous ranges: the neighbour rows a
+  // tile reads are in its own XCD's L2
+  const int ntiles = (int)(m.rows / MP_ROWS);
+  const int tile = xcd_block(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
   load_w(m, w0, MP_OFF_W0, MP_H * MP_FN);
   load_w(m, b0, MP_OFF_B0, MP_H);
-  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  const int64_t i0 = (int64_t)tile * MP_ROWS;
   const int n = t >> 2, q = t & 3;
   const int64_t i = i0 + n;
   {
@@ -413,11 +418,16 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
   uint16_t* const xg = xa;
   uint16_t* const es = xa + MX_EC * MX_HS;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // tiles in XCD-contiguous ranges: the gathered h_j rows of neighbouring
+  // tiles stay in one XCD's L2
+  const int ntiles = (int)(m.rows / MP_ROWS);
+  const int tile = xcd_block(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
   const int base = MP_OFF_L0 + l * MP_L_SIZE;
   load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
   load_w(m, c, base + MP_L_C, MP_H);
   load_w(m, dd, base + MP_L_D, MP_H);
-  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  const int64_t i0 = (int64_t)tile * MP_ROWS;
   if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
   __syncthreads();
   const int n = t >> 2, q = t & 3;
@@ -554,12 +564,16 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
   __shared__ double dg[MP_ROWS];
+  __shared__ double lam_s[MP_ROWS];
   __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
   const int t = threadIdx.x;
+  const int ntiles = (int)(m.rows / MP_ROWS);
+  const int tile = xcd_block(blockIdx.x, ntiles);   // XCD-contiguous tiles
+  if (tile >= ntiles) return;
   load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
   load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
   load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
-  const int64_t i0 = (int64_t)blockIdx.x * MP_ROWS;
+  const int64_t i0 = (int64_t)tile * MP_ROWS;
   if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
   if (t < MP_ROWS) dg[t] = d.diag[i0 + t];
   const int n = t >> 2, q = t & 3;
@@ -578,6 +592,22 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     hb8(i0 + n, v);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = v[kk];
+  }
+  __syncthreads();
+  // node head of a row from its bf16 h (this quad's 8 features), the same
+  // operations for a tile row and for a gathered neighbour
+  auto node_tau = [&](const float* hrow) {
+    float p = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) p += hv[8 * q + kk] * hrow[kk];
+    p += __shfl_xor(p, 1, 64);
+    p += __shfl_xor(p, 2, 64);
+    return p + hv[MP_H];
+  };
+  const bool clamp = m.s_clamp > 0.0 && !m.store_train;
+  if (clamp) {
+    const float tau = node_tau(hi_s + n * MX_FS + 8 * q);
+    if (q == 0) lam_s[n] = (double)softplusf_(tau) + m.lam_floor;
   }
   __syncthreads();
   // no barrier below: the four lanes of a quad share every entry, so the
@@ -610,6 +640,14 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
 #pragma unroll
     for (int f = 0; f < MP_FE; ++f) tt += hze[f] * ef[f];
     tt += hze[MP_FE];
+    if (clamp) {
+      // |S_ij| <= s_clamp sqrt(lam_i lam_j): no 2 x 2 principal block of
+      // diag(lam) + S is indefinite (both ends compute the same bound)
+      const double lj = (double)softplusf_(node_tau(hj)) + m.lam_floor;
+      const double bound = m.s_clamp * sqrt(lam_s[r] * lj);
+      const double tv = (double)tt;
+      tt = (float)(tv > bound ? bound : (tv < -bound ? -bound : tv));
+    }
     if (q == 0) {
       m.moff[e] = (float)((double)tt / sqrt(dg[r] * dj));
       if (m.store_train) m.tg[e] = tt;
@@ -624,7 +662,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     const int64_t i = i0 + n;
     const float tau = p + hv[MP_H];
     m.tau[i] = tau;
-    m.mdiag[i] = ((double)softplusf_(tau) + MP_EPS_LAM) / d.diag[i];
+    m.mdiag[i] = ((double)softplusf_(tau) + m.lam_floor) / d.diag[i];
   }
 }
 
@@ -1061,10 +1099,11 @@ static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t)
 hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
   const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
   if (m.round_act) {
-    hipLaunchKernelGGL(k_mp_encode_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+    const dim3 g((unsigned)xcd_grid((int)blocks));
+    hipLaunchKernelGGL(k_mp_encode_mx, g, dim3(MP_THREADS), 0, s, d, m);
     for (int l = 0; l < MP_NL; ++l)
-      hipLaunchKernelGGL(k_mp_layer_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
-    hipLaunchKernelGGL(k_mp_heads_mx, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+      hipLaunchKernelGGL(k_mp_layer_mx, g, dim3(MP_THREADS), 0, s, d, m, l);
+    hipLaunchKernelGGL(k_mp_heads_mx, g, dim3(MP_THREADS), 0, s, d, m);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_mp_features, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m);

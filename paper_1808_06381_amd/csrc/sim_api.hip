@@ -74,7 +74,10 @@ struct sim_t {
   std::vector<hipEvent_t> prof_ev;      // pool of event pairs
   struct Sample { int kernel; int iter; int ev; float ms; };
   std::vector<Sample> prof_pending;     // recorded in the current solve
-  sim_kernel_prof prof_acc[3] = {};
+  sim_kernel_prof prof_acc[4] = {};
+  int64_t prof_solves = 0;              // probed solves so far (alternate the two forms)
+  std::vector<hipEvent_t> prof_run_ev;  // iteration form: before iteration 0, after each
+  int32_t prof_run_n = 0;               // iterations recorded in the current solve
   // learned preconditioner
   bool learned = false;      // precond == SIM_PC_LEARNED
   MpPtrs mp{};
@@ -84,6 +87,7 @@ struct sim_t {
   int32_t mp_adam_t = 0;
   int32_t learned_maxit = 0;  // 0: cg_maxit
   bool system_valid = false; // A, b, x of a successful solve are in place
+  bool er_built = false;     // the last build wrote er (the network's edge input)
   // whole steps replayed as HIP graphs (sim_graph_mode)
   struct StepGraph {
     hipGraphExec_t exec;
@@ -119,8 +123,15 @@ struct sim_t {
   sim_tuning tune{};
 };
 
-static const int kProfKernels = 3;
-static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_apply"};
+// The probe's records: three CG kernels (every prof_every-th iteration of a
+// probed solve bracketed launch by launch) and the CG iteration as a whole
+// (in every other probed solve, one event pair around a run of whole
+// iterations of the first chunk: every kernel, the finisher and the gaps
+// between launches), priced at the solve's algorithmic bytes per iteration.
+static const int kProfKernels = 4;
+static const int kProfIteration = 3;
+static const char* kProfNames[kProfKernels] = {"k_cg_vec", "k_cg_spmv", "k_cg_apply",
+                                               "cg_iteration"};
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -318,6 +329,8 @@ static int ensure_mp(sim_t* s, bool training) {
     HIPCHK(hipMemset(m.grad, 0, sizeof(float) * MP_NPARAMS));
     m.rows = s->rows;
     m.round_act = 1;
+    m.lam_floor = MP_EPS_LAM;
+    m.s_clamp = 0.0;
     s->mp_ready = true;
   }
   if (s->mp_nnz_cap != s->d.nnz_cap) {
@@ -350,6 +363,7 @@ static int ensure_mp(sim_t* s, bool training) {
   }
 #undef MPALLOC
   m.er = s->d.er;
+  s->d.want_er = 1;  // later builds write the network's edge input
   s->d.mdiag = m.mdiag;
   s->d.moff = m.moff;
   return SIM_OK;
@@ -380,6 +394,7 @@ static int build_system(sim_t* s) {
   HIPCHK(launch_nbr_list(d, s->nbr_slots, st));
   if (s->block) HIPCHK(launch_pair_block(d, s->bp, st));
   else HIPCHK(launch_pair_terms(d, st));
+  s->er_built = d.want_er != 0;
   return SIM_OK;
 }
 
@@ -489,9 +504,19 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
   const DevPtrs& d = s->d;
   hipStream_t stream = s->stream;
   const bool ext = d.learned || d.ic0;  // a separate preconditioner pass
+  // iteration form of the probe: an event before iteration 0 of the first
+  // chunk and one after each of its iterations; the poll keeps the longest
+  // run of iterations that every component went through
+  const bool run_form = probes && s->prof_every > 0 && (s->prof_solves & 1) && first == 0 &&
+                        n + 1 <= (int)s->prof_run_ev.size();
+  if (run_form) {
+    s->prof_run_n = n;
+    HIPCHK(hipEventRecord(s->prof_run_ev[0], stream));
+  }
   for (int k = 0; k < n; ++k) {
     const int g = first + k;
-    const bool probe = probes && s->prof_every > 0 && g % s->prof_every == s->prof_phase &&
+    const bool probe = probes && !(s->prof_solves & 1) && s->prof_every > 0 &&
+                       g % s->prof_every == s->prof_phase &&
                        (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
     // vector update, then (learned) u = M^-1 r, then w = A u
     const int order[3] = {0, 2, 1};
@@ -513,6 +538,7 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
       }
     }
     HIPCHK(launch_cg_finish(d, 2, stream));
+    if (run_form) HIPCHK(hipEventRecord(s->prof_run_ev[k + 1], stream));
   }
   HIPCHK(launch_cg_spmv(d, 1, 0, stream));
   HIPCHK(launch_cg_finish(d, 3, stream));
@@ -569,6 +595,7 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
   }
   if (status == SIM_EOVERFLOW_INTERNAL || status == SIM_ESTALL_INTERNAL) {
     s->prof_pending.clear();
+    s->prof_run_n = 0;
     return status;
   }
   int itmax = 0, restarts = 0, breakdown = 0;
@@ -586,7 +613,7 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
     breakdown |= c.breakdown;
   }
   s->last_iters = itmax;
-  if (!s->prof_pending.empty()) {
+  if (!s->prof_pending.empty() || s->prof_run_n > 0) {
     // keep launches in which every component of every replica iterated
     int itmin = INT32_MAX;
     for (int r = 0; r < s->R; ++r)
@@ -603,11 +630,36 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
         // learned apply: row pointers (4), r (24), M^-1 diagonal (8), u written (24),
         // column + FP32 value per entry
         rows * 60.0 + 4.0 + nnz * 8.0 + ntile * 3.0 * 8.0};
+    // one CG iteration's algorithmic bytes over the real particles N with
+    // nnz off-diagonal entries (k = nnz / N per row): the matrix 12(k + 1) + 4
+    // (value 8 + column 4 per entry, the diagonal as one more entry, a row
+    // pointer 4; values 4 bytes with the FP32 product) and 200 vector bytes
+    // per row (p read 24, q written and read 48, x and r read and written
+    // 96, 1/diag 8, p written 24); the learned form adds one matrix pass for
+    // its M^-1 product
+    double npart = 0.0;
+    for (const RepDev& R : s->reph) npart += (double)R.n;
+    const double vb = s->d.spmv_fp32 ? 8.0 : 12.0;
+    const double mat = vb * (nnz + npart) + 4.0 * npart;
+    const double per_iter = mat + 200.0 * npart + (learned ? 12.0 * (nnz + npart) + 4.0 * npart : 0.0);
+    if (s->prof_run_n > 0) {
+      // iterations 0 .. m-1, which every component went through in full
+      const int m = itmin == INT32_MAX ? 0 : std::min(s->prof_run_n, itmin - 1);
+      if (m >= 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->prof_run_ev[0], s->prof_run_ev[m]));
+        sim_kernel_prof& acc = s->prof_acc[kProfIteration];
+        acc.launches += m;
+        acc.ms += ms;
+        acc.bytes += per_iter * m;
+      }
+      s->prof_run_n = 0;
+    }
     for (auto& smp : s->prof_pending) {
       float ms = 0.0f;
       HIPCHK(hipEventElapsedTime(&ms, s->prof_ev[2 * smp.ev], s->prof_ev[2 * smp.ev + 1]));
-      if (smp.iter >= itmin - 1) continue;
       sim_kernel_prof& acc = s->prof_acc[smp.kernel];
+      if (smp.iter >= itmin - 1) continue;
       acc.launches += 1;
       acc.ms += ms;
       acc.bytes += per_launch[smp.kernel];
@@ -615,7 +667,7 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
     s->prof_pending.clear();
     // the next solve samples the next residue, so that every position in a
     // solve is sampled alike (its first iterations run with colder caches)
-    s->prof_phase = (s->prof_phase + 1) % s->prof_every;
+    if (!(s->prof_solves & 1)) s->prof_phase = (s->prof_phase + 1) % s->prof_every;
   }
   if (st) {
     for (int k = 0; k < 3; ++k) {
@@ -692,7 +744,9 @@ static int cg_solve(sim_t* s, double tol, bool warm, sim_stats* st) {
   if (rc) return rc;
   const int n = std::max(1, std::min(s->last_iters > 2 ? s->last_iters - 1 : 8, cg_maxit(s) + 1));
   if ((rc = cg_queue_chunk(s, n, 0, true))) return rc;
-  return cg_poll_loop(s, n, st, nullptr);
+  rc = cg_poll_loop(s, n, st, nullptr);
+  if (s->prof_every > 0) s->prof_solves += 1;  // the probe alternates its two forms
+  return rc;
 }
 
 static int build_and_solve(sim_t* s, bool replace_rhs, double tol, sim_stats* st) {
@@ -760,6 +814,7 @@ void sim_destroy(sim_t* s) {
   if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
   for (void* p : s->allocs) (void)hipFree(p);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->prof_run_ev) (void)hipEventDestroy(e);
   if (s->ctrl_h) (void)hipHostFree(s->ctrl_h);
   if (s->cg_h) (void)hipHostFree(s->cg_h);
   if (s->bcg_h) (void)hipHostFree(s->bcg_h);
@@ -849,6 +904,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   d.rows = s->rows;
   d.nblk = blk_off;
   d.finish_threads = 64;
+  d.want_er = s->learned ? 1 : 0;
   for (int r = 0; r < replicas; ++r)
     d.finish_threads = std::max(d.finish_threads, finish_threads_for(s->reph[r].nblk));
   d.nrep = replicas;
@@ -1053,12 +1109,15 @@ int sim_graph_info(sim_t* s, int64_t* captures, int64_t* replays) {
 static bool valid_variant(int32_t v) { return v >= 0 && v < CSR_VARIANTS; }
 
 int sim_set_tuning(sim_t* s, const sim_tuning* t) {
-  if (!s || !t || !valid_variant(t->spmv_variant) || !valid_variant(t->apply_variant))
+  if (!s || !t || !valid_variant(t->spmv_variant) || !valid_variant(t->apply_variant) ||
+      (t->vec_variant != 0 && t->vec_variant != 1))
     return SIM_EINVAL;
   s->tune.spmv_variant = t->spmv_variant;
   s->tune.apply_variant = t->apply_variant;
+  s->tune.vec_variant = t->vec_variant;
   s->d.spmv_var = t->spmv_variant;
   s->d.apply_var = t->apply_variant;
+  s->d.vec_nt = t->vec_variant;
   drop_graphs(s);
   return SIM_OK;
 }
@@ -1109,12 +1168,26 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
     if (kind == 0) t.spmv_variant = pick;
     else t.apply_variant = pick;
   }
+  // the vector kernel with ordinary and with nontemporal accesses (its
+  // iteration form; the values it leaves do not matter here)
+  for (int v = 0; v < 2 && err == hipSuccess; ++v) {
+    d.vec_nt = v;
+    if ((err = launch_cg_vec(d, 2, s->stream))) break;  // untimed warm-up
+    if ((err = hipEventRecord(e0, s->stream))) break;
+    for (int k = 0; k < reps && err == hipSuccess; ++k) err = launch_cg_vec(d, 2, s->stream);
+    if (err || (err = hipEventRecord(e1, s->stream)) || (err = hipEventSynchronize(e1))) break;
+    float ms = 0.0f;
+    if ((err = hipEventElapsedTime(&ms, e0, e1))) break;
+    t.vec_us[v] = 1000.0f * ms / (float)reps;
+  }
+  t.vec_variant = t.vec_us[1] < t.vec_us[0] ? 1 : 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   d.learned = 0;
   if (err != hipSuccess) {
     d.spmv_var = s->tune.spmv_variant;
     d.apply_var = s->tune.apply_variant;
+    d.vec_nt = s->tune.vec_variant;
     sim_note_error(err, "autotune", __LINE__);
     return SIM_EDEVICE;
   }
@@ -1122,6 +1195,7 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
   s->tune = t;
   d.spmv_var = t.spmv_variant;
   d.apply_var = t.apply_variant;
+  d.vec_nt = t.vec_variant;
   drop_graphs(s);
   if (out) *out = t;
   return SIM_OK;
@@ -1155,6 +1229,18 @@ int sim_precond_config(sim_t* s, int32_t round_act, int32_t learned_maxit) {
   return SIM_OK;
 }
 
+int sim_precond_floor(sim_t* s, double lam_floor, double s_clamp) {
+  if (!s || !(lam_floor >= 0.0) || !std::isfinite(lam_floor) || !(s_clamp >= 0.0) ||
+      !std::isfinite(s_clamp))
+    return SIM_EINVAL;
+  if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
+  int rc = ensure_mp(s, false);
+  if (rc) return rc;
+  s->mp.lam_floor = lam_floor;
+  s->mp.s_clamp = s_clamp;
+  return SIM_OK;
+}
+
 int sim_load_precond(sim_t* s, const char* path) {
   if (!s || !path) return SIM_EINVAL;
   FILE* f = std::fopen(path, "rb");
@@ -1170,10 +1256,20 @@ int sim_load_precond(sim_t* s, const char* path) {
   return sim_precond_weights(s, th.data(), MP_NPARAMS, 1);
 }
 
+// training on a system built before the handle had network buffers: the
+// pair terms did not write the edge input then
+static int no_edge_input() {
+  snprintf(g_last_error, sizeof(g_last_error),
+           "the system was built before any preconditioner call on this handle: set the "
+           "weights (or configure the network) before the step or solve that training uses");
+  return SIM_EINVAL;
+}
+
 int sim_train_step(sim_t* s, double lr, double* loss) {
   if (!s || !(lr >= 0.0)) return SIM_EINVAL;
   if (s->R != 1 || s->block) return SIM_ENOTSUP;  // the network reads the scalar system
   if (!s->system_valid) return SIM_EINVAL;
+  if (!s->er_built) return no_edge_input();
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, true);
   if (rc) return rc;
@@ -1194,6 +1290,7 @@ int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t 
   if (!s || !(lr >= 0.0) || (euclid != 0 && euclid != 1)) return SIM_EINVAL;
   if (s->block) return SIM_ENOTSUP;  // the network reads the scalar system
   if (!s->system_valid) return SIM_EINVAL;
+  if (!s->er_built) return no_edge_input();
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, true);
   if (rc) return rc;
@@ -1592,9 +1689,13 @@ int sim_profile_enable(sim_t* s, int32_t sample_every) {
     // invalidation) when they complete, which would lengthen and perturb
     // the bracketed kernel; they are read after the solve's own sync
     for (auto& e : s->prof_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    s->prof_run_ev.resize(1025);
+    for (auto& e : s->prof_run_ev)
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   s->prof_every = sample_every;
   s->prof_phase = 0;
+  s->prof_solves = 0;
   return SIM_OK;
 }
 

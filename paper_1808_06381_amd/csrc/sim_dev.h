@@ -133,6 +133,8 @@ struct DevPtrs {
   int32_t ic0;              // 1: u = M^-1 r by the IC(0) triangular solves
   int32_t pc_none;          // 1: no preconditioner, u = r
   int32_t finish_threads;   // block size of the per-replica CG finisher
+  int32_t want_er;          // 1: the pair terms write er (the network's edge input)
+  int32_t vec_nt;           // 1: the CG vector kernel streams with nontemporal accesses
 };
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
 

@@ -29,7 +29,7 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
             "sim_copy_probe", "sim_event_probe", "sim_structure_factor",
             "sim_structure_factor_noalloc",
             "sim_velocity_correlation", "sim_precond_weights",
-            "sim_precond_config", "sim_train_step",
+            "sim_precond_config", "sim_precond_floor", "sim_train_step",
             "sim_precond_grad", "sim_debug_precond", "sim_graph_mode", "sim_graph_info",
             "sim_autotune", "sim_set_tuning", "sim_train_probe", "sim_precond_optimizer",
             "sim_destroy", "sim_strerror"]
@@ -44,11 +44,13 @@ CSR_VARIANTS = [(1, 0), (2, 0), (4, 0), (8, 0), (2, 2), (4, 1), (4, 2), (4, 3)]
 class SimTuning(C.Structure):
     _fields_ = [("spmv_variant", C.c_int32), ("apply_variant", C.c_int32),
                 ("spmv_us", C.c_float * len(CSR_VARIANTS)),
-                ("apply_us", C.c_float * len(CSR_VARIANTS))]
+                ("apply_us", C.c_float * len(CSR_VARIANTS)),
+                ("vec_variant", C.c_int32), ("vec_us", C.c_float * 2)]
 
     def as_dict(self):
         return dict(spmv_variant=self.spmv_variant, apply_variant=self.apply_variant,
-                    spmv_us=list(self.spmv_us), apply_us=list(self.apply_us))
+                    spmv_us=list(self.spmv_us), apply_us=list(self.apply_us),
+                    vec_variant=self.vec_variant, vec_us=list(self.vec_us))
 
 
 class SimParams(C.Structure):
@@ -159,6 +161,7 @@ def lib():
                                       P(C.c_double)]
         L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
         L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sim_precond_floor.argtypes = [vp, C.c_double, C.c_double]
         L.sim_graph_mode.argtypes = [vp, C.c_int32]
         L.sim_train_probe.argtypes = [vp, C.c_double, C.c_uint64, C.c_uint64, C.c_int32,
                                       P(C.c_double)]
@@ -441,10 +444,12 @@ class Sim:
         _check(lib().sim_autotune(self.h, int(reps), C.byref(t)), "sim_autotune")
         return t.as_dict()
 
-    def set_tuning(self, spmv_variant=6, apply_variant=6):
-        """Fix the CSR product variants (indices into CSR_VARIANTS)."""
+    def set_tuning(self, spmv_variant=6, apply_variant=6, vec_variant=0):
+        """Fix the CSR product variants (indices into CSR_VARIANTS) and the
+        vector kernel's form (0 ordinary, 1 nontemporal accesses)."""
         t = SimTuning()
         t.spmv_variant, t.apply_variant = int(spmv_variant), int(apply_variant)
+        t.vec_variant = int(vec_variant)
         _check(lib().sim_set_tuning(self.h, C.byref(t)), "sim_set_tuning")
 
     def set_weights(self, theta):
@@ -459,6 +464,12 @@ class Sim:
     def precond_config(self, round_act=True, learned_maxit=0):
         _check(lib().sim_precond_config(self.h, int(bool(round_act)), int(learned_maxit)),
                "sim_precond_config")
+
+    def precond_floor(self, lam_floor=0.1, s_clamp=0.0):
+        """Floor added to the learned diagonal head (default 0.1) and the
+        inference clamp |S_ij| <= s_clamp sqrt(lam_i lam_j) (0: off)."""
+        _check(lib().sim_precond_floor(self.h, float(lam_floor), float(s_clamp)),
+               "sim_precond_floor")
 
     def train_step(self, lr):
         loss = C.c_double()

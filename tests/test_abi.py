@@ -35,7 +35,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(S.SimParams) == 8 + 11 * 8 + 8 * 4 + 8 + 16 + 16
     assert C.sizeof(S.SimStats) == 3 * 4 + 4 + 3 * 8 + 8 + 4 + 4 + 8 + 8
     assert C.sizeof(S.SimMeta) == 8 + 8 + 8 + 4 + 4 + 8
-    assert C.sizeof(S.SimTuning) == 2 * 4 + 2 * len(S.CSR_VARIANTS) * 4
+    assert C.sizeof(S.SimTuning) == 2 * 4 + 2 * len(S.CSR_VARIANTS) * 4 + 4 + 2 * 4
 
 
 def test_strerror():
