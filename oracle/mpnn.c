@@ -17,7 +17,7 @@
  *   h0_i = relu(W0 x_i + b0)
  *   layer l:  y_j = P_l h_j;   m_i = (1/8) sum_j relu(y_j + Q_l e_ij + c_l)
  *             h_i <- h_i + relu(U_l h_i + V_l m_i + d_l)
- *   heads:    lam_i = softplus(v . h_i + v0) + eps              (eps = 0.1)
+ *   heads:    lam_i = softplus(v . h_i + v0) + eps              (eps = 0.3)
  *             S_ij  = z . (h_i * h_j) + ze . e_ij + z0          (symmetric)
  * Preconditioner:
  *   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2:  mdiag_i = lam_i / D_i,
@@ -44,7 +44,7 @@
 #define FN 3
 #define FE 3
 #define NL 3
-#define EPS_LAM 0.1
+#define EPS_LAM 0.3
 #define MSG_SCALE 0.125
 
 /* parameter offsets (floats) */

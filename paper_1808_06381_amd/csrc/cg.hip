@@ -10,12 +10,12 @@
 //
 // Per iteration three launches, none with a cache write-back fence:
 //   k_cg_vec   every vector update, element-parallel (fully coalesced), and
-//              the partial sums of (r, u) and (r, r) per tile;
+//              the partial sums of (r, u) and (r, r) per sub-tile of 256 rows;
 //   k_cg_spmv  w = A u with a group of 1, 2, 4 or 8 lanes per CSR row (4
 //              unless the autotuner picked another), so the neighbours of a
 //              row -- contiguous runs of the cell-sorted order -- are fetched
 //              by adjacent lanes; partial sums of (w, u);
-//   k_cg_finish one block per replica: the tile partials in a fixed order,
+//   k_cg_finish one block per replica: the sub-tile partials in a fixed order,
 //              then the scalar recurrences and the convergence state.
 // Sums are deterministic (fixed trees, no floating-point atomics).
 #include "sim_dev.h"
@@ -23,7 +23,7 @@
 
 #include <hip/hip_ext.h>
 
-#define VEC_ELEMS (3 * ROWS_PER_BLOCK)  // elements (row, component) per tile
+#define VEC_ELEMS (3 * SUB_ROWS)  // elements (row, component) per sub-tile
 
 // sum over the LANES lanes of a row's group, on registers (DPP): lanes
 // exchange with lane ^ 1, then lane ^ 2 (quad permutes), then, for 8 lanes,
@@ -72,11 +72,12 @@ __device__ __forceinline__ void turns_to_components(const double (&vt)[TURNS<LAN
   }
 }
 
-// tile partial sums: [gamma0..2, delta0..2, rr0..2]; `first`..`first+n` written
+// sub-tile partial sums: [gamma0..2, delta0..2, rr0..2]; `first`..`first+n`
+// written (blocks of SUB_THREADS threads)
 template <int N>
-__device__ __forceinline__ void write_partials(const DevPtrs& d, int tile, int first,
+__device__ __forceinline__ void write_partials(const DevPtrs& d, int sub, int first,
                                                double (&v)[N]) {
-  __shared__ double lds[BLOCK_THREADS / 64][9];
+  __shared__ double lds[SUB_THREADS / 64][9];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
@@ -87,9 +88,16 @@ __device__ __forceinline__ void write_partials(const DevPtrs& d, int tile, int f
   __syncthreads();
   if (threadIdx.x < N) {
     double s = 0.0;
-    for (int w = 0; w < BLOCK_THREADS / 64; ++w) s += lds[w][threadIdx.x];
-    d.partial[(int64_t)tile * NPART + first + threadIdx.x] = s;
+    for (int w = 0; w < SUB_THREADS / 64; ++w) s += lds[w][threadIdx.x];
+    d.partial[(int64_t)sub * NPART + first + threadIdx.x] = s;
   }
+}
+
+// XCD-contiguous sub-tile of this block (or -1 past the end) and its tile
+__device__ __forceinline__ int sub_of_block(const DevPtrs& d) {
+  const int nsub = SUBS_PER_TILE * d.nblk;
+  const int sub = xcd_block(blockIdx.x, nsub);
+  return sub < nsub ? sub : -1;
 }
 
 __global__ void k_cg_reset(DevPtrs d, double tol_override) {
@@ -125,8 +133,8 @@ __device__ __forceinline__ void stv(T* p, T v) {
   else *p = v;
 }
 
-// Element-parallel vector work of one tile (3 * 1024 consecutive doubles of
-// the AoS arrays; element e is row e/3, component e%3).  NT: the streams
+// Element-parallel vector work of one sub-tile (3 * 256 consecutive doubles
+// of the AoS arrays; element e is row e/3, component e%3).  NT: the streams
 // that are not read again within the iteration (r, p, w, s, x, 1/diag) are
 // loaded and stored as nontemporal, u (gathered by the product next) as
 // usual: on a working set larger than the last-level cache this streams
@@ -138,10 +146,10 @@ __device__ __forceinline__ void stv(T* p, T v) {
 //                           r -= alpha s, u = M^-1 r
 // Partials (r, u) and (r, r) of the components touched.
 template <bool NT>
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const int rid = d.blk_rep[tile];
+__global__ __launch_bounds__(SUB_THREADS) void k_cg_vec(DevPtrs d, int mode) {
+  const int sub = sub_of_block(d);
+  if (sub < 0) return;
+  const int rid = d.blk_rep[sub / SUBS_PER_TILE];
   const CgRep& cr = d.cg[rid];
   if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
   bool on[3];
@@ -153,17 +161,17 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
     be[k] = cr.beta[k];
   }
   double v[6] = {0, 0, 0, 0, 0, 0};  // (r,u)[3], (r,r)[3]
-  const int64_t base = (int64_t)tile * VEC_ELEMS;
+  const int64_t base = (int64_t)sub * VEC_ELEMS;
   const bool ext = d.learned || d.ic0;  // u = M^-1 r comes from a separate pass
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int le = q * BLOCK_THREADS + threadIdx.x;
+    const int le = q * SUB_THREADS + threadIdx.x;
     const int k = le % 3;
     if (!on[k]) continue;
     const int64_t e = base + le;
     // 1/diag only where this kernel applies Jacobi itself
     const double di =
-        (ext || d.pc_none) ? 1.0 : ldv<NT>(d.dinv + (int64_t)tile * ROWS_PER_BLOCK + le / 3);
+        (ext || d.pc_none) ? 1.0 : ldv<NT>(d.dinv + (int64_t)sub * SUB_ROWS + le / 3);
     double rk;
     if (mode == 0) {
       rk = d.b[e];
@@ -195,28 +203,28 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   }
   double g[3] = {v[0], v[1], v[2]}, rr[3] = {v[3], v[4], v[5]};
   if (!ext) {
-    write_partials<3>(d, tile, 0, g);
+    write_partials<3>(d, sub, 0, g);
     __syncthreads();
   }
-  write_partials<3>(d, tile, 6, rr);
+  write_partials<3>(d, sub, 6, rr);
 }
 
-// Partials (r, u) per tile after an external preconditioner pass (IC(0)),
+// Partials (r, u) per sub-tile after an external preconditioner pass (IC(0)),
 // component selection as k_cg_vec's mode.
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const CgRep& cr = d.cg[d.blk_rep[tile]];
+__global__ __launch_bounds__(SUB_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) {
+  const int sub = sub_of_block(d);
+  if (sub < 0) return;
+  const CgRep& cr = d.cg[d.blk_rep[sub / SUBS_PER_TILE]];
   if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
   bool on[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
   double v[3] = {0, 0, 0};
-  const int64_t base = (int64_t)tile * VEC_ELEMS;
+  const int64_t base = (int64_t)sub * VEC_ELEMS;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int le = q * BLOCK_THREADS + threadIdx.x;
+    const int le = q * SUB_THREADS + threadIdx.x;
     const int k = le % 3;
     if (!on_k(on, k)) continue;
     const double add = d.r[base + le] * d.u[base + le];
@@ -224,11 +232,12 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_dot_ru(DevPtrs d, int mode
     v[1] += k == 1 ? add : 0.0;
     v[2] += k == 2 ? add : 0.0;
   }
-  write_partials<3>(d, tile, 0, v);
+  write_partials<3>(d, sub, 0, v);
 }
 
-// Products sum_j M_ij src_j (three components) of the tile's 1024 rows with
-// a group of LANES lanes per row, LANES passes over 1024 / LANES rows each.
+// Products sum_j M_ij src_j (three components) of the sub-tile's 256 rows
+// with a group of LANES lanes per row, LANES passes over 256 / LANES rows
+// each.
 // Lane l of a group takes the row's entries l, l + LANES, l + 2 LANES, ...,
 // adds them in that order, then the group adds its lanes; both forms below
 // therefore give the same bits.
@@ -246,10 +255,10 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_dot_ru(DevPtrs d, int mode
 // t, src_ik, own) receives own = dg_i src_ik + sum_j M_ij src_jk for the
 // components finished by this lane (component k = t * LANES + lane, turn t).
 template <int LANES, int ENT, class Val, class Epi>
-__device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const double* __restrict__ src,
+__device__ __forceinline__ void csr_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
                                          const double* __restrict__ dg, Val val, Epi epi) {
-  constexpr int GROUPS = BLOCK_THREADS / LANES;
-  constexpr int PASSES = ROWS_PER_BLOCK / GROUPS;
+  constexpr int GROUPS = SUB_THREADS / LANES;
+  constexpr int PASSES = SUB_ROWS / GROUPS;
   constexpr int T = TURNS<LANES>;
   const int lane = threadIdx.x & (LANES - 1);
   const int grp = threadIdx.x / LANES;
@@ -258,7 +267,7 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const doubl
   const int cap = (int)d.nnz_cap;
   if constexpr (ENT == 0) {
     for (int pass = 0; pass < PASSES; ++pass) {
-      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + pass * GROUPS + grp;
+      const int64_t i = (int64_t)sub * SUB_ROWS + pass * GROUPS + grp;
       const int e0 = min(d.rowptr[i], cap), e1 = min(d.rowptr[i + 1], cap);
       double a[3] = {0.0, 0.0, 0.0};
       for (int e = e0 + lane; e < e1; e += LANES) {
@@ -282,7 +291,7 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const doubl
     double dv[PASSES], sv[PASSES][T];
 #pragma unroll
     for (int p = 0; p < PASSES; ++p) {
-      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + p * GROUPS + grp;
+      const int64_t i = (int64_t)sub * SUB_ROWS + p * GROUPS + grp;
       e0[p] = min(d.rowptr[i], cap);
       e1[p] = min(d.rowptr[i + 1], cap);
       dv[p] = lane < 3 ? dg[i] : 0.0;
@@ -340,7 +349,7 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const doubl
         a[2] += mv * src[3 * j + 2];
       }
       lane_group_sum<LANES>(a);
-      const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + p * GROUPS + grp;
+      const int64_t i = (int64_t)sub * SUB_ROWS + p * GROUPS + grp;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int k = t * LANES + lane;
@@ -354,10 +363,10 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int tile, const doubl
 // Learned preconditioner: u = M^-1 r with M^-1 in A's pattern, partial
 // (r, u).  Same component selection as k_cg_vec's mode.
 template <int LANES, int ENT>
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const int rid = d.blk_rep[tile];
+__global__ __launch_bounds__(SUB_THREADS) void k_cg_apply(DevPtrs d, int mode) {
+  const int sub = sub_of_block(d);
+  if (sub < 0) return;
+  const int rid = d.blk_rep[sub / SUBS_PER_TILE];
   const CgRep& cr = d.cg[rid];
   if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
   bool on[3];
@@ -367,7 +376,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode)
   const float* __restrict__ moff = d.moff;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, tile, d.r, d.mdiag, [&](int e) { return (double)moff[e]; },
+      d, sub, d.r, d.mdiag, [&](int e) { return (double)moff[e]; },
       [&](int64_t i, int k, int t, double rk, double uk) {
         if (!on_k(on, k)) return;
         d.u[3 * i + k] = uk;
@@ -375,7 +384,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_apply(DevPtrs d, int mode)
       });
   double v[3] = {0, 0, 0};
   turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);
-  write_partials<3>(d, tile, 0, v);
+  write_partials<3>(d, sub, 0, v);
 }
 
 // Advance the recurrences of one replica from its totals
@@ -452,16 +461,17 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
   if (finished) atomicSub(&d.ctrl->n_notdone, finished);
 }
 
-// Sum the replica's tile partials in a fixed order (thread t takes tiles t,
-// t + nthr, ...; then the wave and block trees).  Totals valid in thread 0.
-__device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, double (&tot)[9]) {
-  __shared__ double lds[16][9];
+// Sum `count` partial slots starting at `first` in a fixed order (thread t
+// takes slots t, t + blockDim, ...; then the wave and block trees).  Totals
+// valid in thread 0.
+__device__ __forceinline__ void sum_slots(const double* __restrict__ first, int count,
+                                          double (&tot)[9]) {
+  __shared__ double lds[FINISH_THREADS / 64][9];
   double acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-  const int nthr = finish_threads_for(R.nblk);
-  for (int t = threadIdx.x; threadIdx.x < nthr && t < R.nblk; t += nthr) {
-    const double* src = d.partial + (int64_t)(R.blk_off + t) * NPART;
+  for (int t = threadIdx.x; t < count; t += blockDim.x) {
+    const double* src = first + (int64_t)t * NPART;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
       acc[k] += src[k];
@@ -483,7 +493,7 @@ __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, 
   }
 }
 
-// CSR product over the tile's 1024 rows.
+// CSR product over the sub-tile's 256 rows.
 //   mode 0: w = A u, partial (w, u)  (components iterating / restarting / fresh)
 //   mode 1: r = b - A x, partial (r, r)  (components whose check is pending)
 //   mode 2: r = b - A x, partial (r, r)  (iterating components: the residual
@@ -491,10 +501,10 @@ __device__ __forceinline__ void reduce_tiles(const DevPtrs& d, const RepDev& R, 
 // Lane k of a row's group finishes component k (coalesced stores); with
 // fewer than three lanes, lane l takes components l, l + LANES, ...
 template <bool FP32, int LANES, int ENT>
-__global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
-  const int tile = xcd_block(blockIdx.x, d.nblk);
-  if (tile >= d.nblk) return;
-  const int rid = d.blk_rep[tile];
+__global__ __launch_bounds__(SUB_THREADS) void k_cg_spmv(DevPtrs d, int mode, int start_mode) {
+  const int sub = sub_of_block(d);
+  if (sub < 0) return;
+  const int rid = d.blk_rep[sub / SUBS_PER_TILE];
   const CgRep& cr = d.cg[rid];
   bool on[3];
   if (mode == 0) {
@@ -517,7 +527,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
   const float* __restrict__ valf = d.valf;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, tile, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; },
+      d, sub, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; },
       [&](int64_t i, int k, int t, double sk, double own) {
         if (!on_k(on, k)) return;
         const int64_t e = 3 * i + k;
@@ -532,7 +542,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_spmv(DevPtrs d, int mode, 
       });
   double v[3] = {0, 0, 0};
   turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);
-  write_partials<3>(d, tile, mode == 0 ? 3 : 6, v);
+  write_partials<3>(d, sub, mode == 0 ? 3 : 6, v);
 }
 
 // Warm start: x = the previous step's velocity of each row's particle (kept
@@ -553,16 +563,42 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_cg_warm(DevPtrs d, const int6
     if (cr.state[k] == 0) d.x[3 * i + k] = d.vel_orig[3 * g + k];
 }
 
-// One block per replica: reduce the replica's tile partials and advance.
-__global__ __launch_bounds__(1024) void k_cg_finish(DevPtrs d, int mode) {
+__device__ __forceinline__ bool finish_work(const CgRep& c, int mode) {
+  return (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
+         (mode == 3 && c.check) || (mode == 4 && c.run);
+}
+
+// First level of a large replica's reduction: block b sums L1_SUBS of the
+// replica's sub-tile partials into partial2[b].
+__global__ __launch_bounds__(FINISH_THREADS) void k_cg_reduce1(DevPtrs d, int mode) {
+  const int b = blockIdx.x;
+  const int rid = d.l1_rep[b];
+  const RepDev& R = d.rep[rid];
+  if (!finish_work(d.cg[rid], mode)) return;
+  const int s0 = (b - R.l1_off) * L1_SUBS;
+  const int nsub = SUBS_PER_TILE * R.nblk;
+  const int cnt = nsub - s0 < L1_SUBS ? nsub - s0 : L1_SUBS;
+  double tot[9];
+  sum_slots(d.partial + (int64_t)(SUBS_PER_TILE * R.blk_off + s0) * NPART, cnt, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.partial2[(int64_t)b * NPART + k] = tot[k];
+  }
+}
+
+// One block per replica: its sub-tile partials (or, for a large replica,
+// the first-level sums) in a fixed order, then the recurrences.
+__global__ __launch_bounds__(FINISH_THREADS) void k_cg_finish(DevPtrs d, int mode) {
   const int rid = blockIdx.x;
   const RepDev& R = d.rep[rid];
   CgRep& c = d.cg[rid];
-  const bool work = (mode == 0) || (mode == 1 && c.restart) || (mode == 2 && c.run) ||
-                    (mode == 3 && c.check) || (mode == 4 && c.run);
-  if (!work) return;
+  if (!finish_work(c, mode)) return;
   double tot[9];
-  reduce_tiles(d, R, tot);
+  if (R.l1_cnt > 0)
+    sum_slots(d.partial2 + (int64_t)R.l1_off * NPART, R.l1_cnt, tot);
+  else
+    sum_slots(d.partial + (int64_t)(SUBS_PER_TILE * R.blk_off) * NPART, SUBS_PER_TILE * R.nblk,
+              tot);
   if (threadIdx.x == 0) cg_advance(d, c, mode, tot);
 }
 
@@ -587,16 +623,17 @@ hipError_t launch_cg_reset(const DevPtrs& d, double tol_override, hipStream_t s)
 // ev0/ev1 (optional) take the kernel's own start and end timestamps
 hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1) {
+  const dim3 g(xcd_grid(SUBS_PER_TILE * d.nblk)), b(SUB_THREADS);
   if (d.vec_nt && mode == 2)
-    LAUNCH_EV(k_cg_vec<true>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1, d, mode);
+    LAUNCH_EV(k_cg_vec<true>, g, b, s, ev0, ev1, d, mode);
   else
-    LAUNCH_EV(k_cg_vec<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), s, ev0, ev1, d, mode);
+    LAUNCH_EV(k_cg_vec<false>, g, b, s, ev0, ev1, d, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
-  const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
+  const dim3 g(xcd_grid(SUBS_PER_TILE * d.nblk)), b(SUB_THREADS);
   const bool f32 = d.spmv_fp32 && mode == 0;
   switch (d.spmv_var * 2 + (f32 ? 1 : 0)) {
 #define SPMV_CASE(V, L, E)                                                                  \
@@ -614,13 +651,14 @@ hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_
 }
 
 hipError_t launch_cg_dot_ru(const DevPtrs& d, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dot_ru, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, mode);
+  hipLaunchKernelGGL(k_cg_dot_ru, dim3(xcd_grid(SUBS_PER_TILE * d.nblk)), dim3(SUB_THREADS), 0, s,
+                     d, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
-  const dim3 g(xcd_grid(d.nblk)), b(BLOCK_THREADS);
+  const dim3 g(xcd_grid(SUBS_PER_TILE * d.nblk)), b(SUB_THREADS);
   switch (d.apply_var) {
 #define APPLY_CASE(V, L, E) \
     case V: LAUNCH_EV((k_cg_apply<L, E>), g, b, s, ev0, ev1, d, mode); break;
@@ -637,6 +675,8 @@ hipError_t launch_cg_warm(const DevPtrs& d, const int64_t* id_off, hipStream_t s
 }
 
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_finish, dim3(d.nrep), dim3(d.finish_threads), 0, s, d, mode);
+  if (d.l1_total > 0)
+    hipLaunchKernelGGL(k_cg_reduce1, dim3(d.l1_total), dim3(FINISH_THREADS), 0, s, d, mode);
+  hipLaunchKernelGGL(k_cg_finish, dim3(d.nrep), dim3(FINISH_THREADS), 0, s, d, mode);
   return hipGetLastError();
 }

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bin(DevPtrs d) {
     if (i - R.row_off >= R.n) continue;
     const double4 pp = d.pos[i];
     const int cx = cell_axis(pp.x, R, 0), cy = cell_axis(pp.y, R, 1), cz = cell_axis(pp.z, R, 2);
-    const int c = R.seg_off + (cz * R.nc[1] + cy) * R.nc[0] + cx;
+    const int c = R.seg_off + cell_key(R, cx, cy, cz);
     d.cellidx[i] = c;
     d.slot[i] = atomicAdd(&d.cell_count[c], 1);
   }

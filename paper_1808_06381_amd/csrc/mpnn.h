@@ -11,7 +11,7 @@
 #define MP_THREADS 256 // threads per block (8 nodes x 32 features)
 #define MP_ROWS 64     // rows per block
 #define MP_MSG 0.125f  // message scale
-#define MP_EPS_LAM 0.1 // default floor of the diagonal head lam
+#define MP_EPS_LAM 0.3 // default floor of the diagonal head lam
 
 #define MP_OFF_W0 0
 #define MP_OFF_B0 (MP_OFF_W0 + MP_H * MP_FN)
@@ -68,6 +68,5 @@ struct MpPtrs {
   int loss_euclid; // loss norm: 0 the A-norm, 1 the Euclidean norm
   int pad0;        // explicit: the host compares whole structs bytewise
   double lam_floor; // floor added to the diagonal head: lam = softplus(.) + lam_floor
-  double s_clamp;   // > 0: inference clamps |S_ij| to s_clamp * sqrt(lam_i lam_j)
 };
 static_assert(sizeof(MpPtrs) % 8 == 0, "MpPtrs must have no implicit tail padding");

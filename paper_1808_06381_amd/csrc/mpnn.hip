@@ -9,7 +9,8 @@
 //   h0 = relu(W0 x + b0)
 //   layer: y_j = P h_j, m_i = 1/8 sum_j relu(y_j + Q e_ij + c),
 //          h_i <- h_i + relu(U h_i + V m_i + d)
-//   heads: lam_i = softplus(v.h_i + v0) + 0.1, S_ij = z.(h_i*h_j) + ze.e_ij + z0
+//   heads: lam_i = softplus(v.h_i + v0) + floor (0.3 unless set),
+//          S_ij = z.(h_i*h_j) + ze.e_ij + z0
 //   M^-1 = D^-1/2 (diag(lam) + S) D^-1/2: symmetric, positive diagonal (the
 //   solver's true-residual test and Jacobi fallback cover a non-definite M^-1;
 //   the initial heads give the positive definite two-term Neumann series).
@@ -564,7 +565,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
   __shared__ double dg[MP_ROWS];
-  __shared__ double lam_s[MP_ROWS];
   __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
   const int t = threadIdx.x;
   const int ntiles = (int)(m.rows / MP_ROWS);
@@ -592,22 +592,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     hb8(i0 + n, v);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = v[kk];
-  }
-  __syncthreads();
-  // node head of a row from its bf16 h (this quad's 8 features), the same
-  // operations for a tile row and for a gathered neighbour
-  auto node_tau = [&](const float* hrow) {
-    float p = 0.0f;
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) p += hv[8 * q + kk] * hrow[kk];
-    p += __shfl_xor(p, 1, 64);
-    p += __shfl_xor(p, 2, 64);
-    return p + hv[MP_H];
-  };
-  const bool clamp = m.s_clamp > 0.0 && !m.store_train;
-  if (clamp) {
-    const float tau = node_tau(hi_s + n * MX_FS + 8 * q);
-    if (q == 0) lam_s[n] = (double)softplusf_(tau) + m.lam_floor;
   }
   __syncthreads();
   // no barrier below: the four lanes of a quad share every entry, so the
@@ -640,14 +624,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
 #pragma unroll
     for (int f = 0; f < MP_FE; ++f) tt += hze[f] * ef[f];
     tt += hze[MP_FE];
-    if (clamp) {
-      // |S_ij| <= s_clamp sqrt(lam_i lam_j): no 2 x 2 principal block of
-      // diag(lam) + S is indefinite (both ends compute the same bound)
-      const double lj = (double)softplusf_(node_tau(hj)) + m.lam_floor;
-      const double bound = m.s_clamp * sqrt(lam_s[r] * lj);
-      const double tv = (double)tt;
-      tt = (float)(tv > bound ? bound : (tv < -bound ? -bound : tv));
-    }
     if (q == 0) {
       m.moff[e] = (float)((double)tt / sqrt(dg[r] * dj));
       if (m.store_train) m.tg[e] = tt;

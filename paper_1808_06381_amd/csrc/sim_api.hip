@@ -225,9 +225,13 @@ static RepDev make_rep(const sim_params& p) {
     // keeps two colours per axis, 8 launches per triangular sweep, not 27
     if (p.precond == SIM_PC_IC0 && nc >= 5 && nc % 2 == 1) nc -= 1;
     R.nc[k] = nc;
+    R.brick = std::max(R.brick, nc);
     R.cell_len[k] = p.box[k] / (double)nc;
     R.inv_cell[k] = (double)nc / p.box[k];
   }
+  // bricks of 8^3 cells for boxes of 32 or more cells per axis (the IC(0)
+  // form keeps the z-major order its colour lists are built in)
+  if (p.precond != SIM_PC_IC0 && R.nc[0] >= 32 && R.nc[1] >= 32 && R.nc[2] >= 32) R.brick = 8;
   R.n = (int32_t)p.n;
   R.kT = p.kT;
   R.gamma0 = p.gamma0;
@@ -330,7 +334,6 @@ static int ensure_mp(sim_t* s, bool training) {
     m.rows = s->rows;
     m.round_act = 1;
     m.lam_floor = MP_EPS_LAM;
-    m.s_clamp = 0.0;
     s->mp_ready = true;
   }
   if (s->mp_nnz_cap != s->d.nnz_cap) {
@@ -620,7 +623,7 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
       for (int k = 0; k < 3; ++k)
         if (s->cg_h[r].bb[k] > 0.0) itmin = std::min(itmin, s->cg_h[r].it[k]);
     const double rows = (double)s->rows, nnz = (double)s->ctrl_h->nnz;
-    const double ntile = (double)d.nblk;
+    const double ntile = (double)(SUBS_PER_TILE * d.nblk);  // partial slots written
     const double per_launch[kProfKernels] = {
         // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written
         // (120); with the learned preconditioner u is read instead of 1/diag and not written
@@ -903,10 +906,17 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   DevPtrs& d = s->d;
   d.rows = s->rows;
   d.nblk = blk_off;
-  d.finish_threads = 64;
   d.want_er = s->learned ? 1 : 0;
-  for (int r = 0; r < replicas; ++r)
-    d.finish_threads = std::max(d.finish_threads, finish_threads_for(s->reph[r].nblk));
+  // two-level reduction of the CG partials for replicas of many sub-tiles
+  std::vector<int32_t> l1_rep_h;
+  for (int r = 0; r < replicas; ++r) {
+    RepDev& R = s->reph[r];
+    const int nsub = SUBS_PER_TILE * R.nblk;
+    R.l1_off = (int32_t)l1_rep_h.size();
+    R.l1_cnt = nsub > L1_MIN_SUBS ? (nsub + L1_SUBS - 1) / L1_SUBS : 0;
+    for (int b = 0; b < R.l1_cnt; ++b) l1_rep_h.push_back(r);
+  }
+  d.l1_total = (int32_t)l1_rep_h.size();
   d.nrep = replicas;
   d.ncell_entries = (int32_t)seg_off;
   d.spmv_fp32 = params[0].spmv_fp32;
@@ -936,7 +946,11 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   int32_t* blk_rep_d = nullptr;
   ALLOC(blk_rep_d, sizeof(int32_t) * d.nblk);
   d.blk_rep = blk_rep_d;
-  ALLOC(d.partial, sizeof(double) * NPART * d.nblk);
+  ALLOC(d.partial, sizeof(double) * NPART * SUBS_PER_TILE * d.nblk);
+  ALLOC(d.partial2, sizeof(double) * NPART * std::max(d.l1_total, 1));
+  int32_t* l1_rep_d = nullptr;
+  ALLOC(l1_rep_d, sizeof(int32_t) * std::max<size_t>(l1_rep_h.size(), 1));
+  d.l1_rep = l1_rep_d;
   ALLOC(d.pos, sizeof(double4) * rows);
   ALLOC(d.pos_alt, sizeof(double4) * rows);
   ALLOC(d.cellidx, sizeof(int32_t) * rows);
@@ -973,8 +987,9 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
       for (int c = 0; c < nx * ny * nz; ++c) {
         const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
         const int col = axc(cx, nx) + 3 * (axc(cy, ny) + 3 * axc(cz, nz));
-        ccolor_h[(size_t)(R.seg_off + c)] = col;
-        by_color[col].push_back(R.seg_off + c);
+        const int key = R.seg_off + cell_key(R, cx, cy, cz);
+        ccolor_h[(size_t)key] = col;
+        by_color[col].push_back(key);
       }
     }
     s->ic_color_off.assign(1, 0);
@@ -1027,6 +1042,10 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
     return fail(e, "upload replicas");
   if ((e = hipMemcpy(blk_rep_d, s->blk_rep_h.data(), sizeof(int32_t) * d.nblk, hipMemcpyHostToDevice)))
     return fail(e, "upload block table");
+  if (!l1_rep_h.empty() &&
+      (e = hipMemcpy(l1_rep_d, l1_rep_h.data(), sizeof(int32_t) * l1_rep_h.size(),
+                     hipMemcpyHostToDevice)))
+    return fail(e, "upload reduction table");
   if (s->block) {
     std::vector<BlockRep> br((size_t)replicas);
     for (int r = 0; r < replicas; ++r) {
@@ -1229,15 +1248,12 @@ int sim_precond_config(sim_t* s, int32_t round_act, int32_t learned_maxit) {
   return SIM_OK;
 }
 
-int sim_precond_floor(sim_t* s, double lam_floor, double s_clamp) {
-  if (!s || !(lam_floor >= 0.0) || !std::isfinite(lam_floor) || !(s_clamp >= 0.0) ||
-      !std::isfinite(s_clamp))
-    return SIM_EINVAL;
+int sim_precond_floor(sim_t* s, double lam_floor) {
+  if (!s || !(lam_floor >= 0.0) || !std::isfinite(lam_floor)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, false);
   if (rc) return rc;
   s->mp.lam_floor = lam_floor;
-  s->mp.s_clamp = s_clamp;
   return SIM_OK;
 }
 

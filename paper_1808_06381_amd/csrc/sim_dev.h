@@ -16,7 +16,14 @@
 
 #define ROWS_PER_BLOCK 1024
 #define BLOCK_THREADS 1024
-#define NPART 16  // doubles per tile partial slot (9 used)
+#define NPART 16  // doubles per partial slot (9 used)
+// The CG kernels work on sub-tiles of SUB_ROWS rows with SUB_THREADS threads
+// and leave one partial slot per sub-tile: blocks of four waves wait less at
+// their closing reduction than blocks of sixteen (measured on the CSR product
+// at N = 8e6: 386 -> 332 us)
+#define SUB_ROWS 256
+#define SUB_THREADS 256
+#define SUBS_PER_TILE (ROWS_PER_BLOCK / SUB_ROWS)
 
 // ---------------------------------------------------------------------------
 // Per-replica constants (device copy built at creation)
@@ -39,8 +46,28 @@ struct RepDev {
   double force_soft;          // 2*u_amp/rc (soft)
   double tol2;                // cg_tol^2
   int32_t weight_law, potential, noise_mode, precond;
+  int32_t brick;              // brick edge of the cell order, in cells (>= every nc: z-major)
+  int32_t l1_cnt;             // first-level reduction blocks of the CG partials (0: none)
+  int32_t l1_off;             // the first of them
+  int32_t pad0;
   uint64_t seed, stream;
 };
+
+// Cell order.  Cells are numbered brick by brick: bricks of brick^3 cells
+// (smaller at the high end of an axis) in z-major order, and z-major cells
+// (x fastest) inside a brick, so the numbering is dense and a cell's 26
+// neighbours are mostly a few hundred cells away instead of one cell plane
+// (the row of the gathered neighbour data stays within an XCD's L2).
+// brick >= nc on every axis gives the plain z-major order.
+__host__ __device__ __forceinline__ int cell_key(const RepDev& R, int cx, int cy, int cz) {
+  const int B = R.brick, nx = R.nc[0], ny = R.nc[1], nz = R.nc[2];
+  const int bx = cx / B, by = cy / B, bz = cz / B;
+  const int wx = cx - bx * B, wy = cy - by * B, wz = cz - bz * B;
+  const int sx = nx - bx * B < B ? nx - bx * B : B;
+  const int sy = ny - by * B < B ? ny - by * B : B;
+  const int sz = nz - bz * B < B ? nz - bz * B : B;
+  return bz * B * ny * nx + sz * (by * B) * nx + sz * sy * (bx * B) + (wz * sy + wy) * sx + wx;
+}
 
 // Per-replica conjugate-gradient scalars (three components), written only by
 // the finishing kernel and read by the row kernels that follow it.
@@ -83,7 +110,9 @@ struct DevPtrs {
   CgRep* cg;
   Ctrl* ctrl;
   const int32_t* blk_rep;   // block -> replica
-  double* partial;          // [tiles][NPART]
+  double* partial;          // [sub-tiles][NPART] (the block CG: [tiles][NPART])
+  double* partial2;         // [first-level blocks][NPART]
+  const int32_t* l1_rep;    // first-level block -> replica
   double4* pos;             // current positions (sorted order)
   double4* pos_alt;         // scatter target
   int32_t* cellidx;
@@ -132,9 +161,10 @@ struct DevPtrs {
   int32_t apply_var;
   int32_t ic0;              // 1: u = M^-1 r by the IC(0) triangular solves
   int32_t pc_none;          // 1: no preconditioner, u = r
-  int32_t finish_threads;   // block size of the per-replica CG finisher
+  int32_t l1_total;         // first-level reduction blocks over all replicas
   int32_t want_er;          // 1: the pair terms write er (the network's edge input)
   int32_t vec_nt;           // 1: the CG vector kernel streams with nontemporal accesses
+  int32_t pad1;
 };
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
 
@@ -146,14 +176,16 @@ static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padd
 #define CSR_VARIANT_LIST(X) \
   X(0, 1, 0) X(1, 2, 0) X(2, 4, 0) X(3, 8, 0) X(4, 2, 2) X(5, 4, 1) X(6, 4, 2) X(7, 4, 3)
 
-// Threads that sum a replica's tile partials: a function of the replica
-// alone, so its totals do not depend on the other replicas of a batch (the
-// launch takes the largest; further waves add exact zeros).  Few threads
-// finish a short sum sooner, many a long one (measured: 977 tiles 1.0 us
-// with 256 against 5.0 us with 1024 threads).
-__host__ __device__ __forceinline__ int finish_threads_for(int nblk) {
-  return nblk <= 2048 ? 256 : 1024;
-}
+// The per-replica CG finisher sums the replica's sub-tile partials with
+// FINISH_THREADS threads.  A replica of more than L1_MIN_SUBS sub-tiles has
+// them summed first by blocks of L1_SUBS sub-tiles each (in parallel, one
+// launch) and the finisher adds those blocks' sums: a single block reading
+// every partial of an N = 8e6 box (31,252 slots, 4 MB) took about 60 us per
+// iteration.  Both are functions of the replica alone, so its totals do not
+// depend on the rest of a batch.
+#define FINISH_THREADS 256
+#define L1_SUBS 256
+#define L1_MIN_SUBS 2048
 
 // ---------------------------------------------------------------------------
 // Block -> tile mapping: hardware dispatches workgroups round-robin over the
@@ -256,8 +288,8 @@ __device__ __forceinline__ int imod(int a, int m) {
 // 3 x 3 rows of cells (z, y) and, per row, a run of x cells: the three
 // around cx for rows inside the box, or for a row across the y boundary
 // the cells covering x - s*delta +- rc (the Lees-Edwards-shifted images).
-// Runs of consecutive x cells are contiguous in the sorted order, so each
-// run is one or two row ranges.  f(j) is called for every candidate j != i
+// Consecutive x cells of one brick are contiguous in the sorted order, so
+// each run is a few row ranges.  f(j) is called for every candidate j != i
 // in a fixed order.
 template <typename F>
 __device__ __forceinline__ void for_candidates(const RepDev& R, const int32_t* cell_row,
@@ -289,17 +321,20 @@ __device__ __forceinline__ void for_candidates(const RepDev& R, const int32_t* c
         hi = (int)floor((c0 + R.rc + eps) * R.inv_cell[0]);
         if (hi - lo + 1 >= ncx) { lo = 0; hi = ncx - 1; }
       }
-      const int rowbase = R.seg_off + (cz2 * ncy + cy2) * ncx;
-      // split [lo, hi] at the periodic x edge into at most two runs
+      // split [lo, hi] at the periodic x edge and at brick edges into runs
+      // of consecutive cells (consecutive keys)
       int a = imod(lo, ncx);
       int len = hi - lo + 1;
       while (len > 0) {
-        const int run = (a + len <= ncx) ? len : (ncx - a);
-        const int j0 = cell_row[rowbase + a], j1 = cell_row[rowbase + a + run];
+        int run = (a + len <= ncx) ? len : (ncx - a);
+        const int bend = (a / R.brick + 1) * R.brick - a;
+        run = run < bend ? run : bend;
+        const int c0 = R.seg_off + cell_key(R, a, cy2, cz2);
+        const int j0 = cell_row[c0], j1 = cell_row[c0 + run];
         for (int j = j0; j < j1; ++j)
           if (j != self) f(j);
         len -= run;
-        a = 0;
+        a = a + run == ncx ? 0 : a + run;
       }
     }
   }

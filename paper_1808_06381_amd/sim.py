@@ -161,7 +161,7 @@ def lib():
                                       P(C.c_double)]
         L.sim_precond_weights.argtypes = [vp, vp, C.c_int64, C.c_int32]
         L.sim_precond_config.argtypes = [vp, C.c_int32, C.c_int32]
-        L.sim_precond_floor.argtypes = [vp, C.c_double, C.c_double]
+        L.sim_precond_floor.argtypes = [vp, C.c_double]
         L.sim_graph_mode.argtypes = [vp, C.c_int32]
         L.sim_train_probe.argtypes = [vp, C.c_double, C.c_uint64, C.c_uint64, C.c_int32,
                                       P(C.c_double)]
@@ -465,11 +465,9 @@ class Sim:
         _check(lib().sim_precond_config(self.h, int(bool(round_act)), int(learned_maxit)),
                "sim_precond_config")
 
-    def precond_floor(self, lam_floor=0.1, s_clamp=0.0):
-        """Floor added to the learned diagonal head (default 0.1) and the
-        inference clamp |S_ij| <= s_clamp sqrt(lam_i lam_j) (0: off)."""
-        _check(lib().sim_precond_floor(self.h, float(lam_floor), float(s_clamp)),
-               "sim_precond_floor")
+    def precond_floor(self, lam_floor=0.3):
+        """Floor added to the learned diagonal head (default 0.3)."""
+        _check(lib().sim_precond_floor(self.h, float(lam_floor)), "sim_precond_floor")
 
     def train_step(self, lr):
         loss = C.c_double()

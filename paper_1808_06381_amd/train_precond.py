@@ -11,7 +11,8 @@ A-norm; or on the step's own b and solution with
 
 Evaluation runs held-out boxes (seeds 9001..) at several shear rates with the
 trained network and with Jacobi from identical initial states, and reports
-CG iterations per step and the final true relative residual of each form.
+CG iterations per step and the final true relative residual of each form
+(--eval-only: the weights of --out as they are, at the library's floor).
 
     python -m paper_1808_06381_amd.train_precond --steps 20000 --n 100000 \
         --replicas 4 --out paper_1808_06381_amd/weights/precond_n1e5.bin \
@@ -77,7 +78,29 @@ def main():
     ap.add_argument("--init", default=None, help="start from these weights")
     ap.add_argument("--eval-json", default=None)
     ap.add_argument("--eval-seeds", type=int, default=10)
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the weights of --out (no training) with the library's "
+                         "current head floor; training fields of an existing --eval-json "
+                         "are kept")
     args = ap.parse_args()
+    if args.eval_only:
+        theta = precond.load(args.out)
+        ev = evaluate(theta, args.n, seeds=list(range(9001, 9001 + args.eval_seeds)),
+                      shears=(0.01, 0.1, 1.0))
+        old = {}
+        if args.eval_json and os.path.exists(args.eval_json):
+            with open(args.eval_json) as f:
+                old = json.load(f)
+        keep = {k: v for k, v in old.items() if k not in ev}
+        ev.update(keep)
+        ev["eval_lam_floor"] = precond.LAM_FLOOR
+        if args.eval_json:
+            with open(args.eval_json, "w") as f:
+                json.dump(ev, f, indent=1)
+        print(f"held-out mean CG iterations at head floor {precond.LAM_FLOOR}: jacobi "
+              f"{ev['mean_iters_jacobi']:.2f}, learned {ev['mean_iters_learned']:.2f} "
+              f"(ratio {ev['iteration_ratio']:.3f})", flush=True)
+        return
     theta = precond.load(args.init) if args.init else None
     t0 = time.time()
     theta, losses = precond.train(args.steps, n=args.n, lr=args.lr, seed=args.seed,

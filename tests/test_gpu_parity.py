@@ -9,9 +9,9 @@
 * the paper's own thermal force (Eq. 6a: node noise only) in the paper's
   geometry, right-hand side and a 10-step trajectory;
 * determinism, error paths and the full-size workloads (N = 10^6, and
-  N = 2.2 * 10^6, whose 2149 tiles take the 1024-thread reduction of the CG
-  finisher) checked on the pair set, A's diagonal, b, and the oracle's
-  residual of the GPU velocities.
+  N = 2.2 * 10^6, whose CG partials take the two-level reduction) checked on
+  the pair set, A's diagonal, b, and the oracle's residual of the GPU
+  velocities.
 
 Tolerances: pairs exact; matrix values within 1e-14 relative (the
 polynomial weight is the same IEEE sequence; the Gaussian differs by the
@@ -396,12 +396,14 @@ def test_paper_noise_trajectory_paper_geometry():
 
 @pytest.mark.slow
 def test_full_size_above_2048_tiles():
-    """N = 2.2 * 10^6 in one box (2149 tiles of 1024 rows): the per-replica
-    reduction of the CG finisher runs with 1024 threads here (256 up to 2048
-    tiles), as on the N = 8 * 10^6 box.  The complete pair set equals the
-    oracle's cell list, A's diagonal and b match, and the oracle's own
-    residual of the GPU velocities -- computed without any GPU sum --
-    meets the tolerance, so a wrong reduction cannot pass unseen."""
+    """N = 2.2 * 10^6 in one box (2149 tiles, 8596 sub-tiles of 256 rows):
+    the CG partial sums of this replica are reduced in two levels (blocks of
+    256 sub-tiles, then the finisher), as on the N = 8 * 10^6 box; below 2048
+    sub-tiles the finisher sums them alone.  The cells are numbered in bricks
+    of 8^3.  The complete pair set equals the oracle's cell list, A's diagonal
+    and b match, and the oracle's own residual of the GPU velocities --
+    computed without any GPU sum -- meets the tolerance, so a wrong reduction
+    cannot pass unseen."""
     n = 2_200_000
     cfg = inputs.cube_params(n, 0.5, seed=17)
     tol = 1e-8

@@ -52,7 +52,7 @@ def test_minv_symmetric_with_positive_diagonal():
 
 def test_minv_is_the_neumann_series_at_initial_heads():
     """v = z = 0, ze = (0, 0, 1), z0 = 0: S_ij = What_ij and lam = softplus(v0)
-    + 0.1 (= 1 up to the bf16 rounding of v0), i.e. M^-1 = D^-1/2 (lam I +
+    + 0.3 (= 1 up to the bf16 rounding of v0), i.e. M^-1 = D^-1/2 (lam I +
     What) D^-1/2; with lam = 1 this is D^-1 + D^-1 (D - A) D^-1, the first two
     terms of A^-1 = sum_k (D^-1 (D - A))^k D^-1.  Positive definite: the
     spectral radius of What is below 1 because A is strictly diagonally
@@ -64,7 +64,7 @@ def test_minv_is_the_neumann_series_at_initial_heads():
     ref = -s["val"] / (s["diag"][rows] * s["diag"][s["col"]])
     np.testing.assert_allclose(moff, ref, rtol=1e-14)
     v0 = oracle.bf16(th[precond.LAYOUT["v0"][0]])
-    lam = np.log1p(np.exp(v0)) + 0.1
+    lam = np.log1p(np.exp(v0)) + 0.3
     np.testing.assert_allclose(mdiag * s["diag"], lam, rtol=1e-14)
     assert abs(lam - 1.0) < 4e-3
     A = oracle.dense(s)
