@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="eager steps only")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default lane widths of the CSR products")
+    ap.add_argument("--tuning", default="",
+                    help="spmv,apply,vec variant indices to use instead of the autotuner "
+                         "(e.g. 7,6,1; for counter runs that must match a timed run)")
     ap.add_argument("--c5-preshear", type=int, default=2000,
                     help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--only", default="",
@@ -240,7 +243,12 @@ def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, 
         for sim in sims:
             sim.step(1)
     tuning = []
-    if not args.no_autotune:
+    if args.tuning:
+        sv, av, vv = (int(x) for x in args.tuning.split(","))
+        for sim in sims:
+            sim.set_tuning(spmv_variant=sv, apply_variant=av, vec_variant=vv)
+            sim.step(1)
+    elif not args.no_autotune:
         for sim in sims:
             tuning.append(sim.autotune(reps=10))
             sim.step(1)  # re-records the step graph with the chosen variants
@@ -318,7 +326,7 @@ def preshear(args, S, cfg, pos, stream, name):
         sim.graph_mode(True)
         for k in range(args.c5_preshear):
             sim.step(1)
-            if (k + 1) % 100 == 0:
+            if (k + 1) % 50 == 0:
                 log(f"{name}: pre-shear step {k + 1} ({time.perf_counter() - t0:.0f} s)")
         return sim.state()[0]
 
