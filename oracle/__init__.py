@@ -115,6 +115,13 @@ def lib():
         L.orc_mpnn_loss_grad_norm.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double,
                                               f_p, d_p, d_p, C.c_int, d_p]
         L.orc_mpnn_loss_grad_norm.restype = C.c_double
+        L.orc_mpnn_block_nparams.restype = C.c_int64
+        L.orc_mpnn_block_forward.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p, C.c_double,
+                                             f_p, d_p, d_p]
+        L.orc_mpnn_block_forward.restype = C.c_int
+        L.orc_mpnn_block_loss_grad.argtypes = [C.c_int64, i64_p, i64_p, d_p, d_p, d_p,
+                                               C.c_double, f_p, d_p, d_p, C.c_int, d_p]
+        L.orc_mpnn_block_loss_grad.restype = C.c_double
         _lib = L
     return _lib
 
@@ -411,9 +418,10 @@ def mpnn_set_bf16(on):
 
 
 def edge_r(cfg, pos, sys_, step=0):
-    """r_ij / rc per CSR entry of a build_system result (oracle geometry)."""
+    """r_ij / rc per CSR entry of a build_system or build_block_system result
+    (oracle geometry)."""
     delta = le_offset(cfg, step)
-    n = sys_["diag"].shape[0]
+    n = len(sys_["rowptr"]) - 1
     out = np.zeros(len(sys_["col"]))
     rp = sys_["rowptr"]
     for i in range(n):
@@ -459,4 +467,52 @@ def mpnn_loss_grad(sys_, er, alpha, theta, b, xstar, grad=True, norm="A"):
                                          _dp(sys_["val"]), _dp(sys_["diag"]), _dp(er),
                                          float(alpha), tp, _dp(b), _dp(xstar),
                                          1 if norm == "2" else 0, _dp(g))
+    return (loss, g) if grad else loss
+
+
+def mpnn_block_nparams():
+    return int(lib().orc_mpnn_block_nparams())
+
+
+def _theta_block(theta):
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    assert t.shape == (mpnn_block_nparams(),)
+    return t, t.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mpnn_block_forward(bsys, er, alpha, theta):
+    """M^-1 of the learned preconditioner on a block system (build_block_system):
+    (mdiag (n, 3, 3), moff (nnz, 3, 3)) in A's block pattern."""
+    n = len(bsys["bdiag"])
+    t, tp = _theta_block(theta)
+    nnz = len(bsys["col"])
+    mdiag = np.zeros((n, 3, 3))
+    moff = np.zeros((max(nnz, 1), 3, 3))
+    er = np.ascontiguousarray(er, dtype=np.float64)
+    rc = lib().orc_mpnn_block_forward(n, _ip(bsys["rowptr"]), _ip(np.ascontiguousarray(bsys["col"])),
+                                      _dp(np.ascontiguousarray(bsys["bval"])),
+                                      _dp(np.ascontiguousarray(bsys["bdiag"])), _dp(er),
+                                      float(alpha), tp, _dp(mdiag), _dp(moff))
+    if rc != 0:
+        raise RuntimeError("oracle block mpnn forward failed")
+    return mdiag, moff[:nnz]
+
+
+def mpnn_block_loss_grad(bsys, er, alpha, theta, b, xstar, grad=True, norm="2"):
+    """Loss ||M^-1 b - x*||^2 / ||x*||^2 on a block system in the Euclidean
+    (norm "2") or the A-norm and its gradient (mpnn_block_nparams() values)."""
+    n = len(bsys["bdiag"])
+    t, tp = _theta_block(theta)
+    g = np.zeros(mpnn_block_nparams()) if grad else None
+    er = np.ascontiguousarray(er, dtype=np.float64)
+    b = _f64(b, (n, 3))
+    xstar = _f64(xstar, (n, 3))
+    if norm not in ("A", "2"):
+        raise ValueError("norm must be 'A' or '2'")
+    loss = lib().orc_mpnn_block_loss_grad(n, _ip(bsys["rowptr"]),
+                                          _ip(np.ascontiguousarray(bsys["col"])),
+                                          _dp(np.ascontiguousarray(bsys["bval"])),
+                                          _dp(np.ascontiguousarray(bsys["bdiag"])), _dp(er),
+                                          float(alpha), tp, _dp(b), _dp(xstar),
+                                          1 if norm == "2" else 0, _dp(g))
     return (loss, g) if grad else loss

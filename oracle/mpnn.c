@@ -116,7 +116,8 @@ static void net_free(net_t* t) {
   free(t->tau); free(t->tg); free(t->what);
 }
 
-static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff) {
+/* features, encoder and message-passing layers (h^0 .. h^NL) */
+static int net_trunk(net_t* t, const float* theta) {
   const int64_t n = t->n, nnz = t->nnz;
   for (int k = 0; k < NPARAMS; ++k) t->th[k] = g_use_bf16 ? orc_bf16(theta[k]) : (double)theta[k];
   t->x = (double*)calloc((size_t)(n * FN + 1), sizeof(double));
@@ -188,8 +189,13 @@ static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff
       }
     }
   }
-  /* heads and the preconditioner */
-  const double* hd = th + OFF_HEAD;
+  return 0;
+}
+
+/* scalar heads: tau (node), tg = S (edge) and, if asked, the scalar M^-1 */
+static void net_heads(net_t* t, double* mdiag, double* moff) {
+  const int64_t n = t->n;
+  const double* hd = t->th + OFF_HEAD;
   const double* hf = t->hs + (int64_t)NL * n * H;
   for (int64_t i = 0; i < n; ++i) {
     double acc = hd[H_V0];
@@ -207,7 +213,87 @@ static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff
     }
     if (mdiag) mdiag[i] = (softplus(t->tau[i]) + EPS_LAM) / t->diag[i];
   }
+}
+
+static int net_forward(net_t* t, const float* theta, double* mdiag, double* moff) {
+  if (net_trunk(t, theta) != 0) return -2;
+  net_heads(t, mdiag, moff);
   return 0;
+}
+
+/* backward through the layers and the encoder: dh holds dL/dh^NL on entry
+ * (it is overwritten); dm and da are n x H work arrays */
+static void net_trunk_backward(const net_t* t, double* dh, double* dm, double* da,
+                               double* grad) {
+  const int64_t n = t->n;
+  const int64_t* rowptr = t->rowptr;
+  const int64_t* col = t->col;
+  const double* th = t->th;
+  /* layers, last to first; dh holds dL/dh^{l+1} on entry to layer l */
+  for (int l = NL - 1; l >= 0; --l) {
+    const double* L = th + OFF_L0 + l * L_SIZE;
+    double* G = grad + OFF_L0 + l * L_SIZE;
+    const double* hin = t->hs + (int64_t)l * n * H;
+    const double* y = t->ys + (int64_t)l * n * H;
+    const double* m = t->ms + (int64_t)l * n * H;
+    const double* a = t->as + (int64_t)l * n * H;
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < H; ++k) da[i * H + k] = a[i * H + k] > 0.0 ? dh[i * H + k] : 0.0;
+    /* h_out = h_in + relu(U h_in + V m + d): dh_in = dh_out + U^T da, dm = V^T da */
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < H; ++k) {
+        const double dak = da[i * H + k];
+        G[L_D + k] += dak;
+        for (int q = 0; q < H; ++q) {
+          G[L_U + k * H + q] += dak * hin[i * H + q];
+          G[L_V + k * H + q] += dak * m[i * H + q];
+        }
+      }
+    for (int64_t i = 0; i < n; ++i)
+      for (int q = 0; q < H; ++q) {
+        double su = 0.0, sv = 0.0;
+        for (int k = 0; k < H; ++k) {
+          su += L[L_U + k * H + q] * da[i * H + k];
+          sv += L[L_V + k * H + q] * da[i * H + k];
+        }
+        dh[i * H + q] += su;   /* dh_in = dh_out + U^T da (dh_out already in dh) */
+        dm[i * H + q] = sv;
+      }
+    /* m_i = (1/8) sum_j relu(y_j + Q e_ij + c): dy_j, dQ, dc; dh_in += P^T dy */
+    double* dy = da; /* reuse: da is no longer needed */
+    for (int64_t i = 0; i < n * H; ++i) dy[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const int64_t j = col[q];
+        for (int k = 0; k < H; ++k) {
+          double s = y[j * H + k] + L[L_C + k];
+          for (int f = 0; f < FE; ++f) s += L[L_Q + k * FE + f] * t->e[FE * q + f];
+          if (!(s > 0.0)) continue;
+          const double dq = MSG_SCALE * dm[i * H + k];
+          G[L_C + k] += dq;
+          for (int f = 0; f < FE; ++f) G[L_Q + k * FE + f] += dq * t->e[FE * q + f];
+          dy[j * H + k] += dq;
+        }
+      }
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < H; ++k)
+        for (int q = 0; q < H; ++q) G[L_P + k * H + q] += dy[i * H + k] * hin[i * H + q];
+    for (int64_t i = 0; i < n; ++i)
+      for (int q = 0; q < H; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < H; ++k) s += L[L_P + k * H + q] * dy[i * H + k];
+        dh[i * H + q] += s;
+      }
+  }
+  /* encoder: h0 = relu(W0 x + b0) */
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < H; ++k) {
+      double acc = th[OFF_B0 + k];
+      for (int f = 0; f < FN; ++f) acc += th[OFF_W0 + k * FN + f] * t->x[FN * i + f];
+      if (!(acc > 0.0)) continue;
+      grad[OFF_B0 + k] += dh[i * H + k];
+      for (int f = 0; f < FN; ++f) grad[OFF_W0 + k * FN + f] += dh[i * H + k] * t->x[FN * i + f];
+    }
 }
 
 /* M^-1 (mdiag, moff) for the system (rowptr, col, val, diag) */
@@ -303,71 +389,7 @@ double orc_mpnn_loss_grad_norm(int64_t n, const int64_t* rowptr, const int64_t* 
         }
       }
     }
-    /* layers, last to first; dh holds dL/dh^{l+1} on entry to layer l */
-    for (int l = NL - 1; l >= 0; --l) {
-      const double* L = th + OFF_L0 + l * L_SIZE;
-      double* G = grad + OFF_L0 + l * L_SIZE;
-      const double* hin = t.hs + (int64_t)l * n * H;
-      const double* y = t.ys + (int64_t)l * n * H;
-      const double* m = t.ms + (int64_t)l * n * H;
-      const double* a = t.as + (int64_t)l * n * H;
-      for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < H; ++k) da[i * H + k] = a[i * H + k] > 0.0 ? dh[i * H + k] : 0.0;
-      /* h_out = h_in + relu(U h_in + V m + d): dh_in = dh_out + U^T da, dm = V^T da */
-      for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < H; ++k) {
-          const double dak = da[i * H + k];
-          G[L_D + k] += dak;
-          for (int q = 0; q < H; ++q) {
-            G[L_U + k * H + q] += dak * hin[i * H + q];
-            G[L_V + k * H + q] += dak * m[i * H + q];
-          }
-        }
-      for (int64_t i = 0; i < n; ++i)
-        for (int q = 0; q < H; ++q) {
-          double su = 0.0, sv = 0.0;
-          for (int k = 0; k < H; ++k) {
-            su += L[L_U + k * H + q] * da[i * H + k];
-            sv += L[L_V + k * H + q] * da[i * H + k];
-          }
-          dh[i * H + q] += su;   /* dh_in = dh_out + U^T da (dh_out already in dh) */
-          dm[i * H + q] = sv;
-        }
-      /* m_i = (1/8) sum_j relu(y_j + Q e_ij + c): dy_j, dQ, dc; dh_in += P^T dy */
-      double* dy = da; /* reuse: da is no longer needed */
-      for (int64_t i = 0; i < n * H; ++i) dy[i] = 0.0;
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-          const int64_t j = col[q];
-          for (int k = 0; k < H; ++k) {
-            double s = y[j * H + k] + L[L_C + k];
-            for (int f = 0; f < FE; ++f) s += L[L_Q + k * FE + f] * t.e[FE * q + f];
-            if (!(s > 0.0)) continue;
-            const double dq = MSG_SCALE * dm[i * H + k];
-            G[L_C + k] += dq;
-            for (int f = 0; f < FE; ++f) G[L_Q + k * FE + f] += dq * t.e[FE * q + f];
-            dy[j * H + k] += dq;
-          }
-        }
-      for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < H; ++k)
-          for (int q = 0; q < H; ++q) G[L_P + k * H + q] += dy[i * H + k] * hin[i * H + q];
-      for (int64_t i = 0; i < n; ++i)
-        for (int q = 0; q < H; ++q) {
-          double s = 0.0;
-          for (int k = 0; k < H; ++k) s += L[L_P + k * H + q] * dy[i * H + k];
-          dh[i * H + q] += s;
-        }
-    }
-    /* encoder: h0 = relu(W0 x + b0) */
-    for (int64_t i = 0; i < n; ++i)
-      for (int k = 0; k < H; ++k) {
-        double acc = th[OFF_B0 + k];
-        for (int f = 0; f < FN; ++f) acc += th[OFF_W0 + k * FN + f] * t.x[FN * i + f];
-        if (!(acc > 0.0)) continue;
-        grad[OFF_B0 + k] += dh[i * H + k];
-        for (int f = 0; f < FN; ++f) grad[OFF_W0 + k * FN + f] += dh[i * H + k] * t.x[FN * i + f];
-      }
+    net_trunk_backward(&t, dh, dm, da, grad);
     free(gl); free(gt); free(dh); free(dm); free(da);
   }
 out:
@@ -381,4 +403,298 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
                           const float* theta, const double* b, const double* xstar, double* grad) {
   return orc_mpnn_loss_grad_norm(n, rowptr, col, val, diag, edge_r, alpha, theta, b, xstar, 0,
                                  grad);
+}
+
+/* ===========================================================================
+ * The learned preconditioner for the anisotropic friction system (block.c:
+ * genuine 3 x 3 blocks, A_ij = -W_ij, A_ii = gamma0 I + sum_j W_ij).
+ *
+ * The trunk above runs unchanged on the scalar shadow of A, the traces
+ *   d_i = tr(A_ii) / 3,  omega_ij = tr(W_ij) / 3,
+ * in place of (diag, -val): its features are rotation invariant and equal
+ * those of the isotropic system when every block is a multiple of I_3.  The
+ * heads give four numbers per node / entry:
+ *   lam_i  = softplus(v . h_i + v0) + eps          (the scalar node head)
+ *   S_ij   = z . (h_i * h_j) + ze . e_ij + z0      (the scalar edge head)
+ *   mu_i   = u . h_i + u0                          (node anisotropy)
+ *   sig_ij = s . (h_i * h_j) + se . e_ij + s0      (edge anisotropy)
+ * and the 3 x 3 blocks of the preconditioner are
+ *   X_ii = lam_i A_ii + mu_i (A_ii - d_i I),
+ *   X_ij = S_ij sqrt(d_i d_j) I + sig_ij (W_ij - omega_ij I),
+ *   M^-1 = B X B,  B = blockdiag(A_ii^-1).
+ * Built from I and A's own blocks only, M^-1 turns with the system under a
+ * rotation; it is symmetric (X_ji = X_ij = X_ij^T); when every block of A is
+ * a multiple of I_3 both anisotropy terms vanish and M^-1 is the scalar
+ * network's preconditioner times I_3.  lam = 1, mu = 0, S = What, sig = 1
+ * give M^-1 = B (2D - A) B, D = blockdiag(A_ii): the two-term Neumann series
+ * of the block-Jacobi splitting, positive definite since each pair adds the
+ * positive semidefinite [[W, W], [W, W]] to 2D - A = gamma0 I + ...
+ * Parameters: the scalar network's, then u[32], u0, s[32], se[3], s0.
+ * =========================================================================== */
+#define NPHI (H + 1 + H + FE + 1)
+#define PHI_U 0
+#define PHI_U0 (PHI_U + H)
+#define PHI_S (PHI_U0 + 1)
+#define PHI_SE (PHI_S + H)
+#define PHI_S0 (PHI_SE + FE)
+
+int64_t orc_mpnn_block_nparams(void) { return NPARAMS + NPHI; }
+
+/* inverse of a 3 x 3 matrix (row-major) by Gauss-Jordan elimination with
+ * partial pivoting; -1 if singular */
+static int inv3(const double* a, double* out) {
+  double m[3][6];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 6; ++c) m[r][c] = c < 3 ? a[3 * r + c] : (c - 3 == r ? 1.0 : 0.0);
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (fabs(m[r][c]) > fabs(m[piv][c])) piv = r;
+    if (m[piv][c] == 0.0) return -1;
+    if (piv != c)
+      for (int k = 0; k < 6; ++k) {
+        const double tmp = m[c][k];
+        m[c][k] = m[piv][k];
+        m[piv][k] = tmp;
+      }
+    const double p = m[c][c];
+    for (int k = 0; k < 6; ++k) m[c][k] /= p;
+    for (int r = 0; r < 3; ++r) {
+      if (r == c) continue;
+      const double f = m[r][c];
+      for (int k = 0; k < 6; ++k) m[r][k] -= f * m[c][k];
+    }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) out[3 * r + c] = m[r][c + 3];
+  return 0;
+}
+
+/* out = a b c (3 x 3, row-major) */
+static void mul33(const double* a, const double* b, const double* c, double* out) {
+  double ab[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += a[3 * r + l] * b[3 * l + k];
+      ab[3 * r + k] = s;
+    }
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += ab[3 * r + l] * c[3 * l + k];
+      out[3 * r + k] = s;
+    }
+}
+
+typedef struct {
+  net_t t;
+  double phi[NPHI];     /* anisotropy head weights (bf16-valued) */
+  double *val, *diag;   /* scalar shadow: -omega per entry, d per node */
+  double *binv;         /* n x 9: A_ii^-1 */
+  double *md, *mo;      /* M^-1 blocks: n x 9, nnz x 9 */
+} bnet_t;
+
+static void bnet_free(bnet_t* B) {
+  free(B->val); free(B->diag); free(B->binv); free(B->md); free(B->mo);
+  net_free(&B->t);
+}
+
+static int bnet_forward(bnet_t* B, int64_t n, const int64_t* rowptr, const int64_t* col,
+                        const double* bval, const double* bdiag, const double* edge_r,
+                        double alpha, const float* theta) {
+  const int64_t nnz = rowptr[n];
+  B->val = (double*)calloc((size_t)(nnz + 1), sizeof(double));
+  B->diag = (double*)calloc((size_t)(n + 1), sizeof(double));
+  B->binv = (double*)calloc((size_t)(9 * n + 1), sizeof(double));
+  B->md = (double*)calloc((size_t)(9 * n + 1), sizeof(double));
+  B->mo = (double*)calloc((size_t)(9 * nnz + 1), sizeof(double));
+  if (!B->val || !B->diag || !B->binv || !B->md || !B->mo) return -2;
+  for (int64_t q = 0; q < nnz; ++q)
+    B->val[q] = ((bval[9 * q] + bval[9 * q + 4]) + bval[9 * q + 8]) / 3.0;
+  for (int64_t i = 0; i < n; ++i) {
+    B->diag[i] = ((bdiag[9 * i] + bdiag[9 * i + 4]) + bdiag[9 * i + 8]) / 3.0;
+    if (inv3(bdiag + 9 * i, B->binv + 9 * i) != 0) return -1;
+  }
+  net_t* t = &B->t;
+  t->n = n; t->nnz = nnz; t->rowptr = rowptr; t->col = col; t->val = B->val;
+  t->diag = B->diag; t->edge_r = edge_r; t->alpha = alpha;
+  if (net_trunk(t, theta) != 0) return -2;
+  net_heads(t, NULL, NULL);
+  for (int k = 0; k < NPHI; ++k)
+    B->phi[k] = g_use_bf16 ? orc_bf16(theta[NPARAMS + k]) : (double)theta[NPARAMS + k];
+  const double* ph = B->phi;
+  const double* hf = t->hs + (int64_t)NL * n * H;
+  for (int64_t i = 0; i < n; ++i) {
+    const double* Ai = bdiag + 9 * i;
+    const double di = B->diag[i];
+    double mu = ph[PHI_U0];
+    for (int k = 0; k < H; ++k) mu += ph[PHI_U + k] * hf[i * H + k];
+    const double lam = softplus(t->tau[i]) + EPS_LAM;
+    double X[9];
+    for (int m = 0; m < 9; ++m) X[m] = lam * Ai[m] + mu * (Ai[m] - (m % 4 == 0 ? di : 0.0));
+    mul33(B->binv + 9 * i, X, B->binv + 9 * i, B->md + 9 * i);
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      const int64_t j = col[q];
+      double sg = ph[PHI_S0];
+      for (int k = 0; k < H; ++k) sg += ph[PHI_S + k] * (hf[i * H + k] * hf[j * H + k]);
+      for (int f = 0; f < FE; ++f) sg += ph[PHI_SE + f] * t->e[FE * q + f];
+      const double om = -B->val[q];
+      const double sq = sqrt(di * B->diag[j]);
+      for (int m = 0; m < 9; ++m) {
+        const double w = -bval[9 * q + m];
+        const double id = m % 4 == 0 ? 1.0 : 0.0;
+        X[m] = t->tg[q] * sq * id + sg * (w - om * id);
+      }
+      mul33(B->binv + 9 * i, X, B->binv + 9 * j, B->mo + 9 * q);
+    }
+  }
+  return 0;
+}
+
+/* M^-1 blocks (row-major 3 x 3: mdiag n x 9, moff nnz x 9) for the block
+ * system (rowptr, col, bval, bdiag) of block.c in original order */
+int orc_mpnn_block_forward(int64_t n, const int64_t* rowptr, const int64_t* col,
+                           const double* bval, const double* bdiag, const double* edge_r,
+                           double alpha, const float* theta, double* mdiag, double* moff) {
+  bnet_t B;
+  memset(&B, 0, sizeof(B));
+  int rc = bnet_forward(&B, n, rowptr, col, bval, bdiag, edge_r, alpha, theta);
+  if (rc == 0) {
+    memcpy(mdiag, B.md, sizeof(double) * 9 * (size_t)n);
+    memcpy(moff, B.mo, sizeof(double) * 9 * (size_t)rowptr[n]);
+  }
+  bnet_free(&B);
+  return rc;
+}
+
+/* y = A x (block system, stacked 3n vectors) */
+static void bsys_mul(int64_t n, const int64_t* rowptr, const int64_t* col, const double* offd,
+                     const double* dg, const double* x, double* y) {
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += dg[9 * i + 3 * c + l] * x[3 * i + l];
+      for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+        for (int l = 0; l < 3; ++l) s += offd[9 * q + 3 * c + l] * x[3 * col[q] + l];
+      y[3 * i + c] = s;
+    }
+}
+
+/* Loss L = ||M^-1 b - x*||^2 / ||x*||^2 on the block system, in the A-norm
+ * (euclid = 0) or the Euclidean norm (euclid = 1), and, if grad is given,
+ * dL/dtheta (NPARAMS + NPHI values).  dL/dM_ij = G_i b_j^T with
+ * G = 2 W (M^-1 b - x*) / ||x*||_W^2; through M^-1 = B X B,
+ * dL/dX_ij = B_i dL/dM_ij B_j, and the heads enter X linearly:
+ *   dL/dlam_i = <dX_ii, A_ii>, dL/dmu_i = <dX_ii, A_ii - d_i I>,
+ *   dL/dS_ij = sqrt(d_i d_j) tr dX_ij, dL/dsig_ij = <dX_ij, W_ij - omega_ij I>
+ * (<., .> the Frobenius product).                                          */
+double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col,
+                                const double* bval, const double* bdiag, const double* edge_r,
+                                double alpha, const float* theta, const double* b,
+                                const double* xstar, int euclid, double* grad) {
+  bnet_t B;
+  memset(&B, 0, sizeof(B));
+  const int64_t nnz = rowptr[n];
+  double* z = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
+  double* ae = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
+  double* ax = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
+  double loss = NAN;
+  if (!z || !ae || !ax ||
+      bnet_forward(&B, n, rowptr, col, bval, bdiag, edge_r, alpha, theta) != 0)
+    goto out;
+  /* z = M^-1 b - x* */
+  bsys_mul(n, rowptr, col, B.mo, B.md, b, z);
+  for (int64_t i = 0; i < 3 * n; ++i) z[i] -= xstar[i];
+  if (euclid) {
+    memcpy(ae, z, sizeof(double) * 3 * (size_t)n);
+    memcpy(ax, xstar, sizeof(double) * 3 * (size_t)n);
+  } else {
+    bsys_mul(n, rowptr, col, bval, bdiag, z, ae);
+    bsys_mul(n, rowptr, col, bval, bdiag, xstar, ax);
+  }
+  {
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < 3 * n; ++i) {
+      num += z[i] * ae[i];
+      den += xstar[i] * ax[i];
+    }
+    loss = num / den;
+    if (!grad) goto out;
+    for (int k = 0; k < NPARAMS + NPHI; ++k) grad[k] = 0.0;
+    const net_t* t = &B.t;
+    const double* hd = t->th + OFF_HEAD;
+    const double* ph = B.phi;
+    double* gh = grad + OFF_HEAD;
+    double* gp = grad + NPARAMS;
+    const double* hf = t->hs + (int64_t)NL * n * H;
+    double* dh = (double*)calloc((size_t)(n * H + 1), sizeof(double));
+    double* dm = (double*)calloc((size_t)(n * H + 1), sizeof(double));
+    double* da = (double*)calloc((size_t)(n * H + 1), sizeof(double));
+    if (!dh || !dm || !da) {
+      free(dh); free(dm); free(da);
+      loss = NAN;
+      goto out;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      const double* Ai = bdiag + 9 * i;
+      const double* Bi = B.binv + 9 * i;
+      const double di = B.diag[i];
+      double gi[3];
+      for (int c = 0; c < 3; ++c) gi[c] = 2.0 * ae[3 * i + c] / den;
+      /* node block */
+      double dM[9], dX[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) dM[3 * r + c] = gi[r] * b[3 * i + c];
+      mul33(Bi, dM, Bi, dX);
+      double dlam = 0.0, dmu = 0.0;
+      for (int m = 0; m < 9; ++m) {
+        dlam += dX[m] * Ai[m];
+        dmu += dX[m] * (Ai[m] - (m % 4 == 0 ? di : 0.0));
+      }
+      const double gt = dlam * sigm(t->tau[i]);
+      gh[H_V0] += gt;
+      gp[PHI_U0] += dmu;
+      for (int k = 0; k < H; ++k) {
+        gh[H_V + k] += gt * hf[i * H + k];
+        gp[PHI_U + k] += dmu * hf[i * H + k];
+        dh[i * H + k] += gt * hd[H_V + k] + dmu * ph[PHI_U + k];
+      }
+      /* edge blocks: each directed entry evaluates its own S_ij and sig_ij */
+      for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+        const int64_t j = col[q];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) dM[3 * r + c] = gi[r] * b[3 * j + c];
+        mul33(Bi, dM, B.binv + 9 * j, dX);
+        const double om = -B.val[q];
+        double tr = 0.0, dsg = 0.0;
+        for (int m = 0; m < 9; ++m) {
+          const double id = m % 4 == 0 ? 1.0 : 0.0;
+          tr += dX[m] * id;
+          dsg += dX[m] * (-bval[9 * q + m] - om * id);
+        }
+        const double dS = sqrt(di * B.diag[j]) * tr;
+        gh[H_Z0] += dS;
+        gp[PHI_S0] += dsg;
+        for (int f = 0; f < FE; ++f) {
+          gh[H_ZE + f] += dS * t->e[FE * q + f];
+          gp[PHI_SE + f] += dsg * t->e[FE * q + f];
+        }
+        for (int k = 0; k < H; ++k) {
+          gh[H_Z + k] += dS * (hf[i * H + k] * hf[j * H + k]);
+          gp[PHI_S + k] += dsg * (hf[i * H + k] * hf[j * H + k]);
+          const double wk = dS * hd[H_Z + k] + dsg * ph[PHI_S + k];
+          dh[i * H + k] += wk * hf[j * H + k];
+          dh[j * H + k] += wk * hf[i * H + k];
+        }
+      }
+    }
+    net_trunk_backward(t, dh, dm, da, grad);
+    free(dh); free(dm); free(da);
+  }
+out:
+  free(z); free(ae); free(ax);
+  bnet_free(&B);
+  (void)nnz;
+  return loss;
 }

@@ -146,6 +146,18 @@ double orc_mpnn_loss_grad_norm(int64_t n, const int64_t* rowptr, const int64_t* 
 double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, const double* val,
                           const double* diag, const double* edge_r, double alpha,
                           const float* theta, const double* b, const double* xstar, double* grad);
+/* the same network with 3 x 3 heads on the anisotropic block system
+ * (block.c layout, original order): M^-1 blocks row-major, mdiag n x 9,
+ * moff nnz x 9; theta holds orc_mpnn_block_nparams() values (the scalar
+ * network's, then the anisotropy heads u[32], u0, s[32], se[3], s0) */
+int64_t orc_mpnn_block_nparams(void);
+int orc_mpnn_block_forward(int64_t n, const int64_t* rowptr, const int64_t* col,
+                           const double* bval, const double* bdiag, const double* edge_r,
+                           double alpha, const float* theta, double* mdiag, double* moff);
+double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col,
+                                const double* bval, const double* bdiag, const double* edge_r,
+                                double alpha, const float* theta, const double* b,
+                                const double* xstar, int euclid, double* grad);
 
 #ifdef __cplusplus
 }

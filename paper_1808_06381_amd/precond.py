@@ -59,6 +59,44 @@ def layout():
 LAYOUT, NPARAMS = layout()
 
 
+def block_layout():
+    """The parameters of the 3 x 3 heads on the anisotropic block system,
+    appended after the scalar network's (the trunk and the scalar heads
+    lam_i and S_ij are shared):
+        mu_i   = u . h_i + u0                      node anisotropy
+        sig_ij = s . (h_i * h_j) + se . e_ij + s0  edge anisotropy
+    X_ii = lam_i A_ii + mu_i (A_ii - d_i I),
+    X_ij = S_ij sqrt(d_i d_j) I + sig_ij (W_ij - omega_ij I),
+    M^-1 = B X B with B = blockdiag(A_ii^-1), d_i = tr A_ii / 3,
+    omega_ij = tr W_ij / 3 (A_ij = -W_ij); the trunk sees the traces."""
+    out = dict(LAYOUT)
+    off = NPARAMS
+    for name, shape in (("u", (H,)), ("u0", (1,)), ("s", (H,)), ("se", (FE,)), ("s0", (1,))):
+        out[name] = (off, shape)
+        off += int(np.prod(shape))
+    return out, off
+
+
+BLOCK_LAYOUT, NPARAMS_BLOCK = block_layout()
+
+
+def block_params(theta=None, seed=0):
+    """Weights of the block form: the scalar network's (theta, or the initial
+    ones) and anisotropy heads mu = 0, sig = 1, which keep the anisotropic
+    part of every pair block of the two-term Neumann series: with the initial
+    scalar heads M^-1 = B (2D - A) B, D = blockdiag(A_ii) (positive
+    definite)."""
+    base = init_params(seed) if theta is None else np.asarray(theta, dtype=np.float32)
+    if base.size == NPARAMS_BLOCK:
+        return base.copy()
+    if base.size != NPARAMS:
+        raise ValueError("weight count mismatch")
+    out = np.zeros(NPARAMS_BLOCK, dtype=np.float32)
+    out[:NPARAMS] = base
+    out[BLOCK_LAYOUT["s0"][0]] = 1.0
+    return out
+
+
 def init_params(seed=0, scale=0.5):
     """Small random weights; the heads start at lam = softplus(v0) + eps = 1
     and S_ij = What_ij, i.e. the two-term Neumann series
@@ -98,7 +136,7 @@ def load(path):
             raise ValueError("not a preconditioner weight file")
         (n,) = struct.unpack("<q", head[8:])
         theta = np.frombuffer(f.read(4 * n), dtype=np.float32).copy()
-    if theta.size != NPARAMS:
+    if theta.size not in (NPARAMS, NPARAMS_BLOCK):
         raise ValueError("weight count mismatch")
     return theta
 
