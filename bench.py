@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--tuning", default="",
                     help="spmv,apply,vec variant indices to use instead of the autotuner "
                          "(e.g. 7,6,1; for counter runs that must match a timed run)")
+    ap.add_argument("--preshear-cache", default="",
+                    help="directory for pre-sheared states (profiling runs share one)")
     ap.add_argument("--c5-preshear", type=int, default=2000,
                     help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--only", default="",
@@ -319,7 +321,19 @@ def form_summary(r, np):
 
 
 def preshear(args, S, cfg, pos, stream, name):
-    """Plain graph steps at the workload's shear from uniform positions."""
+    """Plain graph steps at the workload's shear from uniform positions.  With
+    --preshear-cache DIR the state is read from / written to DIR (the steps
+    are deterministic, so a cached state is the state a fresh run reaches)."""
+    import numpy as np
+
+    cache = None
+    if args.preshear_cache:
+        os.makedirs(args.preshear_cache, exist_ok=True)
+        cache = os.path.join(args.preshear_cache,
+                             f"{name}_n{cfg['n']}_seed{cfg['seed']}_steps{args.c5_preshear}.npy")
+        if os.path.exists(cache):
+            log(f"{name}: pre-sheared state from {cache}")
+            return np.load(cache)
     log(f"{name}: pre-shearing {args.c5_preshear} steps")
     t0 = time.perf_counter()
     with S.Sim(cfg, pos, tol=args.tol, maxit=5000, stream=stream) as sim:
@@ -328,7 +342,10 @@ def preshear(args, S, cfg, pos, stream, name):
             sim.step(1)
             if (k + 1) % 50 == 0:
                 log(f"{name}: pre-shear step {k + 1} ({time.perf_counter() - t0:.0f} s)")
-        return sim.state()[0]
+        out = sim.state()[0]
+    if cache:
+        np.save(cache, out)
+    return out
 
 
 def iteration_roofline(r, copy_gbs, traffic):

@@ -132,8 +132,8 @@ typedef struct sim_params {
    * isotropic method.  When any replica has a value other than 1 the handle
    * solves the block system: block-Jacobi CG over the 3n coupled unknowns,
    * one true-residual tolerance per replica on the stacked vector; steps run
-   * eagerly (no step graphs); precond must be Jacobi or none and spmv_fp32,
-   * warm_start 0, else SIM_ENOTSUP.                                          */
+   * eagerly (no step graphs); precond must be Jacobi, none or learned (the
+   * 3 x 3 heads below) and spmv_fp32, warm_start 0, else SIM_ENOTSUP.        */
   double friction_par;
   double friction_perp;
 } sim_params;
@@ -268,7 +268,8 @@ int sim_velocity_correlation(sim_t* sim, double r_max, int32_t nbins, int32_t fl
 int sim_set_stream(sim_t* sim, void* hip_stream);
 
 /* Load learned-preconditioner weights from a file: 8 bytes "SIMPC001", an
- * int64 count (= SIM_MPNN_NPARAMS), then the FP32 weights, little-endian.
+ * int64 count (SIM_MPNN_NPARAMS or SIM_MPNN_NPARAMS_BLOCK), then the FP32
+ * weights, little-endian, set as sim_precond_weights sets them.
  * SIM_EINVAL for a malformed file.                                        */
 int sim_load_precond(sim_t* sim, const char* path);
 
@@ -306,8 +307,9 @@ int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
  * A three-layer message-passing network on the pair graph of A (hidden 32)
  * maps node features (t_i, a_i, deg_i/8) and edge features (r_ij/rc, w_ij,
  * What_ij) to M^-1 = D^-1/2 (diag(lam) + S) D^-1/2 in A's sparsity, with
- * S_ij = z.(h_i*h_j) + ze.e_ij + z0 symmetric and lam_i = softplus(.) + 0.1
- * (D = diag A, What_ij = alpha w_ij / sqrt(D_i D_j)).  M^-1 is symmetric
+ * S_ij = z.(h_i*h_j) + ze.e_ij + z0 symmetric and lam_i = softplus(.) +
+ * floor (sim_precond_floor, 0.3 unless set; D = diag A,
+ * What_ij = alpha w_ij / sqrt(D_i D_j)).  M^-1 is symmetric
  * with a positive diagonal but positive definite only for suitable weights
  * (the best sparse approximate inverses of A are not diagonally dominant);
  * lam = 1, S = What is the two-term Neumann series of A^-1, which is.  It
@@ -319,10 +321,34 @@ int sim_debug_set_gaussians(sim_t* sim, const double* xi, const double* eta);
  * The weights are SIM_MPNN_NPARAMS FP32 values (bfloat16 in the kernels),
  * in this order: W0[32][3], b0[32], then per layer P[32][32], Q[32][3],
  * c[32], U[32][32], V[32][32], d[32], then v[32], v0, z[32], ze[3], z0.
- * A new handle starts with all weights zero: S = 0, lam = ln 2 + 0.1, a
- * scaled Jacobi preconditioner.                                           */
+ * A new handle starts with all weights zero: S = 0, lam = ln 2 + floor, a
+ * scaled Jacobi preconditioner.
+ *
+ * Anisotropic friction (the block system, friction_par / friction_perp;
+ * Discussion): the same network runs on the traces of A's 3 x 3 blocks,
+ * d_i = tr A_ii / 3 and omega_ij = tr W_ij / 3 (A_ij = -W_ij), in place of
+ * (D_i, alpha w_ij), and two more heads, mu_i = u.h_i + u0 and
+ * sig_ij = s.(h_i*h_j) + se.e_ij + s0, give 3 x 3 blocks in the frame
+ * where every diagonal block of A is the identity, R = blockdiag(A_ii^-1/2)
+ * (the block analogue of D^-1/2 above; symmetric roots):
+ *   Xh_ii = lam_i I + mu_i (d_i A_ii^-1 - I),
+ *   Xh_ij = S_ij I + sig_ij (R_i W_ij R_j - What_ij I),
+ *   M^-1 = R Xh R,
+ * stored block by block and applied as one more block product per CG
+ * iteration.  M^-1 is symmetric, turns with the system under rotations, and
+ * is the scalar network's times I_3 when every block of A is a multiple of
+ * I_3; lam = 1, mu = 0, S = What, sig = 1 give D^-1 + D^-1 (D - A) D^-1,
+ * D = blockdiag(A_ii), the two-term Neumann series of the block-Jacobi
+ * splitting (positive definite).  Weights trained on the scalar system
+ * carry over (in that frame their S_ij acts as on a scalar system).  A
+ * stalled or broken-down solve is redone with block-Jacobi.  The weights are
+ * SIM_MPNN_NPARAMS_BLOCK values: the SIM_MPNN_NPARAMS above, then u[32],
+ * u0, s[32], se[3], s0.                                                    */
 #define SIM_MPNN_NPARAMS 9893
-/* Copy the FP32 master weights in (set = 1) or out (set = 0).            */
+#define SIM_MPNN_NPARAMS_BLOCK 9962
+/* Copy the FP32 master weights in (set = 1) or out (set = 0): count =
+ * SIM_MPNN_NPARAMS (the anisotropy heads, used by block handles only, keep
+ * their values) or SIM_MPNN_NPARAMS_BLOCK.  Setting clears the Adam state. */
 int sim_precond_weights(sim_t* sim, float* theta, int64_t count, int32_t set);
 /* Activations entering the network's products are rounded to bfloat16
  * (round_act = 1, default) or kept in FP32 (0, for parity tests).
@@ -346,8 +372,8 @@ int sim_precond_floor(sim_t* sim, double lam_floor);
  * or when that system was built before the first preconditioner call on
  * the handle (sim_precond_weights, sim_precond_config, sim_load_precond,
  * sim_precond_floor; a Jacobi handle writes the network's edge input only
- * from then on); SIM_ENOTSUP for batches and for handles with anisotropic
- * friction.                                                               */
+ * from then on); SIM_ENOTSUP for batches.  Block handles train all
+ * SIM_MPNN_NPARAMS_BLOCK weights on the block system (A-norm of A's blocks). */
 int sim_train_step(sim_t* sim, double lr, double* loss);
 /* One training step on a white-noise probe of the current system (any
  * number of replicas; needs a successful solve): x* = z with z_ik ~ N(0, 1)
@@ -362,17 +388,19 @@ int sim_train_step(sim_t* sim, double lr, double* loss);
 int sim_train_probe(sim_t* sim, double lr, uint64_t seed, uint64_t index, int32_t euclid,
                     double* loss);
 /* Adam state of the training steps: first and second moments (count =
- * SIM_MPNN_NPARAMS each) and the step count t, copied out (set = 0) or in
- * (set = 1), so that training can move between handles.  Setting weights
- * with sim_precond_weights clears it.                                     */
+ * SIM_MPNN_NPARAMS or SIM_MPNN_NPARAMS_BLOCK each) and the step count t,
+ * copied out (set = 0) or in (set = 1), so that training can move between
+ * handles.  Setting weights with sim_precond_weights clears it.           */
 int sim_precond_optimizer(sim_t* sim, float* m1, float* m2, int64_t count, int32_t* t,
                           int32_t set);
-/* The gradient dL/dtheta of the last sim_train_step (with respect to the
- * bfloat16 weights), count = SIM_MPNN_NPARAMS.                           */
+/* The gradient dL/dtheta of the last training step (with respect to the
+ * bfloat16 weights), count = SIM_MPNN_NPARAMS or SIM_MPNN_NPARAMS_BLOCK
+ * (zero beyond the weights the handle trains).                           */
 int sim_precond_grad(sim_t* sim, float* grad, int64_t count);
 /* Parity export of the preconditioner of the current positions and step.
  * Learned: M^-1 in the form of sim_debug_system (off-diagonal triples,
- * diagonal).  IC(0): the strictly lower triangle of L (in the IC order) as
+ * diagonal); block handles write 9 values per entry (the row-major 3 x 3
+ * block M_ij) into vals and 9 per particle into mdiag.  IC(0): the strictly lower triangle of L (in the IC order) as
  * (row, col, L_row,col) triples at the positions of A's off-diagonal
  * entries, row = col = -1 in the slots of upper entries, and L's diagonal.
  * SIM_ENOTSUP for Jacobi and no preconditioner.                           */

@@ -412,23 +412,28 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
  * The trunk above runs unchanged on the scalar shadow of A, the traces
  *   d_i = tr(A_ii) / 3,  omega_ij = tr(W_ij) / 3,
  * in place of (diag, -val): its features are rotation invariant and equal
- * those of the isotropic system when every block is a multiple of I_3.  The
- * heads give four numbers per node / entry:
+ * those of the isotropic system when every block is a multiple of I_3
+ * (What_ij = omega_ij / sqrt(d_i d_j)).  The heads give four numbers per
+ * node / entry:
  *   lam_i  = softplus(v . h_i + v0) + eps          (the scalar node head)
  *   S_ij   = z . (h_i * h_j) + ze . e_ij + z0      (the scalar edge head)
  *   mu_i   = u . h_i + u0                          (node anisotropy)
  *   sig_ij = s . (h_i * h_j) + se . e_ij + s0      (edge anisotropy)
- * and the 3 x 3 blocks of the preconditioner are
- *   X_ii = lam_i A_ii + mu_i (A_ii - d_i I),
- *   X_ij = S_ij sqrt(d_i d_j) I + sig_ij (W_ij - omega_ij I),
- *   M^-1 = B X B,  B = blockdiag(A_ii^-1).
+ * and the preconditioner is built in the frame where every diagonal block
+ * of A is the identity, R = blockdiag(A_ii^-1/2) (symmetric roots), the
+ * block analogue of the scalar network's D^-1/2 (Lambda + S) D^-1/2:
+ *   Nh_ij = R_i W_ij R_j                           (normalised pair block)
+ *   Xh_ii = lam_i I + mu_i (d_i A_ii^-1 - I),
+ *   Xh_ij = S_ij I + sig_ij (Nh_ij - What_ij I),
+ *   M^-1 = R Xh R.
  * Built from I and A's own blocks only, M^-1 turns with the system under a
- * rotation; it is symmetric (X_ji = X_ij = X_ij^T); when every block of A is
- * a multiple of I_3 both anisotropy terms vanish and M^-1 is the scalar
+ * rotation; it is symmetric (Xh_ji = Xh_ij^T); when every block of A is a
+ * multiple of I_3 both anisotropy terms vanish and M^-1 is the scalar
  * network's preconditioner times I_3.  lam = 1, mu = 0, S = What, sig = 1
- * give M^-1 = B (2D - A) B, D = blockdiag(A_ii): the two-term Neumann series
- * of the block-Jacobi splitting, positive definite since each pair adds the
- * positive semidefinite [[W, W], [W, W]] to 2D - A = gamma0 I + ...
+ * give Xh = I + Nh, i.e. M^-1 = D^-1 + D^-1 (D - A) D^-1, D = blockdiag(A_ii):
+ * the two-term Neumann series of the block-Jacobi splitting, positive
+ * definite since each pair adds the positive semidefinite [[W, W], [W, W]]
+ * to 2D - A = gamma0 I + ...
  * Parameters: the scalar network's, then u[32], u0, s[32], se[3], s0.
  * =========================================================================== */
 #define NPHI (H + 1 + H + FE + 1)
@@ -439,36 +444,6 @@ double orc_mpnn_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col, 
 #define PHI_S0 (PHI_SE + FE)
 
 int64_t orc_mpnn_block_nparams(void) { return NPARAMS + NPHI; }
-
-/* inverse of a 3 x 3 matrix (row-major) by Gauss-Jordan elimination with
- * partial pivoting; -1 if singular */
-static int inv3(const double* a, double* out) {
-  double m[3][6];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 6; ++c) m[r][c] = c < 3 ? a[3 * r + c] : (c - 3 == r ? 1.0 : 0.0);
-  for (int c = 0; c < 3; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < 3; ++r)
-      if (fabs(m[r][c]) > fabs(m[piv][c])) piv = r;
-    if (m[piv][c] == 0.0) return -1;
-    if (piv != c)
-      for (int k = 0; k < 6; ++k) {
-        const double tmp = m[c][k];
-        m[c][k] = m[piv][k];
-        m[piv][k] = tmp;
-      }
-    const double p = m[c][c];
-    for (int k = 0; k < 6; ++k) m[c][k] /= p;
-    for (int r = 0; r < 3; ++r) {
-      if (r == c) continue;
-      const double f = m[r][c];
-      for (int k = 0; k < 6; ++k) m[r][k] -= f * m[c][k];
-    }
-  }
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) out[3 * r + c] = m[r][c + 3];
-  return 0;
-}
 
 /* out = a b c (3 x 3, row-major) */
 static void mul33(const double* a, const double* b, const double* c, double* out) {
@@ -487,16 +462,80 @@ static void mul33(const double* a, const double* b, const double* c, double* out
     }
 }
 
+/* eigenvalues w and orthonormal eigenvectors (columns of V) of a symmetric
+ * 3 x 3 matrix by the cyclic Jacobi method (Golub & Van Loan, sec. 8.5):
+ * rotations that zero one off-diagonal entry at a time, sweeps until the
+ * off-diagonal part is negligible */
+static void eig_sym3(const double* a, double* w, double* V) {
+  double m[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      m[r][c] = a[3 * r + c];
+      V[3 * r + c] = r == c ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = m[0][1] * m[0][1] + m[0][2] * m[0][2] + m[1][2] * m[1][2];
+    const double dia = m[0][0] * m[0][0] + m[1][1] * m[1][1] + m[2][2] * m[2][2];
+    if (off <= 1e-34 * dia) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (m[p][q] == 0.0) continue;
+        /* c, s of the rotation that zeroes m[p][q] (the smaller angle) */
+        const double theta = (m[q][q] - m[p][p]) / (2.0 * m[p][q]);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        /* m <- J^T m J, V <- V J, J the rotation in the (p, q) plane */
+        for (int k = 0; k < 3; ++k) {
+          const double mkp = m[k][p], mkq = m[k][q];
+          m[k][p] = c * mkp - s * mkq;
+          m[k][q] = s * mkp + c * mkq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double mpk = m[p][k], mqk = m[q][k];
+          m[p][k] = c * mpk - s * mqk;
+          m[q][k] = s * mpk + c * mqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+          V[3 * k + p] = c * vkp - s * vkq;
+          V[3 * k + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int k = 0; k < 3; ++k) w[k] = m[k][k];
+}
+
+/* f(a) = V diag(f(w)) V^T for symmetric positive definite a: power -1/2
+ * (inverse square root) or -1 (inverse); -1 if not positive definite */
+static int sym3_power(const double* a, double power, double* out) {
+  double w[3], V[9];
+  eig_sym3(a, w, V);
+  double fw[3];
+  for (int k = 0; k < 3; ++k) {
+    if (!(w[k] > 0.0)) return -1;
+    fw[k] = power == -1.0 ? 1.0 / w[k] : 1.0 / sqrt(w[k]);
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += V[3 * r + k] * fw[k] * V[3 * c + k];
+      out[3 * r + c] = s;
+    }
+  return 0;
+}
+
 typedef struct {
   net_t t;
   double phi[NPHI];     /* anisotropy head weights (bf16-valued) */
   double *val, *diag;   /* scalar shadow: -omega per entry, d per node */
-  double *binv;         /* n x 9: A_ii^-1 */
+  double *rt, *binv;    /* n x 9: A_ii^-1/2 and A_ii^-1 */
+  double *nh;           /* nnz x 9: Nh_ij = R_i W_ij R_j */
   double *md, *mo;      /* M^-1 blocks: n x 9, nnz x 9 */
 } bnet_t;
 
 static void bnet_free(bnet_t* B) {
-  free(B->val); free(B->diag); free(B->binv); free(B->md); free(B->mo);
+  free(B->val); free(B->diag); free(B->rt); free(B->binv); free(B->nh); free(B->md);
+  free(B->mo);
   net_free(&B->t);
 }
 
@@ -506,16 +545,25 @@ static int bnet_forward(bnet_t* B, int64_t n, const int64_t* rowptr, const int64
   const int64_t nnz = rowptr[n];
   B->val = (double*)calloc((size_t)(nnz + 1), sizeof(double));
   B->diag = (double*)calloc((size_t)(n + 1), sizeof(double));
+  B->rt = (double*)calloc((size_t)(9 * n + 1), sizeof(double));
   B->binv = (double*)calloc((size_t)(9 * n + 1), sizeof(double));
+  B->nh = (double*)calloc((size_t)(9 * nnz + 1), sizeof(double));
   B->md = (double*)calloc((size_t)(9 * n + 1), sizeof(double));
   B->mo = (double*)calloc((size_t)(9 * nnz + 1), sizeof(double));
-  if (!B->val || !B->diag || !B->binv || !B->md || !B->mo) return -2;
+  if (!B->val || !B->diag || !B->rt || !B->binv || !B->nh || !B->md || !B->mo) return -2;
   for (int64_t q = 0; q < nnz; ++q)
     B->val[q] = ((bval[9 * q] + bval[9 * q + 4]) + bval[9 * q + 8]) / 3.0;
   for (int64_t i = 0; i < n; ++i) {
     B->diag[i] = ((bdiag[9 * i] + bdiag[9 * i + 4]) + bdiag[9 * i + 8]) / 3.0;
-    if (inv3(bdiag + 9 * i, B->binv + 9 * i) != 0) return -1;
+    if (sym3_power(bdiag + 9 * i, -0.5, B->rt + 9 * i) != 0) return -1;
+    if (sym3_power(bdiag + 9 * i, -1.0, B->binv + 9 * i) != 0) return -1;
   }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      double W[9];
+      for (int m = 0; m < 9; ++m) W[m] = -bval[9 * q + m];
+      mul33(B->rt + 9 * i, W, B->rt + 9 * col[q], B->nh + 9 * q);
+    }
   net_t* t = &B->t;
   t->n = n; t->nnz = nnz; t->rowptr = rowptr; t->col = col; t->val = B->val;
   t->diag = B->diag; t->edge_r = edge_r; t->alpha = alpha;
@@ -526,27 +574,28 @@ static int bnet_forward(bnet_t* B, int64_t n, const int64_t* rowptr, const int64
   const double* ph = B->phi;
   const double* hf = t->hs + (int64_t)NL * n * H;
   for (int64_t i = 0; i < n; ++i) {
-    const double* Ai = bdiag + 9 * i;
+    const double* Ri = B->rt + 9 * i;
     const double di = B->diag[i];
     double mu = ph[PHI_U0];
     for (int k = 0; k < H; ++k) mu += ph[PHI_U + k] * hf[i * H + k];
     const double lam = softplus(t->tau[i]) + EPS_LAM;
     double X[9];
-    for (int m = 0; m < 9; ++m) X[m] = lam * Ai[m] + mu * (Ai[m] - (m % 4 == 0 ? di : 0.0));
-    mul33(B->binv + 9 * i, X, B->binv + 9 * i, B->md + 9 * i);
+    for (int m = 0; m < 9; ++m) {
+      const double id = m % 4 == 0 ? 1.0 : 0.0;
+      X[m] = lam * id + mu * (di * B->binv[9 * i + m] - id);
+    }
+    mul33(Ri, X, Ri, B->md + 9 * i);
     for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
       const int64_t j = col[q];
       double sg = ph[PHI_S0];
       for (int k = 0; k < H; ++k) sg += ph[PHI_S + k] * (hf[i * H + k] * hf[j * H + k]);
       for (int f = 0; f < FE; ++f) sg += ph[PHI_SE + f] * t->e[FE * q + f];
-      const double om = -B->val[q];
-      const double sq = sqrt(di * B->diag[j]);
+      const double what = t->what[q];
       for (int m = 0; m < 9; ++m) {
-        const double w = -bval[9 * q + m];
         const double id = m % 4 == 0 ? 1.0 : 0.0;
-        X[m] = t->tg[q] * sq * id + sg * (w - om * id);
+        X[m] = t->tg[q] * id + sg * (B->nh[9 * q + m] - what * id);
       }
-      mul33(B->binv + 9 * i, X, B->binv + 9 * j, B->mo + 9 * q);
+      mul33(Ri, X, B->rt + 9 * j, B->mo + 9 * q);
     }
   }
   return 0;
@@ -584,10 +633,10 @@ static void bsys_mul(int64_t n, const int64_t* rowptr, const int64_t* col, const
 /* Loss L = ||M^-1 b - x*||^2 / ||x*||^2 on the block system, in the A-norm
  * (euclid = 0) or the Euclidean norm (euclid = 1), and, if grad is given,
  * dL/dtheta (NPARAMS + NPHI values).  dL/dM_ij = G_i b_j^T with
- * G = 2 W (M^-1 b - x*) / ||x*||_W^2; through M^-1 = B X B,
- * dL/dX_ij = B_i dL/dM_ij B_j, and the heads enter X linearly:
- *   dL/dlam_i = <dX_ii, A_ii>, dL/dmu_i = <dX_ii, A_ii - d_i I>,
- *   dL/dS_ij = sqrt(d_i d_j) tr dX_ij, dL/dsig_ij = <dX_ij, W_ij - omega_ij I>
+ * G = 2 W (M^-1 b - x*) / ||x*||_W^2; through M^-1 = R Xh R,
+ * dL/dXh_ij = R_i dL/dM_ij R_j, and the heads enter Xh linearly:
+ *   dL/dlam_i = tr dXh_ii, dL/dmu_i = <dXh_ii, d_i A_ii^-1 - I>,
+ *   dL/dS_ij = tr dXh_ij, dL/dsig_ij = <dXh_ij, Nh_ij - What_ij I>
  * (<., .> the Frobenius product).                                          */
 double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t* col,
                                 const double* bval, const double* bdiag, const double* edge_r,
@@ -595,7 +644,6 @@ double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t*
                                 const double* xstar, int euclid, double* grad) {
   bnet_t B;
   memset(&B, 0, sizeof(B));
-  const int64_t nnz = rowptr[n];
   double* z = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
   double* ae = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
   double* ax = (double*)calloc((size_t)(3 * n + 1), sizeof(double));
@@ -637,8 +685,7 @@ double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t*
       goto out;
     }
     for (int64_t i = 0; i < n; ++i) {
-      const double* Ai = bdiag + 9 * i;
-      const double* Bi = B.binv + 9 * i;
+      const double* Ri = B.rt + 9 * i;
       const double di = B.diag[i];
       double gi[3];
       for (int c = 0; c < 3; ++c) gi[c] = 2.0 * ae[3 * i + c] / den;
@@ -646,11 +693,12 @@ double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t*
       double dM[9], dX[9];
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) dM[3 * r + c] = gi[r] * b[3 * i + c];
-      mul33(Bi, dM, Bi, dX);
+      mul33(Ri, dM, Ri, dX);
       double dlam = 0.0, dmu = 0.0;
       for (int m = 0; m < 9; ++m) {
-        dlam += dX[m] * Ai[m];
-        dmu += dX[m] * (Ai[m] - (m % 4 == 0 ? di : 0.0));
+        const double id = m % 4 == 0 ? 1.0 : 0.0;
+        dlam += dX[m] * id;
+        dmu += dX[m] * (di * B.binv[9 * i + m] - id);
       }
       const double gt = dlam * sigm(t->tau[i]);
       gh[H_V0] += gt;
@@ -665,15 +713,14 @@ double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t*
         const int64_t j = col[q];
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c) dM[3 * r + c] = gi[r] * b[3 * j + c];
-        mul33(Bi, dM, B.binv + 9 * j, dX);
-        const double om = -B.val[q];
-        double tr = 0.0, dsg = 0.0;
+        mul33(Ri, dM, B.rt + 9 * j, dX);
+        const double what = t->what[q];
+        double dS = 0.0, dsg = 0.0;
         for (int m = 0; m < 9; ++m) {
           const double id = m % 4 == 0 ? 1.0 : 0.0;
-          tr += dX[m] * id;
-          dsg += dX[m] * (-bval[9 * q + m] - om * id);
+          dS += dX[m] * id;
+          dsg += dX[m] * (B.nh[9 * q + m] - what * id);
         }
-        const double dS = sqrt(di * B.diag[j]) * tr;
         gh[H_Z0] += dS;
         gp[PHI_S0] += dsg;
         for (int f = 0; f < FE; ++f) {
@@ -695,6 +742,5 @@ double orc_mpnn_block_loss_grad(int64_t n, const int64_t* rowptr, const int64_t*
 out:
   free(z); free(ae); free(ax);
   bnet_free(&B);
-  (void)nnz;
   return loss;
 }

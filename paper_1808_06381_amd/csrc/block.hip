@@ -41,6 +41,13 @@ __device__ __forceinline__ void sym_mul(const double* m, const double v[3], doub
   out[2] = (m[2] * v[0] + m[4] * v[1]) + m[5] * v[2];
 }
 
+// row-major 3 x 3 in FP32 (the learned preconditioner's M_ij) times a vector
+__device__ __forceinline__ void full_mul(const float* a, const double v[3], double out[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    out[r] = ((double)a[3 * r] * v[0] + (double)a[3 * r + 1] * v[1]) + (double)a[3 * r + 2] * v[2];
+}
+
 __device__ __forceinline__ void sym_inverse(const double* m, double* inv) {
   const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
   const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
@@ -149,6 +156,10 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_block(DevPtrs d, BlockPtrs 
         out[m] = -W[m];
         contrib[m][t] = W[m];
       }
+      if (d.want_er) {  // the learned preconditioner's input: traces, r / rc
+        d.val[e] = -((W[0] + W[3]) + W[5]) / 3.0;
+        d.er[e] = (float)(r / R.rc);
+      }
       // conservative force and boundary drag W V, V = kappa Ly s x (column 0)
       const double fc = pforce(R, r2, r);
       const double v = vunit * (double)s;
@@ -193,6 +204,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_block(DevPtrs d, BlockPtrs 
     Dp[0] = Dp[3] = Dp[5] = Ip[0] = Ip[3] = Ip[5] = 1.0;
     Dp[1] = Dp[2] = Dp[4] = Ip[1] = Ip[2] = Ip[4] = 0.0;
     d.b[3 * i] = d.b[3 * i + 1] = d.b[3 * i + 2] = 0.0;
+    if (d.want_er) d.diag[i] = 1.0;
     return;
   }
   const double4 pi = d.pos[i];
@@ -206,6 +218,7 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_block(DevPtrs d, BlockPtrs 
 #pragma unroll
   for (int m = 0; m < 6; ++m) Dout[m] = D[m];
   sym_inverse(D, bp.binv + 6 * i);
+  if (d.want_er) d.diag[i] = ((D[0] + D[3]) + D[5]) / 3.0;
   d.b[3 * i] = R.gamma0 * R.shear * (pi.y - R.hL[1]) + R.amp_node * gn[0] + acc[0];
   d.b[3 * i + 1] = R.amp_node * gn[1] + acc[1];
   d.b[3 * i + 2] = R.amp_node * gn[2] + acc[2];
@@ -281,7 +294,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs
       sym_mul(bp.binv + 6 * i, r, z);
       if (lane < 3) {
         d.r[3 * i + lane] = r[lane];
-        d.u[3 * i + lane] = z[lane];
+        if (!bp.learned) d.u[3 * i + lane] = z[lane];  // learned: k_bcg_apply forms u
         d.p[3 * i + lane] = 0.0;
         d.s[3 * i + lane] = 0.0;
         v1 += r[lane] * z[lane];
@@ -337,9 +350,55 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_vec(DevPtrs d, BlockPtrs 
   rs[3 * t + 1] = z[1];
   rs[3 * t + 2] = z[2];
   __syncthreads();
+  if (!bp.learned)  // learned: k_bcg_apply forms u
 #pragma unroll
-  for (int q = 0; q < 3; ++q) d.u[base + q * BLOCK_THREADS + t] = rs[q * BLOCK_THREADS + t];
+    for (int q = 0; q < 3; ++q) d.u[base + q * BLOCK_THREADS + t] = rs[q * BLOCK_THREADS + t];
   tile_partials<2>(d, tile, 1, v);
+}
+
+// the learned preconditioner: u = M^-1 r with the stored blocks (M_ii
+// symmetric FP64, M_ij row-major FP32), partial (r, u) into slot 1 (over the
+// (r, B r) the vector pass or residual round left there).  mode 0 after a
+// vector pass, 1 in a residual round.  Lanes and turns as k_bcg_spmv.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_apply(DevPtrs d, BlockPtrs bp, int mode) {
+  const int tile = xcd_block(blockIdx.x, d.nblk);
+  if (tile >= d.nblk) return;
+  const BcgRep& B = bp.bcg[d.blk_rep[tile]];
+  if (B.state != (mode == 0 ? 0 : 1)) return;
+  const int lane = threadIdx.x & (BLANES - 1);
+  double v1 = 0.0;
+  for (int turn = 0; turn < BLANES; ++turn) {
+    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + turn * (BLOCK_THREADS / BLANES) +
+                      (threadIdx.x / BLANES);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t e1 = d.rowptr[i + 1];
+    for (int64_t e = d.rowptr[i] + lane; e < e1; e += BLANES) {
+      const int64_t j = d.col[e];
+      const double rj[3] = {d.r[3 * j], d.r[3 * j + 1], d.r[3 * j + 2]};
+      double o[3];
+      full_mul(bp.xo + 9 * e, rj, o);
+      acc[0] += o[0];
+      acc[1] += o[1];
+      acc[2] += o[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc[k] += __shfl_xor(acc[k], 1, 64);
+      acc[k] += __shfl_xor(acc[k], 2, 64);
+    }
+    const double ri[3] = {d.r[3 * i], d.r[3 * i + 1], d.r[3 * i + 2]};
+    double dg[3];
+    sym_mul(bp.xd + 6 * i, ri, dg);
+    double u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = dg[k] + acc[k];
+    if (lane < 3) {
+      d.u[3 * i + lane] = u[lane];
+      v1 += d.r[3 * i + lane] * u[lane];
+    }
+  }
+  double v[1] = {v1};
+  tile_partials<1>(d, tile, 1, v);
 }
 
 // one block per replica: the tile partials [(w, u), (r, u), (r, r)] in tile
@@ -449,6 +508,8 @@ hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, h
 
 hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
   hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
+  if (bp.learned)
+    hipLaunchKernelGGL(k_bcg_apply, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
   hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 2);
   return hipGetLastError();
 }
@@ -457,6 +518,8 @@ hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream
   hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
   hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 0);
   hipLaunchKernelGGL(k_bcg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
+  if (bp.learned)
+    hipLaunchKernelGGL(k_bcg_apply, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
   return hipGetLastError();
 }
 

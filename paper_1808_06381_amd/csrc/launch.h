@@ -130,6 +130,16 @@ struct BlockPtrs {
   double* binv;         // its inverse (6 values): the block-Jacobi preconditioner
   BcgRep* bcg;          // [replicas]
   const BlockRep* brep; // [replicas]
+  // learned preconditioner with 3 x 3 heads: M^-1 = R Xh R, R = blockdiag(A_ii^-1/2)
+  double* rsq;          // [rows][6] R_i
+  double* xd;           // [rows][6] M_ii
+  float* xo;            // [nnz][9] M_ij, row-major
+  double* t;            // [rows][3] R b (training)
+  double* bh;           // [rows][3] A_ii^-1 b (training)
+  double* gt;           // [rows][3] R G (training)
+  double* gh;           // [rows][3] A_ii^-1 G (training)
+  int32_t learned;      // 1: the block CG applies the learned M^-1
+  int32_t pad0;
 };
 hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
 hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, hipStream_t s);
@@ -138,3 +148,14 @@ hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream
 hipError_t launch_block_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
                                int64_t* rows, int64_t* cols, double* vals, double* diag,
                                double* rhs, hipStream_t s);
+// the learned preconditioner on the block system (mpnn.hip)
+hipError_t launch_mp_trunk(const DevPtrs& d, const MpPtrs& m, hipStream_t s);
+hipError_t launch_mpb_heads(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_mpb_loss(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_mpb_backward(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp,
+                               hipStream_t s);
+hipError_t launch_mpb_probe(const DevPtrs& d, const BlockPtrs& bp, double* z, double* b,
+                            uint64_t seed, uint64_t index, hipStream_t s);
+hipError_t launch_mpb_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                             int64_t* rows, int64_t* cols, double* vals, int64_t cap, double* diag,
+                             hipStream_t s);

@@ -30,6 +30,16 @@
 #define MP_H_ZE (MP_H_Z + MP_H)
 #define MP_H_Z0 (MP_H_ZE + MP_FE)
 #define MP_NPARAMS (MP_OFF_HEAD + MP_H_Z0 + 1)
+// the 3 x 3 heads on the anisotropic block system (after the scalar network):
+// mu_i = u.h_i + u0, sig_ij = s.(h_i*h_j) + se.e_ij + s0
+#define MP_OFF_PHI MP_NPARAMS
+#define MP_PHI_U 0
+#define MP_PHI_U0 (MP_PHI_U + MP_H)
+#define MP_PHI_S (MP_PHI_U0 + 1)
+#define MP_PHI_SE (MP_PHI_S + MP_H)
+#define MP_PHI_S0 (MP_PHI_SE + MP_FE)
+#define MP_NPHI (MP_PHI_S0 + 1)
+#define MP_NPARAMS_ALL (MP_NPARAMS + MP_NPHI)
 
 struct MpPtrs {
   uint16_t* w16;   // bf16 weights used by the kernels
@@ -37,7 +47,7 @@ struct MpPtrs {
   float* am;       // Adam first moment
   float* av;       // Adam second moment
   float* grad;     // gradient of the last training step
-  float* gpart;    // [blocks][MP_NPARAMS] partial gradients
+  float* gpart;    // [blocks][MP_NPARAMS_ALL] partial gradients
   float* x;        // [rows][3] node features
   float* ef;       // [nnz][3] edge features
   float* er;       // [nnz] r_ij / rc (written by the pair-terms kernel)
@@ -66,7 +76,7 @@ struct MpPtrs {
   int round_act;   // 1: round activations entering products to bf16
   int store_train; // 1: keep m and a for the backward pass
   int loss_euclid; // loss norm: 0 the A-norm, 1 the Euclidean norm
-  int pad0;        // explicit: the host compares whole structs bytewise
+  int nparams;     // parameters trained: MP_NPARAMS (scalar) or MP_NPARAMS_ALL (blocks)
   double lam_floor; // floor added to the diagonal head: lam = softplus(.) + lam_floor
 };
 static_assert(sizeof(MpPtrs) % 8 == 0, "MpPtrs must have no implicit tail padding");

@@ -819,7 +819,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_bwd(DevPtrs d, MpPtrs m
     }
     m.dh[i * MP_H + k] = dh;
   }
-  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + MP_OFF_HEAD;
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS_ALL + MP_OFF_HEAD;
   slot_reduce_store(g_v, red, dst + MP_H_V);
   slot_reduce_store(g_z, red, dst + MP_H_Z);
   // scalar terms live in lane 0 of each slot
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_a(DevPtrs d, MpPtrs
     m.dm[i * MP_H + k] = sv;
     __syncthreads();
   }
-  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + base;
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS_ALL + base;
   slot_reduce_matrix(accU, red, dst + MP_L_U);
   slot_reduce_matrix(accV, red, dst + MP_L_V);
   slot_reduce_store(accd, red, dst + MP_L_D);
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_layer_bwd_b(DevPtrs d, MpPtrs
     m.dh[j * MP_H + k] = m.dh2[j * MP_H + k] + sp;  // dL/dh^l for the next part A
     __syncthreads();
   }
-  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS + base;
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS_ALL + base;
   slot_reduce_matrix(accP, red, dst + MP_L_P);
   slot_reduce_store(accc, red, dst + MP_L_C);
   for (int f = 0; f < MP_FE; ++f) {
@@ -969,7 +969,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_bwd(DevPtrs d, MpPtrs 
       for (int f = 0; f < MP_FN; ++f) gw[f] += dh * x[f];
     }
   }
-  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS;
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS_ALL;
   slot_reduce_store(gb, red, dst + MP_OFF_B0);
   for (int f = 0; f < MP_FN; ++f) {
     red[threadIdx.x] = gw[f];
@@ -983,19 +983,24 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_bwd(DevPtrs d, MpPtrs 
   }
 }
 
-// grad[p] = (1/den) sum_b gpart[b][p], blocks in order
+// grad[p] = (1/den) sum_b gpart[b][p], blocks in order (zero beyond the
+// parameters this handle trains)
 __global__ __launch_bounds__(256) void k_mp_grad_reduce(MpPtrs m, int nblk) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= MP_NPARAMS) return;
+  if (p >= MP_NPARAMS_ALL) return;
+  if (p >= m.nparams) {
+    m.grad[p] = 0.0f;
+    return;
+  }
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += m.gpart[(int64_t)b * MP_NPARAMS + p];
+  for (int b = 0; b < nblk; ++b) s += m.gpart[(int64_t)b * MP_NPARAMS_ALL + p];
   m.grad[p] = (float)(s * m.loss[1]);
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master weights, then the bf16 copy
 __global__ __launch_bounds__(256) void k_mp_adam(MpPtrs m, float lr, int t) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= MP_NPARAMS) return;
+  if (p >= m.nparams) return;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const float g = m.grad[p];
   const float mo = b1 * m.am[p] + (1.0f - b1) * g;
@@ -1012,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_mp_adam(MpPtrs m, float lr, int t) {
 // bf16 copy of the master weights
 __global__ __launch_bounds__(256) void k_mp_cast(MpPtrs m) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < MP_NPARAMS) m.w16[p] = bf16_bits(m.th32[p]);
+  if (p < MP_NPARAMS_ALL) m.w16[p] = bf16_bits(m.th32[p]);
 }
 
 // parity export of M^-1 in global original numbering (as k_export_system)
@@ -1068,25 +1073,478 @@ __global__ __launch_bounds__(256) void k_mp_probe_b(DevPtrs d, const double* __r
 }
 
 // ---------------------------------------------------------------------------
+// 3 x 3 heads on the anisotropic block system (A_ii = gamma0 I + sum_j W_ij,
+// A_ij = -W_ij).  The trunk above runs on the traces d_i = tr A_ii / 3 and
+// -omega_ij = -tr W_ij / 3 (written to d.diag and d.val by the block pair
+// pass), so its features are rotation invariant (What_ij = omega_ij /
+// sqrt(d_i d_j)); the heads give lam_i, S_ij (the scalar heads) and
+// mu_i = u.h_i + u0, sig_ij = s.(h_i*h_j) + se.e_ij + s0.  The blocks live in
+// the frame where every diagonal block of A is the identity,
+// R = blockdiag(A_ii^-1/2) (the block analogue of the scalar D^-1/2):
+//   Nh_ij = R_i W_ij R_j,
+//   Xh_ii = lam_i I + mu_i (d_i A_ii^-1 - I),
+//   Xh_ij = S_ij I + sig_ij (Nh_ij - What_ij I),
+//   M^-1 = R Xh R, i.e. with B = A_ii^-1 = R^2:
+//   M_ii = lam_i B_i + mu_i (d_i B_i^2 - B_i),
+//   M_ij = (S_ij - sig_ij What_ij) R_i R_j + sig_ij B_i W_ij B_j.
+// Symmetric (M_ji = M_ij^T), turning with the system, and the scalar
+// network's M^-1 times I_3 when every block of A is a multiple of I_3.  The
+// blocks of M^-1 are stored (M_ii in FP64, M_ij in FP32, row-major) and the
+// block CG applies them as one more block product per iteration.
+// ---------------------------------------------------------------------------
+namespace {
+
+// 3 x 3 symmetric (xx, xy, xz, yy, yz, zz) times a vector
+__device__ __forceinline__ void bsym_mul(const double* a, const double v[3], double out[3]) {
+  out[0] = (a[0] * v[0] + a[1] * v[1]) + a[2] * v[2];
+  out[1] = (a[1] * v[0] + a[3] * v[1]) + a[4] * v[2];
+  out[2] = (a[2] * v[0] + a[4] * v[1]) + a[5] * v[2];
+}
+
+// row-major 3 x 3 (FP32) times a vector
+__device__ __forceinline__ void bfull_mul(const float* a, const double v[3], double out[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    out[r] = ((double)a[3 * r] * v[0] + (double)a[3 * r + 1] * v[1]) + (double)a[3 * r + 2] * v[2];
+}
+
+// row-major 3 x 3 of a symmetric 6-value block
+__device__ __forceinline__ void bsym_full(const double* a, double out[9]) {
+  const int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+#pragma unroll
+  for (int q = 0; q < 9; ++q) out[q] = a[map[q]];
+}
+
+// out = a b (row-major 3 x 3)
+__device__ __forceinline__ void bmul33(const double a[9], const double b[9], double out[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      out[3 * r + c] = (a[3 * r] * b[c] + a[3 * r + 1] * b[3 + c]) + a[3 * r + 2] * b[6 + c];
+}
+
+// A^-1/2 of a symmetric positive definite 3 x 3 (six values in and out):
+// eigenvectors by cyclic Jacobi rotations (each zeroes one off-diagonal
+// entry; sweeps until the off-diagonal part is below 1e-34 of the diagonal,
+// at most 12), then V diag(w^-1/2) V^T
+__device__ void sym3_inv_sqrt(const double* a6, double* out6) {
+  double m[3][3], V[3][3];
+  const int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m[r][c] = a6[map[3 * r + c]];
+      V[r][c] = r == c ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = (m[0][1] * m[0][1] + m[0][2] * m[0][2]) + m[1][2] * m[1][2];
+    const double dia = (m[0][0] * m[0][0] + m[1][1] * m[1][1]) + m[2][2] * m[2][2];
+    if (off <= 1e-34 * dia) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = m[p][q];
+      if (apq == 0.0) continue;
+      const double theta = (m[q][q] - m[p][p]) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double mkp = m[k][p], mkq = m[k][q];
+        m[k][p] = c * mkp - s * mkq;
+        m[k][q] = s * mkp + c * mkq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double mpk = m[p][k], mqk = m[q][k];
+        m[p][k] = c * mpk - s * mqk;
+        m[q][k] = s * mpk + c * mqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][q] = s * vkp + c * vkq;
+      }
+    }
+  }
+  const double f[3] = {1.0 / sqrt(m[0][0]), 1.0 / sqrt(m[1][1]), 1.0 / sqrt(m[2][2])};
+  const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int r = rr[q], c = cc[q];
+    out6[q] = (V[r][0] * f[0] * V[c][0] + V[r][1] * f[1] * V[c][1]) + V[r][2] * f[2] * V[c][2];
+  }
+}
+
+// the final hidden state as the heads consume it (bf16 when activations are
+// rounded: the rounded copy the last layer wrote)
+__device__ __forceinline__ float head_h(const MpPtrs& m, int64_t i, int k) {
+  if (m.round_act) return bf16_value(m.hb[i * MP_H + k]);
+  return m.h[((int64_t)MP_NL * m.rows + i) * MP_H + k];
+}
+
+__device__ __forceinline__ float head_ef(const MpPtrs& m, int64_t e, int f) {
+  if (m.round_act) return bf16_value(m.efh[4 * e + f]);
+  return m.ef[3 * e + f];
+}
+
+}  // namespace
+
+// R_i = A_ii^-1/2 of every row (padding rows: the identity)
+__global__ __launch_bounds__(256) void k_mpb_root(DevPtrs d, BlockPtrs bp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  sym3_inv_sqrt(bp.bdiag + 6 * i, bp.rsq + 6 * i);
+}
+
+// heads: the blocks M_ii and M_ij; one half-wave per node, lane k = hidden
+// feature k
+__global__ __launch_bounds__(MP_THREADS) void k_mpb_heads(DevPtrs d, MpPtrs m, BlockPtrs bp) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
+  __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1], hu[MP_H + 1], hs[MP_H], hse[MP_FE + 1];
+  load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
+  load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
+  load_w(m, hze, MP_OFF_HEAD + MP_H_ZE, MP_FE + 1);
+  load_w(m, hu, MP_OFF_PHI + MP_PHI_U, MP_H + 1);
+  load_w(m, hs, MP_OFF_PHI + MP_PHI_S, MP_H);
+  load_w(m, hse, MP_OFF_PHI + MP_PHI_SE, MP_FE + 1);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const float hk = head_h(m, i, k);
+    const float tau = half_sum(hv[k] * hk) + hv[MP_H];
+    const float mu = half_sum(hu[k] * hk) + hu[MP_H];
+    const double di = d.diag[i];
+    double Ri[9], Bi[9];
+    bsym_full(bp.rsq + 6 * i, Ri);
+    bsym_full(bp.binv + 6 * i, Bi);
+    const int e0 = d.rowptr[i], e1 = d.rowptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+      const int64_t j = d.col[e];
+      const float hj = head_h(m, j, k);
+      float t = half_sum(hz[k] * (hk * hj));
+      float sg = half_sum(hs[k] * (hk * hj));
+#pragma unroll
+      for (int f = 0; f < MP_FE; ++f) {
+        const float ef = head_ef(m, e, f);
+        t += hze[f] * ef;
+        sg += hse[f] * ef;
+      }
+      t += hze[MP_FE];
+      sg += hse[MP_FE];
+      if (k == 0) {
+        // M_ij = (S - sig What) R_i R_j + sig B_i W B_j, W = -bval
+        double Rj[9], Bj[9], W[9], P[9], T[9], Q[9];
+        bsym_full(bp.rsq + 6 * j, Rj);
+        bsym_full(bp.binv + 6 * j, Bj);
+        bsym_full(bp.bval + 6 * (int64_t)e, W);
+        bmul33(Ri, Rj, P);
+        bmul33(Bi, W, T);
+        bmul33(T, Bj, Q);
+        const double what = -d.val[e] / sqrt(di * d.diag[j]);
+        const double a = (double)t - (double)sg * what, c = -(double)sg;  // -sig: W = -bval
+        float* mo = bp.xo + 9 * (int64_t)e;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) mo[q] = (float)(a * P[q] + c * Q[q]);
+      }
+    }
+    if (k == 0) {
+      if (m.store_train) m.tau[i] = tau;
+      const double lam = (double)softplusf_(tau) + m.lam_floor;
+      // M_ii = lam B + mu (d B^2 - B)
+      double B2[9];
+      bmul33(Bi, Bi, B2);
+      const double* b6 = bp.binv + 6 * i;
+      const int full[6] = {0, 1, 2, 4, 5, 8};
+      double* md = bp.xd + 6 * i;
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        md[q] = lam * b6[q] + (double)mu * (di * B2[full[q]] - b6[q]);
+    }
+  }
+}
+
+// zb = M^-1 b - x*
+__global__ __launch_bounds__(256) void k_mpb_resid(DevPtrs d, MpPtrs m, BlockPtrs bp) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const double bi[3] = {d.b[3 * i], d.b[3 * i + 1], d.b[3 * i + 2]};
+  double acc[3];
+  bsym_mul(bp.xd + 6 * i, bi, acc);
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int64_t j = d.col[e];
+    const double bj[3] = {d.b[3 * j], d.b[3 * j + 1], d.b[3 * j + 2]};
+    double o[3];
+    bfull_mul(bp.xo + 9 * (int64_t)e, bj, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += o[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m.zb[3 * i + c] = acc[c] - d.x[3 * i + c];
+}
+
+// G = 2 W zb and partials (zb.W zb, x*.W x*), W = A or I
+__global__ __launch_bounds__(256) void k_mpb_aprod(DevPtrs d, MpPtrs m, BlockPtrs bp) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
+  __shared__ double lds[4][2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double num = 0.0, den = 0.0;
+  if (i < d.rows) {
+    const double zi[3] = {m.zb[3 * i], m.zb[3 * i + 1], m.zb[3 * i + 2]};
+    const double xi[3] = {d.x[3 * i], d.x[3 * i + 1], d.x[3 * i + 2]};
+    double az[3], ax[3];
+    if (m.loss_euclid) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        az[c] = zi[c];
+        ax[c] = xi[c];
+      }
+    } else {
+      bsym_mul(bp.bdiag + 6 * i, zi, az);
+      bsym_mul(bp.bdiag + 6 * i, xi, ax);
+      for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+        const int64_t j = d.col[e];
+        const double zj[3] = {m.zb[3 * j], m.zb[3 * j + 1], m.zb[3 * j + 2]};
+        const double xj[3] = {d.x[3 * j], d.x[3 * j + 1], d.x[3 * j + 2]};
+        double oz[3], ox[3];
+        bsym_mul(bp.bval + 6 * (int64_t)e, zj, oz);
+        bsym_mul(bp.bval + 6 * (int64_t)e, xj, ox);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          az[c] += oz[c];
+          ax[c] += ox[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      m.G[3 * i + c] = 2.0 * az[c];
+      num += zi[c] * az[c];
+      den += xi[c] * ax[c];
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6][0] = num;
+    lds[threadIdx.x >> 6][1] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double s = 0.0;
+    for (int w = 0; w < 4; ++w) s += lds[w][threadIdx.x];
+    m.lpart[2 * (int64_t)blockIdx.x + threadIdx.x] = s;
+  }
+}
+
+// the node-local transforms of G and b the heads' backward reads:
+// R G, B G, R b, B b
+__global__ __launch_bounds__(256) void k_mpb_pre(DevPtrs d, MpPtrs m, BlockPtrs bp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const double g[3] = {m.G[3 * i], m.G[3 * i + 1], m.G[3 * i + 2]};
+  const double b[3] = {d.b[3 * i], d.b[3 * i + 1], d.b[3 * i + 2]};
+  double o[4][3];
+  bsym_mul(bp.rsq + 6 * i, g, o[0]);
+  bsym_mul(bp.binv + 6 * i, g, o[1]);
+  bsym_mul(bp.rsq + 6 * i, b, o[2]);
+  bsym_mul(bp.binv + 6 * i, b, o[3]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    bp.gt[3 * i + c] = o[0][c];
+    bp.gh[3 * i + c] = o[1][c];
+    bp.t[3 * i + c] = o[2][c];
+    bp.bh[3 * i + c] = o[3][c];
+  }
+}
+
+// heads backward.  With g = R G, gh = B G, c = R b, ch = B b (bp.gt, gh, t,
+// bh), dL/dXh_ij = g_i c_j^T, so
+//   dL/dlam_i = g_i.c_i,  dL/dmu_i = d_i gh_i.ch_i - g_i.c_i,
+//   dL/dS_ij = g_i.c_j,   dL/dsig_ij = gh_i.W_ij ch_j - What_ij g_i.c_j
+// (unscaled by 1/den: the reduction applies it); dL/dh^3 into dh and the head
+// parameters v, v0, z, ze, z0, u, u0, s, se, s0
+__global__ __launch_bounds__(MP_THREADS) void k_mpb_heads_bwd(DevPtrs d, MpPtrs m, BlockPtrs bp) {
+  if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
+  __shared__ float hv[MP_H + 1], hz[MP_H], hu[MP_H + 1], hs[MP_H];
+  __shared__ float red[NODES * MP_H];
+  load_w(m, hv, MP_OFF_HEAD + MP_H_V, MP_H + 1);
+  load_w(m, hz, MP_OFF_HEAD + MP_H_Z, MP_H);
+  load_w(m, hu, MP_OFF_PHI + MP_PHI_U, MP_H + 1);
+  load_w(m, hs, MP_OFF_PHI + MP_PHI_S, MP_H);
+  __syncthreads();
+  const int slot = threadIdx.x / MP_H, k = threadIdx.x % MP_H;
+  const float* __restrict__ hf = m.h + (int64_t)MP_NL * m.rows * MP_H;
+  float g_v = 0.0f, g_z = 0.0f, g_u = 0.0f, g_s = 0.0f;
+  // scalar terms (lane 0 of each slot): v0, z0, ze[3], u0, s0, se[3]
+  float g_sc[10] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  auto ld3 = [](const double* p, int64_t r, double (&v)[3]) {
+    v[0] = p[3 * r];
+    v[1] = p[3 * r + 1];
+    v[2] = p[3 * r + 2];
+  };
+  auto dot3 = [](const double (&a)[3], const double (&b)[3]) {
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+  };
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t i = (int64_t)blockIdx.x * MP_ROWS + pass * NODES + slot;
+    const double di = d.diag[i];
+    double gi[3], ghi[3], ci[3], chi[3];
+    ld3(bp.gt, i, gi);
+    ld3(bp.gh, i, ghi);
+    ld3(bp.t, i, ci);
+    ld3(bp.bh, i, chi);
+    const double gc = dot3(gi, ci);
+    const double dl = gc, dmu = di * dot3(ghi, chi) - gc;
+    const float tau = m.tau[i];
+    const float gt = (float)dl * sigmoidf_(tau);
+    const float gm = (float)dmu;
+    const float hk = act_in(m, hf[i * MP_H + k]);
+    float dh = gt * hv[k] + gm * hu[k];
+    g_v += gt * hk;
+    g_u += gm * hk;
+    if (k == 0) {
+      g_sc[0] += gt;
+      g_sc[5] += gm;
+    }
+    for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+      const int64_t j = d.col[e];
+      double gj[3], ghj[3], cj[3], chj[3];
+      ld3(bp.gt, j, gj);
+      ld3(bp.gh, j, ghj);
+      ld3(bp.t, j, cj);
+      ld3(bp.bh, j, chj);
+      const double* bv = bp.bval + 6 * (int64_t)e;  // -W
+      double wcj[3], wci[3];
+      bsym_mul(bv, chj, wcj);
+      bsym_mul(bv, chi, wci);
+      const double what = -d.val[e] / sqrt(di * d.diag[j]);
+      const double s_own = dot3(gi, cj), s_rev = dot3(gj, ci);
+      const double q_own = -dot3(ghi, wcj) - what * s_own;
+      const double q_rev = -dot3(ghj, wci) - what * s_rev;
+      const float dS_own = (float)s_own, dS_rev = (float)s_rev;
+      const float dq_own = (float)q_own, dq_rev = (float)q_rev;
+      const float hj = act_in(m, hf[j * MP_H + k]);
+      dh += ((dS_own + dS_rev) * hz[k] + (dq_own + dq_rev) * hs[k]) * hj;
+      g_z += dS_own * (hk * hj);
+      g_s += dq_own * (hk * hj);
+      if (k == 0) {
+        g_sc[1] += dS_own;
+        g_sc[6] += dq_own;
+#pragma unroll
+        for (int f = 0; f < MP_FE; ++f) {
+          const float ef = act_in(m, m.ef[3 * (int64_t)e + f]);
+          g_sc[2 + f] += dS_own * ef;
+          g_sc[7 + f] += dq_own * ef;
+        }
+      }
+    }
+    m.dh[i * MP_H + k] = dh;
+  }
+  float* dst = m.gpart + (int64_t)blockIdx.x * MP_NPARAMS_ALL;
+  slot_reduce_store(g_v, red, dst + MP_OFF_HEAD + MP_H_V);
+  slot_reduce_store(g_z, red, dst + MP_OFF_HEAD + MP_H_Z);
+  slot_reduce_store(g_u, red, dst + MP_OFF_PHI + MP_PHI_U);
+  slot_reduce_store(g_s, red, dst + MP_OFF_PHI + MP_PHI_S);
+  const int offs[10] = {MP_OFF_HEAD + MP_H_V0, MP_OFF_HEAD + MP_H_Z0, MP_OFF_HEAD + MP_H_ZE,
+                        MP_OFF_HEAD + MP_H_ZE + 1, MP_OFF_HEAD + MP_H_ZE + 2,
+                        MP_OFF_PHI + MP_PHI_U0, MP_OFF_PHI + MP_PHI_S0, MP_OFF_PHI + MP_PHI_SE,
+                        MP_OFF_PHI + MP_PHI_SE + 1, MP_OFF_PHI + MP_PHI_SE + 2};
+  for (int q = 0; q < 10; ++q) {
+    red[threadIdx.x] = g_sc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.0f;
+      for (int sl = 0; sl < NODES; ++sl) s += red[sl * MP_H];
+      dst[offs[q]] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// b = A z on the block system (the probe's right-hand side)
+__global__ __launch_bounds__(256) void k_mpb_probe_b(DevPtrs d, BlockPtrs bp,
+                                                     const double* __restrict__ z,
+                                                     double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows || d.ctrl->overflow) return;
+  const double zi[3] = {z[3 * i], z[3 * i + 1], z[3 * i + 2]};
+  double acc[3];
+  bsym_mul(bp.bdiag + 6 * i, zi, acc);
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    const int64_t j = d.col[e];
+    const double zj[3] = {z[3 * j], z[3 * j + 1], z[3 * j + 2]};
+    double o[3];
+    bsym_mul(bp.bval + 6 * (int64_t)e, zj, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += o[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[3 * i + c] = acc[c];
+}
+
+// parity export: the blocks M_ii and M_ij, row-major 3 x 3, in global
+// original numbering (as k_block_export)
+__global__ __launch_bounds__(256) void k_mpb_export(DevPtrs d, BlockPtrs bp,
+                                                    const int64_t* __restrict__ id_off,
+                                                    int64_t* __restrict__ rows,
+                                                    int64_t* __restrict__ cols,
+                                                    double* __restrict__ vals, int64_t cap,
+                                                    double* __restrict__ diag_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.rows) return;
+  const int rid = d.blk_rep[i / ROWS_PER_BLOCK];
+  const RepDev& R = d.rep[rid];
+  if (i - R.row_off >= R.n) return;
+  const int64_t gi = id_off[rid] + (int64_t)d.pos[i].w;
+  double M[9];
+  bsym_full(bp.xd + 6 * i, M);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) diag_out[9 * gi + q] = M[q];
+  for (int e = d.rowptr[i]; e < d.rowptr[i + 1]; ++e) {
+    if (e >= cap) break;
+    rows[e] = gi;
+    cols[e] = id_off[rid] + (int64_t)d.pos[d.col[e]].w;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) vals[9 * (int64_t)e + q] = (double)bp.xo[9 * (int64_t)e + q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+hipError_t launch_mp_trunk(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
   const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
   if (m.round_act) {
     const dim3 g((unsigned)xcd_grid((int)blocks));
     hipLaunchKernelGGL(k_mp_encode_mx, g, dim3(MP_THREADS), 0, s, d, m);
     for (int l = 0; l < MP_NL; ++l)
       hipLaunchKernelGGL(k_mp_layer_mx, g, dim3(MP_THREADS), 0, s, d, m, l);
-    hipLaunchKernelGGL(k_mp_heads_mx, g, dim3(MP_THREADS), 0, s, d, m);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_mp_features, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m);
   hipLaunchKernelGGL(k_mp_encode, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
   for (int l = 0; l < MP_NL; ++l)
     hipLaunchKernelGGL(k_mp_layer, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
-  hipLaunchKernelGGL(k_mp_heads, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_forward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+  hipError_t e = launch_mp_trunk(d, m, s);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
+  if (m.round_act)
+    hipLaunchKernelGGL(k_mp_heads_mx, dim3((unsigned)xcd_grid((int)blocks)), dim3(MP_THREADS), 0,
+                       s, d, m);
+  else
+    hipLaunchKernelGGL(k_mp_heads, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
   return hipGetLastError();
 }
 
@@ -1098,21 +1556,30 @@ hipError_t launch_mp_loss(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mp_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+// the layers' and the encoder's backward from dL/dh^NL in m.dh, then the
+// parameter gradient
+static hipError_t launch_mp_trunk_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
   const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
-  hipLaunchKernelGGL(k_mp_heads_bwd, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
   for (int l = MP_NL - 1; l >= 0; --l) {
     hipLaunchKernelGGL(k_mp_layer_bwd_a, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
     hipLaunchKernelGGL(k_mp_layer_bwd_b, dim3(blocks), dim3(MP_THREADS), 0, s, d, m, l);
   }
   hipLaunchKernelGGL(k_mp_encode_bwd, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
-  hipLaunchKernelGGL(k_mp_grad_reduce, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m,
+  hipLaunchKernelGGL(k_mp_grad_reduce, dim3(nb(MP_NPARAMS_ALL, 256)), dim3(256), 0, s, m,
                      (int)blocks);
   return hipGetLastError();
 }
 
+hipError_t launch_mp_backward(const DevPtrs& d, const MpPtrs& m, hipStream_t s) {
+  const unsigned blocks = (unsigned)(d.rows / MP_ROWS);
+  hipLaunchKernelGGL(k_mp_heads_bwd, dim3(blocks), dim3(MP_THREADS), 0, s, d, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_mp_trunk_backward(d, m, s);
+}
+
 hipError_t launch_mp_adam(const MpPtrs& m, float lr, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_mp_adam, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m, lr, t);
+  hipLaunchKernelGGL(k_mp_adam, dim3(nb(MP_NPARAMS_ALL, 256)), dim3(256), 0, s, m, lr, t);
   return hipGetLastError();
 }
 
@@ -1131,6 +1598,47 @@ hipError_t launch_mp_probe(const DevPtrs& d, double* z, double* b, uint64_t seed
 }
 
 hipError_t launch_mp_cast(const MpPtrs& m, hipStream_t s) {
-  hipLaunchKernelGGL(k_mp_cast, dim3(nb(MP_NPARAMS, 256)), dim3(256), 0, s, m);
+  hipLaunchKernelGGL(k_mp_cast, dim3(nb(MP_NPARAMS_ALL, 256)), dim3(256), 0, s, m);
+  return hipGetLastError();
+}
+
+// ---- the 3 x 3 heads on the block system --------------------------------
+hipError_t launch_mpb_heads(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_mpb_root, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, bp);
+  hipLaunchKernelGGL(k_mpb_heads, dim3((unsigned)(d.rows / MP_ROWS)), dim3(MP_THREADS), 0, s, d, m,
+                     bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpb_loss(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp, hipStream_t s) {
+  const unsigned b = nb(d.rows, 256);
+  hipLaunchKernelGGL(k_mpb_resid, dim3(b), dim3(256), 0, s, d, m, bp);
+  hipLaunchKernelGGL(k_mpb_aprod, dim3(b), dim3(256), 0, s, d, m, bp);
+  hipLaunchKernelGGL(k_mp_loss, dim3(1), dim3(1024), 0, s, m, (int)b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpb_backward(const DevPtrs& d, const MpPtrs& m, const BlockPtrs& bp,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_mpb_pre, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, m, bp);
+  hipLaunchKernelGGL(k_mpb_heads_bwd, dim3((unsigned)(d.rows / MP_ROWS)), dim3(MP_THREADS), 0, s,
+                     d, m, bp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_mp_trunk_backward(d, m, s);
+}
+
+hipError_t launch_mpb_probe(const DevPtrs& d, const BlockPtrs& bp, double* z, double* b,
+                            uint64_t seed, uint64_t index, hipStream_t s) {
+  hipLaunchKernelGGL(k_mp_probe_z, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, z, seed, index);
+  hipLaunchKernelGGL(k_mpb_probe_b, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, bp, z, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpb_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                             int64_t* rows, int64_t* cols, double* vals, int64_t cap, double* diag,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_mpb_export, dim3(nb(d.rows, 256)), dim3(256), 0, s, d, bp, id_off, rows,
+                     cols, vals, cap, diag);
   return hipGetLastError();
 }

@@ -312,11 +312,11 @@ static int ensure_mp(sim_t* s, bool training) {
 #define MPALLOC(ptr, bytes) \
   if ((rc = dalloc(s, (void**)&(ptr), (bytes))) != SIM_OK) return rc;
   if (!s->mp_ready) {
-    MPALLOC(m.w16, sizeof(uint16_t) * MP_NPARAMS);
-    MPALLOC(m.th32, sizeof(float) * MP_NPARAMS);
-    MPALLOC(m.am, sizeof(float) * MP_NPARAMS);
-    MPALLOC(m.av, sizeof(float) * MP_NPARAMS);
-    MPALLOC(m.grad, sizeof(float) * MP_NPARAMS);
+    MPALLOC(m.w16, sizeof(uint16_t) * MP_NPARAMS_ALL);
+    MPALLOC(m.th32, sizeof(float) * MP_NPARAMS_ALL);
+    MPALLOC(m.am, sizeof(float) * MP_NPARAMS_ALL);
+    MPALLOC(m.av, sizeof(float) * MP_NPARAMS_ALL);
+    MPALLOC(m.grad, sizeof(float) * MP_NPARAMS_ALL);
     MPALLOC(m.x, sizeof(float) * 3 * rows);
     MPALLOC(m.h, sizeof(float) * (MP_NL + 1) * rows * H);
     MPALLOC(m.y, sizeof(float) * MP_NL * rows * H);
@@ -326,14 +326,19 @@ static int ensure_mp(sim_t* s, bool training) {
     MPALLOC(m.mdiag, sizeof(double) * rows);
     MPALLOC(m.lpart, sizeof(double) * 2 * (rows / 256 + 1));
     MPALLOC(m.loss, sizeof(double) * 2);
-    HIPCHK(hipMemset(m.w16, 0, sizeof(uint16_t) * MP_NPARAMS));
-    HIPCHK(hipMemset(m.th32, 0, sizeof(float) * MP_NPARAMS));
-    HIPCHK(hipMemset(m.am, 0, sizeof(float) * MP_NPARAMS));
-    HIPCHK(hipMemset(m.av, 0, sizeof(float) * MP_NPARAMS));
-    HIPCHK(hipMemset(m.grad, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemset(m.w16, 0, sizeof(uint16_t) * MP_NPARAMS_ALL));
+    HIPCHK(hipMemset(m.th32, 0, sizeof(float) * MP_NPARAMS_ALL));
+    HIPCHK(hipMemset(m.am, 0, sizeof(float) * MP_NPARAMS_ALL));
+    HIPCHK(hipMemset(m.av, 0, sizeof(float) * MP_NPARAMS_ALL));
+    HIPCHK(hipMemset(m.grad, 0, sizeof(float) * MP_NPARAMS_ALL));
     m.rows = s->rows;
     m.round_act = 1;
     m.lam_floor = MP_EPS_LAM;
+    m.nparams = s->block ? MP_NPARAMS_ALL : MP_NPARAMS;
+    if (s->block) {  // the 3 x 3 heads: A_ii^-1/2 and the node blocks of M^-1
+      MPALLOC(s->bp.rsq, sizeof(double) * 6 * rows);
+      MPALLOC(s->bp.xd, sizeof(double) * 6 * rows);
+    }
     s->mp_ready = true;
   }
   if (s->mp_nnz_cap != s->d.nnz_cap) {
@@ -342,13 +347,16 @@ static int ensure_mp(sim_t* s, bool training) {
     dfree(s, m.efh);
     dfree(s, m.tg);
     dfree(s, m.moff);
+    dfree(s, s->bp.xo);
     m.ef = m.tg = m.moff = nullptr;
     m.efh = nullptr;
+    s->bp.xo = nullptr;
     const size_t cap = (size_t)s->d.nnz_cap;
     MPALLOC(m.ef, sizeof(float) * 3 * cap);
     MPALLOC(m.efh, sizeof(uint16_t) * 4 * cap);
     MPALLOC(m.tg, sizeof(float) * cap);
     MPALLOC(m.moff, sizeof(float) * cap);
+    if (s->block) MPALLOC(s->bp.xo, sizeof(float) * 9 * cap);
     s->mp_nnz_cap = s->d.nnz_cap;
   }
   if (training && !s->mp_train) {
@@ -359,9 +367,15 @@ static int ensure_mp(sim_t* s, bool training) {
     MPALLOC(m.dh, sizeof(float) * rows * H);
     MPALLOC(m.dh2, sizeof(float) * rows * H);
     MPALLOC(m.dm, sizeof(float) * rows * H);
-    MPALLOC(m.gpart, sizeof(float) * (rows / MP_ROWS) * MP_NPARAMS);
+    MPALLOC(m.gpart, sizeof(float) * (rows / MP_ROWS) * MP_NPARAMS_ALL);
     MPALLOC(m.pz, sizeof(double) * 3 * rows);
     MPALLOC(m.pb, sizeof(double) * 3 * rows);
+    if (s->block) {  // R G, A_ii^-1 G, R b, A_ii^-1 b
+      MPALLOC(s->bp.gt, sizeof(double) * 3 * rows);
+      MPALLOC(s->bp.gh, sizeof(double) * 3 * rows);
+      MPALLOC(s->bp.t, sizeof(double) * 3 * rows);
+      MPALLOC(s->bp.bh, sizeof(double) * 3 * rows);
+    }
     s->mp_train = true;
   }
 #undef MPALLOC
@@ -460,7 +474,12 @@ static int prepare_precond(sim_t* s) {
     int rc = ensure_mp(s, false);
     if (rc) return rc;
     s->mp.store_train = 0;
-    HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+    if (s->block) {
+      HIPCHK(launch_mp_trunk(s->d, s->mp, s->stream));
+      HIPCHK(launch_mpb_heads(s->d, s->mp, s->bp, s->stream));
+    } else {
+      HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+    }
     s->d.learned = 1;
   }
   if (s->ic0)
@@ -692,6 +711,7 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
 // per-replica states after each chunk
 static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
   s->vv_valid = false;
+  s->bp.learned = s->learned && s->d.learned ? 1 : 0;
   HIPCHK(hipMemcpyAsync(s->ctrl_h, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   if (s->ctrl_h->overflow) return SIM_EOVERFLOW_INTERNAL;
@@ -700,20 +720,37 @@ static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
   const int maxit = cg_maxit(s);
   int chunk = std::max(4, std::min(32, s->last_iters > 0 ? s->last_iters : 8));
   int status = SIM_OK;
+  std::vector<std::pair<int, double>> hist;  // (iterations, worst relative residual^2)
   for (;;) {
     HIPCHK(hipMemcpyAsync(s->bcg_h, s->bp.bcg, sizeof(BcgRep) * (size_t)s->R,
                           hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     bool all_done = true, broke = false;
     int itmax = 0;
+    double worst = 0.0;
     for (int r = 0; r < s->R; ++r) {
-      all_done = all_done && s->bcg_h[r].state == 2;
-      broke = broke || s->bcg_h[r].breakdown;
-      itmax = std::max(itmax, (int)s->bcg_h[r].it);
+      const BcgRep& B = s->bcg_h[r];
+      all_done = all_done && B.state == 2;
+      broke = broke || B.breakdown;
+      itmax = std::max(itmax, (int)B.it);
+      if (B.state != 2 && B.bb > 0.0) worst = std::max(worst, B.rr / B.bb);
     }
     if (broke) { status = SIM_EBREAKDOWN; break; }
     if (all_done) break;
     if (itmax >= maxit) { status = SIM_ENOCONV; break; }
+    if (s->bp.learned) {
+      // stall (as the scalar solve): the worst residual of an unfinished
+      // replica not 10 % lower over the last 10 or more iterations (after 20)
+      hist.push_back({itmax, worst});
+      if (itmax >= 20) {
+        for (auto it = hist.rbegin(); it != hist.rend(); ++it)
+          if (itmax - it->first >= 10) {
+            if (!(worst < 0.81 * it->second)) status = SIM_ESTALL_INTERNAL;
+            break;
+          }
+        if (status) break;
+      }
+    }
     const int k = std::min(chunk, maxit - itmax);
     for (int q = 0; q < k; ++q) HIPCHK(launch_bcg_iteration(s->d, s->bp, s->stream));
     HIPCHK(launch_bcg_residual(s->d, s->bp, s->stream));
@@ -850,8 +887,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   for (int r = 0; r < replicas; ++r) s->block = s->block || anisotropic(params[r]);
   if (s->block)
     for (int r = 0; r < replicas; ++r)
-      if (params[r].precond == SIM_PC_LEARNED || params[r].precond == SIM_PC_IC0 ||
-          params[r].spmv_fp32 || params[r].warm_start) {
+      if (params[r].precond == SIM_PC_IC0 || params[r].spmv_fp32 || params[r].warm_start) {
         delete s;
         return SIM_ENOTSUP;
       }
@@ -1220,20 +1256,26 @@ int sim_autotune(sim_t* s, int32_t reps, sim_tuning* out) {
   return SIM_OK;
 }
 
+// parameter counts the weight calls take: the scalar network, or it and the
+// 3 x 3 heads of the block system
+static bool weight_count_ok(int64_t count) {
+  return count == MP_NPARAMS || count == MP_NPARAMS_ALL;
+}
+
 int sim_precond_weights(sim_t* s, float* theta, int64_t count, int32_t set) {
-  if (!s || !theta || count != MP_NPARAMS) return SIM_EINVAL;
+  if (!s || !theta || !weight_count_ok(count)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, false);
   if (rc) return rc;
   if (set) {
-    HIPCHK(hipMemcpy(s->mp.th32, theta, sizeof(float) * MP_NPARAMS, hipMemcpyHostToDevice));
-    HIPCHK(hipMemset(s->mp.am, 0, sizeof(float) * MP_NPARAMS));
-    HIPCHK(hipMemset(s->mp.av, 0, sizeof(float) * MP_NPARAMS));
+    HIPCHK(hipMemcpy(s->mp.th32, theta, sizeof(float) * (size_t)count, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(s->mp.am, 0, sizeof(float) * MP_NPARAMS_ALL));
+    HIPCHK(hipMemset(s->mp.av, 0, sizeof(float) * MP_NPARAMS_ALL));
     s->mp_adam_t = 0;
     HIPCHK(launch_mp_cast(s->mp, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
   } else {
-    HIPCHK(hipMemcpy(theta, s->mp.th32, sizeof(float) * MP_NPARAMS, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(theta, s->mp.th32, sizeof(float) * (size_t)count, hipMemcpyDeviceToHost));
   }
   return SIM_OK;
 }
@@ -1263,13 +1305,13 @@ int sim_load_precond(sim_t* s, const char* path) {
   if (!f) return SIM_EINVAL;
   char magic[8];
   int64_t count = 0;
-  std::vector<float> th(MP_NPARAMS);
+  std::vector<float> th(MP_NPARAMS_ALL);
   const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "SIMPC001", 8) == 0 &&
-                  std::fread(&count, sizeof(count), 1, f) == 1 && count == MP_NPARAMS &&
-                  std::fread(th.data(), sizeof(float), MP_NPARAMS, f) == (size_t)MP_NPARAMS;
+                  std::fread(&count, sizeof(count), 1, f) == 1 && weight_count_ok(count) &&
+                  std::fread(th.data(), sizeof(float), (size_t)count, f) == (size_t)count;
   std::fclose(f);
   if (!ok) return SIM_EINVAL;
-  return sim_precond_weights(s, th.data(), MP_NPARAMS, 1);
+  return sim_precond_weights(s, th.data(), count, 1);
 }
 
 // training on a system built before the handle had network buffers: the
@@ -1281,18 +1323,31 @@ static int no_edge_input() {
   return SIM_EINVAL;
 }
 
+// network forward, loss and backward on the system (b, x*) of dp
+static int train_pass(sim_t* s, const DevPtrs& dp, const MpPtrs& mq) {
+  if (s->block) {
+    HIPCHK(launch_mp_trunk(dp, mq, s->stream));
+    HIPCHK(launch_mpb_heads(dp, mq, s->bp, s->stream));
+    HIPCHK(launch_mpb_loss(dp, mq, s->bp, s->stream));
+    HIPCHK(launch_mpb_backward(dp, mq, s->bp, s->stream));
+  } else {
+    HIPCHK(launch_mp_forward(dp, mq, s->stream));
+    HIPCHK(launch_mp_loss(dp, mq, s->stream));
+    HIPCHK(launch_mp_backward(dp, mq, s->stream));
+  }
+  return SIM_OK;
+}
+
 int sim_train_step(sim_t* s, double lr, double* loss) {
   if (!s || !(lr >= 0.0)) return SIM_EINVAL;
-  if (s->R != 1 || s->block) return SIM_ENOTSUP;  // the network reads the scalar system
+  if (s->R != 1) return SIM_ENOTSUP;  // one system: the solution loss of one replica
   if (!s->system_valid) return SIM_EINVAL;
   if (!s->er_built) return no_edge_input();
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, true);
   if (rc) return rc;
   s->mp.store_train = 1;
-  HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
-  HIPCHK(launch_mp_loss(s->d, s->mp, s->stream));
-  HIPCHK(launch_mp_backward(s->d, s->mp, s->stream));
+  if ((rc = train_pass(s, s->d, s->mp))) return rc;
   if (lr > 0.0) HIPCHK(launch_mp_adam(s->mp, (float)lr, ++s->mp_adam_t, s->stream));
   double l[2] = {0.0, 0.0};
   HIPCHK(hipMemcpyAsync(l, s->mp.loss, sizeof(l), hipMemcpyDeviceToHost, s->stream));
@@ -1304,7 +1359,6 @@ int sim_train_step(sim_t* s, double lr, double* loss) {
 int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t euclid,
                     double* loss) {
   if (!s || !(lr >= 0.0) || (euclid != 0 && euclid != 1)) return SIM_EINVAL;
-  if (s->block) return SIM_ENOTSUP;  // the network reads the scalar system
   if (!s->system_valid) return SIM_EINVAL;
   if (!s->er_built) return no_edge_input();
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
@@ -1318,10 +1372,11 @@ int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t 
   dp.b = s->mp.pb;
   MpPtrs mq = s->mp;
   mq.loss_euclid = euclid;
-  HIPCHK(launch_mp_probe(dp, s->mp.pz, s->mp.pb, seed, index, s->stream));
-  HIPCHK(launch_mp_forward(dp, mq, s->stream));
-  HIPCHK(launch_mp_loss(dp, mq, s->stream));
-  HIPCHK(launch_mp_backward(dp, mq, s->stream));
+  if (s->block)
+    HIPCHK(launch_mpb_probe(dp, s->bp, s->mp.pz, s->mp.pb, seed, index, s->stream));
+  else
+    HIPCHK(launch_mp_probe(dp, s->mp.pz, s->mp.pb, seed, index, s->stream));
+  if ((rc = train_pass(s, dp, mq))) return rc;
   if (lr > 0.0) HIPCHK(launch_mp_adam(s->mp, (float)lr, ++s->mp_adam_t, s->stream));
   double l[2] = {0.0, 0.0};
   HIPCHK(hipMemcpyAsync(l, s->mp.loss, sizeof(l), hipMemcpyDeviceToHost, s->stream));
@@ -1331,11 +1386,11 @@ int sim_train_probe(sim_t* s, double lr, uint64_t seed, uint64_t index, int32_t 
 }
 
 int sim_precond_optimizer(sim_t* s, float* m1, float* m2, int64_t count, int32_t* t, int32_t set) {
-  if (!s || !m1 || !m2 || !t || count != MP_NPARAMS || (set && *t < 0)) return SIM_EINVAL;
+  if (!s || !m1 || !m2 || !t || !weight_count_ok(count) || (set && *t < 0)) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
   int rc = ensure_mp(s, false);
   if (rc) return rc;
-  const size_t bytes = sizeof(float) * MP_NPARAMS;
+  const size_t bytes = sizeof(float) * (size_t)count;
   if (set) {
     HIPCHK(hipMemcpy(s->mp.am, m1, bytes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(s->mp.av, m2, bytes, hipMemcpyHostToDevice));
@@ -1349,9 +1404,9 @@ int sim_precond_optimizer(sim_t* s, float* m1, float* m2, int64_t count, int32_t
 }
 
 int sim_precond_grad(sim_t* s, float* grad, int64_t count) {
-  if (!s || !grad || count != MP_NPARAMS || !s->mp_ready) return SIM_EINVAL;
+  if (!s || !grad || !weight_count_ok(count) || !s->mp_ready) return SIM_EINVAL;
   if (hipSetDevice(s->device) != hipSuccess) return SIM_EDEVICE;
-  HIPCHK(hipMemcpy(grad, s->mp.grad, sizeof(float) * MP_NPARAMS, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(grad, s->mp.grad, sizeof(float) * (size_t)count, hipMemcpyDeviceToHost));
   return SIM_OK;
 }
 
@@ -1366,7 +1421,12 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   if (s->learned) {
     if ((rc = ensure_mp(s, false))) return rc;
     s->mp.store_train = 0;
-    HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+    if (s->block) {
+      HIPCHK(launch_mp_trunk(s->d, s->mp, s->stream));
+      HIPCHK(launch_mpb_heads(s->d, s->mp, s->bp, s->stream));
+    } else {
+      HIPCHK(launch_mp_forward(s->d, s->mp, s->stream));
+    }
   } else {
     HIPCHK(launch_ic_factor(s->d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1,
                             s->stream));
@@ -1374,24 +1434,29 @@ int sim_debug_precond(sim_t* s, int64_t* rows, int64_t* cols, double* vals, int6
   const int64_t nnz = s->ctrl_h->nnz;
   *count = nnz;
   if (nnz > cap) return SIM_ECAPACITY;
+  const size_t per = s->block ? 9 : 1;  // values per entry and per particle
   int64_t *r_d = nullptr, *c_d = nullptr;
   double *v_d = nullptr, *dg_d = nullptr;
   const size_t m = (size_t)std::max<int64_t>(nnz, 1);
   if ((rc = dalloc(s, (void**)&r_d, sizeof(int64_t) * m))) return rc;
   if ((rc = dalloc(s, (void**)&c_d, sizeof(int64_t) * m))) return rc;
-  if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * m))) return rc;
-  if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * (size_t)s->n_total))) return rc;
-  if (s->learned)
+  if ((rc = dalloc(s, (void**)&v_d, sizeof(double) * per * m))) return rc;
+  if ((rc = dalloc(s, (void**)&dg_d, sizeof(double) * per * (size_t)s->n_total))) return rc;
+  if (s->learned && s->block)
+    HIPCHK(launch_mpb_export(s->d, s->bp, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, s->stream));
+  else if (s->learned)
     HIPCHK(launch_mp_export(s->d, s->mp, s->id_off_d, r_d, c_d, v_d, nnz, dg_d, s->stream));
   else
     HIPCHK(launch_ic_export(s->d, s->id_off_d, r_d, c_d, v_d, dg_d, s->stream));
   if (nnz > 0) {
     HIPCHK(hipMemcpyAsync(rows, r_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipMemcpyAsync(cols, c_d, sizeof(int64_t) * nnz, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(vals, v_d, sizeof(double) * nnz, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(vals, v_d, sizeof(double) * per * nnz, hipMemcpyDeviceToHost,
+                          s->stream));
   }
   if (mdiag)
-    HIPCHK(hipMemcpyAsync(mdiag, dg_d, sizeof(double) * s->n_total, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(mdiag, dg_d, sizeof(double) * per * s->n_total, hipMemcpyDeviceToHost,
+                          s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   dfree(s, r_d);
   dfree(s, c_d);

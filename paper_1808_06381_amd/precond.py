@@ -65,10 +65,11 @@ def block_layout():
     lam_i and S_ij are shared):
         mu_i   = u . h_i + u0                      node anisotropy
         sig_ij = s . (h_i * h_j) + se . e_ij + s0  edge anisotropy
-    X_ii = lam_i A_ii + mu_i (A_ii - d_i I),
-    X_ij = S_ij sqrt(d_i d_j) I + sig_ij (W_ij - omega_ij I),
-    M^-1 = B X B with B = blockdiag(A_ii^-1), d_i = tr A_ii / 3,
-    omega_ij = tr W_ij / 3 (A_ij = -W_ij); the trunk sees the traces."""
+    In the frame R = blockdiag(A_ii^-1/2) (symmetric roots):
+    Xh_ii = lam_i I + mu_i (d_i A_ii^-1 - I),
+    Xh_ij = S_ij I + sig_ij (R_i W_ij R_j - What_ij I),  M^-1 = R Xh R,
+    d_i = tr A_ii / 3, omega_ij = tr W_ij / 3 (A_ij = -W_ij),
+    What_ij = omega_ij / sqrt(d_i d_j); the trunk sees the traces."""
     out = dict(LAYOUT)
     off = NPARAMS
     for name, shape in (("u", (H,)), ("u0", (1,)), ("s", (H,)), ("se", (FE,)), ("s0", (1,))):
@@ -83,9 +84,9 @@ BLOCK_LAYOUT, NPARAMS_BLOCK = block_layout()
 def block_params(theta=None, seed=0):
     """Weights of the block form: the scalar network's (theta, or the initial
     ones) and anisotropy heads mu = 0, sig = 1, which keep the anisotropic
-    part of every pair block of the two-term Neumann series: with the initial
-    scalar heads M^-1 = B (2D - A) B, D = blockdiag(A_ii) (positive
-    definite)."""
+    part of every normalised pair block R_i W_ij R_j: with the initial scalar
+    heads M^-1 = D^-1 + D^-1 (D - A) D^-1, D = blockdiag(A_ii), the block
+    two-term Neumann series (positive definite)."""
     base = init_params(seed) if theta is None else np.asarray(theta, dtype=np.float32)
     if base.size == NPARAMS_BLOCK:
         return base.copy()

@@ -34,6 +34,7 @@ EXPORTED = ["sim_create", "sim_create_batch", "sim_step", "sim_solve", "sim_stat
             "sim_autotune", "sim_set_tuning", "sim_train_probe", "sim_precond_optimizer",
             "sim_destroy", "sim_strerror"]
 MPNN_NPARAMS = 9893
+MPNN_NPARAMS_BLOCK = 9962  # with the 3 x 3 heads of the block system
 
 
 # CSR product variants of sim_tuning: (lanes per row, entries per lane loaded one
@@ -234,6 +235,11 @@ class Sim:
         pos0 = np.ascontiguousarray(pos0, dtype=np.float64).reshape(-1, 3)
         self.n_total = sum(int(c["n"]) for c in cfgs)
         self.replicas = len(cfgs)
+        # friction other than 1 along or across the line of centres (0 stands
+        # for 1): the library solves the block system (3 x 3 blocks)
+        self.block = any(float(c.get(k, 1.0)) not in (0.0, 1.0)
+                         for c in cfgs for k in ("friction_par", "friction_perp"))
+        self.nparams = MPNN_NPARAMS_BLOCK if self.block else MPNN_NPARAMS
         if pos0.shape[0] != self.n_total:
             raise ValueError("pos0 rows != total particles")
         h = C.c_void_p()
@@ -416,10 +422,10 @@ class Sim:
         return loss.value
 
     def get_optimizer(self):
-        m1 = np.zeros(MPNN_NPARAMS, dtype=np.float32)
-        m2 = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        m1 = np.zeros(self.nparams, dtype=np.float32)
+        m2 = np.zeros(self.nparams, dtype=np.float32)
         t = C.c_int32()
-        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), MPNN_NPARAMS, C.byref(t), 0),
+        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), m1.size, C.byref(t), 0),
                "sim_precond_optimizer")
         return m1, m2, t.value
 
@@ -428,7 +434,7 @@ class Sim:
         m1 = np.ascontiguousarray(m1, dtype=np.float32)
         m2 = np.ascontiguousarray(m2, dtype=np.float32)
         tt = C.c_int32(int(t))
-        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), MPNN_NPARAMS, C.byref(tt), 1),
+        _check(lib().sim_precond_optimizer(self.h, _ptr(m1), _ptr(m2), m1.size, C.byref(tt), 1),
                "sim_precond_optimizer")
 
     def graph_mode(self, on=True):
@@ -457,7 +463,7 @@ class Sim:
         _check(lib().sim_precond_weights(self.h, _ptr(theta), theta.size, 1), "sim_precond_weights")
 
     def get_weights(self):
-        theta = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        theta = np.zeros(self.nparams, dtype=np.float32)
         _check(lib().sim_precond_weights(self.h, _ptr(theta), theta.size, 0), "sim_precond_weights")
         return theta
 
@@ -475,14 +481,15 @@ class Sim:
         return loss.value
 
     def precond_grad(self):
-        g = np.zeros(MPNN_NPARAMS, dtype=np.float32)
+        g = np.zeros(self.nparams, dtype=np.float32)
         _check(lib().sim_precond_grad(self.h, _ptr(g), g.size), "sim_precond_grad")
         return g
 
     def precond_matrix(self):
         """(rows, cols, vals, diag) of the preconditioner at the current
         positions: the learned M^-1, or L's strictly lower triangle and diagonal
-        for IC(0) (unused slots dropped)."""
+        for IC(0) (unused slots dropped).  Block handles: vals (nnz, 3, 3) and
+        diag (n, 3, 3), the blocks of the learned M^-1."""
         cnt = C.c_int64()
         rc = lib().sim_debug_precond(self.h, None, None, None, 0, C.byref(cnt), None)
         if rc not in (SIM_OK, -6):
@@ -490,8 +497,9 @@ class Sim:
         m = max(cnt.value, 1)
         rows = np.zeros(m, dtype=np.int64)
         cols = np.zeros(m, dtype=np.int64)
-        vals = np.zeros(m)
-        mdiag = np.zeros(self.n_total)
+        shape = (3, 3) if self.block else ()
+        vals = np.zeros((m,) + shape)
+        mdiag = np.zeros((self.n_total,) + shape)
         _check(lib().sim_debug_precond(self.h, _ptr(rows), _ptr(cols), _ptr(vals), cnt.value,
                                        C.byref(cnt), _ptr(mdiag)), "sim_debug_precond")
         k = cnt.value

@@ -1,9 +1,11 @@
 """Pins of the oracle's learned preconditioner on the anisotropic block system
-(3 x 3 heads): with isotropic friction it is the scalar network times I_3 for
-any anisotropy weights; at the initial heads it is the two-term Neumann
-series of the block-Jacobi splitting (closed form, positive definite); it is
-symmetric and turns with the system under a rotation; the loss is its
-definition and the analytic gradient matches central finite differences."""
+(3 x 3 heads, M^-1 = R Xh R with R = blockdiag(A_ii^-1/2)): with isotropic
+friction it is the scalar network times I_3 for any anisotropy weights; at
+the initial heads it is the two-term Neumann series of the block-Jacobi
+splitting (closed form, positive definite; a wrong root R fails it); it is
+symmetric and turns with the system under a rotation (a root that is not
+the symmetric one fails it); the loss is its definition and the analytic
+gradient matches central finite differences."""
 import numpy as np
 import pytest
 
@@ -70,9 +72,9 @@ def test_isotropic_friction_reduces_to_the_scalar_network():
 
 
 def test_initial_heads_are_the_block_neumann_series():
-    """v = z = z0 = 0, ze = (0, 0, 1), mu = 0, sig = 1: X_ii = lam A_ii and
-    X_ij = What_ij sqrt(d_i d_j) I + (W_ij - omega_ij I) = W_ij, so
-    M^-1 = lam B + B (D - A) B with D = blockdiag(A_ii), B = D^-1; at lam = 1
+    """v = z = z0 = 0, ze = (0, 0, 1), mu = 0, sig = 1: Xh_ii = lam I and
+    Xh_ij = What_ij I + (Nh_ij - What_ij I) = R_i W_ij R_j, so with
+    R^2 = B = D^-1, D = blockdiag(A_ii): M^-1 = lam B + B (D - A) B; at lam = 1
     the first two terms of A^-1 = sum_k (D^-1 (D - A))^k D^-1.  Positive
     definite: 2D - A = gamma0 I + sum over pairs of [[W, W], [W, W]]."""
     cfg, pos, bs, er = block_case()
@@ -183,3 +185,24 @@ def test_block_gradient_matches_finite_differences(norm):
             assert np.any(g[off:off + int(np.prod(shape))] != 0), name
     finally:
         oracle.mpnn_set_bf16(True)
+
+
+def test_scalar_trained_weights_stay_definite_on_anisotropic_blocks():
+    """The frame of R = A_ii^-1/2 is where the scalar network's S_ij was
+    trained (D^-1/2 A D^-1/2 with unit diagonal): with the shipped weights and
+    the default anisotropy heads (mu = 0, sig = 1) M^-1 stays positive
+    definite on strongly anisotropic boxes.  (Scaling the isotropic part of
+    each pair block by A_ii^-1 instead of A_ii^-1/2 makes it indefinite there:
+    the weak directions of A_ii get d_i / a times too much coupling.)"""
+    import os
+    path = os.path.join(os.path.dirname(precond.__file__), "weights", "precond_n1e5.bin")
+    th = precond.block_params(precond.load(path))
+    for a_par, a_perp in ((3.0, 0.5), (0.5, 2.0)):
+        # the training boxes' physics: density 1, the friction-matrix workload
+        cfg = inputs.cube_params(800, 0.3, seed=41)
+        pos = inputs.uniform_positions(800, cfg["box"], 41)
+        bs = oracle.build_block_system(cfg, pos, a_par, a_perp, 0)
+        er = oracle.edge_r(cfg, pos, bs, 0)
+        mdiag, moff = oracle.mpnn_block_forward(bs, er, cfg["alpha"], th)
+        M = dense_blocks(bs, mdiag, moff)
+        assert np.linalg.eigvalsh(0.5 * (M + M.T))[0] > 0, (a_par, a_perp)
