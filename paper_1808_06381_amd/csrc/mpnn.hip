@@ -3,7 +3,9 @@
 // that produces an SPD approximate inverse with the sparsity of A, its
 // training loss and gradient, and Adam.
 //
-// Network (hidden 32; weights enter as bfloat16, products accumulate in FP32):
+// Network (hidden 32; weights enter as bfloat16, products accumulate in FP32;
+// with bfloat16 activations, the default, the products see bf16 inputs and
+// the residual stream h is stored in bf16 between layers):
 //   x_i = (t_i, a_i, deg_i/8), t_i = alpha sum_j w_ij / D_i, a_i = sum_j What_ij,
 //   What_ij = alpha w_ij / sqrt(D_i D_j); e_ij = (r_ij/rc, w_ij, What_ij)
 //   h0 = relu(W0 x + b0)
@@ -388,9 +390,11 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
     hv[kk] = acc > 0.0f ? acc : 0.0f;
     xh[n * MX_HS + k] = bf16_bits(hv[kk]);
   }
-  float4* hp = reinterpret_cast<float4*>(m.h + i * MP_H + 8 * q);
-  hp[0] = make_float4(hv[0], hv[1], hv[2], hv[3]);
-  hp[1] = make_float4(hv[4], hv[5], hv[6], hv[7]);
+  if (m.store_train) {  // FP32 h0 for the backward pass (which rounds it to bf16)
+    float4* hp = reinterpret_cast<float4*>(m.h + i * MP_H + 8 * q);
+    hp[0] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+    hp[1] = make_float4(hv[4], hv[5], hv[6], hv[7]);
+  }
   __syncthreads();
   *reinterpret_cast<uint4*>(mx_hb(m, 0) + i * MP_H + 8 * q) =
       *reinterpret_cast<const uint4*>(xh + n * MX_HS + 8 * q);
@@ -496,18 +500,20 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
     // msg is next written after the next chunk's first barrier
   }
   __syncthreads();   // every row has summed its messages: msg and xa are restaged
-  // stage [bf16(h) | bf16(m)] and the FP32 residual h of the tile
+  // stage [bf16(h) | bf16(m)] and the residual h of the tile: the residual
+  // stream is kept in bf16 (the copy this layer gathers), so no FP32 h is
+  // read or, outside training, written
   {
     const int64_t i = i0 + n;
-    const float4* hp = reinterpret_cast<const float4*>(m.h + ((int64_t)l * rows + i) * MP_H + 8 * q);
-    const float4 h0 = hp[0], h1 = hp[1];
-    const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+    const uint4 hq8 = *reinterpret_cast<const uint4*>(hbl + i * MP_H + 8 * q);
+    const uint32_t hw[4] = {hq8.x, hq8.y, hq8.z, hq8.w};
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       const int k = 8 * q + kk;
+      const uint16_t hb16 = (uint16_t)((kk & 1) ? (hw[kk >> 1] >> 16) : (hw[kk >> 1] & 0xffffu));
       acc[kk] *= MP_MSG;
-      hs[n * MX_FS + k] = hv[kk];
-      xa[n * MX_AS + k] = bf16_bits(hv[kk]);
+      hs[n * MX_FS + k] = bf16_value(hb16);
+      xa[n * MX_AS + k] = hb16;
       xa[n * MX_AS + MP_H + k] = bf16_bits(acc[kk]);
     }
     if (m.store_train) {
@@ -540,9 +546,10 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
       const float a = av[nt][r];
       const float hn = hs[row * MX_FS + k] + (a > 0.0f ? a : 0.0f);
       const uint16_t hnb = bf16_bits(hn);
-      // the final h feeds the heads, which round it to bf16; its FP32 copy
-      // is for the backward pass only
-      if (l + 1 < MP_NL || m.store_train) hout[(i0 + row) * MP_H + k] = hn;
+      // h^{l+1} is stored rounded to bf16 (the next layer's residual and
+      // product input, the heads' input); its FP32 copy, the same value, is
+      // for the backward pass only
+      if (m.store_train) hout[(i0 + row) * MP_H + k] = bf16_value(hnb);
       if (m.store_train) m.a[((int64_t)l * rows + i0 + row) * MP_H + k] = a;
       xa[row * MX_AS + k] = hnb;
     }
