@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--c5-preshear", type=int, default=2000,
                     help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--only", default="",
-                    help="c5: the scale workloads only; c5-single: the N = 8e6 box only")
+                    help="c5: the scale workloads only; c5-single: the N = 8e6 box only; "
+                         "small: the N = 1000 case and the paper's box only (no headline line)")
     ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -498,6 +499,10 @@ def main():
             from paper_1808_06381_amd import precond
             theta = precond.load(args.weights)
     head = "learned" if "learned" in forms else forms[0]
+    if args.only == "small":
+        # the latency-bound small workloads alone (not the metric's line)
+        print(json.dumps(run_small(args, S, inputs, theta, stream, torch, np)), flush=True)
+        return
 
     c5, batch_state = run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs)
     hr = c5["single_n8e6"]["runs"][head]

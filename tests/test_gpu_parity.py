@@ -4,7 +4,8 @@
   Lees-Edwards offset and in boxes with fewer than three cells per axis;
 * the friction system (A and b, thermal force included) element by element;
 * solves against dense LAPACK and the oracle's PCG;
-* trajectories of the small workload (N = 1000, L = 10) step by step;
+* trajectories of the small workload (N = 1000, L = 10): 20 steps advanced
+  independently, and all 100 of its steps each checked from the GPU's state;
 * a batch of replicas of uneven size against per-replica oracle runs;
 * the paper's own thermal force (Eq. 6a: node noise only) in the paper's
   geometry, right-hand side and a 10-step trajectory;
@@ -263,6 +264,27 @@ def test_trajectory_small_workload():
             assert max(st["relres"]) <= 1e-10
 
 
+def test_small_workload_all_100_steps():
+    """The N = 1000, L = 10 workload over its 100 steps: every step checked
+    from the GPU's own positions (the oracle advances the same state one step),
+    so that differences cannot compound; velocities within 1e-8 relative,
+    positions within 1e-9, iterations within 2 of the oracle's."""
+    case = inputs.small_case(seed=4)
+    cfg = case["params"]
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(cfg, pos0, tol=1e-10) as sim:
+        for k in range(100):
+            p_before, _, meta = sim.state()
+            assert meta["step"] == k
+            st = sim.step(1)
+            pos_g, vel_g, _ = sim.state()
+            pos_o, vel_o, its = oracle.step(cfg, p_before, k, tol=1e-10)
+            rel = np.linalg.norm(vel_g - vel_o, axis=0) / np.linalg.norm(vel_o, axis=0)
+            assert np.all(rel < 1e-8), (k, rel)
+            assert np.max(np.abs(le_diff(cfg, k + 1, pos_g, pos_o))) < 1e-9, k
+            assert max(abs(a - b) for a, b in zip(st["iters"], its)) <= 2, k
+
+
 def test_determinism_bitwise():
     case = inputs.small_case(seed=2)
     cfg = case["params"]
@@ -343,6 +365,16 @@ def test_full_size_single_box():
     assert np.array_equal(got, oracle.pairs(cfg, p2, oracle.le_offset(cfg, 2), "cells"))
     np.testing.assert_allclose(diag, ref["diag"], rtol=1e-14)
     np.testing.assert_allclose(rhs, ref["rhs"], rtol=0, atol=1e-11 * np.abs(ref["rhs"]).max())
+    # sampled off-diagonal values of A (every 97th entry of the GPU export),
+    # bit-exact (polynomial weight: the same rounded operations on both sides)
+    n = cfg["n"]
+    o_rows = np.repeat(np.arange(n), np.diff(ref["rowptr"]))
+    key_o = o_rows * n + ref["col"]
+    order = np.argsort(key_o)
+    pick = np.arange(0, len(rows), 97)
+    idx = order[np.searchsorted(key_o[order], rows[pick] * n + cols[pick])]
+    assert np.array_equal(key_o[idx], rows[pick] * n + cols[pick])
+    assert np.array_equal(vals[pick], ref["val"][idx])
     Av = oracle.spmv3(ref, v2)
     res = np.linalg.norm(ref["rhs"] - Av, axis=0) / np.linalg.norm(ref["rhs"], axis=0)
     assert np.all(res <= tol * 1.01), res
