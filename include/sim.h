@@ -473,14 +473,19 @@ int sim_graph_info(sim_t* sim, int64_t* captures, int64_t* replays);
 /* Tuning of the CSR products (rows of ~5 entries) w = A u and the learned
  * u = M^-1 r.  A variant is a group of `lanes` lanes per row and a number
  * of entries per lane whose columns and values are loaded one pass of rows
- * ahead of the gathers (0: one entry at a time, no look-ahead); index:
+ * ahead of the gathers (0: one entry at a time, no look-ahead), or, with
+ * lanes 0, the entry-parallel form: the 256-row sub-tile's entries striped
+ * over its threads (`entries` per thread and pass), the products staged in
+ * LDS and each row summed by one thread in entry order; index:
  * (lanes, entries)
  *   0: (1, 0)  1: (2, 0)  2: (4, 0)  3: (8, 0)
  *   4: (2, 2)  5: (4, 1)  6: (4, 2)  7: (4, 3)
+ *   8: (0, 2)  9: (0, 3)
  * The lane count fixes the summation order of a row; variants with the same
- * lanes give the same bits, others agree to rounding.  A fixed choice is
- * bitwise reproducible.  Default 6 and 6.                                */
-#define SIM_CSR_VARIANTS 8
+ * lanes give the same bits (the entry-parallel ones those of variant 0),
+ * others agree to rounding.  A fixed choice is
+ * bitwise reproducible.  Default 8 and 8.                                */
+#define SIM_CSR_VARIANTS 10
 typedef struct sim_tuning {
   int32_t spmv_variant;  /* 0 .. SIM_CSR_VARIANTS - 1 */
   int32_t apply_variant;

@@ -50,8 +50,10 @@ __device__ __forceinline__ void lane_group_sum(double (&a)[3]) {
 // Components per row are finished by lanes 0..2 of the row's group; with
 // LANES < 3 a lane takes TURNS turns (component t * LANES + lane in turn t).
 // Register arrays are only indexed with compile-time indices here.
+// The entry-parallel form (LANES == 0) gives each thread one whole row: three
+// turns, turn k being component k.
 template <int LANES>
-constexpr int TURNS = LANES >= 3 ? 1 : (3 + LANES - 1) / LANES;
+constexpr int TURNS = LANES == 0 ? 3 : (LANES >= 3 ? 1 : (3 + LANES - 1) / LANES);
 
 __device__ __forceinline__ double pick3(const double (&a)[3], int k) {
   return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
@@ -63,6 +65,12 @@ __device__ __forceinline__ bool on_k(const bool (&on)[3], int k) {
 template <int LANES>
 __device__ __forceinline__ void turns_to_components(const double (&vt)[TURNS<LANES>], int lane,
                                                     double (&v)[3]) {
+  if constexpr (LANES == 0) {
+    v[0] = vt[0];
+    v[1] = vt[1];
+    v[2] = vt[2];
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < TURNS<LANES>; ++t) {
     const int k = t * LANES + lane;
@@ -235,6 +243,121 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) 
   write_partials<3>(d, sub, 0, v);
 }
 
+// Entry-parallel product over a sub-tile (the (0, EPT) variants).  The
+// sub-tile's off-diagonal entries are one contiguous CSR range [E0, E1); it is
+// striped over the block's threads in passes of SUB_THREADS * EPT entries
+// (entry E0 + c0 + t + k * SUB_THREADS to thread t), so the column and value
+// loads are coalesced, all of a thread's are in flight together, and none
+// waits on the row pointers of its own row; the next pass's are loaded while
+// this pass's gathers are summed.  Each thread gathers its entries' rows of
+// src and leaves the three products in LDS; after a barrier the thread of row
+// i adds its row's products in entry order (the same order for every EPT: the
+// variants give the same bits, and those of the one-lane loop form).  A row
+// that spans passes continues its sum in the next one.  The sub-tile's own
+// rows of src come in, and its results go out, through LDS as contiguous runs
+// of 3 * SUB_ROWS doubles.  Measured at N = 8e6 (brick order, k = 5.5): 244 us
+// against 321 us for four lanes per row, the loads no longer waiting on a
+// row-pointer load of their own and every lane carrying an entry.
+template <int EPT, class Val, class Fin>
+__device__ __forceinline__ void ep_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
+                                        const double* __restrict__ dg, Val val, const bool (&on)[3],
+                                        double* __restrict__ out, Fin fin) {
+  static_assert(SUB_THREADS == SUB_ROWS, "one thread per row of the sub-tile");
+  static_assert(SUB_THREADS % 3 == 1, "component of an io element");
+  constexpr int CAP = SUB_THREADS * EPT;
+  __shared__ double prod[3][CAP];
+  __shared__ double io[3 * SUB_ROWS];
+  const int cap = (int)d.nnz_cap;  // clamped as in lane_tile
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)sub * SUB_ROWS;
+  const int E0 = min(d.rowptr[base], cap);
+  const int ne = min(d.rowptr[base + SUB_ROWS], cap) - E0;
+  const int64_t i = base + t;
+  const int r0 = min(d.rowptr[i], cap) - E0, r1 = min(d.rowptr[i + 1], cap) - E0;
+  const double dgi = dg[i];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) io[t + q * SUB_THREADS] = src[3 * base + t + q * SUB_THREADS];
+  int c[EPT];
+  double m[EPT];
+  auto load = [&](int c0, int (&cl)[EPT], double (&ml)[EPT]) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = c0 + t + k * SUB_THREADS;
+      cl[k] = -1;
+      ml[k] = 0.0;
+      if (e < ne) {
+        cl[k] = d.col[E0 + e];
+        ml[k] = val(E0 + e);
+      }
+    }
+  };
+  load(0, c, m);
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < ne; c0 += CAP) {
+    double g[EPT][3];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      g[k][0] = g[k][1] = g[k][2] = 0.0;
+      if (c[k] >= 0) {
+        const double* gp = src + 3 * (int64_t)c[k];
+        g[k][0] = gp[0];
+        g[k][1] = gp[1];
+        g[k][2] = gp[2];
+      }
+    }
+    int cn[EPT];
+    double mn[EPT];
+    if (c0 + CAP < ne) {
+      load(c0 + CAP, cn, mn);
+    } else {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        cn[k] = -1;
+        mn[k] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      if (c[k] >= 0) {
+        const int slot = t + k * SUB_THREADS;
+        prod[0][slot] = m[k] * g[k][0];
+        prod[1][slot] = m[k] * g[k][1];
+        prod[2][slot] = m[k] * g[k][2];
+      }
+    }
+    __syncthreads();
+    const int lo = r0 > c0 ? r0 : c0, hi = r1 < c0 + CAP ? r1 : c0 + CAP;
+    for (int e = lo; e < hi; ++e) {
+      a[0] += prod[0][e - c0];
+      a[1] += prod[1][e - c0];
+      a[2] += prod[2][e - c0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      c[k] = cn[k];
+      m[k] = mn[k];
+    }
+  }
+  if (ne == 0) __syncthreads();  // the own rows in io, as after a pass
+  double v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double sk = io[3 * t + k];
+    v[k] = on_k(on, k) ? fin(i, k, k, sk, dgi * sk + a[k]) : 0.0;
+  }
+  __syncthreads();  // every own row read
+#pragma unroll
+  for (int k = 0; k < 3; ++k) io[3 * t + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    int k = t % 3 + q;  // component of element t + q * SUB_THREADS (SUB_THREADS = 1 mod 3)
+    k = k >= 3 ? k - 3 : k;
+    if (on_k(on, k)) out[3 * base + t + q * SUB_THREADS] = io[t + q * SUB_THREADS];
+  }
+}
+
 // Products sum_j M_ij src_j (three components) of the sub-tile's 256 rows
 // with a group of LANES lanes per row, LANES passes over 256 / LANES rows
 // each.
@@ -251,12 +374,14 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) 
 //            in a row follow in the loop form.  Loads of missing entries are
 //            masked, not issued.  (Loading further ahead was measured slower:
 //            the extra data in flight no longer fits the L1 cache.)
-// val(e) is the off-diagonal value of CSR entry e, dg the diagonal; epi(i, k,
-// t, src_ik, own) receives own = dg_i src_ik + sum_j M_ij src_jk for the
-// components finished by this lane (component k = t * LANES + lane, turn t).
-template <int LANES, int ENT, class Val, class Epi>
-__device__ __forceinline__ void csr_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
-                                         const double* __restrict__ dg, Val val, Epi epi) {
+// val(e) is the off-diagonal value of CSR entry e, dg the diagonal; for the
+// components finished by this lane (component k = t * LANES + lane, turn t)
+// that are on, out[3i+k] = fin(i, k, t, src_ik, own) with
+// own = dg_i src_ik + sum_j M_ij src_jk.
+template <int LANES, int ENT, class Val, class Fin>
+__device__ __forceinline__ void lane_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
+                                          const double* __restrict__ dg, Val val, const bool (&on)[3],
+                                          double* __restrict__ out, Fin fin) {
   constexpr int GROUPS = SUB_THREADS / LANES;
   constexpr int PASSES = SUB_ROWS / GROUPS;
   constexpr int T = TURNS<LANES>;
@@ -282,8 +407,9 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int sub, const double
       for (int t = 0; t < T; ++t) {
         const int k = t * LANES + lane;
         if (k >= 3) continue;
+        if (!on_k(on, k)) continue;
         const double sk = src[3 * i + k];
-        epi(i, k, t, sk, dg[i] * sk + pick3(a, k));
+        out[3 * i + k] = fin(i, k, t, sk, dg[i] * sk + pick3(a, k));
       }
     }
   } else {
@@ -353,11 +479,25 @@ __device__ __forceinline__ void csr_tile(const DevPtrs& d, int sub, const double
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const int k = t * LANES + lane;
-        if (k >= 3) continue;
-        epi(i, k, t, sv[p][t], dv[p] * sv[p][t] + pick3(a, k));
+        if (k >= 3 || !on_k(on, k)) continue;
+        out[3 * i + k] = fin(i, k, t, sv[p][t], dv[p] * sv[p][t] + pick3(a, k));
       }
     }
   }
+}
+
+// The product of one sub-tile in the form of variant (LANES, ENT): for every
+// row i and component k with on[k], out[3i+k] = fin(i, k, t, src_ik, own)
+// with own = dg_i src_ik + sum_j M_ij src_jk (fin also takes the partial sums;
+// t is the turn of the calling lane)
+template <int LANES, int ENT, class Val, class Fin>
+__device__ __forceinline__ void csr_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
+                                         const double* __restrict__ dg, Val val, const bool (&on)[3],
+                                         double* __restrict__ out, Fin fin) {
+  if constexpr (LANES == 0)
+    ep_tile<ENT>(d, sub, src, dg, val, on, out, fin);
+  else
+    lane_tile<LANES, ENT>(d, sub, src, dg, val, on, out, fin);
 }
 
 // Learned preconditioner: u = M^-1 r with M^-1 in A's pattern, partial
@@ -376,11 +516,10 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_apply(DevPtrs d, int mode) {
   const float* __restrict__ moff = d.moff;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, sub, d.r, d.mdiag, [&](int e) { return (double)moff[e]; },
-      [&](int64_t i, int k, int t, double rk, double uk) {
-        if (!on_k(on, k)) return;
-        d.u[3 * i + k] = uk;
+      d, sub, d.r, d.mdiag, [&](int e) { return (double)moff[e]; }, on, d.u,
+      [&](int64_t, int, int t, double rk, double uk) {
         vt[t] += rk * uk;
+        return uk;
       });
   double v[3] = {0, 0, 0};
   turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);
@@ -527,18 +666,16 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_spmv(DevPtrs d, int mode, in
   const float* __restrict__ valf = d.valf;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, sub, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; },
+      d, sub, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; }, on,
+      mode == 0 ? d.w : d.r,
       [&](int64_t i, int k, int t, double sk, double own) {
-        if (!on_k(on, k)) return;
-        const int64_t e = 3 * i + k;
         if (mode == 0) {
-          d.w[e] = own;
           vt[t] += own * sk;
-        } else {
-          const double rk = d.b[e] - own;
-          d.r[e] = rk;
-          vt[t] += rk * rk;
+          return own;
         }
+        const double rk = d.b[3 * i + k] - own;
+        vt[t] += rk * rk;
+        return rk;
       });
   double v[3] = {0, 0, 0};
   turns_to_components<LANES>(vt, threadIdx.x & (LANES - 1), v);

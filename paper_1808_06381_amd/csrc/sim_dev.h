@@ -169,12 +169,14 @@ struct DevPtrs {
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
 
 // CSR product variants: X(index, lanes per row, entries per lane loaded
-// one pass ahead of the gathers; 0 = one entry at a time).  The order is the public
-// one of sim_tuning.
-#define CSR_VARIANTS 8
-#define CSR_VARIANT_DEFAULT 6
+// one pass ahead of the gathers; 0 = one entry at a time), or (0, entries per
+// thread and pass) for the entry-parallel form.  The order is the public one
+// of sim_tuning.
+#define CSR_VARIANTS 10
+#define CSR_VARIANT_DEFAULT 8
 #define CSR_VARIANT_LIST(X) \
-  X(0, 1, 0) X(1, 2, 0) X(2, 4, 0) X(3, 8, 0) X(4, 2, 2) X(5, 4, 1) X(6, 4, 2) X(7, 4, 3)
+  X(0, 1, 0) X(1, 2, 0) X(2, 4, 0) X(3, 8, 0) X(4, 2, 2) X(5, 4, 1) X(6, 4, 2) X(7, 4, 3) \
+  X(8, 0, 2) X(9, 0, 3)
 
 // The per-replica CG finisher sums the replica's sub-tile partials with
 // FINISH_THREADS threads.  A replica of more than L1_MIN_SUBS sub-tiles has

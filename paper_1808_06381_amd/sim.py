@@ -38,8 +38,9 @@ MPNN_NPARAMS_BLOCK = 9962  # with the 3 x 3 heads of the block system
 
 
 # CSR product variants of sim_tuning: (lanes per row, entries per lane loaded one
-# pass ahead of the gathers; 0 = one at a time), in the library's index order
-CSR_VARIANTS = [(1, 0), (2, 0), (4, 0), (8, 0), (2, 2), (4, 1), (4, 2), (4, 3)]
+# pass ahead of the gathers; 0 = one at a time), or (0, entries per thread and
+# pass) for the entry-parallel form, in the library's index order
+CSR_VARIANTS = [(1, 0), (2, 0), (4, 0), (8, 0), (2, 2), (4, 1), (4, 2), (4, 3), (0, 2), (0, 3)]
 
 
 class SimTuning(C.Structure):
@@ -450,7 +451,7 @@ class Sim:
         _check(lib().sim_autotune(self.h, int(reps), C.byref(t)), "sim_autotune")
         return t.as_dict()
 
-    def set_tuning(self, spmv_variant=6, apply_variant=6, vec_variant=0):
+    def set_tuning(self, spmv_variant=8, apply_variant=8, vec_variant=0):
         """Fix the CSR product variants (indices into CSR_VARIANTS) and the
         vector kernel's form (0 ordinary, 1 nontemporal accesses)."""
         t = SimTuning()

@@ -118,11 +118,15 @@ def test_every_csr_variant_solves_to_tolerance(variant):
 def test_prefetching_variants_give_the_loop_forms_bits():
     """Variants that load entries ahead of the gathers sum each row in the
     order of the loop form with the same lanes per row, so whole solves agree
-    bit for bit -- including rows longer than lanes x entries (the tail)."""
+    bit for bit -- including rows longer than lanes x entries (the tail).  The
+    entry-parallel variants add a row's products in entry order, one thread
+    per row, as the one-lane loop form does, so they give its bits too (rows
+    that span the LDS passes included: a sub-tile holds ~5 entries per row,
+    more than one pass of 2 or 3 per thread)."""
     cfg = inputs.cube_params(20000, 0.5, seed=21)
     pos = inputs.uniform_positions(cfg["n"], cfg["box"], 21)
     theta = precond.load(WEIGHTS)
-    pairs = [(1, 4), (2, 5), (2, 6), (2, 7)]   # (loop form, pipelined form)
+    pairs = [(1, 4), (2, 5), (2, 6), (2, 7), (0, 8), (0, 9)]   # (loop form, pipelined form)
     for fp32 in (0, 1):
         out = {}
         for v in sorted({v for p in pairs for v in p}):
