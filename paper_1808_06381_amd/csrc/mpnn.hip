@@ -301,6 +301,33 @@ __device__ __forceinline__ void mx_py(const s16x4 (&pw)[2][2], const uint16_t* x
   }
 }
 
+// P (at w16[off]) in LDS, row n (output) at n * MX_PS: the B operand of a
+// 16-input step is one 8-byte read per lane, the 16 rows of a tile on
+// distinct bank pairs
+constexpr int MX_PS = MP_H + 4;
+__device__ __forceinline__ void mx_stage_p(const uint16_t* __restrict__ w16, int off, uint16_t* ps) {
+  for (int idx = threadIdx.x; idx < MP_H * MP_H; idx += blockDim.x)
+    ps[(idx / MP_H) * MX_PS + idx % MP_H] = w16[off + idx];
+}
+
+// y = P h as mx_py, the B operands read from the LDS copy of P
+__device__ __forceinline__ void mx_py_lds(const uint16_t* ps, const uint16_t* xh, int stride,
+                                          f32x4 (&acc)[2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const s16x4 a = mx_a(xh, stride, s);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int n = 16 * nt + (lane & 15), q = 16 * s + 4 * (lane >> 4);
+      const s16x4 b = *reinterpret_cast<const s16x4*>(ps + n * MX_PS + q);
+      acc[nt] = mx_mma(a, b, acc[nt]);
+    }
+  }
+}
+
 // bf16 copy of h^l: layer l gathers it, layer l - 1 (or the encoder) writes it
 __device__ __forceinline__ uint16_t* mx_hb(const MpPtrs& m, int l) {
   return ((l ^ MP_NL) & 1) ? m.hb2 : m.hb;
@@ -403,12 +430,15 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_encode_mx(DevPtrs d, MpPtrs m
 
 // one message-passing layer l (bf16 activations): m, a and y^{l+1} (training),
 // h^{l+1} in FP32 and bf16
-// (six waves per SIMD: the gather is latency-bound; the register budget of
-// six still holds the kernel without spills)
-__global__ __launch_bounds__(MP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 8)))
+// (seven waves per SIMD: P is read from LDS rather than held in registers,
+// which leaves room for seven without spills; measured at N = 8e6 against
+// six: 1184 against 1201 us.  Neither more entries per chunk (128, four
+// waves: 1722 us) nor a gather two chunks ahead (1276-1318 us) was faster.)
+__global__ __launch_bounds__(MP_THREADS) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float Q[MP_H * MP_FE], c[MP_H], dd[MP_H];
+  __shared__ __align__(16) uint16_t ps[MP_H * MX_PS];
   __shared__ int rp[MP_ROWS + 1];
   // msg holds one chunk's messages during the gather, then the tile's FP32 h
   __shared__ __align__(16) float msg[MX_EC * MX_FS];
@@ -432,6 +462,7 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
   load_w(m, Q, base + MP_L_Q, MP_H * MP_FE);
   load_w(m, c, base + MP_L_C, MP_H);
   load_w(m, dd, base + MP_L_D, MP_H);
+  mx_stage_p(m.w16, base + MP_L_P, ps);
   const int64_t i0 = (int64_t)tile * MP_ROWS;
   if (t <= MP_ROWS) rp[t] = d.rowptr[i0 + t];
   __syncthreads();
@@ -442,8 +473,6 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
   float acc[8];
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0f;
-  s16x4 pw[2][2];
-  mx_load_p(m.w16, base + MP_L_P, pw);
   const int E0 = rp[0], E1 = rp[MP_ROWS];
   // software pipeline: while a chunk is processed, the gather of the next one
   // is in flight and the column indices of the one after are being read
@@ -472,7 +501,7 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
     // y_j = P h_j on the matrix cores, then the message of each entry
     {
       f32x4 yv[2];
-      mx_py(pw, xg, MX_HS, yv);
+      mx_py_lds(ps, xg, MX_HS, yv);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int en = 16 * w + 4 * (lane >> 4) + r;
