@@ -112,7 +112,7 @@ __global__ void k_cg_reset(DevPtrs d, double tol_override) {
   for (int r = threadIdx.x; r < d.nrep; r += blockDim.x) {
     CgRep& c = d.cg[r];
     for (int k = 0; k < 3; ++k) {
-      c.bb[k] = c.rr[k] = c.gamma[k] = c.alpha[k] = c.beta[k] = 0.0;
+      c.bb[k] = c.rr[k] = c.gamma[k] = c.alpha[k] = c.alpha_prev[k] = c.beta[k] = 0.0;
       c.state[k] = 0;
       c.it[k] = 0;
     }
@@ -153,6 +153,13 @@ __device__ __forceinline__ void stv(T* p, T v) {
 //   mode 2 (iteration):     p = u + beta p, s = w + beta s, x += alpha p,
 //                           r -= alpha s, u = M^-1 r
 // Partials (r, u) and (r, r) of the components touched.
+// x is updated every other iteration: in iteration j (j = it, counted per
+// component from the start) with j even the term alpha_j p_j is left
+// pending, with j odd x += alpha_{j-1} p_{j-1} + alpha_j p_j, p_{j-1} being
+// the p this iteration reads anyway; the x stream (48 bytes per row) is
+// touched in half the iterations.  k_cg_flush adds a pending term before
+// a true-residual check reads x; a start or restart zeroes p, so no pending
+// term outlives one.
 template <bool NT>
 __global__ __launch_bounds__(SUB_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   const int sub = sub_of_block(d);
@@ -160,13 +167,15 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_vec(DevPtrs d, int mode) {
   const int rid = d.blk_rep[sub / SUBS_PER_TILE];
   const CgRep& cr = d.cg[rid];
   if ((mode == 1 && !cr.restart) || (mode == 2 && !cr.run)) return;
-  bool on[3];
-  double al[3], be[3];
+  bool on[3], xodd[3];
+  double al[3], ap[3], be[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     on[k] = mode == 0 ? true : (mode == 1 ? cr.state[k] == 3 : cr.state[k] == 0);
     al[k] = cr.alpha[k];
+    ap[k] = cr.alpha_prev[k];
     be[k] = cr.beta[k];
+    xodd[k] = (cr.it[k] & 1) != 0;
   }
   double v[6] = {0, 0, 0, 0, 0, 0};  // (r,u)[3], (r,r)[3]
   const int64_t base = (int64_t)sub * VEC_ELEMS;
@@ -194,11 +203,12 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_vec(DevPtrs d, int mode) {
     } else {
       const double r0 = ldv<NT>(d.r + e);
       const double uk0 = ext ? ldv<NT>(d.u + e) : di * r0;
-      const double pk = uk0 + be[k] * ldv<NT>(d.p + e);
+      const double pold = ldv<NT>(d.p + e);
+      const double pk = uk0 + be[k] * pold;
       const double sk = ldv<NT>(d.w + e) + be[k] * ldv<NT>(d.s + e);
       stv<NT>(d.p + e, pk);
       stv<NT>(d.s + e, sk);
-      stv<NT>(d.x + e, ldv<NT>(d.x + e) + al[k] * pk);
+      if (on_k(xodd, k)) stv<NT>(d.x + e, ldv<NT>(d.x + e) + (ap[k] * pold + al[k] * pk));
       rk = r0 - al[k] * sk;
       stv<NT>(d.r + e, rk);
     }
@@ -219,6 +229,33 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_vec(DevPtrs d, int mode) {
 
 // Partials (r, u) per sub-tile after an external preconditioner pass (IC(0)),
 // component selection as k_cg_vec's mode.
+// Pending x terms before a true-residual check: x += alpha p for the
+// components whose check is pending and whose last iteration (it - 1) was
+// even (see k_cg_vec); replicas without a pending check return at once.
+__global__ __launch_bounds__(SUB_THREADS) void k_cg_flush(DevPtrs d) {
+  const int sub = sub_of_block(d);
+  if (sub < 0) return;
+  const CgRep& cr = d.cg[d.blk_rep[sub / SUBS_PER_TILE]];
+  if (!cr.check) return;
+  bool on[3];
+  double al[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    on[k] = cr.state[k] == 1 && (cr.it[k] & 1) != 0;
+    al[k] = cr.alpha[k];
+  }
+  if (!on[0] && !on[1] && !on[2]) return;
+  const int64_t base = (int64_t)sub * VEC_ELEMS;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int le = q * SUB_THREADS + threadIdx.x;
+    const int k = le % 3;
+    if (!on_k(on, k)) continue;
+    const int64_t e = base + le;
+    d.x[e] += pick3(al, k) * d.p[e];
+  }
+}
+
 __global__ __launch_bounds__(SUB_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) {
   const int sub = sub_of_block(d);
   if (sub < 0) return;
@@ -551,6 +588,7 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
         c.state[k] = 0;
         c.gamma[k] = gam;
         c.alpha[k] = gam / del;
+        c.alpha_prev[k] = 0.0;
         c.beta[k] = 0.0;
       }
     } else if (mode == 2 && c.state[k] == 0) {
@@ -568,6 +606,7 @@ __device__ void cg_advance(const DevPtrs& d, CgRep& c, int mode, const double (&
           ++finished;
         } else {
           c.beta[k] = beta;
+          c.alpha_prev[k] = c.alpha[k];
           c.alpha[k] = gam / den;
           c.gamma[k] = gam;
         }
@@ -808,6 +847,11 @@ hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t
 
 hipError_t launch_cg_warm(const DevPtrs& d, const int64_t* id_off, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_warm, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, id_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_flush(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_flush, dim3(xcd_grid(SUBS_PER_TILE * d.nblk)), dim3(SUB_THREADS), 0, s, d);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ hipError_t launch_cg_vec(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t e
 hipError_t launch_cg_spmv(const DevPtrs& d, int mode, int start_mode, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_cg_finish(const DevPtrs& d, int mode, hipStream_t s);
+hipError_t launch_cg_flush(const DevPtrs& d, hipStream_t s);
 hipError_t launch_cg_warm(const DevPtrs& d, const int64_t* id_off, hipStream_t s);
 hipError_t launch_cg_apply(const DevPtrs& d, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);

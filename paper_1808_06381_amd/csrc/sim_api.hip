@@ -562,6 +562,7 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
     HIPCHK(launch_cg_finish(d, 2, stream));
     if (run_form) HIPCHK(hipEventRecord(s->prof_run_ev[k + 1], stream));
   }
+  HIPCHK(launch_cg_flush(d, stream));  // x complete where a check is pending
   HIPCHK(launch_cg_spmv(d, 1, 0, stream));
   HIPCHK(launch_cg_finish(d, 3, stream));
   HIPCHK(launch_cg_vec(d, 1, stream));
@@ -645,7 +646,8 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
     const double ntile = (double)(SUBS_PER_TILE * d.nblk);  // partial slots written
     const double per_launch[kProfKernels] = {
         // vector kernel: r, p, w, s, x read (120 B/row), 1/diag (8), p, s, x, r, u written
-        // (120); with the learned preconditioner u is read instead of 1/diag and not written
+        // (120); with the learned preconditioner u is read instead of 1/diag and not written;
+        // x (48 of these bytes) only in odd iterations (see below)
         (learned ? rows * 240.0 : rows * 248.0) + ntile * 6.0 * 8.0,
         // product: row pointers (4), u (24), diag (8), w written (24), CSR col + value
         rows * 60.0 + 4.0 + nnz * (4.0 + (s->d.spmv_fp32 ? 4.0 : 8.0)) + ntile * 3.0 * 8.0,
@@ -684,7 +686,9 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
       if (smp.iter >= itmin - 1) continue;
       acc.launches += 1;
       acc.ms += ms;
-      acc.bytes += per_launch[smp.kernel];
+      // the vector kernel updates x every other iteration: in an even one
+      // (iteration number = every component's count here) x is not touched
+      acc.bytes += per_launch[smp.kernel] - (smp.kernel == 0 && smp.iter % 2 == 0 ? 48.0 * rows : 0.0);
     }
     s->prof_pending.clear();
     // the next solve samples the next residue, so that every position in a

@@ -76,6 +76,7 @@ struct CgRep {
   double rr[3];     // ||r||^2 (recursive while iterating, true after a check)
   double gamma[3];  // (r, M^-1 r) of the current iterate
   double alpha[3];
+  double alpha_prev[3];  // the previous iteration's alpha (0 after a start or restart)
   double beta[3];
   double tol2;      // tolerance^2 of this solve
   int32_t state[3]; // 0 iterating, 1 check pending, 2 done, 3 restart pending
