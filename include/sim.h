@@ -225,9 +225,9 @@ int sim_structure_factor(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz, dou
  * (several host threads or streams) race and must be serialised by the
  * caller.  Arguments as sim_structure_factor (SIM_EINVAL); SIM_ECAPACITY
  * when the scratch would exceed SIM_NOALLOC_SCRATCH_MAX: it needs about
- * 32 KiB x ceil(N_r / 4096) summed over replicas x ceil(nx / 64) x
- * ceil((2 my_max + 1) / 32) (e.g. N = 10^6 with nx = 64, my_max = 64 uses
- * 38 MiB).                                                                */
+ * 1 KiB x W x ceil(N_r / 4096) summed over replicas x ceil(nx / 64) x
+ * ceil(ny / W), ny = 2 my_max + 1, W = ny rounded up to a multiple of 16,
+ * at most 160 (e.g. N = 10^6 with nx = 64, my_max = 64 uses 35 MiB).      */
 #define SIM_NOALLOC_SCRATCH_MAX (48u << 20)
 int sim_structure_factor_noalloc(sim_t* sim, int32_t nx, int32_t my_max, int32_t mz,
                                  double* out);

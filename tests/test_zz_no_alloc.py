@@ -3,9 +3,16 @@ through the C ABI against sim_structure_factor on the same handle: the same
 kernels and chunking, so the same bits; two calls in a row, the second with
 a smaller input (fewer particles and a smaller wavevector grid), the output
 in a caller-owned device buffer; requests beyond the static scratch are
-refused with SIM_ECAPACITY."""
+refused with SIM_ECAPACITY.
+
+torch (the caller's device buffers) is imported when the module is
+collected: the library and torch load the HIP runtime under one soname, and
+the process keeps whichever loads first; torch's device queries fail when the
+library's copy came first, so torch must not be first imported after a test
+has called into the library."""
 import numpy as np
 import pytest
+import torch  # noqa: F401  (before any test loads the library)
 
 from paper_1808_06381_amd import inputs
 from paper_1808_06381_amd import sim as S
@@ -57,6 +64,6 @@ def test_noalloc_refuses_requests_beyond_its_scratch():
             sim.structure_factor_noalloc(256, 128, out)
         assert e.value.code == -6
         out = torch.empty((1, 64, 129), dtype=torch.float64, device="cuda")
-        sim.structure_factor_noalloc(64, 64, out)     # 38 MiB: fits
+        sim.structure_factor_noalloc(64, 64, out)     # 35 MiB: fits
         ref = sim.structure_factor(64, 64)
         np.testing.assert_array_equal(out.cpu().numpy(), ref)
