@@ -51,7 +51,8 @@
 namespace {
 
 constexpr int VV_HOME = 64;       // home particles (threads, one wave) per block
-constexpr int VV_STAGE = 256;     // candidates staged in LDS at a time
+constexpr int VV_STAGE = 64;      // candidates staged in LDS at a time (4 KB: a one-wave
+                                  // block with 256 staged, 16 KB, left two waves per SIMD)
 constexpr int VV_THREADS = 1024;  // threads of the binning kernels
 constexpr int VV_FOLD = 256;      // table blocks folded per first-stage reduce block
 
