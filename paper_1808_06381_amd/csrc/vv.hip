@@ -204,12 +204,13 @@ __global__ __launch_bounds__(VV_HOME) void k_vv_pairs(DevPtrs d, const VvRep* __
   const double delta = le_offset(R, *d.step_d - 1);
   const double scale = ldexp(1.0, vv_scale_exp(umax[B.rep], V.log2p));
   const double rmax2 = V.rmax2, cscale = V.cscale;
-  // lanes: P = next power of two >= the home count; G = 64 / P groups of P
-  // lanes share the wave, group g testing candidates g, g + G, g + 2G, ...
-  int P = 1;
-  while (P < B.count) P <<= 1;
-  const int G = VV_HOME / P, g = t / P, hl = t & (P - 1);
-  const bool home = hl < B.count;
+  // lanes: G = 64 / P groups of P = the home count lanes share the wave (the
+  // lanes past the last whole group idle), group g testing candidates g,
+  // g + G, g + 2G, ...  (Groups of the next power of two >= the count left
+  // up to half the lanes idle.)
+  const int P = B.count > 0 ? B.count : 1;
+  const int G = VV_HOME / P, g = t / P, hl = t - g * P;
+  const bool home = g < G && hl < B.count;
   const int64_t self = (int64_t)B.start + hl;
   double4 hp = make_double4(0.0, 0.0, 0.0, 0.0), hu = hp;
   if (home) {
