@@ -323,7 +323,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pair_terms(DevPtrs d) {
   const int tile = xcd_block(blockIdx.x, PAIR_TILES * d.nblk);  // rows in this XCD's L2
   if (tile >= PAIR_TILES * d.nblk) return;
   const int blk = tile / PAIR_TILES;
-  const RepDev& R = d.rep[d.blk_rep[blk]];
+  const RepDev R = d.rep[d.blk_rep[blk]];  // a copy: no reloads after the entry stores
   if (d.ctrl->overflow) return;
   __shared__ int rp[PAIR_THREADS + 1];        // row pointers of the tile
   __shared__ int16_t erow[PAIR_THREADS];      // tile row of each entry of the chunk
