@@ -243,70 +243,121 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
   d.x[3 * i] = d.x[3 * i + 1] = d.x[3 * i + 2] = 0.0;
 }
 
+// Entry-parallel 3 x 3 block product over a 1024-row tile (the scalar CG's
+// entry-parallel form with a block per entry): the tile's entries, one
+// contiguous CSR range, are striped over the block's threads, BEP per thread
+// and pass, so the column and block loads are coalesced and none waits on
+// its own row's pointers; each thread forms W_e src_j for its entries into
+// LDS, and after a barrier the thread of row i adds its row's products in
+// entry order.  The tile's own rows of src come in through LDS as
+// contiguous runs.  acc = sum_j W_ij src_j, si = src_i.  (Four lanes per row
+// walking interleaved entries: 1.4x the time at N = 1e6.)
+constexpr int BEP = 2;
+constexpr int BCAP = BLOCK_THREADS * BEP;
+template <class Mul>
+__device__ __forceinline__ void bep_tile(const DevPtrs& d, int tile, const double* __restrict__ src,
+                                         Mul mul, double (*prod)[BCAP], double* io,
+                                         double (&acc)[3], double (&si)[3]) {
+  static_assert(ROWS_PER_BLOCK == BLOCK_THREADS, "one thread per row of the tile");
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)tile * ROWS_PER_BLOCK;
+  // clamped: after an overflowing fill the row pointers may pass the
+  // capacity (the host discards that solve; the reads stay in bounds)
+  const int cap = (int)d.nnz_cap;
+  const int E0 = min(d.rowptr[base], cap);
+  const int ne = min(d.rowptr[base + ROWS_PER_BLOCK], cap) - E0;
+  const int64_t i = base + t;
+  const int r0 = min(d.rowptr[i], cap) - E0, r1 = min(d.rowptr[i + 1], cap) - E0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) io[t + q * BLOCK_THREADS] = src[3 * base + t + q * BLOCK_THREADS];
+  acc[0] = acc[1] = acc[2] = 0.0;
+  for (int c0 = 0; c0 < ne; c0 += BCAP) {
+    int c[BEP];
+#pragma unroll
+    for (int k = 0; k < BEP; ++k) {
+      const int e = c0 + t + k * BLOCK_THREADS;
+      c[k] = e < ne ? d.col[E0 + e] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < BEP; ++k) {
+      if (c[k] >= 0) {
+        const int64_t j = c[k];
+        const double g[3] = {src[3 * j], src[3 * j + 1], src[3 * j + 2]};
+        double o[3];
+        mul((int64_t)E0 + c0 + t + k * BLOCK_THREADS, g, o);
+        const int slot = t + k * BLOCK_THREADS;
+        prod[0][slot] = o[0];
+        prod[1][slot] = o[1];
+        prod[2][slot] = o[2];
+      }
+    }
+    __syncthreads();
+    const int lo = r0 > c0 ? r0 : c0, hi = r1 < c0 + BCAP ? r1 : c0 + BCAP;
+    for (int e = lo; e < hi; ++e) {
+      acc[0] += prod[0][e - c0];
+      acc[1] += prod[1][e - c0];
+      acc[2] += prod[2][e - c0];
+    }
+    __syncthreads();
+  }
+  if (ne == 0) __syncthreads();  // the own rows in io, as after a pass
+  si[0] = io[3 * t];
+  si[1] = io[3 * t + 1];
+  si[2] = io[3 * t + 2];
+}
+
+// three values per row of the tile to out[3 * (base + row) + k], through LDS
+// as contiguous runs (io free: every thread has read its own row)
+__device__ __forceinline__ void tile_store3(double* io, int64_t base, const double (&v)[3],
+                                            double* __restrict__ out) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  io[3 * t] = v[0];
+  io[3 * t + 1] = v[1];
+  io[3 * t + 2] = v[2];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[3 * base + t + q * BLOCK_THREADS] = io[t + q * BLOCK_THREADS];
+}
+
 // mode 0: w = A u, partial (w, u)                        [iterating replicas]
 // mode 1: r = b - A x, u = M^-1 r, p = s = 0, partials (r, u), (r, r)
 //                                                          [residual round]
-// Four lanes per row (a row's entries are contiguous and interleaved over
-// its lanes, so neighbouring lanes read neighbouring blocks); the lanes'
-// sums meet by shuffles within the group, lane k < 3 finishes component k.
-// A 1024-row tile takes four turns of 256 rows.
-constexpr int BLANES = 4;
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs bp, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
   const BcgRep& B = bp.bcg[d.blk_rep[tile]];
   if (B.state != (mode == 0 ? 0 : 1)) return;
-  const int lane = threadIdx.x & (BLANES - 1);
+  __shared__ double prod[3][BCAP];
+  __shared__ double io[3 * ROWS_PER_BLOCK];
   const double* src = mode == 0 ? d.u : d.x;
-  double v1 = 0.0, v2 = 0.0;  // this lane's dot-product terms
-  for (int turn = 0; turn < BLANES; ++turn) {
-    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + turn * (BLOCK_THREADS / BLANES) +
-                      (threadIdx.x / BLANES);
-    double acc[3] = {0.0, 0.0, 0.0};
-    const int64_t e1 = d.rowptr[i + 1];
-    for (int64_t e = d.rowptr[i] + lane; e < e1; e += BLANES) {
-      const int64_t j = d.col[e];
-      const double sj[3] = {src[3 * j], src[3 * j + 1], src[3 * j + 2]};
-      double t[3];
-      sym_mul(bp.bval + 6 * e, sj, t);
-      acc[0] += t[0];
-      acc[1] += t[1];
-      acc[2] += t[2];
-    }
+  double acc[3], si[3];
+  bep_tile(d, tile, src,
+           [&](int64_t e, const double (&g)[3], double (&o)[3]) { sym_mul(bp.bval + 6 * e, g, o); },
+           prod, io, acc, si);
+  const int64_t base = (int64_t)tile * ROWS_PER_BLOCK;
+  const int64_t i = base + threadIdx.x;
+  double dg[3];
+  sym_mul(bp.bdiag + 6 * i, si, dg);
+  double own[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      acc[k] += __shfl_xor(acc[k], 1, 64);
-      acc[k] += __shfl_xor(acc[k], 2, 64);
-    }
-    const double si[3] = {src[3 * i], src[3 * i + 1], src[3 * i + 2]};
-    double dg[3];
-    sym_mul(bp.bdiag + 6 * i, si, dg);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) acc[k] = dg[k] + acc[k];
-    if (mode == 0) {
-      if (lane < 3) {
-        d.w[3 * i + lane] = acc[lane];
-        v1 += si[lane] * acc[lane];
-      }
-    } else {
-      const double r[3] = {d.b[3 * i] - acc[0], d.b[3 * i + 1] - acc[1], d.b[3 * i + 2] - acc[2]};
-      double z[3];
-      sym_mul(bp.binv + 6 * i, r, z);
-      if (lane < 3) {
-        d.r[3 * i + lane] = r[lane];
-        if (!bp.learned) d.u[3 * i + lane] = z[lane];  // learned: k_bcg_apply forms u
-        d.p[3 * i + lane] = 0.0;
-        d.s[3 * i + lane] = 0.0;
-        v1 += r[lane] * z[lane];
-        v2 += r[lane] * r[lane];
-      }
-    }
-  }
+  for (int k = 0; k < 3; ++k) own[k] = dg[k] + acc[k];
   if (mode == 0) {
-    double v[1] = {v1};
+    double v[1] = {(si[0] * own[0] + si[1] * own[1]) + si[2] * own[2]};
+    tile_store3(io, base, own, d.w);
     tile_partials<1>(d, tile, 0, v);
   } else {
-    double v[2] = {v1, v2};
+    const double r[3] = {d.b[3 * i] - own[0], d.b[3 * i + 1] - own[1], d.b[3 * i + 2] - own[2]};
+    double z[3];
+    sym_mul(bp.binv + 6 * i, r, z);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d.r[3 * i + k] = r[k];
+      if (!bp.learned) d.u[3 * i + k] = z[k];  // learned: k_bcg_apply forms u
+      d.p[3 * i + k] = 0.0;
+      d.s[3 * i + k] = 0.0;
+    }
+    double v[2] = {(r[0] * z[0] + r[1] * z[1]) + r[2] * z[2], (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]};
     tile_partials<2>(d, tile, 1, v);
   }
 }
@@ -359,45 +410,27 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_vec(DevPtrs d, BlockPtrs 
 // the learned preconditioner: u = M^-1 r with the stored blocks (M_ii
 // symmetric FP64, M_ij row-major FP32), partial (r, u) into slot 1 (over the
 // (r, B r) the vector pass or residual round left there).  mode 0 after a
-// vector pass, 1 in a residual round.  Lanes and turns as k_bcg_spmv.
+// vector pass, 1 in a residual round.  Entry-parallel as k_bcg_spmv.
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_apply(DevPtrs d, BlockPtrs bp, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
   const BcgRep& B = bp.bcg[d.blk_rep[tile]];
   if (B.state != (mode == 0 ? 0 : 1)) return;
-  const int lane = threadIdx.x & (BLANES - 1);
-  double v1 = 0.0;
-  for (int turn = 0; turn < BLANES; ++turn) {
-    const int64_t i = (int64_t)tile * ROWS_PER_BLOCK + turn * (BLOCK_THREADS / BLANES) +
-                      (threadIdx.x / BLANES);
-    double acc[3] = {0.0, 0.0, 0.0};
-    const int64_t e1 = d.rowptr[i + 1];
-    for (int64_t e = d.rowptr[i] + lane; e < e1; e += BLANES) {
-      const int64_t j = d.col[e];
-      const double rj[3] = {d.r[3 * j], d.r[3 * j + 1], d.r[3 * j + 2]};
-      double o[3];
-      full_mul(bp.xo + 9 * e, rj, o);
-      acc[0] += o[0];
-      acc[1] += o[1];
-      acc[2] += o[2];
-    }
+  __shared__ double prod[3][BCAP];
+  __shared__ double io[3 * ROWS_PER_BLOCK];
+  double acc[3], ri[3];
+  bep_tile(d, tile, d.r,
+           [&](int64_t e, const double (&g)[3], double (&o)[3]) { full_mul(bp.xo + 9 * e, g, o); },
+           prod, io, acc, ri);
+  const int64_t base = (int64_t)tile * ROWS_PER_BLOCK;
+  const int64_t i = base + threadIdx.x;
+  double dg[3];
+  sym_mul(bp.xd + 6 * i, ri, dg);
+  double u[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      acc[k] += __shfl_xor(acc[k], 1, 64);
-      acc[k] += __shfl_xor(acc[k], 2, 64);
-    }
-    const double ri[3] = {d.r[3 * i], d.r[3 * i + 1], d.r[3 * i + 2]};
-    double dg[3];
-    sym_mul(bp.xd + 6 * i, ri, dg);
-    double u[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = dg[k] + acc[k];
-    if (lane < 3) {
-      d.u[3 * i + lane] = u[lane];
-      v1 += d.r[3 * i + lane] * u[lane];
-    }
-  }
-  double v[1] = {v1};
+  for (int k = 0; k < 3; ++k) u[k] = dg[k] + acc[k];
+  double v[1] = {(ri[0] * u[0] + ri[1] * u[1]) + ri[2] * u[2]};
+  tile_store3(io, base, u, d.u);
   tile_partials<1>(d, tile, 1, v);
 }
 
