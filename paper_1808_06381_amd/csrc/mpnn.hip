@@ -592,16 +592,19 @@ void k_mp_layer_mx(DevPtrs d, MpPtrs m, int l) {
 }
 
 // heads (bf16 activations): M^-1 values, four lanes per CSR entry.  After
-// one barrier (weights, row pointers, the tile's h) every quad walks its
-// entries on its own: the owning row comes from a binary search of the
-// tile's row pointers, and the next entry's column index is read one entry
-// ahead.
+// the tile's h and a table of every entry's row are staged, every quad walks
+// its entries on its own (the owning row read from the table: a binary
+// search of the row pointers per entry took 816 against 787 us at N = 8e6),
+// the next entry's column index read one entry ahead.
 __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m) {
   if (d.ctrl->overflow) return;  // row pointers may exceed the capacity
   __shared__ float hv[MP_H + 1], hz[MP_H], hze[MP_FE + 1];
   __shared__ int rp[MP_ROWS + 1];
   __shared__ double dg[MP_ROWS];
   __shared__ __align__(16) float hi_s[MP_ROWS * MX_FS];
+  constexpr int HEADS_EMAX = 4096;          // entries of a tile in the row table
+  static_assert(MP_ROWS <= 256, "rows fit the table's bytes");
+  __shared__ uint8_t erow[HEADS_EMAX];
   const int t = threadIdx.x;
   const int ntiles = (int)(m.rows / MP_ROWS);
   const int tile = xcd_block(blockIdx.x, ntiles);   // XCD-contiguous tiles
@@ -630,10 +633,17 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     for (int kk = 0; kk < 8; ++kk) hi_s[n * MX_FS + 8 * q + kk] = v[kk];
   }
   __syncthreads();
+  // the tile row of every entry, written by the row's four threads (a
+  // binary search of the row pointers per entry, a chain of six dependent
+  // LDS reads, where the tile holds more entries than the table)
+  const int E0 = rp[0], E1 = rp[MP_ROWS];
+  const bool table = E1 - E0 <= HEADS_EMAX;
+  if (table)
+    for (int e2 = rp[n] + q; e2 < rp[n + 1]; e2 += 4) erow[e2 - E0] = (uint8_t)n;
+  __syncthreads();
   // no barrier below: the four lanes of a quad share every entry, so the
   // quad's shuffles see only active lanes
-  const int E1 = rp[MP_ROWS];
-  int e = rp[0] + n;
+  int e = E0 + n;
   int jn = e < E1 ? d.col[e] : 0;
   for (; e < E1; e += MX_EC) {
     const int64_t j = jn;
@@ -644,9 +654,13 @@ __global__ __launch_bounds__(MP_THREADS) void k_mp_heads_mx(DevPtrs d, MpPtrs m)
     const ushort4 eq = *reinterpret_cast<const ushort4*>(m.efh + 4 * (int64_t)e);
     static_assert((MP_ROWS & (MP_ROWS - 1)) == 0, "the row search halves a power of two");
     int r = 0;   // the last row whose range starts at or before e
+    if (table) {
+      r = erow[e - E0];
+    } else {
 #pragma unroll
-    for (int half = MP_ROWS / 2; half > 0; half >>= 1)
-      if (rp[r + half] <= e) r += half;
+      for (int half = MP_ROWS / 2; half > 0; half >>= 1)
+        if (rp[r + half] <= e) r += half;
+    }
     float p = 0.0f;
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
