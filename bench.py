@@ -70,7 +70,9 @@ def parse():
                     help="plain steps at shear 0.5 before timing (from uniform positions)")
     ap.add_argument("--only", default="",
                     help="c5: the scale workloads only; c5-single: the N = 8e6 box only; "
-                         "small: the N = 1000 case and the paper's box only (no headline line)")
+                         "small: the N = 1000 case and the paper's box only; c2: the N = 1e6 "
+                         "boxes with S(q) and the velocity correlation only (no headline line "
+                         "for small and c2)")
     ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -382,6 +384,52 @@ def iteration_roofline(r, copy_gbs, traffic):
     return out
 
 
+def run_c2(args, S, inputs, theta, forms, head, stream, torch, np, copy_gbs):
+    """The three N = 1e6 boxes (plain, learned, IC(0)), S(q) and the velocity
+    correlation of the first box's final state."""
+    out = {}
+    cfgs, pos0s = [], []
+    for k, shear in enumerate(SHEARS):
+        cfg = inputs.single_box(shear_rate=shear, seed=1 + k)["params"]
+        cfgs.append(cfg)
+        pos0s.append(inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"]))
+    c2 = {}
+    for form in forms + ["ic0"]:
+        after = (lambda sims: dict(sq=measure_sq(sims[0], cfgs[0]["n"], np),
+                                   vv=measure_vv(sims[0], cfgs[0]["n"], np))) \
+            if form == head else None
+        c2[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np,
+                             steps=args.c2_steps, after=after, label="c2 ")
+    out["single_n1e6_x3"] = dict(
+        workload=f"three boxes N=1000000, L=100, shear rates {list(SHEARS)}, same physics, "
+                 f"from uniform positions; one bench step = one time step of each box",
+        forms={f: form_summary(r, np) for f, r in c2.items()},
+        roofline=iteration_roofline(c2[head], copy_gbs, None))
+    if "learned" in c2 and "plain" in c2:
+        out["single_n1e6_x3"]["learned_vs_plain"] = round(c2["learned"]["value"] /
+                                                          c2["plain"]["value"], 4)
+    extra = c2[head].get("extra") or {}
+    sqm = extra.get("sq")
+    if sqm:
+        ms = sqm["kernel_ms_events"] - args.event_over_us * 1e-3
+        tf = sqm["flops_per_call"] / (ms * 1e-3) / 1e12
+        out["structure_factor"] = dict(
+            sqm, kernel="k_sq_partial", kernel_ms=round(ms, 4),
+            roofline=dict(bound="mfma", achieved=round(tf, 2), peak=PEAK_FP64_TFLOPS,
+                          unit="TFLOP/s", frac=round(tf / PEAK_FP64_TFLOPS, 4)))
+    vvm = extra.get("vv")
+    if vvm:
+        ms = vvm["kernel_ms_events"] - args.event_over_us * 1e-3
+        tops = VV_OPS_PER_PAIR * vvm["pairs"] / (ms * 1e-3) / 1e12
+        out["velocity_correlation"] = dict(
+            vvm, kernel="k_vv_pairs", kernel_ms=round(ms, 4),
+            pairs_per_s=round(vvm["pairs"] / (ms * 1e-3), 1),
+            roofline=dict(bound="alu", achieved=round(tops, 3), peak=PEAK_FP64_TOPS,
+                          unit="Top/s", frac=round(tops / PEAK_FP64_TOPS, 4),
+                          ops_per_pair=VV_OPS_PER_PAIR))
+    return out
+
+
 def run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs):
     """Scale workloads: one N = 8e6 box (L = 200) and 16 replicas of N = 5e5
     (L = 79.37), shear 0.5, each pre-sheared from uniform positions; every
@@ -503,6 +551,11 @@ def main():
         # the latency-bound small workloads alone (not the metric's line)
         print(json.dumps(run_small(args, S, inputs, theta, stream, torch, np)), flush=True)
         return
+    if args.only == "c2":
+        # the N = 1e6 boxes with S(q) and the velocity correlation alone
+        print(json.dumps(run_c2(args, S, inputs, theta, forms, head, stream, torch, np, copy_gbs)),
+              flush=True)
+        return
 
     c5, batch_state = run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs)
     hr = c5["single_n8e6"]["runs"][head]
@@ -551,47 +604,7 @@ def main():
     out["event_overhead_us"] = round(args.event_over_us, 2)
 
     if not args.only:
-        # the three N = 1e6 boxes (plain, learned, IC(0)), S(q) and the
-        # velocity correlation of the first box's final state
-        cfgs, pos0s = [], []
-        for k, shear in enumerate(SHEARS):
-            cfg = inputs.single_box(shear_rate=shear, seed=1 + k)["params"]
-            cfgs.append(cfg)
-            pos0s.append(inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"]))
-        c2 = {}
-        for form in forms + ["ic0"]:
-            after = (lambda sims: dict(sq=measure_sq(sims[0], cfgs[0]["n"], np),
-                                       vv=measure_vv(sims[0], cfgs[0]["n"], np))) \
-                if form == head else None
-            c2[form] = time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np,
-                                 steps=args.c2_steps, after=after, label="c2 ")
-        out["single_n1e6_x3"] = dict(
-            workload=f"three boxes N=1000000, L=100, shear rates {list(SHEARS)}, same physics, "
-                     f"from uniform positions; one bench step = one time step of each box",
-            forms={f: form_summary(r, np) for f, r in c2.items()},
-            roofline=iteration_roofline(c2[head], copy_gbs, None))
-        if "learned" in c2 and "plain" in c2:
-            out["single_n1e6_x3"]["learned_vs_plain"] = round(c2["learned"]["value"] /
-                                                              c2["plain"]["value"], 4)
-        extra = c2[head].get("extra") or {}
-        sqm = extra.get("sq")
-        if sqm:
-            ms = sqm["kernel_ms_events"] - args.event_over_us * 1e-3
-            tf = sqm["flops_per_call"] / (ms * 1e-3) / 1e12
-            out["structure_factor"] = dict(
-                sqm, kernel="k_sq_partial", kernel_ms=round(ms, 4),
-                roofline=dict(bound="mfma", achieved=round(tf, 2), peak=PEAK_FP64_TFLOPS,
-                              unit="TFLOP/s", frac=round(tf / PEAK_FP64_TFLOPS, 4)))
-        vvm = extra.get("vv")
-        if vvm:
-            ms = vvm["kernel_ms_events"] - args.event_over_us * 1e-3
-            tops = VV_OPS_PER_PAIR * vvm["pairs"] / (ms * 1e-3) / 1e12
-            out["velocity_correlation"] = dict(
-                vvm, kernel="k_vv_pairs", kernel_ms=round(ms, 4),
-                pairs_per_s=round(vvm["pairs"] / (ms * 1e-3), 1),
-                roofline=dict(bound="alu", achieved=round(tops, 3), peak=PEAK_FP64_TOPS,
-                              unit="Top/s", frac=round(tops / PEAK_FP64_TOPS, 4),
-                              ops_per_pair=VV_OPS_PER_PAIR))
+        out.update(run_c2(args, S, inputs, theta, forms, head, stream, torch, np, copy_gbs))
         # 64 replicas of uneven size in one handle
         bcfgs = inputs.batch_replicas(count=64, seed=7)
         bpos = np.concatenate([inputs.uniform_positions(c["n"], c["box"], c["seed"]) for c in bcfgs])
