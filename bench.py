@@ -25,7 +25,7 @@ paper's own box (4 x 20060 at its four shear rates), anisotropic friction,
 and the oracle's own throughput on the host cores (1 and all) for a bounded
 sample of the pre-sheared scale workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c5|c5-single]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c5|c5-single|c2|small]
                   [--no-cpu-baseline] [--c5-preshear 2000]
 """
 import argparse
