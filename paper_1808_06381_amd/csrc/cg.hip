@@ -8,13 +8,15 @@
 //   w = A u;  gamma = (r, u), delta = (w, u)
 //   beta' = gamma' / gamma, alpha' = gamma' / (delta' - beta' gamma' / alpha)
 //
-// Per iteration three launches, none with a cache write-back fence:
-//   k_cg_vec   every vector update, element-parallel (fully coalesced), and
-//              the partial sums of (r, u) and (r, r) per sub-tile of 256 rows;
-//   k_cg_spmv  w = A u with a group of 1, 2, 4 or 8 lanes per CSR row (4
-//              unless the autotuner picked another), so the neighbours of a
-//              row -- contiguous runs of the cell-sorted order -- are fetched
-//              by adjacent lanes; partial sums of (w, u);
+// Per iteration three launches (four with the learned M^-1 product,
+// k_cg_apply), none with a cache write-back fence:
+//   k_cg_vec   every vector update, element-parallel (fully coalesced; x
+//              every other iteration), and the partial sums of (r, u) and
+//              (r, r) per sub-tile of 256 rows;
+//   k_cg_spmv  w = A u, by default entry-parallel (the sub-tile's entries
+//              striped over its threads, the products summed per row from
+//              LDS), or with a group of 1, 2, 4 or 8 lanes per CSR row (the
+//              tuning variants); partial sums of (w, u);
 //   k_cg_finish one block per replica: the sub-tile partials in a fixed order,
 //              then the scalar recurrences and the convergence state.
 // Sums are deterministic (fixed trees, no floating-point atomics).
