@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
 // LDS, and after a barrier the thread of row i adds its row's products in
 // entry order.  The tile's own rows of src come in through LDS as
 // contiguous runs.  acc = sum_j W_ij src_j, si = src_i.  (Four lanes per row
-// walking interleaved entries: 1.4x the time at N = 1e6.)
+// walking interleaved entries took 82.5 against 74.4 us at N = 1e6.)
 constexpr int BEP = 2;
 constexpr int BCAP = BLOCK_THREADS * BEP;
 template <class Mul>
