@@ -294,9 +294,10 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_dot_ru(DevPtrs d, int mode) 
 // variants give the same bits, and those of the one-lane loop form).  A row
 // that spans passes continues its sum in the next one.  The sub-tile's own
 // rows of src come in, and its results go out, through LDS as contiguous runs
-// of 3 * SUB_ROWS doubles.  Measured at N = 8e6 (brick order, k = 5.5): 244 us
-// against 321 us for four lanes per row, the loads no longer waiting on a
-// row-pointer load of their own and every lane carrying an entry.
+// of 3 * SUB_ROWS doubles.  Measured at N = 8e6 (brick order, k = 5.5): the
+// product 227 against 304 us for four lanes per row (learned CG iterations of
+// the evolved box), the loads no longer waiting on a row-pointer load of
+// their own and every lane carrying an entry.
 template <int EPT, class Val, class Fin>
 __device__ __forceinline__ void ep_tile(const DevPtrs& d, int sub, const double* __restrict__ src,
                                         const double* __restrict__ dg, Val val, const bool (&on)[3],
