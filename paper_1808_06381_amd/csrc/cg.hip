@@ -317,14 +317,17 @@ __device__ __forceinline__ void ep_tile(const DevPtrs& d, int sub, const double*
   const double dgi = dg[i];
 #pragma unroll
   for (int q = 0; q < 3; ++q) io[t + q * SUB_THREADS] = src[3 * base + t + q * SUB_THREADS];
+  // values kept in their stored type until the multiply: a conversion next
+  // to the load would wait for it, and with it for every gather in flight
+  using VT = decltype(val(0));
   int c[EPT];
-  double m[EPT];
-  auto load = [&](int c0, int (&cl)[EPT], double (&ml)[EPT]) {
+  VT m[EPT];
+  auto load = [&](int c0, int (&cl)[EPT], VT (&ml)[EPT]) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = c0 + t + k * SUB_THREADS;
       cl[k] = -1;
-      ml[k] = 0.0;
+      ml[k] = VT(0);
       if (e < ne) {
         cl[k] = d.col[E0 + e];
         ml[k] = val(E0 + e);
@@ -346,23 +349,24 @@ __device__ __forceinline__ void ep_tile(const DevPtrs& d, int sub, const double*
       }
     }
     int cn[EPT];
-    double mn[EPT];
+    VT mn[EPT];
     if (c0 + CAP < ne) {
       load(c0 + CAP, cn, mn);
     } else {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         cn[k] = -1;
-        mn[k] = 0.0;
+        mn[k] = VT(0);
       }
     }
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       if (c[k] >= 0) {
         const int slot = t + k * SUB_THREADS;
-        prod[0][slot] = m[k] * g[k][0];
-        prod[1][slot] = m[k] * g[k][1];
-        prod[2][slot] = m[k] * g[k][2];
+        const double mk = m[k];
+        prod[0][slot] = mk * g[k][0];
+        prod[1][slot] = mk * g[k][1];
+        prod[2][slot] = mk * g[k][2];
       }
     }
     __syncthreads();
@@ -414,7 +418,8 @@ __device__ __forceinline__ void ep_tile(const DevPtrs& d, int sub, const double*
 //            in a row follow in the loop form.  Loads of missing entries are
 //            masked, not issued.  (Loading further ahead was measured slower:
 //            the extra data in flight no longer fits the L1 cache.)
-// val(e) is the off-diagonal value of CSR entry e, dg the diagonal; for the
+// val(e) is the off-diagonal value of CSR entry e (in its stored type, FP32
+// or FP64; the products are formed in FP64), dg the diagonal; for the
 // components finished by this lane (component k = t * LANES + lane, turn t)
 // that are on, out[3i+k] = fin(i, k, t, src_ik, own) with
 // own = dg_i src_ik + sum_j M_ij src_jk.
@@ -468,13 +473,13 @@ __device__ __forceinline__ void lane_tile(const DevPtrs& d, int sub, const doubl
       }
     }
     int c[2][ENT];      // columns of the current / next pass (-1: no entry)
-    double m[2][ENT];
+    decltype(val(0)) m[2][ENT];  // values in their stored type (as in ep_tile)
     auto load_entries = [&](int p, int buf) {
 #pragma unroll
       for (int q = 0; q < ENT; ++q) {
         const int e = e0[p] + lane + q * LANES;
         c[buf][q] = -1;
-        m[buf][q] = 0.0;
+        m[buf][q] = 0;
         if (e < e1[p]) {
           c[buf][q] = d.col[e];
           m[buf][q] = val(e);
@@ -503,7 +508,7 @@ __device__ __forceinline__ void lane_tile(const DevPtrs& d, int sub, const doubl
         a[k] = 0.0;
 #pragma unroll
         for (int q = 0; q < ENT; ++q) {
-          const double prod = m[cur][q] * g[q][k];
+          const double prod = (double)m[cur][q] * g[q][k];
           a[k] += c[cur][q] >= 0 ? prod : 0.0;  // adding +0 leaves the bits
         }
       }
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_apply(DevPtrs d, int mode) {
   const float* __restrict__ moff = d.moff;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, sub, d.r, d.mdiag, [&](int e) { return (double)moff[e]; }, on, d.u,
+      d, sub, d.r, d.mdiag, [&](int e) { return moff[e]; }, on, d.u,
       [&](int64_t, int, int t, double rk, double uk) {
         vt[t] += rk * uk;
         return uk;
@@ -708,7 +713,12 @@ __global__ __launch_bounds__(SUB_THREADS) void k_cg_spmv(DevPtrs d, int mode, in
   const float* __restrict__ valf = d.valf;
   double vt[TURNS<LANES>] = {};  // this lane's sums, one per turn
   csr_tile<LANES, ENT>(
-      d, sub, src, d.diag, [&](int e) { return FP32 ? (double)valf[e] : val[e]; }, on,
+      d, sub, src, d.diag, [&](int e) {
+        if constexpr (FP32)
+          return valf[e];
+        else
+          return val[e];
+      }, on,
       mode == 0 ? d.w : d.r,
       [&](int64_t i, int k, int t, double sk, double own) {
         if (mode == 0) {
