@@ -41,6 +41,12 @@ __device__ __forceinline__ void sym_mul(const double* m, const double v[3], doub
   out[2] = (m[2] * v[0] + m[4] * v[1]) + m[5] * v[2];
 }
 
+// the same with the six values rounded to FP32 (products and sums in FP64)
+__device__ __forceinline__ void sym_mul_f(const float* mf, const double v[3], double out[3]) {
+  const double m[6] = {mf[0], mf[1], mf[2], mf[3], mf[4], mf[5]};
+  sym_mul(m, v, out);
+}
+
 // row-major 3 x 3 in FP32 (the learned preconditioner's M_ij) times a vector
 __device__ __forceinline__ void full_mul(const float* a, const double v[3], double out[3]) {
 #pragma unroll
@@ -155,6 +161,11 @@ __global__ __launch_bounds__(PB_THREADS) void k_pair_block(DevPtrs d, BlockPtrs 
       for (int m = 0; m < 6; ++m) {
         out[m] = -W[m];
         contrib[m][t] = W[m];
+      }
+      if (bp.fp32) {
+        float* outf = bp.bvalf + 6 * (int64_t)e;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) outf[m] = (float)(-W[m]);
       }
       if (d.want_er) {  // the learned preconditioner's input: traces, r / rc
         d.val[e] = -((W[0] + W[3]) + W[5]) / 3.0;
@@ -323,6 +334,10 @@ __device__ __forceinline__ void tile_store3(double* io, int64_t base, const doub
 // mode 0: w = A u, partial (w, u)                        [iterating replicas]
 // mode 1: r = b - A x, u = M^-1 r, p = s = 0, partials (r, u), (r, r)
 //                                                          [residual round]
+// FP32: the off-diagonal blocks of mode 0 from their FP32 copies (the
+// residual round always takes the FP64 blocks, so the stopping test is the
+// FP64 residual)
+template <bool FP32>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs bp, int mode) {
   const int tile = xcd_block(blockIdx.x, d.nblk);
   if (tile >= d.nblk) return;
@@ -333,7 +348,12 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_spmv(DevPtrs d, BlockPtrs
   const double* src = mode == 0 ? d.u : d.x;
   double acc[3], si[3];
   bep_tile(d, tile, src,
-           [&](int64_t e, const double (&g)[3], double (&o)[3]) { sym_mul(bp.bval + 6 * e, g, o); },
+           [&](int64_t e, const double (&g)[3], double (&o)[3]) {
+             if constexpr (FP32)
+               sym_mul_f(bp.bvalf + 6 * e, g, o);
+             else
+               sym_mul(bp.bval + 6 * e, g, o);
+           },
            prod, io, acc, si);
   const int64_t base = (int64_t)tile * ROWS_PER_BLOCK;
   const int64_t i = base + threadIdx.x;
@@ -540,7 +560,7 @@ hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, h
 }
 
 hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
+  hipLaunchKernelGGL(k_bcg_spmv<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
   if (bp.learned)
     hipLaunchKernelGGL(k_bcg_apply, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
   hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 2);
@@ -548,7 +568,10 @@ hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_
 }
 
 hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
-  hipLaunchKernelGGL(k_bcg_spmv, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
+  if (bp.fp32)
+    hipLaunchKernelGGL(k_bcg_spmv<true>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
+  else
+    hipLaunchKernelGGL(k_bcg_spmv<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 0);
   hipLaunchKernelGGL(k_bcg_finish, dim3(d.nrep), dim3(256), 0, s, d, bp, 0);
   hipLaunchKernelGGL(k_bcg_vec, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp);
   if (bp.learned)

@@ -127,6 +127,7 @@ struct BcgRep {         // per-replica scalars of the block CG (3n stacked unkno
 };
 struct BlockPtrs {
   double* bval;         // -W_ij per CSR entry: xx, xy, xz, yy, yz, zz
+  float* bvalf;         // the same rounded to FP32 (iteration products when fp32)
   double* bdiag;        // gamma0 I + sum_j W_ij per row (6 values)
   double* binv;         // its inverse (6 values): the block-Jacobi preconditioner
   BcgRep* bcg;          // [replicas]
@@ -140,7 +141,7 @@ struct BlockPtrs {
   double* gt;           // [rows][3] R G (training)
   double* gh;           // [rows][3] A_ii^-1 G (training)
   int32_t learned;      // 1: the block CG applies the learned M^-1
-  int32_t pad0;
+  int32_t fp32;         // 1: w = A u of the iterations with the FP32 blocks
 };
 hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
 hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, hipStream_t s);

@@ -290,8 +290,12 @@ static int alloc_csr(sim_t* s, int64_t cap) {
   if ((rc = dalloc(s, (void**)&s->d.er, sizeof(float) * (size_t)cap))) return rc;
   if (s->block) {
     dfree(s, s->bp.bval);
+    dfree(s, s->bp.bvalf);
     s->bp.bval = nullptr;
+    s->bp.bvalf = nullptr;
     if ((rc = dalloc(s, (void**)&s->bp.bval, sizeof(double) * 6 * (size_t)cap))) return rc;
+    if (s->bp.fp32 && (rc = dalloc(s, (void**)&s->bp.bvalf, sizeof(float) * 6 * (size_t)cap)))
+      return rc;
   }
   if (s->ic0) {
     if ((rc = dalloc(s, (void**)&s->d.lcol, sizeof(int32_t) * (size_t)cap))) return rc;
@@ -891,7 +895,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   for (int r = 0; r < replicas; ++r) s->block = s->block || anisotropic(params[r]);
   if (s->block)
     for (int r = 0; r < replicas; ++r)
-      if (params[r].precond == SIM_PC_IC0 || params[r].spmv_fp32 || params[r].warm_start) {
+      if (params[r].precond == SIM_PC_IC0 || params[r].warm_start) {
         delete s;
         return SIM_ENOTSUP;
       }
@@ -1052,6 +1056,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
     ALLOC(s->bp.bdiag, sizeof(double) * 6 * rows);
     ALLOC(s->bp.binv, sizeof(double) * 6 * rows);
     s->bp.brep = s->brep_d;
+    s->bp.fp32 = params[0].spmv_fp32 ? 1 : 0;
   }
   {
     const int64_t m = std::max<int64_t>(s->rows + 1, d.ncell_entries);

@@ -12,7 +12,8 @@ new positions within dt times that velocity error.
 Cases: the system at creation and after steps with a large Lees-Edwards
 offset; ten steps, each from the GPU's positions; a scaled isotropic tensor (a_par = a_perp = 2)
 against the scalar path with alpha doubled; a batch with an isotropic and
-two anisotropic replicas; sim_solve against a dense solve; refused options.
+two anisotropic replicas; sim_solve against a dense solve; the FP32-valued
+product (a dense solve and ten steps); refused options.
 """
 import numpy as np
 import pytest
@@ -180,10 +181,62 @@ def test_solve_against_dense():
     assert st["iters"][0] > 0
 
 
+def test_fp32_product_solve_against_dense():
+    """FP32 copies of the off-diagonal blocks in the iteration products, FP64
+    diagonal blocks, dots and residual rounds: the stopping test is the FP64
+    stacked residual of the FP64 path, so the answer meets the same
+    forward-error bound kappa(A) tau; 1e-5 relative is the stated floor."""
+    cfg = aniso(inputs.cube_params(300, 0.6, seed=35), 5.0, 0.3)
+    pos0 = inputs.uniform_positions(300, cfg["box"], 35)
+    b = np.random.default_rng(1).normal(size=(300, 3))
+    with S.Sim(dict(cfg, spmv_fp32=1), pos0) as sim:
+        v, st = sim.solve(b, tol=1e-10)
+        # the exported system is the FP64 one
+        rows, cols, vals, diag, rhs = sim.block_system()
+    with S.Sim(cfg, pos0) as sim:
+        v64, st64 = sim.solve(b, tol=1e-10)
+        rows64, cols64, vals64, diag64, _ = sim.block_system()
+    np.testing.assert_array_equal(vals, vals64)
+    np.testing.assert_array_equal(diag, diag64)
+    ref = oracle.build_block_system(cfg, pos0, 5.0, 0.3)
+    A = oracle.block_dense(ref)
+    want = np.linalg.solve(A, b.ravel()).reshape(-1, 3)
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(v - want) / np.linalg.norm(want)
+    assert err <= 1e-5 and err <= kappa * 1e-10, (err, kappa)
+    res = np.linalg.norm(b.ravel() - A @ v.ravel()) / np.linalg.norm(b)
+    assert res <= 1e-10 * (1 + 1e-6), res
+    assert max(st["relres"]) <= 1e-10
+    assert max(st["iters"]) <= max(st64["iters"]) + 40
+    assert not np.array_equal(v, v64)   # the FP32 blocks were used
+
+
+def test_fp32_product_steps_match_oracle():
+    """Ten steps with the FP32 product, each compared with the oracle's FP64
+    step from the GPU's own positions: velocities within 1e-5 relative (the
+    stated floor; both solves meet the FP64 residual 1e-10)."""
+    case = inputs.small_case(seed=6)
+    cfg = aniso(dict(case["params"], shear_rate=0.5), 2.5, 0.4)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    with S.Sim(dict(cfg, spmv_fp32=1), pos0, tol=1e-10) as sim:
+        for k in range(10):
+            pos_k, _, meta = sim.state()
+            assert meta["step"] == k
+            st = sim.step(1)
+            pos_g, vel_g, _ = sim.state()
+            pos_o, vel_o, _ = oracle.step_block(cfg, pos_k, k, 2.5, 0.4, tol=1e-10)
+            kap = kappa_bound(cfg, pos_k, 2.5, 0.4, k)
+            rel = np.linalg.norm(vel_g - vel_o) / np.linalg.norm(vel_o)
+            assert rel < 1e-5 and rel < 2 * kap * 1e-10, (k, rel, kap)
+            assert max(st["relres"]) <= 1e-10
+            dx = np.abs(le_diff(cfg, k + 1, pos_g, pos_o)).max()
+            assert dx <= cfg["dt"] * 2 * kap * 1e-10 * np.linalg.norm(vel_o) + 1e-13, k
+
+
 def test_refused_options():
     base = inputs.cube_params(500, 0.1, seed=36)
     pos0 = inputs.uniform_positions(500, base["box"], 36)
-    for extra in (dict(precond="ic0"), dict(warm_start=1), dict(spmv_fp32=1)):
+    for extra in (dict(precond="ic0"), dict(warm_start=1)):
         with pytest.raises(S.SimError):
             S.Sim(aniso(dict(base, **extra), 2.0, 1.0), pos0)
     with S.Sim(aniso(base, 2.0, 1.0), pos0) as sim:
