@@ -200,29 +200,36 @@ def measure_vv(sim, n, np, r_max=10.0, nbins=100, reps=3):
 
 def measure_aniso(args, S, inputs, np, a_par=2.0, a_perp=0.5, warm=3, steps=10):
     """Anisotropic pair friction (3 x 3 blocks, block-Jacobi CG over the 3n
-    coupled unknowns) on the N = 1e6 shear-0.1 box: eager steps."""
-    cfg = inputs.single_box(shear_rate=0.1, seed=1)["params"]
-    cfg = dict(cfg, friction_par=a_par, friction_perp=a_perp)
-    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
-    with S.Sim(cfg, pos0, tol=args.tol) as sim:
-        sim.step(warm)
-        its = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            st = sim.step(1)
-            its.append(st["iters"][0])
-        dt = time.perf_counter() - t0
-        nnz = st["nnz"]
-        rows = (cfg["n"] + 1023) // 1024 * 1024   # rows padded to whole 1024-row tiles
-    return dict(workload=f"the N={cfg['n']} box at shear 0.1 with pair friction a_par={a_par} "
-                         f"along and a_perp={a_perp} across the line of centres",
-                value=round(cfg["n"] * steps / dt, 1), unit="particle-steps/s",
-                ms_per_step=round(dt / steps * 1e3, 3), steps=steps,
-                mean_cg_iters=round(float(np.mean(its)), 2),
-                # block product per launch: row pointers 8, own vector 24,
-                # diagonal block 48, result 24 B per row; block 48 + column 4 B
-                # per entry (each gathered vector counted once)
-                k_bcg_spmv_bytes_per_launch=104 * rows + 52 * nnz)
+    coupled unknowns) on the N = 1e6 shear-0.1 box: eager steps, with FP64
+    blocks and with FP32-valued iteration products (spmv_fp32)."""
+    cfg0 = inputs.single_box(shear_rate=0.1, seed=1)["params"]
+    pos0 = inputs.uniform_positions(cfg0["n"], cfg0["box"], cfg0["seed"])
+    res = {}
+    for fp32 in (0, 1):
+        cfg = dict(cfg0, friction_par=a_par, friction_perp=a_perp, spmv_fp32=fp32)
+        with S.Sim(cfg, pos0, tol=args.tol) as sim:
+            sim.step(warm)
+            its = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st = sim.step(1)
+                its.append(st["iters"][0])
+            dt = time.perf_counter() - t0
+            nnz = st["nnz"]
+            rows = (cfg["n"] + 1023) // 1024 * 1024   # rows padded to whole 1024-row tiles
+        res[fp32] = dict(value=round(cfg["n"] * steps / dt, 1),
+                         ms_per_step=round(dt / steps * 1e3, 3),
+                         mean_cg_iters=round(float(np.mean(its)), 2),
+                         # block product per launch: row pointers 8, own vector
+                         # 24, diagonal block 48, result 24 B per row; block 48
+                         # (FP32: 24) + column 4 B per entry (each gathered
+                         # vector counted once)
+                         k_bcg_spmv_bytes_per_launch=104 * rows + (28 if fp32 else 52) * nnz)
+    out = dict(workload=f"the N={cfg0['n']} box at shear 0.1 with pair friction a_par={a_par} "
+                        f"along and a_perp={a_perp} across the line of centres",
+               unit="particle-steps/s", steps=steps, **res[0])
+    out["fp32_product"] = res[1]
+    return out
 
 
 def time_form(args, S, cfgs, pos0s, form, theta, stream, torch, np, steps=None, label="",
