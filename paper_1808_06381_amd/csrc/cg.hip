@@ -103,10 +103,16 @@ __device__ __forceinline__ void write_partials(const DevPtrs& d, int sub, int fi
   }
 }
 
-// XCD-contiguous sub-tile of this block (or -1 past the end) and its tile
+// XCD-contiguous sub-tile of this block (or -1 past the end).  With d.rev
+// each XCD takes its range from the last sub-tile down: a kernel launched
+// right after one that walked forward starts on the rows that one touched
+// last, the most likely to be still in the Infinity Cache.  Partials go to
+// their sub-tile's slot either way, so the order changes no bits.
 __device__ __forceinline__ int sub_of_block(const DevPtrs& d) {
   const int nsub = SUBS_PER_TILE * d.nblk;
-  const int sub = xcd_block(blockIdx.x, nsub);
+  const int per = (nsub + 7) >> 3;
+  const int hw = blockIdx.x;
+  const int sub = d.rev ? (hw & 7) * per + (per - 1 - (hw >> 3)) : xcd_block(hw, nsub);
   return sub < nsub ? sub : -1;
 }
 

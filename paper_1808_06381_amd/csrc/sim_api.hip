@@ -460,8 +460,9 @@ static int cg_maxit(const sim_t* s) {
 
 // u = M^-1 r by the learned product or the IC(0) triangular solves (with
 // the (r, u) partials), for the components selected by mode
-static int queue_apply(sim_t* s, int mode, hipEvent_t e0, hipEvent_t e1) {
-  const DevPtrs& d = s->d;
+static int queue_apply(sim_t* s, int mode, hipEvent_t e0, hipEvent_t e1, int rev = 0) {
+  DevPtrs d = s->d;
+  d.rev = rev;
   if (d.ic0) {
     HIPCHK(launch_ic_apply(d, s->ic_color_off.data(), (int)s->ic_color_off.size() - 1, s->stream));
     HIPCHK(launch_cg_dot_ru(d, mode, s->stream));
@@ -539,16 +540,20 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
     s->prof_run_n = n;
     HIPCHK(hipEventRecord(s->prof_run_ev[0], stream));
   }
+  int nstream = 0;  // streaming CG launches queued so far in this chunk
   for (int k = 0; k < n; ++k) {
     const int g = first + k;
     const bool probe = probes && !(s->prof_solves & 1) && s->prof_every > 0 &&
                        g % s->prof_every == s->prof_phase &&
                        (int)s->prof_pending.size() + kProfKernels <= (int)s->prof_ev.size() / 2;
-    // vector update, then (learned) u = M^-1 r, then w = A u
+    // vector update, then (learned) u = M^-1 r, then w = A u; consecutive
+    // streaming launches walk their sub-tiles in opposite directions
     const int order[3] = {0, 2, 1};
     for (int oi = 0; oi < 3; ++oi) {
       const int kern = order[oi];
       if (kern == 2 && !ext) continue;
+      DevPtrs dk = d;
+      dk.rev = nstream++ & 1;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (probe && !(kern == 2 && d.ic0)) {  // the IC(0) pass is many launches: not probed
         const int ev = (int)s->prof_pending.size();
@@ -556,10 +561,10 @@ static int cg_queue_chunk(sim_t* s, int n, int first, bool probes) {
         e0 = s->prof_ev[2 * ev];
         e1 = s->prof_ev[2 * ev + 1];
       }
-      if (kern == 0) HIPCHK(launch_cg_vec(d, 2, stream, e0, e1));
-      else if (kern == 1) HIPCHK(launch_cg_spmv(d, 0, 2, stream, e0, e1));
+      if (kern == 0) HIPCHK(launch_cg_vec(dk, 2, stream, e0, e1));
+      else if (kern == 1) HIPCHK(launch_cg_spmv(dk, 0, 2, stream, e0, e1));
       else {
-        int rc = queue_apply(s, 2, e0, e1);
+        int rc = queue_apply(s, 2, e0, e1, dk.rev);
         if (rc) return rc;
       }
     }

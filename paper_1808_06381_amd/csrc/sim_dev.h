@@ -165,7 +165,7 @@ struct DevPtrs {
   int32_t l1_total;         // first-level reduction blocks over all replicas
   int32_t want_er;          // 1: the pair terms write er (the network's edge input)
   int32_t vec_nt;           // 1: the CG vector kernel streams with nontemporal accesses
-  int32_t pad1;
+  int32_t rev;              // 1: each XCD walks its CG sub-tiles from the last
 };
 static_assert(sizeof(DevPtrs) % 8 == 0, "DevPtrs must have no implicit tail padding");
 
