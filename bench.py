@@ -25,7 +25,7 @@ paper's own box (4 x 20060 at its four shear rates), anisotropic friction,
 and the oracle's own throughput on the host cores (1 and all) for a bounded
 sample of the pre-sheared scale workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c5|c5-single|c2|small]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c5|c5-single|c2|small|aniso]
                   [--no-cpu-baseline] [--c5-preshear 2000]
 """
 import argparse
@@ -71,8 +71,9 @@ def parse():
     ap.add_argument("--only", default="",
                     help="c5: the scale workloads only; c5-single: the N = 8e6 box only; "
                          "small: the N = 1000 case and the paper's box only; c2: the N = 1e6 "
-                         "boxes with S(q) and the velocity correlation only (no headline line "
-                         "for small and c2)")
+                         "boxes with S(q) and the velocity correlation only; aniso: the "
+                         "anisotropic-friction box only (no headline line for small, c2 and "
+                         "aniso)")
     ap.add_argument("--c2-steps", type=int, default=20)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -562,6 +563,10 @@ def main():
         # the N = 1e6 boxes with S(q) and the velocity correlation alone
         print(json.dumps(run_c2(args, S, inputs, theta, forms, head, stream, torch, np, copy_gbs)),
               flush=True)
+        return
+    if args.only == "aniso":
+        # the anisotropic-friction box alone (FP64 and FP32-valued block products)
+        print(json.dumps({"anisotropic": measure_aniso(args, S, inputs, np)}), flush=True)
         return
 
     c5, batch_state = run_c5(args, S, inputs, theta, forms, stream, torch, np, copy_gbs)
