@@ -133,9 +133,11 @@ typedef struct sim_params {
    * solves the block system: block-Jacobi CG over the 3n coupled unknowns,
    * one true-residual tolerance per replica on the stacked vector; steps run
    * eagerly (no step graphs); precond must be Jacobi, none or learned (the
-   * 3 x 3 heads below) and warm_start 0, else SIM_ENOTSUP; spmv_fp32 = 1
-   * rounds the six values of every off-diagonal block to FP32 for the
-   * iteration products (diagonal blocks, residual rounds in FP64).          */
+   * 3 x 3 heads below), else SIM_ENOTSUP; spmv_fp32 = 1 rounds the six
+   * values of every off-diagonal block to FP32 for the iteration products
+   * (diagonal blocks, residual rounds in FP64); warm_start = 1 starts each
+   * step's solve from the previous step's velocities, as for the scalar
+   * system.                                                                 */
   double friction_par;
   double friction_perp;
 } sim_params;

@@ -248,6 +248,34 @@ __global__ void k_bcg_reset(DevPtrs d, BlockPtrs bp, double tol) {
   B.first = 1;
 }
 
+// Warm start, after the first residual round (which set ||b||^2 from x = 0
+// and finished the replicas with b = 0): x = the previous step's velocity
+// of each row's particle (kept in original order) for the replicas still
+// iterating.  Padding rows keep x = 0.
+__global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_warm(DevPtrs d, BlockPtrs bp,
+                                                            const int64_t* __restrict__ id_off) {
+  static_assert(ROWS_PER_BLOCK == BLOCK_THREADS, "one row per thread");
+  const int blk = blockIdx.x;
+  const int rid = d.blk_rep[blk];
+  if (bp.bcg[rid].state != 0) return;
+  const RepDev& R = d.rep[rid];
+  const int64_t i = (int64_t)blk * ROWS_PER_BLOCK + threadIdx.x;
+  if (i - R.row_off >= R.n) return;
+  const int64_t g = id_off[rid] + (int64_t)d.pos[i].w;
+  d.x[3 * i] = d.vel_orig[3 * g];
+  d.x[3 * i + 1] = d.vel_orig[3 * g + 1];
+  d.x[3 * i + 2] = d.vel_orig[3 * g + 2];
+}
+
+// the replicas still iterating take one more residual round (r = b - A x
+// from the warm x; no iteration has run, so it counts as no restart)
+__global__ void k_bcg_rearm(DevPtrs d, BlockPtrs bp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.nrep) return;
+  BcgRep& B = bp.bcg[r];
+  if (B.state == 0) B.state = 1;
+}
+
 __global__ __launch_bounds__(BLOCK_THREADS) void k_bcg_zero(DevPtrs d) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK_THREADS + threadIdx.x;
   if (i >= d.rows) return;
@@ -559,6 +587,12 @@ hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, h
   return hipGetLastError();
 }
 
+hipError_t launch_bcg_warm(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_bcg_warm, dim3(d.nblk), dim3(BLOCK_THREADS), 0, s, d, bp, id_off);
+  hipLaunchKernelGGL(k_bcg_rearm, dim3((d.nrep + 255) / 256), dim3(256), 0, s, d, bp);
+  return hipGetLastError();
+}
 hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s) {
   hipLaunchKernelGGL(k_bcg_spmv<false>, dim3(xcd_grid(d.nblk)), dim3(BLOCK_THREADS), 0, s, d, bp, 1);
   if (bp.learned)

@@ -146,6 +146,8 @@ struct BlockPtrs {
 hipError_t launch_pair_block(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
 hipError_t launch_bcg_reset(const DevPtrs& d, const BlockPtrs& bp, double tol, hipStream_t s);
 hipError_t launch_bcg_residual(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
+hipError_t launch_bcg_warm(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
+                           hipStream_t s);
 hipError_t launch_bcg_iteration(const DevPtrs& d, const BlockPtrs& bp, hipStream_t s);
 hipError_t launch_block_export(const DevPtrs& d, const BlockPtrs& bp, const int64_t* id_off,
                                int64_t* rows, int64_t* cols, double* vals, double* diag,

@@ -719,10 +719,11 @@ static int cg_poll_loop(sim_t* s, int launched, sim_stats* st, bool* first_final
   return SIM_OK;
 }
 
-// the block system's CG (anisotropic friction): residual round, then chunks
-// of iterations each closed by a residual round, the host reading the
+// the block system's CG (anisotropic friction): residual round (with a warm
+// start, a second one from the previous step's velocities), then chunks of
+// iterations each closed by a residual round, the host reading the
 // per-replica states after each chunk
-static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
+static int bcg_solve(sim_t* s, double tol, bool warm, sim_stats* st) {
   s->vv_valid = false;
   s->bp.learned = s->learned && s->d.learned ? 1 : 0;
   HIPCHK(hipMemcpyAsync(s->ctrl_h, s->d.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
@@ -730,6 +731,10 @@ static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
   if (s->ctrl_h->overflow) return SIM_EOVERFLOW_INTERNAL;
   HIPCHK(launch_bcg_reset(s->d, s->bp, tol, s->stream));
   HIPCHK(launch_bcg_residual(s->d, s->bp, s->stream));
+  if (warm) {
+    HIPCHK(launch_bcg_warm(s->d, s->bp, s->id_off_d, s->stream));
+    HIPCHK(launch_bcg_residual(s->d, s->bp, s->stream));
+  }
   const int maxit = cg_maxit(s);
   int chunk = std::max(4, std::min(32, s->last_iters > 0 ? s->last_iters : 8));
   int status = SIM_OK;
@@ -792,7 +797,7 @@ static int bcg_solve(sim_t* s, double tol, sim_stats* st) {
 }
 
 static int cg_solve(sim_t* s, double tol, bool warm, sim_stats* st) {
-  if (s->block) return bcg_solve(s, tol, st);
+  if (s->block) return bcg_solve(s, tol, warm, st);
   int rc = cg_queue_start(s, tol, warm);
   if (rc) return rc;
   const int n = std::max(1, std::min(s->last_iters > 2 ? s->last_iters - 1 : 8, cg_maxit(s) + 1));
@@ -900,7 +905,7 @@ int sim_create_batch(const sim_params* params, int32_t replicas, const double* p
   for (int r = 0; r < replicas; ++r) s->block = s->block || anisotropic(params[r]);
   if (s->block)
     for (int r = 0; r < replicas; ++r)
-      if (params[r].precond == SIM_PC_IC0 || params[r].warm_start) {
+      if (params[r].precond == SIM_PC_IC0) {
         delete s;
         return SIM_ENOTSUP;
       }

@@ -13,7 +13,8 @@ Cases: the system at creation and after steps with a large Lees-Edwards
 offset; ten steps, each from the GPU's positions; a scaled isotropic tensor (a_par = a_perp = 2)
 against the scalar path with alpha doubled; a batch with an isotropic and
 two anisotropic replicas; sim_solve against a dense solve; the FP32-valued
-product (a dense solve and ten steps); refused options.
+product (a dense solve and ten steps); the warm start (steps against the
+oracle, iterations saved without noise); refused options.
 """
 import numpy as np
 import pytest
@@ -233,10 +234,64 @@ def test_fp32_product_steps_match_oracle():
             assert dx <= cfg["dt"] * 2 * kap * 1e-10 * np.linalg.norm(vel_o) + 1e-13, k
 
 
+def block_run(cfg, pos0, steps, tol=1e-10):
+    its, vels, poss = [], [], [pos0.copy()]
+    with S.Sim(cfg, pos0, tol=tol) as sim:
+        for _ in range(steps):
+            st = sim.step(1)
+            its.append(st["iters"][0])
+            assert max(st["relres"]) <= tol
+            p, v, _ = sim.state()
+            poss.append(p)
+            vels.append(v)
+    return poss, vels, its
+
+
+def test_warm_start_steps_match_oracle():
+    """Each step's solve starts from the previous step's velocities: only the
+    starting point differs, not the system or the stopping rule, so every
+    step agrees with the oracle's cold solve at the GPU's positions within
+    the same 2 kappa tau as cold steps."""
+    case = inputs.small_case(seed=6)
+    cfg = aniso(dict(case["params"], shear_rate=0.5, warm_start=1), 2.5, 0.4)
+    pos0 = inputs.uniform_positions(cfg["n"], cfg["box"], cfg["seed"])
+    poss, vels, _ = block_run(cfg, pos0, 8)
+    for k in range(8):
+        _, vo, _ = oracle.step_block(cfg, poss[k], k, 2.5, 0.4, tol=1e-10)
+        kap = kappa_bound(cfg, poss[k], 2.5, 0.4, k)
+        rel = np.linalg.norm(vels[k] - vo) / np.linalg.norm(vo)
+        assert rel < 2 * kap * 1e-10, (k, rel, kap)
+
+
+def test_warm_start_saves_iterations_without_noise():
+    """Affine Couette flow on a sheared simple cubic lattice (kT = 0) solves
+    the block system exactly at every step (each pair's relative velocity is
+    the imposed one, whatever its tensor), so from the second step the warm
+    guess meets the stacked tolerance with no iteration; from a uniform
+    random start (blobs relaxing) the warm start only has to save some."""
+    counts, a = (12, 12, 12), 0.9
+    L = counts[0] * a
+    cfg = aniso(inputs.base_params(n=int(np.prod(counts)), box=(L, L, L), shear_rate=0.1,
+                                   kT=0.0, seed=8), 3.0, 0.5)
+    pos0 = inputs.lattice_positions(counts, a, origin=(0.45, 0.45, 0.45))
+    _, vc, cold = block_run(cfg, pos0, 6)
+    _, vw, warm = block_run(dict(cfg, warm_start=1), pos0, 6)
+    assert warm[0] == cold[0] and cold[0] > 3
+    assert all(it == 0 for it in warm[1:]) and all(it > 3 for it in cold), (warm, cold)
+    for a_, b_ in zip(vc, vw):
+        assert np.linalg.norm(a_ - b_) / np.linalg.norm(a_) < 1e-8
+    cfg2 = aniso(inputs.cube_params(4000, 0.2, seed=8, kT=0.0), 2.0, 0.5)
+    pos2 = inputs.uniform_positions(cfg2["n"], cfg2["box"], 8)
+    _, _, cold2 = block_run(cfg2, pos2, 6)
+    _, _, warm2 = block_run(dict(cfg2, warm_start=1), pos2, 6)
+    assert warm2[0] == cold2[0]
+    assert sum(warm2[1:]) < sum(cold2[1:]), (warm2, cold2)
+
+
 def test_refused_options():
     base = inputs.cube_params(500, 0.1, seed=36)
     pos0 = inputs.uniform_positions(500, base["box"], 36)
-    for extra in (dict(precond="ic0"), dict(warm_start=1)):
+    for extra in (dict(precond="ic0"),):
         with pytest.raises(S.SimError):
             S.Sim(aniso(dict(base, **extra), 2.0, 1.0), pos0)
     with S.Sim(aniso(base, 2.0, 1.0), pos0) as sim:
